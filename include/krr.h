@@ -1,0 +1,293 @@
+/*
+ * krr.h -- C ABI of the MI355X (gfx950) Gaussian-kernel ridge regression
+ * library: recursive two-means ordering, HSS compression by randomized
+ * sampling, ULV factorization and solve, refinement, prediction, gradients.
+ *
+ * The system solved is (K + lambda I) alpha = y with the Gaussian kernel
+ * K_ij = exp(-||x_i - x_j||^2 / (2 h^2)) (eq. (1.1); Algorithm 1 steps 1-2),
+ * then test labels are the signs of K(X', X) alpha (Algorithm 1 steps 3-4).
+ *
+ * Conventions for every entry point:
+ *   - Pointers are DEVICE pointers unless the parameter name ends in _host.
+ *     Device buffers belong to the caller and must stay alive until the work
+ *     enqueued on `stream` has completed.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is enqueued on it; calls that must read results back to plan the
+ *     next launch (noted per call) synchronize that stream.
+ *   - Matrices are row-major and densely packed (leading dimension = columns).
+ *   - Point arrays have dtype KRR_F32 or KRR_F64 (argument `xprec`).
+ *   - Return value: KRR_OK (0) or a negative KRR_E_* code.  On error no
+ *     handle is created, and krr_last_error() returns a message for the
+ *     calling thread.  Nothing throws across this boundary.
+ *   - After clustering every quantity is in the PERMUTED order:
+ *     perm[i] is the original index of position i.
+ *   - A handle must not be used from two host threads at once.
+ */
+#ifndef KRR_H
+#define KRR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    KRR_OK = 0,
+    KRR_E_INVAL = -1,         /* invalid argument (sizes, NULL pointers, h <= 0, lambda < 0) */
+    KRR_E_NOMEM = -2,         /* device allocation failed */
+    KRR_E_HIP = -3,           /* a HIP runtime call or kernel launch failed */
+    KRR_E_RANK_CAP = -4,      /* adaptive sampling reached r_max before ranks were revealed */
+    KRR_E_NUMERIC = -5,       /* non-finite sample, or a non-positive pivot in a Cholesky factor */
+    KRR_E_NOT_CONVERGED = -6, /* refinement stopped at max_iter above the requested tolerance */
+    KRR_E_NODEVICE = -7       /* no HIP device is available */
+};
+
+/* Arithmetic of the kernel products. */
+enum {
+    KRR_F64 = 0,        /* all FP64 */
+    KRR_F32 = 1,        /* FP32 entries and products, FP32 matrix cores for samples */
+    KRR_F16_SPLIT = 2,  /* samples: kernel entries split into FP16 hi (+ lo) terms, FP32 accumulation */
+    KRR_BF16_SPLIT = 3  /* samples: as above with BF16 terms */
+};
+
+typedef struct krr_tree_s *krr_tree;
+typedef struct hss_s *hss_t;
+typedef struct hss_ulv_s *hss_ulv_t;
+
+/* ---------------------------------------------------------------- errors */
+
+/* Message for the last failed call on this thread ("" if none). */
+const char *krr_last_error(void);
+
+/* Number of usable HIP devices (0 when none); never fails. */
+int krr_device_count(void);
+
+/* ---------------------------------------------------- clustering (A1, A2) */
+
+typedef struct {
+    int32_t leaf_size; /* nodes larger than this are split (> 0) */
+    int32_t max_iter;  /* Lloyd iteration cap per split (>= 1; 100 recommended) */
+    uint64_t seed;     /* key of the counter-based seeding draws */
+} krr_cluster_opts;
+
+/*
+ * Recursive two-means ordering and cluster tree (Section 4.2 steps 1-3;
+ * Section 4.3 "Recursive two-means"; leaf-size rule of Section 4.3; postorder
+ * tree of Fig. 3).  Per node [b, e) larger than the leaf size: first seed
+ * uniform over the node, second seed with probability proportional to the
+ * distance from the first, Lloyd iterations until no label changes (ties to
+ * the first cluster, at most max_iter), stable split with first-cluster points
+ * first; an empty cluster or all-equal points split the node in halves by
+ * position.  The result is bit-for-bit deterministic for a given seed.
+ *
+ *   X      n x d points (xprec), not modified
+ *   perm   (out, n int64) perm[new position] = original index
+ *   out    (out) tree handle; free with krr_tree_destroy
+ * Synchronizes `stream` once per tree level and once per Lloyd iteration.
+ */
+int krr_cluster_2mn(const void *X, int32_t xprec, int64_t n, int32_t d,
+                    const krr_cluster_opts *opts, void *stream, int64_t *perm,
+                    krr_tree *out);
+
+/* Builds a tree handle from a host node table (n_nodes rows of begin, end,
+ * left, right, parent; postorder, children before parents, root last; leaves
+ * have left = right = -1).  Lets any ordering (or a test) drive compression. */
+int krr_tree_from_host(const int64_t *nodes_host, int64_t n_nodes, krr_tree *out);
+
+/* Number of points and of nodes of a tree. */
+int krr_tree_size(krr_tree t, int64_t *n_host, int64_t *n_nodes_host);
+
+/* Copies the node table (n_nodes x 5 int64, layout of krr_tree_from_host)
+ * and the clustering statistics (4 int64: fallback splits, splits that hit
+ * max_iter, Lloyd iterations, levels; zeros for a tree built from a table). */
+int krr_tree_export(krr_tree t, int64_t *nodes_host, int64_t *stats_host);
+
+void krr_tree_destroy(krr_tree t);
+
+/* dst[i, :] = src[perm[i], :]  (rows of `cols` elements of dtype prec). */
+int krr_gather_rows(const void *src, int32_t prec, int64_t n, int32_t cols,
+                    const int64_t *perm, void *dst, void *stream);
+
+/* dst[perm[i], :] = src[i, :]  (inverse of krr_gather_rows). */
+int krr_scatter_rows(const void *src, int32_t prec, int64_t n, int32_t cols,
+                     const int64_t *perm, void *dst, void *stream);
+
+/* ----------------------------------------------------- kernel products */
+
+/*
+ * Out = K(X, Y; h) W + beta * Out  with the Gaussian kernel of eq. (1.1)
+ * (Algorithm 1 step 3 for prediction; the residual of refinement).  K is
+ * never stored.
+ *   X    m x d points, Y  n x d points (both xprec)
+ *   W    n x nrhs FP64,  Out  m x nrhs FP64 (read only if beta != 0)
+ *   prec KRR_F64: FP64 throughout.  KRR_F32: kernel entries and products in
+ *        FP32 from exact coordinate differences, sums over each column tile in
+ *        FP32 and across tiles in FP64.
+ *   1 <= nrhs <= 64.
+ */
+int kernel_matvec(const void *X, int64_t m, const void *Y, int64_t n, int32_t d,
+                  int32_t xprec, double h, const double *W, int32_t nrhs, double beta,
+                  double *Out, int32_t prec, void *stream);
+
+/*
+ * Off-diagonal sampling product of the randomized HSS construction
+ * (Section 3.1): S = K(X, X; h) R where row i skips the columns of its own
+ * leaf [leaf_begin[i], leaf_end[i]) (pass both NULL for no masking).
+ *   X  n x d points (xprec);  R  n x r FP32 random block (values exactly
+ *   representable in the chosen precision, e.g. +-1);  S  n x r FP32 out
+ *   (FP64 when prec == KRR_F64).  r must be a multiple of 32.
+ *   prec: KRR_F64, KRR_F32, KRR_F16_SPLIT, KRR_BF16_SPLIT;
+ *   split_terms: 1 or 2 terms of the kernel entries for the split modes.
+ */
+int kernel_sample(const void *X, int64_t n, int32_t d, int32_t xprec, double h,
+                  const float *R, int32_t r, const int32_t *leaf_begin,
+                  const int32_t *leaf_end, void *S, int32_t prec, int32_t split_terms,
+                  void *stream);
+
+/* The random block hss_compress draws: R[i, c] = +-1 from a counter-based
+ * generator keyed by (seed, i, c0 + c); n x r FP32 out. */
+int krr_random_block(uint64_t seed, int64_t n, int32_t r, int32_t c0, float *R,
+                     void *stream);
+
+/*
+ * Backward of Out = K(X, Y; h) W for the upstream gradient G (m x nrhs):
+ *   dW = K(X, Y)^T G                 (n x nrhs FP64)
+ *   P  = K o (G W^T)  (formed on the fly, never stored)
+ *   dX_i = -(1/h^2) [ (sum_j P_ij) x_i - (P Y)_i ]      (m x d FP64)
+ *   dY_j =  (1/h^2) [ (P^T X)_j - (sum_i P_ij) y_j ]    (n x d FP64)
+ *   dh   = sum_ij P_ij ||x_i - y_j||^2 / h^3            (1 FP64, device)
+ * Any of dX, dY, dW, dh may be NULL.  W, G FP64; prec as for kernel_matvec.
+ */
+int kernel_matvec_bwd(const void *X, int64_t m, const void *Y, int64_t n, int32_t d,
+                      int32_t xprec, double h, const double *W, const double *G,
+                      int32_t nrhs, double *dX, double *dY, double *dW, double *dh,
+                      int32_t prec, void *stream);
+
+/* ------------------------------------------------- HSS compression (A3-A5) */
+
+typedef struct {
+    double rtol;         /* relative ID tolerance on the pivoted-QR diagonal */
+    double atol;         /* absolute tolerance on |R_jj| / sqrt(r) (0 = off) */
+    int32_t r0;          /* initial sample width (multiple of 32) */
+    int32_t dr;          /* growth step of the sample width (multiple of 32) */
+    int32_t r_max;       /* cap of the sample width */
+    int32_t oversample;  /* p: ranks must stay <= r - p, else the sample grows */
+    int32_t prec;        /* sampling arithmetic (KRR_F64 .. KRR_BF16_SPLIT) */
+    int32_t split_terms; /* 1 or 2 for the split modes */
+    uint64_t seed;       /* random block key */
+} hss_opts;
+
+typedef struct {
+    int64_t n, n_nodes, levels;
+    int32_t r_final;          /* sample width that revealed every rank */
+    int32_t regrowths;        /* times the sample was widened */
+    int32_t max_rank;
+    int32_t pad_;
+    int64_t bytes_paper;      /* memory metric: D, U, V, B_ij, B_ji as stored separately */
+    int64_t bytes_stored;     /* generators actually stored (symmetric: U = V) */
+    double t_sample_ms;       /* phase times (HIP events) */
+    double t_id_ms;
+    double t_total_ms;
+} hss_stats;
+
+/*
+ * Randomized HSS compression of K(Xp, Xp; h) on the tree `t`
+ * (Section 3.1; the randomized construction with adaptive sampling of
+ * Section 1.1): S = K R with each leaf's own block removed; per tree level,
+ * leaves take the interpolative decomposition (ID) of their sample rows,
+ * parents of their children's skeleton rows minus the coupling B times the
+ * sibling's reduced random block; D = K(I, I) at leaves and
+ * B = K(J_left, J_right) at parents are extracted in FP64.  IDs, D and B are
+ * FP64.  If some rank exceeds r - oversample the sample is widened by dr
+ * (only the new columns are sampled) and the IDs are redone, up to r_max.
+ *   Xp     n x d points in tree order (xprec)
+ *   stats_host  optional (may be NULL)
+ * Synchronizes `stream` once per level (ranks size the next level).
+ */
+int hss_compress(krr_tree t, const void *Xp, int32_t xprec, int32_t d, double h,
+                 const hss_opts *opts, void *stream, hss_t *out, hss_stats *stats_host);
+
+void hss_destroy(hss_t H);
+
+/* Sizes of the generator export: node count, FP64 values, int64 values. */
+int hss_export_sizes(hss_t H, int64_t *n_nodes_host, int64_t *n_dbl_host,
+                     int64_t *n_int_host);
+
+/*
+ * Copies the generators to the host.  table_host: n_nodes rows of 10 int64 =
+ * (begin, end, left, right, m, k, off_U, off_D, off_B, off_J), offsets into
+ * dbl_host / int_host, -1 where absent.  U is m x k (leaf: basis over the
+ * leaf's points; non-leaf: transfer matrix over the children's skeletons),
+ * D is (end-begin)^2 at leaves, B = K(J_left, J_right) at non-leaves, J the
+ * k skeleton positions.  Synchronizes `stream`.
+ */
+int hss_export(hss_t H, int64_t *table_host, double *dbl_host, int64_t *int_host,
+               void *stream);
+
+/* ------------------------------------------------ ULV factor / solve (A6, A7) */
+
+/*
+ * ULV factorization of K_hss + lambda I (Section 3.1; lambda changes only the
+ * leaf diagonal blocks, Section 5.3, so a new lambda needs no new compression).
+ * Bottom-up per level: an orthogonal Q with Q^T U = [R; 0], D' = Q^T D Q,
+ * Cholesky elimination of the rows outside U's range, the Schur complement on
+ * the remaining k rows merged with the coupling blocks into the parent; dense
+ * Cholesky at the root.  FP64.  Fails with KRR_E_NUMERIC on a non-positive
+ * pivot.  Synchronizes `stream` once at the end (pivot check).
+ */
+int hss_ulv_factor(hss_t H, double lambda, void *stream, hss_ulv_t *out);
+
+void hss_ulv_destroy(hss_ulv_t F);
+
+/* Xout = (K_hss + lambda I)^{-1} B for n x nrhs FP64 B (permuted order).
+ * B and Xout may alias.  The factor is symmetric, so it also solves the
+ * transposed system. */
+int hss_solve(hss_ulv_t F, const double *B, int32_t nrhs, double *Xout, void *stream);
+
+/* --------------------------------------------------- refinement (A8) */
+
+typedef struct {
+    int32_t iterations;
+    int32_t matvecs;
+    double relres[64];   /* final true relative residual per right-hand side */
+    double t_ms;
+} krr_refine_stats;
+
+/*
+ * Preconditioned conjugate gradients on (K + lambda I) alpha = Y with the ULV
+ * factor as preconditioner and kernel_matvec (prec mv_prec) for the products;
+ * the stopping test uses the recomputed true residual ||Y - (K + lambda I)
+ * alpha|| / ||Y|| <= tol per column.  alpha: in = start, out = solution
+ * (n x nrhs FP64, permuted order).  Returns KRR_E_NOT_CONVERGED if max_iter
+ * is reached first (alpha then holds the last iterate).  Synchronizes
+ * `stream` once per iteration.
+ */
+int krr_refine(hss_ulv_t F, const void *Xp, int32_t xprec, int32_t d, double h,
+               double lambda, const double *Y, int32_t nrhs, double *alpha, double tol,
+               int32_t max_iter, int32_t mv_prec, void *stream, krr_refine_stats *stats_host);
+
+/* --------------------------------------------------- prediction (A9) */
+
+/*
+ * scores = K(Xt, Xp; h) alpha (m x nrhs FP64) and labels (m int32):
+ * nrhs == 1: sign, zero counts as +1 (Algorithm 1 step 4);
+ * nrhs > 1: index of the largest signed score, ties to the lowest (one-vs-all,
+ * Section 2).  labels may be NULL.
+ */
+int krr_predict(const void *Xt, int64_t m, const void *Xp, int64_t n, int32_t d,
+                int32_t xprec, double h, const double *alpha, int32_t nrhs,
+                double *scores, int32_t *labels, int32_t prec, void *stream);
+
+/* ------------------------------------------------ small vector kernels */
+
+/* out[c] = sum_i a[i, c] * b[i, c] (n x k FP64, deterministic order; device out). */
+int krr_dot_columns(const double *a, const double *b, int64_t n, int32_t k, double *out,
+                    void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KRR_H */

@@ -1,0 +1,327 @@
+"""Python binding of libkrr, the MI355X (gfx950) Gaussian-kernel ridge
+regression library (include/krr.h).
+
+This module only marshals arguments: torch tensors provide device memory and
+the current stream; every computation runs in the library's HIP kernels.
+There is no CPU fallback -- if libkrr.so is missing, every call raises.
+
+Order convention: after clustering, points, labels, samples and solutions are
+in the permuted ("tree") order; perm[i] is the original index of position i.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import (KRR_BF16_SPLIT, KRR_F16_SPLIT, KRR_F32, KRR_F64, ClusterOpts, HssOpts, HssStats,  # noqa: F401
+                   KrrError, RefineStats, check, load)
+
+PREC = {"f64": KRR_F64, "f32": KRR_F32, "f16": KRR_F16_SPLIT, "bf16": KRR_BF16_SPLIT}
+
+
+def _prec(p):
+    return PREC[p] if isinstance(p, str) else int(p)
+
+
+def _xprec(t: torch.Tensor) -> int:
+    if t.dtype == torch.float64:
+        return KRR_F64
+    if t.dtype == torch.float32:
+        return KRR_F32
+    raise TypeError(f"points must be float32 or float64, got {t.dtype}")
+
+
+def _dev(t: torch.Tensor, dtype=None) -> torch.Tensor:
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def device_count() -> int:
+    return load().krr_device_count()
+
+
+# ------------------------------------------------------------------ trees
+
+class Tree:
+    """Cluster tree handle (postorder nodes: begin, end, left, right, parent)."""
+
+    def __init__(self, handle):
+        self.h = handle
+        n, nn = ctypes.c_int64(), ctypes.c_int64()
+        check(load().krr_tree_size(handle, ctypes.byref(n), ctypes.byref(nn)))
+        self.n, self.n_nodes = n.value, nn.value
+        self.nodes = np.empty((self.n_nodes, 5), dtype=np.int64)
+        self.stats = np.zeros(4, dtype=np.int64)
+        check(load().krr_tree_export(handle, self.nodes.ctypes.data_as(ctypes.c_void_p),
+                                     self.stats.ctypes.data_as(ctypes.c_void_p)))
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib._lib is not None:
+            _lib._lib.krr_tree_destroy(self.h)
+            self.h = None
+
+
+def cluster_2mn(X: torch.Tensor, leaf: int, seed: int, max_iter: int = 100):
+    """Recursive two-means ordering; returns (perm int64 tensor, Tree)."""
+    _dev(X)
+    n, d = X.shape
+    perm = torch.empty(n, dtype=torch.int64, device=X.device)
+    opts = ClusterOpts(int(leaf), int(max_iter), int(seed) & (2**64 - 1))
+    h = ctypes.c_void_p()
+    check(load().krr_cluster_2mn(_p(X), _xprec(X), n, d, ctypes.byref(opts), _stream(), _p(perm),
+                                 ctypes.byref(h)))
+    return perm, Tree(h)
+
+
+def tree_from_nodes(nodes) -> Tree:
+    arr = np.ascontiguousarray(np.asarray(nodes, dtype=np.int64)[:, :5])
+    h = ctypes.c_void_p()
+    check(load().krr_tree_from_host(arr.ctypes.data_as(ctypes.c_void_p), arr.shape[0], ctypes.byref(h)))
+    return Tree(h)
+
+
+def gather_rows(src: torch.Tensor, perm: torch.Tensor) -> torch.Tensor:
+    """dst[i] = src[perm[i]]."""
+    _dev(src)
+    _dev(perm, torch.int64)
+    s2 = src.reshape(src.shape[0], -1)
+    dst = torch.empty_like(s2)
+    check(load().krr_gather_rows(_p(s2), _xprec(s2), s2.shape[0], s2.shape[1], _p(perm), _p(dst), _stream()))
+    return dst.reshape(src.shape)
+
+
+def scatter_rows(src: torch.Tensor, perm: torch.Tensor) -> torch.Tensor:
+    """dst[perm[i]] = src[i]."""
+    _dev(src)
+    _dev(perm, torch.int64)
+    s2 = src.reshape(src.shape[0], -1)
+    dst = torch.empty_like(s2)
+    check(load().krr_scatter_rows(_p(s2), _xprec(s2), s2.shape[0], s2.shape[1], _p(perm), _p(dst), _stream()))
+    return dst.reshape(src.shape)
+
+
+# -------------------------------------------------------------- products
+
+def kernel_matvec(X, Y, h, W, beta=0.0, out=None, prec="f32"):
+    """out = K(X, Y; h) W + beta out  (W, out float64)."""
+    _dev(X)
+    _dev(Y)
+    _dev(W, torch.float64)
+    W2 = W.reshape(W.shape[0], -1)
+    m, n = X.shape[0], Y.shape[0]
+    if out is None:
+        out = torch.empty((m, W2.shape[1]), dtype=torch.float64, device=X.device)
+    _dev(out, torch.float64)
+    check(load().kernel_matvec(_p(X), m, _p(Y), n, X.shape[1], _xprec(X), float(h), _p(W2), W2.shape[1],
+                               float(beta), _p(out), _prec(prec), _stream()))
+    return out.reshape((m,) + tuple(W.shape[1:]))
+
+
+def kernel_sample(X, h, R, leaf_begin=None, leaf_end=None, prec="f32", split_terms=2):
+    """Off-diagonal sample S = K(X, X; h) R with each row's own leaf removed."""
+    _dev(X)
+    _dev(R, torch.float32)
+    n, r = R.shape
+    p = _prec(prec)
+    S = torch.empty((n, r), dtype=torch.float64 if p == KRR_F64 else torch.float32, device=X.device)
+    check(load().kernel_sample(_p(X), n, X.shape[1], _xprec(X), float(h), _p(R), r,
+                               _p(leaf_begin) if leaf_begin is not None else None,
+                               _p(leaf_end) if leaf_end is not None else None, _p(S), p, int(split_terms),
+                               _stream()))
+    return S
+
+
+def random_block(seed, n, r, c0=0, device="cuda"):
+    R = torch.empty((n, r), dtype=torch.float32, device=device)
+    check(load().krr_random_block(int(seed) & (2**64 - 1), n, r, c0, _p(R), _stream()))
+    return R
+
+
+def kernel_matvec_bwd(X, Y, h, W, G, prec="f32", want=("dX", "dY", "dW", "dh")):
+    """Backward of Out = K(X, Y; h) W: returns dict with the requested grads."""
+    _dev(X)
+    _dev(Y)
+    W2 = _dev(W, torch.float64).reshape(W.shape[0], -1)
+    G2 = _dev(G, torch.float64).reshape(G.shape[0], -1)
+    m, n, d = X.shape[0], Y.shape[0], X.shape[1]
+    dev = X.device
+    out = {}
+    out["dX"] = torch.empty((m, d), dtype=torch.float64, device=dev) if "dX" in want else None
+    out["dY"] = torch.empty((n, d), dtype=torch.float64, device=dev) if "dY" in want else None
+    out["dW"] = torch.empty((n, W2.shape[1]), dtype=torch.float64, device=dev) if "dW" in want else None
+    out["dh"] = torch.empty(1, dtype=torch.float64, device=dev) if "dh" in want else None
+    check(load().kernel_matvec_bwd(_p(X), m, _p(Y), n, d, _xprec(X), float(h), _p(W2), _p(G2), W2.shape[1],
+                                   _p(out["dX"]), _p(out["dY"]), _p(out["dW"]), _p(out["dh"]), _prec(prec),
+                                   _stream()))
+    if out["dW"] is not None:
+        out["dW"] = out["dW"].reshape(W.shape)
+    return {k: v for k, v in out.items() if v is not None}
+
+
+def dot_columns(a, b):
+    a2 = _dev(a, torch.float64).reshape(a.shape[0], -1)
+    b2 = _dev(b, torch.float64).reshape(b.shape[0], -1)
+    out = torch.empty(a2.shape[1], dtype=torch.float64, device=a.device)
+    check(load().krr_dot_columns(_p(a2), _p(b2), a2.shape[0], a2.shape[1], _p(out), _stream()))
+    return out
+
+
+# ------------------------------------------------------------ HSS + ULV
+
+@dataclass
+class HssOptions:
+    rtol: float = 1e-2
+    atol: float = 0.0
+    r0: int = 256
+    dr: int = 256
+    r_max: int = 4096
+    oversample: int = 10
+    prec: str = "f32"
+    split_terms: int = 2
+    seed: int = 1
+
+    def c(self):
+        return HssOpts(self.rtol, self.atol, self.r0, self.dr, self.r_max, self.oversample, _prec(self.prec),
+                       self.split_terms, self.seed & (2**64 - 1))
+
+
+class HSS:
+    """Compressed HSS generators of K(Xp, Xp; h) (device resident)."""
+
+    def __init__(self, tree: Tree, Xp: torch.Tensor, h: float, opts: HssOptions = HssOptions()):
+        _dev(Xp)
+        self.tree = tree
+        self.stats = HssStats()
+        h_ = ctypes.c_void_p()
+        check(load().hss_compress(tree.h, _p(Xp), _xprec(Xp), Xp.shape[1], float(h), ctypes.byref(opts.c()),
+                                  _stream(), ctypes.byref(h_), ctypes.byref(self.stats)))
+        self.h = h_
+
+    def export(self):
+        """Generators on the host: dict with nodes (n x 10 table), U, D, B, J per node."""
+        nn, nd, ni = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        check(load().hss_export_sizes(self.h, ctypes.byref(nn), ctypes.byref(nd), ctypes.byref(ni)))
+        table = np.empty((nn.value, 10), dtype=np.int64)
+        dbl = np.empty(max(nd.value, 1), dtype=np.float64)
+        ints = np.empty(max(ni.value, 1), dtype=np.int64)
+        check(load().hss_export(self.h, table.ctypes.data_as(ctypes.c_void_p), dbl.ctypes.data_as(ctypes.c_void_p),
+                                ints.ctypes.data_as(ctypes.c_void_p), _stream()))
+        U, D, B, J = {}, {}, {}, {}
+        for i, (b, e, l, r, m, k, oU, oD, oB, oJ) in enumerate(table):
+            if oU >= 0:
+                U[i] = dbl[oU:oU + m * k].reshape(m, k).copy()
+                J[i] = ints[oJ:oJ + k].copy()
+            if oD >= 0:
+                D[i] = dbl[oD:oD + (e - b) ** 2].reshape(e - b, e - b).copy()
+            if oB >= 0:
+                kl, kr = table[l, 5], table[r, 5]
+                B[i] = dbl[oB:oB + kl * kr].reshape(kl, kr).copy()
+        return {"nodes": table, "U": U, "D": D, "B": B, "J": J}
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib._lib is not None:
+            _lib._lib.hss_destroy(self.h)
+            self.h = None
+
+
+class ULV:
+    """ULV factor of K_hss + lambda I."""
+
+    def __init__(self, H: HSS, lam: float):
+        h_ = ctypes.c_void_p()
+        check(load().hss_ulv_factor(H.h, float(lam), _stream(), ctypes.byref(h_)))
+        self.h = h_
+        self.hss = H
+        self.lam = lam
+
+    def solve(self, B: torch.Tensor, out=None) -> torch.Tensor:
+        _dev(B, torch.float64)
+        B2 = B.reshape(B.shape[0], -1)
+        if out is None:
+            out = torch.empty_like(B2)
+        check(load().hss_solve(self.h, _p(B2), B2.shape[1], _p(out), _stream()))
+        return out.reshape(B.shape)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib._lib is not None:
+            _lib._lib.hss_ulv_destroy(self.h)
+            self.h = None
+
+
+def refine(F: ULV, Xp, h, lam, Y, alpha, tol=1e-6, max_iter=100, mv_prec="f32", raise_on_fail=True):
+    """PCG on (K + lam I) alpha = Y preconditioned by the ULV factor (alpha updated in place)."""
+    _dev(Xp)
+    Y2 = _dev(Y, torch.float64).reshape(Y.shape[0], -1)
+    a2 = _dev(alpha, torch.float64).reshape(alpha.shape[0], -1)
+    st = RefineStats()
+    rc = load().krr_refine(F.h, _p(Xp), _xprec(Xp), Xp.shape[1], float(h), float(lam), _p(Y2), Y2.shape[1],
+                           _p(a2), float(tol), int(max_iter), _prec(mv_prec), _stream(), ctypes.byref(st))
+    if rc != 0 and (raise_on_fail or rc != _lib.KRR_E_NOT_CONVERGED):
+        check(rc)
+    return {"iterations": st.iterations, "matvecs": st.matvecs, "relres": list(st.relres[:Y2.shape[1]]),
+            "t_ms": st.t_ms, "converged": rc == 0}
+
+
+def predict(Xt, Xp, h, alpha, prec="f32"):
+    """(scores, labels): sign for one column, argmax for several."""
+    _dev(Xt)
+    _dev(Xp)
+    a2 = _dev(alpha, torch.float64).reshape(alpha.shape[0], -1)
+    m = Xt.shape[0]
+    scores = torch.empty((m, a2.shape[1]), dtype=torch.float64, device=Xt.device)
+    labels = torch.empty(m, dtype=torch.int32, device=Xt.device)
+    check(load().krr_predict(_p(Xt), m, _p(Xp), Xp.shape[0], Xp.shape[1], _xprec(Xt), float(h), _p(a2), a2.shape[1],
+                             _p(scores), _p(labels), _prec(prec), _stream()))
+    return scores, labels
+
+
+# ------------------------------------------------------------------ fit
+
+@dataclass
+class FitResult:
+    alpha: torch.Tensor        # solution in the original order (n x nrhs or n)
+    alpha_perm: torch.Tensor   # solution in tree order
+    perm: torch.Tensor
+    Xp: torch.Tensor
+    tree: Tree
+    hss: HSS
+    ulv: ULV
+    info: dict = field(default_factory=dict)
+
+
+def fit(X, y, h, lam, leaf=128, opts: HssOptions = HssOptions(), seed=7, tol=1e-6, max_iter=200,
+        mv_prec="f32", refine_solution=True, raise_on_fail=True):
+    """Algorithm 1 steps 0-2: cluster, compress, factor, solve, refine."""
+    _dev(X)
+    y2 = _dev(y, torch.float64).reshape(y.shape[0], -1)
+    perm, tree = cluster_2mn(X, leaf, seed)
+    Xp = gather_rows(X, perm)
+    yp = gather_rows(y2, perm)
+    H = HSS(tree, Xp, h, opts)
+    F = ULV(H, lam)
+    ap = F.solve(yp)
+    info = {"hss": H.stats.as_dict(), "tree_stats": tree.stats.tolist()}
+    if refine_solution:
+        info["refine"] = refine(F, Xp, h, lam, yp, ap, tol=tol, max_iter=max_iter, mv_prec=mv_prec,
+                                raise_on_fail=raise_on_fail)
+    alpha = scatter_rows(ap, perm)
+    if y.dim() == 1:
+        alpha = alpha.reshape(-1)
+    return FitResult(alpha, ap, perm, Xp, tree, H, F, info)

@@ -1,0 +1,386 @@
+// The extern "C" boundary of libkrr (declared in include/krr.h): argument
+// checks, handle lifetime, and translation of internal failures into status
+// codes with a per-thread message.  Nothing throws across this boundary.
+#include <cstdarg>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "internal.hpp"
+
+namespace krr {
+
+thread_local std::string g_last_error;
+
+void fail(int code, const char *fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    throw Error(code, buf);
+}
+
+void cluster_2mn(const void *X, int32_t xprec, int64_t n, int32_t d, const krr_cluster_opts &o, hipStream_t s,
+                 int64_t *perm, krr_tree_s &tree);
+void kernel_matvec_impl(const void *X, int64_t m, const void *Y, int64_t n, int d, int xprec, double h,
+                        const double *W, int nrhs, double beta, double *Out, int prec, hipStream_t s);
+void kernel_matvec_bwd_impl(const void *X, int64_t m, const void *Y, int64_t n, int d, int xprec, double h,
+                            const double *W, const double *G, int nrhs, double *dX, double *dY, double *dW,
+                            double *dh, int prec, hipStream_t s);
+void sample_product(const void *X, int64_t n, int d, int xprec, double h, const float *R, int r, const int32_t *lb,
+                    const int32_t *le, void *S, int prec, int split, hipStream_t s);
+void random_block(uint64_t seed, int64_t n, int r, int c0, float *R, int ldr, hipStream_t s);
+void gather_rows(const void *src, int prec, int64_t n, int cols, const int64_t *perm, void *dst, bool scatter,
+                 hipStream_t s);
+void compress(const krr_tree_s *t, const void *Xp, int xprec, int d, double h, const hss_opts &o, hipStream_t s,
+              hss_s *H, hss_stats *st);
+void ulv_factor(const hss_s *H, double lambda, hipStream_t s, hss_ulv_s *F);
+void ulv_solve(const hss_ulv_s *F, const double *Bin, int nrhs, double *Xout, hipStream_t s);
+int refine(const hss_ulv_s *F, const void *Xp, int xprec, int d, double h, double lambda, const double *Y, int nrhs,
+           double *alpha, double tol, int max_iter, int mv_prec, hipStream_t s, krr_refine_stats *st);
+void predict_labels(const double *scores, int64_t m, int k, int32_t *labels, hipStream_t s);
+void dot_columns(const double *a, const double *b, int64_t n, int k, double *out, DBuf &scratch, hipStream_t s);
+
+namespace {
+
+template <class F> int guard(F &&f) {
+    try {
+        g_last_error.clear();
+        return f();
+    } catch (const Error &e) {
+        g_last_error = e.what();
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g_last_error = "host allocation failed";
+        return KRR_E_NOMEM;
+    } catch (const std::exception &e) {
+        g_last_error = e.what();
+        return KRR_E_HIP;
+    } catch (...) {
+        g_last_error = "unknown failure";
+        return KRR_E_HIP;
+    }
+}
+
+void require_device() {
+    int cnt = 0;
+    if (hipGetDeviceCount(&cnt) != hipSuccess || cnt == 0) {
+        (void)hipGetLastError();
+        fail(KRR_E_NODEVICE, "no HIP device available");
+    }
+}
+
+hipStream_t S(void *p) { return static_cast<hipStream_t>(p); }
+
+void check_xprec(int32_t xprec) {
+    KRR_REQUIRE(xprec == KRR_F32 || xprec == KRR_F64, "point dtype must be KRR_F32 or KRR_F64 (got %d)", xprec);
+}
+
+}  // namespace
+}  // namespace krr
+
+using namespace krr;
+
+extern "C" {
+
+const char *krr_last_error(void) { return g_last_error.c_str(); }
+
+int krr_device_count(void) {
+    int cnt = 0;
+    if (hipGetDeviceCount(&cnt) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return cnt;
+}
+
+int krr_cluster_2mn(const void *X, int32_t xprec, int64_t n, int32_t d, const krr_cluster_opts *opts, void *stream,
+                    int64_t *perm, krr_tree *out) {
+    return guard([&] {
+        KRR_REQUIRE(out != nullptr && opts != nullptr, "krr_cluster_2mn: NULL opts or out");
+        *out = nullptr;
+        check_xprec(xprec);
+        KRR_REQUIRE(n >= 1 && d >= 1, "krr_cluster_2mn: need n >= 1 and d >= 1");
+        KRR_REQUIRE(n <= INT32_MAX, "krr_cluster_2mn: n must fit in int32");
+        KRR_REQUIRE(X != nullptr && perm != nullptr, "krr_cluster_2mn: NULL X or perm");
+        KRR_REQUIRE(opts->leaf_size >= 1 && opts->max_iter >= 1, "krr_cluster_2mn: leaf_size and max_iter must be >= 1");
+        require_device();
+        auto *t = new krr_tree_s();
+        try {
+            cluster_2mn(X, xprec, n, d, *opts, S(stream), perm, *t);
+        } catch (...) {
+            delete t;
+            throw;
+        }
+        *out = t;
+        return KRR_OK;
+    });
+}
+
+int krr_tree_from_host(const int64_t *nodes_host, int64_t n_nodes, krr_tree *out) {
+    return guard([&] {
+        KRR_REQUIRE(out != nullptr && nodes_host != nullptr && n_nodes >= 1, "krr_tree_from_host: bad arguments");
+        *out = nullptr;
+        auto *t = new krr_tree_s();
+        t->nodes.assign(nodes_host, nodes_host + 5 * n_nodes);
+        t->n = t->e(n_nodes - 1) - t->b(n_nodes - 1);
+        try {
+            validate_tree(t);
+        } catch (...) {
+            delete t;
+            throw;
+        }
+        *out = t;
+        return KRR_OK;
+    });
+}
+
+int krr_tree_size(krr_tree t, int64_t *n_host, int64_t *n_nodes_host) {
+    return guard([&] {
+        KRR_REQUIRE(t != nullptr, "krr_tree_size: NULL tree");
+        if (n_host) *n_host = t->n;
+        if (n_nodes_host) *n_nodes_host = t->n_nodes();
+        return KRR_OK;
+    });
+}
+
+int krr_tree_export(krr_tree t, int64_t *nodes_host, int64_t *stats_host) {
+    return guard([&] {
+        KRR_REQUIRE(t != nullptr, "krr_tree_export: NULL tree");
+        if (nodes_host) std::memcpy(nodes_host, t->nodes.data(), sizeof(int64_t) * t->nodes.size());
+        if (stats_host) std::memcpy(stats_host, t->stats.data(), sizeof(int64_t) * 4);
+        return KRR_OK;
+    });
+}
+
+void krr_tree_destroy(krr_tree t) { delete t; }
+
+int krr_gather_rows(const void *src, int32_t prec, int64_t n, int32_t cols, const int64_t *perm, void *dst,
+                    void *stream) {
+    return guard([&] {
+        KRR_REQUIRE(n >= 0 && cols >= 1, "krr_gather_rows: bad sizes");
+        KRR_REQUIRE(n == 0 || (src && dst && perm), "krr_gather_rows: NULL pointer");
+        check_xprec(prec);
+        require_device();
+        gather_rows(src, prec, n, cols, perm, dst, false, S(stream));
+        return KRR_OK;
+    });
+}
+
+int krr_scatter_rows(const void *src, int32_t prec, int64_t n, int32_t cols, const int64_t *perm, void *dst,
+                     void *stream) {
+    return guard([&] {
+        KRR_REQUIRE(n >= 0 && cols >= 1, "krr_scatter_rows: bad sizes");
+        KRR_REQUIRE(n == 0 || (src && dst && perm), "krr_scatter_rows: NULL pointer");
+        check_xprec(prec);
+        require_device();
+        gather_rows(src, prec, n, cols, perm, dst, true, S(stream));
+        return KRR_OK;
+    });
+}
+
+int kernel_matvec(const void *X, int64_t m, const void *Y, int64_t n, int32_t d, int32_t xprec, double h,
+                  const double *W, int32_t nrhs, double beta, double *Out, int32_t prec, void *stream) {
+    return guard([&] {
+        check_xprec(xprec);
+        KRR_REQUIRE(m >= 0 && n >= 1 && d >= 1, "kernel_matvec: need m >= 0, n >= 1, d >= 1");
+        KRR_REQUIRE(nrhs >= 1 && nrhs <= 64, "kernel_matvec: nrhs must be in [1, 64]");
+        KRR_REQUIRE(h > 0.0 && h == h, "kernel_matvec: h must be positive");
+        KRR_REQUIRE(prec == KRR_F32 || prec == KRR_F64, "kernel_matvec: prec must be KRR_F32 or KRR_F64");
+        KRR_REQUIRE(m == 0 || (X && Y && W && Out), "kernel_matvec: NULL pointer");
+        require_device();
+        kernel_matvec_impl(X, m, Y, n, d, xprec, h, W, nrhs, beta, Out, prec, S(stream));
+        return KRR_OK;
+    });
+}
+
+int kernel_sample(const void *X, int64_t n, int32_t d, int32_t xprec, double h, const float *R, int32_t r,
+                  const int32_t *leaf_begin, const int32_t *leaf_end, void *Sout, int32_t prec, int32_t split_terms,
+                  void *stream) {
+    return guard([&] {
+        check_xprec(xprec);
+        KRR_REQUIRE(n >= 1 && d >= 1, "kernel_sample: need n >= 1 and d >= 1");
+        KRR_REQUIRE(r >= 32 && r % 32 == 0, "kernel_sample: r must be a positive multiple of 32");
+        KRR_REQUIRE(h > 0.0, "kernel_sample: h must be positive");
+        KRR_REQUIRE(prec >= KRR_F64 && prec <= KRR_BF16_SPLIT, "kernel_sample: bad prec %d", prec);
+        KRR_REQUIRE(split_terms == 1 || split_terms == 2, "kernel_sample: split_terms must be 1 or 2");
+        KRR_REQUIRE((leaf_begin == nullptr) == (leaf_end == nullptr), "kernel_sample: give both leaf arrays or none");
+        KRR_REQUIRE(X && R && Sout, "kernel_sample: NULL pointer");
+        require_device();
+        sample_product(X, n, d, xprec, h, R, r, leaf_begin, leaf_end, Sout, prec, split_terms, S(stream));
+        return KRR_OK;
+    });
+}
+
+int krr_random_block(uint64_t seed, int64_t n, int32_t r, int32_t c0, float *R, void *stream) {
+    return guard([&] {
+        KRR_REQUIRE(n >= 0 && r >= 1 && c0 >= 0 && (n == 0 || R), "krr_random_block: bad arguments");
+        require_device();
+        random_block(seed, n, r, c0, R, r, S(stream));
+        return KRR_OK;
+    });
+}
+
+int kernel_matvec_bwd(const void *X, int64_t m, const void *Y, int64_t n, int32_t d, int32_t xprec, double h,
+                      const double *W, const double *G, int32_t nrhs, double *dX, double *dY, double *dW,
+                      double *dh, int32_t prec, void *stream) {
+    return guard([&] {
+        check_xprec(xprec);
+        KRR_REQUIRE(m >= 1 && n >= 1 && d >= 1 && nrhs >= 1, "kernel_matvec_bwd: bad sizes");
+        KRR_REQUIRE(h > 0.0, "kernel_matvec_bwd: h must be positive");
+        KRR_REQUIRE(prec == KRR_F32 || prec == KRR_F64, "kernel_matvec_bwd: prec must be KRR_F32 or KRR_F64");
+        KRR_REQUIRE(X && Y && W && G, "kernel_matvec_bwd: NULL pointer");
+        require_device();
+        kernel_matvec_bwd_impl(X, m, Y, n, d, xprec, h, W, G, nrhs, dX, dY, dW, dh, prec, S(stream));
+        return KRR_OK;
+    });
+}
+
+int hss_compress(krr_tree t, const void *Xp, int32_t xprec, int32_t d, double h, const hss_opts *opts, void *stream,
+                 hss_t *out, hss_stats *stats_host) {
+    return guard([&] {
+        KRR_REQUIRE(out != nullptr, "hss_compress: NULL out");
+        *out = nullptr;
+        KRR_REQUIRE(t != nullptr && opts != nullptr && Xp != nullptr, "hss_compress: NULL argument");
+        check_xprec(xprec);
+        KRR_REQUIRE(d >= 1 && h > 0.0, "hss_compress: need d >= 1 and h > 0");
+        const hss_opts &o = *opts;
+        KRR_REQUIRE(o.rtol >= 0.0 && o.atol >= 0.0, "hss_compress: tolerances must be >= 0");
+        KRR_REQUIRE(o.r0 >= 32 && o.r0 % 32 == 0, "hss_compress: r0 must be a positive multiple of 32");
+        KRR_REQUIRE(o.dr >= 32 && o.dr % 32 == 0, "hss_compress: dr must be a positive multiple of 32");
+        KRR_REQUIRE(o.r_max >= o.r0, "hss_compress: r_max < r0");
+        KRR_REQUIRE(o.oversample >= 0 && o.oversample < o.r0, "hss_compress: bad oversample");
+        KRR_REQUIRE(o.prec >= KRR_F64 && o.prec <= KRR_BF16_SPLIT, "hss_compress: bad prec");
+        KRR_REQUIRE(o.split_terms == 1 || o.split_terms == 2, "hss_compress: split_terms must be 1 or 2");
+        validate_tree(t);
+        require_device();
+        auto *H = new hss_s();
+        try {
+            compress(t, Xp, xprec, d, h, o, S(stream), H, stats_host);
+        } catch (...) {
+            delete H;
+            throw;
+        }
+        *out = H;
+        return KRR_OK;
+    });
+}
+
+void hss_destroy(hss_t H) { delete H; }
+
+int hss_export_sizes(hss_t H, int64_t *n_nodes_host, int64_t *n_dbl_host, int64_t *n_int_host) {
+    return guard([&] {
+        KRR_REQUIRE(H != nullptr, "hss_export_sizes: NULL handle");
+        if (n_nodes_host) *n_nodes_host = (int64_t)H->node.size();
+        if (n_dbl_host) *n_dbl_host = H->nU + H->nD + H->nB;
+        if (n_int_host) *n_int_host = H->nJ;
+        return KRR_OK;
+    });
+}
+
+int hss_export(hss_t H, int64_t *table_host, double *dbl_host, int64_t *int_host, void *stream) {
+    return guard([&] {
+        KRR_REQUIRE(H != nullptr && table_host && dbl_host && int_host, "hss_export: NULL argument");
+        hipStream_t s = S(stream);
+        const int64_t nn = (int64_t)H->node.size();
+        const int64_t baseD = H->nU, baseB = H->nU + H->nD;
+        for (int64_t i = 0; i < nn; ++i) {
+            const HNode &q = H->node[i];
+            int64_t *row = table_host + 10 * i;
+            row[0] = q.b;
+            row[1] = q.e;
+            row[2] = q.left;
+            row[3] = q.right;
+            row[4] = q.m;
+            row[5] = q.k;
+            row[6] = q.offU;
+            row[7] = q.offD >= 0 ? baseD + q.offD : -1;
+            row[8] = q.offB >= 0 ? baseB + q.offB : -1;
+            row[9] = q.offJ;
+        }
+        d2h(dbl_host, H->U.as<double>(), H->nU, s);
+        d2h(dbl_host + baseD, H->D.as<double>(), H->nD, s);
+        d2h(dbl_host + baseB, H->B.as<double>(), H->nB, s);
+        std::vector<int32_t> j32(H->nJ);
+        d2h(j32.data(), H->J.as<int32_t>(), H->nJ, s);
+        sync(s);
+        for (int64_t i = 0; i < H->nJ; ++i) int_host[i] = j32[i];
+        return KRR_OK;
+    });
+}
+
+int hss_ulv_factor(hss_t H, double lambda, void *stream, hss_ulv_t *out) {
+    return guard([&] {
+        KRR_REQUIRE(out != nullptr, "hss_ulv_factor: NULL out");
+        *out = nullptr;
+        KRR_REQUIRE(H != nullptr, "hss_ulv_factor: NULL handle");
+        KRR_REQUIRE(lambda >= 0.0, "hss_ulv_factor: lambda must be >= 0");
+        require_device();
+        auto *F = new hss_ulv_s();
+        try {
+            ulv_factor(H, lambda, S(stream), F);
+        } catch (...) {
+            delete F;
+            throw;
+        }
+        *out = F;
+        return KRR_OK;
+    });
+}
+
+void hss_ulv_destroy(hss_ulv_t F) { delete F; }
+
+int hss_solve(hss_ulv_t F, const double *B, int32_t nrhs, double *Xout, void *stream) {
+    return guard([&] {
+        KRR_REQUIRE(F != nullptr && B && Xout, "hss_solve: NULL argument");
+        KRR_REQUIRE(nrhs >= 1, "hss_solve: nrhs must be >= 1");
+        require_device();
+        ulv_solve(F, B, nrhs, Xout, S(stream));
+        return KRR_OK;
+    });
+}
+
+int krr_refine(hss_ulv_t F, const void *Xp, int32_t xprec, int32_t d, double h, double lambda, const double *Y,
+               int32_t nrhs, double *alpha, double tol, int32_t max_iter, int32_t mv_prec, void *stream,
+               krr_refine_stats *stats_host) {
+    return guard([&] {
+        KRR_REQUIRE(F && Xp && Y && alpha, "krr_refine: NULL argument");
+        check_xprec(xprec);
+        KRR_REQUIRE(nrhs >= 1 && nrhs <= 64, "krr_refine: nrhs must be in [1, 64]");
+        KRR_REQUIRE(h > 0.0 && lambda >= 0.0 && tol > 0.0 && max_iter >= 0, "krr_refine: bad parameters");
+        KRR_REQUIRE(mv_prec == KRR_F32 || mv_prec == KRR_F64, "krr_refine: mv_prec must be KRR_F32 or KRR_F64");
+        require_device();
+        int rc = refine(F, Xp, xprec, d, h, lambda, Y, nrhs, alpha, tol, max_iter, mv_prec, S(stream), stats_host);
+        if (rc == KRR_E_NOT_CONVERGED) g_last_error = "krr_refine: tolerance not reached within max_iter";
+        return rc;
+    });
+}
+
+int krr_predict(const void *Xt, int64_t m, const void *Xp, int64_t n, int32_t d, int32_t xprec, double h,
+                const double *alpha, int32_t nrhs, double *scores, int32_t *labels, int32_t prec, void *stream) {
+    return guard([&] {
+        check_xprec(xprec);
+        KRR_REQUIRE(m >= 0 && n >= 1 && d >= 1 && nrhs >= 1 && nrhs <= 64, "krr_predict: bad sizes");
+        KRR_REQUIRE(h > 0.0, "krr_predict: h must be positive");
+        KRR_REQUIRE(prec == KRR_F32 || prec == KRR_F64, "krr_predict: prec must be KRR_F32 or KRR_F64");
+        KRR_REQUIRE(m == 0 || (Xt && Xp && alpha && scores), "krr_predict: NULL pointer");
+        require_device();
+        kernel_matvec_impl(Xt, m, Xp, n, d, xprec, h, alpha, nrhs, 0.0, scores, prec, S(stream));
+        if (labels) predict_labels(scores, m, nrhs, labels, S(stream));
+        return KRR_OK;
+    });
+}
+
+int krr_dot_columns(const double *a, const double *b, int64_t n, int32_t k, double *out, void *stream) {
+    return guard([&] {
+        KRR_REQUIRE(a && b && out && n >= 0 && k >= 1, "krr_dot_columns: bad arguments");
+        require_device();
+        DBuf scratch;
+        dot_columns(a, b, n, k, out, scratch, S(stream));
+        sync(S(stream));
+        return KRR_OK;
+    });
+}
+
+}  // extern "C"

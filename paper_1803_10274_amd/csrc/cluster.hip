@@ -1,0 +1,517 @@
+// Recursive two-means (2MN) ordering on the GPU (Section 4.2 steps 1-3,
+// Section 4.3 "Recursive two-means"), level-synchronous: every node of a tree
+// level that is larger than the leaf size is split by the same launches.
+//
+// The split is specified down to the last bit so that it does not depend on
+// how the work is scheduled:
+//   * first seed  i1 = b + mulhi(draw(seed, b, e, 0), size);
+//   * second seed drawn with probability proportional to the Euclidean
+//     distance from the first seed, with exact integer weights
+//     w_j = isqrt(floor(q_j * 2^(62 - ex))), q_j the FP64 squared distance and
+//     2^ex > max q; u = mulhi(draw(seed, b, e, 1), sum w); i2 = first position
+//     whose inclusive prefix sum of w exceeds u;
+//   * Lloyd iterations: label 1 iff strictly closer to the second center
+//     (FP64, coordinates summed in order, no fused multiply-add); centers are
+//     sums over consecutive 256-position chunks (in order), then over chunks
+//     (in order), divided by the count; stop when no label changes, at most
+//     max_iter iterations;
+//   * empty cluster / all-equal points: split in halves by position;
+//   * stable partition, first cluster first.
+// draw() chains four SplitMix64 output steps over (seed, b, e, k).
+#include "internal.hpp"
+
+// This file is compiled with -ffp-contract=off; the pragma keeps it so even if
+// the flag is dropped.
+#pragma clang fp contract(off)
+
+namespace krr {
+namespace {
+
+constexpr int CH = 256;  // positions per chunk (also the block size of point kernels)
+constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
+enum : int32_t { ACTIVE = 0, CONVERGED = 1, FALLBACK = 2 };
+
+uint64_t sm_out(uint64_t x) {
+    uint64_t z = x + kGamma;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+uint64_t node_draw(uint64_t seed, int64_t b, int64_t e, uint64_t k) {
+    uint64_t v = sm_out(seed);
+    v = sm_out(v ^ (uint64_t)b);
+    v = sm_out(v ^ (uint64_t)e);
+    return sm_out(v ^ k);
+}
+
+uint64_t mulhi_u64(uint64_t a, uint64_t b) {
+    return (uint64_t)(((unsigned __int128)a * b) >> 64);
+}
+
+__device__ __forceinline__ uint64_t isqrt_u64(uint64_t v) {
+    uint64_t res = 0, bit = 1ull << 62;
+    while (bit > v) bit >>= 2;
+    while (bit) {
+        if (v >= res + bit) {
+            v -= res + bit;
+            res = (res >> 1) + bit;
+        } else {
+            res >>= 1;
+        }
+        bit >>= 2;
+    }
+    return res;
+}
+
+template <class T>
+__device__ __forceinline__ double sqdist_c(const T *x, const double *c, int d) {
+    double acc = 0.0;
+    for (int k = 0; k < d; ++k) {
+        double t = (double)x[k] - c[k];
+        acc = acc + t * t;
+    }
+    return acc;
+}
+
+template <class T>
+__device__ __forceinline__ double sqdist_p(const T *x, const T *y, int d) {
+    double acc = 0.0;
+    for (int k = 0; k < d; ++k) {
+        double t = (double)x[k] - (double)y[k];
+        acc = acc + t * t;
+    }
+    return acc;
+}
+
+struct Level {
+    // per active node
+    const int64_t *nb, *ne, *i1;
+    const uint64_t *draw1;
+    const int32_t *ch0, *nch;
+    int64_t *i2, *n1;
+    uint64_t *qmax, *W;
+    int32_t *status, *changed, *iters;
+    double *c0, *c1;
+    int64_t *off0, *off1;
+    // per chunk
+    const int32_t *cnode;
+    const int64_t *cb, *ce;
+    uint64_t *cw;
+    int32_t *cn1;
+    double *cps;
+    int32_t *n_active;
+};
+
+template <class T>
+__global__ void k_q(const T *__restrict__ X, int d, Level L, double *__restrict__ q) {
+    int c = blockIdx.x;
+    int node = L.cnode[c];
+    int64_t p = L.cb[c] + threadIdx.x;
+    uint64_t bits = 0;
+    if (p < L.ce[c]) {
+        double v = sqdist_p(X + p * d, X + L.i1[node] * d, d);
+        q[p] = v;
+        bits = (uint64_t)__double_as_longlong(v);
+    }
+    bits = wave_max(bits);
+    if ((threadIdx.x & 63) == 0 && bits) atomicMax((unsigned long long *)&L.qmax[node], (unsigned long long)bits);
+}
+
+__global__ void k_w(Level L, const double *__restrict__ q, uint64_t *__restrict__ w) {
+    __shared__ uint64_t part[CH / 64];
+    int c = blockIdx.x;
+    int node = L.cnode[c];
+    int64_t p = L.cb[c] + threadIdx.x;
+    double qm = __longlong_as_double((long long)L.qmax[node]);
+    uint64_t wv = 0;
+    if (p < L.ce[c] && qm > 0.0) {
+        int ex;
+        frexp(qm, &ex);
+        double v = floor(ldexp(q[p], 62 - ex));
+        wv = isqrt_u64((uint64_t)v);
+    }
+    if (p < L.ce[c]) w[p] = wv;
+    uint64_t s = wave_sum(wv);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t t = 0;
+        for (int i = 0; i < CH / 64; ++i) t += part[i];
+        L.cw[c] = t;
+        if (t) atomicAdd((unsigned long long *)&L.W[node], (unsigned long long)t);
+    }
+}
+
+__global__ void k_pick(Level L, int na, const uint64_t *__restrict__ w) {
+    int node = blockIdx.x * blockDim.x + threadIdx.x;
+    if (node >= na) return;
+    uint64_t W = L.W[node];
+    if (W == 0) {
+        L.status[node] = FALLBACK;
+        return;
+    }
+    uint64_t u = __umul64hi(L.draw1[node], W);
+    uint64_t acc = 0;
+    int c = L.ch0[node], cend = L.ch0[node] + L.nch[node];
+    for (; c < cend - 1; ++c) {
+        if (acc + L.cw[c] > u) break;
+        acc += L.cw[c];
+    }
+    int64_t i2 = L.ce[c] - 1;
+    for (int64_t p = L.cb[c]; p < L.ce[c]; ++p) {
+        acc += w[p];
+        if (acc > u) {
+            i2 = p;
+            break;
+        }
+    }
+    L.i2[node] = i2;
+}
+
+template <class T>
+__global__ void k_seed_centers(const T *__restrict__ X, int d, int na, Level L) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)na * d) return;
+    int node = (int)(t / d), k = (int)(t % d);
+    if (L.status[node] != ACTIVE) return;
+    L.c0[t] = (double)X[L.i1[node] * d + k];
+    L.c1[t] = (double)X[L.i2[node] * d + k];
+}
+
+template <class T>
+__global__ void k_assign(const T *__restrict__ X, int d, Level L, uint8_t *__restrict__ lab, int first) {
+    __shared__ int part[CH / 64];
+    __shared__ int chg[CH / 64];
+    int c = blockIdx.x;
+    int node = L.cnode[c];
+    if (L.status[node] != ACTIVE) return;
+    int64_t p = L.cb[c] + threadIdx.x;
+    int one = 0, changed = 0;
+    if (p < L.ce[c]) {
+        const T *x = X + p * d;
+        double d0 = sqdist_c(x, L.c0 + (int64_t)node * d, d);
+        double d1 = sqdist_c(x, L.c1 + (int64_t)node * d, d);
+        uint8_t lb = (d1 < d0) ? 1 : 0;
+        if (!first) changed = (lab[p] != lb);
+        lab[p] = lb;
+        one = lb;
+    }
+    int s = wave_sum(one);
+    int ch = wave_sum(changed);
+    if ((threadIdx.x & 63) == 0) {
+        part[threadIdx.x >> 6] = s;
+        chg[threadIdx.x >> 6] = ch;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0, u = 0;
+        for (int i = 0; i < CH / 64; ++i) {
+            t += part[i];
+            u += chg[i];
+        }
+        L.cn1[c] = t;
+        if (u) atomicOr(&L.changed[node], 1);
+    }
+}
+
+__global__ void k_node_update(Level L, int na, int first) {
+    int node = blockIdx.x * blockDim.x + threadIdx.x;
+    if (node >= na || L.status[node] != ACTIVE) return;
+    int64_t n1 = 0;
+    for (int c = L.ch0[node]; c < L.ch0[node] + L.nch[node]; ++c) n1 += L.cn1[c];
+    int64_t s = L.ne[node] - L.nb[node];
+    L.n1[node] = n1;
+    if (!first) L.iters[node] += 1;
+    if (n1 == 0 || n1 == s) {
+        L.status[node] = FALLBACK;
+    } else if (!first && !L.changed[node]) {
+        L.status[node] = CONVERGED;
+    } else {
+        atomicAdd(L.n_active, 1);
+    }
+    L.changed[node] = 0;
+}
+
+template <class T>
+__global__ void k_centroid_partial(const T *__restrict__ X, int d, int nc, Level L,
+                                   const uint8_t *__restrict__ lab) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)nc * d) return;
+    int c = (int)(t / d), k = (int)(t % d);
+    if (L.status[L.cnode[c]] != ACTIVE) return;
+    double p0 = 0.0, p1 = 0.0;
+    for (int64_t p = L.cb[c]; p < L.ce[c]; ++p) {
+        double v = (double)X[p * d + k];
+        if (lab[p] == 0)
+            p0 = p0 + v;
+        else
+            p1 = p1 + v;
+    }
+    L.cps[2 * t] = p0;
+    L.cps[2 * t + 1] = p1;
+}
+
+__global__ void k_centroid_final(int d, int na, Level L) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)na * d) return;
+    int node = (int)(t / d), k = (int)(t % d);
+    if (L.status[node] != ACTIVE) return;
+    double s0 = 0.0, s1 = 0.0;
+    for (int c = L.ch0[node]; c < L.ch0[node] + L.nch[node]; ++c) {
+        s0 = s0 + L.cps[2 * ((int64_t)c * d + k)];
+        s1 = s1 + L.cps[2 * ((int64_t)c * d + k) + 1];
+    }
+    int64_t n1 = L.n1[node];
+    int64_t n0 = (L.ne[node] - L.nb[node]) - n1;
+    L.c0[t] = s0 / (double)n0;
+    L.c1[t] = s1 / (double)n1;
+}
+
+__global__ void k_part_prefix(Level L, int na) {
+    int node = blockIdx.x * blockDim.x + threadIdx.x;
+    if (node >= na || L.status[node] == FALLBACK) return;
+    int64_t o0 = 0, o1 = 0;
+    for (int c = L.ch0[node]; c < L.ch0[node] + L.nch[node]; ++c) {
+        L.off0[c] = o0;
+        L.off1[c] = o1;
+        int64_t sz = L.ce[c] - L.cb[c];
+        o0 += sz - L.cn1[c];
+        o1 += L.cn1[c];
+    }
+}
+
+__global__ void k_iota(int64_t n, int64_t *__restrict__ dest) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n) dest[p] = p;
+}
+
+__global__ void k_part_dest(Level L, const uint8_t *__restrict__ lab, int64_t *__restrict__ dest) {
+    __shared__ int wz[CH / 64];
+    int c = blockIdx.x;
+    int node = L.cnode[c];
+    if (L.status[node] == FALLBACK) return;
+    int64_t p = L.cb[c] + threadIdx.x;
+    bool valid = p < L.ce[c];
+    int isz = valid && lab[p] == 0;
+    uint64_t mask = __ballot(isz);
+    int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    int before_in_wave = __popcll(mask & lt);
+    if (lane == 0) wz[wv] = __popcll(mask);
+    __syncthreads();
+    int before = before_in_wave;
+    for (int i = 0; i < wv; ++i) before += wz[i];
+    if (!valid) return;
+    int64_t nb = L.nb[node];
+    int64_t n0 = (L.ne[node] - nb) - L.n1[node];
+    int64_t pos_in_chunk = threadIdx.x;
+    if (isz)
+        dest[p] = nb + L.off0[c] + before;
+    else
+        dest[p] = nb + n0 + L.off1[c] + (pos_in_chunk - before);
+}
+
+template <class T>
+__global__ void k_move(const T *__restrict__ X, const int64_t *__restrict__ perm, int64_t n, int d,
+                       const int64_t *__restrict__ dest, T *__restrict__ Xo, int64_t *__restrict__ permo) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * d) return;
+    int64_t p = t / d;
+    int k = (int)(t % d);
+    int64_t q = dest[p];
+    Xo[q * d + k] = X[t];
+    if (k == 0) permo[q] = perm[p];
+}
+
+__global__ void k_perm_init(int64_t n, int64_t *perm) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n) perm[p] = p;
+}
+
+struct TmpNode {
+    int64_t b, e;
+    int64_t left = -1, right = -1;  // indices into the TmpNode list
+};
+
+template <class T>
+void cluster_impl(const T *X, int64_t n, int d, const krr_cluster_opts &o, hipStream_t s,
+                  int64_t *perm_out, krr_tree_s &tree) {
+    const int leaf = o.leaf_size;
+    DBuf xa = dalloc<T>(n * d), xb = dalloc<T>(n * d);
+    DBuf pa = dalloc<int64_t>(n), pb = dalloc<int64_t>(n);
+    DBuf q = dalloc<double>(n), w = dalloc<uint64_t>(n), lab = dalloc<uint8_t>(n), dest = dalloc<int64_t>(n);
+    KRR_HIP(hipMemcpyAsync(xa.get(), X, sizeof(T) * n * d, hipMemcpyDeviceToDevice, s));
+    k_perm_init<<<ceil_div(n, 256), 256, 0, s>>>(n, pa.as<int64_t>());
+    check_launch("k_perm_init");
+
+    std::vector<TmpNode> tn;
+    tn.push_back({0, n});
+    std::vector<int64_t> active;
+    if (n > leaf) active.push_back(0);
+    DBuf counter = dalloc<int32_t>(1);
+    int64_t levels = 0, fallbacks = 0, capped = 0, iterations = 0;
+
+    while (!active.empty()) {
+        ++levels;
+        const int na = (int)active.size();
+        std::vector<int64_t> nb(na), ne(na), i1(na);
+        std::vector<uint64_t> draw1(na);
+        std::vector<int32_t> ch0(na), nch(na);
+        std::vector<int32_t> cnode;
+        std::vector<int64_t> cb, ce;
+        for (int a = 0; a < na; ++a) {
+            const TmpNode &t = tn[active[a]];
+            nb[a] = t.b;
+            ne[a] = t.e;
+            uint64_t sz = (uint64_t)(t.e - t.b);
+            i1[a] = t.b + (int64_t)mulhi_u64(node_draw(o.seed, t.b, t.e, 0), sz);
+            draw1[a] = node_draw(o.seed, t.b, t.e, 1);
+            ch0[a] = (int32_t)cnode.size();
+            for (int64_t p = t.b; p < t.e; p += CH) {
+                cnode.push_back(a);
+                cb.push_back(p);
+                ce.push_back(std::min<int64_t>(p + CH, t.e));
+            }
+            nch[a] = (int32_t)cnode.size() - ch0[a];
+        }
+        const int nc = (int)cnode.size();
+        DBuf d_nb = upload(nb, s), d_ne = upload(ne, s), d_i1 = upload(i1, s), d_draw1 = upload(draw1, s);
+        DBuf d_ch0 = upload(ch0, s), d_nch = upload(nch, s), d_cnode = upload(cnode, s);
+        DBuf d_cb = upload(cb, s), d_ce = upload(ce, s);
+        DBuf d_i2 = dalloc<int64_t>(na), d_n1 = dalloc<int64_t>(na), d_qmax = dalloc<uint64_t>(na),
+             d_W = dalloc<uint64_t>(na), d_status = dalloc<int32_t>(na), d_changed = dalloc<int32_t>(na),
+             d_iters = dalloc<int32_t>(na), d_c0 = dalloc<double>((size_t)na * d),
+             d_c1 = dalloc<double>((size_t)na * d), d_off0 = dalloc<int64_t>(nc), d_off1 = dalloc<int64_t>(nc),
+             d_cw = dalloc<uint64_t>(nc), d_cn1 = dalloc<int32_t>(nc), d_cps = dalloc<double>((size_t)nc * d * 2);
+        KRR_HIP(hipMemsetAsync(d_qmax.get(), 0, sizeof(uint64_t) * na, s));
+        KRR_HIP(hipMemsetAsync(d_W.get(), 0, sizeof(uint64_t) * na, s));
+        KRR_HIP(hipMemsetAsync(d_status.get(), 0, sizeof(int32_t) * na, s));
+        KRR_HIP(hipMemsetAsync(d_changed.get(), 0, sizeof(int32_t) * na, s));
+        KRR_HIP(hipMemsetAsync(d_iters.get(), 0, sizeof(int32_t) * na, s));
+        Level L{d_nb.as<int64_t>(), d_ne.as<int64_t>(), d_i1.as<int64_t>(), d_draw1.as<uint64_t>(),
+                d_ch0.as<int32_t>(), d_nch.as<int32_t>(), d_i2.as<int64_t>(), d_n1.as<int64_t>(),
+                d_qmax.as<uint64_t>(), d_W.as<uint64_t>(), d_status.as<int32_t>(),
+                d_changed.as<int32_t>(), d_iters.as<int32_t>(), d_c0.as<double>(), d_c1.as<double>(),
+                d_off0.as<int64_t>(), d_off1.as<int64_t>(), d_cnode.as<int32_t>(), d_cb.as<int64_t>(),
+                d_ce.as<int64_t>(), d_cw.as<uint64_t>(), d_cn1.as<int32_t>(), d_cps.as<double>(),
+                counter.as<int32_t>()};
+        const T *Xc = xa.as<T>();
+        unsigned gn = ceil_div(na, 64);
+        unsigned gnd = ceil_div((int64_t)na * d, 256);
+        k_q<T><<<nc, CH, 0, s>>>(Xc, d, L, q.as<double>());
+        check_launch("k_q");
+        k_w<<<nc, CH, 0, s>>>(L, q.as<double>(), w.as<uint64_t>());
+        check_launch("k_w");
+        k_pick<<<gn, 64, 0, s>>>(L, na, w.as<uint64_t>());
+        check_launch("k_pick");
+        k_seed_centers<T><<<gnd, 256, 0, s>>>(Xc, d, na, L);
+        check_launch("k_seed_centers");
+        k_assign<T><<<nc, CH, 0, s>>>(Xc, d, L, lab.as<uint8_t>(), 1);
+        check_launch("k_assign");
+        KRR_HIP(hipMemsetAsync(counter.get(), 0, sizeof(int32_t), s));
+        k_node_update<<<gn, 64, 0, s>>>(L, na, 1);
+        check_launch("k_node_update");
+        for (int it = 0; it < o.max_iter; ++it) {
+            int32_t nact = 0;
+            d2h(&nact, counter.as<int32_t>(), 1, s);
+            sync(s);
+            if (nact == 0) break;
+            k_centroid_partial<T><<<ceil_div((int64_t)nc * d, 256), 256, 0, s>>>(Xc, d, nc, L, lab.as<uint8_t>());
+            check_launch("k_centroid_partial");
+            k_centroid_final<<<gnd, 256, 0, s>>>(d, na, L);
+            check_launch("k_centroid_final");
+            k_assign<T><<<nc, CH, 0, s>>>(Xc, d, L, lab.as<uint8_t>(), 0);
+            check_launch("k_assign");
+            KRR_HIP(hipMemsetAsync(counter.get(), 0, sizeof(int32_t), s));
+            k_node_update<<<gn, 64, 0, s>>>(L, na, 0);
+            check_launch("k_node_update");
+        }
+        k_part_prefix<<<gn, 64, 0, s>>>(L, na);
+        check_launch("k_part_prefix");
+        k_iota<<<ceil_div(n, 256), 256, 0, s>>>(n, dest.as<int64_t>());
+        check_launch("k_iota");
+        k_part_dest<<<nc, CH, 0, s>>>(L, lab.as<uint8_t>(), dest.as<int64_t>());
+        check_launch("k_part_dest");
+        k_move<T><<<ceil_div(n * d, 256), 256, 0, s>>>(xa.as<T>(), pa.as<int64_t>(), n, d, dest.as<int64_t>(),
+                                                        xb.as<T>(), pb.as<int64_t>());
+        check_launch("k_move");
+        std::swap(xa, xb);
+        std::swap(pa, pb);
+        std::vector<int64_t> n1(na);
+        std::vector<int32_t> status(na), iters(na);
+        d2h(n1.data(), d_n1.as<int64_t>(), na, s);
+        d2h(status.data(), d_status.as<int32_t>(), na, s);
+        d2h(iters.data(), d_iters.as<int32_t>(), na, s);
+        sync(s);
+        std::vector<int64_t> next;
+        for (int a = 0; a < na; ++a) {
+            int64_t id = active[a];
+            int64_t b = tn[id].b, e = tn[id].e, sz = e - b;
+            int64_t nl;
+            iterations += iters[a];
+            if (status[a] == FALLBACK) {
+                ++fallbacks;
+                nl = sz / 2;
+            } else {
+                if (status[a] == ACTIVE) ++capped;
+                nl = sz - n1[a];
+            }
+            int64_t li = (int64_t)tn.size();
+            tn.push_back({b, b + nl});
+            tn.push_back({b + nl, e});
+            tn[id].left = li;
+            tn[id].right = li + 1;
+            if (nl > leaf) next.push_back(li);
+            if (sz - nl > leaf) next.push_back(li + 1);
+        }
+        active.swap(next);
+    }
+    KRR_HIP(hipMemcpyAsync(perm_out, pa.get(), sizeof(int64_t) * n, hipMemcpyDeviceToDevice, s));
+
+    // postorder numbering of the discovered tree
+    tree.n = n;
+    tree.nodes.assign(tn.size() * 5, -1);
+    std::vector<int64_t> id_of(tn.size(), -1);
+    std::vector<std::pair<int64_t, int>> stack{{0, 0}};
+    int64_t next_id = 0;
+    while (!stack.empty()) {
+        auto &top = stack.back();
+        const TmpNode &t = tn[top.first];
+        if (t.left >= 0 && top.second == 0) {
+            top.second = 1;
+            stack.push_back({t.left, 0});
+        } else if (t.left >= 0 && top.second == 1) {
+            top.second = 2;
+            stack.push_back({t.right, 0});
+        } else {
+            int64_t id = next_id++;
+            id_of[top.first] = id;
+            int64_t *row = &tree.nodes[5 * id];
+            row[0] = t.b;
+            row[1] = t.e;
+            row[2] = t.left >= 0 ? id_of[t.left] : -1;
+            row[3] = t.right >= 0 ? id_of[t.right] : -1;
+            row[4] = -1;
+            if (t.left >= 0) {
+                tree.nodes[5 * row[2] + 4] = id;
+                tree.nodes[5 * row[3] + 4] = id;
+            }
+            stack.pop_back();
+        }
+    }
+    tree.stats = {fallbacks, capped, iterations, levels};
+    sync(s);  // keep the temporaries alive until the last copy is done
+}
+
+}  // namespace
+
+void cluster_2mn(const void *X, int32_t xprec, int64_t n, int32_t d, const krr_cluster_opts &o,
+                 hipStream_t s, int64_t *perm, krr_tree_s &tree) {
+    if (xprec == KRR_F64)
+        cluster_impl<double>(static_cast<const double *>(X), n, d, o, s, perm, tree);
+    else
+        cluster_impl<float>(static_cast<const float *>(X), n, d, o, s, perm, tree);
+}
+
+}  // namespace krr

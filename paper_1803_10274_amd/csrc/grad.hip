@@ -1,0 +1,147 @@
+// Backward of the fused kernel product Out = K(X, Y; h) W for an upstream
+// gradient G.  With P = K o (G W^T) (never stored):
+//   dW   = K(X, Y)^T G = K(Y, X) G                     (a kernel product)
+//   dX_i = -(1/h^2) [ (sum_j P_ij) x_i - (P Y)_i ]
+//   dY_j = -(1/h^2) [ (sum_i P_ij) y_j - (P^T X)_j ]   (same form, roles swapped)
+//   dh   = sum_ij P_ij ||x_i - y_j||^2 / h^3
+// One thread per row of the left operand; right-operand tiles in LDS; FP32
+// entries from exact differences inside a 64-column tile, FP64 across tiles
+// (FP64 throughout for prec = KRR_F64).
+#include "internal.hpp"
+
+namespace krr {
+
+void kernel_matvec_impl(const void *X, int64_t m, const void *Y, int64_t n, int d, int xprec, double h,
+                        const double *W, int nrhs, double beta, double *Out, int prec, hipStream_t s);
+
+namespace {
+constexpr int GB_ROWS = 256, GB_TN = 32, GB_DMAX = 64, GB_RMAX = 16;
+
+__device__ __forceinline__ float gexp(float q, float s2) { return __builtin_amdgcn_exp2f(-q * s2); }
+__device__ __forceinline__ double gexp(double q, double s) { return exp(-q * s); }
+
+// For rows a of A: s_a = sum_b P_ab, t_a = sum_b P_ab B_b, u_a = sum_b P_ab ||A_a - B_b||^2
+// with P_ab = K(A_a, B_b) (GA_a . GB_b).  Writes dA_a = -(1/h^2)(s_a A_a - t_a)
+// and u_a (for dh) when the pointers are given.
+template <class T, class C>
+__global__ __launch_bounds__(GB_ROWS) void k_bwd_rows(const T *__restrict__ A, int64_t ma, const T *__restrict__ B,
+                                                      int64_t nb, int d, C scale, const double *__restrict__ GA,
+                                                      const double *__restrict__ GB, int nrhs, double inv_h2,
+                                                      double *__restrict__ dA, double *__restrict__ u_out) {
+    __shared__ C bs[GB_TN][GB_DMAX];
+    __shared__ C gbs[GB_TN][GB_RMAX];
+    const int tid = threadIdx.x;
+    const int64_t a = (int64_t)blockIdx.x * GB_ROWS + tid;
+    C xa[GB_DMAX];
+    C ga[GB_RMAX];
+#pragma unroll
+    for (int k = 0; k < GB_DMAX; ++k) xa[k] = (a < ma && k < d) ? (C)A[a * d + k] : (C)0;
+#pragma unroll
+    for (int r = 0; r < GB_RMAX; ++r) ga[r] = (a < ma && r < nrhs) ? (C)GA[a * nrhs + r] : (C)0;
+    double s = 0.0, u = 0.0;
+    double t[GB_DMAX];
+#pragma unroll
+    for (int k = 0; k < GB_DMAX; ++k) t[k] = 0.0;
+    for (int64_t j0 = 0; j0 < nb; j0 += GB_TN) {
+        for (int e = tid; e < GB_TN * GB_DMAX; e += GB_ROWS) {
+            int jj = e / GB_DMAX, k = e % GB_DMAX;
+            int64_t j = j0 + jj;
+            bs[jj][k] = (j < nb && k < d) ? (C)B[j * d + k] : (C)0;
+        }
+        for (int e = tid; e < GB_TN * GB_RMAX; e += GB_ROWS) {
+            int jj = e / GB_RMAX, r = e % GB_RMAX;
+            int64_t j = j0 + jj;
+            gbs[jj][r] = (j < nb && r < nrhs) ? (C)GB[j * nrhs + r] : (C)0;
+        }
+        __syncthreads();
+        C ps = 0, pu = 0;
+        C pt[GB_DMAX];
+#pragma unroll
+        for (int k = 0; k < GB_DMAX; ++k) pt[k] = 0;
+        for (int jj = 0; jj < GB_TN; ++jj) {
+            C q = 0;
+#pragma unroll
+            for (int k = 0; k < GB_DMAX; ++k) {
+                C df = xa[k] - bs[jj][k];
+                q = fma(df, df, q);
+            }
+            C g = 0;
+#pragma unroll
+            for (int r = 0; r < GB_RMAX; ++r) g = fma(ga[r], gbs[jj][r], g);
+            C p = gexp(q, scale) * g;
+            ps += p;
+            pu = fma(p, q, pu);
+#pragma unroll
+            for (int k = 0; k < GB_DMAX; ++k) pt[k] = fma(p, bs[jj][k], pt[k]);
+        }
+        s += (double)ps;
+        u += (double)pu;
+#pragma unroll
+        for (int k = 0; k < GB_DMAX; ++k) t[k] += (double)pt[k];
+        __syncthreads();
+    }
+    if (a >= ma) return;
+    if (dA)
+        for (int k = 0; k < d; ++k) dA[a * d + k] = -inv_h2 * (s * (double)A[a * d + k] - t[k]);
+    if (u_out) u_out[a] = u;
+}
+
+__global__ void k_sum_scaled(const double *__restrict__ u, int64_t m, double scale, double *__restrict__ out) {
+    __shared__ double red[4];
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < m; i += blockDim.x) acc += u[i];
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) *out = scale * (red[0] + red[1] + red[2] + red[3]);
+}
+
+template <class T, class C>
+void bwd_rows(const T *A, int64_t ma, const T *B, int64_t nb, int d, double h, const double *GA, const double *GB,
+              int nrhs, double *dA, double *u, hipStream_t s) {
+    C scale = (sizeof(C) == 4) ? (C)(1.4426950408889634 / (2.0 * h * h)) : (C)(1.0 / (2.0 * h * h));
+    k_bwd_rows<T, C><<<ceil_div(ma, GB_ROWS), GB_ROWS, 0, s>>>(A, ma, B, nb, d, scale, GA, GB, nrhs, 1.0 / (h * h),
+                                                                dA, u);
+    check_launch("k_bwd_rows");
+}
+
+template <class T>
+void bwd_typed(const T *X, int64_t m, const T *Y, int64_t n, int d, double h, const double *W, const double *G,
+               int nrhs, double *dX, double *dY, double *dh, int prec, hipStream_t s) {
+    DBuf u;
+    if (dh) u = dalloc<double>(m);
+    if (dX || dh) {
+        if (prec == KRR_F64)
+            bwd_rows<T, double>(X, m, Y, n, d, h, G, W, nrhs, dX, dh ? u.as<double>() : nullptr, s);
+        else
+            bwd_rows<T, float>(X, m, Y, n, d, h, G, W, nrhs, dX, dh ? u.as<double>() : nullptr, s);
+    }
+    if (dY) {
+        if (prec == KRR_F64)
+            bwd_rows<T, double>(Y, n, X, m, d, h, W, G, nrhs, dY, nullptr, s);
+        else
+            bwd_rows<T, float>(Y, n, X, m, d, h, W, G, nrhs, dY, nullptr, s);
+    }
+    if (dh) {
+        k_sum_scaled<<<1, 256, 0, s>>>(u.as<double>(), m, 1.0 / (h * h * h), dh);
+        check_launch("k_sum_scaled");
+        sync(s);
+    }
+}
+}  // namespace
+
+void kernel_matvec_bwd_impl(const void *X, int64_t m, const void *Y, int64_t n, int d, int xprec, double h,
+                            const double *W, const double *G, int nrhs, double *dX, double *dY, double *dW,
+                            double *dh, int prec, hipStream_t s) {
+    KRR_REQUIRE(d <= GB_DMAX, "kernel_matvec_bwd: d = %d exceeds %d", d, GB_DMAX);
+    KRR_REQUIRE(nrhs <= GB_RMAX, "kernel_matvec_bwd: nrhs = %d exceeds %d", nrhs, GB_RMAX);
+    if (dW) kernel_matvec_impl(Y, n, X, m, d, xprec, h, G, nrhs, 0.0, dW, prec, s);
+    if (xprec == KRR_F64)
+        bwd_typed<double>(static_cast<const double *>(X), m, static_cast<const double *>(Y), n, d, h, W, G, nrhs, dX,
+                          dY, dh, prec, s);
+    else
+        bwd_typed<float>(static_cast<const float *>(X), m, static_cast<const float *>(Y), n, d, h, W, G, nrhs, dX, dY,
+                         dh, prec, s);
+}
+
+}  // namespace krr

@@ -1,0 +1,440 @@
+// Gaussian-kernel products without storing K (eq. (1.1)):
+//   * kernel_matvec: Out = K(X, Y; h) W for a few right-hand sides, entries
+//     formed from exact coordinate differences (no norm expansion, so no
+//     cancellation), FP32 sums over a 64-column tile and FP64 across tiles;
+//   * the tiled VALU sampling product S = K R with each row's own leaf block
+//     removed (Section 3.1 randomized construction), used for FP64 samples
+//     and as the portable reference of the matrix-core sampler;
+//   * small helpers: the +-1 random block, row gather / scatter, column dots.
+#include "internal.hpp"
+
+namespace krr {
+
+// ------------------------------------------------------------------ exp
+
+__device__ __forceinline__ float kexp(float q, float s2) {
+    // exp(-q / (2 h^2)) = exp2(-q * log2(e) / (2 h^2)); v_exp_f32
+    return __builtin_amdgcn_exp2f(-q * s2);
+}
+__device__ __forceinline__ double kexp(double q, double s) { return exp(-q * s); }
+
+template <class C> C kernel_scale(double h);
+template <> float kernel_scale<float>(double h) { return (float)(1.4426950408889634 / (2.0 * h * h)); }
+template <> double kernel_scale<double>(double h) { return 1.0 / (2.0 * h * h); }
+
+// ---------------------------------------------------------- kernel_matvec
+
+namespace {
+constexpr int MV_ROWS = 256;
+constexpr int MV_TN = 64;
+
+// part[(split * m + i) * nrhs + rhs0 + r] = sum over the split's columns.
+template <class T, class C, int D, int NR>
+__global__ __launch_bounds__(MV_ROWS) void k_kmv(const T *__restrict__ X, int64_t m,
+                                                 const T *__restrict__ Y, int64_t n, int d, C scale,
+                                                 const double *__restrict__ W, int nrhs, int rhs0,
+                                                 int64_t cols_per_split, double *__restrict__ part) {
+    __shared__ C ys[MV_TN][D];
+    __shared__ C ws[MV_TN][NR];
+    const int tid = threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * MV_ROWS + tid;
+    const int split = blockIdx.y;
+    const int64_t j0 = split * cols_per_split;
+    const int64_t j1 = min(n, j0 + cols_per_split);
+    C x[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) x[k] = (i < m && k < d) ? (C)X[i * d + k] : (C)0;
+    double acc[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) acc[r] = 0.0;
+    const int nr = min(NR, nrhs - rhs0);
+    for (int64_t jt = j0; jt < j1; jt += MV_TN) {
+        for (int t = tid; t < MV_TN * D; t += MV_ROWS) {
+            int jj = t / D, k = t % D;
+            int64_t j = jt + jj;
+            ys[jj][k] = (j < j1 && k < d) ? (C)Y[j * d + k] : (C)0;
+        }
+        for (int t = tid; t < MV_TN * NR; t += MV_ROWS) {
+            int jj = t / NR, r = t % NR;
+            int64_t j = jt + jj;
+            ws[jj][r] = (j < j1 && r < nr) ? (C)W[j * nrhs + rhs0 + r] : (C)0;
+        }
+        __syncthreads();
+        C pacc[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) pacc[r] = (C)0;
+        for (int jj = 0; jj < MV_TN; ++jj) {
+            C q = (C)0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                C t = x[k] - ys[jj][k];
+                q = fma(t, t, q);
+            }
+            C kv = kexp(q, scale);
+#pragma unroll
+            for (int r = 0; r < NR; ++r) pacc[r] = fma(kv, ws[jj][r], pacc[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < NR; ++r) acc[r] += (double)pacc[r];
+        __syncthreads();
+    }
+    if (i < m) {
+        for (int r = 0; r < nr; ++r) part[((int64_t)split * m + i) * nrhs + rhs0 + r] = acc[r];
+    }
+}
+
+// Large d: coordinates streamed from memory instead of registers.
+template <class T, class C, int NR>
+__global__ __launch_bounds__(MV_ROWS) void k_kmv_wide(const T *__restrict__ X, int64_t m,
+                                                      const T *__restrict__ Y, int64_t n, int d, C scale,
+                                                      const double *__restrict__ W, int nrhs, int rhs0,
+                                                      int64_t cols_per_split, double *__restrict__ part) {
+    constexpr int TK = 64;
+    __shared__ C ys[16][TK + 1];
+    __shared__ C ws[16][NR];
+    const int tid = threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * MV_ROWS + tid;
+    const int split = blockIdx.y;
+    const int64_t j0 = split * cols_per_split;
+    const int64_t j1 = min(n, j0 + cols_per_split);
+    const int nr = min(NR, nrhs - rhs0);
+    double acc[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) acc[r] = 0.0;
+    const T *xr = X + (i < m ? i : 0) * (int64_t)d;
+    for (int64_t jt = j0; jt < j1; jt += 16) {
+        C q[16];
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) q[jj] = (C)0;
+        for (int k0 = 0; k0 < d; k0 += TK) {
+            for (int t = tid; t < 16 * TK; t += MV_ROWS) {
+                int jj = t / TK, k = t % TK;
+                int64_t j = jt + jj;
+                ys[jj][k] = (j < j1 && k0 + k < d) ? (C)Y[j * d + k0 + k] : (C)0;
+            }
+            __syncthreads();
+            int kend = min(TK, d - k0);
+            for (int k = 0; k < kend; ++k) {
+                C xv = (C)xr[k0 + k];
+#pragma unroll
+                for (int jj = 0; jj < 16; ++jj) {
+                    C t = xv - ys[jj][k];
+                    q[jj] = fma(t, t, q[jj]);
+                }
+            }
+            __syncthreads();
+        }
+        for (int t = tid; t < 16 * NR; t += MV_ROWS) {
+            int jj = t / NR, r = t % NR;
+            int64_t j = jt + jj;
+            ws[jj][r] = (j < j1 && r < nr) ? (C)W[j * nrhs + rhs0 + r] : (C)0;
+        }
+        __syncthreads();
+        C pacc[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) pacc[r] = (C)0;
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) {
+            C kv = kexp(q[jj], scale);
+#pragma unroll
+            for (int r = 0; r < NR; ++r) pacc[r] = fma(kv, ws[jj][r], pacc[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < NR; ++r) acc[r] += (double)pacc[r];
+        __syncthreads();
+    }
+    if (i < m) {
+        for (int r = 0; r < nr; ++r) part[((int64_t)split * m + i) * nrhs + rhs0 + r] = acc[r];
+    }
+}
+
+__global__ void k_reduce_splits(const double *__restrict__ part, int nsplit, int64_t mn, double beta,
+                                double *__restrict__ out) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= mn) return;
+    double s = 0.0;
+    for (int k = 0; k < nsplit; ++k) s += part[(int64_t)k * mn + t];
+    out[t] = (beta != 0.0) ? s + beta * out[t] : s;
+}
+
+template <class T, class C, int D, int NR>
+void launch_kmv(const T *X, int64_t m, const T *Y, int64_t n, int d, C scale, const double *W,
+                int nrhs, int rhs0, int nsplit, int64_t cps, double *part, hipStream_t s) {
+    dim3 grid(ceil_div(m, MV_ROWS), nsplit);
+    if (D > 0)
+        k_kmv<T, C, (D > 0 ? D : 1), NR><<<grid, MV_ROWS, 0, s>>>(X, m, Y, n, d, scale, W, nrhs, rhs0, cps, part);
+    else
+        k_kmv_wide<T, C, NR><<<grid, MV_ROWS, 0, s>>>(X, m, Y, n, d, scale, W, nrhs, rhs0, cps, part);
+    check_launch("k_kmv");
+}
+
+template <class T, class C, int NR>
+void dispatch_d(const T *X, int64_t m, const T *Y, int64_t n, int d, C scale, const double *W, int nrhs,
+                int rhs0, int nsplit, int64_t cps, double *part, hipStream_t s) {
+    if (d <= 8)
+        launch_kmv<T, C, 8, NR>(X, m, Y, n, d, scale, W, nrhs, rhs0, nsplit, cps, part, s);
+    else if (d <= 16)
+        launch_kmv<T, C, 16, NR>(X, m, Y, n, d, scale, W, nrhs, rhs0, nsplit, cps, part, s);
+    else if (d <= 32)
+        launch_kmv<T, C, 32, NR>(X, m, Y, n, d, scale, W, nrhs, rhs0, nsplit, cps, part, s);
+    else if (d <= 64)
+        launch_kmv<T, C, 64, NR>(X, m, Y, n, d, scale, W, nrhs, rhs0, nsplit, cps, part, s);
+    else
+        launch_kmv<T, C, 0, NR>(X, m, Y, n, d, scale, W, nrhs, rhs0, nsplit, cps, part, s);
+}
+
+template <class T, class C>
+void kmv_typed(const T *X, int64_t m, const T *Y, int64_t n, int d, double h, const double *W, int nrhs,
+               double beta, double *Out, hipStream_t s) {
+    const C scale = kernel_scale<C>(h);
+    // split the columns so that the grid has enough blocks to fill the chip
+    const int64_t row_blocks = ceil_div(m, MV_ROWS);
+    int nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(2048, row_blocks), ceil_div(n, 4 * MV_TN)));
+    int64_t cps = (int64_t)ceil_div(n, nsplit);
+    cps = (cps + MV_TN - 1) / MV_TN * MV_TN;
+    nsplit = (int)ceil_div(n, cps);
+    DBuf part = dalloc<double>((size_t)nsplit * m * nrhs);
+    for (int r0 = 0; r0 < nrhs;) {
+        int left = nrhs - r0;
+        if (left >= 16) {
+            dispatch_d<T, C, 16>(X, m, Y, n, d, scale, W, nrhs, r0, nsplit, cps, part.as<double>(), s);
+            r0 += 16;
+        } else if (left >= 8) {
+            dispatch_d<T, C, 8>(X, m, Y, n, d, scale, W, nrhs, r0, nsplit, cps, part.as<double>(), s);
+            r0 += 8;
+        } else if (left >= 4) {
+            dispatch_d<T, C, 4>(X, m, Y, n, d, scale, W, nrhs, r0, nsplit, cps, part.as<double>(), s);
+            r0 += 4;
+        } else if (left >= 2) {
+            dispatch_d<T, C, 2>(X, m, Y, n, d, scale, W, nrhs, r0, nsplit, cps, part.as<double>(), s);
+            r0 += 2;
+        } else {
+            dispatch_d<T, C, 1>(X, m, Y, n, d, scale, W, nrhs, r0, nsplit, cps, part.as<double>(), s);
+            r0 += 1;
+        }
+    }
+    const int64_t mn = m * nrhs;
+    k_reduce_splits<<<ceil_div(mn, 256), 256, 0, s>>>(part.as<double>(), nsplit, mn, beta, Out);
+    check_launch("k_reduce_splits");
+    sync(s);  // `part` is released on return
+}
+}  // namespace
+
+void kernel_matvec_impl(const void *X, int64_t m, const void *Y, int64_t n, int d, int xprec, double h,
+                        const double *W, int nrhs, double beta, double *Out, int prec, hipStream_t s) {
+    if (m == 0) return;
+    if (n == 0) {
+        fail(KRR_E_INVAL, "kernel_matvec: n == 0");
+    }
+    if (xprec == KRR_F64) {
+        auto Xd = static_cast<const double *>(X);
+        auto Yd = static_cast<const double *>(Y);
+        if (prec == KRR_F64)
+            kmv_typed<double, double>(Xd, m, Yd, n, d, h, W, nrhs, beta, Out, s);
+        else
+            kmv_typed<double, float>(Xd, m, Yd, n, d, h, W, nrhs, beta, Out, s);
+    } else {
+        auto Xf = static_cast<const float *>(X);
+        auto Yf = static_cast<const float *>(Y);
+        if (prec == KRR_F64)
+            kmv_typed<float, double>(Xf, m, Yf, n, d, h, W, nrhs, beta, Out, s);
+        else
+            kmv_typed<float, float>(Xf, m, Yf, n, d, h, W, nrhs, beta, Out, s);
+    }
+}
+
+// ------------------------------------------------- tiled VALU sampling
+
+namespace {
+constexpr int SP_TM = 64, SP_TR = 64, SP_TK = 16;
+
+// S[i, c] = sum_{j not in own leaf} K(x_i, x_j) R[j, c] for the block's 64 rows
+// and 64 columns.  Thread (ty, tx) owns rows 4 ty.. and columns 4 tx..
+template <class T, class C, class RT, class ST>
+__global__ __launch_bounds__(256) void k_sample_valu(const T *__restrict__ X, int64_t n, int d, C scale,
+                                                     const RT *__restrict__ R, int r,
+                                                     const int32_t *__restrict__ lb,
+                                                     const int32_t *__restrict__ le, ST *__restrict__ S) {
+    __shared__ C es[SP_TK][SP_TM + 1];
+    __shared__ C rs[SP_TK][SP_TR];
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    const int64_t i0 = (int64_t)blockIdx.x * SP_TM;
+    const int c0 = blockIdx.y * SP_TR;
+    C acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = (C)0;
+    // the entry this thread evaluates in each E tile: row er, column ej
+    const int er = tid & 63, ej = tid >> 6;  // 64 rows x 4 column groups (4 entries each)
+    const int64_t gi = i0 + er;
+    const bool row_ok = gi < n;
+    const int32_t my_lb = row_ok && lb ? lb[gi] : 0, my_le = row_ok && le ? le[gi] : 0;
+    for (int64_t jt = 0; jt < n; jt += SP_TK) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            int jj = ej * 4 + u;
+            int64_t j = jt + jj;
+            C v = (C)0;
+            if (row_ok && j < n && !(j >= my_lb && j < my_le)) {
+                C q = (C)0;
+                for (int k = 0; k < d; ++k) {
+                    C t = (C)X[gi * d + k] - (C)X[j * d + k];
+                    q = fma(t, t, q);
+                }
+                v = kexp(q, scale);
+            }
+            es[jj][er] = v;
+        }
+        for (int t = tid; t < SP_TK * SP_TR; t += 256) {
+            int jj = t / SP_TR, c = t % SP_TR;
+            int64_t j = jt + jj;
+            rs[jj][c] = (j < n && c0 + c < r) ? (C)R[j * r + c0 + c] : (C)0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int jj = 0; jj < SP_TK; ++jj) {
+            C ev[4], rv[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) ev[a] = es[jj][4 * ty + a];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) rv[b] = rs[jj][4 * tx + b];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] = fma(ev[a], rv[b], acc[a][b]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        int64_t i = i0 + 4 * ty + a;
+        if (i >= n) continue;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            int c = c0 + 4 * tx + b;
+            if (c < r) S[i * r + c] = (ST)acc[a][b];
+        }
+    }
+}
+}  // namespace
+
+void sample_valu(const void *X, int64_t n, int d, int xprec, double h, const float *R, int r,
+                 const int32_t *lb, const int32_t *le, void *S, int prec, hipStream_t s) {
+    dim3 grid(ceil_div(n, SP_TM), ceil_div(r, SP_TR));
+    if (prec == KRR_F64) {
+        double sc = kernel_scale<double>(h);
+        if (xprec == KRR_F64)
+            k_sample_valu<double, double, float, double><<<grid, 256, 0, s>>>(
+                static_cast<const double *>(X), n, d, sc, R, r, lb, le, static_cast<double *>(S));
+        else
+            k_sample_valu<float, double, float, double><<<grid, 256, 0, s>>>(
+                static_cast<const float *>(X), n, d, sc, R, r, lb, le, static_cast<double *>(S));
+    } else {
+        float sc = kernel_scale<float>(h);
+        if (xprec == KRR_F64)
+            k_sample_valu<double, float, float, float><<<grid, 256, 0, s>>>(
+                static_cast<const double *>(X), n, d, sc, R, r, lb, le, static_cast<float *>(S));
+        else
+            k_sample_valu<float, float, float, float><<<grid, 256, 0, s>>>(
+                static_cast<const float *>(X), n, d, sc, R, r, lb, le, static_cast<float *>(S));
+    }
+    check_launch("k_sample_valu");
+}
+
+// ------------------------------------------------------------ helpers
+
+namespace {
+__device__ __forceinline__ uint64_t rb_mix(uint64_t x) {
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ void k_random_block(uint64_t seed, int64_t n, int r, int c0, float *__restrict__ R, int ldr) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * r) return;
+    int64_t i = t / r;
+    int c = (int)(t % r);
+    uint64_t v = rb_mix(rb_mix(rb_mix(seed) ^ (uint64_t)i) ^ (uint64_t)(c0 + c));
+    R[i * ldr + c] = (v >> 63) ? -1.0f : 1.0f;
+}
+
+template <class T>
+__global__ void k_gather(const T *__restrict__ src, int64_t n, int cols, const int64_t *__restrict__ perm,
+                         T *__restrict__ dst, int scatter) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * cols) return;
+    int64_t i = t / cols;
+    int c = (int)(t % cols);
+    if (scatter)
+        dst[perm[i] * cols + c] = src[t];
+    else
+        dst[t] = src[perm[i] * cols + c];
+}
+
+constexpr int DOT_BLOCK = 256, DOT_ROWS = 4096;
+
+__global__ void k_dot_partial(const double *__restrict__ a, const double *__restrict__ b, int64_t n, int k,
+                              double *__restrict__ part) {
+    __shared__ double red[DOT_BLOCK / 64];
+    const int c = blockIdx.y;
+    const int64_t r0 = (int64_t)blockIdx.x * DOT_ROWS;
+    const int64_t r1 = min(n, r0 + DOT_ROWS);
+    double s = 0.0;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += DOT_BLOCK) s += a[i * k + c] * b[i * k + c];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < DOT_BLOCK / 64; ++w) t += red[w];
+        part[(int64_t)c * gridDim.x + blockIdx.x] = t;
+    }
+}
+
+__global__ void k_dot_final(const double *__restrict__ part, int nb, int k, double *__restrict__ out) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= k) return;
+    double t = 0.0;
+    for (int b = 0; b < nb; ++b) t += part[(int64_t)c * nb + b];
+    out[c] = t;
+}
+}  // namespace
+
+void random_block(uint64_t seed, int64_t n, int r, int c0, float *R, int ldr, hipStream_t s) {
+    if (n * r == 0) return;
+    k_random_block<<<ceil_div(n * r, 256), 256, 0, s>>>(seed, n, r, c0, R, ldr);
+    check_launch("k_random_block");
+}
+
+void gather_rows(const void *src, int prec, int64_t n, int cols, const int64_t *perm, void *dst, bool scatter,
+                 hipStream_t s) {
+    if (n * cols == 0) return;
+    unsigned g = ceil_div(n * cols, 256);
+    switch (prec) {
+        case KRR_F64:
+            k_gather<double><<<g, 256, 0, s>>>(static_cast<const double *>(src), n, cols, perm,
+                                               static_cast<double *>(dst), scatter);
+            break;
+        case KRR_F32:
+            k_gather<float><<<g, 256, 0, s>>>(static_cast<const float *>(src), n, cols, perm,
+                                              static_cast<float *>(dst), scatter);
+            break;
+        default:
+            fail(KRR_E_INVAL, "gather: unsupported dtype %d", prec);
+    }
+    check_launch("k_gather");
+}
+
+void dot_columns(const double *a, const double *b, int64_t n, int k, double *out, DBuf &scratch, hipStream_t s) {
+    int nb = (int)std::max<int64_t>(1, ceil_div(n, DOT_ROWS));
+    scratch.reserve(sizeof(double) * (size_t)nb * k);
+    k_dot_partial<<<dim3(nb, k), DOT_BLOCK, 0, s>>>(a, b, n, k, scratch.as<double>());
+    check_launch("k_dot_partial");
+    k_dot_final<<<ceil_div(k, 64), 64, 0, s>>>(scratch.as<double>(), nb, k, out);
+    check_launch("k_dot_final");
+}
+
+}  // namespace krr

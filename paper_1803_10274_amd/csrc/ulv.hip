@@ -1,0 +1,469 @@
+// ULV factorization and solve of K_hss + lambda I (Section 3.1; lambda is
+// added to the leaf diagonal blocks only, Section 5.3).
+//
+// Bottom-up over the levels, one workgroup per node, with the node's dense
+// block Dw (m x m) and basis Uw (m x k):
+//   leaf    Dw = D + lambda I,  Uw = U
+//   parent  Dw = [[S_a, Rh_a B_ab Rh_b^T], [(.)^T, S_b]],  Uw = diag(Rh_a, Rh_b) U
+// 1. Householder QR  Q^T Uw = [Rh; 0]  (Rh k x k is passed to the parent);
+// 2. Dw <- Q^T Dw Q;  the last m - k rows no longer couple to the rest of the
+//    matrix, so with Dw = [[A_cc, A_ce], [A_ec, A_ee]]:
+// 3. A_ee = L L^T (Cholesky), W = A_ce L^{-T}, S = A_cc - W W^T (passed up);
+// the root factors its whole Dw.  Solve: forward sweep b <- Q^T b,
+// z = L^{-1} b_e, c = b_c - W z passed up; root solve; backward sweep
+// x_e = L^{-T} (z - W^T x_c), x = Q [x_c; x_e].
+#include <algorithm>
+#include <cstring>
+
+#include "dense.hpp"
+#include "internal.hpp"
+
+namespace krr {
+namespace {
+
+struct UlvDesc {
+    int32_t m, k, kl, kr, leaf, root;
+    double lambda;
+    const double *D, *U, *B;           // HSS generators
+    const double *S_l, *S_r, *Rh_l, *Rh_r;
+    double *Dw, *Uw, *Tmp;             // scratch
+    double *V, *tau, *L, *W;           // factor
+    double *S_out, *Rh_out;            // passed to the parent
+};
+
+__global__ __launch_bounds__(BG_T) void k_ulv_factor(const UlvDesc *dsc, int32_t *flag) {
+    __shared__ double smem[2 * 16 * 65];
+    __shared__ double red[BG_T / 64];
+    const UlvDesc q = dsc[blockIdx.x];
+    const int m = q.m, k = q.k, ne = m - k, tid = threadIdx.x;
+    double *Dw = q.Dw, *Uw = q.Uw;
+    // ---- assemble
+    if (q.leaf) {
+        for (int t = tid; t < m * m; t += BG_T) Dw[t] = q.D[t] + ((t / m == t % m) ? q.lambda : 0.0);
+        for (int t = tid; t < m * k; t += BG_T) Uw[t] = q.U[t];
+    } else {
+        const int kl = q.kl, kr = q.kr;
+        for (int t = tid; t < kl * kl; t += BG_T) Dw[(t / kl) * m + t % kl] = q.S_l[t];
+        for (int t = tid; t < kr * kr; t += BG_T) Dw[(kl + t / kr) * m + kl + t % kr] = q.S_r[t];
+        __syncthreads();
+        // Tmp = B Rh_r^T (kl x kr);  Dw[0:kl, kl:] = Rh_l Tmp
+        block_gemm(kl, kr, kr, 1.0, q.B, kr, 1, q.Rh_r, 1, kr, 0.0, q.Tmp, kr, smem);
+        block_gemm(kl, kr, kl, 1.0, q.Rh_l, kl, 1, q.Tmp, kr, 1, 0.0, Dw + kl, m, smem);
+        for (int t = tid; t < kl * kr; t += BG_T) {
+            int i = t / kr, j = t % kr;
+            Dw[(int64_t)(kl + j) * m + i] = Dw[(int64_t)i * m + kl + j];
+        }
+        if (!q.root) {
+            block_gemm(kl, k, kl, 1.0, q.Rh_l, kl, 1, q.U, k, 1, 0.0, Uw, k, smem);
+            block_gemm(kr, k, kr, 1.0, q.Rh_r, kr, 1, q.U + (int64_t)kl * k, k, 1, 0.0, Uw + (int64_t)kl * k, k, smem);
+        }
+    }
+    __syncthreads();
+    // ---- Householder QR of Uw, reflectors applied to Dw from both sides
+    for (int j = 0; j < k; ++j) {
+        double part = 0.0;
+        for (int i = j + 1 + tid; i < m; i += BG_T) part += Uw[(int64_t)i * k + j] * Uw[(int64_t)i * k + j];
+        double sig = block_sum(part, red);
+        double alpha = Uw[(int64_t)j * k + j];
+        double tau, beta, scal;
+        if (sig == 0.0) {
+            tau = 0.0;
+            beta = alpha;
+            scal = 0.0;
+        } else {
+            double nrm = sqrt(alpha * alpha + sig);
+            beta = alpha >= 0.0 ? -nrm : nrm;
+            tau = (beta - alpha) / beta;
+            scal = 1.0 / (alpha - beta);
+        }
+        // reflector v: v[j] = 1, v[i > j] = x[i] * scal; stored in column j of V
+        for (int i = tid; i < m; i += BG_T) {
+            double v = (i < j) ? 0.0 : (i == j ? 1.0 : Uw[(int64_t)i * k + j] * scal);
+            q.V[(int64_t)i * k + j] = v;
+        }
+        if (tid == 0) q.tau[j] = tau;
+        __syncthreads();
+        const double *v = q.V + j;  // stride k
+        // Uw[j:, c] for c > j
+        for (int c = j + 1 + tid; c < k; c += BG_T) {
+            double w = 0.0;
+            for (int i = j; i < m; ++i) w += v[(int64_t)i * k] * Uw[(int64_t)i * k + c];
+            w *= tau;
+            for (int i = j; i < m; ++i) Uw[(int64_t)i * k + c] -= w * v[(int64_t)i * k];
+        }
+        __syncthreads();
+        if (tid == 0) Uw[(int64_t)j * k + j] = beta;
+        for (int i = j + 1 + tid; i < m; i += BG_T) Uw[(int64_t)i * k + j] = 0.0;
+        // Dw <- H Dw (columns), then Dw <- Dw H (rows)
+        for (int c = tid; c < m; c += BG_T) {
+            double w = 0.0;
+            for (int i = j; i < m; ++i) w += v[(int64_t)i * k] * Dw[(int64_t)i * m + c];
+            w *= tau;
+            for (int i = j; i < m; ++i) Dw[(int64_t)i * m + c] -= w * v[(int64_t)i * k];
+        }
+        __syncthreads();
+        for (int r = tid; r < m; r += BG_T) {
+            double *row = Dw + (int64_t)r * m;
+            double w = 0.0;
+            for (int i = j; i < m; ++i) w += row[i] * v[(int64_t)i * k];
+            w *= tau;
+            for (int i = j; i < m; ++i) row[i] -= w * v[(int64_t)i * k];
+        }
+        __syncthreads();
+    }
+    if (!q.root)
+        for (int t = tid; t < k * k; t += BG_T) {
+            int i = t / k, c = t % k;
+            q.Rh_out[t] = (c >= i) ? Uw[(int64_t)i * k + c] : 0.0;
+        }
+    // ---- Cholesky of A_ee = Dw[k:, k:] (right-looking, in place)
+    bool bad = false;
+    for (int j = 0; j < ne; ++j) {
+        double *Ajj = Dw + (int64_t)(k + j) * m + k + j;
+        double djj = *Ajj;
+        if (!(djj > 0.0)) {
+            bad = true;
+            break;
+        }
+        double ljj = sqrt(djj);
+        __syncthreads();
+        if (tid == 0) *Ajj = ljj;
+        for (int i = j + 1 + tid; i < ne; i += BG_T) Dw[(int64_t)(k + i) * m + k + j] /= ljj;
+        __syncthreads();
+        for (int i = j + 1 + tid; i < ne; i += BG_T) {
+            double lij = Dw[(int64_t)(k + i) * m + k + j];
+            double *rowi = Dw + (int64_t)(k + i) * m + k;
+            for (int c = j + 1; c <= i; ++c) rowi[c] -= lij * Dw[(int64_t)(k + c) * m + k + j];
+        }
+        __syncthreads();
+    }
+    if (bad) {
+        if (tid == 0) atomicOr(flag, 1);
+        return;
+    }
+    for (int t = tid; t < ne * ne; t += BG_T) {
+        int i = t / ne, c = t % ne;
+        q.L[t] = (c <= i) ? Dw[(int64_t)(k + i) * m + k + c] : 0.0;
+    }
+    if (q.root) return;
+    __syncthreads();
+    // W = A_ce L^{-T}: row i of W solves L w = A_ce[i, :]^T
+    for (int i = tid; i < k; i += BG_T) {
+        double *w = q.W + (int64_t)i * ne;
+        const double *a = Dw + (int64_t)i * m + k;
+        for (int c = 0; c < ne; ++c) {
+            double t = a[c];
+            for (int l = 0; l < c; ++l) t -= q.L[(int64_t)c * ne + l] * w[l];
+            w[c] = t / q.L[(int64_t)c * ne + c];
+        }
+    }
+    __syncthreads();
+    // S = A_cc - W W^T
+    block_gemm(k, k, ne, -1.0, q.W, ne, 1, q.W, 1, ne, 1.0, Dw, m, smem);
+    for (int t = tid; t < k * k; t += BG_T) {
+        int i = t / k, c = t % k;
+        q.S_out[t] = 0.5 * (Dw[(int64_t)i * m + c] + Dw[(int64_t)c * m + i]);
+    }
+}
+
+struct SolveDesc {
+    int32_t m, k, leaf, root;
+    int64_t b;
+    const double *V, *tau, *L, *W;
+    double *bw;              // m x nrhs: rhs on the way up, solution on the way down
+    double *z;               // (m - k) x nrhs
+    double *c_out;           // k x nrhs (passed up)
+    const double *c_l, *c_r; // children's reduced rhs
+    int32_t kl, kr;
+    const double *x_par;     // parent's solution rows for this node (k x nrhs), set for the backward sweep
+};
+
+// Apply H_j = I - tau v v^T to columns of bw (m x nrhs), one wave per column.
+__device__ void apply_reflector(const double *v, int ldv, double tau, int j, int m, double *bw, int nrhs) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int c = wv; c < nrhs; c += BG_T / 64) {
+        double w = 0.0;
+        for (int i = j + lane; i < m; i += 64) w += v[(int64_t)i * ldv] * bw[(int64_t)i * nrhs + c];
+        w = wave_sum(w) * tau;
+        for (int i = j + lane; i < m; i += 64) bw[(int64_t)i * nrhs + c] -= w * v[(int64_t)i * ldv];
+    }
+}
+
+// Triangular solve with the lower factor L (n x n): L y = y, or L^T y = y
+// when `trans`, in place on the n x nrhs block y (leading dimension ldy).
+// One wave per right-hand side; the column is staged in the wave's LDS slice
+// (lds: BG_T / 64 slices of nmax doubles) so every lane sees the entries lane
+// 0 has just solved for.
+__device__ void tri_solve(const double *L, int n, double *y, int nrhs, int ldy, bool trans, double *lds, int nmax) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double *v = lds + wv * nmax;
+    for (int c = wv; c < nrhs; c += BG_T / 64) {
+        for (int i = lane; i < n; i += 64) v[i] = y[(int64_t)i * ldy + c];
+        __threadfence_block();
+        if (!trans) {
+            for (int i = 0; i < n; ++i) {
+                double t = 0.0;
+                for (int l = lane; l < i; l += 64) t += L[(int64_t)i * n + l] * v[l];
+                t = wave_sum(t);
+                if (lane == 0) v[i] = (v[i] - t) / L[(int64_t)i * n + i];
+                __threadfence_block();
+            }
+        } else {
+            for (int i = n - 1; i >= 0; --i) {
+                double t = 0.0;
+                for (int l = i + 1 + lane; l < n; l += 64) t += L[(int64_t)l * n + i] * v[l];
+                t = wave_sum(t);
+                if (lane == 0) v[i] = (v[i] - t) / L[(int64_t)i * n + i];
+                __threadfence_block();
+            }
+        }
+        for (int i = lane; i < n; i += 64) y[(int64_t)i * ldy + c] = v[i];
+        __threadfence_block();
+    }
+}
+
+__global__ __launch_bounds__(BG_T) void k_ulv_fwd(const SolveDesc *dsc, const double *__restrict__ Bin, int nrhs,
+                                                  int nmax) {
+    extern __shared__ double lds[];
+    const SolveDesc q = dsc[blockIdx.x];
+    const int m = q.m, k = q.k, ne = m - k, tid = threadIdx.x;
+    if (q.leaf) {
+        for (int64_t t = tid; t < (int64_t)m * nrhs; t += BG_T) q.bw[t] = Bin[q.b * nrhs + t];
+    } else {
+        for (int64_t t = tid; t < (int64_t)q.kl * nrhs; t += BG_T) q.bw[t] = q.c_l[t];
+        for (int64_t t = tid; t < (int64_t)q.kr * nrhs; t += BG_T) q.bw[(int64_t)q.kl * nrhs + t] = q.c_r[t];
+    }
+    __syncthreads();
+    for (int j = 0; j < k; ++j) {
+        apply_reflector(q.V + j, k, q.tau[j], j, m, q.bw, nrhs);
+        __syncthreads();
+    }
+    // z = L^{-1} b_e
+    for (int64_t t = tid; t < (int64_t)ne * nrhs; t += BG_T) q.z[t] = q.bw[(int64_t)k * nrhs + t];
+    __syncthreads();
+    tri_solve(q.L, ne, q.z, nrhs, nrhs, false, lds, nmax);
+    __syncthreads();
+    if (q.root) {
+        // whole solve at the root: x = L^{-T} z
+        tri_solve(q.L, ne, q.z, nrhs, nrhs, true, lds, nmax);
+        __syncthreads();
+        for (int64_t t = tid; t < (int64_t)m * nrhs; t += BG_T) q.bw[t] = q.z[t];
+        return;
+    }
+    // c = b_c - W z
+    for (int64_t t = tid; t < (int64_t)k * nrhs; t += BG_T) {
+        int i = (int)(t / nrhs), c = (int)(t % nrhs);
+        double s = q.bw[(int64_t)i * nrhs + c];
+        for (int l = 0; l < ne; ++l) s -= q.W[(int64_t)i * ne + l] * q.z[(int64_t)l * nrhs + c];
+        q.c_out[t] = s;
+    }
+}
+
+__global__ __launch_bounds__(BG_T) void k_ulv_bwd(const SolveDesc *dsc, double *__restrict__ Xout, int nrhs,
+                                                  int nmax) {
+    extern __shared__ double lds[];
+    const SolveDesc q = dsc[blockIdx.x];
+    const int m = q.m, k = q.k, ne = m - k, tid = threadIdx.x;
+    // x_c from the parent; x_e = L^{-T} (z - W^T x_c)
+    for (int64_t t = tid; t < (int64_t)k * nrhs; t += BG_T) q.bw[t] = q.x_par[t];
+    for (int64_t t = tid; t < (int64_t)ne * nrhs; t += BG_T) {
+        int l = (int)(t / nrhs), c = (int)(t % nrhs);
+        double s = q.z[t];
+        for (int i = 0; i < k; ++i) s -= q.W[(int64_t)i * ne + l] * q.x_par[(int64_t)i * nrhs + c];
+        q.bw[(int64_t)k * nrhs + t] = s;
+    }
+    __syncthreads();
+    tri_solve(q.L, ne, q.bw + (int64_t)k * nrhs, nrhs, nrhs, true, lds, nmax);
+    __syncthreads();
+    for (int j = k - 1; j >= 0; --j) {
+        apply_reflector(q.V + j, k, q.tau[j], j, m, q.bw, nrhs);
+        __syncthreads();
+    }
+    if (q.leaf)
+        for (int64_t t = tid; t < (int64_t)m * nrhs; t += BG_T) Xout[q.b * nrhs + t] = q.bw[t];
+}
+
+}  // namespace
+
+void ulv_factor(const hss_s *H, double lambda, hipStream_t s, hss_ulv_s *F) {
+    const int nn = (int)H->node.size();
+    const int root = nn - 1;
+    F->n = H->n;
+    F->lambda = lambda;
+    F->node = H->node;
+    F->levels = H->levels;
+    F->offV.assign(nn, 0);
+    F->offT.assign(nn, 0);
+    F->offL.assign(nn, 0);
+    F->offW.assign(nn, 0);
+    // per-node sizes: m (rows of the reduced block) and k
+    std::vector<int> m(nn), k(nn);
+    for (int i = 0; i < nn; ++i) {
+        const HNode &q = H->node[i];
+        k[i] = (i == root) ? 0 : q.k;
+        m[i] = (q.left < 0) ? (int)(q.e - q.b) : k[q.left] + k[q.right];
+        F->node[i].m = m[i];
+        F->node[i].k = k[i];
+    }
+    int64_t nv = 0, nt = 0, nl = 0, nw = 0;
+    for (int i = 0; i < nn; ++i) {
+        int ne = m[i] - k[i];
+        F->offV[i] = nv; nv += (int64_t)m[i] * k[i];
+        F->offT[i] = nt; nt += k[i];
+        F->offL[i] = nl; nl += (int64_t)ne * ne;
+        F->offW[i] = nw; nw += (int64_t)k[i] * ne;
+    }
+    F->V.alloc(8 * std::max<int64_t>(nv, 1));
+    F->T.alloc(8 * std::max<int64_t>(nt, 1));
+    F->L.alloc(8 * std::max<int64_t>(nl, 1));
+    F->W.alloc(8 * std::max<int64_t>(nw, 1));
+    F->nV = nv; F->nT = nt; F->nL = nl; F->nW = nw;
+    // S and Rh of every non-root node live until the parent is done
+    std::vector<int64_t> offS(nn, 0);
+    int64_t ns = 0;
+    for (int i = 0; i < nn; ++i) {
+        offS[i] = ns;
+        ns += (int64_t)k[i] * k[i];
+    }
+    DBuf Sb = dalloc<double>(std::max<int64_t>(ns, 1)), Rb = dalloc<double>(std::max<int64_t>(ns, 1));
+    DBuf flag = dalloc<int32_t>(1);
+    KRR_HIP(hipMemsetAsync(flag.get(), 0, sizeof(int32_t), s));
+    for (const auto &lv : H->levels) {
+        const int cnt = (int)lv.size();
+        int64_t dsz = 0, usz = 0, tsz = 0;
+        for (int id : lv) {
+            dsz += (int64_t)m[id] * m[id];
+            usz += (int64_t)m[id] * k[id];
+            const HNode &q = H->node[id];
+            if (q.left >= 0) tsz += (int64_t)k[q.left] * k[q.right];
+        }
+        DBuf Dw = dalloc<double>(std::max<int64_t>(dsz, 1)), Uw = dalloc<double>(std::max<int64_t>(usz, 1)),
+             Tm = dalloc<double>(std::max<int64_t>(tsz, 1));
+        std::vector<UlvDesc> dsc(cnt);
+        int64_t od = 0, ou = 0, ot = 0;
+        for (int a = 0; a < cnt; ++a) {
+            const int id = lv[a];
+            const HNode &q = H->node[id];
+            UlvDesc &u = dsc[a];
+            std::memset(&u, 0, sizeof u);
+            u.m = m[id];
+            u.k = k[id];
+            u.leaf = q.left < 0;
+            u.root = id == root;
+            u.lambda = lambda;
+            if (u.leaf) {
+                u.D = H->D.as<double>() + q.offD;
+            } else {
+                u.kl = k[q.left];
+                u.kr = k[q.right];
+                u.B = H->B.as<double>() + q.offB;
+                u.S_l = Sb.as<double>() + offS[q.left];
+                u.S_r = Sb.as<double>() + offS[q.right];
+                u.Rh_l = Rb.as<double>() + offS[q.left];
+                u.Rh_r = Rb.as<double>() + offS[q.right];
+                u.Tmp = Tm.as<double>() + ot;
+                ot += (int64_t)u.kl * u.kr;
+            }
+            if (!u.root) u.U = H->U.as<double>() + q.offU;
+            u.Dw = Dw.as<double>() + od;
+            u.Uw = Uw.as<double>() + ou;
+            od += (int64_t)u.m * u.m;
+            ou += (int64_t)u.m * u.k;
+            u.V = F->V.as<double>() + F->offV[id];
+            u.tau = F->T.as<double>() + F->offT[id];
+            u.L = F->L.as<double>() + F->offL[id];
+            u.W = F->W.as<double>() + F->offW[id];
+            u.S_out = Sb.as<double>() + offS[id];
+            u.Rh_out = Rb.as<double>() + offS[id];
+        }
+        DBuf dd = upload(dsc, s);
+        k_ulv_factor<<<cnt, BG_T, 0, s>>>(dd.as<UlvDesc>(), flag.as<int32_t>());
+        check_launch("k_ulv_factor");
+        sync(s);
+    }
+    int32_t bad = 0;
+    d2h(&bad, flag.as<int32_t>(), 1, s);
+    sync(s);
+    if (bad) fail(KRR_E_NUMERIC, "ULV: non-positive pivot in a Cholesky factor (K_hss + lambda I not SPD)");
+}
+
+void ulv_solve(const hss_ulv_s *F, const double *Bin, int nrhs, double *Xout, hipStream_t s) {
+    const int nn = (int)F->node.size();
+    const int root = nn - 1;
+    std::vector<int64_t> ob(nn), oz(nn), oc(nn);
+    int64_t nb = 0, nz = 0, nc = 0;
+    for (int i = 0; i < nn; ++i) {
+        const HNode &q = F->node[i];
+        ob[i] = nb; nb += (int64_t)q.m * nrhs;
+        oz[i] = nz; nz += (int64_t)(q.m - q.k) * nrhs;
+        oc[i] = nc; nc += (int64_t)q.k * nrhs;
+    }
+    DBuf bw = dalloc<double>(std::max<int64_t>(nb, 1)), zb = dalloc<double>(std::max<int64_t>(nz, 1)),
+         cb = dalloc<double>(std::max<int64_t>(nc, 1));
+    auto make = [&](int id) {
+        const HNode &q = F->node[id];
+        SolveDesc d;
+        std::memset(&d, 0, sizeof d);
+        d.m = q.m;
+        d.k = q.k;
+        d.leaf = q.left < 0;
+        d.root = id == root;
+        d.b = q.b;
+        d.V = F->V.as<double>() + F->offV[id];
+        d.tau = F->T.as<double>() + F->offT[id];
+        d.L = F->L.as<double>() + F->offL[id];
+        d.W = F->W.as<double>() + F->offW[id];
+        d.bw = bw.as<double>() + ob[id];
+        d.z = zb.as<double>() + oz[id];
+        d.c_out = cb.as<double>() + oc[id];
+        if (!d.leaf) {
+            d.kl = F->node[q.left].k;
+            d.kr = F->node[q.right].k;
+            d.c_l = cb.as<double>() + oc[q.left];
+            d.c_r = cb.as<double>() + oc[q.right];
+        }
+        if (!d.root) {
+            const HNode &p = F->node[q.parent];
+            int64_t off = (p.left == id) ? 0 : (int64_t)F->node[p.left].k;
+            d.x_par = bw.as<double>() + ob[q.parent] + off * nrhs;
+        }
+        return d;
+    };
+    std::vector<DBuf> keep;
+    std::vector<std::vector<SolveDesc>> hold;  // host copies stay alive until the final sync
+    auto nmax_of = [&](const std::vector<SolveDesc> &v) {
+        int nm = 1;
+        for (const auto &d : v) nm = std::max(nm, d.m);
+        return nm;
+    };
+    for (const auto &lv : F->levels) {
+        hold.emplace_back();
+        for (int id : lv) hold.back().push_back(make(id));
+        const int nm = nmax_of(hold.back());
+        keep.push_back(upload(hold.back(), s));
+        k_ulv_fwd<<<(unsigned)hold.back().size(), BG_T, sizeof(double) * nm * (BG_T / 64), s>>>(
+            keep.back().as<SolveDesc>(), Bin, nrhs, nm);
+        check_launch("k_ulv_fwd");
+    }
+    for (int h = (int)F->levels.size() - 1; h >= 0; --h) {
+        hold.emplace_back();
+        for (int id : F->levels[h])
+            if (id != root) hold.back().push_back(make(id));
+        if (hold.back().empty()) {
+            if (F->node[root].left < 0 && h == 0) {
+                // single-node tree: the root is a leaf; copy its solution out
+                KRR_HIP(hipMemcpyAsync(Xout, bw.as<double>() + ob[root], sizeof(double) * F->n * nrhs,
+                                       hipMemcpyDeviceToDevice, s));
+            }
+            continue;
+        }
+        const int nm = nmax_of(hold.back());
+        keep.push_back(upload(hold.back(), s));
+        k_ulv_bwd<<<(unsigned)hold.back().size(), BG_T, sizeof(double) * nm * (BG_T / 64), s>>>(
+            keep.back().as<SolveDesc>(), Xout, nrhs, nm);
+        check_launch("k_ulv_bwd");
+    }
+    sync(s);
+}
+
+}  // namespace krr

@@ -1,0 +1,153 @@
+"""GPU kernel products against the oracle's FP64 matrix-free products:
+kernel_matvec (FP64 and FP32 entries), the masked sampling product, the
+random block, gather / scatter, prediction labels and the matvec backward."""
+import numpy as np
+import pytest
+import torch
+
+import synthdata as sd
+from oracle import cmath, grad as og, cluster as oc, kernel as ok
+from gpu_util import fp32_product_bound, leaf_ranges, sqdist, U32
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("d", [8, 18, 54, 100, 784])
+@pytest.mark.parametrize("nrhs", [1, 5, 17])
+def test_matvec_fp64(gpu_lib, d, nrhs):
+    X = sd.points(301, d, seed=1, scale=0.3, dtype=np.float64)
+    Y = sd.points(517, d, seed=2, scale=0.3, dtype=np.float64)
+    W = sd.vectors(517, nrhs, seed=3)
+    h = 0.2 * np.sqrt(d)
+    got = gpu_lib.kernel_matvec(_t(X), _t(Y), h, _t(W), prec="f64").cpu().numpy()
+    ref = cmath.kmv(X, Y, W, h)
+    scale = cmath.kmv(X, Y, np.abs(W), h)
+    assert np.all(np.abs(got - ref) <= 1e-13 * scale + 1e-300)
+
+
+@pytest.mark.parametrize("d", [8, 18, 54, 784])
+@pytest.mark.parametrize("nrhs", [1, 2, 10])
+def test_matvec_fp32(gpu_lib, d, nrhs):
+    X = sd.points(333, d, seed=4, scale=0.3)
+    Y = sd.points(1029, d, seed=5, scale=0.3)
+    W = sd.vectors(1029, nrhs, seed=6)
+    h = 0.2 * np.sqrt(d)
+    got = gpu_lib.kernel_matvec(_t(X), _t(Y), h, _t(W), prec="f32").cpu().numpy()
+    ref = cmath.kmv(X, Y, W, h)
+    assert np.all(np.abs(got - ref) <= fp32_product_bound(X, Y, W, h))
+
+
+def test_matvec_beta_and_empty(gpu_lib):
+    X = sd.points(70, 3, seed=7, dtype=np.float64)
+    W = sd.vectors(70, 2, seed=8)
+    out0 = sd.vectors(70, 2, seed=9)
+    out = _t(out0)
+    gpu_lib.kernel_matvec(_t(X), _t(X), 0.7, _t(W), beta=-2.0, out=out, prec="f64")
+    ref = cmath.kmv(X, X, W, 0.7) - 2.0 * out0
+    np.testing.assert_allclose(out.cpu().numpy(), ref, rtol=1e-12, atol=1e-12)
+    empty = gpu_lib.kernel_matvec(_t(X[:0]), _t(X), 0.7, _t(W), prec="f64")
+    assert empty.shape == (0, 2)
+
+
+def test_matvec_large_sampled_rows(gpu_lib):
+    # the refinement product at the 16-Gaussian workload size, checked on sampled rows
+    p = sd.c2_sixteen_gaussians(n=1 << 18, m=1)
+    W = sd.vectors(p.n, 1, seed=10)
+    got = gpu_lib.kernel_matvec(_t(p.X), _t(p.X), p.h, _t(W), prec="f32").cpu().numpy()
+    rows = np.random.default_rng(0).choice(p.n, 64, replace=False)
+    ref = cmath.kmv(p.X, p.X, W, p.h, rows=rows)
+    bound = fp32_product_bound(p.X[rows], p.X, W, p.h)
+    assert np.all(np.abs(got[rows] - ref) <= bound)
+
+
+def _tree_ranges(X, leaf, seed=1):
+    t = oc.cluster2mn(X, leaf, seed)
+    Xp = np.ascontiguousarray(X[t.perm])
+    lb, le = leaf_ranges(t.nodes, X.shape[0])
+    return Xp, lb, le
+
+
+@pytest.mark.parametrize("n,d,r", [(200, 8, 32), (777, 18, 64), (1500, 8, 256)])
+def test_sample_fp64(gpu_lib, n, d, r):
+    X = sd.c1_two_gaussians(n=n, m=1, d=d).X
+    Xp, lb, le = _tree_ranges(X, 48)
+    R = sd.random_block(n, r, seed=3)
+    S = gpu_lib.kernel_sample(_t(Xp), 1.0, _t(R), _t(lb), _t(le), prec="f64").cpu().numpy()
+    ref = cmath.sample_masked(Xp, R, 1.0, lb, le, np.arange(n))
+    scale = cmath.sample_masked(Xp, np.abs(R), 1.0, lb, le, np.arange(n))
+    assert np.all(np.abs(S - ref) <= 1e-13 * scale + 1e-300)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16", "bf16"])
+def test_sample_reduced_precision(gpu_lib, prec):
+    n, d, r = 1200, 8, 64
+    X = sd.c2_sixteen_gaussians(n=n, m=1).X
+    Xp, lb, le = _tree_ranges(X, 100)
+    R = sd.random_block(n, r, seed=4)
+    S = gpu_lib.kernel_sample(_t(Xp), 0.75, _t(R), _t(lb), _t(le), prec=prec).cpu().numpy()
+    ref = cmath.sample_masked(Xp, R, 0.75, lb, le, np.arange(n))
+    mask = (np.arange(n)[None, :] >= lb[:, None]) & (np.arange(n)[None, :] < le[:, None])
+    bound = fp32_product_bound(Xp, Xp, R, 0.75, mask=mask)
+    if prec != "f32":
+        # split terms: each entry carries at most 2^-22 (fp16) / 2^-16 (bf16) relative error
+        q = sqdist(Xp, Xp)
+        K = np.where(mask, 0.0, np.exp(-q / (2 * 0.75 ** 2)))
+        bound = bound + 4 * (2.0 ** -16 if prec == "bf16" else 2.0 ** -22) * (K @ np.abs(R))
+    assert np.all(np.abs(S - ref) <= bound)
+
+
+def test_sample_unmasked_matches_matvec(gpu_lib):
+    X = sd.points(300, 5, seed=11, dtype=np.float64)
+    R = sd.random_block(300, 32, seed=5)
+    S = gpu_lib.kernel_sample(_t(X), 0.9, _t(R), prec="f64").cpu().numpy()
+    ref = cmath.kmv(X, X, R.astype(np.float64), 0.9)
+    np.testing.assert_allclose(S, ref, rtol=1e-12, atol=1e-12)
+
+
+def test_random_block(gpu_lib):
+    R = gpu_lib.random_block(5, 1000, 64).cpu().numpy()
+    assert set(np.unique(R)) == {-1.0, 1.0}
+    assert abs(R.mean()) < 0.02
+    R2 = gpu_lib.random_block(5, 1000, 32, c0=32).cpu().numpy()
+    np.testing.assert_array_equal(R[:, 32:], R2)
+
+
+def test_gather_scatter(gpu_lib):
+    X = sd.points(1000, 7, seed=12)
+    perm = np.random.default_rng(1).permutation(1000)
+    g = gpu_lib.gather_rows(_t(X), _t(perm.astype(np.int64))).cpu().numpy()
+    np.testing.assert_array_equal(g, X[perm])
+    s = gpu_lib.scatter_rows(_t(g), _t(perm.astype(np.int64))).cpu().numpy()
+    np.testing.assert_array_equal(s, X)
+
+
+def test_predict_labels(gpu_lib):
+    p = sd.c1_two_gaussians(n=500, m=300)
+    a = ok.krr_fit_dense(p.X, p.y, p.h, p.lam)
+    sc, lab = gpu_lib.predict(_t(p.Xt), _t(p.X), p.h, _t(a), prec="f64")
+    ref = ok.scores(p.Xt, p.X, a, p.h)
+    np.testing.assert_allclose(sc.cpu().numpy()[:, 0], ref, rtol=1e-11, atol=1e-12)
+    np.testing.assert_array_equal(lab.cpu().numpy(), ok.labels_binary(ref).astype(np.int32))
+    # one-vs-all argmax over three score columns
+    A = sd.vectors(500, 3, seed=13)
+    sc, lab = gpu_lib.predict(_t(p.Xt), _t(p.X), p.h, _t(A), prec="f64")
+    np.testing.assert_array_equal(lab.cpu().numpy(), ok.labels_one_vs_all(ok.scores(p.Xt, p.X, A, p.h)))
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-11), ("f32", 2e-5)])
+def test_matvec_backward(gpu_lib, prec, tol):
+    X = sd.points(211, 6, seed=14, scale=0.5, dtype=np.float64)
+    Y = sd.points(157, 6, seed=15, scale=0.5, dtype=np.float64)
+    W = sd.vectors(157, 3, seed=16)
+    G = sd.vectors(211, 3, seed=17)
+    h = 0.8
+    out = gpu_lib.kernel_matvec_bwd(_t(X), _t(Y), h, _t(W), _t(G), prec=prec)
+    dX, dY, dW, dh = og.matvec_bwd(X, Y, W, G, h)
+    for name, ref in (("dX", dX), ("dY", dY), ("dW", dW)):
+        got = out[name].cpu().numpy()
+        assert np.linalg.norm(got - ref) <= tol * np.linalg.norm(ref), name
+    assert abs(out["dh"].item() - dh) <= tol * abs(dh)
