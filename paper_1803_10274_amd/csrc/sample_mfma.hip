@@ -1,0 +1,354 @@
+// Matrix-core sampling product S = K(X, X; h) R (each row's own leaf block
+// removed): the dominant kernel of the randomized HSS construction.
+//
+// Per workgroup: 256 rows (8 waves x 32 rows) and up to 256 sample columns
+// (RB blocks of 32), loop over all points j in tiles of 32.  Per tile each
+// lane evaluates the 16 kernel entries it feeds to the matrix cores -- its
+// row i = lane % 32 and points j = 8 g + q, 16 + 8 g + q (g = lane / 32,
+// q = 0..7), exactly the A-operand layout of v_mfma_f32_32x32x16_{f16,bf16}
+// -- so the entries never leave registers:
+//     t = -c |x'_i|^2 - c |y'_j|^2 + sum_k (2 c x'_ik) y'_jk,  e = exp2(t),
+// with c = log2(e) / (2 h^2) and x' = x - a, y' = y - a re-centred on the
+// workgroup's first point a (the kernel is translation invariant; this keeps
+// the FP32 norm expansion free of large cancellations for the pairs that
+// matter).  e is split into FP16 / BF16 hi (+ lo = e - hi) terms and
+// multiplied into the FP32 accumulators with the random block, which is
+// pre-swizzled into the B-operand layout and staged through LDS.  The FP32
+// mode uses v_mfma_f32_32x32x2_f32 on the FP32 entries instead.
+#include "internal.hpp"
+
+namespace krr {
+
+namespace {
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef float f16v __attribute__((ext_vector_type(16)));
+
+enum Mode : int { M_F32 = 0, M_F16 = 1, M_BF16 = 2 };
+
+constexpr int WAVES = 8;
+constexpr int THREADS = 64 * WAVES;
+constexpr int ROWS = 32 * WAVES;  // rows per workgroup
+constexpr int JT = 32;            // points per tile
+// points per staged Y super-tile (a multiple of JT, smaller for wide points)
+template <int D> struct YTile { static constexpr int N = D <= 16 ? 256 : (D <= 32 ? 128 : 64); };
+
+// ---------------------------------------------------------------- swizzle
+
+// Rsw layout for FP16 / BF16: [tile][cb][kb][lane][q] with point
+// j = 32 tile + 16 kb + 8 (lane / 32) + q and column 32 cb + lane % 32.
+template <class H>
+__global__ void k_swizzle_h(const float *__restrict__ R, int64_t n, int r, int64_t tiles, H *__restrict__ Rsw) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int RBt = r / 32;
+    if (t >= tiles * RBt * 2 * 64) return;
+    int lane = (int)(t % 64);
+    int64_t u = t / 64;
+    int kb = (int)(u % 2);
+    u /= 2;
+    int cb = (int)(u % RBt);
+    int64_t tile = u / RBt;
+    int col = 32 * cb + lane % 32;
+    for (int q = 0; q < 8; ++q) {
+        int64_t j = 32 * tile + 16 * kb + 8 * (lane / 32) + q;
+        float v = j < n ? R[j * r + col] : 0.0f;
+        Rsw[t * 8 + q] = (H)v;
+    }
+}
+
+// Rsw layout for FP32: [tile][cb][s][lane] with point j = 32 tile + 2 s + lane / 32.
+__global__ void k_swizzle_f(const float *__restrict__ R, int64_t n, int r, int64_t tiles, float *__restrict__ Rsw) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int RBt = r / 32;
+    if (t >= tiles * RBt * 16 * 64) return;
+    int lane = (int)(t % 64);
+    int64_t u = t / 64;
+    int s = (int)(u % 16);
+    u /= 16;
+    int cb = (int)(u % RBt);
+    int64_t tile = u / RBt;
+    int64_t j = 32 * tile + 2 * s + lane / 32;
+    Rsw[t] = j < n ? R[j * r + 32 * cb + lane % 32] : 0.0f;
+}
+
+__global__ void k_to_float(const double *__restrict__ x, int64_t len, float *__restrict__ y) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < len) y[t] = (float)x[t];
+}
+
+// ----------------------------------------------------------------- kernel
+
+template <int MODE> struct Op;
+template <> struct Op<M_F16> {
+    typedef _Float16 H;
+    typedef half8 V;
+    static __device__ __forceinline__ f16v mfma(V a, V b, f16v c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Op<M_BF16> {
+    typedef __bf16 H;
+    typedef bf8 V;
+    static __device__ __forceinline__ f16v mfma(V a, V b, f16v c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+    }
+};
+
+template <class T, int D, int YS = YTile<D>::N>
+__device__ __forceinline__ void stage_y(const T *__restrict__ X, int64_t n, int d, int64_t j0, const float *anchor,
+                                        float cs, float (*ys)[D + 1]) {
+    // ys[p][0..D) = y' = y - a, ys[p][D] = -c |y'|^2 (or -inf past the end)
+    for (int p = threadIdx.x; p < YS; p += THREADS) {
+        int64_t j = j0 + p;
+        float nrm = 0.0f;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            float v = (j < n && k < d) ? (float)X[j * d + k] - anchor[k] : 0.0f;
+            ys[p][k] = v;
+            nrm = fmaf(v, v, nrm);
+        }
+        ys[p][D] = j < n ? -cs * nrm : -INFINITY;
+    }
+}
+
+// Entry t for the lane's row (xs = 2 c x', nx = -c |x'|^2) and staged point p.
+template <int D>
+__device__ __forceinline__ float entry(const float *xs, float nx, const float (*ys)[D + 1], int p) {
+    float t = nx + ys[p][D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) t = fmaf(xs[k], ys[p][k], t);
+    return __builtin_amdgcn_exp2f(t);
+}
+
+template <class T, int D, int RB, int MODE, int TERMS>
+__global__ __launch_bounds__(THREADS) void k_sample_mfma(const T *__restrict__ X, int64_t n, int d, float cs,
+                                                         const void *__restrict__ Rsw_, int RBt, int cb0,
+                                                         const int32_t *__restrict__ lb, const int32_t *__restrict__ le,
+                                                         float *__restrict__ S, int ldS) {
+    typedef typename Op<MODE == M_F32 ? M_F16 : MODE>::H H;
+    typedef typename Op<MODE == M_F32 ? M_F16 : MODE>::V V;
+    constexpr int RTILE_H = RB * 2 * 64 * 8;       // halves per tile (FP16 / BF16)
+    constexpr int RTILE_F = RB * 16 * 64;          // floats per tile (FP32)
+    constexpr int RTILE_B = MODE == M_F32 ? RTILE_F * 4 : RTILE_H * 2;  // bytes per tile
+    __shared__ __attribute__((aligned(16))) char rbuf[2][RTILE_B];
+    constexpr int YS = YTile<D>::N;
+    __shared__ float ysh[2][YS][D + 1];
+    __shared__ float anchor[D];
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 5;
+    const int64_t i0 = (int64_t)blockIdx.x * ROWS;
+    const int64_t i = i0 + 32 * w + (lane & 31);
+    const bool row_ok = i < n;
+    if (tid < D) anchor[tid] = (tid < d) ? (float)X[i0 * d + tid] : 0.0f;
+    __syncthreads();
+    float xs[D];
+    float nx = 0.0f;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        float v = (row_ok && k < d) ? (float)X[i * d + k] - anchor[k] : 0.0f;
+        nx = fmaf(v, v, nx);
+        xs[k] = 2.0f * cs * v;
+    }
+    nx = -cs * nx;
+    const int32_t my_lb = (row_ok && lb) ? lb[i] : 0;
+    const int32_t my_le = (row_ok && lb) ? le[i] : 0;
+
+    const int64_t tiles = (n + JT - 1) / JT;
+    const char *Rg = static_cast<const char *>(Rsw_);
+    const int64_t tile_stride_b = (int64_t)RBt * (RTILE_B / RB);  // bytes per tile across all column blocks
+    const int64_t cb_off_b = (int64_t)cb0 * (RTILE_B / RB);
+    // R tile staging: RTILE_B bytes by THREADS threads in 16-byte pieces
+    constexpr int PIECES = RTILE_B / 16;
+    constexpr int PER_T = (PIECES + THREADS - 1) / THREADS;
+    static_assert(PER_T <= 4, "R tile too large for the prefetch registers");
+    // prefetch registers (named, so they stay in VGPRs across the loop)
+    uint4 pre0, pre1, pre2, pre3;
+#define KRR_PIECE_OK(u) ((u) < PER_T && (PIECES % THREADS == 0 || tid + (u) * THREADS < PIECES))
+#define KRR_LOAD_R(tile)                                                                          \
+    do {                                                                                          \
+        const uint4 *src_ = reinterpret_cast<const uint4 *>(Rg + (tile) * tile_stride_b + cb_off_b); \
+        if (KRR_PIECE_OK(0)) pre0 = src_[tid];                                                    \
+        if (KRR_PIECE_OK(1)) pre1 = src_[tid + THREADS];                                          \
+        if (KRR_PIECE_OK(2)) pre2 = src_[tid + 2 * THREADS];                                      \
+        if (KRR_PIECE_OK(3)) pre3 = src_[tid + 3 * THREADS];                                      \
+    } while (0)
+#define KRR_STORE_R(buf)                                                                          \
+    do {                                                                                          \
+        uint4 *dst_ = reinterpret_cast<uint4 *>(rbuf[buf]);                                       \
+        if (KRR_PIECE_OK(0)) dst_[tid] = pre0;                                                    \
+        if (KRR_PIECE_OK(1)) dst_[tid + THREADS] = pre1;                                          \
+        if (KRR_PIECE_OK(2)) dst_[tid + 2 * THREADS] = pre2;                                      \
+        if (KRR_PIECE_OK(3)) dst_[tid + 3 * THREADS] = pre3;                                      \
+    } while (0)
+
+    f16v acc[RB];
+#pragma unroll
+    for (int c = 0; c < RB; ++c)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc[c][q] = 0.0f;
+
+    // prologue: Y super-tile 0, R tile 0
+    stage_y<T, D>(X, n, d, 0, anchor, cs, ysh[0]);
+    KRR_LOAD_R(0);
+    KRR_STORE_R(0);
+    if (tiles > 1) KRR_LOAD_R(1);
+    __syncthreads();
+
+    for (int64_t t = 0; t < tiles; ++t) {
+        const int yb = (int)((t * JT / YS) & 1);
+        const int pbase = (int)((t * JT) % YS);
+        const int64_t jt = t * JT;
+        const bool mask_tile = (jt < my_le) && (jt + JT > my_lb);
+        if constexpr (MODE == M_F32) {
+            const float *rt = reinterpret_cast<const float *>(rbuf[t & 1]);
+#pragma unroll
+            for (int s = 0; s < 16; ++s) {
+                const int p = pbase + 2 * s + g;
+                float e = entry<D>(xs, nx, ysh[yb], p);
+                if (mask_tile) {
+                    int64_t j = jt + 2 * s + g;
+                    if (j >= my_lb && j < my_le) e = 0.0f;
+                }
+#pragma unroll
+                for (int c = 0; c < RB; ++c) {
+                    float b = rt[(c * 16 + s) * 64 + lane];
+                    acc[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(e, b, acc[c], 0, 0, 0);
+                }
+            }
+        } else {
+            V ahi[2], alo[2];
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int jj = 16 * kb + 8 * g + q;
+                    float e = entry<D>(xs, nx, ysh[yb], pbase + jj);
+                    if (mask_tile) {
+                        int64_t j = jt + jj;
+                        if (j >= my_lb && j < my_le) e = 0.0f;
+                    }
+                    H hi = (H)e;
+                    ahi[kb][q] = hi;
+                    if (TERMS == 2) alo[kb][q] = (H)(e - (float)hi);
+                }
+            const V *rt = reinterpret_cast<const V *>(rbuf[t & 1]);
+#pragma unroll
+            for (int c = 0; c < RB; ++c)
+#pragma unroll
+                for (int kb = 0; kb < 2; ++kb) {
+                    V b = rt[(c * 2 + kb) * 64 + lane];
+                    acc[c] = Op<MODE>::mfma(ahi[kb], b, acc[c]);
+                    if (TERMS == 2) acc[c] = Op<MODE>::mfma(alo[kb], b, acc[c]);
+                }
+        }
+        // next R tile into the other buffer; next Y super-tile when this one ends.
+        // Both targets were last read one iteration (R) or a whole super-tile
+        // (Y) ago, so a single barrier per tile orders writes and reads.
+        if (t + 1 < tiles) {
+            KRR_STORE_R((t + 1) & 1);
+            if (t + 2 < tiles) KRR_LOAD_R(t + 2);
+            if (((t + 1) * JT) % YS == 0) stage_y<T, D>(X, n, d, (t + 1) * JT, anchor, cs, ysh[yb ^ 1]);
+        }
+        __syncthreads();
+    }
+    // write out: lane holds column 32 c + lane % 32 of rows 8 (q / 4) + 4 g + q % 4
+#pragma unroll
+    for (int c = 0; c < RB; ++c)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int m = 8 * (q >> 2) + 4 * g + (q & 3);
+            const int64_t row = i0 + 32 * w + m;
+            if (row < n) S[row * ldS + 32 * (cb0 + c) + (lane & 31)] = acc[c][q];
+        }
+#undef KRR_LOAD_R
+#undef KRR_STORE_R
+#undef KRR_PIECE_OK
+}
+
+template <class T, int D, int MODE, int TERMS>
+void launch_passes(const T *X, int64_t n, int d, float cs, const void *Rsw, int r, const int32_t *lb,
+                   const int32_t *le, float *S, hipStream_t s) {
+    const int RBt = r / 32;
+    int cb0 = 0;
+    while (cb0 < RBt) {
+        const int left = RBt - cb0;
+        dim3 grid(ceil_div(n, ROWS));
+        if (left >= 8) {
+            k_sample_mfma<T, D, 8, MODE, TERMS><<<grid, THREADS, 0, s>>>(X, n, d, cs, Rsw, RBt, cb0, lb, le, S, r);
+            cb0 += 8;
+        } else if (left >= 2) {
+            k_sample_mfma<T, D, 2, MODE, TERMS><<<grid, THREADS, 0, s>>>(X, n, d, cs, Rsw, RBt, cb0, lb, le, S, r);
+            cb0 += 2;
+        } else {
+            k_sample_mfma<T, D, 1, MODE, TERMS><<<grid, THREADS, 0, s>>>(X, n, d, cs, Rsw, RBt, cb0, lb, le, S, r);
+            cb0 += 1;
+        }
+        check_launch("k_sample_mfma");
+    }
+}
+
+template <class T, int D>
+void dispatch_mode(const T *X, int64_t n, int d, float cs, const void *Rsw, int r, const int32_t *lb, const int32_t *le,
+                   float *S, int prec, int split, hipStream_t s) {
+    if (prec == KRR_F32)
+        launch_passes<T, D, M_F32, 1>(X, n, d, cs, Rsw, r, lb, le, S, s);
+    else if (prec == KRR_F16_SPLIT)
+        split == 2 ? launch_passes<T, D, M_F16, 2>(X, n, d, cs, Rsw, r, lb, le, S, s)
+                   : launch_passes<T, D, M_F16, 1>(X, n, d, cs, Rsw, r, lb, le, S, s);
+    else
+        split == 2 ? launch_passes<T, D, M_BF16, 2>(X, n, d, cs, Rsw, r, lb, le, S, s)
+                   : launch_passes<T, D, M_BF16, 1>(X, n, d, cs, Rsw, r, lb, le, S, s);
+}
+
+template <class T>
+void dispatch_d(const T *X, int64_t n, int d, float cs, const void *Rsw, int r, const int32_t *lb, const int32_t *le,
+                float *S, int prec, int split, hipStream_t s) {
+    if (d <= 8)
+        dispatch_mode<T, 8>(X, n, d, cs, Rsw, r, lb, le, S, prec, split, s);
+    else if (d <= 16)
+        dispatch_mode<T, 16>(X, n, d, cs, Rsw, r, lb, le, S, prec, split, s);
+    else if (d <= 32)
+        dispatch_mode<T, 32>(X, n, d, cs, Rsw, r, lb, le, S, prec, split, s);
+    else
+        dispatch_mode<T, 64>(X, n, d, cs, Rsw, r, lb, le, S, prec, split, s);
+}
+
+}  // namespace
+
+constexpr int kSampleMfmaMaxD = 64;
+
+bool sample_mfma_supported(int d, int prec) { return prec != KRR_F64 && d <= kSampleMfmaMaxD; }
+
+// R: n x r FP32 (exact in the operand precision); S: n x r FP32.
+void sample_mfma(const void *X, int64_t n, int d, int xprec, double h, const float *R, int r, const int32_t *lb,
+                 const int32_t *le, float *S, int prec, int split, hipStream_t s) {
+    const int64_t tiles = (n + JT - 1) / JT;
+    const float cs = (float)(1.4426950408889634 / (2.0 * h * h));
+    DBuf Rsw;
+    if (prec == KRR_F32) {
+        Rsw.alloc(sizeof(float) * tiles * 32 * r);
+        int64_t tot = tiles * (r / 32) * 16 * 64;
+        k_swizzle_f<<<ceil_div(tot, 256), 256, 0, s>>>(R, n, r, tiles, Rsw.as<float>());
+    } else {
+        Rsw.alloc(2 * tiles * 32 * r);
+        int64_t tot = tiles * (r / 32) * 2 * 64;
+        if (prec == KRR_F16_SPLIT)
+            k_swizzle_h<_Float16><<<ceil_div(tot, 256), 256, 0, s>>>(R, n, r, tiles, Rsw.as<_Float16>());
+        else
+            k_swizzle_h<__bf16><<<ceil_div(tot, 256), 256, 0, s>>>(R, n, r, tiles, Rsw.as<__bf16>());
+    }
+    check_launch("k_swizzle");
+    DBuf Xf;
+    const float *Xs = static_cast<const float *>(X);
+    if (xprec == KRR_F64) {
+        Xf.alloc(sizeof(float) * n * d);
+        k_to_float<<<ceil_div(n * d, 256), 256, 0, s>>>(static_cast<const double *>(X), n * d, Xf.as<float>());
+        check_launch("k_to_float");
+        Xs = Xf.as<float>();
+    }
+    dispatch_d<float>(Xs, n, d, cs, Rsw.get(), r, lb, le, S, prec, split, s);
+    sync(s);  // Rsw is released on return
+}
+
+}  // namespace krr

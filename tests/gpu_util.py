@@ -38,3 +38,38 @@ def leaf_ranges(nodes, n):
             lb[b:e] = b
             le[b:e] = e
     return lb, le
+
+
+# relative rounding of one kernel entry by the split modes
+SPLIT_U = {("f32", 1): 0.0, ("f16", 1): 2.0 ** -11, ("f16", 2): 2.0 ** -22,
+           ("bf16", 1): 2.0 ** -8, ("bf16", 2): 2.0 ** -16}
+
+
+def mfma_sample_bound(Xp, R, h, lb, le, prec, split, rows, rows_per_block=256, safety=4.0):
+    """Bound for the matrix-core sampler on the given rows.
+
+    Entry e_ij = exp2(t) with t formed in FP32 from coordinates re-centred on
+    the workgroup's first point a (x' = x - a, y' = y - a): the FMA chain of
+    d + 2 terms gives |dt| <= (d + 2) u c (|x'| + |y'|)^2 in log2 units, so
+    |de| <= e u [2 + (d + 2) (|x'| + |y'|)^2 / (2 h^2)] plus the split's own
+    rounding SPLIT_U * e.  The FP32 accumulation over n terms is charged with
+    the probabilistic model sqrt(n_adds) u ||e o r||_2 (Higham and Mary 2019),
+    n_adds = n / 16 + 16 for the 16-deep FP16 / BF16 products and n / 2 + 2
+    for the 2-deep FP32 ones."""
+    Xp = np.asarray(Xp, dtype=np.float64)
+    R = np.asarray(R, dtype=np.float64)
+    n, d = Xp.shape
+    out = np.zeros((len(rows), R.shape[1]))
+    us = SPLIT_U[(prec, split)]
+    nadd = n / 2 + 2 if prec == "f32" else n / 16 + 16
+    for t, i in enumerate(rows):
+        a = Xp[(i // rows_per_block) * rows_per_block]
+        xr = np.linalg.norm(Xp[i] - a)
+        yr = np.linalg.norm(Xp - a, axis=1)
+        q = ((Xp - Xp[i]) ** 2).sum(axis=1)
+        e = np.exp(-q / (2 * h * h))
+        e[lb[i]:le[i]] = 0.0
+        de = e * (U32 * (2 + (d + 2) * (xr + yr) ** 2 / (2 * h * h)) + us)
+        acc = np.sqrt(nadd) * U32 * np.sqrt((e[:, None] ** 2 * R ** 2).sum(axis=0))
+        out[t] = safety * (de @ np.abs(R) + acc)
+    return out
