@@ -11,7 +11,8 @@
 // with c = log2(e) / (2 h^2) and x' = x - a, y' = y - a re-centred on the
 // workgroup's first point a (the kernel is translation invariant; this keeps
 // the FP32 norm expansion free of large cancellations for the pairs that
-// matter).  e is split into FP16 / BF16 hi (+ lo = e - hi) terms and
+// matter).  e is split into FP16 / BF16 hi (+ lo = e - hi) terms (FP16
+// entries carry a 2^14 scale so small values keep full precision) and
 // multiplied into the FP32 accumulators with the random block, which is
 // pre-swizzled into the B-operand layout and staged through LDS.  The FP32
 // mode uses v_mfma_f32_32x32x2_f32 on the FP32 entries instead.
@@ -150,7 +151,12 @@ __global__ __launch_bounds__(THREADS) void k_sample_mfma(const T *__restrict__ X
         nx = fmaf(v, v, nx);
         xs[k] = 2.0f * cs * v;
     }
-    nx = -cs * nx;
+    // FP16 entries are evaluated as e * 2^14 (the exponent gains 14) so that
+    // small kernel values stay in FP16's normal range; the accumulators are
+    // scaled back by 2^-14 on write-out (both exact power-of-two scalings).
+    constexpr float kE2 = MODE == M_F16 ? 14.0f : 0.0f;
+    constexpr float kInvScale = MODE == M_F16 ? 1.0f / 16384.0f : 1.0f;
+    nx = -cs * nx + kE2;
     const int32_t my_lb = (row_ok && lb) ? lb[i] : 0;
     const int32_t my_le = (row_ok && lb) ? le[i] : 0;
 
@@ -259,7 +265,7 @@ __global__ __launch_bounds__(THREADS) void k_sample_mfma(const T *__restrict__ X
         for (int q = 0; q < 16; ++q) {
             const int m = 8 * (q >> 2) + 4 * g + (q & 3);
             const int64_t row = i0 + 32 * w + m;
-            if (row < n) S[row * ldS + 32 * (cb0 + c) + (lane & 31)] = acc[c][q];
+            if (row < n) S[row * ldS + 32 * (cb0 + c) + (lane & 31)] = acc[c][q] * kInvScale;
         }
 #undef KRR_LOAD_R
 #undef KRR_STORE_R

@@ -54,6 +54,8 @@ def mfma_sample_bound(Xp, R, h, lb, le, prec, split, rows, rows_per_block=256, s
     |de| <= e u [2 + (d + 2) (|x'| + |y'|)^2 / (2 h^2)] plus the split's own
     rounding SPLIT_U * e.  The FP32 accumulation over n terms is charged with
     the probabilistic model sqrt(n_adds) u ||e o r||_2 (Higham and Mary 2019),
+    FP16 entries (scaled by 2^14) add 2^-38 absolute where they fall below
+    FP16's normal range,
     n_adds = n / 16 + 16 for the 16-deep FP16 / BF16 products and n / 2 + 2
     for the 2-deep FP32 ones."""
     Xp = np.asarray(Xp, dtype=np.float64)
@@ -70,6 +72,10 @@ def mfma_sample_bound(Xp, R, h, lb, le, prec, split, rows, rows_per_block=256, s
         e = np.exp(-q / (2 * h * h))
         e[lb[i]:le[i]] = 0.0
         de = e * (U32 * (2 + (d + 2) * (xr + yr) ** 2 / (2 * h * h)) + us)
+        if prec == "f16":
+            # entries carry a 2^14 scale; below FP16's normal range the hi and
+            # lo terms keep an absolute precision of 2^-25 in scaled units
+            de = de + np.where(e > 0, 2.0 ** -38, 0.0)
         acc = np.sqrt(nadd) * U32 * np.sqrt((e[:, None] ** 2 * R ** 2).sum(axis=0))
         out[t] = safety * (de @ np.abs(R) + acc)
     return out

@@ -82,24 +82,6 @@ def test_sample_fp64(gpu_lib, n, d, r):
     assert np.all(np.abs(S - ref) <= 1e-13 * scale + 1e-300)
 
 
-@pytest.mark.parametrize("prec", ["f32", "f16", "bf16"])
-def test_sample_reduced_precision(gpu_lib, prec):
-    n, d, r = 1200, 8, 64
-    X = sd.c2_sixteen_gaussians(n=n, m=1).X
-    Xp, lb, le = _tree_ranges(X, 100)
-    R = sd.random_block(n, r, seed=4)
-    S = gpu_lib.kernel_sample(_t(Xp), 0.75, _t(R), _t(lb), _t(le), prec=prec).cpu().numpy()
-    ref = cmath.sample_masked(Xp, R, 0.75, lb, le, np.arange(n))
-    mask = (np.arange(n)[None, :] >= lb[:, None]) & (np.arange(n)[None, :] < le[:, None])
-    bound = fp32_product_bound(Xp, Xp, R, 0.75, mask=mask)
-    if prec != "f32":
-        # split terms: each entry carries at most 2^-22 (fp16) / 2^-16 (bf16) relative error
-        q = sqdist(Xp, Xp)
-        K = np.where(mask, 0.0, np.exp(-q / (2 * 0.75 ** 2)))
-        bound = bound + 4 * (2.0 ** -16 if prec == "bf16" else 2.0 ** -22) * (K @ np.abs(R))
-    assert np.all(np.abs(S - ref) <= bound)
-
-
 def test_sample_unmasked_matches_matvec(gpu_lib):
     X = sd.points(300, 5, seed=11, dtype=np.float64)
     R = sd.random_block(300, 32, seed=5)
