@@ -176,6 +176,7 @@ typedef struct {
     int32_t oversample;  /* p: ranks must stay <= r - p, else the sample grows */
     int32_t prec;        /* sampling arithmetic (KRR_F64 .. KRR_BF16_SPLIT) */
     int32_t split_terms; /* 1 or 2 for the split modes */
+    int32_t cap_policy;  /* at r_max: 0 = fail with KRR_E_RANK_CAP, 1 = truncate ranks to r_max - p */
     uint64_t seed;       /* random block key */
 } hss_opts;
 
@@ -184,7 +185,7 @@ typedef struct {
     int32_t r_final;          /* sample width that revealed every rank */
     int32_t regrowths;        /* times the sample was widened */
     int32_t max_rank;
-    int32_t pad_;
+    int32_t truncated;        /* 1 if ranks were cut at r_max - oversample */
     int64_t bytes_paper;      /* memory metric: D, U, V, B_ij, B_ji as stored separately */
     int64_t bytes_stored;     /* generators actually stored (symmetric: U = V) */
     double t_sample_ms;       /* phase times (HIP events) */
@@ -201,7 +202,9 @@ typedef struct {
  * sibling's reduced random block; D = K(I, I) at leaves and
  * B = K(J_left, J_right) at parents are extracted in FP64.  IDs, D and B are
  * FP64.  If some rank exceeds r - oversample the sample is widened by dr
- * (only the new columns are sampled) and the IDs are redone, up to r_max.
+ * (only the new columns are sampled) and the IDs are redone, up to r_max;
+ * there, cap_policy 1 truncates every rank to r_max - oversample (recorded in
+ * the statistics) instead of failing.
  *   Xp     n x d points in tree order (xprec)
  *   stats_host  optional (may be NULL)
  * Synchronizes `stream` once per level (ranks size the next level).
@@ -238,6 +241,18 @@ int hss_export(hss_t H, int64_t *table_host, double *dbl_host, int64_t *int_host
  * pivot.  Synchronizes `stream` once at the end (pivot check).
  */
 int hss_ulv_factor(hss_t H, double lambda, void *stream, hss_ulv_t *out);
+
+/*
+ * As hss_ulv_factor, for use as a preconditioner.  In exact arithmetic every
+ * Cholesky pivot of a Schur complement of K + lambda I is at least lambda; a
+ * truncated compression can drive pivots of K_hss + lambda I below that (or
+ * negative).  Here any pivot below pivot_floor (> 0; lambda / 2 is a good
+ * choice) is raised to pivot_floor, which factors exactly the symmetric
+ * positive definite matrix K_hss + lambda I + (node-local diagonal terms) in a
+ * single pass.  clamped_host (optional) receives the number of raised pivots.
+ */
+int hss_ulv_factor_spd(hss_t H, double lambda, double pivot_floor, void *stream, hss_ulv_t *out,
+                       int64_t *clamped_host);
 
 void hss_ulv_destroy(hss_ulv_t F);
 

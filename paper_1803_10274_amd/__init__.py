@@ -195,11 +195,12 @@ class HssOptions:
     oversample: int = 10
     prec: str = "f32"
     split_terms: int = 2
+    cap_policy: int = 0
     seed: int = 1
 
     def c(self):
         return HssOpts(self.rtol, self.atol, self.r0, self.dr, self.r_max, self.oversample, _prec(self.prec),
-                       self.split_terms, self.seed & (2**64 - 1))
+                       self.split_terms, self.cap_policy, self.seed & (2**64 - 1))
 
 
 class HSS:
@@ -242,11 +243,20 @@ class HSS:
 
 
 class ULV:
-    """ULV factor of K_hss + lambda I."""
+    """ULV factor of K_hss + lambda I.  With pivot_floor > 0 (preconditioner
+    use), Cholesky pivots below the floor are raised to it so that the factor
+    is always positive definite; `clamped` counts them."""
 
-    def __init__(self, H: HSS, lam: float):
+    def __init__(self, H: HSS, lam: float, pivot_floor: float = 0.0):
         h_ = ctypes.c_void_p()
-        check(load().hss_ulv_factor(H.h, float(lam), _stream(), ctypes.byref(h_)))
+        self.clamped = 0
+        if pivot_floor > 0:
+            cl = ctypes.c_int64()
+            check(load().hss_ulv_factor_spd(H.h, float(lam), float(pivot_floor), _stream(), ctypes.byref(h_),
+                                            ctypes.byref(cl)))
+            self.clamped = cl.value
+        else:
+            check(load().hss_ulv_factor(H.h, float(lam), _stream(), ctypes.byref(h_)))
         self.h = h_
         self.hss = H
         self.lam = lam
@@ -315,9 +325,10 @@ def fit(X, y, h, lam, leaf=128, opts: HssOptions = HssOptions(), seed=7, tol=1e-
     Xp = gather_rows(X, perm)
     yp = gather_rows(y2, perm)
     H = HSS(tree, Xp, h, opts)
-    F = ULV(H, lam)
+    # as a preconditioner the factor only has to be positive definite
+    F = ULV(H, lam, pivot_floor=0.5 * lam if refine_solution else 0.0)
     ap = F.solve(yp)
-    info = {"hss": H.stats.as_dict(), "tree_stats": tree.stats.tolist()}
+    info = {"hss": H.stats.as_dict(), "tree_stats": tree.stats.tolist(), "ulv_clamped": F.clamped}
     if refine_solution:
         info["refine"] = refine(F, Xp, h, lam, yp, ap, tol=tol, max_iter=max_iter, mv_prec=mv_prec,
                                 raise_on_fail=raise_on_fail)

@@ -28,17 +28,18 @@ class ClusterOpts(ctypes.Structure):
 class HssOpts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("atol", ctypes.c_double), ("r0", ctypes.c_int32),
                 ("dr", ctypes.c_int32), ("r_max", ctypes.c_int32), ("oversample", ctypes.c_int32),
-                ("prec", ctypes.c_int32), ("split_terms", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+                ("prec", ctypes.c_int32), ("split_terms", ctypes.c_int32), ("cap_policy", ctypes.c_int32),
+                ("seed", ctypes.c_uint64)]
 
 
 class HssStats(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("n_nodes", ctypes.c_int64), ("levels", ctypes.c_int64),
                 ("r_final", ctypes.c_int32), ("regrowths", ctypes.c_int32), ("max_rank", ctypes.c_int32),
-                ("pad_", ctypes.c_int32), ("bytes_paper", ctypes.c_int64), ("bytes_stored", ctypes.c_int64),
+                ("truncated", ctypes.c_int32), ("bytes_paper", ctypes.c_int64), ("bytes_stored", ctypes.c_int64),
                 ("t_sample_ms", ctypes.c_double), ("t_id_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double)]
 
     def as_dict(self):
-        return {f[0]: getattr(self, f[0]) for f in self._fields_ if f[0] != "pad_"}
+        return {f[0]: getattr(self, f[0]) for f in self._fields_}
 
 
 class RefineStats(ctypes.Structure):
@@ -70,6 +71,7 @@ SIGNATURES = {
     "hss_export_sizes": (ctypes.c_int, [_vp, _P(_i64), _P(_i64), _P(_i64)]),
     "hss_export": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "hss_ulv_factor": (ctypes.c_int, [_vp, _dbl, _vp, _P(_vp)]),
+    "hss_ulv_factor_spd": (ctypes.c_int, [_vp, _dbl, _dbl, _vp, _P(_vp), _P(_i64)]),
     "hss_ulv_destroy": (None, [_vp]),
     "hss_solve": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp]),
     "krr_refine": (ctypes.c_int, [_vp, _vp, _i32, _i32, _dbl, _dbl, _vp, _i32, _vp, _dbl, _i32, _i32, _vp,

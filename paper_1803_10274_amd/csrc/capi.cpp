@@ -1,7 +1,9 @@
 // The extern "C" boundary of libkrr (declared in include/krr.h): argument
 // checks, handle lifetime, and translation of internal failures into status
 // codes with a per-thread message.  Nothing throws across this boundary.
+#include <algorithm>
 #include <cstdarg>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -11,6 +13,14 @@
 namespace krr {
 
 thread_local std::string g_last_error;
+
+bool verbose() {
+    static const bool v = [] {
+        const char *e = std::getenv("KRR_VERBOSE");
+        return e && *e && *e != '0';
+    }();
+    return v;
+}
 
 void fail(int code, const char *fmt, ...) {
     char buf[1024];
@@ -35,7 +45,7 @@ void gather_rows(const void *src, int prec, int64_t n, int cols, const int64_t *
                  hipStream_t s);
 void compress(const krr_tree_s *t, const void *Xp, int xprec, int d, double h, const hss_opts &o, hipStream_t s,
               hss_s *H, hss_stats *st);
-void ulv_factor(const hss_s *H, double lambda, hipStream_t s, hss_ulv_s *F);
+int64_t ulv_factor(const hss_s *H, double lambda, double pivot_floor, hipStream_t s, hss_ulv_s *F);
 void ulv_solve(const hss_ulv_s *F, const double *Bin, int nrhs, double *Xout, hipStream_t s);
 int refine(const hss_ulv_s *F, const void *Xp, int xprec, int d, double h, double lambda, const double *Y, int nrhs,
            double *alpha, double tol, int max_iter, int mv_prec, hipStream_t s, krr_refine_stats *st);
@@ -253,6 +263,7 @@ int hss_compress(krr_tree t, const void *Xp, int32_t xprec, int32_t d, double h,
         KRR_REQUIRE(o.oversample >= 0 && o.oversample < o.r0, "hss_compress: bad oversample");
         KRR_REQUIRE(o.prec >= KRR_F64 && o.prec <= KRR_BF16_SPLIT, "hss_compress: bad prec");
         KRR_REQUIRE(o.split_terms == 1 || o.split_terms == 2, "hss_compress: split_terms must be 1 or 2");
+        KRR_REQUIRE(o.cap_policy == 0 || o.cap_policy == 1, "hss_compress: cap_policy must be 0 or 1");
         validate_tree(t);
         require_device();
         auto *H = new hss_s();
@@ -319,7 +330,30 @@ int hss_ulv_factor(hss_t H, double lambda, void *stream, hss_ulv_t *out) {
         require_device();
         auto *F = new hss_ulv_s();
         try {
-            ulv_factor(H, lambda, S(stream), F);
+            ulv_factor(H, lambda, 0.0, S(stream), F);
+        } catch (...) {
+            delete F;
+            throw;
+        }
+        *out = F;
+        return KRR_OK;
+    });
+}
+
+int hss_ulv_factor_spd(hss_t H, double lambda, double pivot_floor, void *stream, hss_ulv_t *out,
+                       int64_t *clamped_host) {
+    return guard([&] {
+        KRR_REQUIRE(out != nullptr, "hss_ulv_factor_spd: NULL out");
+        *out = nullptr;
+        KRR_REQUIRE(H != nullptr, "hss_ulv_factor_spd: NULL handle");
+        KRR_REQUIRE(lambda >= 0.0, "hss_ulv_factor_spd: lambda must be >= 0");
+        KRR_REQUIRE(pivot_floor > 0.0, "hss_ulv_factor_spd: pivot_floor must be > 0");
+        require_device();
+        auto *F = new hss_ulv_s();
+        try {
+            int64_t clamped = ulv_factor(H, lambda, pivot_floor, S(stream), F);
+            if (clamped_host) *clamped_host = clamped;
+            if (verbose()) fprintf(stderr, "[krr] ulv factor: %lld pivots raised to %g\n", (long long)clamped, pivot_floor);
         } catch (...) {
             delete F;
             throw;

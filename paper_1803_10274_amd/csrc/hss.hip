@@ -124,7 +124,7 @@ __global__ __launch_bounds__(BG_T) void k_gram(const NodeDesc *nds, int r) {
 
 // Pivoted Cholesky of G = Y Y^T with the ID stopping rule.  Dynamic LDS:
 // m doubles (residual diagonal) + m ints (pivoted flags).
-__global__ __launch_bounds__(BG_T) void k_pivchol(const NodeDesc *nds, int r, double rtol, double atol_abs,
+__global__ __launch_bounds__(BG_T) void k_pivchol(const NodeDesc *nds, int r, int kmax, double rtol, double atol_abs,
                                                   int32_t *kout, int32_t *flag) {
     extern __shared__ double dyn[];
     __shared__ double redv[BG_T / 64];
@@ -138,7 +138,7 @@ __global__ __launch_bounds__(BG_T) void k_pivchol(const NodeDesc *nds, int r, do
         done[i] = 0;
     }
     __syncthreads();
-    const int kcap = min(m, r);
+    const int kcap = min(m, min(r, kmax));
     double r00 = 0.0;
     int j = 0;
     bool bad = false;
@@ -252,7 +252,7 @@ struct Attempt {
 
 // Runs every level with sample width r.  Returns false when some rank
 // reached r - p while its sample could have hidden more.
-bool run_levels(hss_s *H, const void *Xp, int xprec, int d, double h, const hss_opts &o, int r,
+bool run_levels(hss_s *H, const void *Xp, int xprec, int d, double h, const hss_opts &o, int r, bool truncate,
                 const float *R, const void *S, bool s64, double *Dpool, const std::vector<int64_t> &doff,
                 Attempt &A, hipStream_t s, double &t_id) {
     EventTimer timer(s);
@@ -338,7 +338,8 @@ bool run_levels(hss_s *H, const void *Xp, int xprec, int d, double h, const hss_
         DBuf kout = dalloc<int32_t>(cnt);
         size_t dyn = (size_t)mmax * (sizeof(double) + sizeof(int));
         KRR_REQUIRE(dyn <= 150 * 1024, "node sample of %d rows exceeds the LDS budget", mmax);
-        k_pivchol<<<cnt, BG_T, dyn, s>>>(dq, r, o.rtol, atol_abs, kout.as<int32_t>(), flag.as<int32_t>());
+        const int kmax = truncate ? std::max(0, r - o.oversample) : r;
+        k_pivchol<<<cnt, BG_T, dyn, s>>>(dq, r, kmax, o.rtol, atol_abs, kout.as<int32_t>(), flag.as<int32_t>());
         check_launch("k_pivchol");
         std::vector<int32_t> ks(cnt);
         int32_t bad = 0;
@@ -354,7 +355,16 @@ bool run_levels(hss_s *H, const void *Xp, int xprec, int d, double h, const hss_
             usz += (int64_t)nd[a].m * ks[a];
             ksz += ks[a];
         }
-        if (grow) return false;
+        if (verbose()) {
+            int mk = 0, mm = 0;
+            for (int a = 0; a < cnt; ++a) {
+                mk = std::max(mk, (int)ks[a]);
+                mm = std::max(mm, (int)nd[a].m);
+            }
+            fprintf(stderr, "[krr] compress r=%d level h=%d nodes=%d max m=%d max k=%d%s\n", r,
+                    H->node[ids[0]].height, cnt, mm, mk, grow ? " -> grow" : "");
+        }
+        if (grow && !truncate) return false;
         DBuf Ub = dalloc<double>(usz), Jb = dalloc<int32_t>(ksz), Sk = dalloc<double>(ksz * r),
              Om = dalloc<double>(ksz * r);
         {
@@ -434,9 +444,15 @@ void compress(const krr_tree_s *t, const void *Xp, int xprec, int d, double h, c
     }
     Attempt A;
     int regrowths = 0;
-    while (!run_levels(H, Xp, xprec, d, h, o, r, R.as<float>(), S.get(), s64, H->D.as<double>(), doff, A, s, t_id)) {
-        if (r >= o.r_max)
-            fail(KRR_E_RANK_CAP, "ranks not revealed with the sample width cap r_max = %d", o.r_max);
+    bool truncated = false;
+    while (!run_levels(H, Xp, xprec, d, h, o, r, truncated, R.as<float>(), S.get(), s64, H->D.as<double>(), doff, A,
+                       s, t_id)) {
+        if (r >= o.r_max) {
+            if (o.cap_policy == 0)
+                fail(KRR_E_RANK_CAP, "ranks not revealed with the sample width cap r_max = %d", o.r_max);
+            truncated = true;  // redo the levels once more, cutting ranks at r_max - p
+            continue;
+        }
         int r2 = std::min(o.r_max, r + o.dr);
         int dr = r2 - r;
         EventTimer ts(s);
@@ -504,7 +520,9 @@ void compress(const krr_tree_s *t, const void *Xp, int xprec, int d, double h, c
     H->r_final = r;
     H->regrowths = regrowths;
     H->max_rank = maxk;
+    H->truncated = truncated ? 1 : 0;
     if (st) {
+        st->truncated = H->truncated;
         st->n = n;
         st->n_nodes = nn;
         st->levels = (int64_t)H->levels.size();

@@ -40,6 +40,9 @@ std::vector<std::vector<int>> levels_by_height(std::vector<HNode> &nodes);
 
 void validate_tree(const krr_tree_s *t);
 
+// Diagnostic logging to stderr when the environment sets KRR_VERBOSE.
+bool verbose();
+
 }  // namespace krr
 
 struct hss_s {
@@ -50,7 +53,7 @@ struct hss_s {
     std::vector<std::vector<int>> levels;
     krr::DBuf U, D, B, J;     // generator pools (FP64, FP64, FP64, int32)
     int64_t nU = 0, nD = 0, nB = 0, nJ = 0;
-    int32_t r_final = 0, regrowths = 0, max_rank = 0;
+    int32_t r_final = 0, regrowths = 0, max_rank = 0, truncated = 0;
 };
 
 struct hss_ulv_s {

@@ -1,7 +1,8 @@
 // Gaussian-kernel products without storing K (eq. (1.1)):
-//   * kernel_matvec: Out = K(X, Y; h) W for a few right-hand sides, entries
-//     formed from exact coordinate differences (no norm expansion, so no
-//     cancellation), FP32 sums over a 64-column tile and FP64 across tiles;
+//   * kernel_matvec: Out = K(X, Y; h) W for a few right-hand sides; FP64
+//     entries from exact coordinate differences, FP32 entries from an FP64
+//     norm expansion of the exponent; FP32 sums over a 64-column tile and
+//     FP64 across tiles;
 //   * the tiled VALU sampling product S = K R with each row's own leaf block
 //     removed (Section 3.1 randomized construction), used for FP64 samples
 //     and as the portable reference of the matrix-core sampler;
@@ -20,6 +21,8 @@ __device__ __forceinline__ double kexp(double q, double s) { return exp(-q * s);
 
 template <class C> C kernel_scale(double h);
 template <> float kernel_scale<float>(double h) { return (float)(1.4426950408889634 / (2.0 * h * h)); }
+// the FP64 exponent of the FP32-entry expansion kernel keeps c in FP64
+inline double kernel_scale_log2(double h) { return 1.4426950408889634 / (2.0 * h * h); }
 template <> double kernel_scale<double>(double h) { return 1.0 / (2.0 * h * h); }
 
 // ---------------------------------------------------------- kernel_matvec
@@ -73,6 +76,75 @@ __global__ __launch_bounds__(MV_ROWS) void k_kmv(const T *__restrict__ X, int64_
             C kv = kexp(q, scale);
 #pragma unroll
             for (int r = 0; r < NR; ++r) pacc[r] = fma(kv, ws[jj][r], pacc[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < NR; ++r) acc[r] += (double)pacc[r];
+        __syncthreads();
+    }
+    if (i < m) {
+        for (int r = 0; r < nr; ++r) part[((int64_t)split * m + i) * nrhs + rhs0 + r] = acc[r];
+    }
+}
+
+// FP32-entry mode for d <= 64: the exponent is formed in FP64 by the norm
+// expansion t = -c |x_i|^2 - c |y_j|^2 + sum_k (2 c x_ik) y_jk (c in log2
+// units): FP64 FMAs cost the same as FP32 ones on this chip, the expansion
+// needs d + 1 of them instead of 2 d for the differences, and in FP64 its
+// cancellation is harmless.  The kernel value is exp2 of t rounded to FP32;
+// products and the tile sum are FP32, sums across tiles FP64.
+template <class T, int D, int NR>
+__global__ __launch_bounds__(MV_ROWS) void k_kmv_expand(const T *__restrict__ X, int64_t m,
+                                                        const T *__restrict__ Y, int64_t n, int d, double c2,
+                                                        const double *__restrict__ W, int nrhs, int rhs0,
+                                                        int64_t cols_per_split, double *__restrict__ part) {
+    __shared__ double ys[MV_TN][D + 1];
+    __shared__ float ws[MV_TN][NR];
+    const int tid = threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * MV_ROWS + tid;
+    const int split = blockIdx.y;
+    const int64_t j0 = split * cols_per_split;
+    const int64_t j1 = min(n, j0 + cols_per_split);
+    double xs[D];
+    double nx = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        double v = (i < m && k < d) ? (double)X[i * d + k] : 0.0;
+        nx = fma(v, v, nx);
+        xs[k] = 2.0 * c2 * v;
+    }
+    nx = -c2 * nx;
+    double acc[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) acc[r] = 0.0;
+    const int nr = min(NR, nrhs - rhs0);
+    for (int64_t jt = j0; jt < j1; jt += MV_TN) {
+        for (int jj = tid; jj < MV_TN; jj += MV_ROWS) {
+            int64_t j = jt + jj;
+            double nrm = 0.0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                double v = (j < j1 && k < d) ? (double)Y[j * d + k] : 0.0;
+                ys[jj][k] = v;
+                nrm = fma(v, v, nrm);
+            }
+            ys[jj][D] = (j < j1) ? -c2 * nrm : -1e300;
+        }
+        for (int t = tid; t < MV_TN * NR; t += MV_ROWS) {
+            int jj = t / NR, r = t % NR;
+            int64_t j = jt + jj;
+            ws[jj][r] = (j < j1 && r < nr) ? (float)W[j * nrhs + rhs0 + r] : 0.0f;
+        }
+        __syncthreads();
+        float pacc[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) pacc[r] = 0.0f;
+        for (int jj = 0; jj < MV_TN; ++jj) {
+            double t = nx + ys[jj][D];
+#pragma unroll
+            for (int k = 0; k < D; ++k) t = fma(xs[k], ys[jj][k], t);
+            float kv = __builtin_amdgcn_exp2f((float)fmax(t, -1000.0));
+#pragma unroll
+            for (int r = 0; r < NR; ++r) pacc[r] = fmaf(kv, ws[jj][r], pacc[r]);
         }
 #pragma unroll
         for (int r = 0; r < NR; ++r) acc[r] += (double)pacc[r];
@@ -158,10 +230,12 @@ __global__ void k_reduce_splits(const double *__restrict__ part, int nsplit, int
 }
 
 template <class T, class C, int D, int NR>
-void launch_kmv(const T *X, int64_t m, const T *Y, int64_t n, int d, C scale, const double *W,
+void launch_kmv(const T *X, int64_t m, const T *Y, int64_t n, int d, C scale, double c2, const double *W,
                 int nrhs, int rhs0, int nsplit, int64_t cps, double *part, hipStream_t s) {
     dim3 grid(ceil_div(m, MV_ROWS), nsplit);
-    if (D > 0)
+    if (D > 0 && sizeof(C) == 4)
+        k_kmv_expand<T, (D > 0 ? D : 1), NR><<<grid, MV_ROWS, 0, s>>>(X, m, Y, n, d, c2, W, nrhs, rhs0, cps, part);
+    else if (D > 0)
         k_kmv<T, C, (D > 0 ? D : 1), NR><<<grid, MV_ROWS, 0, s>>>(X, m, Y, n, d, scale, W, nrhs, rhs0, cps, part);
     else
         k_kmv_wide<T, C, NR><<<grid, MV_ROWS, 0, s>>>(X, m, Y, n, d, scale, W, nrhs, rhs0, cps, part);
@@ -169,24 +243,25 @@ void launch_kmv(const T *X, int64_t m, const T *Y, int64_t n, int d, C scale, co
 }
 
 template <class T, class C, int NR>
-void dispatch_d(const T *X, int64_t m, const T *Y, int64_t n, int d, C scale, const double *W, int nrhs,
+void dispatch_d(const T *X, int64_t m, const T *Y, int64_t n, int d, C scale, double c2, const double *W, int nrhs,
                 int rhs0, int nsplit, int64_t cps, double *part, hipStream_t s) {
     if (d <= 8)
-        launch_kmv<T, C, 8, NR>(X, m, Y, n, d, scale, W, nrhs, rhs0, nsplit, cps, part, s);
+        launch_kmv<T, C, 8, NR>(X, m, Y, n, d, scale, c2, W, nrhs, rhs0, nsplit, cps, part, s);
     else if (d <= 16)
-        launch_kmv<T, C, 16, NR>(X, m, Y, n, d, scale, W, nrhs, rhs0, nsplit, cps, part, s);
+        launch_kmv<T, C, 16, NR>(X, m, Y, n, d, scale, c2, W, nrhs, rhs0, nsplit, cps, part, s);
     else if (d <= 32)
-        launch_kmv<T, C, 32, NR>(X, m, Y, n, d, scale, W, nrhs, rhs0, nsplit, cps, part, s);
+        launch_kmv<T, C, 32, NR>(X, m, Y, n, d, scale, c2, W, nrhs, rhs0, nsplit, cps, part, s);
     else if (d <= 64)
-        launch_kmv<T, C, 64, NR>(X, m, Y, n, d, scale, W, nrhs, rhs0, nsplit, cps, part, s);
+        launch_kmv<T, C, 64, NR>(X, m, Y, n, d, scale, c2, W, nrhs, rhs0, nsplit, cps, part, s);
     else
-        launch_kmv<T, C, 0, NR>(X, m, Y, n, d, scale, W, nrhs, rhs0, nsplit, cps, part, s);
+        launch_kmv<T, C, 0, NR>(X, m, Y, n, d, scale, c2, W, nrhs, rhs0, nsplit, cps, part, s);
 }
 
 template <class T, class C>
 void kmv_typed(const T *X, int64_t m, const T *Y, int64_t n, int d, double h, const double *W, int nrhs,
                double beta, double *Out, hipStream_t s) {
     const C scale = kernel_scale<C>(h);
+    const double c2 = kernel_scale_log2(h);
     // split the columns so that the grid has enough blocks to fill the chip
     const int64_t row_blocks = ceil_div(m, MV_ROWS);
     int nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(2048, row_blocks), ceil_div(n, 4 * MV_TN)));
@@ -197,19 +272,19 @@ void kmv_typed(const T *X, int64_t m, const T *Y, int64_t n, int d, double h, co
     for (int r0 = 0; r0 < nrhs;) {
         int left = nrhs - r0;
         if (left >= 16) {
-            dispatch_d<T, C, 16>(X, m, Y, n, d, scale, W, nrhs, r0, nsplit, cps, part.as<double>(), s);
+            dispatch_d<T, C, 16>(X, m, Y, n, d, scale, c2, W, nrhs, r0, nsplit, cps, part.as<double>(), s);
             r0 += 16;
         } else if (left >= 8) {
-            dispatch_d<T, C, 8>(X, m, Y, n, d, scale, W, nrhs, r0, nsplit, cps, part.as<double>(), s);
+            dispatch_d<T, C, 8>(X, m, Y, n, d, scale, c2, W, nrhs, r0, nsplit, cps, part.as<double>(), s);
             r0 += 8;
         } else if (left >= 4) {
-            dispatch_d<T, C, 4>(X, m, Y, n, d, scale, W, nrhs, r0, nsplit, cps, part.as<double>(), s);
+            dispatch_d<T, C, 4>(X, m, Y, n, d, scale, c2, W, nrhs, r0, nsplit, cps, part.as<double>(), s);
             r0 += 4;
         } else if (left >= 2) {
-            dispatch_d<T, C, 2>(X, m, Y, n, d, scale, W, nrhs, r0, nsplit, cps, part.as<double>(), s);
+            dispatch_d<T, C, 2>(X, m, Y, n, d, scale, c2, W, nrhs, r0, nsplit, cps, part.as<double>(), s);
             r0 += 2;
         } else {
-            dispatch_d<T, C, 1>(X, m, Y, n, d, scale, W, nrhs, r0, nsplit, cps, part.as<double>(), s);
+            dispatch_d<T, C, 1>(X, m, Y, n, d, scale, c2, W, nrhs, r0, nsplit, cps, part.as<double>(), s);
             r0 += 1;
         }
     }

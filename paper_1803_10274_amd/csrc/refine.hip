@@ -140,6 +140,7 @@ int refine(const hss_ulv_s *F, const void *Xp, int xprec, int d, double h, doubl
             axpby(ma, q.as<double>(), one, r.as<double>(), n, nrhs, coef, s); // r -= a q
             rr = dots(r.as<double>(), r.as<double>(), n, nrhs, dout, scratch, s);
             std::vector<double> rec = rel(rr);
+            if (verbose()) fprintf(stderr, "[krr] refine it=%d relres(recurrence)=%.3e\n", it, rec[0]);
             bool stop = true;
             for (int c = 0; c < nrhs; ++c) {
                 if (rec[c] <= 0.5 * tol) done[c] = true;
@@ -160,6 +161,7 @@ int refine(const hss_ulv_s *F, const void *Xp, int xprec, int d, double h, doubl
         rr = dots(r.as<double>(), r.as<double>(), n, nrhs, dout, scratch, s);
         relres = rel(rr);
         converged = all_below(relres);
+        if (verbose()) fprintf(stderr, "[krr] refine it=%d true relres=%.3e\n", it, relres[0]);
     }
     if (st) {
         st->iterations = it;

@@ -31,7 +31,8 @@ struct UlvDesc {
     double *S_out, *Rh_out;            // passed to the parent
 };
 
-__global__ __launch_bounds__(BG_T) void k_ulv_factor(const UlvDesc *dsc, int32_t *flag) {
+__global__ __launch_bounds__(BG_T) void k_ulv_factor(const UlvDesc *dsc, double pivot_floor, int32_t *flag,
+                                                     unsigned long long *clamped) {
     __shared__ double smem[2 * 16 * 65];
     __shared__ double red[BG_T / 64];
     const UlvDesc q = dsc[blockIdx.x];
@@ -116,11 +117,20 @@ __global__ __launch_bounds__(BG_T) void k_ulv_factor(const UlvDesc *dsc, int32_t
             int i = t / k, c = t % k;
             q.Rh_out[t] = (c >= i) ? Uw[(int64_t)i * k + c] : 0.0;
         }
-    // ---- Cholesky of A_ee = Dw[k:, k:] (right-looking, in place)
+    // ---- Cholesky of A_ee = Dw[k:, k:] (right-looking, in place); with a
+    // pivot floor, smaller pivots are raised to it (adds a diagonal term)
     bool bad = false;
     for (int j = 0; j < ne; ++j) {
         double *Ajj = Dw + (int64_t)(k + j) * m + k + j;
         double djj = *Ajj;
+        if (pivot_floor > 0.0 && !(djj >= pivot_floor)) {
+            if (!(djj == djj) || isinf(djj)) {
+                bad = true;
+                break;
+            }
+            djj = pivot_floor;
+            if (tid == 0) atomicAdd(clamped, 1ull);
+        }
         if (!(djj > 0.0)) {
             bad = true;
             break;
@@ -285,7 +295,7 @@ __global__ __launch_bounds__(BG_T) void k_ulv_bwd(const SolveDesc *dsc, double *
 
 }  // namespace
 
-void ulv_factor(const hss_s *H, double lambda, hipStream_t s, hss_ulv_s *F) {
+int64_t ulv_factor(const hss_s *H, double lambda, double pivot_floor, hipStream_t s, hss_ulv_s *F) {
     const int nn = (int)H->node.size();
     const int root = nn - 1;
     F->n = H->n;
@@ -326,8 +336,9 @@ void ulv_factor(const hss_s *H, double lambda, hipStream_t s, hss_ulv_s *F) {
         ns += (int64_t)k[i] * k[i];
     }
     DBuf Sb = dalloc<double>(std::max<int64_t>(ns, 1)), Rb = dalloc<double>(std::max<int64_t>(ns, 1));
-    DBuf flag = dalloc<int32_t>(1);
+    DBuf flag = dalloc<int32_t>(1), nclamp = dalloc<unsigned long long>(1);
     KRR_HIP(hipMemsetAsync(flag.get(), 0, sizeof(int32_t), s));
+    KRR_HIP(hipMemsetAsync(nclamp.get(), 0, sizeof(unsigned long long), s));
     for (const auto &lv : H->levels) {
         const int cnt = (int)lv.size();
         int64_t dsz = 0, usz = 0, tsz = 0;
@@ -377,14 +388,18 @@ void ulv_factor(const hss_s *H, double lambda, hipStream_t s, hss_ulv_s *F) {
             u.Rh_out = Rb.as<double>() + offS[id];
         }
         DBuf dd = upload(dsc, s);
-        k_ulv_factor<<<cnt, BG_T, 0, s>>>(dd.as<UlvDesc>(), flag.as<int32_t>());
+        k_ulv_factor<<<cnt, BG_T, 0, s>>>(dd.as<UlvDesc>(), pivot_floor, flag.as<int32_t>(),
+                                          nclamp.as<unsigned long long>());
         check_launch("k_ulv_factor");
         sync(s);
     }
     int32_t bad = 0;
+    unsigned long long cl = 0;
     d2h(&bad, flag.as<int32_t>(), 1, s);
+    d2h(&cl, nclamp.as<unsigned long long>(), 1, s);
     sync(s);
     if (bad) fail(KRR_E_NUMERIC, "ULV: non-positive pivot in a Cholesky factor (K_hss + lambda I not SPD)");
+    return (int64_t)cl;
 }
 
 void ulv_solve(const hss_ulv_s *F, const double *Bin, int nrhs, double *Xout, hipStream_t s) {
