@@ -214,6 +214,11 @@ int hss_compress(krr_tree t, const void *Xp, int32_t xprec, int32_t d, double h,
 
 void hss_destroy(hss_t H);
 
+/* y = K_hss x for n x nrhs FP64 blocks in the permuted order (the matrix the
+ * generators represent, without lambda): upward pass through the nested
+ * bases, coupling blocks, downward pass, dense leaf blocks. */
+int hss_matvec(hss_t H, const double *x, int32_t nrhs, double *y, void *stream);
+
 /* Sizes of the generator export: node count, FP64 values, int64 values. */
 int hss_export_sizes(hss_t H, int64_t *n_nodes_host, int64_t *n_dbl_host,
                      int64_t *n_int_host);

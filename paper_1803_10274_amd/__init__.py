@@ -215,6 +215,13 @@ class HSS:
                                   _stream(), ctypes.byref(h_), ctypes.byref(self.stats)))
         self.h = h_
 
+    def matvec(self, x: torch.Tensor) -> torch.Tensor:
+        """K_hss x (permuted order, FP64)."""
+        x2 = _dev(x, torch.float64).reshape(x.shape[0], -1)
+        y = torch.empty_like(x2)
+        check(load().hss_matvec(self.h, _p(x2), x2.shape[1], _p(y), _stream()))
+        return y.reshape(x.shape)
+
     def export(self):
         """Generators on the host: dict with nodes (n x 10 table), U, D, B, J per node."""
         nn, nd, ni = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()

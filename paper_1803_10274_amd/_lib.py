@@ -68,6 +68,7 @@ SIGNATURES = {
                                          _vp, _i32, _vp]),
     "hss_compress": (ctypes.c_int, [_vp, _vp, _i32, _i32, _dbl, _P(HssOpts), _vp, _P(_vp), _P(HssStats)]),
     "hss_destroy": (None, [_vp]),
+    "hss_matvec": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp]),
     "hss_export_sizes": (ctypes.c_int, [_vp, _P(_i64), _P(_i64), _P(_i64)]),
     "hss_export": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "hss_ulv_factor": (ctypes.c_int, [_vp, _dbl, _vp, _P(_vp)]),

@@ -47,6 +47,7 @@ void compress(const krr_tree_s *t, const void *Xp, int xprec, int d, double h, c
               hss_s *H, hss_stats *st);
 int64_t ulv_factor(const hss_s *H, double lambda, double pivot_floor, hipStream_t s, hss_ulv_s *F);
 void ulv_solve(const hss_ulv_s *F, const double *Bin, int nrhs, double *Xout, hipStream_t s);
+void hss_matvec_impl(const hss_s *H, const double *x, int nrhs, double *y, hipStream_t s);
 int refine(const hss_ulv_s *F, const void *Xp, int xprec, int d, double h, double lambda, const double *Y, int nrhs,
            double *alpha, double tol, int max_iter, int mv_prec, hipStream_t s, krr_refine_stats *st);
 void predict_labels(const double *scores, int64_t m, int k, int32_t *labels, hipStream_t s);
@@ -279,6 +280,15 @@ int hss_compress(krr_tree t, const void *Xp, int32_t xprec, int32_t d, double h,
 }
 
 void hss_destroy(hss_t H) { delete H; }
+
+int hss_matvec(hss_t H, const double *x, int32_t nrhs, double *y, void *stream) {
+    return guard([&] {
+        KRR_REQUIRE(H != nullptr && x && y && nrhs >= 1, "hss_matvec: bad arguments");
+        require_device();
+        hss_matvec_impl(H, x, nrhs, y, S(stream));
+        return KRR_OK;
+    });
+}
 
 int hss_export_sizes(hss_t H, int64_t *n_nodes_host, int64_t *n_dbl_host, int64_t *n_int_host) {
     return guard([&] {

@@ -117,18 +117,42 @@ __global__ __launch_bounds__(BG_T) void k_ulv_factor(const UlvDesc *dsc, double 
             int i = t / k, c = t % k;
             q.Rh_out[t] = (c >= i) ? Uw[(int64_t)i * k + c] : 0.0;
         }
-    // ---- Cholesky of A_ee = Dw[k:, k:] (right-looking, in place); with a
-    // pivot floor, smaller pivots are raised to it (adds a diagonal term)
+    // ---- Cholesky of A_ee = Dw[k:, k:] (right-looking, in place).  With a
+    // pivot floor, a pivot d below it is replaced, as in the modified Cholesky
+    // of Gill, Murray and Wright, by max(floor, |d|, theta^2 / beta^2), theta
+    // the largest entry below the pivot and beta^2 the largest diagonal entry
+    // of A_ee: this bounds the factor's entries by beta (no growth) and adds a
+    // nonnegative diagonal term.
     bool bad = false;
+    double beta2 = 0.0;
+    if (pivot_floor > 0.0) {
+        double mx = 0.0;
+        for (int i = tid; i < ne; i += BG_T) mx = fmax(mx, fabs(Dw[(int64_t)(k + i) * m + k + i]));
+        mx = wave_max(mx);
+        __syncthreads();
+        if ((tid & 63) == 0) red[tid >> 6] = mx;
+        __syncthreads();
+        for (int i = 0; i < BG_T / 64; ++i) beta2 = fmax(beta2, red[i]);
+        beta2 = fmax(beta2, pivot_floor);
+        __syncthreads();
+    }
     for (int j = 0; j < ne; ++j) {
         double *Ajj = Dw + (int64_t)(k + j) * m + k + j;
         double djj = *Ajj;
+        if (!(djj == djj) || isinf(djj)) {
+            bad = true;
+            break;
+        }
         if (pivot_floor > 0.0 && !(djj >= pivot_floor)) {
-            if (!(djj == djj) || isinf(djj)) {
-                bad = true;
-                break;
-            }
-            djj = pivot_floor;
+            double th = 0.0;
+            for (int i = j + 1 + tid; i < ne; i += BG_T) th = fmax(th, fabs(Dw[(int64_t)(k + i) * m + k + j]));
+            th = wave_max(th);
+            __syncthreads();
+            if ((tid & 63) == 0) red[tid >> 6] = th;
+            __syncthreads();
+            double theta = 0.0;
+            for (int i = 0; i < BG_T / 64; ++i) theta = fmax(theta, red[i]);
+            djj = fmax(fmax(pivot_floor, fabs(djj)), theta * theta / beta2);
             if (tid == 0) atomicAdd(clamped, 1ull);
         }
         if (!(djj > 0.0)) {

@@ -163,3 +163,12 @@ def test_refined_fit_reaches_tolerance(gpu_lib, prec):
     a_ref = ok.krr_fit_dense(p.X, p.y, p.h, p.lam)
     assert np.linalg.norm(a - a_ref) / np.linalg.norm(a_ref) <= 1e-4
     assert res.info["refine"]["converged"]
+
+
+def test_hss_matvec_matches_assembled(gpu_lib):
+    p = sd.c1_two_gaussians()
+    t, Xp, H = _compress(gpu_lib, p.X, p.leaf, p.h, 1e-3)
+    A = oh.assemble(_as_oracle(H.export(), t.nodes))
+    x = sd.vectors(p.n, 3, seed=21)
+    got = H.matvec(_t(x)).cpu().numpy()
+    np.testing.assert_allclose(got, A @ x, rtol=1e-12, atol=1e-12 * np.abs(A @ x).max())
