@@ -36,6 +36,7 @@ def parse():
     ap.add_argument("--split", type=int, default=2)
     ap.add_argument("--rtol", type=float, default=1e-2)
     ap.add_argument("--r0", type=int, default=256)
+    ap.add_argument("--atol", type=float, default=3.0)
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-sampling comparison fit")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--sample-reps", type=int, default=3)
@@ -65,7 +66,8 @@ def main():
     y = torch.from_numpy(p.y).to(dev)
     Xt = torch.from_numpy(p.Xt).to(dev)
     torch.cuda.synchronize()
-    opts = krr.HssOptions(rtol=args.rtol, r0=args.r0, dr=args.r0, prec=args.prec, split_terms=args.split)
+    opts = krr.HssOptions(rtol=args.rtol, atol=args.atol, r0=args.r0, dr=args.r0, r_max=args.r0, prec=args.prec,
+                          split_terms=args.split, cap_policy=1)
 
     def step(o):
         res = krr.fit(X, y, p.h, p.lam, leaf=p.leaf, opts=o, tol=1e-6, max_iter=300, raise_on_fail=False)
@@ -79,7 +81,8 @@ def main():
         t0 = time.perf_counter()
         res, lab, t_fit = step(opts)
         log(f"warmup {i}: fit {t_fit - t0:.3f} s, total {time.perf_counter() - t0:.3f} s, "
-            f"hss {res.info['hss']}, refine {res.info['refine']}")
+            f"phases {res.info['phases']}, shift {res.info['ulv_shift']}, hss {res.info['hss']}, "
+            f"refine it {res.info['refine']['iterations']} relres {res.info['refine']['relres'][0]:.2e}")
     fit_times, step_times = [], []
     torch.cuda.synchronize()
     t_all = time.perf_counter()
@@ -88,7 +91,7 @@ def main():
         res, lab, t_fit = step(opts)
         fit_times.append(t_fit - t0)
         step_times.append(time.perf_counter() - t0)
-        log(f"step {i}: fit {fit_times[-1]:.3f} s, step {step_times[-1]:.3f} s, "
+        log(f"step {i}: fit {fit_times[-1]:.3f} s, step {step_times[-1]:.3f} s, phases {res.info['phases']}, "
             f"refine {res.info['refine']['iterations']} it relres {res.info['refine']['relres'][0]:.2e}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_all
@@ -99,10 +102,11 @@ def main():
     # FP32-sampling comparison fit, same data, tree, lambda and tolerance
     fp32 = None
     if not args.no_fp32:
-        o32 = krr.HssOptions(rtol=args.rtol, r0=args.r0, dr=args.r0, prec="f32")
+        o32 = krr.HssOptions(rtol=args.rtol, atol=args.atol, r0=args.r0, dr=args.r0, r_max=args.r0, prec="f32",
+                             cap_policy=1)
         t0 = time.perf_counter()
         r32, _, t_fit32 = step(o32)
-        fp32 = {"fit_s": t_fit32 - t0, "t_sample_ms": r32.info["hss"]["t_sample_ms"],
+        fp32 = {"fit_s": t_fit32 - t0, "phases": r32.info["phases"], "t_sample_ms": r32.info["hss"]["t_sample_ms"],
                 "refine_iterations": r32.info["refine"]["iterations"],
                 "relres": r32.info["refine"]["relres"][0], "r_final": r32.info["hss"]["r_final"]}
         log(f"fp32 fit: {fp32}")
@@ -158,9 +162,11 @@ def main():
         "dtype": f"{args.prec}-split{args.split}/f32/f64",
         "data": "synthetic",
         "config": {"workload": f"sixteen_gaussians n={n} d={p.d} h={p.h} lambda={p.lam} leaf={p.leaf} "
-                               f"rtol={args.rtol} r0={args.r0} test_m={args.m}",
+                               f"rtol={args.rtol} atol={args.atol} r={args.r0} test_m={args.m}",
                    "sampling": args.prec, "split_terms": args.split},
         "fit_s_min": float(np.min(fit_times)),
+        "phases_s": res.info["phases"],
+        "ulv_shift": res.info["ulv_shift"],
         "fp32": fp32,
         "sample_tflops": achieved / 1e12,
         "relres": rf["relres"][0],

@@ -259,6 +259,17 @@ int hss_ulv_factor(hss_t H, double lambda, void *stream, hss_ulv_t *out);
 int hss_ulv_factor_spd(hss_t H, double lambda, double pivot_floor, void *stream, hss_ulv_t *out,
                        int64_t *clamped_host);
 
+/*
+ * As hss_ulv_factor, for use as a preconditioner: factors K_hss + (lambda +
+ * delta) I with the smallest delta found (0 first) for which every pivot is
+ * at least lambda / 2.  After a failed pass, which is completed with raised
+ * pivots so that the largest deficit d over all nodes is known, the next try
+ * uses delta + 1.5 d + lambda / 4; at most 8 tries (else KRR_E_NUMERIC).
+ * The refinement still applies the exact operator K + lambda I.  shift_host
+ * (optional) receives delta.
+ */
+int hss_ulv_factor_shifted(hss_t H, double lambda, void *stream, hss_ulv_t *out, double *shift_host);
+
 void hss_ulv_destroy(hss_ulv_t F);
 
 /* Xout = (K_hss + lambda I)^{-1} B for n x nrhs FP64 B (permuted order).

@@ -254,10 +254,15 @@ class ULV:
     use), Cholesky pivots below the floor are raised to it so that the factor
     is always positive definite; `clamped` counts them."""
 
-    def __init__(self, H: HSS, lam: float, pivot_floor: float = 0.0):
+    def __init__(self, H: HSS, lam: float, pivot_floor: float = 0.0, shifted: bool = False):
         h_ = ctypes.c_void_p()
         self.clamped = 0
-        if pivot_floor > 0:
+        self.shift = 0.0
+        if shifted:
+            sh = ctypes.c_double()
+            check(load().hss_ulv_factor_shifted(H.h, float(lam), _stream(), ctypes.byref(h_), ctypes.byref(sh)))
+            self.shift = sh.value
+        elif pivot_floor > 0:
             cl = ctypes.c_int64()
             check(load().hss_ulv_factor_spd(H.h, float(lam), float(pivot_floor), _stream(), ctypes.byref(h_),
                                             ctypes.byref(cl)))
@@ -325,21 +330,43 @@ class FitResult:
 
 def fit(X, y, h, lam, leaf=128, opts: HssOptions = HssOptions(), seed=7, tol=1e-6, max_iter=200,
         mv_prec="f32", refine_solution=True, raise_on_fail=True):
-    """Algorithm 1 steps 0-2: cluster, compress, factor, solve, refine."""
+    """Algorithm 1 steps 0-2: cluster, compress, factor, solve, refine.
+
+    info["phases"] holds the wall time of each library call (seconds, the
+    stream synchronized in between)."""
+    import time
+
     _dev(X)
     y2 = _dev(y, torch.float64).reshape(y.shape[0], -1)
+    ph = {}
+
+    def mark(name, t0):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ph[name] = t1 - t0
+        return t1
+
+    t = time.perf_counter()
     perm, tree = cluster_2mn(X, leaf, seed)
+    t = mark("cluster", t)
     Xp = gather_rows(X, perm)
     yp = gather_rows(y2, perm)
+    t = mark("permute", t)
     H = HSS(tree, Xp, h, opts)
-    # as a preconditioner the factor only has to be positive definite
-    F = ULV(H, lam, pivot_floor=0.5 * lam if refine_solution else 0.0)
+    t = mark("compress", t)
+    # as a preconditioner the factor only has to be positive definite: shift if needed
+    F = ULV(H, lam, shifted=refine_solution)
+    t = mark("factor", t)
     ap = F.solve(yp)
-    info = {"hss": H.stats.as_dict(), "tree_stats": tree.stats.tolist(), "ulv_clamped": F.clamped}
+    t = mark("solve", t)
+    info = {"hss": H.stats.as_dict(), "tree_stats": tree.stats.tolist(), "ulv_shift": F.shift}
     if refine_solution:
         info["refine"] = refine(F, Xp, h, lam, yp, ap, tol=tol, max_iter=max_iter, mv_prec=mv_prec,
                                 raise_on_fail=raise_on_fail)
+        t = mark("refine", t)
     alpha = scatter_rows(ap, perm)
     if y.dim() == 1:
         alpha = alpha.reshape(-1)
+    mark("unpermute", t)
+    info["phases"] = ph
     return FitResult(alpha, ap, perm, Xp, tree, H, F, info)

@@ -45,7 +45,8 @@ void gather_rows(const void *src, int prec, int64_t n, int cols, const int64_t *
                  hipStream_t s);
 void compress(const krr_tree_s *t, const void *Xp, int xprec, int d, double h, const hss_opts &o, hipStream_t s,
               hss_s *H, hss_stats *st);
-int64_t ulv_factor(const hss_s *H, double lambda, double pivot_floor, hipStream_t s, hss_ulv_s *F);
+int64_t ulv_factor(const hss_s *H, double lambda, double pivot_floor, hipStream_t s, hss_ulv_s *F,
+                   double *worst_deficit = nullptr);
 void ulv_solve(const hss_ulv_s *F, const double *Bin, int nrhs, double *Xout, hipStream_t s);
 void hss_matvec_impl(const hss_s *H, const double *x, int nrhs, double *y, hipStream_t s);
 int refine(const hss_ulv_s *F, const void *Xp, int xprec, int d, double h, double lambda, const double *Y, int nrhs,
@@ -370,6 +371,39 @@ int hss_ulv_factor_spd(hss_t H, double lambda, double pivot_floor, void *stream,
         }
         *out = F;
         return KRR_OK;
+    });
+}
+
+int hss_ulv_factor_shifted(hss_t H, double lambda, void *stream, hss_ulv_t *out, double *shift_host) {
+    return guard([&] {
+        KRR_REQUIRE(out != nullptr, "hss_ulv_factor_shifted: NULL out");
+        *out = nullptr;
+        KRR_REQUIRE(H != nullptr, "hss_ulv_factor_shifted: NULL handle");
+        KRR_REQUIRE(lambda > 0.0, "hss_ulv_factor_shifted: lambda must be > 0");
+        require_device();
+        double delta = 0.0;
+        for (int attempt = 0; attempt < 8; ++attempt) {
+            auto *F = new hss_ulv_s();
+            double deficit = 0.0;
+            int64_t raised = 0;
+            try {
+                raised = ulv_factor(H, lambda + delta, 0.5 * lambda, S(stream), F, &deficit);
+            } catch (...) {
+                delete F;
+                throw;
+            }
+            if (verbose())
+                fprintf(stderr, "[krr] ulv shift %.4g: %lld pivots below lambda/2 (deficit %.4g)\n", delta,
+                        (long long)raised, deficit);
+            if (raised == 0) {
+                *out = F;
+                if (shift_host) *shift_host = delta;
+                return KRR_OK;
+            }
+            delete F;
+            delta += 1.5 * deficit + 0.25 * lambda;
+        }
+        fail(KRR_E_NUMERIC, "ULV: no positive definite shift found in 8 tries");
     });
 }
 

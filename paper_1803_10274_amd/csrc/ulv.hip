@@ -32,7 +32,7 @@ struct UlvDesc {
 };
 
 __global__ __launch_bounds__(BG_T) void k_ulv_factor(const UlvDesc *dsc, double pivot_floor, int32_t *flag,
-                                                     unsigned long long *clamped) {
+                                                     unsigned long long *clamped, unsigned long long *worst) {
     __shared__ double smem[2 * 16 * 65];
     __shared__ double red[BG_T / 64];
     const UlvDesc q = dsc[blockIdx.x];
@@ -152,8 +152,12 @@ __global__ __launch_bounds__(BG_T) void k_ulv_factor(const UlvDesc *dsc, double 
             __syncthreads();
             double theta = 0.0;
             for (int i = 0; i < BG_T / 64; ++i) theta = fmax(theta, red[i]);
+            if (tid == 0) {
+                atomicAdd(clamped, 1ull);
+                // largest deficit below the floor (non-negative, so its bits order like integers)
+                atomicMax(worst, (unsigned long long)__double_as_longlong(pivot_floor - djj));
+            }
             djj = fmax(fmax(pivot_floor, fabs(djj)), theta * theta / beta2);
-            if (tid == 0) atomicAdd(clamped, 1ull);
         }
         if (!(djj > 0.0)) {
             bad = true;
@@ -319,7 +323,8 @@ __global__ __launch_bounds__(BG_T) void k_ulv_bwd(const SolveDesc *dsc, double *
 
 }  // namespace
 
-int64_t ulv_factor(const hss_s *H, double lambda, double pivot_floor, hipStream_t s, hss_ulv_s *F) {
+int64_t ulv_factor(const hss_s *H, double lambda, double pivot_floor, hipStream_t s, hss_ulv_s *F,
+                   double *worst_deficit) {
     const int nn = (int)H->node.size();
     const int root = nn - 1;
     F->n = H->n;
@@ -360,9 +365,9 @@ int64_t ulv_factor(const hss_s *H, double lambda, double pivot_floor, hipStream_
         ns += (int64_t)k[i] * k[i];
     }
     DBuf Sb = dalloc<double>(std::max<int64_t>(ns, 1)), Rb = dalloc<double>(std::max<int64_t>(ns, 1));
-    DBuf flag = dalloc<int32_t>(1), nclamp = dalloc<unsigned long long>(1);
+    DBuf flag = dalloc<int32_t>(1), nclamp = dalloc<unsigned long long>(2);
     KRR_HIP(hipMemsetAsync(flag.get(), 0, sizeof(int32_t), s));
-    KRR_HIP(hipMemsetAsync(nclamp.get(), 0, sizeof(unsigned long long), s));
+    KRR_HIP(hipMemsetAsync(nclamp.get(), 0, 2 * sizeof(unsigned long long), s));
     for (const auto &lv : H->levels) {
         const int cnt = (int)lv.size();
         int64_t dsz = 0, usz = 0, tsz = 0;
@@ -413,17 +418,18 @@ int64_t ulv_factor(const hss_s *H, double lambda, double pivot_floor, hipStream_
         }
         DBuf dd = upload(dsc, s);
         k_ulv_factor<<<cnt, BG_T, 0, s>>>(dd.as<UlvDesc>(), pivot_floor, flag.as<int32_t>(),
-                                          nclamp.as<unsigned long long>());
+                                          nclamp.as<unsigned long long>(), nclamp.as<unsigned long long>() + 1);
         check_launch("k_ulv_factor");
         sync(s);
     }
     int32_t bad = 0;
-    unsigned long long cl = 0;
+    unsigned long long cl[2] = {0, 0};
     d2h(&bad, flag.as<int32_t>(), 1, s);
-    d2h(&cl, nclamp.as<unsigned long long>(), 1, s);
+    d2h(cl, nclamp.as<unsigned long long>(), 2, s);
     sync(s);
+    if (worst_deficit) *worst_deficit = cl[1] ? __builtin_bit_cast(double, (uint64_t)cl[1]) : 0.0;
     if (bad) fail(KRR_E_NUMERIC, "ULV: non-positive pivot in a Cholesky factor (K_hss + lambda I not SPD)");
-    return (int64_t)cl;
+    return (int64_t)cl[0];
 }
 
 void ulv_solve(const hss_ulv_s *F, const double *Bin, int nrhs, double *Xout, hipStream_t s) {
