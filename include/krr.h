@@ -261,12 +261,12 @@ int hss_ulv_factor_spd(hss_t H, double lambda, double pivot_floor, void *stream,
 
 /*
  * As hss_ulv_factor, for use as a preconditioner: factors K_hss + (lambda +
- * delta) I with the smallest delta found (0 first) for which every pivot is
- * at least lambda / 2.  After a failed pass, which is completed with raised
- * pivots so that the largest deficit d over all nodes is known, the next try
- * uses delta + 1.5 d + lambda / 4; at most 8 tries (else KRR_E_NUMERIC).
+ * delta) I for the first delta in 0, lambda, 4 lambda, 16 lambda, ... (12
+ * tries) at which every Cholesky pivot is at least lambda / 2 -- in exact
+ * arithmetic every pivot of K + lambda I is at least lambda, so smaller ones
+ * are compression error.  A try stops at the first level with such a pivot.
  * The refinement still applies the exact operator K + lambda I.  shift_host
- * (optional) receives delta.
+ * (optional) receives delta.  KRR_E_NUMERIC if no try succeeds.
  */
 int hss_ulv_factor_shifted(hss_t H, double lambda, void *stream, hss_ulv_t *out, double *shift_host);
 
@@ -288,14 +288,15 @@ typedef struct {
 
 /*
  * Preconditioned conjugate gradients on (K + lambda I) alpha = Y with the ULV
- * factor as preconditioner and kernel_matvec (prec mv_prec) for the products;
+ * factor as preconditioner (F = NULL: no preconditioner) and kernel_matvec
+ * (prec mv_prec) for the products;
  * the stopping test uses the recomputed true residual ||Y - (K + lambda I)
  * alpha|| / ||Y|| <= tol per column.  alpha: in = start, out = solution
  * (n x nrhs FP64, permuted order).  Returns KRR_E_NOT_CONVERGED if max_iter
  * is reached first (alpha then holds the last iterate).  Synchronizes
  * `stream` once per iteration.
  */
-int krr_refine(hss_ulv_t F, const void *Xp, int32_t xprec, int32_t d, double h,
+int krr_refine(hss_ulv_t F, const void *Xp, int64_t n, int32_t xprec, int32_t d, double h,
                double lambda, const double *Y, int32_t nrhs, double *alpha, double tol,
                int32_t max_iter, int32_t mv_prec, void *stream, krr_refine_stats *stats_host);
 

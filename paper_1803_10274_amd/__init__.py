@@ -287,13 +287,15 @@ class ULV:
             self.h = None
 
 
-def refine(F: ULV, Xp, h, lam, Y, alpha, tol=1e-6, max_iter=100, mv_prec="f32", raise_on_fail=True):
-    """PCG on (K + lam I) alpha = Y preconditioned by the ULV factor (alpha updated in place)."""
+def refine(F, Xp, h, lam, Y, alpha, tol=1e-6, max_iter=100, mv_prec="f32", raise_on_fail=True):
+    """PCG on (K + lam I) alpha = Y preconditioned by the ULV factor F (None:
+    plain CG); alpha is updated in place."""
     _dev(Xp)
     Y2 = _dev(Y, torch.float64).reshape(Y.shape[0], -1)
     a2 = _dev(alpha, torch.float64).reshape(alpha.shape[0], -1)
     st = RefineStats()
-    rc = load().krr_refine(F.h, _p(Xp), _xprec(Xp), Xp.shape[1], float(h), float(lam), _p(Y2), Y2.shape[1],
+    rc = load().krr_refine(F.h if F is not None else None, _p(Xp), Xp.shape[0], _xprec(Xp), Xp.shape[1], float(h),
+                           float(lam), _p(Y2), Y2.shape[1],
                            _p(a2), float(tol), int(max_iter), _prec(mv_prec), _stream(), ctypes.byref(st))
     if rc != 0 and (raise_on_fail or rc != _lib.KRR_E_NOT_CONVERGED):
         check(rc)

@@ -76,7 +76,7 @@ SIGNATURES = {
     "hss_ulv_factor_shifted": (ctypes.c_int, [_vp, _dbl, _vp, _P(_vp), _P(_dbl)]),
     "hss_ulv_destroy": (None, [_vp]),
     "hss_solve": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp]),
-    "krr_refine": (ctypes.c_int, [_vp, _vp, _i32, _i32, _dbl, _dbl, _vp, _i32, _vp, _dbl, _i32, _i32, _vp,
+    "krr_refine": (ctypes.c_int, [_vp, _vp, _i64, _i32, _i32, _dbl, _dbl, _vp, _i32, _vp, _dbl, _i32, _i32, _vp,
                                   _P(RefineStats)]),
     "krr_predict": (ctypes.c_int, [_vp, _i64, _vp, _i64, _i32, _i32, _dbl, _vp, _i32, _vp, _vp, _i32, _vp]),
     "krr_dot_columns": (ctypes.c_int, [_vp, _vp, _i64, _i32, _vp, _vp]),

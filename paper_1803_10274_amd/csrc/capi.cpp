@@ -46,11 +46,11 @@ void gather_rows(const void *src, int prec, int64_t n, int cols, const int64_t *
 void compress(const krr_tree_s *t, const void *Xp, int xprec, int d, double h, const hss_opts &o, hipStream_t s,
               hss_s *H, hss_stats *st);
 int64_t ulv_factor(const hss_s *H, double lambda, double pivot_floor, hipStream_t s, hss_ulv_s *F,
-                   double *worst_deficit = nullptr);
+                   double *worst_deficit = nullptr, bool stop_at_floor = false);
 void ulv_solve(const hss_ulv_s *F, const double *Bin, int nrhs, double *Xout, hipStream_t s);
 void hss_matvec_impl(const hss_s *H, const double *x, int nrhs, double *y, hipStream_t s);
-int refine(const hss_ulv_s *F, const void *Xp, int xprec, int d, double h, double lambda, const double *Y, int nrhs,
-           double *alpha, double tol, int max_iter, int mv_prec, hipStream_t s, krr_refine_stats *st);
+int refine(const hss_ulv_s *F, int64_t n, const void *Xp, int xprec, int d, double h, double lambda, const double *Y,
+           int nrhs, double *alpha, double tol, int max_iter, int mv_prec, hipStream_t s, krr_refine_stats *st);
 void predict_labels(const double *scores, int64_t m, int k, int32_t *labels, hipStream_t s);
 void dot_columns(const double *a, const double *b, int64_t n, int k, double *out, DBuf &scratch, hipStream_t s);
 
@@ -382,28 +382,26 @@ int hss_ulv_factor_shifted(hss_t H, double lambda, void *stream, hss_ulv_t *out,
         KRR_REQUIRE(lambda > 0.0, "hss_ulv_factor_shifted: lambda must be > 0");
         require_device();
         double delta = 0.0;
-        for (int attempt = 0; attempt < 8; ++attempt) {
+        for (int attempt = 0; attempt < 12; ++attempt) {
             auto *F = new hss_ulv_s();
-            double deficit = 0.0;
             int64_t raised = 0;
             try {
-                raised = ulv_factor(H, lambda + delta, 0.5 * lambda, S(stream), F, &deficit);
+                raised = ulv_factor(H, lambda + delta, 0.5 * lambda, S(stream), F, nullptr, true);
             } catch (...) {
                 delete F;
                 throw;
             }
             if (verbose())
-                fprintf(stderr, "[krr] ulv shift %.4g: %lld pivots below lambda/2 (deficit %.4g)\n", delta,
-                        (long long)raised, deficit);
+                fprintf(stderr, "[krr] ulv shift %.4g: %s\n", delta, raised ? "pivot below lambda/2, retry" : "ok");
             if (raised == 0) {
                 *out = F;
                 if (shift_host) *shift_host = delta;
                 return KRR_OK;
             }
             delete F;
-            delta += 1.5 * deficit + 0.25 * lambda;
+            delta = delta == 0.0 ? lambda : 4.0 * delta;
         }
-        fail(KRR_E_NUMERIC, "ULV: no positive definite shift found in 8 tries");
+        fail(KRR_E_NUMERIC, "ULV: no positive definite shift found in 12 tries");
     });
 }
 
@@ -419,17 +417,18 @@ int hss_solve(hss_ulv_t F, const double *B, int32_t nrhs, double *Xout, void *st
     });
 }
 
-int krr_refine(hss_ulv_t F, const void *Xp, int32_t xprec, int32_t d, double h, double lambda, const double *Y,
-               int32_t nrhs, double *alpha, double tol, int32_t max_iter, int32_t mv_prec, void *stream,
-               krr_refine_stats *stats_host) {
+int krr_refine(hss_ulv_t F, const void *Xp, int64_t n, int32_t xprec, int32_t d, double h, double lambda,
+               const double *Y, int32_t nrhs, double *alpha, double tol, int32_t max_iter, int32_t mv_prec,
+               void *stream, krr_refine_stats *stats_host) {
     return guard([&] {
-        KRR_REQUIRE(F && Xp && Y && alpha, "krr_refine: NULL argument");
+        KRR_REQUIRE(Xp && Y && alpha, "krr_refine: NULL argument");
+        KRR_REQUIRE(n >= 1 && (!F || F->n == n), "krr_refine: n must be >= 1 and match the factor");
         check_xprec(xprec);
         KRR_REQUIRE(nrhs >= 1 && nrhs <= 64, "krr_refine: nrhs must be in [1, 64]");
         KRR_REQUIRE(h > 0.0 && lambda >= 0.0 && tol > 0.0 && max_iter >= 0, "krr_refine: bad parameters");
         KRR_REQUIRE(mv_prec == KRR_F32 || mv_prec == KRR_F64, "krr_refine: mv_prec must be KRR_F32 or KRR_F64");
         require_device();
-        int rc = refine(F, Xp, xprec, d, h, lambda, Y, nrhs, alpha, tol, max_iter, mv_prec, S(stream), stats_host);
+        int rc = refine(F, n, Xp, xprec, d, h, lambda, Y, nrhs, alpha, tol, max_iter, mv_prec, S(stream), stats_host);
         if (rc == KRR_E_NOT_CONVERGED) g_last_error = "krr_refine: tolerance not reached within max_iter";
         return rc;
     });

@@ -86,13 +86,18 @@ void predict_labels(const double *scores, int64_t m, int k, int32_t *labels, hip
     check_launch("k_labels");
 }
 
-int refine(const hss_ulv_s *F, const void *Xp, int xprec, int d, double h, double lambda, const double *Y, int nrhs,
-           double *alpha, double tol, int max_iter, int mv_prec, hipStream_t s, krr_refine_stats *st) {
+int refine(const hss_ulv_s *F, int64_t n, const void *Xp, int xprec, int d, double h, double lambda, const double *Y,
+           int nrhs, double *alpha, double tol, int max_iter, int mv_prec, hipStream_t s, krr_refine_stats *st) {
     EventTimer timer(s);
-    const int64_t n = F->n;
     const int64_t len = n * nrhs;
     DBuf r = dalloc<double>(len), z = dalloc<double>(len), p = dalloc<double>(len), q = dalloc<double>(len);
     DBuf dout, scratch, coef;
+    auto precond = [&](const double *in, double *out) {
+        if (F)
+            ulv_solve(F, in, nrhs, out, s);
+        else
+            KRR_HIP(hipMemcpyAsync(out, in, sizeof(double) * len, hipMemcpyDeviceToDevice, s));
+    };
     int matvecs = 0;
     auto true_residual = [&]() {
         kernel_matvec_impl(Xp, n, Xp, n, d, xprec, h, alpha, nrhs, 0.0, q.as<double>(), mv_prec, s);
@@ -119,7 +124,7 @@ int refine(const hss_ulv_s *F, const void *Xp, int xprec, int d, double h, doubl
     bool converged = all_below(relres);
     while (!converged && it < max_iter) {
         // (re)start: z = M^{-1} r, p = z
-        ulv_solve(F, r.as<double>(), nrhs, z.as<double>(), s);
+        precond(r.as<double>(), z.as<double>());
         KRR_HIP(hipMemcpyAsync(p.get(), z.get(), sizeof(double) * len, hipMemcpyDeviceToDevice, s));
         std::vector<double> rz = dots(r.as<double>(), z.as<double>(), n, nrhs, dout, scratch, s);
         std::vector<bool> done(nrhs);
@@ -147,7 +152,7 @@ int refine(const hss_ulv_s *F, const void *Xp, int xprec, int d, double h, doubl
                 stop = stop && done[c];
             }
             if (stop) break;
-            ulv_solve(F, r.as<double>(), nrhs, z.as<double>(), s);
+            precond(r.as<double>(), z.as<double>());
             std::vector<double> rz2 = dots(r.as<double>(), z.as<double>(), n, nrhs, dout, scratch, s);
             std::vector<double> beta(nrhs);
             for (int c = 0; c < nrhs; ++c) {

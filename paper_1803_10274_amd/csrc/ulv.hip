@@ -324,7 +324,7 @@ __global__ __launch_bounds__(BG_T) void k_ulv_bwd(const SolveDesc *dsc, double *
 }  // namespace
 
 int64_t ulv_factor(const hss_s *H, double lambda, double pivot_floor, hipStream_t s, hss_ulv_s *F,
-                   double *worst_deficit) {
+                   double *worst_deficit, bool stop_at_floor) {
     const int nn = (int)H->node.size();
     const int root = nn - 1;
     F->n = H->n;
@@ -421,6 +421,12 @@ int64_t ulv_factor(const hss_s *H, double lambda, double pivot_floor, hipStream_
                                           nclamp.as<unsigned long long>(), nclamp.as<unsigned long long>() + 1);
         check_launch("k_ulv_factor");
         sync(s);
+        if (stop_at_floor) {
+            unsigned long long c0 = 0;
+            d2h(&c0, nclamp.as<unsigned long long>(), 1, s);
+            sync(s);
+            if (c0) return (int64_t)c0;  // a pivot fell below the floor: stop here
+        }
     }
     int32_t bad = 0;
     unsigned long long cl[2] = {0, 0};
