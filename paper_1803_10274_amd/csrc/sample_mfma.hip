@@ -122,18 +122,115 @@ __device__ __forceinline__ float entry(const float *xs, float nx, const float (*
     return __builtin_amdgcn_exp2f(t);
 }
 
+// A operand of one 32-point tile for the lane's row: 16 entries
+// (j = 16 kb + 8 g + q), split into hi (+ lo) FP16 / BF16 terms.
+template <int D, int MODE, int TERMS, bool MASK>
+__device__ __forceinline__ void make_a(typename Op<MODE>::V (&ahi)[2], typename Op<MODE>::V (&alo)[2],
+                                       const float *xs, float nx, const float (*ys)[D + 1], int pbase, int g,
+                                       int64_t jt, int32_t my_lb, int32_t my_le) {
+    typedef typename Op<MODE>::H H;
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int jj = 16 * kb + 8 * g + q;
+            float e = entry<D>(xs, nx, ys, pbase + jj);
+            if (MASK) {
+                const int64_t j = jt + jj;
+                e = (j >= my_lb && j < my_le) ? 0.0f : e;
+            }
+            const H hi = (H)e;
+            ahi[kb][q] = hi;
+            if (TERMS == 2) alo[kb][q] = (H)(e - (float)hi);
+        }
+}
+
+// MFMAs of the current tile (A = acur, B = the staged R tile) interleaved in
+// program order with the A operand of the next tile, so that each wave keeps
+// the matrix pipe and the vector ALUs busy at the same time.
+template <int D, int RB, int MODE, int TERMS, bool MASK>
+__device__ __forceinline__ void step_h(f16v (&acc)[RB], const typename Op<MODE>::V (&chi)[2],
+                                       const typename Op<MODE>::V (&clo)[2], typename Op<MODE>::V (&nhi)[2],
+                                       typename Op<MODE>::V (&nlo)[2], const char *rtile, const float *xs, float nx,
+                                       const float (*ys)[D + 1], int pbase, int g, int lane, int64_t jt,
+                                       int32_t my_lb, int32_t my_le) {
+    typedef typename Op<MODE>::H H;
+    typedef typename Op<MODE>::V V;
+    const V *rt = reinterpret_cast<const V *>(rtile);
+    constexpr int PER = 16 / RB;  // next-tile entries evaluated per column block
+#pragma unroll
+    for (int c = 0; c < RB; ++c) {
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb) {
+            const V b = rt[(c * 2 + kb) * 64 + lane];
+            acc[c] = Op<MODE>::mfma(chi[kb], b, acc[c]);
+            if (TERMS == 2) acc[c] = Op<MODE>::mfma(clo[kb], b, acc[c]);
+        }
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int ent = c * PER + u, kb = ent >> 3, q = ent & 7;
+            const int jj = 16 * kb + 8 * g + q;
+            float e = entry<D>(xs, nx, ys, pbase + jj);
+            if (MASK) {
+                const int64_t j = jt + jj;
+                e = (j >= my_lb && j < my_le) ? 0.0f : e;
+            }
+            const H hi = (H)e;
+            nhi[kb][q] = hi;
+            if (TERMS == 2) nlo[kb][q] = (H)(e - (float)hi);
+        }
+    }
+}
+
+// FP32 mode: 16 v_mfma_f32_32x32x2_f32 steps per column block; the lane's
+// entries are its row and points j = 2 s + g.
+template <int D, int RB, bool MASK>
+__device__ __forceinline__ void step_f(f16v (&acc)[RB], const float (&cur)[16], float (&nxt)[16], const char *rtile,
+                                       const float *xs, float nx, const float (*ys)[D + 1], int pbase, int g,
+                                       int lane, int64_t jt, int32_t my_lb, int32_t my_le) {
+    const float *rt = reinterpret_cast<const float *>(rtile);
+#pragma unroll
+    for (int sidx = 0; sidx < 16; ++sidx) {
+#pragma unroll
+        for (int c = 0; c < RB; ++c) {
+            const float b = rt[(c * 16 + sidx) * 64 + lane];
+            acc[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(cur[sidx], b, acc[c], 0, 0, 0);
+        }
+        const int jj = 2 * sidx + g;
+        float e = entry<D>(xs, nx, ys, pbase + jj);
+        if (MASK) {
+            const int64_t j = jt + jj;
+            e = (j >= my_lb && j < my_le) ? 0.0f : e;
+        }
+        nxt[sidx] = e;
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void make_f(float (&a)[16], const float *xs, float nx, const float (*ys)[D + 1], int pbase,
+                                       int g, int64_t jt, int32_t my_lb, int32_t my_le) {
+#pragma unroll
+    for (int sidx = 0; sidx < 16; ++sidx) {
+        const int jj = 2 * sidx + g;
+        float e = entry<D>(xs, nx, ys, pbase + jj);
+        const int64_t j = jt + jj;
+        a[sidx] = (j >= my_lb && j < my_le) ? 0.0f : e;
+    }
+}
+
 template <class T, int D, int RB, int MODE, int TERMS>
 __global__ __launch_bounds__(THREADS) void k_sample_mfma(const T *__restrict__ X, int64_t n, int d, float cs,
                                                          const void *__restrict__ Rsw_, int RBt, int cb0,
                                                          const int32_t *__restrict__ lb, const int32_t *__restrict__ le,
                                                          float *__restrict__ S, int ldS) {
-    typedef typename Op<MODE == M_F32 ? M_F16 : MODE>::H H;
-    typedef typename Op<MODE == M_F32 ? M_F16 : MODE>::V V;
-    constexpr int RTILE_H = RB * 2 * 64 * 8;       // halves per tile (FP16 / BF16)
-    constexpr int RTILE_F = RB * 16 * 64;          // floats per tile (FP32)
-    constexpr int RTILE_B = MODE == M_F32 ? RTILE_F * 4 : RTILE_H * 2;  // bytes per tile
-    __shared__ __attribute__((aligned(16))) char rbuf[2][RTILE_B];
+    constexpr int OPM = MODE == M_F32 ? M_F16 : MODE;
+    typedef typename Op<OPM>::V V;
+    constexpr int RTILE_H = RB * 2 * 64 * 8;
+    constexpr int RTILE_F = RB * 16 * 64;
+    constexpr int RTILE_B = MODE == M_F32 ? RTILE_F * 4 : RTILE_H * 2;
     constexpr int YS = YTile<D>::N;
+    constexpr int SUPER = YS / JT;  // tiles per Y super-tile
+    __shared__ __attribute__((aligned(16))) char rbuf[2][RTILE_B];
     __shared__ float ysh[2][YS][D + 1];
     __shared__ float anchor[D];
 
@@ -159,16 +256,21 @@ __global__ __launch_bounds__(THREADS) void k_sample_mfma(const T *__restrict__ X
     nx = -cs * nx + kE2;
     const int32_t my_lb = (row_ok && lb) ? lb[i] : 0;
     const int32_t my_le = (row_ok && lb) ? le[i] : 0;
+    // the wave's masked column range (tiles outside it take the unmasked path)
+    int32_t wlb = (row_ok && lb) ? my_lb : INT32_MAX, wle = (row_ok && lb) ? my_le : INT32_MIN;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        wlb = min(wlb, __shfl_xor(wlb, o, 64));
+        wle = max(wle, __shfl_xor(wle, o, 64));
+    }
 
     const int64_t tiles = (n + JT - 1) / JT;
     const char *Rg = static_cast<const char *>(Rsw_);
-    const int64_t tile_stride_b = (int64_t)RBt * (RTILE_B / RB);  // bytes per tile across all column blocks
+    const int64_t tile_stride_b = (int64_t)RBt * (RTILE_B / RB);
     const int64_t cb_off_b = (int64_t)cb0 * (RTILE_B / RB);
-    // R tile staging: RTILE_B bytes by THREADS threads in 16-byte pieces
     constexpr int PIECES = RTILE_B / 16;
     constexpr int PER_T = (PIECES + THREADS - 1) / THREADS;
     static_assert(PER_T <= 4, "R tile too large for the prefetch registers");
-    // prefetch registers (named, so they stay in VGPRs across the loop)
     uint4 pre0, pre1, pre2, pre3;
 #define KRR_PIECE_OK(u) ((u) < PER_T && (PIECES % THREADS == 0 || tid + (u) * THREADS < PIECES))
 #define KRR_LOAD_R(tile)                                                                          \
@@ -194,69 +296,77 @@ __global__ __launch_bounds__(THREADS) void k_sample_mfma(const T *__restrict__ X
 #pragma unroll
         for (int q = 0; q < 16; ++q) acc[c][q] = 0.0f;
 
-    // prologue: Y super-tile 0, R tile 0
+    // prologue: Y super-tile 0, R tile 0 in LDS, R tile 1 in flight
     stage_y<T, D>(X, n, d, 0, anchor, cs, ysh[0]);
     KRR_LOAD_R(0);
     KRR_STORE_R(0);
-    if (tiles > 1) KRR_LOAD_R(1);
+    KRR_LOAD_R(1);
     __syncthreads();
 
-    for (int64_t t = 0; t < tiles; ++t) {
-        const int yb = (int)((t * JT / YS) & 1);
-        const int pbase = (int)((t * JT) % YS);
-        const int64_t jt = t * JT;
-        const bool mask_tile = (jt < my_le) && (jt + JT > my_lb);
-        if constexpr (MODE == M_F32) {
-            const float *rt = reinterpret_cast<const float *>(rbuf[t & 1]);
+    // the padded random block has two zero tiles past the end, so every
+    // prefetch below is in bounds; tiles past n evaluate to exp2(-inf) = 0
+    // Tile t's masking (wave-uniform decision): its columns meet the wave's leaf range.
+#define KRR_TILE_MASKED(tt) ((int64_t)(tt) * JT < (int64_t)wle && (int64_t)(tt) * JT + JT > (int64_t)wlb)
+    if constexpr (MODE == M_F32) {
+        float a0[16], a1[16];
+        make_f<D>(a0, xs, nx, ysh[0], 0, g, 0, my_lb, my_le);
+        for (int64_t t = 0; t < tiles; t += 2) {
 #pragma unroll
-            for (int s = 0; s < 16; ++s) {
-                const int p = pbase + 2 * s + g;
-                float e = entry<D>(xs, nx, ysh[yb], p);
-                if (mask_tile) {
-                    int64_t j = jt + 2 * s + g;
-                    if (j >= my_lb && j < my_le) e = 0.0f;
+            for (int half = 0; half < 2; ++half) {
+                const int64_t tc = t + half;
+                if (half == 1 && tc >= tiles) break;
+                if (tc % SUPER == 0) {
+                    const int64_t sup = tc / SUPER + 1;
+                    stage_y<T, D>(X, n, d, sup * YS, anchor, cs, ysh[sup & 1]);
                 }
-#pragma unroll
-                for (int c = 0; c < RB; ++c) {
-                    float b = rt[(c * 16 + s) * 64 + lane];
-                    acc[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(e, b, acc[c], 0, 0, 0);
-                }
+                const int64_t tn = tc + 1;
+                const float(*ysn)[D + 1] = ysh[(tn / SUPER) & 1];
+                const int pbn = (int)((tn * JT) % YS);
+                float(&cur)[16] = half == 0 ? a0 : a1;
+                float(&nxt)[16] = half == 0 ? a1 : a0;
+                if (KRR_TILE_MASKED(tn))
+                    step_f<D, RB, true>(acc, cur, nxt, rbuf[tc & 1], xs, nx, ysn, pbn, g, lane, tn * JT, my_lb, my_le);
+                else
+                    step_f<D, RB, false>(acc, cur, nxt, rbuf[tc & 1], xs, nx, ysn, pbn, g, lane, tn * JT, my_lb,
+                                         my_le);
+                KRR_STORE_R((tc + 1) & 1);
+                KRR_LOAD_R(tc + 2);
+                __syncthreads();
             }
-        } else {
-            V ahi[2], alo[2];
-#pragma unroll
-            for (int kb = 0; kb < 2; ++kb)
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const int jj = 16 * kb + 8 * g + q;
-                    float e = entry<D>(xs, nx, ysh[yb], pbase + jj);
-                    if (mask_tile) {
-                        int64_t j = jt + jj;
-                        if (j >= my_lb && j < my_le) e = 0.0f;
-                    }
-                    H hi = (H)e;
-                    ahi[kb][q] = hi;
-                    if (TERMS == 2) alo[kb][q] = (H)(e - (float)hi);
-                }
-            const V *rt = reinterpret_cast<const V *>(rbuf[t & 1]);
-#pragma unroll
-            for (int c = 0; c < RB; ++c)
-#pragma unroll
-                for (int kb = 0; kb < 2; ++kb) {
-                    V b = rt[(c * 2 + kb) * 64 + lane];
-                    acc[c] = Op<MODE>::mfma(ahi[kb], b, acc[c]);
-                    if (TERMS == 2) acc[c] = Op<MODE>::mfma(alo[kb], b, acc[c]);
-                }
         }
-        // next R tile into the other buffer; next Y super-tile when this one ends.
-        // Both targets were last read one iteration (R) or a whole super-tile
-        // (Y) ago, so a single barrier per tile orders writes and reads.
-        if (t + 1 < tiles) {
-            KRR_STORE_R((t + 1) & 1);
-            if (t + 2 < tiles) KRR_LOAD_R(t + 2);
-            if (((t + 1) * JT) % YS == 0) stage_y<T, D>(X, n, d, (t + 1) * JT, anchor, cs, ysh[yb ^ 1]);
+    } else {
+        V h0[2], l0[2], h1[2], l1[2];
+        if (KRR_TILE_MASKED(0))
+            make_a<D, MODE, TERMS, true>(h0, l0, xs, nx, ysh[0], 0, g, 0, my_lb, my_le);
+        else
+            make_a<D, MODE, TERMS, false>(h0, l0, xs, nx, ysh[0], 0, g, 0, my_lb, my_le);
+        for (int64_t t = 0; t < tiles; t += 2) {
+#pragma unroll
+            for (int half = 0; half < 2; ++half) {
+                const int64_t tc = t + half;
+                if (half == 1 && tc >= tiles) break;
+                if (tc % SUPER == 0) {
+                    const int64_t sup = tc / SUPER + 1;
+                    stage_y<T, D>(X, n, d, sup * YS, anchor, cs, ysh[sup & 1]);
+                }
+                const int64_t tn = tc + 1;
+                const float(*ysn)[D + 1] = ysh[(tn / SUPER) & 1];
+                const int pbn = (int)((tn * JT) % YS);
+                V(&ch)[2] = half == 0 ? h0 : h1;
+                V(&cl)[2] = half == 0 ? l0 : l1;
+                V(&nh)[2] = half == 0 ? h1 : h0;
+                V(&nl)[2] = half == 0 ? l1 : l0;
+                if (KRR_TILE_MASKED(tn))
+                    step_h<D, RB, MODE, TERMS, true>(acc, ch, cl, nh, nl, rbuf[tc & 1], xs, nx, ysn, pbn, g, lane,
+                                                     tn * JT, my_lb, my_le);
+                else
+                    step_h<D, RB, MODE, TERMS, false>(acc, ch, cl, nh, nl, rbuf[tc & 1], xs, nx, ysn, pbn, g, lane,
+                                                      tn * JT, my_lb, my_le);
+                KRR_STORE_R((tc + 1) & 1);
+                KRR_LOAD_R(tc + 2);
+                __syncthreads();
+            }
         }
-        __syncthreads();
     }
     // write out: lane holds column 32 c + lane % 32 of rows 8 (q / 4) + 4 g + q % 4
 #pragma unroll
@@ -267,22 +377,35 @@ __global__ __launch_bounds__(THREADS) void k_sample_mfma(const T *__restrict__ X
             const int64_t row = i0 + 32 * w + m;
             if (row < n) S[row * ldS + 32 * (cb0 + c) + (lane & 31)] = acc[c][q] * kInvScale;
         }
+#undef KRR_TILE_MASKED
 #undef KRR_LOAD_R
 #undef KRR_STORE_R
 #undef KRR_PIECE_OK
 }
 
+// Column blocks per pass: 8 (256 columns) where the accumulators fit in
+// registers next to the operands, fewer for wide points and the FP32 mode.
+template <int D, int MODE> struct RbMax {
+    static constexpr int V = MODE == M_F32 ? (D <= 8 ? 8 : (D <= 32 ? 4 : 2)) : (D <= 32 ? 8 : 4);
+};
+
 template <class T, int D, int MODE, int TERMS>
 void launch_passes(const T *X, int64_t n, int d, float cs, const void *Rsw, int r, const int32_t *lb,
                    const int32_t *le, float *S, hipStream_t s) {
+    constexpr int RBM = RbMax<D, MODE>::V;
     const int RBt = r / 32;
     int cb0 = 0;
     while (cb0 < RBt) {
         const int left = RBt - cb0;
         dim3 grid(ceil_div(n, ROWS));
-        if (left >= 8) {
-            k_sample_mfma<T, D, 8, MODE, TERMS><<<grid, THREADS, 0, s>>>(X, n, d, cs, Rsw, RBt, cb0, lb, le, S, r);
+        if (RBM >= 8 && left >= 8) {
+            k_sample_mfma<T, D, (RBM >= 8 ? 8 : RBM), MODE, TERMS><<<grid, THREADS, 0, s>>>(X, n, d, cs, Rsw, RBt, cb0,
+                                                                                        lb, le, S, r);
             cb0 += 8;
+        } else if (RBM >= 4 && left >= 4) {
+            k_sample_mfma<T, D, (RBM >= 4 ? 4 : RBM), MODE, TERMS><<<grid, THREADS, 0, s>>>(X, n, d, cs, Rsw, RBt, cb0,
+                                                                                        lb, le, S, r);
+            cb0 += 4;
         } else if (left >= 2) {
             k_sample_mfma<T, D, 2, MODE, TERMS><<<grid, THREADS, 0, s>>>(X, n, d, cs, Rsw, RBt, cb0, lb, le, S, r);
             cb0 += 2;
@@ -329,7 +452,8 @@ bool sample_mfma_supported(int d, int prec) { return prec != KRR_F64 && d <= kSa
 // R: n x r FP32 (exact in the operand precision); S: n x r FP32.
 void sample_mfma(const void *X, int64_t n, int d, int xprec, double h, const float *R, int r, const int32_t *lb,
                  const int32_t *le, float *S, int prec, int split, hipStream_t s) {
-    const int64_t tiles = (n + JT - 1) / JT;
+    // two zero tiles past the end keep the kernel's prefetches in bounds
+    const int64_t tiles = (n + JT - 1) / JT + 2;
     const float cs = (float)(1.4426950408889634 / (2.0 * h * h));
     DBuf Rsw;
     if (prec == KRR_F32) {
