@@ -37,8 +37,10 @@ template <int D> struct YTile { static constexpr int N = D <= 16 ? 256 : (D <= 3
 
 // ---------------------------------------------------------------- swizzle
 
-// Rsw layout for FP16 / BF16: [tile][cb][kb][lane][q] with point
-// j = 32 tile + 16 kb + 8 (lane / 32) + q and column 32 cb + lane % 32.
+// Rsw layout for FP16 / BF16: [tile][cb][kb][lane][q] with column
+// 32 cb + lane % 32 and point j = 32 tile + 16 kb + p(q, g), g = lane / 32,
+// p = 4 g + q for q < 4 and 8 + 4 g + (q - 4) above: the order in which the
+// distance product leaves the kernel entries in each lane's registers.
 template <class H>
 __global__ void k_swizzle_h(const float *__restrict__ R, int64_t n, int r, int64_t tiles, H *__restrict__ Rsw) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -52,7 +54,8 @@ __global__ void k_swizzle_h(const float *__restrict__ R, int64_t n, int r, int64
     int64_t tile = u / RBt;
     int col = 32 * cb + lane % 32;
     for (int q = 0; q < 8; ++q) {
-        int64_t j = 32 * tile + 16 * kb + 8 * (lane / 32) + q;
+        const int gg = lane / 32;
+        int64_t j = 32 * tile + 16 * kb + (q < 4 ? 4 * gg + q : 8 + 4 * gg + (q - 4));
         float v = j < n ? R[j * r + col] : 0.0f;
         Rsw[t * 8 + q] = (H)v;
     }
@@ -120,6 +123,64 @@ __device__ __forceinline__ float entry(const float *xs, float nx, const float (*
 #pragma unroll
     for (int k = 0; k < D; ++k) t = fmaf(xs[k], ys[p][k], t);
     return __builtin_amdgcn_exp2f(t);
+}
+
+// Augmented points for the distance product: row p of ya holds
+// (y'_1 .. y'_D, 1, -c |y'_p|^2) (zero past the end of the data, where the
+// last entry is -inf so that the kernel value is exactly 0).
+template <class T, int D, int YS>
+__device__ __forceinline__ void stage_ya(const T *__restrict__ X, int64_t n, int d, int64_t j0, const float *anchor,
+                                         float cs, float (*ya)[D + 3]) {
+    for (int p = threadIdx.x; p < YS; p += THREADS) {
+        int64_t j = j0 + p;
+        float nrm = 0.0f;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            float v = (j < n && k < d) ? (float)X[j * d + k] - anchor[k] : 0.0f;
+            ya[p][k] = v;
+            nrm = fmaf(v, v, nrm);
+        }
+        ya[p][D] = 1.0f;
+        ya[p][D + 1] = j < n ? -cs * nrm : -INFINITY;
+    }
+}
+
+// Exponents of one 32 x 32 (point j, row i) block on the matrix cores:
+// t[r] = x~_i . y~_j for j = 8 (r / 4) + 4 g + r % 4 (the C layout of
+// v_mfma_f32_32x32x2_f32 with points as rows and the wave's rows as columns).
+// xa[s] holds the lane's own x~ entry 2 s + g.
+template <int D>
+__device__ __forceinline__ f16v dist_mfma(const float *xa, const float (*ya)[D + 3], int pbase, int lane) {
+    constexpr int KS = (D + 2 + 1) / 2;
+    const int g = lane >> 5;
+    f16v t = {};
+#pragma unroll
+    for (int sidx = 0; sidx < KS; ++sidx) {
+        const int k = 2 * sidx + g;
+        const float a = (k < D + 2) ? ya[pbase + (lane & 31)][k] : 0.0f;
+        t = __builtin_amdgcn_mfma_f32_32x32x2f32(a, xa[sidx], t, 0, 0, 0);
+    }
+    return t;
+}
+
+// Kernel entries from the exponents (masking entries of the row's own leaf),
+// split into the A operands of the two 16-point blocks: block kb takes
+// registers 8 kb .. 8 kb + 7, i.e. points 16 kb + (4 g + q, 8 + 4 g + q).
+template <int MODE, int TERMS, bool MASK>
+__device__ __forceinline__ void exp_split(typename Op<MODE>::V (&ahi)[2], typename Op<MODE>::V (&alo)[2],
+                                          const f16v &t, int g, int64_t jt, int32_t my_lb, int32_t my_le) {
+    typedef typename Op<MODE>::H H;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        float e = __builtin_amdgcn_exp2f(t[r]);
+        if (MASK) {
+            const int64_t j = jt + 8 * (r >> 2) + 4 * g + (r & 3);
+            e = (j >= my_lb && j < my_le) ? 0.0f : e;
+        }
+        const H hi = (H)e;
+        ahi[r >> 3][r & 7] = hi;
+        if (TERMS == 2) alo[r >> 3][r & 7] = (H)(e - (float)hi);
+    }
 }
 
 // A operand of one 32-point tile for the lane's row: 16 entries
@@ -231,8 +292,13 @@ __global__ __launch_bounds__(THREADS) void k_sample_mfma(const T *__restrict__ X
     constexpr int YS = YTile<D>::N;
     constexpr int SUPER = YS / JT;  // tiles per Y super-tile
     __shared__ __attribute__((aligned(16))) char rbuf[2][RTILE_B];
-    __shared__ float ysh[2][YS][D + 1];
+    // plain Y tiles (FP32 mode) or augmented ones (split modes)
+    constexpr int YW = MODE == M_F32 ? D + 1 : D + 3;
+    __shared__ float yab[2][YS][YW];
     __shared__ float anchor[D];
+    float(*ysh0)[D + 1] = reinterpret_cast<float(*)[D + 1]>(&yab[0][0][0]);
+    float(*ysh1)[D + 1] = reinterpret_cast<float(*)[D + 1]>(&yab[1][0][0]);
+    float(*const ysh[2])[D + 1] = {ysh0, ysh1};
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 5;
     const int64_t i0 = (int64_t)blockIdx.x * ROWS;
@@ -296,8 +362,8 @@ __global__ __launch_bounds__(THREADS) void k_sample_mfma(const T *__restrict__ X
 #pragma unroll
         for (int q = 0; q < 16; ++q) acc[c][q] = 0.0f;
 
-    // prologue: Y super-tile 0, R tile 0 in LDS, R tile 1 in flight
-    stage_y<T, D>(X, n, d, 0, anchor, cs, ysh[0]);
+    // prologue: R tile 0 in LDS, R tile 1 in flight (Y tiles per mode below)
+    if constexpr (MODE == M_F32) stage_y<T, D>(X, n, d, 0, anchor, cs, ysh[0]);
     KRR_LOAD_R(0);
     KRR_STORE_R(0);
     KRR_LOAD_R(1);
@@ -335,11 +401,27 @@ __global__ __launch_bounds__(THREADS) void k_sample_mfma(const T *__restrict__ X
             }
         }
     } else {
+        // x~ = (2 c x', -c |x'|^2 (+ 14 for FP16), 1): entries 2 s + g of the lane's own row
+        constexpr int KS = (D + 2 + 1) / 2;
+        float xa[KS];
+#pragma unroll
+        for (int sidx = 0; sidx < KS; ++sidx) {
+            const int k = 2 * sidx + g;
+            xa[sidx] = k < D ? xs[k] : (k == D ? nx : (k == D + 1 ? 1.0f : 0.0f));
+        }
+        // augmented Y tiles replace the plain ones in this mode
+        float(*ya0)[D + 3] = reinterpret_cast<float(*)[D + 3]>(&yab[0][0][0]);
+        float(*ya1)[D + 3] = reinterpret_cast<float(*)[D + 3]>(&yab[1][0][0]);
+        stage_ya<T, D, YS>(X, n, d, 0, anchor, cs, ya0);
+        __syncthreads();
         V h0[2], l0[2], h1[2], l1[2];
-        if (KRR_TILE_MASKED(0))
-            make_a<D, MODE, TERMS, true>(h0, l0, xs, nx, ysh[0], 0, g, 0, my_lb, my_le);
-        else
-            make_a<D, MODE, TERMS, false>(h0, l0, xs, nx, ysh[0], 0, g, 0, my_lb, my_le);
+        {
+            f16v t0 = dist_mfma<D>(xa, ya0, 0, lane);
+            if (KRR_TILE_MASKED(0))
+                exp_split<MODE, TERMS, true>(h0, l0, t0, g, 0, my_lb, my_le);
+            else
+                exp_split<MODE, TERMS, false>(h0, l0, t0, g, 0, my_lb, my_le);
+        }
         for (int64_t t = 0; t < tiles; t += 2) {
 #pragma unroll
             for (int half = 0; half < 2; ++half) {
@@ -347,21 +429,33 @@ __global__ __launch_bounds__(THREADS) void k_sample_mfma(const T *__restrict__ X
                 if (half == 1 && tc >= tiles) break;
                 if (tc % SUPER == 0) {
                     const int64_t sup = tc / SUPER + 1;
-                    stage_y<T, D>(X, n, d, sup * YS, anchor, cs, ysh[sup & 1]);
+                    stage_ya<T, D, YS>(X, n, d, sup * YS, anchor, cs, (sup & 1) ? ya1 : ya0);
                 }
                 const int64_t tn = tc + 1;
-                const float(*ysn)[D + 1] = ysh[(tn / SUPER) & 1];
+                const float(*yan)[D + 3] = ((tn / SUPER) & 1) ? ya1 : ya0;
                 const int pbn = (int)((tn * JT) % YS);
                 V(&ch)[2] = half == 0 ? h0 : h1;
                 V(&cl)[2] = half == 0 ? l0 : l1;
                 V(&nh)[2] = half == 0 ? h1 : h0;
                 V(&nl)[2] = half == 0 ? l1 : l0;
+                // exponents of the next tile first (matrix pipe), then this
+                // tile's products, then the next tile's entries (vector ALUs)
+                const f16v tnext = dist_mfma<D>(xa, yan, pbn, lane);
+                {
+                    const V *rt = reinterpret_cast<const V *>(rbuf[tc & 1]);
+#pragma unroll
+                    for (int c = 0; c < RB; ++c)
+#pragma unroll
+                        for (int kb = 0; kb < 2; ++kb) {
+                            const V b = rt[(c * 2 + kb) * 64 + lane];
+                            acc[c] = Op<MODE>::mfma(ch[kb], b, acc[c]);
+                            if (TERMS == 2) acc[c] = Op<MODE>::mfma(cl[kb], b, acc[c]);
+                        }
+                }
                 if (KRR_TILE_MASKED(tn))
-                    step_h<D, RB, MODE, TERMS, true>(acc, ch, cl, nh, nl, rbuf[tc & 1], xs, nx, ysn, pbn, g, lane,
-                                                     tn * JT, my_lb, my_le);
+                    exp_split<MODE, TERMS, true>(nh, nl, tnext, g, tn * JT, my_lb, my_le);
                 else
-                    step_h<D, RB, MODE, TERMS, false>(acc, ch, cl, nh, nl, rbuf[tc & 1], xs, nx, ysn, pbn, g, lane,
-                                                      tn * JT, my_lb, my_le);
+                    exp_split<MODE, TERMS, false>(nh, nl, tnext, g, tn * JT, my_lb, my_le);
                 KRR_STORE_R((tc + 1) & 1);
                 KRR_LOAD_R(tc + 2);
                 __syncthreads();
