@@ -404,11 +404,9 @@ __global__ __launch_bounds__(THREADS) void k_sample_mfma(const T *__restrict__ X
         // x~ = (2 c x', -c |x'|^2 (+ 14 for FP16), 1): entries 2 s + g of the lane's own row
         constexpr int KS = (D + 2 + 1) / 2;
         float xa[KS];
+        auto xt = [&](int k) { return k < D ? xs[k] : (k == D ? nx : (k == D + 1 ? 1.0f : 0.0f)); };
 #pragma unroll
-        for (int sidx = 0; sidx < KS; ++sidx) {
-            const int k = 2 * sidx + g;
-            xa[sidx] = k < D ? xs[k] : (k == D ? nx : (k == D + 1 ? 1.0f : 0.0f));
-        }
+        for (int sidx = 0; sidx < KS; ++sidx) xa[sidx] = g ? xt(2 * sidx + 1) : xt(2 * sidx);
         // augmented Y tiles replace the plain ones in this mode
         float(*ya0)[D + 3] = reinterpret_cast<float(*)[D + 3]>(&yab[0][0][0]);
         float(*ya1)[D + 3] = reinterpret_cast<float(*)[D + 3]>(&yab[1][0][0]);

@@ -1,0 +1,75 @@
+"""Differentiation on the GPU: the fused kernel-product backward through
+torch.autograd against the oracle's dense FP64 gradients, and the validation
+loss gradient in (log h, log lambda) (adjoint through the ULV-preconditioned
+refinement) against the oracle's analytic gradient and against central
+finite differences of the GPU objective itself."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synthdata as sd
+from oracle import grad as og
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def test_kernel_matvec_autograd(gpu_lib):
+    from paper_1803_10274_amd.autograd import KernelMatvec
+    X = sd.points(300, 18, seed=31, scale=0.4, dtype=np.float64)
+    Y = sd.points(250, 18, seed=32, scale=0.4, dtype=np.float64)
+    W = sd.vectors(250, 2, seed=33)
+    G = sd.vectors(300, 2, seed=34)
+    h = 1.3
+    Xt = _t(X).requires_grad_(True)
+    Yt = _t(Y).requires_grad_(True)
+    Wt = _t(W).requires_grad_(True)
+    ht = torch.tensor(h, dtype=torch.float64, device="cuda", requires_grad=True)
+    out = KernelMatvec.apply(Xt, Yt, Wt, ht, "f64")
+    (out * _t(G)).sum().backward()
+    dX, dY, dW, dh = og.matvec_bwd(X, Y, W, G, h)
+    for got, ref in ((Xt.grad, dX), (Yt.grad, dY), (Wt.grad, dW)):
+        assert np.linalg.norm(got.cpu().numpy() - ref) <= 1e-10 * np.linalg.norm(ref)
+    assert abs(ht.grad.item() - dh) <= 1e-10 * abs(dh)
+
+
+@pytest.mark.parametrize("n,mv", [(2048, 512), (8192, 1024)])
+def test_validation_gradient_against_oracle(gpu_lib, n, mv):
+    from paper_1803_10274_amd.autograd import validation_loss
+    p = sd.c5_eight_gaussians(n=n, m=mv)
+    lh = torch.tensor(math.log(p.h), dtype=torch.float64, device="cuda", requires_grad=True)
+    ll = torch.tensor(math.log(p.lam), dtype=torch.float64, device="cuda", requires_grad=True)
+    L, st = validation_loss(lh, ll, _t(p.X), _t(p.y), _t(p.Xt), _t(p.yt), tol=1e-7)
+    L.backward()
+    L_ref, gh_ref, gl_ref = og.val_loss_grad(p.X.astype(np.float64), p.y, p.Xt.astype(np.float64), p.yt,
+                                             p.h, p.lam)
+    assert abs(L.item() - L_ref) <= 1e-6 * abs(L_ref)
+    assert abs(lh.grad.item() - gh_ref) <= 1e-3 * abs(gh_ref)
+    assert abs(ll.grad.item() - gl_ref) <= 1e-3 * abs(gl_ref)
+
+
+def test_validation_gradient_finite_differences(gpu_lib):
+    # central differences of the GPU objective (tightly refined, so smooth in h)
+    from paper_1803_10274_amd.autograd import validation_loss
+    p = sd.c5_eight_gaussians(n=16384, m=2048)
+    X, y, Xv, yv = _t(p.X), _t(p.y), _t(p.Xt), _t(p.yt)
+    lh = torch.tensor(math.log(p.h), dtype=torch.float64, device="cuda", requires_grad=True)
+    ll = torch.tensor(math.log(p.lam), dtype=torch.float64, device="cuda", requires_grad=True)
+    L, st = validation_loss(lh, ll, X, y, Xv, yv, tol=1e-10, prec="f64")
+    L.backward()
+    s = 1e-3
+
+    def f(a, b):
+        v, _ = validation_loss(torch.tensor(a, dtype=torch.float64, device="cuda"),
+                               torch.tensor(b, dtype=torch.float64, device="cuda"), X, y, Xv, yv, state=st)
+        return v.item()
+
+    fh = (f(math.log(p.h) + s, math.log(p.lam)) - f(math.log(p.h) - s, math.log(p.lam))) / (2 * s)
+    fl = (f(math.log(p.h), math.log(p.lam) + s) - f(math.log(p.h), math.log(p.lam) - s)) / (2 * s)
+    assert abs(lh.grad.item() - fh) <= 2e-3 * abs(fh) + 1e-7
+    assert abs(ll.grad.item() - fl) <= 2e-3 * abs(fl) + 1e-7
