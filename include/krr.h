@@ -93,7 +93,9 @@ int krr_cluster_2mn(const void *X, int32_t xprec, int64_t n, int32_t d,
 
 /* Builds a tree handle from a host node table (n_nodes rows of begin, end,
  * left, right, parent; postorder, children before parents, root last; leaves
- * have left = right = -1).  Lets any ordering (or a test) drive compression. */
+ * have left = right = -1).  Lets any ordering (or a test) drive compression.
+ * A forest (the batched form) lists its trees one after the other, each
+ * ending at its root (parent = -1), the roots covering [0, n) in order. */
 int krr_tree_from_host(const int64_t *nodes_host, int64_t n_nodes, krr_tree *out);
 
 /* Number of points and of nodes of a tree. */
@@ -105,6 +107,11 @@ int krr_tree_size(krr_tree t, int64_t *n_host, int64_t *n_nodes_host);
 int krr_tree_export(krr_tree t, int64_t *nodes_host, int64_t *stats_host);
 
 void krr_tree_destroy(krr_tree t);
+
+/* Roots of the trees of a forest (count_host: their number; roots_host, if
+ * not NULL, receives that many node indices in order).  A single tree has
+ * one root, its last node. */
+int krr_tree_roots(krr_tree t, int64_t *roots_host, int32_t *count_host);
 
 /* dst[i, :] = src[perm[i], :]  (rows of `cols` elements of dtype prec). */
 int krr_gather_rows(const void *src, int32_t prec, int64_t n, int32_t cols,
@@ -311,6 +318,74 @@ int krr_refine(hss_ulv_t F, const void *Xp, int64_t n, int32_t xprec, int32_t d,
 int krr_predict(const void *Xt, int64_t m, const void *Xp, int64_t n, int32_t d,
                 int32_t xprec, double h, const double *alpha, int32_t nrhs,
                 double *scores, int32_t *labels, int32_t prec, void *stream);
+
+/* ---------------------------------------------- batched form (A1-A8) */
+
+/*
+ * A batch is np independent KRR problems of equal dimension d stored one
+ * after the other: problem k owns the points [offsets[k], offsets[k+1]) of a
+ * single n x d array (offsets: host, np + 1 int64, offsets[0] = 0, every
+ * problem non-empty, n = offsets[np]) and has its own kernel width h[k] and
+ * ridge parameter lambda[k] (host arrays of np doubles).  The kernel matrix of
+ * a batch is block diagonal; every batched call runs all problems together
+ * (one launch per phase and tree level over every problem's nodes).  Problems
+ * of different d form separate batches.
+ */
+
+/* 2MN clustering of every problem (the steps of krr_cluster_2mn, each
+ * problem's tree started from its own range; each tree's result is identical
+ * to clustering that problem alone, shifted by its offset).  perm (out, n
+ * int64) keeps each problem within its range; out: a forest whose k-th tree
+ * is problem k.  Synchronizes once per level and Lloyd iteration of the
+ * whole forest. */
+int krr_cluster_2mn_batched(const void *X, int32_t xprec, const int64_t *offsets, int32_t np,
+                            int32_t d, const krr_cluster_opts *opts, void *stream, int64_t *perm,
+                            krr_tree *out);
+
+/* HSS compression of every problem of a forest (as hss_compress; h: host,
+ * one width per tree).  One sampling launch covers every problem (each row
+ * sums over its own problem's columns only); sample width, growth and rank
+ * rule are shared.  Each tree's generators equal those of compressing that
+ * problem alone with the same final sample width and random block rows. */
+int hss_compress_batched(krr_tree t, const void *Xp, int32_t xprec, int32_t d, const double *h,
+                         const hss_opts *opts, void *stream, hss_t *out, hss_stats *stats_host);
+
+/* Number of problems (trees) of a compressed batch. */
+int hss_num_problems(hss_t H, int32_t *np_host);
+
+/* ULV factorization of every problem of a compressed batch with its own
+ * lambda[k] (host, np doubles).  shifted = 0: as hss_ulv_factor.  shifted = 1:
+ * as hss_ulv_factor_shifted with the shift lambda[k] * s for one common s in
+ * 0, 1, 4, 16, ... (shift_mult_host, optional, receives s).  Solve with
+ * hss_solve (the factor is block diagonal over the problems). */
+int hss_ulv_factor_batched(hss_t H, const double *lambda, int32_t shifted, void *stream,
+                           hss_ulv_t *out, double *shift_mult_host);
+
+/* kernel_sample on every problem of a batch in one launch: row i of
+ * problem k gets sum over problem k's columns j outside [leaf_begin[i],
+ * leaf_end[i]) of K(x_i, x_j; h[k]) R[j, :] (arguments as kernel_sample;
+ * leaf ranges in global positions). */
+int kernel_sample_batched(const void *X, int32_t xprec, const int64_t *offsets, int32_t np,
+                          int32_t d, const double *h, const float *R, int32_t r,
+                          const int32_t *leaf_begin, const int32_t *leaf_end, void *S,
+                          int32_t prec, int32_t split_terms, void *stream);
+
+/* Out = blockdiag_k K(X_k, X_k; h[k]) W (kernel_matvec on each problem's
+ * own points; W, Out n x nrhs FP64; prec KRR_F32 or KRR_F64). */
+int kernel_matvec_batched(const void *X, int32_t xprec, const int64_t *offsets, int32_t np,
+                          int32_t d, const double *h, const double *W, int32_t nrhs, double *Out,
+                          int32_t prec, void *stream);
+
+/* krr_refine on every problem at once (one conjugate-gradient recurrence
+ * per problem and right-hand side, sharing each launch).  F: a factor of the
+ * same batch or NULL.  stats_host->relres holds, per right-hand side, the
+ * largest over the problems; relres_host (optional, host np x nrhs) each
+ * problem's own.  Converged when every problem meets tol. */
+int krr_refine_batched(hss_ulv_t F, const void *Xp, int32_t xprec, const int64_t *offsets,
+                       int32_t np, int32_t d, const double *h, const double *lambda,
+                       const double *Y, int32_t nrhs, double *alpha, double tol,
+                       int32_t max_iter, int32_t mv_prec, void *stream,
+                       krr_refine_stats *stats_host, double *relres_host);
 
 /* ------------------------------------------------ small vector kernels */
 

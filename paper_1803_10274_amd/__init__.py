@@ -71,6 +71,11 @@ class Tree:
         self.stats = np.zeros(4, dtype=np.int64)
         check(load().krr_tree_export(handle, self.nodes.ctypes.data_as(ctypes.c_void_p),
                                      self.stats.ctypes.data_as(ctypes.c_void_p)))
+        cnt = ctypes.c_int32()
+        check(load().krr_tree_roots(handle, None, ctypes.byref(cnt)))
+        self.roots = np.empty(cnt.value, dtype=np.int64)
+        check(load().krr_tree_roots(handle, self.roots.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                    ctypes.byref(cnt)))
 
     def __del__(self):
         if getattr(self, "h", None) and _lib._lib is not None:
@@ -372,3 +377,190 @@ def fit(X, y, h, lam, leaf=128, opts: HssOptions = HssOptions(), seed=7, tol=1e-
     mark("unpermute", t)
     info["phases"] = ph
     return FitResult(alpha, ap, perm, Xp, tree, H, F, info)
+
+
+# ------------------------------------------------------------ batched form
+
+def _i64p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+
+def _dblp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def offsets_of(sizes) -> np.ndarray:
+    """Problem offsets (np + 1 int64, from 0) of consecutive problems."""
+    off = np.zeros(len(sizes) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(np.asarray(sizes, dtype=np.int64))
+    return off
+
+
+def cluster_2mn_batched(X: torch.Tensor, offsets, leaf: int, seed: int, max_iter: int = 100):
+    """2MN ordering of every problem of a batch; returns (perm, forest Tree)."""
+    _dev(X)
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    n, d = X.shape
+    if off[-1] != n:
+        raise ValueError("offsets must end at the number of points")
+    perm = torch.empty(n, dtype=torch.int64, device=X.device)
+    opts = ClusterOpts(int(leaf), int(max_iter), int(seed) & (2**64 - 1))
+    h = ctypes.c_void_p()
+    check(load().krr_cluster_2mn_batched(_p(X), _xprec(X), _i64p(off), len(off) - 1, d, ctypes.byref(opts),
+                                         _stream(), _p(perm), ctypes.byref(h)))
+    return perm, Tree(h)
+
+
+class BatchedHSS(HSS):
+    """HSS generators of every problem of a forest (problem k: tree k, width h[k])."""
+
+    def __init__(self, tree: Tree, Xp: torch.Tensor, h, opts: HssOptions = HssOptions()):
+        _dev(Xp)
+        hs = np.ascontiguousarray(h, dtype=np.float64)
+        if hs.shape != (len(tree.roots),):
+            raise ValueError("one kernel width per tree is required")
+        self.tree = tree
+        self.stats = HssStats()
+        h_ = ctypes.c_void_p()
+        check(load().hss_compress_batched(tree.h, _p(Xp), _xprec(Xp), Xp.shape[1], _dblp(hs), ctypes.byref(opts.c()),
+                                          _stream(), ctypes.byref(h_), ctypes.byref(self.stats)))
+        self.h = h_
+        self.hprob = hs
+
+
+class BatchedULV(ULV):
+    """ULV factor of every problem of a BatchedHSS with its own lambda."""
+
+    def __init__(self, H: BatchedHSS, lam, shifted: bool = False):
+        lams = np.ascontiguousarray(lam, dtype=np.float64)
+        h_ = ctypes.c_void_p()
+        mult = ctypes.c_double()
+        check(load().hss_ulv_factor_batched(H.h, _dblp(lams), int(bool(shifted)), _stream(), ctypes.byref(h_),
+                                            ctypes.byref(mult)))
+        self.h = h_
+        self.hss = H
+        self.lam = lams
+        self.clamped = 0
+        self.shift_mult = mult.value
+        self.shift = mult.value
+
+
+def kernel_matvec_batched(X, offsets, h, W, prec="f32"):
+    """Block-diagonal product: problem k's rows get K(X_k, X_k; h[k]) W_k."""
+    _dev(X)
+    W2 = _dev(W, torch.float64).reshape(W.shape[0], -1)
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    hs = np.ascontiguousarray(h, dtype=np.float64)
+    out = torch.empty_like(W2)
+    check(load().kernel_matvec_batched(_p(X), _xprec(X), _i64p(off), len(off) - 1, X.shape[1], _dblp(hs), _p(W2),
+                                       W2.shape[1], _p(out), _prec(prec), _stream()))
+    return out.reshape(W.shape)
+
+
+def kernel_sample_batched(X, offsets, h, R, leaf_begin=None, leaf_end=None, prec="f32", split_terms=2):
+    """Off-diagonal sample of every problem of a batch (one launch)."""
+    _dev(X)
+    _dev(R, torch.float32)
+    n, r = R.shape
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    hs = np.ascontiguousarray(h, dtype=np.float64)
+    p = _prec(prec)
+    S = torch.empty((n, r), dtype=torch.float64 if p == KRR_F64 else torch.float32, device=X.device)
+    check(load().kernel_sample_batched(_p(X), _xprec(X), _i64p(off), len(off) - 1, X.shape[1], _dblp(hs), _p(R), r,
+                                       _p(leaf_begin) if leaf_begin is not None else None,
+                                       _p(leaf_end) if leaf_end is not None else None, _p(S), p, int(split_terms),
+                                       _stream()))
+    return S
+
+
+def refine_batched(F, Xp, offsets, h, lam, Y, alpha, tol=1e-6, max_iter=100, mv_prec="f32", raise_on_fail=True):
+    """PCG on every problem at once (alpha updated in place); returns stats
+    with each problem's final relative residuals."""
+    _dev(Xp)
+    Y2 = _dev(Y, torch.float64).reshape(Y.shape[0], -1)
+    a2 = _dev(alpha, torch.float64).reshape(alpha.shape[0], -1)
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    hs = np.ascontiguousarray(h, dtype=np.float64)
+    ls = np.ascontiguousarray(lam, dtype=np.float64)
+    npb = len(off) - 1
+    rel = np.zeros(npb * Y2.shape[1], dtype=np.float64)
+    st = RefineStats()
+    rc = load().krr_refine_batched(F.h if F is not None else None, _p(Xp), _xprec(Xp), _i64p(off), npb, Xp.shape[1],
+                                   _dblp(hs), _dblp(ls), _p(Y2), Y2.shape[1], _p(a2), float(tol), int(max_iter),
+                                   _prec(mv_prec), _stream(), ctypes.byref(st), _dblp(rel))
+    if rc != 0 and (raise_on_fail or rc != _lib.KRR_E_NOT_CONVERGED):
+        check(rc)
+    return {"iterations": st.iterations, "matvecs": st.matvecs, "relres": rel.reshape(npb, Y2.shape[1]),
+            "t_ms": st.t_ms, "converged": rc == 0}
+
+
+@dataclass
+class BatchedFitResult:
+    alphas: list               # per problem, original order within the problem
+    groups: list               # per group of equal d: dict with perm, Xp, tree, hss, ulv, offsets, members
+    info: dict = field(default_factory=dict)
+
+
+def fit_batched(problems, leaf=128, opts: HssOptions = HssOptions(), seed=7, tol=1e-6, max_iter=200,
+                mv_prec="f32", refine_solution=True, raise_on_fail=True):
+    """Algorithm 1 steps 0-2 for many independent problems at once.
+
+    problems: sequence of (X_k, y_k, h_k, lam_k) with X_k an n_k x d_k GPU
+    tensor.  Problems of equal d (and dtype) form one batch: they are stored
+    one after the other and every library call covers all of them (one launch
+    per phase and tree level).  Returns each problem's alpha in its own order."""
+    import time
+
+    ph = {}
+
+    def mark(name, t0):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ph[name] = ph.get(name, 0.0) + (t1 - t0)
+        return t1
+
+    groups = {}
+    for idx, (X, y, h, lam) in enumerate(problems):
+        _dev(X)
+        groups.setdefault((X.shape[1], X.dtype), []).append(idx)
+    alphas = [None] * len(problems)
+    out_groups = []
+    info = {"refine": [], "hss": [], "ulv_shift_mult": []}
+    for (d, _), members in groups.items():
+        t = time.perf_counter()
+        Xs = [problems[i][0] for i in members]
+        ys = [_dev(problems[i][1], torch.float64).reshape(problems[i][1].shape[0], -1) for i in members]
+        if len({y.shape[1] for y in ys}) != 1:
+            raise ValueError("problems of one batch need the same number of right-hand sides")
+        hs = np.array([problems[i][2] for i in members], dtype=np.float64)
+        ls = np.array([problems[i][3] for i in members], dtype=np.float64)
+        off = offsets_of([x.shape[0] for x in Xs])
+        X = torch.cat(Xs, 0).contiguous()
+        Y = torch.cat(ys, 0).contiguous()
+        t = mark("concat", t)
+        perm, tree = cluster_2mn_batched(X, off, leaf, seed)
+        t = mark("cluster", t)
+        Xp = gather_rows(X, perm)
+        Yp = gather_rows(Y, perm)
+        t = mark("permute", t)
+        H = BatchedHSS(tree, Xp, hs, opts)
+        t = mark("compress", t)
+        F = BatchedULV(H, ls, shifted=refine_solution)
+        t = mark("factor", t)
+        ap = F.solve(Yp)
+        t = mark("solve", t)
+        info["hss"].append(H.stats.as_dict())
+        info["ulv_shift_mult"].append(F.shift_mult)
+        if refine_solution:
+            info["refine"].append(refine_batched(F, Xp, off, hs, ls, Yp, ap, tol=tol, max_iter=max_iter,
+                                                 mv_prec=mv_prec, raise_on_fail=raise_on_fail))
+            t = mark("refine", t)
+        alpha = scatter_rows(ap, perm)
+        for j, i in enumerate(members):
+            a = alpha[off[j]:off[j + 1]]
+            alphas[i] = a.reshape(-1) if problems[i][1].dim() == 1 else a
+        mark("unpermute", t)
+        out_groups.append({"members": members, "offsets": off, "perm": perm, "Xp": Xp, "tree": tree, "hss": H,
+                           "ulv": F, "h": hs, "lam": ls, "alpha_perm": ap})
+    info["phases"] = ph
+    return BatchedFitResult(alphas, out_groups, info)

@@ -80,6 +80,20 @@ SIGNATURES = {
                                   _P(RefineStats)]),
     "krr_predict": (ctypes.c_int, [_vp, _i64, _vp, _i64, _i32, _i32, _dbl, _vp, _i32, _vp, _vp, _i32, _vp]),
     "krr_dot_columns": (ctypes.c_int, [_vp, _vp, _i64, _i32, _vp, _vp]),
+    # batched form
+    "krr_cluster_2mn_batched": (ctypes.c_int, [_vp, _i32, _P(_i64), _i32, _i32, _P(ClusterOpts), _vp, _vp,
+                                               _P(_vp)]),
+    "krr_tree_roots": (ctypes.c_int, [_vp, _P(_i64), _P(_i32)]),
+    "hss_compress_batched": (ctypes.c_int, [_vp, _vp, _i32, _i32, _P(_dbl), _P(HssOpts), _vp, _P(_vp),
+                                            _P(HssStats)]),
+    "hss_num_problems": (ctypes.c_int, [_vp, _P(_i32)]),
+    "hss_ulv_factor_batched": (ctypes.c_int, [_vp, _P(_dbl), _i32, _vp, _P(_vp), _P(_dbl)]),
+    "kernel_sample_batched": (ctypes.c_int, [_vp, _i32, _P(_i64), _i32, _i32, _P(_dbl), _vp, _i32, _vp, _vp, _vp,
+                                             _i32, _i32, _vp]),
+    "kernel_matvec_batched": (ctypes.c_int, [_vp, _i32, _P(_i64), _i32, _i32, _P(_dbl), _vp, _i32, _vp, _i32,
+                                             _vp]),
+    "krr_refine_batched": (ctypes.c_int, [_vp, _vp, _i32, _P(_i64), _i32, _i32, _P(_dbl), _P(_dbl), _vp, _i32,
+                                          _vp, _dbl, _i32, _i32, _vp, _P(RefineStats), _P(_dbl)]),
 }
 
 _lib = None

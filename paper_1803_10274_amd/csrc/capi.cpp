@@ -31,28 +31,6 @@ void fail(int code, const char *fmt, ...) {
     throw Error(code, buf);
 }
 
-void cluster_2mn(const void *X, int32_t xprec, int64_t n, int32_t d, const krr_cluster_opts &o, hipStream_t s,
-                 int64_t *perm, krr_tree_s &tree);
-void kernel_matvec_impl(const void *X, int64_t m, const void *Y, int64_t n, int d, int xprec, double h,
-                        const double *W, int nrhs, double beta, double *Out, int prec, hipStream_t s);
-void kernel_matvec_bwd_impl(const void *X, int64_t m, const void *Y, int64_t n, int d, int xprec, double h,
-                            const double *W, const double *G, int nrhs, double *dX, double *dY, double *dW,
-                            double *dh, int prec, hipStream_t s);
-void sample_product(const void *X, int64_t n, int d, int xprec, double h, const float *R, int r, const int32_t *lb,
-                    const int32_t *le, void *S, int prec, int split, hipStream_t s);
-void random_block(uint64_t seed, int64_t n, int r, int c0, float *R, int ldr, hipStream_t s);
-void gather_rows(const void *src, int prec, int64_t n, int cols, const int64_t *perm, void *dst, bool scatter,
-                 hipStream_t s);
-void compress(const krr_tree_s *t, const void *Xp, int xprec, int d, double h, const hss_opts &o, hipStream_t s,
-              hss_s *H, hss_stats *st);
-int64_t ulv_factor(const hss_s *H, double lambda, double pivot_floor, hipStream_t s, hss_ulv_s *F,
-                   double *worst_deficit = nullptr, bool stop_at_floor = false);
-void ulv_solve(const hss_ulv_s *F, const double *Bin, int nrhs, double *Xout, hipStream_t s);
-void hss_matvec_impl(const hss_s *H, const double *x, int nrhs, double *y, hipStream_t s);
-int refine(const hss_ulv_s *F, int64_t n, const void *Xp, int xprec, int d, double h, double lambda, const double *Y,
-           int nrhs, double *alpha, double tol, int max_iter, int mv_prec, hipStream_t s, krr_refine_stats *st);
-void predict_labels(const double *scores, int64_t m, int k, int32_t *labels, hipStream_t s);
-void dot_columns(const double *a, const double *b, int64_t n, int k, double *out, DBuf &scratch, hipStream_t s);
 
 namespace {
 
@@ -89,6 +67,64 @@ void check_xprec(int32_t xprec) {
     KRR_REQUIRE(xprec == KRR_F32 || xprec == KRR_F64, "point dtype must be KRR_F32 or KRR_F64 (got %d)", xprec);
 }
 
+void check_hss_opts(const hss_opts &o, const char *who) {
+    KRR_REQUIRE(o.rtol >= 0.0 && o.atol >= 0.0, "%s: tolerances must be >= 0", who);
+    KRR_REQUIRE(o.r0 >= 32 && o.r0 % 32 == 0, "%s: r0 must be a positive multiple of 32", who);
+    KRR_REQUIRE(o.dr >= 32 && o.dr % 32 == 0, "%s: dr must be a positive multiple of 32", who);
+    KRR_REQUIRE(o.r_max >= o.r0, "%s: r_max < r0", who);
+    KRR_REQUIRE(o.oversample >= 0 && o.oversample < o.r0, "%s: bad oversample", who);
+    KRR_REQUIRE(o.prec >= KRR_F64 && o.prec <= KRR_BF16_SPLIT, "%s: bad prec", who);
+    KRR_REQUIRE(o.split_terms == 1 || o.split_terms == 2, "%s: split_terms must be 1 or 2", who);
+    KRR_REQUIRE(o.cap_policy == 0 || o.cap_policy == 1, "%s: cap_policy must be 0 or 1", who);
+}
+
+// Problem offsets (host, np + 1 entries from 0, non-decreasing) with
+// per-problem widths and, where given, ridge parameters.
+Batch make_batch(const int64_t *offsets, int32_t np, const double *h, const double *lam, const char *who) {
+    KRR_REQUIRE(np >= 1 && offsets && h, "%s: need np >= 1, offsets and h", who);
+    KRR_REQUIRE(offsets[0] == 0, "%s: offsets[0] must be 0", who);
+    Batch b;
+    b.pbeg.assign(offsets, offsets + np + 1);
+    b.h.assign(h, h + np);
+    if (lam) b.lam.assign(lam, lam + np);
+    for (int k = 0; k < np; ++k) {
+        KRR_REQUIRE(offsets[k + 1] > offsets[k], "%s: problem %d is empty", who, k);
+        KRR_REQUIRE(h[k] > 0.0 && h[k] == h[k], "%s: h[%d] must be positive", who, k);
+        if (lam) KRR_REQUIRE(lam[k] >= 0.0, "%s: lambda[%d] must be >= 0", who, k);
+    }
+    KRR_REQUIRE(offsets[np] <= INT32_MAX, "%s: total size must fit in int32", who);
+    return b;
+}
+
+// Factor with lambda_k (1 + s) for s = 0, 1, 4, 16, ... until no pivot of
+// any problem falls below lambda_k / 2 (see hss_ulv_factor_shifted).
+hss_ulv_s *factor_shifted(const hss_s *H, const std::vector<double> &lam, hipStream_t s, double *mult) {
+    const int np = (int)lam.size();
+    std::vector<double> floor(np), lam_s(np);
+    for (int k = 0; k < np; ++k) floor[k] = 0.5 * lam[k];
+    double sh = 0.0;
+    for (int attempt = 0; attempt < 12; ++attempt) {
+        for (int k = 0; k < np; ++k) lam_s[k] = lam[k] * (1.0 + sh);
+        auto *F = new hss_ulv_s();
+        int64_t raised = 0;
+        try {
+            raised = ulv_factor(H, lam_s, floor, s, F, nullptr, true);
+        } catch (...) {
+            delete F;
+            throw;
+        }
+        if (verbose())
+            fprintf(stderr, "[krr] ulv shift %.4g lambda: %s\n", sh, raised ? "pivot below lambda/2, retry" : "ok");
+        if (raised == 0) {
+            *mult = sh;
+            return F;
+        }
+        delete F;
+        sh = sh == 0.0 ? 1.0 : 4.0 * sh;
+    }
+    fail(KRR_E_NUMERIC, "ULV: no positive definite shift found in 12 tries");
+}
+
 }  // namespace
 }  // namespace krr
 
@@ -120,7 +156,7 @@ int krr_cluster_2mn(const void *X, int32_t xprec, int64_t n, int32_t d, const kr
         require_device();
         auto *t = new krr_tree_s();
         try {
-            cluster_2mn(X, xprec, n, d, *opts, S(stream), perm, *t);
+            cluster_2mn(X, xprec, n, d, std::vector<int64_t>{0, n}, *opts, S(stream), perm, *t);
         } catch (...) {
             delete t;
             throw;
@@ -136,7 +172,10 @@ int krr_tree_from_host(const int64_t *nodes_host, int64_t n_nodes, krr_tree *out
         *out = nullptr;
         auto *t = new krr_tree_s();
         t->nodes.assign(nodes_host, nodes_host + 5 * n_nodes);
-        t->n = t->e(n_nodes - 1) - t->b(n_nodes - 1);
+        // every node without a parent is the root of one tree of a forest
+        for (int64_t i = 0; i < n_nodes; ++i)
+            if (t->parent(i) < 0) t->roots.push_back(i);
+        t->n = t->roots.empty() ? 0 : t->e(t->roots.back());
         try {
             validate_tree(t);
         } catch (...) {
@@ -258,19 +297,12 @@ int hss_compress(krr_tree t, const void *Xp, int32_t xprec, int32_t d, double h,
         check_xprec(xprec);
         KRR_REQUIRE(d >= 1 && h > 0.0, "hss_compress: need d >= 1 and h > 0");
         const hss_opts &o = *opts;
-        KRR_REQUIRE(o.rtol >= 0.0 && o.atol >= 0.0, "hss_compress: tolerances must be >= 0");
-        KRR_REQUIRE(o.r0 >= 32 && o.r0 % 32 == 0, "hss_compress: r0 must be a positive multiple of 32");
-        KRR_REQUIRE(o.dr >= 32 && o.dr % 32 == 0, "hss_compress: dr must be a positive multiple of 32");
-        KRR_REQUIRE(o.r_max >= o.r0, "hss_compress: r_max < r0");
-        KRR_REQUIRE(o.oversample >= 0 && o.oversample < o.r0, "hss_compress: bad oversample");
-        KRR_REQUIRE(o.prec >= KRR_F64 && o.prec <= KRR_BF16_SPLIT, "hss_compress: bad prec");
-        KRR_REQUIRE(o.split_terms == 1 || o.split_terms == 2, "hss_compress: split_terms must be 1 or 2");
-        KRR_REQUIRE(o.cap_policy == 0 || o.cap_policy == 1, "hss_compress: cap_policy must be 0 or 1");
+        check_hss_opts(o, "hss_compress");
         validate_tree(t);
         require_device();
         auto *H = new hss_s();
         try {
-            compress(t, Xp, xprec, d, h, o, S(stream), H, stats_host);
+            compress(t, Xp, xprec, d, std::vector<double>(t->roots.size(), h), o, S(stream), H, stats_host);
         } catch (...) {
             delete H;
             throw;
@@ -341,7 +373,8 @@ int hss_ulv_factor(hss_t H, double lambda, void *stream, hss_ulv_t *out) {
         require_device();
         auto *F = new hss_ulv_s();
         try {
-            ulv_factor(H, lambda, 0.0, S(stream), F);
+            const size_t np = H->hprob.size();
+            ulv_factor(H, std::vector<double>(np, lambda), std::vector<double>(np, 0.0), S(stream), F);
         } catch (...) {
             delete F;
             throw;
@@ -362,7 +395,9 @@ int hss_ulv_factor_spd(hss_t H, double lambda, double pivot_floor, void *stream,
         require_device();
         auto *F = new hss_ulv_s();
         try {
-            int64_t clamped = ulv_factor(H, lambda, pivot_floor, S(stream), F);
+            const size_t np = H->hprob.size();
+            int64_t clamped =
+                ulv_factor(H, std::vector<double>(np, lambda), std::vector<double>(np, pivot_floor), S(stream), F);
             if (clamped_host) *clamped_host = clamped;
             if (verbose()) fprintf(stderr, "[krr] ulv factor: %lld pivots raised to %g\n", (long long)clamped, pivot_floor);
         } catch (...) {
@@ -381,27 +416,10 @@ int hss_ulv_factor_shifted(hss_t H, double lambda, void *stream, hss_ulv_t *out,
         KRR_REQUIRE(H != nullptr, "hss_ulv_factor_shifted: NULL handle");
         KRR_REQUIRE(lambda > 0.0, "hss_ulv_factor_shifted: lambda must be > 0");
         require_device();
-        double delta = 0.0;
-        for (int attempt = 0; attempt < 12; ++attempt) {
-            auto *F = new hss_ulv_s();
-            int64_t raised = 0;
-            try {
-                raised = ulv_factor(H, lambda + delta, 0.5 * lambda, S(stream), F, nullptr, true);
-            } catch (...) {
-                delete F;
-                throw;
-            }
-            if (verbose())
-                fprintf(stderr, "[krr] ulv shift %.4g: %s\n", delta, raised ? "pivot below lambda/2, retry" : "ok");
-            if (raised == 0) {
-                *out = F;
-                if (shift_host) *shift_host = delta;
-                return KRR_OK;
-            }
-            delete F;
-            delta = delta == 0.0 ? lambda : 4.0 * delta;
-        }
-        fail(KRR_E_NUMERIC, "ULV: no positive definite shift found in 12 tries");
+        double mult = 0.0;
+        *out = factor_shifted(H, std::vector<double>(H->hprob.size(), lambda), S(stream), &mult);
+        if (shift_host) *shift_host = mult * lambda;
+        return KRR_OK;
     });
 }
 
@@ -457,6 +475,167 @@ int krr_dot_columns(const double *a, const double *b, int64_t n, int32_t k, doub
         dot_columns(a, b, n, k, out, scratch, S(stream));
         sync(S(stream));
         return KRR_OK;
+    });
+}
+
+// ------------------------------------------------------------ batched form
+
+int krr_cluster_2mn_batched(const void *X, int32_t xprec, const int64_t *offsets, int32_t np, int32_t d,
+                            const krr_cluster_opts *opts, void *stream, int64_t *perm, krr_tree *out) {
+    return guard([&] {
+        KRR_REQUIRE(out != nullptr && opts != nullptr, "krr_cluster_2mn_batched: NULL opts or out");
+        *out = nullptr;
+        check_xprec(xprec);
+        KRR_REQUIRE(np >= 1 && offsets != nullptr && d >= 1, "krr_cluster_2mn_batched: need np >= 1, offsets, d >= 1");
+        KRR_REQUIRE(offsets[0] == 0, "krr_cluster_2mn_batched: offsets[0] must be 0");
+        for (int k = 0; k < np; ++k)
+            KRR_REQUIRE(offsets[k + 1] > offsets[k], "krr_cluster_2mn_batched: problem %d is empty", k);
+        const int64_t n = offsets[np];
+        KRR_REQUIRE(n <= INT32_MAX, "krr_cluster_2mn_batched: total size must fit in int32");
+        KRR_REQUIRE(X != nullptr && perm != nullptr, "krr_cluster_2mn_batched: NULL X or perm");
+        KRR_REQUIRE(opts->leaf_size >= 1 && opts->max_iter >= 1,
+                    "krr_cluster_2mn_batched: leaf_size and max_iter must be >= 1");
+        require_device();
+        auto *t = new krr_tree_s();
+        try {
+            cluster_2mn(X, xprec, n, d, std::vector<int64_t>(offsets, offsets + np + 1), *opts, S(stream), perm, *t);
+        } catch (...) {
+            delete t;
+            throw;
+        }
+        *out = t;
+        return KRR_OK;
+    });
+}
+
+int krr_tree_roots(krr_tree t, int64_t *roots_host, int32_t *count_host) {
+    return guard([&] {
+        KRR_REQUIRE(t != nullptr, "krr_tree_roots: NULL tree");
+        if (count_host) *count_host = (int32_t)t->roots.size();
+        if (roots_host) std::memcpy(roots_host, t->roots.data(), sizeof(int64_t) * t->roots.size());
+        return KRR_OK;
+    });
+}
+
+int hss_compress_batched(krr_tree t, const void *Xp, int32_t xprec, int32_t d, const double *h, const hss_opts *opts,
+                         void *stream, hss_t *out, hss_stats *stats_host) {
+    return guard([&] {
+        KRR_REQUIRE(out != nullptr, "hss_compress_batched: NULL out");
+        *out = nullptr;
+        KRR_REQUIRE(t != nullptr && opts != nullptr && Xp != nullptr && h != nullptr,
+                    "hss_compress_batched: NULL argument");
+        check_xprec(xprec);
+        KRR_REQUIRE(d >= 1, "hss_compress_batched: need d >= 1");
+        check_hss_opts(*opts, "hss_compress_batched");
+        validate_tree(t);
+        const size_t np = t->roots.size();
+        for (size_t k = 0; k < np; ++k) KRR_REQUIRE(h[k] > 0.0, "hss_compress_batched: h[%zu] must be > 0", k);
+        require_device();
+        auto *H = new hss_s();
+        try {
+            compress(t, Xp, xprec, d, std::vector<double>(h, h + np), *opts, S(stream), H, stats_host);
+        } catch (...) {
+            delete H;
+            throw;
+        }
+        *out = H;
+        return KRR_OK;
+    });
+}
+
+int hss_num_problems(hss_t H, int32_t *np_host) {
+    return guard([&] {
+        KRR_REQUIRE(H != nullptr && np_host != nullptr, "hss_num_problems: NULL argument");
+        *np_host = (int32_t)H->hprob.size();
+        return KRR_OK;
+    });
+}
+
+int hss_ulv_factor_batched(hss_t H, const double *lambda, int32_t shifted, void *stream, hss_ulv_t *out,
+                           double *shift_mult_host) {
+    return guard([&] {
+        KRR_REQUIRE(out != nullptr, "hss_ulv_factor_batched: NULL out");
+        *out = nullptr;
+        KRR_REQUIRE(H != nullptr && lambda != nullptr, "hss_ulv_factor_batched: NULL argument");
+        const size_t np = H->hprob.size();
+        std::vector<double> lam(lambda, lambda + np);
+        for (size_t k = 0; k < np; ++k)
+            KRR_REQUIRE(shifted ? lam[k] > 0.0 : lam[k] >= 0.0, "hss_ulv_factor_batched: bad lambda[%zu]", k);
+        require_device();
+        if (shifted) {
+            double mult = 0.0;
+            *out = factor_shifted(H, lam, S(stream), &mult);
+            if (shift_mult_host) *shift_mult_host = mult;
+            return KRR_OK;
+        }
+        auto *F = new hss_ulv_s();
+        try {
+            ulv_factor(H, lam, std::vector<double>(np, 0.0), S(stream), F);
+        } catch (...) {
+            delete F;
+            throw;
+        }
+        if (shift_mult_host) *shift_mult_host = 0.0;
+        *out = F;
+        return KRR_OK;
+    });
+}
+
+int kernel_sample_batched(const void *X, int32_t xprec, const int64_t *offsets, int32_t np, int32_t d,
+                          const double *h, const float *R, int32_t r, const int32_t *leaf_begin,
+                          const int32_t *leaf_end, void *Sout, int32_t prec, int32_t split_terms, void *stream) {
+    return guard([&] {
+        check_xprec(xprec);
+        Batch b = make_batch(offsets, np, h, nullptr, "kernel_sample_batched");
+        KRR_REQUIRE(d >= 1, "kernel_sample_batched: need d >= 1");
+        KRR_REQUIRE(r >= 32 && r % 32 == 0, "kernel_sample_batched: r must be a positive multiple of 32");
+        KRR_REQUIRE(prec >= KRR_F64 && prec <= KRR_BF16_SPLIT, "kernel_sample_batched: bad prec %d", prec);
+        KRR_REQUIRE(split_terms == 1 || split_terms == 2, "kernel_sample_batched: split_terms must be 1 or 2");
+        KRR_REQUIRE((leaf_begin == nullptr) == (leaf_end == nullptr),
+                    "kernel_sample_batched: give both leaf arrays or none");
+        KRR_REQUIRE(X && R && Sout, "kernel_sample_batched: NULL pointer");
+        require_device();
+        sample_product(X, b.pbeg.back(), d, xprec, b.h[0], R, r, leaf_begin, leaf_end, Sout, prec, split_terms,
+                       S(stream), &b);
+        return KRR_OK;
+    });
+}
+
+int kernel_matvec_batched(const void *X, int32_t xprec, const int64_t *offsets, int32_t np, int32_t d,
+                          const double *h, const double *W, int32_t nrhs, double *Out, int32_t prec, void *stream) {
+    return guard([&] {
+        check_xprec(xprec);
+        Batch b = make_batch(offsets, np, h, nullptr, "kernel_matvec_batched");
+        KRR_REQUIRE(d >= 1 && nrhs >= 1 && nrhs <= 64, "kernel_matvec_batched: bad sizes");
+        KRR_REQUIRE(prec == KRR_F32 || prec == KRR_F64, "kernel_matvec_batched: prec must be KRR_F32 or KRR_F64");
+        KRR_REQUIRE(X && W && Out, "kernel_matvec_batched: NULL pointer");
+        require_device();
+        const int64_t n = b.pbeg.back();
+        kernel_matvec_impl(X, n, X, n, d, xprec, b.h[0], W, nrhs, 0.0, Out, prec, S(stream), &b);
+        return KRR_OK;
+    });
+}
+
+int krr_refine_batched(hss_ulv_t F, const void *Xp, int32_t xprec, const int64_t *offsets, int32_t np, int32_t d,
+                       const double *h, const double *lambda, const double *Y, int32_t nrhs, double *alpha,
+                       double tol, int32_t max_iter, int32_t mv_prec, void *stream, krr_refine_stats *stats_host,
+                       double *relres_host) {
+    return guard([&] {
+        check_xprec(xprec);
+        KRR_REQUIRE(lambda != nullptr, "krr_refine_batched: NULL lambda");
+        Batch b = make_batch(offsets, np, h, lambda, "krr_refine_batched");
+        const int64_t n = b.pbeg.back();
+        KRR_REQUIRE(Xp && Y && alpha, "krr_refine_batched: NULL argument");
+        KRR_REQUIRE(!F || (F->n == n && F->lamprob.size() == (size_t)np),
+                    "krr_refine_batched: the factor must cover the same problems");
+        KRR_REQUIRE(d >= 1 && nrhs >= 1 && nrhs <= 64, "krr_refine_batched: bad sizes");
+        KRR_REQUIRE(tol > 0.0 && max_iter >= 0, "krr_refine_batched: bad parameters");
+        KRR_REQUIRE(mv_prec == KRR_F32 || mv_prec == KRR_F64, "krr_refine_batched: mv_prec must be KRR_F32 or KRR_F64");
+        require_device();
+        int rc = refine(F, n, Xp, xprec, d, b.h[0], b.lam[0], Y, nrhs, alpha, tol, max_iter, mv_prec, S(stream),
+                        stats_host, &b, relres_host);
+        if (rc == KRR_E_NOT_CONVERGED) g_last_error = "krr_refine_batched: tolerance not reached within max_iter";
+        return rc;
     });
 }
 

@@ -331,12 +331,13 @@ __global__ void k_perm_init(int64_t n, int64_t *perm) {
 
 struct TmpNode {
     int64_t b, e;
+    int64_t base;                   // first position of the node's problem
     int64_t left = -1, right = -1;  // indices into the TmpNode list
 };
 
 template <class T>
-void cluster_impl(const T *X, int64_t n, int d, const krr_cluster_opts &o, hipStream_t s,
-                  int64_t *perm_out, krr_tree_s &tree) {
+void cluster_impl(const T *X, int64_t n, int d, const std::vector<int64_t> &roots, const krr_cluster_opts &o,
+                  hipStream_t s, int64_t *perm_out, krr_tree_s &tree) {
     const int leaf = o.leaf_size;
     DBuf xa = dalloc<T>(n * d), xb = dalloc<T>(n * d);
     DBuf pa = dalloc<int64_t>(n), pb = dalloc<int64_t>(n);
@@ -345,10 +346,14 @@ void cluster_impl(const T *X, int64_t n, int d, const krr_cluster_opts &o, hipSt
     k_perm_init<<<ceil_div(n, 256), 256, 0, s>>>(n, pa.as<int64_t>());
     check_launch("k_perm_init");
 
+    // one tree per range [roots[k], roots[k + 1]) (a forest for batched problems)
     std::vector<TmpNode> tn;
-    tn.push_back({0, n});
     std::vector<int64_t> active;
-    if (n > leaf) active.push_back(0);
+    const int nroots = (int)roots.size() - 1;
+    for (int k = 0; k < nroots; ++k) {
+        tn.push_back({roots[k], roots[k + 1], roots[k]});
+        if (roots[k + 1] - roots[k] > leaf) active.push_back(k);
+    }
     DBuf counter = dalloc<int32_t>(1);
     int64_t levels = 0, fallbacks = 0, capped = 0, iterations = 0;
 
@@ -365,8 +370,10 @@ void cluster_impl(const T *X, int64_t n, int d, const krr_cluster_opts &o, hipSt
             nb[a] = t.b;
             ne[a] = t.e;
             uint64_t sz = (uint64_t)(t.e - t.b);
-            i1[a] = t.b + (int64_t)mulhi_u64(node_draw(o.seed, t.b, t.e, 0), sz);
-            draw1[a] = node_draw(o.seed, t.b, t.e, 1);
+            // draws keyed by positions within the problem: each tree of a
+            // forest is the tree of its problem clustered alone
+            i1[a] = t.b + (int64_t)mulhi_u64(node_draw(o.seed, t.b - t.base, t.e - t.base, 0), sz);
+            draw1[a] = node_draw(o.seed, t.b - t.base, t.e - t.base, 1);
             ch0[a] = (int32_t)cnode.size();
             for (int64_t p = t.b; p < t.e; p += CH) {
                 cnode.push_back(a);
@@ -458,8 +465,8 @@ void cluster_impl(const T *X, int64_t n, int d, const krr_cluster_opts &o, hipSt
                 nl = sz - n1[a];
             }
             int64_t li = (int64_t)tn.size();
-            tn.push_back({b, b + nl});
-            tn.push_back({b + nl, e});
+            tn.push_back({b, b + nl, tn[id].base});
+            tn.push_back({b + nl, e, tn[id].base});
             tn[id].left = li;
             tn[id].right = li + 1;
             if (nl > leaf) next.push_back(li);
@@ -469,36 +476,40 @@ void cluster_impl(const T *X, int64_t n, int d, const krr_cluster_opts &o, hipSt
     }
     KRR_HIP(hipMemcpyAsync(perm_out, pa.get(), sizeof(int64_t) * n, hipMemcpyDeviceToDevice, s));
 
-    // postorder numbering of the discovered tree
+    // postorder numbering of the discovered trees, one after the other
     tree.n = n;
     tree.nodes.assign(tn.size() * 5, -1);
+    tree.roots.clear();
     std::vector<int64_t> id_of(tn.size(), -1);
-    std::vector<std::pair<int64_t, int>> stack{{0, 0}};
     int64_t next_id = 0;
-    while (!stack.empty()) {
-        auto &top = stack.back();
-        const TmpNode &t = tn[top.first];
-        if (t.left >= 0 && top.second == 0) {
-            top.second = 1;
-            stack.push_back({t.left, 0});
-        } else if (t.left >= 0 && top.second == 1) {
-            top.second = 2;
-            stack.push_back({t.right, 0});
-        } else {
-            int64_t id = next_id++;
-            id_of[top.first] = id;
-            int64_t *row = &tree.nodes[5 * id];
-            row[0] = t.b;
-            row[1] = t.e;
-            row[2] = t.left >= 0 ? id_of[t.left] : -1;
-            row[3] = t.right >= 0 ? id_of[t.right] : -1;
-            row[4] = -1;
-            if (t.left >= 0) {
-                tree.nodes[5 * row[2] + 4] = id;
-                tree.nodes[5 * row[3] + 4] = id;
+    for (int k = 0; k < nroots; ++k) {
+        std::vector<std::pair<int64_t, int>> stack{{(int64_t)k, 0}};
+        while (!stack.empty()) {
+            auto &top = stack.back();
+            const TmpNode &t = tn[top.first];
+            if (t.left >= 0 && top.second == 0) {
+                top.second = 1;
+                stack.push_back({t.left, 0});
+            } else if (t.left >= 0 && top.second == 1) {
+                top.second = 2;
+                stack.push_back({t.right, 0});
+            } else {
+                int64_t id = next_id++;
+                id_of[top.first] = id;
+                int64_t *row = &tree.nodes[5 * id];
+                row[0] = t.b;
+                row[1] = t.e;
+                row[2] = t.left >= 0 ? id_of[t.left] : -1;
+                row[3] = t.right >= 0 ? id_of[t.right] : -1;
+                row[4] = -1;
+                if (t.left >= 0) {
+                    tree.nodes[5 * row[2] + 4] = id;
+                    tree.nodes[5 * row[3] + 4] = id;
+                }
+                stack.pop_back();
             }
-            stack.pop_back();
         }
+        tree.roots.push_back(next_id - 1);
     }
     tree.stats = {fallbacks, capped, iterations, levels};
     sync(s);  // keep the temporaries alive until the last copy is done
@@ -506,12 +517,12 @@ void cluster_impl(const T *X, int64_t n, int d, const krr_cluster_opts &o, hipSt
 
 }  // namespace
 
-void cluster_2mn(const void *X, int32_t xprec, int64_t n, int32_t d, const krr_cluster_opts &o,
-                 hipStream_t s, int64_t *perm, krr_tree_s &tree) {
+void cluster_2mn(const void *X, int32_t xprec, int64_t n, int32_t d, const std::vector<int64_t> &roots,
+                 const krr_cluster_opts &o, hipStream_t s, int64_t *perm, krr_tree_s &tree) {
     if (xprec == KRR_F64)
-        cluster_impl<double>(static_cast<const double *>(X), n, d, o, s, perm, tree);
+        cluster_impl<double>(static_cast<const double *>(X), n, d, roots, o, s, perm, tree);
     else
-        cluster_impl<float>(static_cast<const float *>(X), n, d, o, s, perm, tree);
+        cluster_impl<float>(static_cast<const float *>(X), n, d, roots, o, s, perm, tree);
 }
 
 }  // namespace krr

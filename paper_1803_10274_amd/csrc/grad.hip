@@ -11,8 +11,6 @@
 
 namespace krr {
 
-void kernel_matvec_impl(const void *X, int64_t m, const void *Y, int64_t n, int d, int xprec, double h,
-                        const double *W, int nrhs, double beta, double *Out, int prec, hipStream_t s);
 
 namespace {
 constexpr int GB_ROWS = 256, GB_TN = 32, GB_DMAX = 64, GB_RMAX = 16;

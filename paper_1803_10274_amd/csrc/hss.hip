@@ -24,9 +24,6 @@
 
 namespace krr {
 
-void sample_product(const void *X, int64_t n, int d, int xprec, double h, const float *R, int r,
-                    const int32_t *lb, const int32_t *le, void *S, int prec, int split, hipStream_t s);
-void random_block(uint64_t seed, int64_t n, int r, int c0, float *R, int ldr, hipStream_t s);
 
 std::vector<std::vector<int>> levels_by_height(std::vector<HNode> &nodes) {
     int maxh = 0;
@@ -43,7 +40,7 @@ std::vector<std::vector<int>> levels_by_height(std::vector<HNode> &nodes) {
 void validate_tree(const krr_tree_s *t) {
     const int64_t nn = t->n_nodes();
     KRR_REQUIRE(nn >= 1, "tree has no nodes");
-    KRR_REQUIRE(t->b(nn - 1) == 0 && t->e(nn - 1) == t->n, "root must span [0, n)");
+    KRR_REQUIRE(!t->roots.empty(), "tree has no roots");
     for (int64_t i = 0; i < nn; ++i) {
         KRR_REQUIRE(t->e(i) > t->b(i), "node %lld is empty", (long long)i);
         if (!t->leaf(i)) {
@@ -51,10 +48,25 @@ void validate_tree(const krr_tree_s *t) {
             KRR_REQUIRE(l >= 0 && r >= 0 && l < i && r < i, "node %lld: children must precede it", (long long)i);
             KRR_REQUIRE(t->b(l) == t->b(i) && t->e(l) == t->b(r) && t->e(r) == t->e(i),
                         "node %lld: children must split its range", (long long)i);
+            KRR_REQUIRE(t->parent(l) == i && t->parent(r) == i, "node %lld: children's parent link", (long long)i);
         } else {
             KRR_REQUIRE(t->right(i) < 0, "leaf %lld has a right child", (long long)i);
         }
+        const int64_t p = t->parent(i);
+        KRR_REQUIRE(p < 0 || (p > i && p < nn && (t->left(p) == i || t->right(p) == i)),
+                    "node %lld: parent link", (long long)i);
     }
+    int64_t pos = 0, prev = -1;
+    for (int64_t r : t->roots) {
+        KRR_REQUIRE(r > prev && r < nn && t->parent(r) < 0, "root %lld is not a root", (long long)r);
+        KRR_REQUIRE(t->b(r) == pos, "roots must cover [0, n) in order");
+        // each tree's nodes are stored together, ending at its root
+        for (int64_t i = prev + 1; i <= r; ++i)
+            KRR_REQUIRE(t->b(i) >= t->b(r) && t->e(i) <= t->e(r), "node %lld lies outside its tree", (long long)i);
+        pos = t->e(r);
+        prev = r;
+    }
+    KRR_REQUIRE(pos == t->n && prev == nn - 1, "roots must cover [0, n) and end the node list");
 }
 
 namespace {
@@ -63,6 +75,7 @@ struct NodeDesc {
     int32_t m, kl, kr, leaf;
     int32_t k, pad_;
     int64_t b;
+    double inv;  // 1 / (2 h^2) of the node's problem
     double *Y, *G, *Lf;
     int32_t *piv;
     double *D, *B;
@@ -84,8 +97,9 @@ __device__ __forceinline__ double pair_kernel(const T *__restrict__ X, int d, in
 }
 
 template <class T>
-__global__ __launch_bounds__(BG_T) void k_extract(const T *__restrict__ X, int d, double inv, const NodeDesc *nds) {
+__global__ __launch_bounds__(BG_T) void k_extract(const T *__restrict__ X, int d, const NodeDesc *nds) {
     const NodeDesc nd = nds[blockIdx.x];
+    const double inv = nd.inv;
     if (nd.leaf) {
         const int m = nd.m;
         for (int t = threadIdx.x; t < m * m; t += BG_T) {
@@ -252,15 +266,13 @@ struct Attempt {
 
 // Runs every level with sample width r.  Returns false when some rank
 // reached r - p while its sample could have hidden more.
-bool run_levels(hss_s *H, const void *Xp, int xprec, int d, double h, const hss_opts &o, int r, bool truncate,
+bool run_levels(hss_s *H, const void *Xp, int xprec, int d, const hss_opts &o, int r, bool truncate,
                 const float *R, const void *S, bool s64, double *Dpool, const std::vector<int64_t> &doff,
                 Attempt &A, hipStream_t s, double &t_id) {
     EventTimer timer(s);
     const int nn = (int)H->node.size();
-    const int root = nn - 1;
     A.out.assign(nn, NodeOut());
     A.keep.clear();
-    const double inv = 1.0 / (2.0 * h * h);
     const double atol_abs = o.atol * std::sqrt((double)r);
     DBuf flag = dalloc<int32_t>(1);
     KRR_HIP(hipMemsetAsync(flag.get(), 0, sizeof(int32_t), s));
@@ -277,6 +289,10 @@ bool run_levels(hss_s *H, const void *Xp, int xprec, int d, double h, const hss_
             ids[a] = lv[a];
             q.leaf = hn.left < 0;
             q.b = hn.b;
+            {
+                const double hk = H->hprob[H->nprob[lv[a]]];
+                q.inv = 1.0 / (2.0 * hk * hk);
+            }
             if (q.leaf) {
                 q.m = (int32_t)(hn.e - hn.b);
             } else {
@@ -321,35 +337,55 @@ bool run_levels(hss_s *H, const void *Xp, int xprec, int d, double h, const hss_
         DBuf dnd = upload(nd, s);
         auto *dq = dnd.as<NodeDesc>();
         if (xprec == KRR_F64)
-            k_extract<double><<<cnt, BG_T, 0, s>>>(static_cast<const double *>(Xp), d, inv, dq);
+            k_extract<double><<<cnt, BG_T, 0, s>>>(static_cast<const double *>(Xp), d, dq);
         else
-            k_extract<float><<<cnt, BG_T, 0, s>>>(static_cast<const float *>(Xp), d, inv, dq);
+            k_extract<float><<<cnt, BG_T, 0, s>>>(static_cast<const float *>(Xp), d, dq);
         check_launch("k_extract");
         A.keep.push_back(std::move(Bb));
-        const bool is_root_level = (cnt == 1 && ids[0] == root);
-        if (is_root_level) break;  // the root has no basis
+        // roots have no basis: the rest of the level works on the other nodes
+        {
+            std::vector<NodeDesc> keep_nd;
+            std::vector<int> keep_ids;
+            for (int a = 0; a < cnt; ++a)
+                if (H->node[ids[a]].parent >= 0) {
+                    keep_nd.push_back(nd[a]);
+                    keep_ids.push_back(ids[a]);
+                }
+            if (keep_nd.empty()) {
+                sync(s);
+                continue;
+            }
+            if ((int)keep_nd.size() != cnt) {
+                sync(s);  // the uploaded descriptors are replaced below
+                nd.swap(keep_nd);
+                ids.swap(keep_ids);
+                dnd = upload(nd, s);
+                dq = dnd.as<NodeDesc>();
+            }
+        }
+        const int cnt2 = (int)nd.size();
         if (s64)
-            k_build_y<double><<<cnt, BG_T, 0, s>>>(dq, static_cast<const double *>(S), r);
+            k_build_y<double><<<cnt2, BG_T, 0, s>>>(dq, static_cast<const double *>(S), r);
         else
-            k_build_y<float><<<cnt, BG_T, 0, s>>>(dq, static_cast<const float *>(S), r);
+            k_build_y<float><<<cnt2, BG_T, 0, s>>>(dq, static_cast<const float *>(S), r);
         check_launch("k_build_y");
-        k_gram<<<cnt, BG_T, 0, s>>>(dq, r);
+        k_gram<<<cnt2, BG_T, 0, s>>>(dq, r);
         check_launch("k_gram");
-        DBuf kout = dalloc<int32_t>(cnt);
+        DBuf kout = dalloc<int32_t>(cnt2);
         size_t dyn = (size_t)mmax * (sizeof(double) + sizeof(int));
         KRR_REQUIRE(dyn <= 150 * 1024, "node sample of %d rows exceeds the LDS budget", mmax);
         const int kmax = truncate ? std::max(0, r - o.oversample) : r;
-        k_pivchol<<<cnt, BG_T, dyn, s>>>(dq, r, kmax, o.rtol, atol_abs, kout.as<int32_t>(), flag.as<int32_t>());
+        k_pivchol<<<cnt2, BG_T, dyn, s>>>(dq, r, kmax, o.rtol, atol_abs, kout.as<int32_t>(), flag.as<int32_t>());
         check_launch("k_pivchol");
-        std::vector<int32_t> ks(cnt);
+        std::vector<int32_t> ks(cnt2);
         int32_t bad = 0;
-        d2h(ks.data(), kout.as<int32_t>(), cnt, s);
+        d2h(ks.data(), kout.as<int32_t>(), cnt2, s);
         d2h(&bad, flag.as<int32_t>(), 1, s);
         sync(s);
         if (bad) fail(KRR_E_NUMERIC, "non-finite values in the sampled block rows");
         bool grow = false;
         int64_t usz = 0, ksz = 0;
-        for (int a = 0; a < cnt; ++a) {
+        for (int a = 0; a < cnt2; ++a) {
             nd[a].k = ks[a];
             if (nd[a].m > r - o.oversample && ks[a] > r - o.oversample) grow = true;
             usz += (int64_t)nd[a].m * ks[a];
@@ -357,19 +393,19 @@ bool run_levels(hss_s *H, const void *Xp, int xprec, int d, double h, const hss_
         }
         if (verbose()) {
             int mk = 0, mm = 0;
-            for (int a = 0; a < cnt; ++a) {
+            for (int a = 0; a < cnt2; ++a) {
                 mk = std::max(mk, (int)ks[a]);
                 mm = std::max(mm, (int)nd[a].m);
             }
             fprintf(stderr, "[krr] compress r=%d level h=%d nodes=%d max m=%d max k=%d%s\n", r,
-                    H->node[ids[0]].height, cnt, mm, mk, grow ? " -> grow" : "");
+                    H->node[ids[0]].height, cnt2, mm, mk, grow ? " -> grow" : "");
         }
         if (grow && !truncate) return false;
         DBuf Ub = dalloc<double>(usz), Jb = dalloc<int32_t>(ksz), Sk = dalloc<double>(ksz * r),
              Om = dalloc<double>(ksz * r);
         {
             int64_t ou = 0, ok = 0;
-            for (int a = 0; a < cnt; ++a) {
+            for (int a = 0; a < cnt2; ++a) {
                 NodeDesc &q = nd[a];
                 q.U = Ub.as<double>() + ou;
                 q.J = Jb.as<int32_t>() + ok;
@@ -381,8 +417,8 @@ bool run_levels(hss_s *H, const void *Xp, int xprec, int d, double h, const hss_
                 no.U = q.U; no.J = q.J; no.Ysk = q.Ysk; no.Om = q.Om; no.k = q.k;
             }
         }
-        h2d(dq, nd.data(), cnt, s);
-        k_id_finish<float><<<cnt, BG_T, 0, s>>>(dq, r, R);
+        h2d(dq, nd.data(), cnt2, s);
+        k_id_finish<float><<<cnt2, BG_T, 0, s>>>(dq, r, R);
         check_launch("k_id_finish");
         A.keep.push_back(std::move(Ub));
         A.keep.push_back(std::move(Jb));
@@ -396,15 +432,35 @@ bool run_levels(hss_s *H, const void *Xp, int xprec, int d, double h, const hss_
 
 }  // namespace
 
-void compress(const krr_tree_s *t, const void *Xp, int xprec, int d, double h, const hss_opts &o,
-              hipStream_t s, hss_s *H, hss_stats *st) {
+void compress(const krr_tree_s *t, const void *Xp, int xprec, int d, const std::vector<double> &hprob,
+              const hss_opts &o, hipStream_t s, hss_s *H, hss_stats *st) {
     EventTimer total(s);
     const int64_t n = t->n;
     const int64_t nn = t->n_nodes();
+    const int np = (int)t->roots.size();
+    KRR_REQUIRE((int)hprob.size() == np, "one kernel width per tree is required (%d trees, %d widths)", np,
+                (int)hprob.size());
     H->n = n;
     H->d = d;
-    H->h = h;
+    H->h = hprob[0];
+    H->hprob = hprob;
     H->node.resize(nn);
+    H->nprob.assign(nn, 0);
+    H->pbeg.assign(1, 0);
+    {
+        int64_t first = 0;  // trees are stored one after the other, each ending at its root
+        for (int k = 0; k < np; ++k) {
+            const int64_t rt = t->roots[k];
+            for (int64_t i = first; i <= rt; ++i) H->nprob[i] = k;
+            first = rt + 1;
+            H->pbeg.push_back(t->e(rt));
+        }
+    }
+    Batch batch;
+    batch.pbeg = H->pbeg;
+    batch.h = hprob;
+    const Batch *bp = np > 1 ? &batch : nullptr;
+    const double h = hprob[0];
     for (int64_t i = 0; i < nn; ++i) {
         HNode &q = H->node[i];
         q = HNode{t->b(i), t->e(i), t->left(i), t->right(i), t->parent(i), 0, 0, 0, -1, -1, -1, -1};
@@ -439,13 +495,13 @@ void compress(const krr_tree_s *t, const void *Xp, int xprec, int d, double h, c
         EventTimer ts(s);
         random_block(o.seed, n, r, 0, R.as<float>(), r, s);
         sample_product(Xp, n, d, xprec, h, R.as<float>(), r, plb.as<int32_t>(), ple.as<int32_t>(), S.get(),
-                       o.prec, o.split_terms, s);
+                       o.prec, o.split_terms, s, bp);
         t_sample += ts.stop_ms();
     }
     Attempt A;
     int regrowths = 0;
     bool truncated = false;
-    while (!run_levels(H, Xp, xprec, d, h, o, r, truncated, R.as<float>(), S.get(), s64, H->D.as<double>(), doff, A,
+    while (!run_levels(H, Xp, xprec, d, o, r, truncated, R.as<float>(), S.get(), s64, H->D.as<double>(), doff, A,
                        s, t_id)) {
         if (r >= o.r_max) {
             if (o.cap_policy == 0)
@@ -459,7 +515,7 @@ void compress(const krr_tree_s *t, const void *Xp, int xprec, int d, double h, c
         DBuf Rn = dalloc<float>((size_t)n * dr), Sn((size_t)n * dr * sel);
         random_block(o.seed, n, dr, r, Rn.as<float>(), dr, s);
         sample_product(Xp, n, d, xprec, h, Rn.as<float>(), dr, plb.as<int32_t>(), ple.as<int32_t>(), Sn.get(),
-                       o.prec, o.split_terms, s);
+                       o.prec, o.split_terms, s, bp);
         DBuf R2 = dalloc<float>((size_t)n * r2), S2((size_t)n * r2 * sel);
         KRR_HIP(hipMemcpy2DAsync(R2.get(), r2 * sizeof(float), R.get(), r * sizeof(float), r * sizeof(float), n,
                                  hipMemcpyDeviceToDevice, s));
@@ -484,7 +540,7 @@ void compress(const krr_tree_s *t, const void *Xp, int xprec, int d, double h, c
         q.k = no.k;
         maxk = std::max(maxk, (int)no.k);
         q.offD = doff[i];
-        if (i != nn - 1) {
+        if (q.parent >= 0) {
             q.offU = usz;
             usz += (int64_t)no.m * no.k;
             q.offJ = jsz;

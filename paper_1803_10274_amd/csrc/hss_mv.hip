@@ -61,12 +61,11 @@ __global__ __launch_bounds__(BG_T) void k_mv_leaf(const MvDesc *dsc, const doubl
 
 void hss_matvec_impl(const hss_s *H, const double *x, int nrhs, double *y, hipStream_t s) {
     const int nn = (int)H->node.size();
-    const int root = nn - 1;
     std::vector<int64_t> off(nn);
     int64_t tot = 0;
     for (int i = 0; i < nn; ++i) {
         off[i] = tot;
-        tot += (int64_t)(i == root ? 0 : H->node[i].k) * nrhs;
+        tot += (int64_t)(H->node[i].parent < 0 ? 0 : H->node[i].k) * nrhs;
     }
     DBuf xh = dalloc<double>(std::max<int64_t>(tot, 1)), yh = dalloc<double>(std::max<int64_t>(tot, 1));
     std::vector<MvDesc> all(nn);
@@ -75,7 +74,7 @@ void hss_matvec_impl(const hss_s *H, const double *x, int nrhs, double *y, hipSt
         MvDesc &d = all[i];
         std::memset(&d, 0, sizeof d);
         d.leaf = q.left < 0;
-        d.root = i == root;
+        d.root = q.parent < 0;
         d.m = q.m;
         d.k = d.root ? 0 : q.k;
         d.b = q.b;

@@ -9,7 +9,11 @@
 struct krr_tree_s {
     int64_t n = 0;
     // n_nodes rows of (begin, end, left, right, parent), postorder, root last.
+    // A forest (batched problems) lists its trees one after the other; roots
+    // holds each tree's root (the last node of its run) and problem k spans
+    // [nodes[roots[k]].begin, nodes[roots[k]].end).
     std::vector<int64_t> nodes;
+    std::vector<int64_t> roots;
     std::array<int64_t, 4> stats{{0, 0, 0, 0}};
     int64_t n_nodes() const { return (int64_t)nodes.size() / 5; }
     int64_t b(int64_t i) const { return nodes[5 * i]; }
@@ -18,6 +22,7 @@ struct krr_tree_s {
     int64_t right(int64_t i) const { return nodes[5 * i + 3]; }
     int64_t parent(int64_t i) const { return nodes[5 * i + 4]; }
     bool leaf(int64_t i) const { return nodes[5 * i + 2] < 0; }
+    void set_single_root() { roots.assign(1, n_nodes() - 1); }
 };
 
 namespace krr {
@@ -40,6 +45,30 @@ std::vector<std::vector<int>> levels_by_height(std::vector<HNode> &nodes);
 
 void validate_tree(const krr_tree_s *t);
 
+// Independent problems of a batched (block-diagonal) operation: problem k
+// owns the consecutive points [pbeg[k], pbeg[k + 1]) and has kernel width
+// h[k] and ridge parameter lam[k] (lam may be empty where unused).
+struct Batch {
+    std::vector<int64_t> pbeg;
+    std::vector<double> h, lam;
+    int np() const { return (int)h.size(); }
+    int64_t size(int k) const { return pbeg[k + 1] - pbeg[k]; }
+};
+
+// One workgroup's share of a batched kernel product: rows [i0, iend) and
+// columns [jlo, jhi) of one problem, whose kernel scale is inv = 1 / (2 h^2)
+// (cs = inv log2(e) rounded to FP32 for the exp2 forms).  cps: columns per
+// split-K slice where the product splits its columns.
+struct SampBlock {
+    int64_t i0, iend, jlo, jhi, cps;
+    double inv, c2;
+    float cs, pad_;
+};
+
+// Row blocks of `rows` rows over every problem, larger problems first (their
+// blocks carry the most work, so they start before the short ones).
+std::vector<SampBlock> row_blocks(const Batch &b, int rows);
+
 // Diagnostic logging to stderr when the environment sets KRR_VERBOSE.
 bool verbose();
 
@@ -48,7 +77,10 @@ bool verbose();
 struct hss_s {
     int64_t n = 0;
     int32_t d = 0;
-    double h = 0;
+    double h = 0;                  // kernel width (problem 0; see hprob)
+    std::vector<double> hprob;     // kernel width per problem (forest)
+    std::vector<int64_t> pbeg;     // problem k spans [pbeg[k], pbeg[k + 1])
+    std::vector<int32_t> nprob;    // problem of each node
     std::vector<krr::HNode> node;
     std::vector<std::vector<int>> levels;
     krr::DBuf U, D, B, J;     // generator pools (FP64, FP64, FP64, int32)
@@ -59,6 +91,7 @@ struct hss_s {
 struct hss_ulv_s {
     int64_t n = 0;
     double lambda = 0;
+    std::vector<double> lamprob;        // lambda per problem (forest)
     std::vector<krr::HNode> node;       // copy of the HSS node table
     std::vector<std::vector<int>> levels;
     // Per node: Householder vectors of U's QR (m x k, column j = reflector j),
@@ -69,3 +102,37 @@ struct hss_ulv_s {
     krr::DBuf V, T, L, W;
     int64_t nV = 0, nT = 0, nL = 0, nW = 0;
 };
+
+// ------------------------------------------------ entry points across units
+namespace krr {
+
+void cluster_2mn(const void *X, int32_t xprec, int64_t n, int32_t d, const std::vector<int64_t> &roots,
+                 const krr_cluster_opts &o, hipStream_t s, int64_t *perm, krr_tree_s &tree);
+void kernel_matvec_impl(const void *X, int64_t m, const void *Y, int64_t n, int d, int xprec, double h,
+                        const double *W, int nrhs, double beta, double *Out, int prec, hipStream_t s,
+                        const Batch *batch = nullptr);
+void kernel_matvec_bwd_impl(const void *X, int64_t m, const void *Y, int64_t n, int d, int xprec, double h,
+                            const double *W, const double *G, int nrhs, double *dX, double *dY, double *dW,
+                            double *dh, int prec, hipStream_t s);
+void sample_product(const void *X, int64_t n, int d, int xprec, double h, const float *R, int r, const int32_t *lb,
+                    const int32_t *le, void *S, int prec, int split, hipStream_t s, const Batch *batch = nullptr);
+void random_block(uint64_t seed, int64_t n, int r, int c0, float *R, int ldr, hipStream_t s);
+void gather_rows(const void *src, int prec, int64_t n, int cols, const int64_t *perm, void *dst, bool scatter,
+                 hipStream_t s);
+// hprob: kernel width of each tree of the forest (one entry per root)
+void compress(const krr_tree_s *t, const void *Xp, int xprec, int d, const std::vector<double> &hprob,
+              const hss_opts &o, hipStream_t s, hss_s *H, hss_stats *st);
+// lam / floor: diagonal shift and pivot floor of each problem (per root)
+int64_t ulv_factor(const hss_s *H, const std::vector<double> &lam, const std::vector<double> &floor, hipStream_t s,
+                   hss_ulv_s *F, double *worst_deficit = nullptr, bool stop_at_floor = false);
+void ulv_solve(const hss_ulv_s *F, const double *Bin, int nrhs, double *Xout, hipStream_t s);
+void hss_matvec_impl(const hss_s *H, const double *x, int nrhs, double *y, hipStream_t s);
+// batch == nullptr: one problem (h, lambda); otherwise per-problem h and lam
+// (relres_all, if given, receives np x nrhs relative residuals)
+int refine(const hss_ulv_s *F, int64_t n, const void *Xp, int xprec, int d, double h, double lambda, const double *Y,
+           int nrhs, double *alpha, double tol, int max_iter, int mv_prec, hipStream_t s, krr_refine_stats *st,
+           const Batch *batch = nullptr, double *relres_all = nullptr);
+void predict_labels(const double *scores, int64_t m, int k, int32_t *labels, hipStream_t s);
+void dot_columns(const double *a, const double *b, int64_t n, int k, double *out, DBuf &scratch, hipStream_t s);
+
+}  // namespace krr

@@ -36,17 +36,29 @@ template <class T, class C, int D, int NR>
 __global__ __launch_bounds__(MV_ROWS) void k_kmv(const T *__restrict__ X, int64_t m,
                                                  const T *__restrict__ Y, int64_t n, int d, C scale,
                                                  const double *__restrict__ W, int nrhs, int rhs0,
-                                                 int64_t cols_per_split, double *__restrict__ part) {
+                                                 int64_t cols_per_split, double *__restrict__ part,
+                                                 const SampBlock *__restrict__ bt) {
     __shared__ C ys[MV_TN][D];
     __shared__ C ws[MV_TN][NR];
     const int tid = threadIdx.x;
-    const int64_t i = (int64_t)blockIdx.x * MV_ROWS + tid;
     const int split = blockIdx.y;
-    const int64_t j0 = split * cols_per_split;
-    const int64_t j1 = min(n, j0 + cols_per_split);
+    int64_t i, iend, j0, j1;
+    if (bt) {
+        const SampBlock sb = bt[blockIdx.x];
+        i = sb.i0 + tid;
+        iend = sb.iend;
+        j0 = sb.jlo + split * sb.cps;
+        j1 = min(sb.jhi, j0 + sb.cps);
+        if constexpr (sizeof(C) == 8) scale = sb.inv; else scale = sb.cs;
+    } else {
+        i = (int64_t)blockIdx.x * MV_ROWS + tid;
+        iend = m;
+        j0 = split * cols_per_split;
+        j1 = min(n, j0 + cols_per_split);
+    }
     C x[D];
 #pragma unroll
-    for (int k = 0; k < D; ++k) x[k] = (i < m && k < d) ? (C)X[i * d + k] : (C)0;
+    for (int k = 0; k < D; ++k) x[k] = (i < iend && k < d) ? (C)X[i * d + k] : (C)0;
     double acc[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) acc[r] = 0.0;
@@ -81,7 +93,7 @@ __global__ __launch_bounds__(MV_ROWS) void k_kmv(const T *__restrict__ X, int64_
         for (int r = 0; r < NR; ++r) acc[r] += (double)pacc[r];
         __syncthreads();
     }
-    if (i < m) {
+    if (i < iend) {
         for (int r = 0; r < nr; ++r) part[((int64_t)split * m + i) * nrhs + rhs0 + r] = acc[r];
     }
 }
@@ -96,19 +108,31 @@ template <class T, int D, int NR>
 __global__ __launch_bounds__(MV_ROWS) void k_kmv_expand(const T *__restrict__ X, int64_t m,
                                                         const T *__restrict__ Y, int64_t n, int d, double c2,
                                                         const double *__restrict__ W, int nrhs, int rhs0,
-                                                        int64_t cols_per_split, double *__restrict__ part) {
+                                                        int64_t cols_per_split, double *__restrict__ part,
+                                                        const SampBlock *__restrict__ bt) {
     __shared__ double ys[MV_TN][D + 1];
     __shared__ float ws[MV_TN][NR];
     const int tid = threadIdx.x;
-    const int64_t i = (int64_t)blockIdx.x * MV_ROWS + tid;
     const int split = blockIdx.y;
-    const int64_t j0 = split * cols_per_split;
-    const int64_t j1 = min(n, j0 + cols_per_split);
+    int64_t i, iend, j0, j1;
+    if (bt) {
+        const SampBlock sb = bt[blockIdx.x];
+        i = sb.i0 + tid;
+        iend = sb.iend;
+        j0 = sb.jlo + split * sb.cps;
+        j1 = min(sb.jhi, j0 + sb.cps);
+        c2 = sb.c2;
+    } else {
+        i = (int64_t)blockIdx.x * MV_ROWS + tid;
+        iend = m;
+        j0 = split * cols_per_split;
+        j1 = min(n, j0 + cols_per_split);
+    }
     double xs[D];
     double nx = 0.0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        double v = (i < m && k < d) ? (double)X[i * d + k] : 0.0;
+        double v = (i < iend && k < d) ? (double)X[i * d + k] : 0.0;
         nx = fma(v, v, nx);
         xs[k] = 2.0 * c2 * v;
     }
@@ -150,7 +174,7 @@ __global__ __launch_bounds__(MV_ROWS) void k_kmv_expand(const T *__restrict__ X,
         for (int r = 0; r < NR; ++r) acc[r] += (double)pacc[r];
         __syncthreads();
     }
-    if (i < m) {
+    if (i < iend) {
         for (int r = 0; r < nr; ++r) part[((int64_t)split * m + i) * nrhs + rhs0 + r] = acc[r];
     }
 }
@@ -160,20 +184,32 @@ template <class T, class C, int NR>
 __global__ __launch_bounds__(MV_ROWS) void k_kmv_wide(const T *__restrict__ X, int64_t m,
                                                       const T *__restrict__ Y, int64_t n, int d, C scale,
                                                       const double *__restrict__ W, int nrhs, int rhs0,
-                                                      int64_t cols_per_split, double *__restrict__ part) {
+                                                      int64_t cols_per_split, double *__restrict__ part,
+                                                      const SampBlock *__restrict__ bt) {
     constexpr int TK = 64;
     __shared__ C ys[16][TK + 1];
     __shared__ C ws[16][NR];
     const int tid = threadIdx.x;
-    const int64_t i = (int64_t)blockIdx.x * MV_ROWS + tid;
     const int split = blockIdx.y;
-    const int64_t j0 = split * cols_per_split;
-    const int64_t j1 = min(n, j0 + cols_per_split);
+    int64_t i, iend, j0, j1;
+    if (bt) {
+        const SampBlock sb = bt[blockIdx.x];
+        i = sb.i0 + tid;
+        iend = sb.iend;
+        j0 = sb.jlo + split * sb.cps;
+        j1 = min(sb.jhi, j0 + sb.cps);
+        if constexpr (sizeof(C) == 8) scale = sb.inv; else scale = sb.cs;
+    } else {
+        i = (int64_t)blockIdx.x * MV_ROWS + tid;
+        iend = m;
+        j0 = split * cols_per_split;
+        j1 = min(n, j0 + cols_per_split);
+    }
     const int nr = min(NR, nrhs - rhs0);
     double acc[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) acc[r] = 0.0;
-    const T *xr = X + (i < m ? i : 0) * (int64_t)d;
+    const T *xr = X + (i < iend ? i : 0) * (int64_t)d;
     for (int64_t jt = j0; jt < j1; jt += 16) {
         C q[16];
 #pragma unroll
@@ -215,7 +251,7 @@ __global__ __launch_bounds__(MV_ROWS) void k_kmv_wide(const T *__restrict__ X, i
         for (int r = 0; r < NR; ++r) acc[r] += (double)pacc[r];
         __syncthreads();
     }
-    if (i < m) {
+    if (i < iend) {
         for (int r = 0; r < nr; ++r) part[((int64_t)split * m + i) * nrhs + rhs0 + r] = acc[r];
     }
 }
@@ -231,60 +267,79 @@ __global__ void k_reduce_splits(const double *__restrict__ part, int nsplit, int
 
 template <class T, class C, int D, int NR>
 void launch_kmv(const T *X, int64_t m, const T *Y, int64_t n, int d, C scale, double c2, const double *W,
-                int nrhs, int rhs0, int nsplit, int64_t cps, double *part, hipStream_t s) {
-    dim3 grid(ceil_div(m, MV_ROWS), nsplit);
+                int nrhs, int rhs0, int nsplit, int64_t cps, double *part, hipStream_t s, const SampBlock *bt,
+                int64_t nb) {
+    dim3 grid(bt ? (unsigned)nb : ceil_div(m, MV_ROWS), nsplit);
     if (D > 0 && sizeof(C) == 4)
-        k_kmv_expand<T, (D > 0 ? D : 1), NR><<<grid, MV_ROWS, 0, s>>>(X, m, Y, n, d, c2, W, nrhs, rhs0, cps, part);
+        k_kmv_expand<T, (D > 0 ? D : 1), NR><<<grid, MV_ROWS, 0, s>>>(X, m, Y, n, d, c2, W, nrhs, rhs0, cps, part, bt);
     else if (D > 0)
-        k_kmv<T, C, (D > 0 ? D : 1), NR><<<grid, MV_ROWS, 0, s>>>(X, m, Y, n, d, scale, W, nrhs, rhs0, cps, part);
+        k_kmv<T, C, (D > 0 ? D : 1), NR><<<grid, MV_ROWS, 0, s>>>(X, m, Y, n, d, scale, W, nrhs, rhs0, cps, part, bt);
     else
-        k_kmv_wide<T, C, NR><<<grid, MV_ROWS, 0, s>>>(X, m, Y, n, d, scale, W, nrhs, rhs0, cps, part);
+        k_kmv_wide<T, C, NR><<<grid, MV_ROWS, 0, s>>>(X, m, Y, n, d, scale, W, nrhs, rhs0, cps, part, bt);
     check_launch("k_kmv");
 }
 
 template <class T, class C, int NR>
 void dispatch_d(const T *X, int64_t m, const T *Y, int64_t n, int d, C scale, double c2, const double *W, int nrhs,
-                int rhs0, int nsplit, int64_t cps, double *part, hipStream_t s) {
+                int rhs0, int nsplit, int64_t cps, double *part, hipStream_t s, const SampBlock *bt, int64_t nb) {
     if (d <= 8)
-        launch_kmv<T, C, 8, NR>(X, m, Y, n, d, scale, c2, W, nrhs, rhs0, nsplit, cps, part, s);
+        launch_kmv<T, C, 8, NR>(X, m, Y, n, d, scale, c2, W, nrhs, rhs0, nsplit, cps, part, s, bt, nb);
     else if (d <= 16)
-        launch_kmv<T, C, 16, NR>(X, m, Y, n, d, scale, c2, W, nrhs, rhs0, nsplit, cps, part, s);
+        launch_kmv<T, C, 16, NR>(X, m, Y, n, d, scale, c2, W, nrhs, rhs0, nsplit, cps, part, s, bt, nb);
     else if (d <= 32)
-        launch_kmv<T, C, 32, NR>(X, m, Y, n, d, scale, c2, W, nrhs, rhs0, nsplit, cps, part, s);
+        launch_kmv<T, C, 32, NR>(X, m, Y, n, d, scale, c2, W, nrhs, rhs0, nsplit, cps, part, s, bt, nb);
     else if (d <= 64)
-        launch_kmv<T, C, 64, NR>(X, m, Y, n, d, scale, c2, W, nrhs, rhs0, nsplit, cps, part, s);
+        launch_kmv<T, C, 64, NR>(X, m, Y, n, d, scale, c2, W, nrhs, rhs0, nsplit, cps, part, s, bt, nb);
     else
-        launch_kmv<T, C, 0, NR>(X, m, Y, n, d, scale, c2, W, nrhs, rhs0, nsplit, cps, part, s);
+        launch_kmv<T, C, 0, NR>(X, m, Y, n, d, scale, c2, W, nrhs, rhs0, nsplit, cps, part, s, bt, nb);
 }
 
 template <class T, class C>
 void kmv_typed(const T *X, int64_t m, const T *Y, int64_t n, int d, double h, const double *W, int nrhs,
-               double beta, double *Out, hipStream_t s) {
+               double beta, double *Out, hipStream_t s, const Batch *batch) {
     const C scale = kernel_scale<C>(h);
     const double c2 = kernel_scale_log2(h);
     // split the columns so that the grid has enough blocks to fill the chip
-    const int64_t row_blocks = ceil_div(m, MV_ROWS);
-    int nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(2048, row_blocks), ceil_div(n, 4 * MV_TN)));
-    int64_t cps = (int64_t)ceil_div(n, nsplit);
-    cps = (cps + MV_TN - 1) / MV_TN * MV_TN;
-    nsplit = (int)ceil_div(n, cps);
+    int nsplit;
+    int64_t cps = 0, nb = 0;
+    DBuf btab;
+    if (batch) {
+        std::vector<SampBlock> blocks = row_blocks(*batch, MV_ROWS);
+        nb = (int64_t)blocks.size();
+        int64_t nmax = 0;
+        for (int k = 0; k < batch->np(); ++k) nmax = std::max(nmax, batch->size(k));
+        nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(2048, nb), ceil_div(nmax, 4 * MV_TN)));
+        for (auto &b : blocks) {
+            int64_t c = ceil_div(b.jhi - b.jlo, nsplit);
+            b.cps = (c + MV_TN - 1) / MV_TN * MV_TN;
+        }
+        btab = upload(blocks, s);
+        sync(s);
+    } else {
+        const int64_t row_blocks = ceil_div(m, MV_ROWS);
+        nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(2048, row_blocks), ceil_div(n, 4 * MV_TN)));
+        cps = (int64_t)ceil_div(n, nsplit);
+        cps = (cps + MV_TN - 1) / MV_TN * MV_TN;
+        nsplit = (int)ceil_div(n, cps);
+    }
+    const SampBlock *bt = btab.as<SampBlock>();
     DBuf part = dalloc<double>((size_t)nsplit * m * nrhs);
     for (int r0 = 0; r0 < nrhs;) {
         int left = nrhs - r0;
         if (left >= 16) {
-            dispatch_d<T, C, 16>(X, m, Y, n, d, scale, c2, W, nrhs, r0, nsplit, cps, part.as<double>(), s);
+            dispatch_d<T, C, 16>(X, m, Y, n, d, scale, c2, W, nrhs, r0, nsplit, cps, part.as<double>(), s, bt, nb);
             r0 += 16;
         } else if (left >= 8) {
-            dispatch_d<T, C, 8>(X, m, Y, n, d, scale, c2, W, nrhs, r0, nsplit, cps, part.as<double>(), s);
+            dispatch_d<T, C, 8>(X, m, Y, n, d, scale, c2, W, nrhs, r0, nsplit, cps, part.as<double>(), s, bt, nb);
             r0 += 8;
         } else if (left >= 4) {
-            dispatch_d<T, C, 4>(X, m, Y, n, d, scale, c2, W, nrhs, r0, nsplit, cps, part.as<double>(), s);
+            dispatch_d<T, C, 4>(X, m, Y, n, d, scale, c2, W, nrhs, r0, nsplit, cps, part.as<double>(), s, bt, nb);
             r0 += 4;
         } else if (left >= 2) {
-            dispatch_d<T, C, 2>(X, m, Y, n, d, scale, c2, W, nrhs, r0, nsplit, cps, part.as<double>(), s);
+            dispatch_d<T, C, 2>(X, m, Y, n, d, scale, c2, W, nrhs, r0, nsplit, cps, part.as<double>(), s, bt, nb);
             r0 += 2;
         } else {
-            dispatch_d<T, C, 1>(X, m, Y, n, d, scale, c2, W, nrhs, r0, nsplit, cps, part.as<double>(), s);
+            dispatch_d<T, C, 1>(X, m, Y, n, d, scale, c2, W, nrhs, r0, nsplit, cps, part.as<double>(), s, bt, nb);
             r0 += 1;
         }
     }
@@ -296,8 +351,11 @@ void kmv_typed(const T *X, int64_t m, const T *Y, int64_t n, int d, double h, co
 }  // namespace
 
 void kernel_matvec_impl(const void *X, int64_t m, const void *Y, int64_t n, int d, int xprec, double h,
-                        const double *W, int nrhs, double beta, double *Out, int prec, hipStream_t s) {
+                        const double *W, int nrhs, double beta, double *Out, int prec, hipStream_t s,
+                        const Batch *batch) {
     if (m == 0) return;
+    if (batch && batch->np() == 1) batch = nullptr;  // one problem: the plain launch
+    KRR_REQUIRE(!batch || (X == Y && m == n), "kernel_matvec: a batch multiplies its own points");
     if (n == 0) {
         fail(KRR_E_INVAL, "kernel_matvec: n == 0");
     }
@@ -305,16 +363,16 @@ void kernel_matvec_impl(const void *X, int64_t m, const void *Y, int64_t n, int 
         auto Xd = static_cast<const double *>(X);
         auto Yd = static_cast<const double *>(Y);
         if (prec == KRR_F64)
-            kmv_typed<double, double>(Xd, m, Yd, n, d, h, W, nrhs, beta, Out, s);
+            kmv_typed<double, double>(Xd, m, Yd, n, d, h, W, nrhs, beta, Out, s, batch);
         else
-            kmv_typed<double, float>(Xd, m, Yd, n, d, h, W, nrhs, beta, Out, s);
+            kmv_typed<double, float>(Xd, m, Yd, n, d, h, W, nrhs, beta, Out, s, batch);
     } else {
         auto Xf = static_cast<const float *>(X);
         auto Yf = static_cast<const float *>(Y);
         if (prec == KRR_F64)
-            kmv_typed<float, double>(Xf, m, Yf, n, d, h, W, nrhs, beta, Out, s);
+            kmv_typed<float, double>(Xf, m, Yf, n, d, h, W, nrhs, beta, Out, s, batch);
         else
-            kmv_typed<float, float>(Xf, m, Yf, n, d, h, W, nrhs, beta, Out, s);
+            kmv_typed<float, float>(Xf, m, Yf, n, d, h, W, nrhs, beta, Out, s, batch);
     }
 }
 
@@ -329,11 +387,30 @@ template <class T, class C, class RT, class ST>
 __global__ __launch_bounds__(256) void k_sample_valu(const T *__restrict__ X, int64_t n, int d, C scale,
                                                      const RT *__restrict__ R, int r,
                                                      const int32_t *__restrict__ lb,
-                                                     const int32_t *__restrict__ le, ST *__restrict__ S) {
+                                                     const int32_t *__restrict__ le, ST *__restrict__ S,
+                                                     const SampBlock *__restrict__ bt) {
     __shared__ C es[SP_TK][SP_TM + 1];
     __shared__ C rs[SP_TK][SP_TR];
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-    const int64_t i0 = (int64_t)blockIdx.x * SP_TM;
+    // rows [i0, iend) against columns [jlo, jhi): the whole matrix, or one
+    // problem's diagonal block in a batch
+    int64_t i0, iend, jlo, jhi;
+    if (bt) {
+        const SampBlock sb = bt[blockIdx.x];
+        i0 = sb.i0;
+        iend = sb.iend;
+        jlo = sb.jlo;
+        jhi = sb.jhi;
+        if constexpr (sizeof(C) == 8)
+            scale = sb.inv;
+        else
+            scale = sb.cs;
+    } else {
+        i0 = (int64_t)blockIdx.x * SP_TM;
+        iend = n;
+        jlo = 0;
+        jhi = n;
+    }
     const int c0 = blockIdx.y * SP_TR;
     C acc[4][4];
 #pragma unroll
@@ -343,15 +420,15 @@ __global__ __launch_bounds__(256) void k_sample_valu(const T *__restrict__ X, in
     // the entry this thread evaluates in each E tile: row er, column ej
     const int er = tid & 63, ej = tid >> 6;  // 64 rows x 4 column groups (4 entries each)
     const int64_t gi = i0 + er;
-    const bool row_ok = gi < n;
+    const bool row_ok = gi < iend;
     const int32_t my_lb = row_ok && lb ? lb[gi] : 0, my_le = row_ok && le ? le[gi] : 0;
-    for (int64_t jt = 0; jt < n; jt += SP_TK) {
+    for (int64_t jt = jlo; jt < jhi; jt += SP_TK) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             int jj = ej * 4 + u;
             int64_t j = jt + jj;
             C v = (C)0;
-            if (row_ok && j < n && !(j >= my_lb && j < my_le)) {
+            if (row_ok && j < jhi && !(j >= my_lb && j < my_le)) {
                 C q = (C)0;
                 for (int k = 0; k < d; ++k) {
                     C t = (C)X[gi * d + k] - (C)X[j * d + k];
@@ -364,7 +441,7 @@ __global__ __launch_bounds__(256) void k_sample_valu(const T *__restrict__ X, in
         for (int t = tid; t < SP_TK * SP_TR; t += 256) {
             int jj = t / SP_TR, c = t % SP_TR;
             int64_t j = jt + jj;
-            rs[jj][c] = (j < n && c0 + c < r) ? (C)R[j * r + c0 + c] : (C)0;
+            rs[jj][c] = (j < jhi && c0 + c < r) ? (C)R[j * r + c0 + c] : (C)0;
         }
         __syncthreads();
 #pragma unroll
@@ -384,7 +461,7 @@ __global__ __launch_bounds__(256) void k_sample_valu(const T *__restrict__ X, in
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
         int64_t i = i0 + 4 * ty + a;
-        if (i >= n) continue;
+        if (i >= iend) continue;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             int c = c0 + 4 * tx + b;
@@ -395,26 +472,36 @@ __global__ __launch_bounds__(256) void k_sample_valu(const T *__restrict__ X, in
 }  // namespace
 
 void sample_valu(const void *X, int64_t n, int d, int xprec, double h, const float *R, int r,
-                 const int32_t *lb, const int32_t *le, void *S, int prec, hipStream_t s) {
-    dim3 grid(ceil_div(n, SP_TM), ceil_div(r, SP_TR));
+                 const int32_t *lb, const int32_t *le, void *S, int prec, hipStream_t s, const Batch *batch) {
+    DBuf btab;
+    int64_t nb = ceil_div(n, SP_TM);
+    if (batch) {
+        std::vector<SampBlock> blocks = row_blocks(*batch, SP_TM);
+        nb = (int64_t)blocks.size();
+        btab = upload(blocks, s);
+        sync(s);
+    }
+    const SampBlock *bt = btab.as<SampBlock>();
+    dim3 grid((unsigned)nb, ceil_div(r, SP_TR));
     if (prec == KRR_F64) {
         double sc = kernel_scale<double>(h);
         if (xprec == KRR_F64)
             k_sample_valu<double, double, float, double><<<grid, 256, 0, s>>>(
-                static_cast<const double *>(X), n, d, sc, R, r, lb, le, static_cast<double *>(S));
+                static_cast<const double *>(X), n, d, sc, R, r, lb, le, static_cast<double *>(S), bt);
         else
             k_sample_valu<float, double, float, double><<<grid, 256, 0, s>>>(
-                static_cast<const float *>(X), n, d, sc, R, r, lb, le, static_cast<double *>(S));
+                static_cast<const float *>(X), n, d, sc, R, r, lb, le, static_cast<double *>(S), bt);
     } else {
         float sc = kernel_scale<float>(h);
         if (xprec == KRR_F64)
             k_sample_valu<double, float, float, float><<<grid, 256, 0, s>>>(
-                static_cast<const double *>(X), n, d, sc, R, r, lb, le, static_cast<float *>(S));
+                static_cast<const double *>(X), n, d, sc, R, r, lb, le, static_cast<float *>(S), bt);
         else
             k_sample_valu<float, float, float, float><<<grid, 256, 0, s>>>(
-                static_cast<const float *>(X), n, d, sc, R, r, lb, le, static_cast<float *>(S));
+                static_cast<const float *>(X), n, d, sc, R, r, lb, le, static_cast<float *>(S), bt);
     }
     check_launch("k_sample_valu");
+    sync(s);  // the block table is released on return
 }
 
 // ------------------------------------------------------------ helpers

@@ -11,33 +11,64 @@
 
 namespace krr {
 
-void kernel_matvec_impl(const void *X, int64_t m, const void *Y, int64_t n, int d, int xprec, double h,
-                        const double *W, int nrhs, double beta, double *Out, int prec, hipStream_t s);
-void dot_columns(const double *a, const double *b, int64_t n, int k, double *out, DBuf &scratch, hipStream_t s);
-void ulv_solve(const hss_ulv_s *F, const double *Bin, int nrhs, double *Xout, hipStream_t s);
 
 namespace {
 
+// Per-row problem index of a batch (nullptr: one problem).  Coefficients are
+// stored per (problem, right-hand side): coef[p * k + c].
+__device__ __forceinline__ int prob_of(const int32_t *pid, int64_t i) { return pid ? pid[i] : 0; }
+
 // r = Y - Kx - lambda x
 __global__ void k_residual(const double *__restrict__ Y, const double *__restrict__ Kx, const double *__restrict__ x,
-                           double lambda, int64_t len, double *__restrict__ r) {
+                           const double *__restrict__ lam, const int32_t *__restrict__ pid, int64_t n, int k,
+                           double *__restrict__ r) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < len) r[t] = Y[t] - Kx[t] - lambda * x[t];
+    if (t < n * k) r[t] = Y[t] - Kx[t] - lam[prob_of(pid, t / k)] * x[t];
 }
 
-// y[:, c] = a[c] * x[:, c] + b[c] * y[:, c]
+// y[:, c] = a[p, c] * x[:, c] + b[p, c] * y[:, c]
 __global__ void k_axpby(const double *__restrict__ a, const double *__restrict__ x, const double *__restrict__ b,
-                        double *__restrict__ y, int64_t n, int k) {
+                        double *__restrict__ y, const int32_t *__restrict__ pid, int64_t n, int k) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n * k) return;
-    int c = (int)(t % k);
-    y[t] = a[c] * x[t] + b[c] * y[t];
+    const int c = (int)(t % k);
+    const int64_t ci = (int64_t)prob_of(pid, t / k) * k + c;
+    y[t] = a[ci] * x[t] + b[ci] * y[t];
 }
 
 // q = Kp + lambda p (in place on Kp)
-__global__ void k_add_shift(double *__restrict__ Kp, const double *__restrict__ p, double lambda, int64_t len) {
+__global__ void k_add_shift(double *__restrict__ Kp, const double *__restrict__ p, const double *__restrict__ lam,
+                            const int32_t *__restrict__ pid, int64_t n, int k) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < len) Kp[t] += lambda * p[t];
+    if (t < n * k) Kp[t] += lam[prob_of(pid, t / k)] * p[t];
+}
+
+// Segmented column dots: out[p * k + c] = sum over rows of problem p of a b
+// (one workgroup per (problem, column); rows in order, FP64).
+__global__ __launch_bounds__(256) void k_seg_dot(const double *__restrict__ a, const double *__restrict__ b,
+                                                 const int64_t *__restrict__ pbeg, int k, double *__restrict__ out) {
+    __shared__ double red[4];
+    const int p = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
+    double acc = 0.0;
+    for (int64_t i = pbeg[p] + tid; i < pbeg[p + 1]; i += 256) acc += a[i * k + c] * b[i * k + c];
+    acc = wave_sum(acc);
+    if ((tid & 63) == 0) red[tid >> 6] = acc;
+    __syncthreads();
+    if (tid == 0) out[(int64_t)p * k + c] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ void k_fill_pid(const int64_t *__restrict__ pbeg, int np, int64_t n, int32_t *__restrict__ pid) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int lo = 0, hi = np - 1;  // last p with pbeg[p] <= i
+    while (lo < hi) {
+        int mid = (lo + hi + 1) / 2;
+        if (pbeg[mid] <= i)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    pid[i] = lo;
 }
 
 __global__ void k_labels(const double *__restrict__ S, int64_t m, int k, int32_t *__restrict__ lab) {
@@ -57,26 +88,40 @@ __global__ void k_labels(const double *__restrict__ S, int64_t m, int k, int32_t
     lab[i] = best;
 }
 
-void axpby(const std::vector<double> &a, const double *x, const std::vector<double> &b, double *y, int64_t n, int k,
-           DBuf &coef, hipStream_t s) {
-    std::vector<double> ab(a);
-    ab.insert(ab.end(), b.begin(), b.end());
-    coef.reserve(sizeof(double) * 2 * k);
-    h2d(coef.as<double>(), ab.data(), 2 * k, s);
-    k_axpby<<<ceil_div(n * k, 256), 256, 0, s>>>(coef.as<double>(), x, coef.as<double>() + k, y, n, k);
-    check_launch("k_axpby");
-    sync(s);  // `ab` is released on return
-}
+// The problems of a solve: one (plain column dots) or a batch (segmented).
+struct Segs {
+    int np = 1;
+    int64_t n = 0;
+    int k = 1;
+    DBuf pbeg, pid, lam, coef, out, scratch;
 
-std::vector<double> dots(const double *a, const double *b, int64_t n, int k, DBuf &out, DBuf &scratch,
-                         hipStream_t s) {
-    out.reserve(sizeof(double) * k);
-    dot_columns(a, b, n, k, out.as<double>(), scratch, s);
-    std::vector<double> h(k);
-    d2h(h.data(), out.as<double>(), k, s);
-    sync(s);
-    return h;
-}
+    std::vector<double> dots(const double *a, const double *b, hipStream_t s) {
+        const size_t cnt = (size_t)np * k;
+        out.reserve(sizeof(double) * cnt);
+        if (np == 1) {
+            dot_columns(a, b, n, k, out.as<double>(), scratch, s);
+        } else {
+            k_seg_dot<<<dim3(np, k), 256, 0, s>>>(a, b, pbeg.as<int64_t>(), k, out.as<double>());
+            check_launch("k_seg_dot");
+        }
+        std::vector<double> h(cnt);
+        d2h(h.data(), out.as<double>(), cnt, s);
+        sync(s);
+        return h;
+    }
+    // y = a x + b y with per-(problem, column) coefficients
+    void axpby(const std::vector<double> &a, const double *x, const std::vector<double> &b, double *y, hipStream_t s) {
+        const size_t cnt = (size_t)np * k;
+        std::vector<double> ab(a);
+        ab.insert(ab.end(), b.begin(), b.end());
+        coef.reserve(sizeof(double) * 2 * cnt);
+        h2d(coef.as<double>(), ab.data(), 2 * cnt, s);
+        k_axpby<<<ceil_div(n * k, 256), 256, 0, s>>>(coef.as<double>(), x, coef.as<double>() + cnt, y,
+                                                     pid.as<int32_t>(), n, k);
+        check_launch("k_axpby");
+        sync(s);  // `ab` is released on return
+    }
+};
 
 }  // namespace
 
@@ -87,11 +132,29 @@ void predict_labels(const double *scores, int64_t m, int k, int32_t *labels, hip
 }
 
 int refine(const hss_ulv_s *F, int64_t n, const void *Xp, int xprec, int d, double h, double lambda, const double *Y,
-           int nrhs, double *alpha, double tol, int max_iter, int mv_prec, hipStream_t s, krr_refine_stats *st) {
+           int nrhs, double *alpha, double tol, int max_iter, int mv_prec, hipStream_t s, krr_refine_stats *st,
+           const Batch *batch, double *relres_all) {
     EventTimer timer(s);
     const int64_t len = n * nrhs;
+    Segs sg;
+    sg.n = n;
+    sg.k = nrhs;
+    std::vector<double> lam_h(1, lambda);
+    if (batch && batch->np() > 1) {
+        sg.np = batch->np();
+        lam_h = batch->lam;
+        sg.pbeg = upload(batch->pbeg, s);
+        sg.pid = dalloc<int32_t>(n);
+        k_fill_pid<<<ceil_div(n, 256), 256, 0, s>>>(sg.pbeg.as<int64_t>(), sg.np, n, sg.pid.as<int32_t>());
+        check_launch("k_fill_pid");
+    } else if (batch) {
+        lam_h = batch->lam;
+        h = batch->h[0];
+        batch = nullptr;
+    }
+    sg.lam = upload(lam_h, s);
+    const int np = sg.np, cnt = np * nrhs;
     DBuf r = dalloc<double>(len), z = dalloc<double>(len), p = dalloc<double>(len), q = dalloc<double>(len);
-    DBuf dout, scratch, coef;
     auto precond = [&](const double *in, double *out) {
         if (F)
             ulv_solve(F, in, nrhs, out, s);
@@ -99,19 +162,23 @@ int refine(const hss_ulv_s *F, int64_t n, const void *Xp, int xprec, int d, doub
             KRR_HIP(hipMemcpyAsync(out, in, sizeof(double) * len, hipMemcpyDeviceToDevice, s));
     };
     int matvecs = 0;
-    auto true_residual = [&]() {
-        kernel_matvec_impl(Xp, n, Xp, n, d, xprec, h, alpha, nrhs, 0.0, q.as<double>(), mv_prec, s);
+    auto matvec = [&](const double *x, double *out) {
+        kernel_matvec_impl(Xp, n, Xp, n, d, xprec, h, x, nrhs, 0.0, out, mv_prec, s, batch);
         ++matvecs;
-        k_residual<<<ceil_div(len, 256), 256, 0, s>>>(Y, q.as<double>(), alpha, lambda, len, r.as<double>());
+    };
+    auto true_residual = [&]() {
+        matvec(alpha, q.as<double>());
+        k_residual<<<ceil_div(len, 256), 256, 0, s>>>(Y, q.as<double>(), alpha, sg.lam.as<double>(),
+                                                      sg.pid.as<int32_t>(), n, nrhs, r.as<double>());
         check_launch("k_residual");
     };
-    std::vector<double> ynorm = dots(Y, Y, n, nrhs, dout, scratch, s);
+    std::vector<double> ynorm = sg.dots(Y, Y, s);
     for (auto &v : ynorm) v = std::sqrt(v) > 0 ? std::sqrt(v) : 1.0;
     true_residual();
-    std::vector<double> rr = dots(r.as<double>(), r.as<double>(), n, nrhs, dout, scratch, s);
+    std::vector<double> rr = sg.dots(r.as<double>(), r.as<double>(), s);
     auto rel = [&](const std::vector<double> &v) {
-        std::vector<double> o(nrhs);
-        for (int c = 0; c < nrhs; ++c) o[c] = std::sqrt(std::max(v[c], 0.0)) / ynorm[c];
+        std::vector<double> o(cnt);
+        for (int c = 0; c < cnt; ++c) o[c] = std::sqrt(std::max(v[c], 0.0)) / ynorm[c];
         return o;
     };
     auto all_below = [&](const std::vector<double> &v) {
@@ -126,52 +193,63 @@ int refine(const hss_ulv_s *F, int64_t n, const void *Xp, int xprec, int d, doub
         // (re)start: z = M^{-1} r, p = z
         precond(r.as<double>(), z.as<double>());
         KRR_HIP(hipMemcpyAsync(p.get(), z.get(), sizeof(double) * len, hipMemcpyDeviceToDevice, s));
-        std::vector<double> rz = dots(r.as<double>(), z.as<double>(), n, nrhs, dout, scratch, s);
-        std::vector<bool> done(nrhs);
-        for (int c = 0; c < nrhs; ++c) done[c] = relres[c] <= tol;
+        std::vector<double> rz = sg.dots(r.as<double>(), z.as<double>(), s);
+        std::vector<bool> done(cnt);
+        for (int c = 0; c < cnt; ++c) done[c] = relres[c] <= tol;
         while (it < max_iter) {
             ++it;
-            kernel_matvec_impl(Xp, n, Xp, n, d, xprec, h, p.as<double>(), nrhs, 0.0, q.as<double>(), mv_prec, s);
-            ++matvecs;
-            k_add_shift<<<ceil_div(len, 256), 256, 0, s>>>(q.as<double>(), p.as<double>(), lambda, len);
+            matvec(p.as<double>(), q.as<double>());
+            k_add_shift<<<ceil_div(len, 256), 256, 0, s>>>(q.as<double>(), p.as<double>(), sg.lam.as<double>(),
+                                                           sg.pid.as<int32_t>(), n, nrhs);
             check_launch("k_add_shift");
-            std::vector<double> pq = dots(p.as<double>(), q.as<double>(), n, nrhs, dout, scratch, s);
-            std::vector<double> a(nrhs), one(nrhs, 1.0), ma(nrhs);
-            for (int c = 0; c < nrhs; ++c) {
+            std::vector<double> pq = sg.dots(p.as<double>(), q.as<double>(), s);
+            std::vector<double> a(cnt), one(cnt, 1.0), ma(cnt);
+            for (int c = 0; c < cnt; ++c) {
                 a[c] = (done[c] || pq[c] <= 0.0) ? 0.0 : rz[c] / pq[c];
                 ma[c] = -a[c];
             }
-            axpby(a, p.as<double>(), one, alpha, n, nrhs, coef, s);        // alpha += a p
-            axpby(ma, q.as<double>(), one, r.as<double>(), n, nrhs, coef, s); // r -= a q
-            rr = dots(r.as<double>(), r.as<double>(), n, nrhs, dout, scratch, s);
+            sg.axpby(a, p.as<double>(), one, alpha, s);         // alpha += a p
+            sg.axpby(ma, q.as<double>(), one, r.as<double>(), s); // r -= a q
+            rr = sg.dots(r.as<double>(), r.as<double>(), s);
             std::vector<double> rec = rel(rr);
-            if (verbose()) fprintf(stderr, "[krr] refine it=%d relres(recurrence)=%.3e\n", it, rec[0]);
+            if (verbose()) {
+                double mx = 0;
+                for (double v : rec) mx = std::max(mx, v);
+                fprintf(stderr, "[krr] refine it=%d relres(recurrence, max)=%.3e\n", it, mx);
+            }
             bool stop = true;
-            for (int c = 0; c < nrhs; ++c) {
+            for (int c = 0; c < cnt; ++c) {
                 if (rec[c] <= 0.5 * tol) done[c] = true;
                 stop = stop && done[c];
             }
             if (stop) break;
             precond(r.as<double>(), z.as<double>());
-            std::vector<double> rz2 = dots(r.as<double>(), z.as<double>(), n, nrhs, dout, scratch, s);
-            std::vector<double> beta(nrhs);
-            for (int c = 0; c < nrhs; ++c) {
+            std::vector<double> rz2 = sg.dots(r.as<double>(), z.as<double>(), s);
+            std::vector<double> beta(cnt);
+            for (int c = 0; c < cnt; ++c) {
                 beta[c] = (done[c] || rz[c] == 0.0) ? 0.0 : rz2[c] / rz[c];
                 rz[c] = rz2[c];
             }
-            axpby(one, z.as<double>(), beta, p.as<double>(), n, nrhs, coef, s);  // p = z + beta p
+            sg.axpby(one, z.as<double>(), beta, p.as<double>(), s);  // p = z + beta p
         }
         // confirm on the true residual; restart from it if the recurrence drifted
         true_residual();
-        rr = dots(r.as<double>(), r.as<double>(), n, nrhs, dout, scratch, s);
+        rr = sg.dots(r.as<double>(), r.as<double>(), s);
         relres = rel(rr);
         converged = all_below(relres);
         if (verbose()) fprintf(stderr, "[krr] refine it=%d true relres=%.3e\n", it, relres[0]);
     }
+    if (relres_all) std::copy(relres.begin(), relres.end(), relres_all);
     if (st) {
         st->iterations = it;
         st->matvecs = matvecs;
-        for (int c = 0; c < 64; ++c) st->relres[c] = c < nrhs ? relres[c] : 0.0;
+        // per right-hand side: the largest relative residual over the problems
+        for (int c = 0; c < 64; ++c) {
+            double mx = 0.0;
+            if (c < nrhs)
+                for (int pp = 0; pp < np; ++pp) mx = std::max(mx, relres[(size_t)pp * nrhs + c]);
+            st->relres[c] = mx;
+        }
         st->t_ms = timer.stop_ms();
     }
     sync(s);

@@ -100,19 +100,20 @@ template <> struct Op<M_BF16> {
 };
 
 template <class T, int D, int YS = YTile<D>::N>
-__device__ __forceinline__ void stage_y(const T *__restrict__ X, int64_t n, int d, int64_t j0, const float *anchor,
-                                        float cs, float (*ys)[D + 1]) {
-    // ys[p][0..D) = y' = y - a, ys[p][D] = -c |y'|^2 (or -inf past the end)
+__device__ __forceinline__ void stage_y(const T *__restrict__ X, int64_t jlo, int64_t jhi, int d, int64_t j0,
+                                        const float *anchor, float cs, float (*ys)[D + 1]) {
+    // ys[p][0..D) = y' = y - a, ys[p][D] = -c |y'|^2 (or -inf outside the columns [jlo, jhi))
     for (int p = threadIdx.x; p < YS; p += THREADS) {
         int64_t j = j0 + p;
+        const bool ok = j >= jlo && j < jhi;
         float nrm = 0.0f;
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-            float v = (j < n && k < d) ? (float)X[j * d + k] - anchor[k] : 0.0f;
+            float v = (ok && k < d) ? (float)X[j * d + k] - anchor[k] : 0.0f;
             ys[p][k] = v;
             nrm = fmaf(v, v, nrm);
         }
-        ys[p][D] = j < n ? -cs * nrm : -INFINITY;
+        ys[p][D] = ok ? -cs * nrm : -INFINITY;
     }
 }
 
@@ -126,22 +127,23 @@ __device__ __forceinline__ float entry(const float *xs, float nx, const float (*
 }
 
 // Augmented points for the distance product: row p of ya holds
-// (y'_1 .. y'_D, 1, -c |y'_p|^2) (zero past the end of the data, where the
-// last entry is -inf so that the kernel value is exactly 0).
+// (y'_1 .. y'_D, 1, -c |y'_p|^2) (zero outside the columns [jlo, jhi), where
+// the last entry is -inf so that the kernel value is exactly 0).
 template <class T, int D, int YS>
-__device__ __forceinline__ void stage_ya(const T *__restrict__ X, int64_t n, int d, int64_t j0, const float *anchor,
-                                         float cs, float (*ya)[D + 3]) {
+__device__ __forceinline__ void stage_ya(const T *__restrict__ X, int64_t jlo, int64_t jhi, int d, int64_t j0,
+                                         const float *anchor, float cs, float (*ya)[D + 3]) {
     for (int p = threadIdx.x; p < YS; p += THREADS) {
         int64_t j = j0 + p;
+        const bool ok = j >= jlo && j < jhi;
         float nrm = 0.0f;
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-            float v = (j < n && k < d) ? (float)X[j * d + k] - anchor[k] : 0.0f;
+            float v = (ok && k < d) ? (float)X[j * d + k] - anchor[k] : 0.0f;
             ya[p][k] = v;
             nrm = fmaf(v, v, nrm);
         }
         ya[p][D] = 1.0f;
-        ya[p][D + 1] = j < n ? -cs * nrm : -INFINITY;
+        ya[p][D + 1] = ok ? -cs * nrm : -INFINITY;
     }
 }
 
@@ -283,7 +285,8 @@ template <class T, int D, int RB, int MODE, int TERMS>
 __global__ __launch_bounds__(THREADS) void k_sample_mfma(const T *__restrict__ X, int64_t n, int d, float cs,
                                                          const void *__restrict__ Rsw_, int RBt, int cb0,
                                                          const int32_t *__restrict__ lb, const int32_t *__restrict__ le,
-                                                         float *__restrict__ S, int ldS) {
+                                                         float *__restrict__ S, int ldS,
+                                                         const SampBlock *__restrict__ bt) {
     constexpr int OPM = MODE == M_F32 ? M_F16 : MODE;
     typedef typename Op<OPM>::V V;
     constexpr int RTILE_H = RB * 2 * 64 * 8;
@@ -301,9 +304,24 @@ __global__ __launch_bounds__(THREADS) void k_sample_mfma(const T *__restrict__ X
     float(*const ysh[2])[D + 1] = {ysh0, ysh1};
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 5;
-    const int64_t i0 = (int64_t)blockIdx.x * ROWS;
+    // rows [i0, iend) against columns [jlo, jhi): the whole matrix, or one
+    // problem's diagonal block in a batch
+    int64_t i0, iend, jlo, jhi;
+    if (bt) {
+        const SampBlock sb = bt[blockIdx.x];
+        i0 = sb.i0;
+        iend = sb.iend;
+        jlo = sb.jlo;
+        jhi = sb.jhi;
+        cs = sb.cs;
+    } else {
+        i0 = (int64_t)blockIdx.x * ROWS;
+        iend = n;
+        jlo = 0;
+        jhi = n;
+    }
     const int64_t i = i0 + 32 * w + (lane & 31);
-    const bool row_ok = i < n;
+    const bool row_ok = i < iend;
     if (tid < D) anchor[tid] = (tid < d) ? (float)X[i0 * d + tid] : 0.0f;
     __syncthreads();
     float xs[D];
@@ -330,7 +348,8 @@ __global__ __launch_bounds__(THREADS) void k_sample_mfma(const T *__restrict__ X
         wle = max(wle, __shfl_xor(wle, o, 64));
     }
 
-    const int64_t tiles = (n + JT - 1) / JT;
+    const int64_t t_lo = jlo / JT, t_hi = (jhi + JT - 1) / JT, s0 = t_lo / SUPER;
+    const int t_lo_off = (int)((t_lo * JT) % YS);
     const char *Rg = static_cast<const char *>(Rsw_);
     const int64_t tile_stride_b = (int64_t)RBt * (RTILE_B / RB);
     const int64_t cb_off_b = (int64_t)cb0 * (RTILE_B / RB);
@@ -362,11 +381,15 @@ __global__ __launch_bounds__(THREADS) void k_sample_mfma(const T *__restrict__ X
 #pragma unroll
         for (int q = 0; q < 16; ++q) acc[c][q] = 0.0f;
 
-    // prologue: R tile 0 in LDS, R tile 1 in flight (Y tiles per mode below)
-    if constexpr (MODE == M_F32) stage_y<T, D>(X, n, d, 0, anchor, cs, ysh[0]);
-    KRR_LOAD_R(0);
-    KRR_STORE_R(0);
-    KRR_LOAD_R(1);
+    // prologue: R tile t_lo in LDS, R tile t_lo + 1 in flight; Y super-tiles
+    // s0 and s0 + 1 staged (the loop stages each later one a super-tile ahead)
+    if constexpr (MODE == M_F32) {
+        stage_y<T, D>(X, jlo, jhi, d, s0 * YS, anchor, cs, ysh[s0 & 1]);
+        stage_y<T, D>(X, jlo, jhi, d, (s0 + 1) * YS, anchor, cs, ysh[(s0 + 1) & 1]);
+    }
+    KRR_LOAD_R(t_lo);
+    KRR_STORE_R(t_lo & 1);
+    KRR_LOAD_R(t_lo + 1);
     __syncthreads();
 
     // the padded random block has two zero tiles past the end, so every
@@ -375,15 +398,15 @@ __global__ __launch_bounds__(THREADS) void k_sample_mfma(const T *__restrict__ X
 #define KRR_TILE_MASKED(tt) ((int64_t)(tt) * JT < (int64_t)wle && (int64_t)(tt) * JT + JT > (int64_t)wlb)
     if constexpr (MODE == M_F32) {
         float a0[16], a1[16];
-        make_f<D>(a0, xs, nx, ysh[0], 0, g, 0, my_lb, my_le);
-        for (int64_t t = 0; t < tiles; t += 2) {
+        make_f<D>(a0, xs, nx, ysh[s0 & 1], t_lo_off, g, t_lo * JT, my_lb, my_le);
+        for (int64_t t = t_lo; t < t_hi; t += 2) {
 #pragma unroll
             for (int half = 0; half < 2; ++half) {
                 const int64_t tc = t + half;
-                if (half == 1 && tc >= tiles) break;
-                if (tc % SUPER == 0) {
+                if (half == 1 && tc >= t_hi) break;
+                if (tc % SUPER == 0 && tc != t_lo) {
                     const int64_t sup = tc / SUPER + 1;
-                    stage_y<T, D>(X, n, d, sup * YS, anchor, cs, ysh[sup & 1]);
+                    stage_y<T, D>(X, jlo, jhi, d, sup * YS, anchor, cs, ysh[sup & 1]);
                 }
                 const int64_t tn = tc + 1;
                 const float(*ysn)[D + 1] = ysh[(tn / SUPER) & 1];
@@ -410,24 +433,25 @@ __global__ __launch_bounds__(THREADS) void k_sample_mfma(const T *__restrict__ X
         // augmented Y tiles replace the plain ones in this mode
         float(*ya0)[D + 3] = reinterpret_cast<float(*)[D + 3]>(&yab[0][0][0]);
         float(*ya1)[D + 3] = reinterpret_cast<float(*)[D + 3]>(&yab[1][0][0]);
-        stage_ya<T, D, YS>(X, n, d, 0, anchor, cs, ya0);
+        stage_ya<T, D, YS>(X, jlo, jhi, d, s0 * YS, anchor, cs, (s0 & 1) ? ya1 : ya0);
+        stage_ya<T, D, YS>(X, jlo, jhi, d, (s0 + 1) * YS, anchor, cs, (s0 & 1) ? ya0 : ya1);
         __syncthreads();
         V h0[2], l0[2], h1[2], l1[2];
         {
-            f16v t0 = dist_mfma<D>(xa, ya0, 0, lane);
-            if (KRR_TILE_MASKED(0))
-                exp_split<MODE, TERMS, true>(h0, l0, t0, g, 0, my_lb, my_le);
+            f16v t0 = dist_mfma<D>(xa, (s0 & 1) ? ya1 : ya0, t_lo_off, lane);
+            if (KRR_TILE_MASKED(t_lo))
+                exp_split<MODE, TERMS, true>(h0, l0, t0, g, t_lo * JT, my_lb, my_le);
             else
-                exp_split<MODE, TERMS, false>(h0, l0, t0, g, 0, my_lb, my_le);
+                exp_split<MODE, TERMS, false>(h0, l0, t0, g, t_lo * JT, my_lb, my_le);
         }
-        for (int64_t t = 0; t < tiles; t += 2) {
+        for (int64_t t = t_lo; t < t_hi; t += 2) {
 #pragma unroll
             for (int half = 0; half < 2; ++half) {
                 const int64_t tc = t + half;
-                if (half == 1 && tc >= tiles) break;
-                if (tc % SUPER == 0) {
+                if (half == 1 && tc >= t_hi) break;
+                if (tc % SUPER == 0 && tc != t_lo) {
                     const int64_t sup = tc / SUPER + 1;
-                    stage_ya<T, D, YS>(X, n, d, sup * YS, anchor, cs, (sup & 1) ? ya1 : ya0);
+                    stage_ya<T, D, YS>(X, jlo, jhi, d, sup * YS, anchor, cs, (sup & 1) ? ya1 : ya0);
                 }
                 const int64_t tn = tc + 1;
                 const float(*yan)[D + 3] = ((tn / SUPER) & 1) ? ya1 : ya0;
@@ -467,7 +491,7 @@ __global__ __launch_bounds__(THREADS) void k_sample_mfma(const T *__restrict__ X
         for (int q = 0; q < 16; ++q) {
             const int m = 8 * (q >> 2) + 4 * g + (q & 3);
             const int64_t row = i0 + 32 * w + m;
-            if (row < n) S[row * ldS + 32 * (cb0 + c) + (lane & 31)] = acc[c][q] * kInvScale;
+            if (row < iend) S[row * ldS + 32 * (cb0 + c) + (lane & 31)] = acc[c][q] * kInvScale;
         }
 #undef KRR_TILE_MASKED
 #undef KRR_LOAD_R
@@ -483,26 +507,26 @@ template <int D, int MODE> struct RbMax {
 
 template <class T, int D, int MODE, int TERMS>
 void launch_passes(const T *X, int64_t n, int d, float cs, const void *Rsw, int r, const int32_t *lb,
-                   const int32_t *le, float *S, hipStream_t s) {
+                   const int32_t *le, float *S, hipStream_t s, const SampBlock *bt, int64_t nblk) {
     constexpr int RBM = RbMax<D, MODE>::V;
     const int RBt = r / 32;
     int cb0 = 0;
     while (cb0 < RBt) {
         const int left = RBt - cb0;
-        dim3 grid(ceil_div(n, ROWS));
+        dim3 grid((unsigned)(bt ? nblk : ceil_div(n, ROWS)));
         if (RBM >= 8 && left >= 8) {
             k_sample_mfma<T, D, (RBM >= 8 ? 8 : RBM), MODE, TERMS><<<grid, THREADS, 0, s>>>(X, n, d, cs, Rsw, RBt, cb0,
-                                                                                        lb, le, S, r);
+                                                                                        lb, le, S, r, bt);
             cb0 += 8;
         } else if (RBM >= 4 && left >= 4) {
             k_sample_mfma<T, D, (RBM >= 4 ? 4 : RBM), MODE, TERMS><<<grid, THREADS, 0, s>>>(X, n, d, cs, Rsw, RBt, cb0,
-                                                                                        lb, le, S, r);
+                                                                                        lb, le, S, r, bt);
             cb0 += 4;
         } else if (left >= 2) {
-            k_sample_mfma<T, D, 2, MODE, TERMS><<<grid, THREADS, 0, s>>>(X, n, d, cs, Rsw, RBt, cb0, lb, le, S, r);
+            k_sample_mfma<T, D, 2, MODE, TERMS><<<grid, THREADS, 0, s>>>(X, n, d, cs, Rsw, RBt, cb0, lb, le, S, r, bt);
             cb0 += 2;
         } else {
-            k_sample_mfma<T, D, 1, MODE, TERMS><<<grid, THREADS, 0, s>>>(X, n, d, cs, Rsw, RBt, cb0, lb, le, S, r);
+            k_sample_mfma<T, D, 1, MODE, TERMS><<<grid, THREADS, 0, s>>>(X, n, d, cs, Rsw, RBt, cb0, lb, le, S, r, bt);
             cb0 += 1;
         }
         check_launch("k_sample_mfma");
@@ -511,28 +535,28 @@ void launch_passes(const T *X, int64_t n, int d, float cs, const void *Rsw, int 
 
 template <class T, int D>
 void dispatch_mode(const T *X, int64_t n, int d, float cs, const void *Rsw, int r, const int32_t *lb, const int32_t *le,
-                   float *S, int prec, int split, hipStream_t s) {
+                   float *S, int prec, int split, hipStream_t s, const SampBlock *bt, int64_t nb) {
     if (prec == KRR_F32)
-        launch_passes<T, D, M_F32, 1>(X, n, d, cs, Rsw, r, lb, le, S, s);
+        launch_passes<T, D, M_F32, 1>(X, n, d, cs, Rsw, r, lb, le, S, s, bt, nb);
     else if (prec == KRR_F16_SPLIT)
-        split == 2 ? launch_passes<T, D, M_F16, 2>(X, n, d, cs, Rsw, r, lb, le, S, s)
-                   : launch_passes<T, D, M_F16, 1>(X, n, d, cs, Rsw, r, lb, le, S, s);
+        split == 2 ? launch_passes<T, D, M_F16, 2>(X, n, d, cs, Rsw, r, lb, le, S, s, bt, nb)
+                   : launch_passes<T, D, M_F16, 1>(X, n, d, cs, Rsw, r, lb, le, S, s, bt, nb);
     else
-        split == 2 ? launch_passes<T, D, M_BF16, 2>(X, n, d, cs, Rsw, r, lb, le, S, s)
-                   : launch_passes<T, D, M_BF16, 1>(X, n, d, cs, Rsw, r, lb, le, S, s);
+        split == 2 ? launch_passes<T, D, M_BF16, 2>(X, n, d, cs, Rsw, r, lb, le, S, s, bt, nb)
+                   : launch_passes<T, D, M_BF16, 1>(X, n, d, cs, Rsw, r, lb, le, S, s, bt, nb);
 }
 
 template <class T>
 void dispatch_d(const T *X, int64_t n, int d, float cs, const void *Rsw, int r, const int32_t *lb, const int32_t *le,
-                float *S, int prec, int split, hipStream_t s) {
+                float *S, int prec, int split, hipStream_t s, const SampBlock *bt, int64_t nb) {
     if (d <= 8)
-        dispatch_mode<T, 8>(X, n, d, cs, Rsw, r, lb, le, S, prec, split, s);
+        dispatch_mode<T, 8>(X, n, d, cs, Rsw, r, lb, le, S, prec, split, s, bt, nb);
     else if (d <= 16)
-        dispatch_mode<T, 16>(X, n, d, cs, Rsw, r, lb, le, S, prec, split, s);
+        dispatch_mode<T, 16>(X, n, d, cs, Rsw, r, lb, le, S, prec, split, s, bt, nb);
     else if (d <= 32)
-        dispatch_mode<T, 32>(X, n, d, cs, Rsw, r, lb, le, S, prec, split, s);
+        dispatch_mode<T, 32>(X, n, d, cs, Rsw, r, lb, le, S, prec, split, s, bt, nb);
     else
-        dispatch_mode<T, 64>(X, n, d, cs, Rsw, r, lb, le, S, prec, split, s);
+        dispatch_mode<T, 64>(X, n, d, cs, Rsw, r, lb, le, S, prec, split, s, bt, nb);
 }
 
 }  // namespace
@@ -543,7 +567,7 @@ bool sample_mfma_supported(int d, int prec) { return prec != KRR_F64 && d <= kSa
 
 // R: n x r FP32 (exact in the operand precision); S: n x r FP32.
 void sample_mfma(const void *X, int64_t n, int d, int xprec, double h, const float *R, int r, const int32_t *lb,
-                 const int32_t *le, float *S, int prec, int split, hipStream_t s) {
+                 const int32_t *le, float *S, int prec, int split, hipStream_t s, const Batch *batch) {
     // two zero tiles past the end keep the kernel's prefetches in bounds
     const int64_t tiles = (n + JT - 1) / JT + 2;
     const float cs = (float)(1.4426950408889634 / (2.0 * h * h));
@@ -569,8 +593,16 @@ void sample_mfma(const void *X, int64_t n, int d, int xprec, double h, const flo
         check_launch("k_to_float");
         Xs = Xf.as<float>();
     }
-    dispatch_d<float>(Xs, n, d, cs, Rsw.get(), r, lb, le, S, prec, split, s);
-    sync(s);  // Rsw is released on return
+    DBuf bt;
+    int64_t nb = 0;
+    if (batch) {
+        std::vector<SampBlock> blocks = row_blocks(*batch, ROWS);
+        nb = (int64_t)blocks.size();
+        bt = upload(blocks, s);
+        sync(s);  // `blocks` is released on return from this scope
+    }
+    dispatch_d<float>(Xs, n, d, cs, Rsw.get(), r, lb, le, S, prec, split, s, bt.as<SampBlock>(), nb);
+    sync(s);  // Rsw and the block table are released on return
 }
 
 }  // namespace krr

@@ -23,7 +23,7 @@ namespace {
 
 struct UlvDesc {
     int32_t m, k, kl, kr, leaf, root;
-    double lambda;
+    double lambda, pivot_floor;        // of the node's problem
     const double *D, *U, *B;           // HSS generators
     const double *S_l, *S_r, *Rh_l, *Rh_r;
     double *Dw, *Uw, *Tmp;             // scratch
@@ -31,11 +31,12 @@ struct UlvDesc {
     double *S_out, *Rh_out;            // passed to the parent
 };
 
-__global__ __launch_bounds__(BG_T) void k_ulv_factor(const UlvDesc *dsc, double pivot_floor, int32_t *flag,
-                                                     unsigned long long *clamped, unsigned long long *worst) {
+__global__ __launch_bounds__(BG_T) void k_ulv_factor(const UlvDesc *dsc, int32_t *flag, unsigned long long *clamped,
+                                                     unsigned long long *worst) {
     __shared__ double smem[2 * 16 * 65];
     __shared__ double red[BG_T / 64];
     const UlvDesc q = dsc[blockIdx.x];
+    const double pivot_floor = q.pivot_floor;
     const int m = q.m, k = q.k, ne = m - k, tid = threadIdx.x;
     double *Dw = q.Dw, *Uw = q.Uw;
     // ---- assemble
@@ -261,7 +262,7 @@ __device__ void tri_solve(const double *L, int n, double *y, int nrhs, int ldy, 
 }
 
 __global__ __launch_bounds__(BG_T) void k_ulv_fwd(const SolveDesc *dsc, const double *__restrict__ Bin, int nrhs,
-                                                  int nmax) {
+                                                  int nmax, double *__restrict__ Xout) {
     extern __shared__ double lds[];
     const SolveDesc q = dsc[blockIdx.x];
     const int m = q.m, k = q.k, ne = m - k, tid = threadIdx.x;
@@ -286,6 +287,9 @@ __global__ __launch_bounds__(BG_T) void k_ulv_fwd(const SolveDesc *dsc, const do
         tri_solve(q.L, ne, q.z, nrhs, nrhs, true, lds, nmax);
         __syncthreads();
         for (int64_t t = tid; t < (int64_t)m * nrhs; t += BG_T) q.bw[t] = q.z[t];
+        // a one-node tree (the root is a leaf) has no backward sweep
+        if (q.leaf)
+            for (int64_t t = tid; t < (int64_t)m * nrhs; t += BG_T) Xout[q.b * nrhs + t] = q.z[t];
         return;
     }
     // c = b_c - W z
@@ -323,12 +327,14 @@ __global__ __launch_bounds__(BG_T) void k_ulv_bwd(const SolveDesc *dsc, double *
 
 }  // namespace
 
-int64_t ulv_factor(const hss_s *H, double lambda, double pivot_floor, hipStream_t s, hss_ulv_s *F,
-                   double *worst_deficit, bool stop_at_floor) {
+int64_t ulv_factor(const hss_s *H, const std::vector<double> &lam, const std::vector<double> &floor, hipStream_t s,
+                   hss_ulv_s *F, double *worst_deficit, bool stop_at_floor) {
     const int nn = (int)H->node.size();
-    const int root = nn - 1;
+    const int np = (int)H->hprob.size();
+    KRR_REQUIRE((int)lam.size() == np && (int)floor.size() == np, "ULV: one lambda and floor per problem");
     F->n = H->n;
-    F->lambda = lambda;
+    F->lambda = lam[0];
+    F->lamprob = lam;
     F->node = H->node;
     F->levels = H->levels;
     F->offV.assign(nn, 0);
@@ -339,7 +345,7 @@ int64_t ulv_factor(const hss_s *H, double lambda, double pivot_floor, hipStream_
     std::vector<int> m(nn), k(nn);
     for (int i = 0; i < nn; ++i) {
         const HNode &q = H->node[i];
-        k[i] = (i == root) ? 0 : q.k;
+        k[i] = (q.parent < 0) ? 0 : q.k;
         m[i] = (q.left < 0) ? (int)(q.e - q.b) : k[q.left] + k[q.right];
         F->node[i].m = m[i];
         F->node[i].k = k[i];
@@ -389,8 +395,9 @@ int64_t ulv_factor(const hss_s *H, double lambda, double pivot_floor, hipStream_
             u.m = m[id];
             u.k = k[id];
             u.leaf = q.left < 0;
-            u.root = id == root;
-            u.lambda = lambda;
+            u.root = q.parent < 0;
+            u.lambda = lam[H->nprob[id]];
+            u.pivot_floor = floor[H->nprob[id]];
             if (u.leaf) {
                 u.D = H->D.as<double>() + q.offD;
             } else {
@@ -417,8 +424,8 @@ int64_t ulv_factor(const hss_s *H, double lambda, double pivot_floor, hipStream_
             u.Rh_out = Rb.as<double>() + offS[id];
         }
         DBuf dd = upload(dsc, s);
-        k_ulv_factor<<<cnt, BG_T, 0, s>>>(dd.as<UlvDesc>(), pivot_floor, flag.as<int32_t>(),
-                                          nclamp.as<unsigned long long>(), nclamp.as<unsigned long long>() + 1);
+        k_ulv_factor<<<cnt, BG_T, 0, s>>>(dd.as<UlvDesc>(), flag.as<int32_t>(), nclamp.as<unsigned long long>(),
+                                          nclamp.as<unsigned long long>() + 1);
         check_launch("k_ulv_factor");
         sync(s);
         if (stop_at_floor) {
@@ -440,7 +447,6 @@ int64_t ulv_factor(const hss_s *H, double lambda, double pivot_floor, hipStream_
 
 void ulv_solve(const hss_ulv_s *F, const double *Bin, int nrhs, double *Xout, hipStream_t s) {
     const int nn = (int)F->node.size();
-    const int root = nn - 1;
     std::vector<int64_t> ob(nn), oz(nn), oc(nn);
     int64_t nb = 0, nz = 0, nc = 0;
     for (int i = 0; i < nn; ++i) {
@@ -458,7 +464,7 @@ void ulv_solve(const hss_ulv_s *F, const double *Bin, int nrhs, double *Xout, hi
         d.m = q.m;
         d.k = q.k;
         d.leaf = q.left < 0;
-        d.root = id == root;
+        d.root = q.parent < 0;
         d.b = q.b;
         d.V = F->V.as<double>() + F->offV[id];
         d.tau = F->T.as<double>() + F->offT[id];
@@ -493,21 +499,14 @@ void ulv_solve(const hss_ulv_s *F, const double *Bin, int nrhs, double *Xout, hi
         const int nm = nmax_of(hold.back());
         keep.push_back(upload(hold.back(), s));
         k_ulv_fwd<<<(unsigned)hold.back().size(), BG_T, sizeof(double) * nm * (BG_T / 64), s>>>(
-            keep.back().as<SolveDesc>(), Bin, nrhs, nm);
+            keep.back().as<SolveDesc>(), Bin, nrhs, nm, Xout);
         check_launch("k_ulv_fwd");
     }
     for (int h = (int)F->levels.size() - 1; h >= 0; --h) {
         hold.emplace_back();
         for (int id : F->levels[h])
-            if (id != root) hold.back().push_back(make(id));
-        if (hold.back().empty()) {
-            if (F->node[root].left < 0 && h == 0) {
-                // single-node tree: the root is a leaf; copy its solution out
-                KRR_HIP(hipMemcpyAsync(Xout, bw.as<double>() + ob[root], sizeof(double) * F->n * nrhs,
-                                       hipMemcpyDeviceToDevice, s));
-            }
-            continue;
-        }
+            if (F->node[id].parent >= 0) hold.back().push_back(make(id));
+        if (hold.back().empty()) continue;
         const int nm = nmax_of(hold.back());
         keep.push_back(upload(hold.back(), s));
         k_ulv_bwd<<<(unsigned)hold.back().size(), BG_T, sizeof(double) * nm * (BG_T / 64), s>>>(
