@@ -8,9 +8,16 @@ IDs and ULV factorization, solve, PCG refinement on the FP32 kernel product to
 a relative residual of 1e-6, un-permutation, and prediction of the test set.
 
 Reported: the fit time of the mixed path (value, seconds, lower is better),
-the same fit with FP32 sampling (`fp32_fit_s`), the sampling kernel's
-throughput against the matrix-core roofline (measured with HIP events on the
-stream it runs on), and the CPU oracle timed on a bounded sample.
+the same fit with FP32 sampling (`fp32`), the two hot kernels against their
+rooflines (the sampling product on the matrix cores; the refinement's kernel
+product on the vector ALUs), each timed with HIP events on the stream it runs
+on, the batched form (64 ragged problems) and the hyper-parameter gradient
+(n = 131,072, d = 18) as extra timed legs, and the CPU oracle on a bounded
+sample.
+
+`--kernels-only` runs just one launch of each hot kernel (plus a plain copy of
+known size, for counter calibration) on the same workload: the command the
+hardware-counter profiles are taken with.
 """
 import argparse
 import json
@@ -22,7 +29,9 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+# MI355X published dense peaks (FLOP/s)
 PEAK = {"f16": 2.5e15, "bf16": 2.5e15, "f32": 157.3e12, "f64": 78.6e12}
+PEAK_FP64_VECTOR = 78.6e12
 
 
 def parse():
@@ -39,12 +48,72 @@ def parse():
     ap.add_argument("--atol", type=float, default=3.0)
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-sampling comparison fit")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
-    ap.add_argument("--sample-reps", type=int, default=3)
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-problem batched leg")
+    ap.add_argument("--no-grad", action="store_true", help="skip the gradient leg")
+    ap.add_argument("--kernels-only", action="store_true", help="one launch of each hot kernel (profiling)")
+    ap.add_argument("--reps", type=int, default=3, help="launches per kernel timing")
     return ap.parse_args()
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def leaf_arrays(nodes, n, dev):
+    import numpy as np
+    import torch
+    lbn = np.empty(n, dtype=np.int32)
+    len_ = np.empty(n, dtype=np.int32)
+    for b, e in nodes[nodes[:, 2] < 0][:, :2]:
+        lbn[b:e] = b
+        len_[b:e] = e
+    return torch.from_numpy(lbn).to(dev), torch.from_numpy(len_).to(dev)
+
+
+def time_launches(fn, reps):
+    """Average duration of fn() measured with HIP events on torch's current
+    stream, which is the stream the library launches on."""
+    import torch
+    fn()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / reps
+
+
+def kernels_only(args):
+    """One launch each: a 1 GiB device copy, the sampling product and the
+    refinement kernel product, on the 16-Gaussian workload in tree order."""
+    import torch
+
+    import paper_1803_10274_amd as krr
+    import synthdata as sd
+    krr.load()
+    dev = torch.device("cuda:0")
+    p = sd.c2_sixteen_gaussians(n=args.n, m=1)
+    X = torch.from_numpy(p.X).to(dev)
+    perm, tree = krr.cluster_2mn(X, p.leaf, 7)
+    Xp = krr.gather_rows(X, perm)
+    lb, le = leaf_arrays(tree.nodes, args.n, dev)
+    R = krr.random_block(1, args.n, args.r0)
+    w = torch.from_numpy(sd.vectors(args.n, 1, seed=3)).to(dev)
+    a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    log("copy 1 GiB")
+    b.copy_(a)
+    torch.cuda.synchronize()
+    log("sampling product")
+    krr.kernel_sample(Xp, p.h, R, lb, le, prec=args.prec, split_terms=args.split)
+    torch.cuda.synchronize()
+    log("kernel product")
+    krr.kernel_matvec(Xp, Xp, p.h, w, prec="f32")
+    torch.cuda.synchronize()
+    print(json.dumps({"kernels_only": True, "n": args.n, "r": args.r0, "copy_bytes": 2 * a.numel() * 4}), flush=True)
 
 
 def main():
@@ -53,6 +122,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.kernels_only:
+        kernels_only(args)
+        return
     import numpy as np
     import torch
 
@@ -112,41 +184,40 @@ def main():
         log(f"fp32 fit: {fp32}")
         del r32
 
-    # dominant kernel: the sampling product, timed with HIP events on the current stream
-    r = hs["r_final"]
-    R = krr.random_block(1, args.n, r)
-    Xp = res.Xp
-    lb = torch.empty(args.n, dtype=torch.int32, device=dev)
-    le = torch.empty(args.n, dtype=torch.int32, device=dev)
-    nodes = res.tree.nodes
-    leaves = nodes[nodes[:, 2] < 0]
-    lbn = np.empty(args.n, dtype=np.int32)
-    len_ = np.empty(args.n, dtype=np.int32)
-    for b, e in leaves[:, :2]:
-        lbn[b:e] = b
-        len_[b:e] = e
-    lb.copy_(torch.from_numpy(lbn))
-    le.copy_(torch.from_numpy(len_))
-    krr.kernel_sample(Xp, p.h, R, lb, le, prec=args.prec, split_terms=args.split)
-    stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.sample_reps):
-        krr.kernel_sample(Xp, p.h, R, lb, le, prec=args.prec, split_terms=args.split)
-    e1.record(stream)
-    e1.synchronize()
-    t_sample = e0.elapsed_time(e1) / 1e3 / args.sample_reps
+    # the two hot kernels, each timed with HIP events on the stream it runs on
     n = args.n
+    r = hs["r_final"]
+    R = krr.random_block(1, n, r)
+    Xp = res.Xp
+    lb, le = leaf_arrays(res.tree.nodes, n, dev)
+    t_sample = time_launches(lambda: krr.kernel_sample(Xp, p.h, R, lb, le, prec=args.prec, split_terms=args.split),
+                             args.reps)
     flops = float(n) * n * (2 * p.d + 2 * r)
     achieved = flops / t_sample
     peak = PEAK[args.prec if args.prec in PEAK else "f16"]
-    roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": None, "kernel": "sampling product",
-                "launch_s": t_sample, "algorithmic_flops": flops}
+    executed = achieved * (args.split if args.prec in ("f16", "bf16") else 1)
+    roof_sample = {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                   "frac": achieved / peak, "traffic": None, "kernel": "k_sample_mfma (sampling product S = K R)",
+                   "launch_s": t_sample, "algorithmic_flops": flops, "executed_mfma_frac": executed / peak}
+    del R
+    w = res.alpha_perm.reshape(n, -1)[:, :1].contiguous()
+    t_mv = time_launches(lambda: krr.kernel_matvec(Xp, Xp, p.h, w, prec="f32"), args.reps)
+    mv_flops = float(n) * n * (2 * p.d + 2)
+    roof_mv = {"bound": "alu", "achieved": mv_flops / t_mv / 1e12, "peak": PEAK_FP64_VECTOR / 1e12,
+               "unit": "TFLOP/s", "frac": mv_flops / t_mv / PEAK_FP64_VECTOR, "traffic": None,
+               "kernel": "k_kmv_sc (refinement product K w, FP64 exponent, FP32 entries)", "launch_s": t_mv,
+               "algorithmic_flops": mv_flops, "entries_per_s": float(n) * n / t_mv}
+    log(f"sampling {t_sample * 1e3:.1f} ms ({achieved / 1e12:.1f} TFLOP/s); "
+        f"kernel product {t_mv * 1e3:.1f} ms ({mv_flops / t_mv / 1e12:.1f} TFLOP/s)")
+    # the step's dominant kernel: the one whose phase takes longer
+    ph = res.info["phases"]
+    mv_dominant = ph.get("refine", 0.0) > ph.get("compress", 0.0)
+    roofline = roof_mv if mv_dominant else roof_sample
+    del res
 
-    cpu = None
-    if not args.no_cpu:
-        cpu = cpu_baseline(p)
+    batched = None if args.no_batched else batched_leg()
+    grad = None if args.no_grad else grad_leg()
+    cpu = None if args.no_cpu else cpu_baseline(p)
 
     out = {
         "metric": "KRR fit s at n=1M d=8: mixed vs FP32 HSS at equal acc; sample TFLOP/s",
@@ -165,8 +236,7 @@ def main():
                                f"rtol={args.rtol} atol={args.atol} r={args.r0} test_m={args.m}",
                    "sampling": args.prec, "split_terms": args.split},
         "fit_s_min": float(np.min(fit_times)),
-        "phases_s": res.info["phases"],
-        "ulv_shift": res.info["ulv_shift"],
+        "phases_s": ph,
         "fp32": fp32,
         "sample_tflops": achieved / 1e12,
         "relres": rf["relres"][0],
@@ -175,19 +245,81 @@ def main():
         "hss": {k: hs[k] for k in ("r_final", "regrowths", "max_rank", "levels", "bytes_paper",
                                    "t_sample_ms", "t_id_ms", "t_total_ms")},
         "roofline": roofline,
+        "roofline_sampling": roof_sample,
+        "roofline_kernel_product": roof_mv,
+        "batched": batched,
+        "gradient": grad,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 
 
+def batched_leg():
+    """64 ragged problems (n log-uniform in [2048, 32768], d in {8, 18, 54},
+    per-problem h and lambda): one batched fit per dimension group, mixed
+    sampling, refinement to 1e-6 on every problem."""
+    import numpy as np
+    import torch
+
+    import paper_1803_10274_amd as krr
+    import synthdata as sd
+    ps = sd.c4_ragged_batch()
+    probs = [(torch.from_numpy(q.X).cuda(), torch.from_numpy(q.y).cuda(), q.h, q.lam) for q in ps]
+    opts = krr.HssOptions(rtol=1e-2, atol=0.0, r0=256, dr=256, r_max=512, prec="f16", cap_policy=1)
+    torch.cuda.synchronize()
+    krr.fit_batched(probs[:4], leaf=128, opts=opts, tol=1e-6, max_iter=300, raise_on_fail=False)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = krr.fit_batched(probs, leaf=128, opts=opts, tol=1e-6, max_iter=300, raise_on_fail=False)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    worst = max(float(np.max(rf["relres"])) for rf in res.info["refine"])
+    out = {"workload": "64 ragged problems, n log-uniform in [2048, 32768], d in {8, 18, 54}",
+           "sum_n": int(sum(q.X.shape[0] for q in ps)), "fit_s": t, "phases_s": res.info["phases"],
+           "groups": len(res.groups), "refine_iterations": [rf["iterations"] for rf in res.info["refine"]],
+           "worst_relres": worst}
+    log(f"batched: {out}")
+    return out
+
+
+def grad_leg():
+    """Validation-loss value and gradient in (log h, log lambda) at n = 131,072,
+    d = 18, 16,384 validation points (forward fit + adjoint solve)."""
+    import torch
+
+    import paper_1803_10274_amd as krr
+    from paper_1803_10274_amd import autograd as kag
+    import synthdata as sd
+    p = sd.c5_eight_gaussians()
+    X, y = torch.from_numpy(p.X).cuda(), torch.from_numpy(p.y).cuda()
+    Xv, yv = torch.from_numpy(p.Xt).cuda(), torch.from_numpy(p.yt).cuda()
+
+    def once(state=None):
+        lh = torch.tensor(math.log(p.h), dtype=torch.float64, device="cuda", requires_grad=True)
+        ll = torch.tensor(math.log(p.lam), dtype=torch.float64, device="cuda", requires_grad=True)
+        L, st = kag.validation_loss(lh, ll, X, y, Xv, yv, leaf=p.leaf, state=state)
+        L.backward()
+        torch.cuda.synchronize()
+        return L, lh.grad, ll.grad, st
+
+    _, _, _, st = once()
+    t0 = time.perf_counter()
+    L, gh, gl, _ = once(st)
+    t = time.perf_counter() - t0
+    out = {"workload": f"eight_gaussians n={p.X.shape[0]} d={p.d} m_v={p.Xt.shape[0]} h={p.h} lambda={p.lam}",
+           "loss_and_grad_s": t, "loss": float(L), "dL_dlogh": float(gh), "dL_dloglam": float(gl)}
+    log(f"gradient: {out}")
+    return out
+
+
 def cpu_baseline(p):
     """The oracle on a bounded sample: dense FP64 KRR (form K, Cholesky, solve)
-    at n_s = 4096 points of the same workload, timed on the host, scaled to
+    at n_s = 8192 points of the same workload, timed on the host, scaled to
     n = 2^20 by the O(n^3) Cholesky cost (and its O(n^2) forming cost)."""
     import numpy as np
 
     from oracle import kernel as ok
-    n_s = 4096
+    n_s = 8192
     Xs = p.X[:n_s].astype(np.float64)
     ys = p.y[:n_s]
     t0 = time.perf_counter()
@@ -201,6 +333,9 @@ def cpu_baseline(p):
         cores = len(os.sched_getaffinity(0))
     except AttributeError:
         cores = os.cpu_count()
+    # the BLAS behind the Cholesky uses at most OMP_NUM_THREADS threads
+    if os.environ.get("OMP_NUM_THREADS", "").isdigit():
+        cores = min(cores, int(os.environ["OMP_NUM_THREADS"]))
     return {"value": est, "unit": "s", "cores": cores, "kind": "oracle",
             "sample": f"dense FP64 KRR fit (kernel_dense + Cholesky) on the first {n_s} points, "
                       f"measured form {t1 - t0:.2f} s + solve {t2 - t1:.2f} s, scaled to n={p.n} by "

@@ -98,85 +98,145 @@ __global__ __launch_bounds__(MV_ROWS) void k_kmv(const T *__restrict__ X, int64_
     }
 }
 
-// FP32-entry mode for d <= 64: the exponent is formed in FP64 by the norm
-// expansion t = -c |x_i|^2 - c |y_j|^2 + sum_k (2 c x_ik) y_jk (c in log2
-// units): FP64 FMAs cost the same as FP32 ones on this chip, the expansion
-// needs d + 1 of them instead of 2 d for the differences, and in FP64 its
-// cancellation is harmless.  The kernel value is exp2 of t rounded to FP32;
-// products and the tile sum are FP32, sums across tiles FP64.
-template <class T, int D, int NR>
-__global__ __launch_bounds__(MV_ROWS) void k_kmv_expand(const T *__restrict__ X, int64_t m,
-                                                        const T *__restrict__ Y, int64_t n, int d, double c2,
-                                                        const double *__restrict__ W, int nrhs, int rhs0,
-                                                        int64_t cols_per_split, double *__restrict__ part,
-                                                        const SampBlock *__restrict__ bt) {
-    __shared__ double ys[MV_TN][D + 1];
+// FP32-entry mode for d <= 64.  The exponent is the FP64 norm expansion
+// t = -c |x_i|^2 + (-c |y_j|^2 + sum_k x_ik (2 c y_jk)) (c in log2 units), with
+// the column terms prepared once per product (ya, LDP doubles per column) and
+// staged per 64-column tile in LDS; FP64 FMAs cost the same as FP32 ones here
+// and keep the expansion free of cancellation trouble.  The entry is exp2 of
+// t rounded to FP32 (t = -inf past the end of the tile: entry 0); products and
+// the tile sum are FP32, sums across tiles FP64.  Each thread owns RPT rows,
+// so that every broadcast LDS read of a column serves RPT entries (a wave's
+// LDS reads return one copy per lane and would otherwise bound the loop).
+template <int D> struct ColLd { static constexpr int V = (D + 2) & ~1; };
+
+template <class T, int D, int NR, int RPT>
+__global__ __launch_bounds__(MV_ROWS) void k_kmv_sc(const T *__restrict__ X, int64_t m, int d, double c2,
+                                                    const double *__restrict__ ya, const float *__restrict__ wf,
+                                                    int nrhs, int rhs0, int64_t n, int64_t cols_per_split,
+                                                    double *__restrict__ part, const SampBlock *__restrict__ bt) {
+    constexpr int LD = ColLd<D>::V;
+    __shared__ __attribute__((aligned(16))) double ys[MV_TN][LD];
     __shared__ float ws[MV_TN][NR];
     const int tid = threadIdx.x;
     const int split = blockIdx.y;
-    int64_t i, iend, j0, j1;
+    int64_t i0, iend, j0, j1;
     if (bt) {
         const SampBlock sb = bt[blockIdx.x];
-        i = sb.i0 + tid;
+        i0 = sb.i0;
         iend = sb.iend;
         j0 = sb.jlo + split * sb.cps;
         j1 = min(sb.jhi, j0 + sb.cps);
         c2 = sb.c2;
     } else {
-        i = (int64_t)blockIdx.x * MV_ROWS + tid;
+        i0 = (int64_t)blockIdx.x * (MV_ROWS * RPT);
         iend = m;
         j0 = split * cols_per_split;
         j1 = min(n, j0 + cols_per_split);
     }
-    double xs[D];
-    double nx = 0.0;
+    double xs[RPT][D];
+    double nx[RPT];
 #pragma unroll
-    for (int k = 0; k < D; ++k) {
-        double v = (i < iend && k < d) ? (double)X[i * d + k] : 0.0;
-        nx = fma(v, v, nx);
-        xs[k] = 2.0 * c2 * v;
+    for (int q = 0; q < RPT; ++q) {
+        const int64_t i = i0 + tid + (int64_t)MV_ROWS * q;
+        double a = 0.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            double v = (i < iend && k < d) ? (double)X[i * d + k] : 0.0;
+            a = fma(v, v, a);
+            xs[q][k] = v;
+        }
+        nx[q] = -c2 * a;
     }
-    nx = -c2 * nx;
-    double acc[NR];
+    double acc[RPT][NR];
 #pragma unroll
-    for (int r = 0; r < NR; ++r) acc[r] = 0.0;
-    const int nr = min(NR, nrhs - rhs0);
+    for (int q = 0; q < RPT; ++q)
+#pragma unroll
+        for (int r = 0; r < NR; ++r) acc[q][r] = 0.0;
     for (int64_t jt = j0; jt < j1; jt += MV_TN) {
-        for (int jj = tid; jj < MV_TN; jj += MV_ROWS) {
-            int64_t j = jt + jj;
-            double nrm = 0.0;
-#pragma unroll
-            for (int k = 0; k < D; ++k) {
-                double v = (j < j1 && k < d) ? (double)Y[j * d + k] : 0.0;
-                ys[jj][k] = v;
-                nrm = fma(v, v, nrm);
-            }
-            ys[jj][D] = (j < j1) ? -c2 * nrm : -1e300;
+        const int64_t cnt = min((int64_t)MV_TN, j1 - jt);
+        const double *src = ya + jt * LD;
+        for (int t = tid; t < MV_TN * LD; t += MV_ROWS) {
+            const int jj = t / LD, k = t % LD;
+            ys[jj][k] = jj < cnt ? src[t] : (k == D ? -INFINITY : 0.0);
         }
         for (int t = tid; t < MV_TN * NR; t += MV_ROWS) {
-            int jj = t / NR, r = t % NR;
-            int64_t j = jt + jj;
-            ws[jj][r] = (j < j1 && r < nr) ? (float)W[j * nrhs + rhs0 + r] : 0.0f;
+            const int jj = t / NR, r = t % NR;
+            ws[jj][r] = jj < cnt ? wf[(jt + jj) * nrhs + rhs0 + r] : 0.0f;
         }
         __syncthreads();
-        float pacc[NR];
+        float pacc[RPT][NR];
 #pragma unroll
-        for (int r = 0; r < NR; ++r) pacc[r] = 0.0f;
+        for (int q = 0; q < RPT; ++q)
+#pragma unroll
+            for (int r = 0; r < NR; ++r) pacc[q][r] = 0.0f;
         for (int jj = 0; jj < MV_TN; ++jj) {
-            double t = nx + ys[jj][D];
+            double yv[D + 1];
 #pragma unroll
-            for (int k = 0; k < D; ++k) t = fma(xs[k], ys[jj][k], t);
-            float kv = __builtin_amdgcn_exp2f((float)fmax(t, -1000.0));
+            for (int k = 0; k <= D; ++k) yv[k] = ys[jj][k];
+            float wv[NR];
 #pragma unroll
-            for (int r = 0; r < NR; ++r) pacc[r] = fmaf(kv, ws[jj][r], pacc[r]);
+            for (int r = 0; r < NR; ++r) wv[r] = ws[jj][r];
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                double t = nx[q] + yv[D];
+#pragma unroll
+                for (int k = 0; k < D; ++k) t = fma(xs[q][k], yv[k], t);
+                const float kv = __builtin_amdgcn_exp2f((float)t);
+#pragma unroll
+                for (int r = 0; r < NR; ++r) pacc[q][r] = fmaf(kv, wv[r], pacc[q][r]);
+            }
         }
 #pragma unroll
-        for (int r = 0; r < NR; ++r) acc[r] += (double)pacc[r];
+        for (int q = 0; q < RPT; ++q)
+#pragma unroll
+            for (int r = 0; r < NR; ++r) acc[q][r] += (double)pacc[q][r];
         __syncthreads();
     }
-    if (i < iend) {
-        for (int r = 0; r < nr; ++r) part[((int64_t)split * m + i) * nrhs + rhs0 + r] = acc[r];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int64_t i = i0 + tid + (int64_t)MV_ROWS * q;
+        if (i < iend)
+            for (int r = 0; r < NR; ++r) part[((int64_t)split * m + i) * nrhs + rhs0 + r] = acc[q][r];
     }
+}
+
+// Rows per thread of k_kmv_sc by width (register budget).
+constexpr int sc_rpt(int D) { return D <= 16 ? 4 : (D <= 24 ? 3 : (D <= 32 ? 2 : 1)); }
+
+// Column data of k_kmv_sc: ya[j] = (2 c y_j1 .. 2 c y_jd, 0 .., -c |y_j|^2 at
+// index D, 0 ..) in rows of ld doubles, c the column's problem's scale
+// (pbeg / cprob: a batch) or c2.
+template <class T>
+__global__ void k_col_aug(const T *__restrict__ Y, int64_t n, int d, int D, int ld, double c2,
+                          const int64_t *__restrict__ pbeg, const double *__restrict__ cprob, int np,
+                          double *__restrict__ ya) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double c = c2;
+    if (pbeg) {
+        int lo = 0, hi = np - 1;  // last problem starting at or before j
+        while (lo < hi) {
+            int mid = (lo + hi + 1) / 2;
+            if (pbeg[mid] <= j)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        c = cprob[lo];
+    }
+    double nrm = 0.0;
+    double *row = ya + j * ld;
+    for (int k = 0; k < ld; ++k) {
+        double v = k < d ? (double)Y[j * d + k] : 0.0;
+        nrm = fma(v, v, nrm);
+        if (k != D) row[k] = 2.0 * c * v;
+    }
+    row[D] = -c * nrm;
+}
+
+__global__ void k_w_to_float(const double *__restrict__ W, int64_t len, float *__restrict__ wf) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < len) wf[t] = (float)W[t];
 }
 
 // Large d: coordinates streamed from memory instead of registers.
@@ -270,9 +330,7 @@ void launch_kmv(const T *X, int64_t m, const T *Y, int64_t n, int d, C scale, do
                 int nrhs, int rhs0, int nsplit, int64_t cps, double *part, hipStream_t s, const SampBlock *bt,
                 int64_t nb) {
     dim3 grid(bt ? (unsigned)nb : ceil_div(m, MV_ROWS), nsplit);
-    if (D > 0 && sizeof(C) == 4)
-        k_kmv_expand<T, (D > 0 ? D : 1), NR><<<grid, MV_ROWS, 0, s>>>(X, m, Y, n, d, c2, W, nrhs, rhs0, cps, part, bt);
-    else if (D > 0)
+    if (D > 0)
         k_kmv<T, C, (D > 0 ? D : 1), NR><<<grid, MV_ROWS, 0, s>>>(X, m, Y, n, d, scale, W, nrhs, rhs0, cps, part, bt);
     else
         k_kmv_wide<T, C, NR><<<grid, MV_ROWS, 0, s>>>(X, m, Y, n, d, scale, W, nrhs, rhs0, cps, part, bt);
@@ -294,17 +352,54 @@ void dispatch_d(const T *X, int64_t m, const T *Y, int64_t n, int d, C scale, do
         launch_kmv<T, C, 0, NR>(X, m, Y, n, d, scale, c2, W, nrhs, rhs0, nsplit, cps, part, s, bt, nb);
 }
 
+// Widths of the scalar-operand kernel (coordinates padded with zeros).
+template <class T, int NR>
+void launch_sc(int D, dim3 grid, const T *X, int64_t m, int d, double c2, const double *ya, const float *wf,
+               int nrhs, int rhs0, int64_t n, int64_t cps, double *part, const SampBlock *bt, hipStream_t s) {
+#define KRR_SC(DD)                                                                                              \
+    case DD:                                                                                                     \
+        k_kmv_sc<T, DD, NR, sc_rpt(DD)><<<grid, MV_ROWS, 0, s>>>(X, m, d, c2, ya, wf, nrhs, rhs0, n, cps, part, \
+                                                                 bt);                                        \
+        break;
+    switch (D) {
+        KRR_SC(4)
+        KRR_SC(8)
+        KRR_SC(12)
+        KRR_SC(16)
+        KRR_SC(20)
+        KRR_SC(24)
+        KRR_SC(32)
+        KRR_SC(48)
+        KRR_SC(56)
+        KRR_SC(64)
+        default: fail(KRR_E_INVAL, "kernel_matvec: no scalar-operand variant for width %d", D);
+    }
+#undef KRR_SC
+    check_launch("k_kmv_sc");
+}
+
+int sc_width(int d) {
+    if (d <= 24) return (d + 3) / 4 * 4;
+    if (d <= 32) return 32;
+    if (d <= 48) return 48;
+    if (d <= 56) return 56;
+    return 64;
+}
+
 template <class T, class C>
 void kmv_typed(const T *X, int64_t m, const T *Y, int64_t n, int d, double h, const double *W, int nrhs,
                double beta, double *Out, hipStream_t s, const Batch *batch) {
     const C scale = kernel_scale<C>(h);
     const double c2 = kernel_scale_log2(h);
+    const bool sc = sizeof(C) == 4 && d <= 64;
+    const int D = sc ? sc_width(d) : 0;
+    const int rows_pb = sc ? MV_ROWS * sc_rpt(D) : MV_ROWS;  // rows per workgroup
     // split the columns so that the grid has enough blocks to fill the chip
     int nsplit;
     int64_t cps = 0, nb = 0;
     DBuf btab;
     if (batch) {
-        std::vector<SampBlock> blocks = row_blocks(*batch, MV_ROWS);
+        std::vector<SampBlock> blocks = row_blocks(*batch, rows_pb);
         nb = (int64_t)blocks.size();
         int64_t nmax = 0;
         for (int k = 0; k < batch->np(); ++k) nmax = std::max(nmax, batch->size(k));
@@ -316,7 +411,7 @@ void kmv_typed(const T *X, int64_t m, const T *Y, int64_t n, int d, double h, co
         btab = upload(blocks, s);
         sync(s);
     } else {
-        const int64_t row_blocks = ceil_div(m, MV_ROWS);
+        const int64_t row_blocks = ceil_div(m, rows_pb);
         nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(2048, row_blocks), ceil_div(n, 4 * MV_TN)));
         cps = (int64_t)ceil_div(n, nsplit);
         cps = (cps + MV_TN - 1) / MV_TN * MV_TN;
@@ -324,6 +419,45 @@ void kmv_typed(const T *X, int64_t m, const T *Y, int64_t n, int d, double h, co
     }
     const SampBlock *bt = btab.as<SampBlock>();
     DBuf part = dalloc<double>((size_t)nsplit * m * nrhs);
+    if (sc) {
+        const int LD = (D + 2) & ~1;  // ColLd
+        DBuf ya = dalloc<double>((size_t)n * LD), wf = dalloc<float>((size_t)n * nrhs), pb, cp;
+        if (batch) {
+            std::vector<double> cpr(batch->np());
+            for (int k = 0; k < batch->np(); ++k) cpr[k] = kernel_scale_log2(batch->h[k]);
+            pb = upload(batch->pbeg, s);
+            cp = upload(cpr, s);
+            sync(s);  // `cpr` is released at the end of this scope
+        }
+        k_col_aug<T><<<ceil_div(n, 256), 256, 0, s>>>(Y, n, d, D, LD, c2, pb.as<int64_t>(), cp.as<double>(),
+                                                      batch ? batch->np() : 0, ya.as<double>());
+        check_launch("k_col_aug");
+        k_w_to_float<<<ceil_div(n * nrhs, 256), 256, 0, s>>>(W, n * nrhs, wf.as<float>());
+        check_launch("k_w_to_float");
+        dim3 grid(bt ? (unsigned)nb : ceil_div(m, rows_pb), nsplit);
+        for (int r0 = 0; r0 < nrhs;) {
+            const int left = nrhs - r0;
+            const int nr = left >= 16 ? 16 : left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
+            switch (nr) {
+                case 16: launch_sc<T, 16>(D, grid, X, m, d, c2, ya.as<double>(), wf.as<float>(), nrhs, r0, n, cps,
+                                          part.as<double>(), bt, s); break;
+                case 8: launch_sc<T, 8>(D, grid, X, m, d, c2, ya.as<double>(), wf.as<float>(), nrhs, r0, n, cps,
+                                        part.as<double>(), bt, s); break;
+                case 4: launch_sc<T, 4>(D, grid, X, m, d, c2, ya.as<double>(), wf.as<float>(), nrhs, r0, n, cps,
+                                        part.as<double>(), bt, s); break;
+                case 2: launch_sc<T, 2>(D, grid, X, m, d, c2, ya.as<double>(), wf.as<float>(), nrhs, r0, n, cps,
+                                        part.as<double>(), bt, s); break;
+                default: launch_sc<T, 1>(D, grid, X, m, d, c2, ya.as<double>(), wf.as<float>(), nrhs, r0, n, cps,
+                                         part.as<double>(), bt, s); break;
+            }
+            r0 += nr;
+        }
+        const int64_t mn = m * nrhs;
+        k_reduce_splits<<<ceil_div(mn, 256), 256, 0, s>>>(part.as<double>(), nsplit, mn, beta, Out);
+        check_launch("k_reduce_splits");
+        sync(s);  // the temporaries are released on return
+        return;
+    }
     for (int r0 = 0; r0 < nrhs;) {
         int left = nrhs - r0;
         if (left >= 16) {
