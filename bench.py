@@ -265,7 +265,7 @@ def batched_leg():
     import synthdata as sd
     ps = sd.c4_ragged_batch()
     probs = [(torch.from_numpy(q.X).cuda(), torch.from_numpy(q.y).cuda(), q.h, q.lam) for q in ps]
-    opts = krr.HssOptions(rtol=1e-2, atol=0.0, r0=256, dr=256, r_max=512, prec="f16", cap_policy=1)
+    opts = krr.HssOptions(rtol=1e-2, atol=1.0, r0=256, dr=256, r_max=256, prec="f16", cap_policy=1)
     torch.cuda.synchronize()
     krr.fit_batched(probs[:4], leaf=128, opts=opts, tol=1e-6, max_iter=300, raise_on_fail=False)  # warm-up
     torch.cuda.synchronize()

@@ -279,6 +279,14 @@ int hss_ulv_factor_shifted(hss_t H, double lambda, void *stream, hss_ulv_t *out,
 
 void hss_ulv_destroy(hss_ulv_t F);
 
+/* Graph replay of solves (default on): the first hss_solve with a given
+ * nrhs builds a plan (sweep workspace and per-level descriptors on the
+ * device) and captures its launches into a HIP graph; later solves copy B in,
+ * replay the graph and copy the solution out, with no allocation, upload or
+ * synchronization.  enable = 0 issues the same launches directly instead.
+ * Either way a factor must not be used by two host threads at once. */
+int hss_ulv_use_graph(hss_ulv_t F, int32_t enable);
+
 /* Xout = (K_hss + lambda I)^{-1} B for n x nrhs FP64 B (permuted order).
  * B and Xout may alias.  The factor is symmetric, so it also solves the
  * transposed system. */
@@ -355,8 +363,10 @@ int hss_num_problems(hss_t H, int32_t *np_host);
 
 /* ULV factorization of every problem of a compressed batch with its own
  * lambda[k] (host, np doubles).  shifted = 0: as hss_ulv_factor.  shifted = 1:
- * as hss_ulv_factor_shifted with the shift lambda[k] * s for one common s in
- * 0, 1, 4, 16, ... (shift_mult_host, optional, receives s).  Solve with
+ * as hss_ulv_factor_shifted, each problem with its own shift lambda[k] s_k,
+ * s_k in 0, 1, 4, 16, ... (a retry refactors only the problems that still
+ * have a pivot below lambda[k] / 2; shift_mult_host, optional, host np
+ * doubles, receives every s_k, zeros when shifted = 0).  Solve with
  * hss_solve (the factor is block diagonal over the problems). */
 int hss_ulv_factor_batched(hss_t H, const double *lambda, int32_t shifted, void *stream,
                            hss_ulv_t *out, double *shift_mult_host);

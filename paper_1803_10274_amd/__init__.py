@@ -278,6 +278,11 @@ class ULV:
         self.hss = H
         self.lam = lam
 
+    def use_graph(self, enable: bool = True):
+        """Replay solves as a captured HIP graph (default) or issue them directly."""
+        check(load().hss_ulv_use_graph(self.h, int(bool(enable))))
+        return self
+
     def solve(self, B: torch.Tensor, out=None) -> torch.Tensor:
         _dev(B, torch.float64)
         B2 = B.reshape(B.shape[0], -1)
@@ -434,15 +439,16 @@ class BatchedULV(ULV):
     def __init__(self, H: BatchedHSS, lam, shifted: bool = False):
         lams = np.ascontiguousarray(lam, dtype=np.float64)
         h_ = ctypes.c_void_p()
-        mult = ctypes.c_double()
+        mult = np.zeros(lams.shape[0], dtype=np.float64)
         check(load().hss_ulv_factor_batched(H.h, _dblp(lams), int(bool(shifted)), _stream(), ctypes.byref(h_),
-                                            ctypes.byref(mult)))
+                                            _dblp(mult)))
         self.h = h_
         self.hss = H
         self.lam = lams
         self.clamped = 0
-        self.shift_mult = mult.value
-        self.shift = mult.value
+        self.shift_mults = mult            # each problem's s_k (shift lambda_k s_k)
+        self.shift_mult = float(mult.max()) if mult.size else 0.0
+        self.shift = self.shift_mult
 
 
 def kernel_matvec_batched(X, offsets, h, W, prec="f32"):
@@ -550,7 +556,7 @@ def fit_batched(problems, leaf=128, opts: HssOptions = HssOptions(), seed=7, tol
         ap = F.solve(Yp)
         t = mark("solve", t)
         info["hss"].append(H.stats.as_dict())
-        info["ulv_shift_mult"].append(F.shift_mult)
+        info["ulv_shift_mult"].append(F.shift_mults.tolist())
         if refine_solution:
             info["refine"].append(refine_batched(F, Xp, off, hs, ls, Yp, ap, tol=tol, max_iter=max_iter,
                                                  mv_prec=mv_prec, raise_on_fail=raise_on_fail))

@@ -75,6 +75,7 @@ SIGNATURES = {
     "hss_ulv_factor_spd": (ctypes.c_int, [_vp, _dbl, _dbl, _vp, _P(_vp), _P(_i64)]),
     "hss_ulv_factor_shifted": (ctypes.c_int, [_vp, _dbl, _vp, _P(_vp), _P(_dbl)]),
     "hss_ulv_destroy": (None, [_vp]),
+    "hss_ulv_use_graph": (ctypes.c_int, [_vp, _i32]),
     "hss_solve": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp]),
     "krr_refine": (ctypes.c_int, [_vp, _vp, _i64, _i32, _i32, _dbl, _dbl, _vp, _i32, _vp, _dbl, _i32, _i32, _vp,
                                   _P(RefineStats)]),

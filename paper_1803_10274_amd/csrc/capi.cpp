@@ -96,32 +96,41 @@ Batch make_batch(const int64_t *offsets, int32_t np, const double *h, const doub
     return b;
 }
 
-// Factor with lambda_k (1 + s) for s = 0, 1, 4, 16, ... until no pivot of
-// any problem falls below lambda_k / 2 (see hss_ulv_factor_shifted).
-hss_ulv_s *factor_shifted(const hss_s *H, const std::vector<double> &lam, hipStream_t s, double *mult) {
+// Factor with lambda_k (1 + s_k), each problem's s_k running through 0, 1, 4,
+// 16, ... until none of its pivots falls below lambda_k / 2 (see
+// hss_ulv_factor_shifted).  A pass stops a problem at its first level with
+// such a pivot; the next pass refactors only the problems that stopped, with
+// their larger shifts.  mult receives every s_k.
+hss_ulv_s *factor_shifted(const hss_s *H, const std::vector<double> &lam, hipStream_t s, std::vector<double> &mult) {
     const int np = (int)lam.size();
-    std::vector<double> floor(np), lam_s(np);
+    std::vector<double> floor(np), lam_s(np), sh(np, 0.0);
     for (int k = 0; k < np; ++k) floor[k] = 0.5 * lam[k];
-    double sh = 0.0;
-    for (int attempt = 0; attempt < 12; ++attempt) {
-        for (int k = 0; k < np; ++k) lam_s[k] = lam[k] * (1.0 + sh);
-        auto *F = new hss_ulv_s();
-        int64_t raised = 0;
-        try {
-            raised = ulv_factor(H, lam_s, floor, s, F, nullptr, true);
-        } catch (...) {
-            delete F;
-            throw;
+    std::vector<uint8_t> todo(np, 1);
+    auto *F = new hss_ulv_s();
+    try {
+        for (int attempt = 0; attempt < 12; ++attempt) {
+            for (int k = 0; k < np; ++k) lam_s[k] = lam[k] * (1.0 + sh[k]);
+            std::vector<uint8_t> act = todo;
+            ulv_factor(H, lam_s, floor, s, F, nullptr, true, &act);
+            int left = 0;
+            for (int k = 0; k < np; ++k) {
+                todo[k] = act[k];
+                if (act[k]) {
+                    sh[k] = sh[k] == 0.0 ? 1.0 : 4.0 * sh[k];
+                    ++left;
+                }
+            }
+            if (verbose()) fprintf(stderr, "[krr] ulv shift pass %d: %d of %d problems retry\n", attempt, left, np);
+            if (left == 0) {
+                mult = sh;
+                return F;
+            }
         }
-        if (verbose())
-            fprintf(stderr, "[krr] ulv shift %.4g lambda: %s\n", sh, raised ? "pivot below lambda/2, retry" : "ok");
-        if (raised == 0) {
-            *mult = sh;
-            return F;
-        }
+    } catch (...) {
         delete F;
-        sh = sh == 0.0 ? 1.0 : 4.0 * sh;
+        throw;
     }
+    delete F;
     fail(KRR_E_NUMERIC, "ULV: no positive definite shift found in 12 tries");
 }
 
@@ -416,14 +425,22 @@ int hss_ulv_factor_shifted(hss_t H, double lambda, void *stream, hss_ulv_t *out,
         KRR_REQUIRE(H != nullptr, "hss_ulv_factor_shifted: NULL handle");
         KRR_REQUIRE(lambda > 0.0, "hss_ulv_factor_shifted: lambda must be > 0");
         require_device();
-        double mult = 0.0;
-        *out = factor_shifted(H, std::vector<double>(H->hprob.size(), lambda), S(stream), &mult);
-        if (shift_host) *shift_host = mult * lambda;
+        std::vector<double> mult;
+        *out = factor_shifted(H, std::vector<double>(H->hprob.size(), lambda), S(stream), mult);
+        if (shift_host) *shift_host = *std::max_element(mult.begin(), mult.end()) * lambda;
         return KRR_OK;
     });
 }
 
 void hss_ulv_destroy(hss_ulv_t F) { delete F; }
+
+int hss_ulv_use_graph(hss_ulv_t F, int32_t enable) {
+    return guard([&] {
+        KRR_REQUIRE(F != nullptr, "hss_ulv_use_graph: NULL factor");
+        F->use_graph = enable != 0;
+        return KRR_OK;
+    });
+}
 
 int hss_solve(hss_ulv_t F, const double *B, int32_t nrhs, double *Xout, void *stream) {
     return guard([&] {
@@ -563,9 +580,9 @@ int hss_ulv_factor_batched(hss_t H, const double *lambda, int32_t shifted, void 
             KRR_REQUIRE(shifted ? lam[k] > 0.0 : lam[k] >= 0.0, "hss_ulv_factor_batched: bad lambda[%zu]", k);
         require_device();
         if (shifted) {
-            double mult = 0.0;
-            *out = factor_shifted(H, lam, S(stream), &mult);
-            if (shift_mult_host) *shift_mult_host = mult;
+            std::vector<double> mult;
+            *out = factor_shifted(H, lam, S(stream), mult);
+            if (shift_mult_host) std::copy(mult.begin(), mult.end(), shift_mult_host);
             return KRR_OK;
         }
         auto *F = new hss_ulv_s();
@@ -575,7 +592,7 @@ int hss_ulv_factor_batched(hss_t H, const double *lambda, int32_t shifted, void 
             delete F;
             throw;
         }
-        if (shift_mult_host) *shift_mult_host = 0.0;
+        if (shift_mult_host) std::fill(shift_mult_host, shift_mult_host + np, 0.0);
         *out = F;
         return KRR_OK;
     });

@@ -14,6 +14,7 @@
 // x_e = L^{-T} (z - W^T x_c), x = Q [x_c; x_e].
 #include <algorithm>
 #include <cstring>
+#include <memory>
 
 #include "dense.hpp"
 #include "internal.hpp"
@@ -23,6 +24,7 @@ namespace {
 
 struct UlvDesc {
     int32_t m, k, kl, kr, leaf, root;
+    int32_t prob, pad_;                // the node's problem (batch)
     double lambda, pivot_floor;        // of the node's problem
     const double *D, *U, *B;           // HSS generators
     const double *S_l, *S_r, *Rh_l, *Rh_r;
@@ -154,7 +156,7 @@ __global__ __launch_bounds__(BG_T) void k_ulv_factor(const UlvDesc *dsc, int32_t
             double theta = 0.0;
             for (int i = 0; i < BG_T / 64; ++i) theta = fmax(theta, red[i]);
             if (tid == 0) {
-                atomicAdd(clamped, 1ull);
+                atomicAdd(clamped + q.prob, 1ull);
                 // largest deficit below the floor (non-negative, so its bits order like integers)
                 atomicMax(worst, (unsigned long long)__double_as_longlong(pivot_floor - djj));
             }
@@ -328,19 +330,27 @@ __global__ __launch_bounds__(BG_T) void k_ulv_bwd(const SolveDesc *dsc, double *
 }  // namespace
 
 int64_t ulv_factor(const hss_s *H, const std::vector<double> &lam, const std::vector<double> &floor, hipStream_t s,
-                   hss_ulv_s *F, double *worst_deficit, bool stop_at_floor) {
+                   hss_ulv_s *F, double *worst_deficit, bool stop_at_floor, std::vector<uint8_t> *active) {
     const int nn = (int)H->node.size();
     const int np = (int)H->hprob.size();
     KRR_REQUIRE((int)lam.size() == np && (int)floor.size() == np, "ULV: one lambda and floor per problem");
+    KRR_REQUIRE(!active || (int)active->size() == np, "ULV: one activity flag per problem");
+    const bool reuse = !F->node.empty();  // a later pass over some problems of the same factor
+    KRR_REQUIRE(!reuse || (F->node.size() == H->node.size() && F->n == H->n), "ULV: factor of another matrix");
     F->n = H->n;
     F->lambda = lam[0];
-    F->lamprob = lam;
-    F->node = H->node;
-    F->levels = H->levels;
-    F->offV.assign(nn, 0);
-    F->offT.assign(nn, 0);
-    F->offL.assign(nn, 0);
-    F->offW.assign(nn, 0);
+    if (!reuse) F->lamprob = lam;
+    for (int p = 0; p < np; ++p)
+        if (!active || (*active)[p]) F->lamprob[p] = lam[p];
+    F->plans.clear();  // solve plans describe the previous values
+    if (!reuse) {
+        F->node = H->node;
+        F->levels = H->levels;
+        F->offV.assign(nn, 0);
+        F->offT.assign(nn, 0);
+        F->offL.assign(nn, 0);
+        F->offW.assign(nn, 0);
+    }
     // per-node sizes: m (rows of the reduced block) and k
     std::vector<int> m(nn), k(nn);
     for (int i = 0; i < nn; ++i) {
@@ -350,19 +360,23 @@ int64_t ulv_factor(const hss_s *H, const std::vector<double> &lam, const std::ve
         F->node[i].m = m[i];
         F->node[i].k = k[i];
     }
-    int64_t nv = 0, nt = 0, nl = 0, nw = 0;
-    for (int i = 0; i < nn; ++i) {
-        int ne = m[i] - k[i];
-        F->offV[i] = nv; nv += (int64_t)m[i] * k[i];
-        F->offT[i] = nt; nt += k[i];
-        F->offL[i] = nl; nl += (int64_t)ne * ne;
-        F->offW[i] = nw; nw += (int64_t)k[i] * ne;
+    if (!reuse) {
+        int64_t nv = 0, nt = 0, nl = 0, nw = 0;
+        for (int i = 0; i < nn; ++i) {
+            int ne = m[i] - k[i];
+            F->offV[i] = nv; nv += (int64_t)m[i] * k[i];
+            F->offT[i] = nt; nt += k[i];
+            F->offL[i] = nl; nl += (int64_t)ne * ne;
+            F->offW[i] = nw; nw += (int64_t)k[i] * ne;
     }
     F->V.alloc(8 * std::max<int64_t>(nv, 1));
     F->T.alloc(8 * std::max<int64_t>(nt, 1));
     F->L.alloc(8 * std::max<int64_t>(nl, 1));
     F->W.alloc(8 * std::max<int64_t>(nw, 1));
     F->nV = nv; F->nT = nt; F->nL = nl; F->nW = nw;
+    }
+    std::vector<uint8_t> act(np, 1);
+    if (active) act = *active;
     // S and Rh of every non-root node live until the parent is done
     std::vector<int64_t> offS(nn, 0);
     int64_t ns = 0;
@@ -371,10 +385,16 @@ int64_t ulv_factor(const hss_s *H, const std::vector<double> &lam, const std::ve
         ns += (int64_t)k[i] * k[i];
     }
     DBuf Sb = dalloc<double>(std::max<int64_t>(ns, 1)), Rb = dalloc<double>(std::max<int64_t>(ns, 1));
-    DBuf flag = dalloc<int32_t>(1), nclamp = dalloc<unsigned long long>(2);
+    // counters: raised pivots per problem, then the largest deficit
+    DBuf flag = dalloc<int32_t>(1), nclamp = dalloc<unsigned long long>(np + 1);
     KRR_HIP(hipMemsetAsync(flag.get(), 0, sizeof(int32_t), s));
-    KRR_HIP(hipMemsetAsync(nclamp.get(), 0, 2 * sizeof(unsigned long long), s));
-    for (const auto &lv : H->levels) {
+    KRR_HIP(hipMemsetAsync(nclamp.get(), 0, (np + 1) * sizeof(unsigned long long), s));
+    std::vector<uint8_t> raised(np, 0);
+    for (const auto &lv_all : H->levels) {
+        std::vector<int> lv;  // this level's nodes of the problems still being factored
+        for (int id : lv_all)
+            if (act[H->nprob[id]]) lv.push_back(id);
+        if (lv.empty()) continue;
         const int cnt = (int)lv.size();
         int64_t dsz = 0, usz = 0, tsz = 0;
         for (int id : lv) {
@@ -396,6 +416,7 @@ int64_t ulv_factor(const hss_s *H, const std::vector<double> &lam, const std::ve
             u.k = k[id];
             u.leaf = q.left < 0;
             u.root = q.parent < 0;
+            u.prob = H->nprob[id];
             u.lambda = lam[H->nprob[id]];
             u.pivot_floor = floor[H->nprob[id]];
             if (u.leaf) {
@@ -425,27 +446,63 @@ int64_t ulv_factor(const hss_s *H, const std::vector<double> &lam, const std::ve
         }
         DBuf dd = upload(dsc, s);
         k_ulv_factor<<<cnt, BG_T, 0, s>>>(dd.as<UlvDesc>(), flag.as<int32_t>(), nclamp.as<unsigned long long>(),
-                                          nclamp.as<unsigned long long>() + 1);
+                                          nclamp.as<unsigned long long>() + np);
         check_launch("k_ulv_factor");
         sync(s);
         if (stop_at_floor) {
-            unsigned long long c0 = 0;
-            d2h(&c0, nclamp.as<unsigned long long>(), 1, s);
+            // a problem with a pivot below its floor stops here (its factor
+            // is left incomplete); the others go on
+            std::vector<unsigned long long> c(np);
+            d2h(c.data(), nclamp.as<unsigned long long>(), np, s);
             sync(s);
-            if (c0) return (int64_t)c0;  // a pivot fell below the floor: stop here
+            for (int p = 0; p < np; ++p)
+                if (act[p] && c[p]) {
+                    act[p] = 0;
+                    raised[p] = 1;
+                }
         }
     }
     int32_t bad = 0;
-    unsigned long long cl[2] = {0, 0};
+    std::vector<unsigned long long> cl(np + 1);
     d2h(&bad, flag.as<int32_t>(), 1, s);
-    d2h(cl, nclamp.as<unsigned long long>(), 2, s);
+    d2h(cl.data(), nclamp.as<unsigned long long>(), np + 1, s);
     sync(s);
-    if (worst_deficit) *worst_deficit = cl[1] ? __builtin_bit_cast(double, (uint64_t)cl[1]) : 0.0;
+    if (worst_deficit) *worst_deficit = cl[np] ? __builtin_bit_cast(double, (uint64_t)cl[np]) : 0.0;
     if (bad) fail(KRR_E_NUMERIC, "ULV: non-positive pivot in a Cholesky factor (K_hss + lambda I not SPD)");
-    return (int64_t)cl[0];
+    if (active && stop_at_floor) *active = raised;
+    int64_t tot = 0;
+    for (int p = 0; p < np; ++p) tot += (int64_t)cl[p];
+    return tot;
 }
 
-void ulv_solve(const hss_ulv_s *F, const double *Bin, int nrhs, double *Xout, hipStream_t s) {
+// A solve plan for one factor and one number of right-hand sides: the sweep
+// workspace and the per-level descriptor arrays live on the device for the
+// factor's lifetime, so that a solve issues only its kernel launches (no
+// allocation, upload or synchronization); with graphs on, those launches are
+// captured once into a HIP graph and replayed (the right-hand side is copied
+// into the plan's input block and the solution out of its output block).
+struct UlvSolvePlan {
+    int nrhs = 0;
+    int64_t n = 0;
+    DBuf bw, zb, cb, in, out;
+    std::vector<DBuf> desc;             // forward levels, then backward levels
+    std::vector<int> cnt, nmax, fwd;    // per launch: blocks, LDS rows, 1 = forward
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~UlvSolvePlan() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
+namespace {
+
+constexpr size_t kSolveLdsMax = 160 * 1024;
+
+std::shared_ptr<UlvSolvePlan> make_plan(const hss_ulv_s *F, int nrhs, hipStream_t s) {
+    auto P = std::make_shared<UlvSolvePlan>();
+    P->nrhs = nrhs;
+    P->n = F->n;
     const int nn = (int)F->node.size();
     std::vector<int64_t> ob(nn), oz(nn), oc(nn);
     int64_t nb = 0, nz = 0, nc = 0;
@@ -455,8 +512,10 @@ void ulv_solve(const hss_ulv_s *F, const double *Bin, int nrhs, double *Xout, hi
         oz[i] = nz; nz += (int64_t)(q.m - q.k) * nrhs;
         oc[i] = nc; nc += (int64_t)q.k * nrhs;
     }
-    DBuf bw = dalloc<double>(std::max<int64_t>(nb, 1)), zb = dalloc<double>(std::max<int64_t>(nz, 1)),
-         cb = dalloc<double>(std::max<int64_t>(nc, 1));
+    P->bw = dalloc<double>(std::max<int64_t>(nb, 1));
+    P->zb = dalloc<double>(std::max<int64_t>(nz, 1));
+    P->cb = dalloc<double>(std::max<int64_t>(nc, 1));
+    double *bw = P->bw.as<double>(), *zb = P->zb.as<double>(), *cb = P->cb.as<double>();
     auto make = [&](int id) {
         const HNode &q = F->node[id];
         SolveDesc d;
@@ -470,50 +529,105 @@ void ulv_solve(const hss_ulv_s *F, const double *Bin, int nrhs, double *Xout, hi
         d.tau = F->T.as<double>() + F->offT[id];
         d.L = F->L.as<double>() + F->offL[id];
         d.W = F->W.as<double>() + F->offW[id];
-        d.bw = bw.as<double>() + ob[id];
-        d.z = zb.as<double>() + oz[id];
-        d.c_out = cb.as<double>() + oc[id];
+        d.bw = bw + ob[id];
+        d.z = zb + oz[id];
+        d.c_out = cb + oc[id];
         if (!d.leaf) {
             d.kl = F->node[q.left].k;
             d.kr = F->node[q.right].k;
-            d.c_l = cb.as<double>() + oc[q.left];
-            d.c_r = cb.as<double>() + oc[q.right];
+            d.c_l = cb + oc[q.left];
+            d.c_r = cb + oc[q.right];
         }
         if (!d.root) {
             const HNode &p = F->node[q.parent];
             int64_t off = (p.left == id) ? 0 : (int64_t)F->node[p.left].k;
-            d.x_par = bw.as<double>() + ob[q.parent] + off * nrhs;
+            d.x_par = bw + ob[q.parent] + off * nrhs;
         }
         return d;
     };
-    std::vector<DBuf> keep;
-    std::vector<std::vector<SolveDesc>> hold;  // host copies stay alive until the final sync
-    auto nmax_of = [&](const std::vector<SolveDesc> &v) {
+    auto add = [&](const std::vector<SolveDesc> &v, int forward) {
+        if (v.empty()) return;
         int nm = 1;
         for (const auto &d : v) nm = std::max(nm, d.m);
-        return nm;
+        KRR_REQUIRE(sizeof(double) * nm * (BG_T / 64) <= kSolveLdsMax,
+                    "ULV solve: a node of %d rows exceeds the LDS budget", nm);
+        P->desc.push_back(upload(v, s));
+        P->cnt.push_back((int)v.size());
+        P->nmax.push_back(nm);
+        P->fwd.push_back(forward);
+        sync(s);  // `v` is a temporary of the caller
     };
     for (const auto &lv : F->levels) {
-        hold.emplace_back();
-        for (int id : lv) hold.back().push_back(make(id));
-        const int nm = nmax_of(hold.back());
-        keep.push_back(upload(hold.back(), s));
-        k_ulv_fwd<<<(unsigned)hold.back().size(), BG_T, sizeof(double) * nm * (BG_T / 64), s>>>(
-            keep.back().as<SolveDesc>(), Bin, nrhs, nm, Xout);
-        check_launch("k_ulv_fwd");
+        std::vector<SolveDesc> v;
+        for (int id : lv) v.push_back(make(id));
+        add(v, 1);
     }
     for (int h = (int)F->levels.size() - 1; h >= 0; --h) {
-        hold.emplace_back();
+        std::vector<SolveDesc> v;
         for (int id : F->levels[h])
-            if (F->node[id].parent >= 0) hold.back().push_back(make(id));
-        if (hold.back().empty()) continue;
-        const int nm = nmax_of(hold.back());
-        keep.push_back(upload(hold.back(), s));
-        k_ulv_bwd<<<(unsigned)hold.back().size(), BG_T, sizeof(double) * nm * (BG_T / 64), s>>>(
-            keep.back().as<SolveDesc>(), Xout, nrhs, nm);
-        check_launch("k_ulv_bwd");
+            if (F->node[id].parent >= 0) v.push_back(make(id));
+        add(v, 0);
     }
-    sync(s);
+    return P;
+}
+
+void enqueue_solve(const UlvSolvePlan &P, const double *Bin, double *Xout, hipStream_t s) {
+    for (size_t l = 0; l < P.desc.size(); ++l) {
+        const size_t lds = sizeof(double) * P.nmax[l] * (BG_T / 64);
+        if (P.fwd[l]) {
+            k_ulv_fwd<<<(unsigned)P.cnt[l], BG_T, lds, s>>>(P.desc[l].as<SolveDesc>(), Bin, P.nrhs, P.nmax[l], Xout);
+            check_launch("k_ulv_fwd");
+        } else {
+            k_ulv_bwd<<<(unsigned)P.cnt[l], BG_T, lds, s>>>(P.desc[l].as<SolveDesc>(), Xout, P.nrhs, P.nmax[l]);
+            check_launch("k_ulv_bwd");
+        }
+    }
+}
+
+void capture(UlvSolvePlan &P) {
+    P.in = dalloc<double>((size_t)P.n * P.nrhs);
+    P.out = dalloc<double>((size_t)P.n * P.nrhs);
+    hipStream_t cs = nullptr;
+    KRR_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    try {
+        KRR_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        try {
+            enqueue_solve(P, P.in.as<double>(), P.out.as<double>(), cs);
+        } catch (...) {
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(cs, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        KRR_HIP(hipStreamEndCapture(cs, &P.graph));
+        KRR_HIP(hipGraphInstantiate(&P.exec, P.graph, nullptr, nullptr, 0));
+    } catch (...) {
+        (void)hipStreamDestroy(cs);
+        throw;
+    }
+    KRR_HIP(hipStreamDestroy(cs));
+}
+
+}  // namespace
+
+void ulv_solve(const hss_ulv_s *F, const double *Bin, int nrhs, double *Xout, hipStream_t s) {
+    auto *Fm = const_cast<hss_ulv_s *>(F);  // the plan cache is not part of the factor's value
+    std::shared_ptr<UlvSolvePlan> P;
+    for (auto &q : Fm->plans)
+        if (q->nrhs == nrhs) P = q;
+    if (!P) {
+        P = make_plan(F, nrhs, s);
+        Fm->plans.push_back(P);
+    }
+    if (!F->use_graph) {
+        enqueue_solve(*P, Bin, Xout, s);
+        return;
+    }
+    if (!P->exec) capture(*P);
+    const size_t bytes = sizeof(double) * (size_t)F->n * nrhs;
+    KRR_HIP(hipMemcpyAsync(P->in.get(), Bin, bytes, hipMemcpyDeviceToDevice, s));
+    KRR_HIP(hipGraphLaunch(P->exec, s));
+    KRR_HIP(hipMemcpyAsync(Xout, P->out.get(), bytes, hipMemcpyDeviceToDevice, s));
 }
 
 }  // namespace krr

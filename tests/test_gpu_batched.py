@@ -206,3 +206,33 @@ def test_batched_refine_without_preconditioner(gpu_lib):
     for k, p in enumerate(ps):
         ref = ok.krr_fit_dense(p.X, p.y, p.h, p.lam)
         assert np.linalg.norm(a[off[k]:off[k + 1]] - ref) <= 1e-7 * np.linalg.norm(ref), k
+
+
+def test_batched_shift_per_problem(gpu_lib):
+    # one problem whose truncated compression needs a diagonal shift to factor
+    # (16-Gaussian data, rank capped at r - p) beside one with K = I exactly
+    # (h -> 0): only the first is shifted, and each problem's factor solves
+    # its own K_hss + lambda_k (1 + s_k) I
+    hard = sd.c2_sixteen_gaussians(n=16384, m=1)
+    easy = sd.c1_two_gaussians(n=1000, m=1)
+    X = np.concatenate([hard.X, easy.X.astype(np.float32)])
+    off = np.array([0, 16384, 17384], dtype=np.int64)
+    hs = [hard.h, 1e-3]
+    lams = [hard.lam, 0.5]
+    perm, tree = gpu_lib.cluster_2mn_batched(_t(X), off, 128, 7)
+    Xp = X[perm.cpu().numpy()]
+    opts = gpu_lib.HssOptions(rtol=1e-2, atol=3.0, r0=128, dr=128, r_max=128, prec="f16", cap_policy=1)
+    H = gpu_lib.BatchedHSS(tree, _t(Xp), hs, opts)
+    F = gpu_lib.BatchedULV(H, lams, shifted=True)
+    s = F.shift_mults
+    assert s[1] == 0.0
+    B = sd.vectors(X.shape[0], 2, seed=3)
+    x = F.solve(_t(B))
+    r = (H.matvec(x)).cpu().numpy() - B
+    xs = x.cpu().numpy()
+    for k in range(2):
+        a, b = off[k], off[k + 1]
+        rk = r[a:b] + lams[k] * (1.0 + s[k]) * xs[a:b]
+        assert np.linalg.norm(rk) <= 1e-9 * np.linalg.norm(B[a:b]), (k, s)
+    # the easy problem is the identity plus its lambda: x = b / (1 + lambda)
+    np.testing.assert_allclose(xs[off[1]:], B[off[1]:] / (1.0 + lams[1]), rtol=1e-13)

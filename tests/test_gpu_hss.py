@@ -172,3 +172,27 @@ def test_hss_matvec_matches_assembled(gpu_lib):
     x = sd.vectors(p.n, 3, seed=21)
     got = H.matvec(_t(x)).cpu().numpy()
     np.testing.assert_allclose(got, A @ x, rtol=1e-12, atol=1e-12 * np.abs(A @ x).max())
+
+
+def test_ulv_graph_replays_match_eager(gpu_lib):
+    # the captured solve graph replayed several times, with other device work
+    # and synchronizations in between, gives exactly the direct launches' result
+    p = sd.c1_two_gaussians()
+    t, Xp, H = _compress(gpu_lib, p.X, p.leaf, p.h, 1e-4)
+    F = gpu_lib.ULV(H, p.lam)
+    for nrhs in (1, 3):
+        Bs = [_t(sd.vectors(p.n, nrhs, seed=20 + i)) for i in range(4)]
+        F.use_graph(False)
+        eager = [F.solve(B).clone() for B in Bs]
+        F.use_graph(True)
+        for rep in range(3):
+            for i, B in enumerate(Bs):
+                junk = torch.randn(1 << 16, device="cuda").sum()  # unrelated work on the stream
+                got = F.solve(B)
+                torch.cuda.synchronize()
+                assert torch.equal(got, eager[i]), (nrhs, rep, i)
+                del junk
+        # in place (B and the solution share memory)
+        B = Bs[0].clone()
+        F.solve(B, out=B)
+        assert torch.equal(B, eager[0])
