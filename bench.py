@@ -33,6 +33,35 @@ sys.path.insert(0, ROOT)
 PEAK = {"f16": 2.5e15, "bf16": 2.5e15, "f32": 157.3e12, "f64": 78.6e12}
 PEAK_FP64_VECTOR = 78.6e12
 
+# HBM traffic per launch at n = 2^20, d = 8 (r = 256 for the sampler), from
+# two hardware-counter runs of `bench.py --kernels-only` (FETCH_SIZE, then
+# WRITE_SIZE, KiB per dispatch), each scaled by what the counter reads for a
+# plain 1 GiB device copy in the same run (FETCH_SIZE 524,315 KiB -> x2.000;
+# WRITE_SIZE 1,048,576 KiB -> x1.000).  Valid only while the kernel's source
+# file is unchanged (sha256 below); otherwise the bench reports null.
+PMC_TRAFFIC = {
+    "sampling": {"fetch_kib": 35674236.125, "write_kib": 1048576.0, "fetch_scale": 2.0, "write_scale": 1.0,
+                 "source": "paper_1803_10274_amd/csrc/sample_mfma.hip",
+                 "sha256": "34a228afb2cf46c429fcd00819fd17c5f9e5c103f9a09bb91169f0ad2abd2e13", "n": 1 << 20, "r": 256},
+    "kernel_product": {"fetch_kib": 1394495.0, "write_kib": 16384.0, "fetch_scale": 2.0, "write_scale": 1.0,
+                       "source": "paper_1803_10274_amd/csrc/matvec.hip",
+                       "sha256": "4f55f48be5d3ad2a63f2ae4b03f489221f786ca2a50ebf37bcc39ea70812665d",
+                       "n": 1 << 20, "r": None},
+}
+
+
+def pmc_traffic(kind, n, r=None):
+    """Calibrated HBM bytes per launch, or None if the counters do not
+    describe the current kernel and size."""
+    import hashlib
+    t = PMC_TRAFFIC[kind]
+    if t["n"] != n or (t["r"] is not None and t["r"] != r):
+        return None
+    with open(os.path.join(ROOT, t["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != t["sha256"]:
+            return None
+    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -52,7 +81,36 @@ def parse():
     ap.add_argument("--no-grad", action="store_true", help="skip the gradient leg")
     ap.add_argument("--kernels-only", action="store_true", help="one launch of each hot kernel (profiling)")
     ap.add_argument("--reps", type=int, default=3, help="launches per kernel timing")
+    ap.add_argument("--summarize-trace", metavar="CSV",
+                    help="print per-(kernel, grid) launch statistics of a rocprofv3 kernel-trace CSV and exit")
     return ap.parse_args()
+
+
+def summarize_trace(path, top=25):
+    """Launch statistics of a rocprofv3 kernel trace grouped by kernel and grid
+    size (the same kernel at different sizes is listed separately)."""
+    import csv
+    groups = {}
+    with open(path, newline="") as f:
+        for row in csv.DictReader(f):
+            grid = row.get("Grid_Size") or "x".join(row.get(k, "?") for k in ("Grid_Size_X", "Grid_Size_Y",
+                                                                            "Grid_Size_Z"))
+            key = (row["Kernel_Name"], grid)
+            dur = int(row["End_Timestamp"]) - int(row["Start_Timestamp"])
+            g = groups.setdefault(key, [0, 0, None, 0])
+            g[0] += 1
+            g[1] += dur
+            g[2] = dur if g[2] is None else min(g[2], dur)
+            g[3] = max(g[3], dur)
+    total = sum(g[1] for g in groups.values())
+    print("| kernel | grid | calls | total ms | avg ms | min ms | max ms | % |")
+    print("|---|---|---|---|---|---|---|---|")
+    for (name, grid), (c, t, lo, hi) in sorted(groups.items(), key=lambda kv: -kv[1][1])[:top]:
+        short = name.split("(")[0].replace("krr::(anonymous namespace)::", "").replace("void ", "")
+        if short.startswith("krr::"):
+            short = short[5:]
+        print(f"| {short[:70]} | {grid} | {c} | {t / 1e6:.3f} | {t / c / 1e6:.3f} | {lo / 1e6:.3f} | {hi / 1e6:.3f} | "
+              f"{100.0 * t / total:.2f} |")
 
 
 def log(*a):
@@ -118,6 +176,9 @@ def kernels_only(args):
 
 def main():
     args = parse()
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
@@ -197,14 +258,16 @@ def main():
     peak = PEAK[args.prec if args.prec in PEAK else "f16"]
     executed = achieved * (args.split if args.prec in ("f16", "bf16") else 1)
     roof_sample = {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                   "frac": achieved / peak, "traffic": None, "kernel": "k_sample_mfma (sampling product S = K R)",
+                   "frac": achieved / peak, "traffic": pmc_traffic("sampling", n, r),
+                   "kernel": "k_sample_mfma (sampling product S = K R)",
                    "launch_s": t_sample, "algorithmic_flops": flops, "executed_mfma_frac": executed / peak}
     del R
     w = res.alpha_perm.reshape(n, -1)[:, :1].contiguous()
     t_mv = time_launches(lambda: krr.kernel_matvec(Xp, Xp, p.h, w, prec="f32"), args.reps)
     mv_flops = float(n) * n * (2 * p.d + 2)
     roof_mv = {"bound": "alu", "achieved": mv_flops / t_mv / 1e12, "peak": PEAK_FP64_VECTOR / 1e12,
-               "unit": "TFLOP/s", "frac": mv_flops / t_mv / PEAK_FP64_VECTOR, "traffic": None,
+               "unit": "TFLOP/s", "frac": mv_flops / t_mv / PEAK_FP64_VECTOR,
+               "traffic": pmc_traffic("kernel_product", n),
                "kernel": "k_kmv_sc (refinement product K w, FP64 exponent, FP32 entries)", "launch_s": t_mv,
                "algorithmic_flops": mv_flops, "entries_per_s": float(n) * n / t_mv}
     log(f"sampling {t_sample * 1e3:.1f} ms ({achieved / 1e12:.1f} TFLOP/s); "

@@ -78,7 +78,7 @@ class Tree:
                                     ctypes.byref(cnt)))
 
     def __del__(self):
-        if getattr(self, "h", None) and _lib._lib is not None:
+        if getattr(self, "h", None) and _lib is not None and _lib._lib is not None:
             _lib._lib.krr_tree_destroy(self.h)
             self.h = None
 
@@ -249,7 +249,7 @@ class HSS:
         return {"nodes": table, "U": U, "D": D, "B": B, "J": J}
 
     def __del__(self):
-        if getattr(self, "h", None) and _lib._lib is not None:
+        if getattr(self, "h", None) and _lib is not None and _lib._lib is not None:
             _lib._lib.hss_destroy(self.h)
             self.h = None
 
@@ -292,7 +292,7 @@ class ULV:
         return out.reshape(B.shape)
 
     def __del__(self):
-        if getattr(self, "h", None) and _lib._lib is not None:
+        if getattr(self, "h", None) and _lib is not None and _lib._lib is not None:
             _lib._lib.hss_ulv_destroy(self.h)
             self.h = None
 
