@@ -397,6 +397,21 @@ int krr_refine_batched(hss_ulv_t F, const void *Xp, int32_t xprec, const int64_t
                        int32_t max_iter, int32_t mv_prec, void *stream,
                        krr_refine_stats *stats_host, double *relres_host);
 
+/* ------------------------------------------------------------ tuning */
+
+/* Launch-shape knobs of the hot kernels (process-wide; the autotuner in the
+ * Python package sets them from its cache).  Values are validated; results
+ * do not depend on them beyond floating-point summation order. */
+enum {
+    KRR_TUNE_SYMMETRIC = 0,  /* 1: K(X, X) W evaluates each off-diagonal entry once (default 1) */
+    KRR_TUNE_SAMPLE_RB = 1,  /* max 32-column blocks per sampling pass: 1, 2, 4 or 8 (default 8) */
+    KRR_TUNE_MV_BLOCKS = 2,  /* workgroups the split-K kernel product aims for, 64..65536 (default 2048) */
+    KRR_TUNE_SYM_CHUNK = 3,  /* columns per item of the symmetric product, multiple of 64 (default 16384) */
+    KRR_TUNE_COUNT = 4
+};
+int krr_set_tuning(int32_t knob, int32_t value);
+int krr_get_tuning(int32_t knob, int32_t *value_host);
+
 /* ------------------------------------------------ small vector kernels */
 
 /* out[c] = sum_i a[i, c] * b[i, c] (n x k FP64, deterministic order; device out). */

@@ -180,6 +180,21 @@ def kernel_matvec_bwd(X, Y, h, W, G, prec="f32", want=("dX", "dY", "dW", "dh")):
     return {k: v for k, v in out.items() if v is not None}
 
 
+TUNE = {"symmetric": _lib.KRR_TUNE_SYMMETRIC, "sample_rb": _lib.KRR_TUNE_SAMPLE_RB,
+        "mv_blocks": _lib.KRR_TUNE_MV_BLOCKS, "sym_chunk": _lib.KRR_TUNE_SYM_CHUNK}
+
+
+def set_tuning(knob: str, value: int):
+    """Set a launch-shape knob of the hot kernels (process-wide)."""
+    check(load().krr_set_tuning(TUNE[knob], int(value)))
+
+
+def get_tuning(knob: str) -> int:
+    v = ctypes.c_int32()
+    check(load().krr_get_tuning(TUNE[knob], ctypes.byref(v)))
+    return v.value
+
+
 def dot_columns(a, b):
     a2 = _dev(a, torch.float64).reshape(a.shape[0], -1)
     b2 = _dev(b, torch.float64).reshape(b.shape[0], -1)

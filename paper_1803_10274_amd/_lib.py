@@ -9,6 +9,7 @@ LIB_PATH = os.path.join(HERE, "libkrr.so")
 KRR_OK, KRR_E_INVAL, KRR_E_NOMEM, KRR_E_HIP = 0, -1, -2, -3
 KRR_E_RANK_CAP, KRR_E_NUMERIC, KRR_E_NOT_CONVERGED, KRR_E_NODEVICE = -4, -5, -6, -7
 KRR_F64, KRR_F32, KRR_F16_SPLIT, KRR_BF16_SPLIT = 0, 1, 2, 3
+KRR_TUNE_SYMMETRIC, KRR_TUNE_SAMPLE_RB, KRR_TUNE_MV_BLOCKS, KRR_TUNE_SYM_CHUNK = 0, 1, 2, 3
 
 _CODES = {KRR_E_INVAL: "KRR_E_INVAL", KRR_E_NOMEM: "KRR_E_NOMEM", KRR_E_HIP: "KRR_E_HIP",
           KRR_E_RANK_CAP: "KRR_E_RANK_CAP", KRR_E_NUMERIC: "KRR_E_NUMERIC",
@@ -81,6 +82,8 @@ SIGNATURES = {
                                   _P(RefineStats)]),
     "krr_predict": (ctypes.c_int, [_vp, _i64, _vp, _i64, _i32, _i32, _dbl, _vp, _i32, _vp, _vp, _i32, _vp]),
     "krr_dot_columns": (ctypes.c_int, [_vp, _vp, _i64, _i32, _vp, _vp]),
+    "krr_set_tuning": (ctypes.c_int, [_i32, _i32]),
+    "krr_get_tuning": (ctypes.c_int, [_i32, _P(_i32)]),
     # batched form
     "krr_cluster_2mn_batched": (ctypes.c_int, [_vp, _i32, _P(_i64), _i32, _i32, _P(ClusterOpts), _vp, _vp,
                                                _P(_vp)]),

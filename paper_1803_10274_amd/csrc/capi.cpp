@@ -2,6 +2,7 @@
 // checks, handle lifetime, and translation of internal failures into status
 // codes with a per-thread message.  Nothing throws across this boundary.
 #include <algorithm>
+#include <atomic>
 #include <cstdarg>
 #include <cstdlib>
 #include <cstring>
@@ -13,6 +14,10 @@
 namespace krr {
 
 thread_local std::string g_last_error;
+
+std::atomic<int> g_tune[KRR_TUNE_COUNT] = {{1}, {8}, {2048}, {16384}};
+
+int tune_get(int knob) { return g_tune[knob].load(std::memory_order_relaxed); }
 
 bool verbose() {
     static const bool v = [] {
@@ -480,6 +485,32 @@ int krr_predict(const void *Xt, int64_t m, const void *Xp, int64_t n, int32_t d,
         require_device();
         kernel_matvec_impl(Xt, m, Xp, n, d, xprec, h, alpha, nrhs, 0.0, scores, prec, S(stream));
         if (labels) predict_labels(scores, m, nrhs, labels, S(stream));
+        return KRR_OK;
+    });
+}
+
+int krr_set_tuning(int32_t knob, int32_t value) {
+    return guard([&] {
+        KRR_REQUIRE(knob >= 0 && knob < KRR_TUNE_COUNT, "krr_set_tuning: unknown knob %d", knob);
+        switch (knob) {
+            case KRR_TUNE_SYMMETRIC: KRR_REQUIRE(value == 0 || value == 1, "krr_set_tuning: symmetric is 0 or 1"); break;
+            case KRR_TUNE_SAMPLE_RB:
+                KRR_REQUIRE(value == 1 || value == 2 || value == 4 || value == 8, "krr_set_tuning: sample RB is 1, 2, 4 or 8");
+                break;
+            case KRR_TUNE_MV_BLOCKS: KRR_REQUIRE(value >= 64 && value <= 65536, "krr_set_tuning: blocks in [64, 65536]"); break;
+            case KRR_TUNE_SYM_CHUNK:
+                KRR_REQUIRE(value >= 64 && value % 64 == 0 && value <= (1 << 24), "krr_set_tuning: chunk multiple of 64");
+                break;
+        }
+        g_tune[knob].store(value, std::memory_order_relaxed);
+        return KRR_OK;
+    });
+}
+
+int krr_get_tuning(int32_t knob, int32_t *value_host) {
+    return guard([&] {
+        KRR_REQUIRE(knob >= 0 && knob < KRR_TUNE_COUNT && value_host, "krr_get_tuning: bad arguments");
+        *value_host = tune_get(knob);
         return KRR_OK;
     });
 }

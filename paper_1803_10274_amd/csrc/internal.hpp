@@ -73,6 +73,9 @@ std::vector<SampBlock> row_blocks(const Batch &b, int rows);
 // Diagnostic logging to stderr when the environment sets KRR_VERBOSE.
 bool verbose();
 
+// Current value of a KRR_TUNE_* knob.
+int tune_get(int knob);
+
 }  // namespace krr
 
 struct hss_s {

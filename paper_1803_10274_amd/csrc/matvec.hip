@@ -203,6 +203,182 @@ __global__ __launch_bounds__(MV_ROWS) void k_kmv_sc(const T *__restrict__ X, int
 // Rows per thread of k_kmv_sc by width (register budget).
 constexpr int sc_rpt(int D) { return D <= 16 ? 4 : (D <= 24 ? 3 : (D <= 32 ? 2 : 1)); }
 
+// ------------------------------------------------ symmetric kernel product
+//
+// y = K(X, X) w uses K's symmetry: the entries right of each row block's
+// diagonal block are evaluated once and used twice, for the block's rows
+// (row sums, as in k_kmv_sc) and for the columns (column sums reduced across
+// the workgroup's rows).  An item is one row block (RPT * 256 rows) against
+// one chunk of columns right of its diagonal block, inside its problem.
+// Row partials go to rowpart[chunk][row] (FP64), column partials to
+// colpart[block][column] (FP32: a 256-term tree sum per block and column), and
+// k_sym_reduce adds them in a fixed order with the diagonal blocks' products.
+struct SymItem {
+    int64_t i0, iend, j0, j1;
+    int64_t blk, chunk;
+    double c2;
+};
+
+template <class T, int D, int NR, int RPT>
+__global__ __launch_bounds__(MV_ROWS) void k_kmv_sym(const T *__restrict__ X, int d, const double *__restrict__ ya,
+                                                     const float *__restrict__ wf, int nrhs, int64_t n,
+                                                     const SymItem *__restrict__ items, double *__restrict__ rowpart,
+                                                     float *__restrict__ colpart) {
+    constexpr int LD = ColLd<D>::V;
+    constexpr int NW = MV_ROWS / 64;
+    __shared__ __attribute__((aligned(16))) double ys[MV_TN][LD];
+    __shared__ float ws[MV_TN][NR];
+    __shared__ float csum[NW][NR][64];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const SymItem it = items[blockIdx.x];
+    const double c2 = it.c2;
+    double xs[RPT][D];
+    double nx[RPT];
+    float wi[RPT][NR];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int64_t i = it.i0 + tid + (int64_t)MV_ROWS * q;
+        const bool ok = i < it.iend;
+        double a = 0.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            double v = (ok && k < d) ? (double)X[i * d + k] : 0.0;
+            a = fma(v, v, a);
+            xs[q][k] = v;
+        }
+        nx[q] = -c2 * a;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) wi[q][r] = ok ? wf[i * nrhs + r] : 0.0f;
+    }
+    double acc[RPT][NR];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q)
+#pragma unroll
+        for (int r = 0; r < NR; ++r) acc[q][r] = 0.0;
+    for (int64_t jt = it.j0; jt < it.j1; jt += MV_TN) {
+        const int64_t cnt = min((int64_t)MV_TN, it.j1 - jt);
+        const double *src = ya + jt * LD;
+        for (int t = tid; t < MV_TN * LD; t += MV_ROWS) {
+            const int jj = t / LD, k = t % LD;
+            ys[jj][k] = jj < cnt ? src[t] : (k == D ? -INFINITY : 0.0);
+        }
+        for (int t = tid; t < MV_TN * NR; t += MV_ROWS) {
+            const int jj = t / NR, r = t % NR;
+            ws[jj][r] = jj < cnt ? wf[(jt + jj) * nrhs + r] : 0.0f;
+        }
+        __syncthreads();
+        float pacc[RPT][NR];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q)
+#pragma unroll
+            for (int r = 0; r < NR; ++r) pacc[q][r] = 0.0f;
+        // columns in groups of 8: this lane's rows' contributions to each column
+        // of the group are summed across the wave (reduce-scatter inside each
+        // 8-lane group, then across the groups), leaving column jg + (l & 7) in
+        // lane l; the four waves' sums meet in LDS
+#pragma unroll 1
+        for (int jg = 0; jg < MV_TN; jg += 8) {
+            float cacc[8][NR];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int jj = jg + u;
+                double yv[D + 1];
+#pragma unroll
+                for (int k = 0; k <= D; ++k) yv[k] = ys[jj][k];
+                float wv[NR];
+#pragma unroll
+                for (int r = 0; r < NR; ++r) {
+                    wv[r] = ws[jj][r];
+                    cacc[u][r] = 0.0f;
+                }
+#pragma unroll
+                for (int q = 0; q < RPT; ++q) {
+                    double t = nx[q] + yv[D];
+#pragma unroll
+                    for (int k = 0; k < D; ++k) t = fma(xs[q][k], yv[k], t);
+                    const float kv = __builtin_amdgcn_exp2f((float)t);
+#pragma unroll
+                    for (int r = 0; r < NR; ++r) {
+                        pacc[q][r] = fmaf(kv, wv[r], pacc[q][r]);
+                        cacc[u][r] = fmaf(kv, wi[q][r], cacc[u][r]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int o = 4; o >= 1; o >>= 1) {
+                const bool up = (lane & o) != 0;
+#pragma unroll
+                for (int kk = 0; kk < o; ++kk)
+#pragma unroll
+                    for (int r = 0; r < NR; ++r) {
+                        const float a = cacc[kk][r], b = cacc[kk + o][r];
+                        const float send = up ? a : b;
+                        cacc[kk][r] = (up ? b : a) + __shfl_xor(send, o, 64);
+                    }
+            }
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                float v = cacc[0][r];
+                v += __shfl_xor(v, 8, 64);
+                v += __shfl_xor(v, 16, 64);
+                v += __shfl_xor(v, 32, 64);
+                if (lane < 8) csum[wv][r][jg + lane] = v;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < RPT; ++q)
+#pragma unroll
+            for (int r = 0; r < NR; ++r) acc[q][r] += (double)pacc[q][r];
+        __syncthreads();
+        if (wv == 0 && lane < cnt) {
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                float c = csum[0][r][lane];
+#pragma unroll
+                for (int w = 1; w < NW; ++w) c += csum[w][r][lane];
+                colpart[((int64_t)it.blk * n + jt + lane) * NR + r] = c;
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int64_t i = it.i0 + tid + (int64_t)MV_ROWS * q;
+        if (i < it.iend)
+            for (int r = 0; r < NR; ++r) rowpart[((int64_t)it.chunk * n + i) * NR + r] = acc[q][r];
+    }
+}
+
+// Per row block of the symmetric product (problem order).
+struct SymBlock {
+    int64_t i0, iend;
+    int64_t first_blk;           // the problem's first block
+    int64_t chunk_lo, chunk_hi;  // chunks holding this block's row partials
+};
+
+// Out[i] = diag[i] + sum of the row partials of i's block + the column
+// partials of i from the earlier blocks of its problem (+ beta Out[i]).
+template <int NR>
+__global__ void k_sym_reduce(const SymBlock *__restrict__ blocks, int rows_pb, const double *__restrict__ diag,
+                             const double *__restrict__ rowpart, const float *__restrict__ colpart, int64_t n,
+                             double beta, double *__restrict__ out) {
+    const SymBlock b = blocks[blockIdx.y];
+    const int64_t i = b.i0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= b.iend) return;
+    const int64_t blk = blockIdx.y;
+    double s[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) s[r] = diag[i * NR + r];
+    for (int64_t c = b.chunk_lo; c < b.chunk_hi; ++c)
+#pragma unroll
+        for (int r = 0; r < NR; ++r) s[r] += rowpart[(c * n + i) * NR + r];
+    for (int64_t bb = b.first_blk; bb < blk; ++bb)
+#pragma unroll
+        for (int r = 0; r < NR; ++r) s[r] += (double)colpart[(bb * n + i) * NR + r];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) out[i * NR + r] = beta != 0.0 ? s[r] + beta * out[i * NR + r] : s[r];
+}
+
 // Column data of k_kmv_sc: ya[j] = (2 c y_j1 .. 2 c y_jd, 0 .., -c |y_j|^2 at
 // index D, 0 ..) in rows of ld doubles, c the column's problem's scale
 // (pbeg / cprob: a batch) or c2.
@@ -386,9 +562,137 @@ int sc_width(int d) {
     return 64;
 }
 
+
+// Column data ya and FP32 weights wf of the FP32-entry kernels.
+template <class T>
+void prep_columns(const T *Y, int64_t n, int d, int D, double c2, const double *W, int nrhs, const Batch *batch,
+                  DBuf &ya, DBuf &wf, hipStream_t s) {
+    const int LD = (D + 2) & ~1;  // ColLd
+    ya = dalloc<double>((size_t)n * LD);
+    wf = dalloc<float>((size_t)n * nrhs);
+    DBuf pb, cp;
+    if (batch) {
+        std::vector<double> cpr(batch->np());
+        for (int k = 0; k < batch->np(); ++k) cpr[k] = kernel_scale_log2(batch->h[k]);
+        pb = upload(batch->pbeg, s);
+        cp = upload(cpr, s);
+        sync(s);  // `cpr` is released at the end of this scope
+    }
+    k_col_aug<T><<<ceil_div(n, 256), 256, 0, s>>>(Y, n, d, D, LD, c2, pb.as<int64_t>(), cp.as<double>(),
+                                                  batch ? batch->np() : 0, ya.as<double>());
+    check_launch("k_col_aug");
+    k_w_to_float<<<ceil_div(n * nrhs, 256), 256, 0, s>>>(W, n * nrhs, wf.as<float>());
+    check_launch("k_w_to_float");
+    sync(s);  // pb / cp are released on return
+}
+
+template <class T, int D, int NR>
+void launch_sym(dim3 gd, dim3 gs, dim3 gr, int rows_pb, const T *X, int d, double c2, const double *ya,
+                const float *wf, int64_t n, const SampBlock *dt, const SymItem *it, const SymBlock *bl, double *diag,
+                double *rowpart, float *colpart, double beta, double *Out, hipStream_t s) {
+    constexpr int RPT = sc_rpt(D);
+    k_kmv_sc<T, D, NR, RPT><<<gd, MV_ROWS, 0, s>>>(X, n, d, c2, ya, wf, NR, 0, n, 0, diag, dt);
+    check_launch("k_kmv_sc (diagonal blocks)");
+    if (gs.x > 0) {
+        k_kmv_sym<T, D, NR, RPT><<<gs, MV_ROWS, 0, s>>>(X, d, ya, wf, NR, n, it, rowpart, colpart);
+        check_launch("k_kmv_sym");
+    }
+    k_sym_reduce<NR><<<gr, 256, 0, s>>>(bl, rows_pb, diag, rowpart, colpart, n, beta, Out);
+    check_launch("k_sym_reduce");
+}
+
+// The symmetric product y = K(X, X) W + beta y (FP32 entries) when it
+// applies (d <= 16, one or two right-hand sides, partial sums within budget);
+// returns false otherwise.
+template <class T>
+bool kmv_sym(const T *X, int64_t n, int d, double h, const double *W, int nrhs, double beta, double *Out,
+             hipStream_t s, const Batch *batch) {
+    const int D = sc_width(d);
+    if (D > 16 || (nrhs != 1 && nrhs != 2)) return false;
+    const int rows_pb = MV_ROWS * sc_rpt(D);
+    const int64_t CH = tune_get(KRR_TUNE_SYM_CHUNK);  // columns per item: a multiple of the tile width
+    std::vector<int64_t> pb = batch ? batch->pbeg : std::vector<int64_t>{0, n};
+    std::vector<double> hs = batch ? batch->h : std::vector<double>{h};
+    const int np = (int)hs.size();
+    std::vector<SymBlock> blocks;
+    std::vector<SymItem> items;
+    std::vector<SampBlock> diag;
+    int64_t nchunks = 0;
+    for (int p = 0; p < np; ++p) {
+        const double c2 = kernel_scale_log2(hs[p]);
+        const int64_t first = (int64_t)blocks.size(), pe = pb[p + 1];
+        for (int64_t i0 = pb[p]; i0 < pe; i0 += rows_pb) {
+            SymBlock b{};
+            b.i0 = i0;
+            b.iend = std::min<int64_t>(pe, i0 + rows_pb);
+            b.first_blk = first;
+            const int64_t blk = (int64_t)blocks.size(), off = b.iend;
+            if (off < pe) {
+                b.chunk_lo = off / CH;
+                b.chunk_hi = (pe - 1) / CH + 1;
+            }
+            for (int64_t c = b.chunk_lo; c < b.chunk_hi; ++c) {
+                SymItem it{};
+                it.i0 = b.i0;
+                it.iend = b.iend;
+                it.j0 = std::max(off, c * CH);
+                it.j1 = std::min(pe, (c + 1) * CH);
+                it.blk = blk;
+                it.chunk = c;
+                it.c2 = c2;
+                items.push_back(it);
+            }
+            nchunks = std::max(nchunks, b.chunk_hi);
+            blocks.push_back(b);
+            SampBlock sb{};
+            sb.i0 = b.i0;
+            sb.iend = b.iend;
+            sb.jlo = b.i0;
+            sb.jhi = b.iend;
+            sb.cps = rows_pb;
+            sb.c2 = c2;
+            diag.push_back(sb);
+        }
+    }
+    const double col_bytes = (double)blocks.size() * n * nrhs * sizeof(float);
+    const double row_bytes = (double)nchunks * n * nrhs * sizeof(double);
+    if (col_bytes + row_bytes > 24e9) return false;  // the plain product needs no partial sums
+    const double c2 = kernel_scale_log2(h);
+    DBuf ya, wf;
+    prep_columns<T>(X, n, d, D, c2, W, nrhs, batch, ya, wf, s);
+    DBuf dd = dalloc<double>((size_t)n * nrhs), rp = dalloc<double>(std::max<size_t>((size_t)(row_bytes / 8), 1)),
+         cpart = dalloc<float>(std::max<size_t>((size_t)(col_bytes / 4), 1));
+    DBuf dt = upload(diag, s), it = upload(items, s), bl = upload(blocks, s);
+    sync(s);  // the host tables are released on return
+    dim3 gd((unsigned)diag.size()), gs((unsigned)items.size()), gr(ceil_div(rows_pb, 256), (unsigned)blocks.size());
+#define KRR_SYM(DD, NRR)                                                                                       \
+    launch_sym<T, DD, NRR>(gd, gs, gr, rows_pb, X, d, c2, ya.as<double>(), wf.as<float>(), n, dt.as<SampBlock>(), \
+                           it.as<SymItem>(), bl.as<SymBlock>(), dd.as<double>(), rp.as<double>(),              \
+                           cpart.as<float>(), beta, Out, s)
+    switch (D * 4 + nrhs) {
+        case 4 * 4 + 1: KRR_SYM(4, 1); break;
+        case 4 * 4 + 2: KRR_SYM(4, 2); break;
+        case 8 * 4 + 1: KRR_SYM(8, 1); break;
+        case 8 * 4 + 2: KRR_SYM(8, 2); break;
+        case 12 * 4 + 1: KRR_SYM(12, 1); break;
+        case 12 * 4 + 2: KRR_SYM(12, 2); break;
+        case 16 * 4 + 1: KRR_SYM(16, 1); break;
+        case 16 * 4 + 2: KRR_SYM(16, 2); break;
+        default: fail(KRR_E_INVAL, "kernel_matvec: no symmetric variant for width %d", D);
+    }
+#undef KRR_SYM
+    sync(s);  // temporaries are released on return
+    return true;
+}
+
 template <class T, class C>
 void kmv_typed(const T *X, int64_t m, const T *Y, int64_t n, int d, double h, const double *W, int nrhs,
                double beta, double *Out, hipStream_t s, const Batch *batch) {
+    if constexpr (sizeof(C) == 4) {
+        // K(X, X): each off-diagonal entry once, for its row and its column
+        if (X == Y && m == n && tune_get(KRR_TUNE_SYMMETRIC) && kmv_sym<T>(X, n, d, h, W, nrhs, beta, Out, s, batch))
+            return;
+    }
     const C scale = kernel_scale<C>(h);
     const double c2 = kernel_scale_log2(h);
     const bool sc = sizeof(C) == 4 && d <= 64;
@@ -403,7 +707,7 @@ void kmv_typed(const T *X, int64_t m, const T *Y, int64_t n, int d, double h, co
         nb = (int64_t)blocks.size();
         int64_t nmax = 0;
         for (int k = 0; k < batch->np(); ++k) nmax = std::max(nmax, batch->size(k));
-        nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(2048, nb), ceil_div(nmax, 4 * MV_TN)));
+        nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(tune_get(KRR_TUNE_MV_BLOCKS), nb), ceil_div(nmax, 4 * MV_TN)));
         for (auto &b : blocks) {
             int64_t c = ceil_div(b.jhi - b.jlo, nsplit);
             b.cps = (c + MV_TN - 1) / MV_TN * MV_TN;
@@ -412,7 +716,7 @@ void kmv_typed(const T *X, int64_t m, const T *Y, int64_t n, int d, double h, co
         sync(s);
     } else {
         const int64_t row_blocks = ceil_div(m, rows_pb);
-        nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(2048, row_blocks), ceil_div(n, 4 * MV_TN)));
+        nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(tune_get(KRR_TUNE_MV_BLOCKS), row_blocks), ceil_div(n, 4 * MV_TN)));
         cps = (int64_t)ceil_div(n, nsplit);
         cps = (cps + MV_TN - 1) / MV_TN * MV_TN;
         nsplit = (int)ceil_div(n, cps);

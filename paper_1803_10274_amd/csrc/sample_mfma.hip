@@ -16,6 +16,8 @@
 // multiplied into the FP32 accumulators with the random block, which is
 // pre-swizzled into the B-operand layout and staged through LDS.  The FP32
 // mode uses v_mfma_f32_32x32x2_f32 on the FP32 entries instead.
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace krr {
@@ -509,20 +511,21 @@ template <class T, int D, int MODE, int TERMS>
 void launch_passes(const T *X, int64_t n, int d, float cs, const void *Rsw, int r, const int32_t *lb,
                    const int32_t *le, float *S, hipStream_t s, const SampBlock *bt, int64_t nblk) {
     constexpr int RBM = RbMax<D, MODE>::V;
+    const int cap = std::min(RBM, tune_get(KRR_TUNE_SAMPLE_RB));  // column blocks per pass
     const int RBt = r / 32;
     int cb0 = 0;
     while (cb0 < RBt) {
         const int left = RBt - cb0;
         dim3 grid((unsigned)(bt ? nblk : ceil_div(n, ROWS)));
-        if (RBM >= 8 && left >= 8) {
+        if (RBM >= 8 && cap >= 8 && left >= 8) {
             k_sample_mfma<T, D, (RBM >= 8 ? 8 : RBM), MODE, TERMS><<<grid, THREADS, 0, s>>>(X, n, d, cs, Rsw, RBt, cb0,
                                                                                         lb, le, S, r, bt);
             cb0 += 8;
-        } else if (RBM >= 4 && left >= 4) {
+        } else if (RBM >= 4 && cap >= 4 && left >= 4) {
             k_sample_mfma<T, D, (RBM >= 4 ? 4 : RBM), MODE, TERMS><<<grid, THREADS, 0, s>>>(X, n, d, cs, Rsw, RBt, cb0,
                                                                                         lb, le, S, r, bt);
             cb0 += 4;
-        } else if (left >= 2) {
+        } else if (cap >= 2 && left >= 2) {
             k_sample_mfma<T, D, 2, MODE, TERMS><<<grid, THREADS, 0, s>>>(X, n, d, cs, Rsw, RBt, cb0, lb, le, S, r, bt);
             cb0 += 2;
         } else {

@@ -236,3 +236,16 @@ def test_batched_shift_per_problem(gpu_lib):
         assert np.linalg.norm(rk) <= 1e-9 * np.linalg.norm(B[a:b]), (k, s)
     # the easy problem is the identity plus its lambda: x = b / (1 + lambda)
     np.testing.assert_allclose(xs[off[1]:], B[off[1]:] / (1.0 + lams[1]), rtol=1e-13)
+
+
+def test_batched_symmetric_matvec_per_problem(gpu_lib):
+    # d = 8: the batched product takes the symmetric path (each problem's
+    # off-diagonal entries once), with per-problem widths
+    ps = _problems(d=8, n_hi=3000, seed=11)
+    X, off = _concat(ps)
+    W = sd.vectors(X.shape[0], 1, seed=2)
+    out = gpu_lib.kernel_matvec_batched(_t(X), off, [p.h for p in ps], _t(W), prec="f32").cpu().numpy()
+    for k, p in enumerate(ps):
+        a, b = off[k], off[k + 1]
+        ref = cmath.kmv(X[a:b], X[a:b], W[a:b], p.h)
+        assert np.all(np.abs(out[a:b] - ref) <= fp32_product_bound(X[a:b], X[a:b], W[a:b], p.h)), k

@@ -133,3 +133,49 @@ def test_matvec_backward(gpu_lib, prec, tol):
         got = out[name].cpu().numpy()
         assert np.linalg.norm(got - ref) <= tol * np.linalg.norm(ref), name
     assert abs(out["dh"].item() - dh) <= tol * abs(dh)
+
+
+@pytest.fixture
+def sym_chunk(gpu_lib):
+    """Small symmetric-product items (many chunks per row block), restored after."""
+    old = gpu_lib.get_tuning("sym_chunk")
+    gpu_lib.set_tuning("sym_chunk", 1024)
+    yield
+    gpu_lib.set_tuning("sym_chunk", old)
+
+
+@pytest.mark.parametrize("d", [3, 8, 16])
+@pytest.mark.parametrize("nrhs", [1, 2])
+def test_symmetric_product(gpu_lib, sym_chunk, d, nrhs):
+    # K(X, X) W with each off-diagonal entry evaluated once: 5000 points are
+    # 5 row blocks (a ragged last one) and several column chunks per block
+    n, h = 5000, 0.9
+    X = sd.points(n, d, seed=d, scale=0.7)
+    W = sd.vectors(n, nrhs, seed=nrhs)
+    Xd = _t(X)
+    out = gpu_lib.kernel_matvec(Xd, Xd, h, _t(W), prec="f32").cpu().numpy().reshape(n, nrhs)
+    ref = cmath.kmv(X, X, W, h)
+    assert np.all(np.abs(out - ref) <= fp32_product_bound(X, X, W, h))
+    # the plain product (the same points at another address) agrees to the same bound
+    plain = gpu_lib.kernel_matvec(Xd, Xd.clone(), h, _t(W), prec="f32").cpu().numpy().reshape(n, nrhs)
+    assert np.all(np.abs(plain - ref) <= fp32_product_bound(X, X, W, h))
+    # beta accumulates into the output
+    base = _t(W)
+    got = gpu_lib.kernel_matvec(Xd, Xd, h, _t(W), beta=0.5, out=base.clone(), prec="f32").cpu().numpy()
+    np.testing.assert_allclose(got.reshape(n, nrhs), out + 0.5 * W, rtol=0, atol=1e-12 + 1e-6 * np.abs(out).max())
+
+
+def test_symmetric_product_switch(gpu_lib):
+    n, d, h = 3000, 8, 1.1
+    X = sd.points(n, d, seed=4)
+    W = sd.vectors(n, 1, seed=5)
+    Xd = _t(X)
+    gpu_lib.set_tuning("symmetric", 0)
+    try:
+        a = gpu_lib.kernel_matvec(Xd, Xd, h, _t(W), prec="f32").cpu().numpy()
+    finally:
+        gpu_lib.set_tuning("symmetric", 1)
+    b = gpu_lib.kernel_matvec(Xd, Xd, h, _t(W), prec="f32").cpu().numpy()
+    ref = cmath.kmv(X, X, W, h)
+    bound = fp32_product_bound(X, X, W, h)
+    assert np.all(np.abs(a - ref) <= bound) and np.all(np.abs(b - ref) <= bound)
