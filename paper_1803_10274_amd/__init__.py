@@ -356,14 +356,18 @@ class FitResult:
 
 
 def fit(X, y, h, lam, leaf=128, opts: HssOptions = HssOptions(), seed=7, tol=1e-6, max_iter=200,
-        mv_prec="f32", refine_solution=True, raise_on_fail=True):
+        mv_prec="f32", refine_solution=True, raise_on_fail=True, tune_cache=None):
     """Algorithm 1 steps 0-2: cluster, compress, factor, solve, refine.
 
     info["phases"] holds the wall time of each library call (seconds, the
-    stream synchronized in between)."""
+    stream synchronized in between).  tune_cache: an autotuner cache whose
+    entry for this shape sets the launch knobs first (see tune.py)."""
     import time
 
     _dev(X)
+    if tune_cache is not None:
+        from .tune import apply
+        apply(X.shape[1], opts.r0, opts.prec, path=tune_cache)
     y2 = _dev(y, torch.float64).reshape(y.shape[0], -1)
     ph = {}
 
