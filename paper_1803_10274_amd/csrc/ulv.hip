@@ -29,6 +29,7 @@ struct UlvDesc {
     const double *D, *U, *B;           // HSS generators
     const double *S_l, *S_r, *Rh_l, *Rh_r;
     double *Dw, *Uw, *Tmp;             // scratch
+    double *Yw, *Zw, *Tw;              // scratch of the blocked transform: k x m, k x m, k x k
     double *V, *tau, *L, *W;           // factor
     double *S_out, *Rh_out;            // passed to the parent
 };
@@ -63,7 +64,7 @@ __global__ __launch_bounds__(BG_T) void k_ulv_factor(const UlvDesc *dsc, int32_t
         }
     }
     __syncthreads();
-    // ---- Householder QR of Uw, reflectors applied to Dw from both sides
+    // ---- Householder QR of Uw (reflectors kept in V, tau)
     for (int j = 0; j < k; ++j) {
         double part = 0.0;
         for (int i = j + 1 + tid; i < m; i += BG_T) part += Uw[(int64_t)i * k + j] * Uw[(int64_t)i * k + j];
@@ -98,22 +99,35 @@ __global__ __launch_bounds__(BG_T) void k_ulv_factor(const UlvDesc *dsc, int32_t
         __syncthreads();
         if (tid == 0) Uw[(int64_t)j * k + j] = beta;
         for (int i = j + 1 + tid; i < m; i += BG_T) Uw[(int64_t)i * k + j] = 0.0;
-        // Dw <- H Dw (columns), then Dw <- Dw H (rows)
-        for (int c = tid; c < m; c += BG_T) {
-            double w = 0.0;
-            for (int i = j; i < m; ++i) w += v[(int64_t)i * k] * Dw[(int64_t)i * m + c];
-            w *= tau;
-            for (int i = j; i < m; ++i) Dw[(int64_t)i * m + c] -= w * v[(int64_t)i * k];
-        }
+    }
+    __syncthreads();
+    if (k > 0) {
+        // ---- compact WY form Q = H_0 ... H_(k-1) = I - V T V^T (T upper
+        // triangular): with G = V^T V, column j of T is T(0:j, j) =
+        // -tau_j T(0:j, 0:j) G(0:j, j) and T(j, j) = tau_j
+        double *G = q.Yw;  // k x k, before Yw is needed
+        block_gemm(k, k, m, 1.0, q.V, 1, k, q.V, k, 1, 0.0, G, k, smem);
+        for (int t = tid; t < k * k; t += BG_T) q.Tw[t] = 0.0;
         __syncthreads();
-        for (int r = tid; r < m; r += BG_T) {
-            double *row = Dw + (int64_t)r * m;
-            double w = 0.0;
-            for (int i = j; i < m; ++i) w += row[i] * v[(int64_t)i * k];
-            w *= tau;
-            for (int i = j; i < m; ++i) row[i] -= w * v[(int64_t)i * k];
+        for (int j = 0; j < k; ++j) {
+            const double tj = q.tau[j];
+            for (int i = tid; i < j; i += BG_T) {
+                double acc = 0.0;
+                for (int l = i; l < j; ++l) acc += q.Tw[(int64_t)i * k + l] * G[(int64_t)l * k + j];
+                q.Tw[(int64_t)i * k + j] = -tj * acc;
+            }
+            if (tid == 0) q.Tw[(int64_t)j * k + j] = tj;
+            __syncthreads();
         }
-        __syncthreads();
+        // ---- Dw <- Q^T Dw Q as GEMMs: left Dw -= V (T^T (V^T Dw)),
+        // right Dw -= ((Dw V) T) V^T
+        double *Y = q.Yw, *Z = q.Zw;
+        block_gemm(k, m, m, 1.0, q.V, 1, k, Dw, m, 1, 0.0, Y, m, smem);         // Y = V^T Dw   (k x m)
+        block_gemm(k, m, k, 1.0, q.Tw, 1, k, Y, m, 1, 0.0, Z, m, smem);         // Z = T^T Y    (k x m)
+        block_gemm(m, m, k, -1.0, q.V, k, 1, Z, m, 1, 1.0, Dw, m, smem);        // Dw -= V Z
+        block_gemm(m, k, m, 1.0, Dw, m, 1, q.V, k, 1, 0.0, Y, k, smem);         // Y = Dw V     (m x k)
+        block_gemm(m, k, k, 1.0, Y, k, 1, q.Tw, k, 1, 0.0, Z, k, smem);         // Z = Y T      (m x k)
+        block_gemm(m, m, k, -1.0, Z, k, 1, q.V, 1, k, 1.0, Dw, m, smem);        // Dw -= Z V^T
     }
     if (!q.root)
         for (int t = tid; t < k * k; t += BG_T) {
@@ -396,17 +410,20 @@ int64_t ulv_factor(const hss_s *H, const std::vector<double> &lam, const std::ve
             if (act[H->nprob[id]]) lv.push_back(id);
         if (lv.empty()) continue;
         const int cnt = (int)lv.size();
-        int64_t dsz = 0, usz = 0, tsz = 0;
+        int64_t dsz = 0, usz = 0, tsz = 0, ysz = 0, wsz = 0;
         for (int id : lv) {
             dsz += (int64_t)m[id] * m[id];
             usz += (int64_t)m[id] * k[id];
             const HNode &q = H->node[id];
             if (q.left >= 0) tsz += (int64_t)k[q.left] * k[q.right];
+            ysz += (int64_t)std::max(m[id], k[id]) * k[id];
+            wsz += (int64_t)k[id] * k[id];
         }
         DBuf Dw = dalloc<double>(std::max<int64_t>(dsz, 1)), Uw = dalloc<double>(std::max<int64_t>(usz, 1)),
-             Tm = dalloc<double>(std::max<int64_t>(tsz, 1));
+             Tm = dalloc<double>(std::max<int64_t>(tsz, 1)), Yb = dalloc<double>(std::max<int64_t>(ysz, 1)),
+             Zb = dalloc<double>(std::max<int64_t>(ysz, 1)), Tb = dalloc<double>(std::max<int64_t>(wsz, 1));
         std::vector<UlvDesc> dsc(cnt);
-        int64_t od = 0, ou = 0, ot = 0;
+        int64_t od = 0, ou = 0, ot = 0, oy = 0, ow = 0;
         for (int a = 0; a < cnt; ++a) {
             const int id = lv[a];
             const HNode &q = H->node[id];
@@ -435,8 +452,13 @@ int64_t ulv_factor(const hss_s *H, const std::vector<double> &lam, const std::ve
             if (!u.root) u.U = H->U.as<double>() + q.offU;
             u.Dw = Dw.as<double>() + od;
             u.Uw = Uw.as<double>() + ou;
+            u.Yw = Yb.as<double>() + oy;
+            u.Zw = Zb.as<double>() + oy;
+            u.Tw = Tb.as<double>() + ow;
             od += (int64_t)u.m * u.m;
             ou += (int64_t)u.m * u.k;
+            oy += (int64_t)std::max(u.m, u.k) * u.k;
+            ow += (int64_t)u.k * u.k;
             u.V = F->V.as<double>() + F->offV[id];
             u.tau = F->T.as<double>() + F->offT[id];
             u.L = F->L.as<double>() + F->offL[id];
