@@ -271,7 +271,9 @@ int hss_ulv_factor_spd(hss_t H, double lambda, double pivot_floor, void *stream,
  * delta) I for the first delta in 0, lambda, 4 lambda, 16 lambda, ... (12
  * tries) at which every Cholesky pivot is at least lambda / 2 -- in exact
  * arithmetic every pivot of K + lambda I is at least lambda, so smaller ones
- * are compression error.  A try stops at the first level with such a pivot.
+ * are compression error.  A try stops at the first level with such a pivot;
+ * the next try skips the deltas below the previous delta plus the largest
+ * deficit (lambda / 2 - pivot) seen.
  * The refinement still applies the exact operator K + lambda I.  shift_host
  * (optional) receives delta.  KRR_E_NUMERIC if no try succeeds.
  */

@@ -116,12 +116,19 @@ hss_ulv_s *factor_shifted(const hss_s *H, const std::vector<double> &lam, hipStr
         for (int attempt = 0; attempt < 12; ++attempt) {
             for (int k = 0; k < np; ++k) lam_s[k] = lam[k] * (1.0 + sh[k]);
             std::vector<uint8_t> act = todo;
-            ulv_factor(H, lam_s, floor, s, F, nullptr, true, &act);
+            std::vector<double> deficit;
+            ulv_factor(H, lam_s, floor, s, F, &deficit, true, &act);
             int left = 0;
             for (int k = 0; k < np; ++k) {
                 todo[k] = act[k];
                 if (act[k]) {
-                    sh[k] = sh[k] == 0.0 ? 1.0 : 4.0 * sh[k];
+                    // the next shift on the grid 1, 4, 16, ... that also covers
+                    // the deficit seen (a pivot below lambda / 2 by D needs a
+                    // diagonal shift of about D)
+                    const double target = sh[k] * lam[k] + deficit[k];
+                    double next = sh[k] == 0.0 ? 1.0 : 4.0 * sh[k];
+                    while (next * lam[k] < target && next < 1e12) next *= 4.0;
+                    sh[k] = next;
                     ++left;
                 }
             }

@@ -134,12 +134,14 @@ void gather_rows(const void *src, int prec, int64_t n, int cols, const int64_t *
 void compress(const krr_tree_s *t, const void *Xp, int xprec, int d, const std::vector<double> &hprob,
               const hss_opts &o, hipStream_t s, hss_s *H, hss_stats *st);
 // lam / floor: diagonal shift and pivot floor of each problem (per root).
-// Returns the number of pivots raised to the floor.  With stop_at_floor, a
-// problem whose pivot falls below its floor stops at that level.  active (if
-// given): in, the problems to factor (a factor F already holding the others
-// is completed in place); out (with stop_at_floor), the problems that stopped.
+// Returns the number of pivots raised to the floor; deficit (if given)
+// receives each problem's largest floor - pivot over the raised pivots.  With
+// stop_at_floor, a problem whose pivot falls below its floor stops at that
+// level.  active (if given): in, the problems to factor (a factor F already
+// holding the others is completed in place); out (with stop_at_floor), the
+// problems that stopped.
 int64_t ulv_factor(const hss_s *H, const std::vector<double> &lam, const std::vector<double> &floor, hipStream_t s,
-                   hss_ulv_s *F, double *worst_deficit = nullptr, bool stop_at_floor = false,
+                   hss_ulv_s *F, std::vector<double> *deficit = nullptr, bool stop_at_floor = false,
                    std::vector<uint8_t> *active = nullptr);
 void ulv_solve(const hss_ulv_s *F, const double *Bin, int nrhs, double *Xout, hipStream_t s);
 void hss_matvec_impl(const hss_s *H, const double *x, int nrhs, double *y, hipStream_t s);

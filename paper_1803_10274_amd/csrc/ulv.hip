@@ -172,7 +172,7 @@ __global__ __launch_bounds__(BG_T) void k_ulv_factor(const UlvDesc *dsc, int32_t
             if (tid == 0) {
                 atomicAdd(clamped + q.prob, 1ull);
                 // largest deficit below the floor (non-negative, so its bits order like integers)
-                atomicMax(worst, (unsigned long long)__double_as_longlong(pivot_floor - djj));
+                atomicMax(worst + q.prob, (unsigned long long)__double_as_longlong(pivot_floor - djj));
             }
             djj = fmax(fmax(pivot_floor, fabs(djj)), theta * theta / beta2);
         }
@@ -344,7 +344,7 @@ __global__ __launch_bounds__(BG_T) void k_ulv_bwd(const SolveDesc *dsc, double *
 }  // namespace
 
 int64_t ulv_factor(const hss_s *H, const std::vector<double> &lam, const std::vector<double> &floor, hipStream_t s,
-                   hss_ulv_s *F, double *worst_deficit, bool stop_at_floor, std::vector<uint8_t> *active) {
+                   hss_ulv_s *F, std::vector<double> *deficit, bool stop_at_floor, std::vector<uint8_t> *active) {
     const int nn = (int)H->node.size();
     const int np = (int)H->hprob.size();
     KRR_REQUIRE((int)lam.size() == np && (int)floor.size() == np, "ULV: one lambda and floor per problem");
@@ -399,10 +399,10 @@ int64_t ulv_factor(const hss_s *H, const std::vector<double> &lam, const std::ve
         ns += (int64_t)k[i] * k[i];
     }
     DBuf Sb = dalloc<double>(std::max<int64_t>(ns, 1)), Rb = dalloc<double>(std::max<int64_t>(ns, 1));
-    // counters: raised pivots per problem, then the largest deficit
-    DBuf flag = dalloc<int32_t>(1), nclamp = dalloc<unsigned long long>(np + 1);
+    // counters: raised pivots per problem, then each problem's largest deficit
+    DBuf flag = dalloc<int32_t>(1), nclamp = dalloc<unsigned long long>(2 * np);
     KRR_HIP(hipMemsetAsync(flag.get(), 0, sizeof(int32_t), s));
-    KRR_HIP(hipMemsetAsync(nclamp.get(), 0, (np + 1) * sizeof(unsigned long long), s));
+    KRR_HIP(hipMemsetAsync(nclamp.get(), 0, 2 * np * sizeof(unsigned long long), s));
     std::vector<uint8_t> raised(np, 0);
     for (const auto &lv_all : H->levels) {
         std::vector<int> lv;  // this level's nodes of the problems still being factored
@@ -485,11 +485,15 @@ int64_t ulv_factor(const hss_s *H, const std::vector<double> &lam, const std::ve
         }
     }
     int32_t bad = 0;
-    std::vector<unsigned long long> cl(np + 1);
+    std::vector<unsigned long long> cl(2 * np);
     d2h(&bad, flag.as<int32_t>(), 1, s);
-    d2h(cl.data(), nclamp.as<unsigned long long>(), np + 1, s);
+    d2h(cl.data(), nclamp.as<unsigned long long>(), 2 * np, s);
     sync(s);
-    if (worst_deficit) *worst_deficit = cl[np] ? __builtin_bit_cast(double, (uint64_t)cl[np]) : 0.0;
+    if (deficit) {
+        deficit->assign(np, 0.0);
+        for (int p = 0; p < np; ++p)
+            (*deficit)[p] = cl[np + p] ? __builtin_bit_cast(double, (uint64_t)cl[np + p]) : 0.0;
+    }
     if (bad) fail(KRR_E_NUMERIC, "ULV: non-positive pivot in a Cholesky factor (K_hss + lambda I not SPD)");
     if (active && stop_at_floor) *active = raised;
     int64_t tot = 0;
