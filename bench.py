@@ -75,7 +75,7 @@ def parse():
     ap.add_argument("--split", type=int, default=2)
     ap.add_argument("--rtol", type=float, default=1e-2)
     ap.add_argument("--r0", type=int, default=256)
-    ap.add_argument("--atol", type=float, default=3.0)
+    ap.add_argument("--atol", type=float, default=6.0)
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-sampling comparison fit")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-problem batched leg")

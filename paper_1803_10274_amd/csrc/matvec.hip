@@ -602,13 +602,13 @@ void launch_sym(dim3 gd, dim3 gs, dim3 gr, int rows_pb, const T *X, int d, doubl
 }
 
 // The symmetric product y = K(X, X) W + beta y (FP32 entries) when it
-// applies (d <= 16, one or two right-hand sides, partial sums within budget);
+// applies (d <= 32, one or two right-hand sides, partial sums within budget);
 // returns false otherwise.
 template <class T>
 bool kmv_sym(const T *X, int64_t n, int d, double h, const double *W, int nrhs, double beta, double *Out,
              hipStream_t s, const Batch *batch) {
     const int D = sc_width(d);
-    if (D > 16 || (nrhs != 1 && nrhs != 2)) return false;
+    if (D > 32 || (nrhs != 1 && nrhs != 2)) return false;
     const int rows_pb = MV_ROWS * sc_rpt(D);
     const int64_t CH = tune_get(KRR_TUNE_SYM_CHUNK);  // columns per item: a multiple of the tile width
     std::vector<int64_t> pb = batch ? batch->pbeg : std::vector<int64_t>{0, n};
@@ -678,6 +678,12 @@ bool kmv_sym(const T *X, int64_t n, int d, double h, const double *W, int nrhs, 
         case 12 * 4 + 2: KRR_SYM(12, 2); break;
         case 16 * 4 + 1: KRR_SYM(16, 1); break;
         case 16 * 4 + 2: KRR_SYM(16, 2); break;
+        case 20 * 4 + 1: KRR_SYM(20, 1); break;
+        case 20 * 4 + 2: KRR_SYM(20, 2); break;
+        case 24 * 4 + 1: KRR_SYM(24, 1); break;
+        case 24 * 4 + 2: KRR_SYM(24, 2); break;
+        case 32 * 4 + 1: KRR_SYM(32, 1); break;
+        case 32 * 4 + 2: KRR_SYM(32, 2); break;
         default: fail(KRR_E_INVAL, "kernel_matvec: no symmetric variant for width %d", D);
     }
 #undef KRR_SYM

@@ -144,11 +144,11 @@ def sym_chunk(gpu_lib):
     gpu_lib.set_tuning("sym_chunk", old)
 
 
-@pytest.mark.parametrize("d", [3, 8, 16])
+@pytest.mark.parametrize("d", [3, 8, 16, 18, 24, 30])
 @pytest.mark.parametrize("nrhs", [1, 2])
 def test_symmetric_product(gpu_lib, sym_chunk, d, nrhs):
     # K(X, X) W with each off-diagonal entry evaluated once: 5000 points are
-    # 5 row blocks (a ragged last one) and several column chunks per block
+    # several row blocks (a ragged last one) and several column chunks per block
     n, h = 5000, 0.9
     X = sd.points(n, d, seed=d, scale=0.7)
     W = sd.vectors(n, nrhs, seed=nrhs)
