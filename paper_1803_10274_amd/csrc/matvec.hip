@@ -694,6 +694,12 @@ bool kmv_sym(const T *X, int64_t n, int d, double h, const double *W, int nrhs, 
 template <class T, class C>
 void kmv_typed(const T *X, int64_t m, const T *Y, int64_t n, int d, double h, const double *W, int nrhs,
                double beta, double *Out, hipStream_t s, const Batch *batch) {
+    if constexpr (sizeof(C) == 4 && sizeof(T) == 4) {
+        if (d > 64) {  // wide points: the exponents as a matrix-core GEMM
+            kmv_wide_mfma(X, m, Y, n, d, h, W, nrhs, beta, Out, s, batch);
+            return;
+        }
+    }
     if constexpr (sizeof(C) == 4) {
         // K(X, X): each off-diagonal entry once, for its row and its column
         if (X == Y && m == n && tune_get(KRR_TUNE_SYMMETRIC) && kmv_sym<T>(X, n, d, h, W, nrhs, beta, Out, s, batch))

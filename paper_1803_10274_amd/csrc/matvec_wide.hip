@@ -1,0 +1,192 @@
+// FP32-entry kernel product Out = K(X, Y; h) W for wide points (d > 64) on
+// the matrix cores.  The exponents are a GEMM of prepared coordinates (see
+// wide.hpp): a workgroup owns 128 rows (4 waves x 32) and walks the columns
+// in panels of 128 points, accumulating t = x~_i . y~_j over K chunks of 64
+// staged through LDS with v_mfma_f32_32x32x2_f32 (points as A rows, the
+// wave's rows as B columns).  Each lane then holds, for its row, the
+// exponents of 16 points of every 32-point tile; exp2 turns them into FP32
+// entries that are directly the A operand of a second v_mfma_f32_32x32x2_f32
+// product with the panel's weights (B: the weights of the same points, up to
+// 32 right-hand sides), so E never leaves registers.  Products are summed in
+// FP32 over a panel and in FP64 across panels; the columns are split across
+// workgroups (split-K) and reduced in order afterwards.
+#include "internal.hpp"
+#include "wide.hpp"
+
+namespace krr {
+namespace {
+
+typedef float f16v __attribute__((ext_vector_type(16)));
+
+constexpr int KW = 4;           // waves per workgroup
+constexpr int KROWS = 32 * KW;  // rows per workgroup
+constexpr int KPT = 4;          // 32-point tiles per panel
+constexpr int KKC = 64;         // augmented coordinates per LDS chunk
+
+// point of register s of a lane in half g of the wave (the C layout of the
+// exponent GEMM): 8 (s / 4) + 4 g + s % 4
+__device__ __forceinline__ int reg_point(int s, int g) { return 8 * (s >> 2) + 4 * g + (s & 3); }
+
+__global__ __launch_bounds__(64 * KW) void k_kmv_wmfma(const float *__restrict__ XA, int64_t m,
+                                                       const float *__restrict__ YA, int64_t n, int KP,
+                                                       const float *__restrict__ wf, int nrhs, int rhs0, int nrc,
+                                                       int64_t cols_per_split, double *__restrict__ part,
+                                                       const SampBlock *__restrict__ bt) {
+    constexpr int TH = 64 * KW;
+    constexpr int LDK = KKC + 1;
+    __shared__ __attribute__((aligned(16))) float lds[2 * KROWS * LDK];
+    float(*xs)[LDK] = reinterpret_cast<float(*)[LDK]>(lds);
+    float(*ys)[LDK] = reinterpret_cast<float(*)[LDK]>(lds + KROWS * LDK);
+    float(*ws)[33] = reinterpret_cast<float(*)[33]>(lds);  // the panel's weights, after the GEMM
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 5;
+    const int split = blockIdx.y;
+    int64_t i0, iend, j0, j1;
+    if (bt) {
+        const SampBlock sb = bt[blockIdx.x];
+        i0 = sb.i0;
+        iend = sb.iend;
+        j0 = sb.jlo + split * sb.cps;
+        j1 = min(sb.jhi, j0 + sb.cps);
+    } else {
+        i0 = (int64_t)blockIdx.x * KROWS;
+        iend = m;
+        j0 = split * cols_per_split;
+        j1 = min(n, j0 + cols_per_split);
+    }
+    double acc[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+    for (int64_t p0 = (j0 / 32) * 32; p0 < j1; p0 += 32 * KPT) {
+        f16v t[KPT];
+#pragma unroll
+        for (int pt = 0; pt < KPT; ++pt)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) t[pt][q] = 0.0f;
+        for (int kc = 0; kc < KP; kc += KKC) {
+            for (int u = tid; u < KROWS * KKC; u += TH) {
+                const int rr = u / KKC, kk = u % KKC;
+                const int64_t gi = i0 + rr, gj = p0 + rr;
+                xs[rr][kk] = gi < iend ? XA[gi * KP + kc + kk] : 0.0f;
+                ys[rr][kk] = (gj >= j0 && gj < j1) ? YA[gj * KP + kc + kk] : 0.0f;
+            }
+            __syncthreads();
+#pragma unroll 4
+            for (int s2 = 0; s2 < KKC / 2; ++s2) {
+                const int kk = 2 * s2 + g;
+                const float b = xs[32 * w + (lane & 31)][kk];
+#pragma unroll
+                for (int pt = 0; pt < KPT; ++pt)
+                    t[pt] = __builtin_amdgcn_mfma_f32_32x32x2f32(ys[32 * pt + (lane & 31)][kk], b, t[pt], 0, 0, 0);
+            }
+            __syncthreads();
+        }
+        // the panel's weights (zero outside the column range and past nrc)
+        for (int u = tid; u < 32 * KPT * 32; u += TH) {
+            const int pp = u / 32, col = u % 32;
+            const int64_t gj = p0 + pp;
+            ws[pp][col] = (col < nrc && gj >= j0 && gj < j1) ? wf[gj * nrhs + rhs0 + col] : 0.0f;
+        }
+        __syncthreads();
+        f16v pa;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) pa[q] = 0.0f;
+#pragma unroll
+        for (int pt = 0; pt < KPT; ++pt)
+#pragma unroll
+            for (int sidx = 0; sidx < 16; ++sidx) {
+                const int pp = 32 * pt + reg_point(sidx, g);
+                const float e = __builtin_amdgcn_exp2f(t[pt][sidx]);  // masked points meet zero weights
+                pa = __builtin_amdgcn_mfma_f32_32x32x2f32(e, ws[pp][lane & 31], pa, 0, 0, 0);
+            }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc[q] += (double)pa[q];
+        __syncthreads();
+    }
+    // lane: right-hand side lane % 32, rows 8 (q / 4) + 4 g + q % 4 of the wave's 32
+    const int col = lane & 31;
+    if (col < nrc) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int64_t row = i0 + 32 * w + 8 * (q >> 2) + 4 * g + (q & 3);
+            if (row < iend) part[((int64_t)split * m + row) * nrhs + rhs0 + col] = acc[q];
+        }
+    }
+}
+
+__global__ void k_w_to_float_wide(const double *__restrict__ W, int64_t len, float *__restrict__ wf) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < len) wf[t] = (float)W[t];
+}
+
+__global__ void k_reduce_parts(const double *__restrict__ part, int nsplit, int64_t mn, double beta,
+                               double *__restrict__ out) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= mn) return;
+    double s = 0.0;
+    for (int k = 0; k < nsplit; ++k) s += part[(int64_t)k * mn + t];
+    out[t] = (beta != 0.0) ? s + beta * out[t] : s;
+}
+
+}  // namespace
+
+// Out = K(X, Y; h) W + beta Out with FP32 entries for d > 64 (X: m FP32
+// points, Y: n FP32 points; a batch multiplies its own points).
+void kmv_wide_mfma(const float *X, int64_t m, const float *Y, int64_t n, int d, double h, const double *W, int nrhs,
+                   double beta, double *Out, hipStream_t s, const Batch *batch) {
+    const int KP = (d + 2 + KKC - 1) / KKC * KKC;
+    const double c2 = 1.4426950408889634 / (2.0 * h * h);
+    DBuf mean = dalloc<double>(d), XA = dalloc<float>((size_t)m * KP), YA = dalloc<float>((size_t)n * KP);
+    DBuf wf = dalloc<float>((size_t)n * nrhs), pb, cp, btab;
+    int64_t nb = 0, cps = 0;
+    int nsplit;
+    if (batch) {
+        std::vector<double> cpr(batch->np());
+        for (int k = 0; k < batch->np(); ++k) cpr[k] = 1.4426950408889634 / (2.0 * batch->h[k] * batch->h[k]);
+        pb = upload(batch->pbeg, s);
+        cp = upload(cpr, s);
+        std::vector<SampBlock> blocks = row_blocks(*batch, KROWS);
+        nb = (int64_t)blocks.size();
+        int64_t nmax = 0;
+        for (int k = 0; k < batch->np(); ++k) nmax = std::max(nmax, batch->size(k));
+        nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(tune_get(KRR_TUNE_MV_BLOCKS), nb),
+                                                             ceil_div(nmax, 4 * 32 * KPT)));
+        for (auto &b : blocks) {
+            int64_t c = ceil_div(b.jhi - b.jlo, nsplit);
+            b.cps = (c + 127) / 128 * 128;
+        }
+        btab = upload(blocks, s);
+        sync(s);
+    } else {
+        const int64_t rb = ceil_div(m, KROWS);
+        nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(tune_get(KRR_TUNE_MV_BLOCKS), rb),
+                                                             ceil_div(n, 4 * 32 * KPT)));
+        cps = (ceil_div(n, nsplit) + 127) / 128 * 128;
+        nsplit = (int)ceil_div(n, cps);
+    }
+    // one anchor for rows and columns: the mean of the columns' points
+    k_col_mean<<<d, 256, 0, s>>>(Y, n, d, mean.as<double>());
+    check_launch("k_col_mean");
+    k_wide_aug<<<(unsigned)m, 256, 0, s>>>(X, m, d, KP, mean.as<double>(), c2, pb.as<int64_t>(), cp.as<double>(),
+                                          batch ? batch->np() : 0, 0.0f, 0, XA.as<float>());
+    check_launch("k_wide_aug");
+    k_wide_aug<<<(unsigned)n, 256, 0, s>>>(Y, n, d, KP, mean.as<double>(), c2, pb.as<int64_t>(), cp.as<double>(),
+                                          batch ? batch->np() : 0, 0.0f, 1, YA.as<float>());
+    check_launch("k_wide_aug");
+    k_w_to_float_wide<<<ceil_div(n * nrhs, 256), 256, 0, s>>>(W, n * nrhs, wf.as<float>());
+    check_launch("k_w_to_float_wide");
+    DBuf part = dalloc<double>((size_t)nsplit * m * nrhs);
+    dim3 grid((unsigned)(batch ? nb : ceil_div(m, KROWS)), nsplit);
+    for (int r0 = 0; r0 < nrhs; r0 += 32) {
+        const int nrc = std::min(32, nrhs - r0);
+        k_kmv_wmfma<<<grid, 64 * KW, 0, s>>>(XA.as<float>(), m, YA.as<float>(), n, KP, wf.as<float>(), nrhs, r0, nrc,
+                                            cps, part.as<double>(), btab.as<SampBlock>());
+        check_launch("k_kmv_wmfma");
+    }
+    const int64_t mn = m * nrhs;
+    k_reduce_parts<<<ceil_div(mn, 256), 256, 0, s>>>(part.as<double>(), nsplit, mn, beta, Out);
+    check_launch("k_reduce_parts");
+    sync(s);  // temporaries are released on return
+}
+
+}  // namespace krr

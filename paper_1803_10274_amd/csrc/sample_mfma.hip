@@ -19,6 +19,7 @@
 #include <algorithm>
 
 #include "internal.hpp"
+#include "wide.hpp"
 
 namespace krr {
 
@@ -562,17 +563,216 @@ void dispatch_d(const T *X, int64_t n, int d, float cs, const void *Rsw, int r, 
         dispatch_mode<T, 64>(X, n, d, cs, Rsw, r, lb, le, S, prec, split, s, bt, nb);
 }
 
+
+// ------------------------------------------------------ wide points (d > 64)
+//
+// For wide points the augmented coordinates no longer fit in registers, so
+// the exponents are an ordinary GEMM on the matrix cores: a workgroup owns
+// 128 rows (4 waves x 32) and walks the points in panels of 128 (4 tiles of
+// 32); per panel it accumulates t = x~_i . y~_j over the K = d + 2 augmented
+// coordinates in chunks of 64 staged through LDS (v_mfma_f32_32x32x2_f32,
+// points as A rows, the wave's rows as B columns: the C layout is the one
+// exp_split turns into the FP16 / BF16 A operands), then applies exp2, the
+// split and the products with the panel's random block as in k_sample_mfma.
+// The coordinates are centred on the mean point (x' = x - mean) and prepared
+// once per call: XA_i = (2 c x'_i, -c |x'_i|^2 (+14 in FP16 mode), 1, 0..),
+// YA_j = (x'_j, 1, -c |x'_j|^2, 0..), rows of KP floats, c per problem.
+constexpr int WW = 4;            // waves per workgroup (wide kernel)
+constexpr int WROWS = 32 * WW;   // rows per workgroup
+constexpr int WPT = 4;           // point tiles per panel
+constexpr int WKC = 64;          // augmented coordinates per LDS chunk
+constexpr int WRB = 4;           // 32-column blocks per pass
+
+// Kernel entries of one 32-point tile from its exponents, masking the row's
+// own leaf and points outside the row's problem [jlo, jhi).
+template <int MODE, int TERMS>
+__device__ __forceinline__ void exp_split_range(typename Op<MODE>::V (&ahi)[2], typename Op<MODE>::V (&alo)[2],
+                                                const f16v &t, int g, int64_t jt, int32_t my_lb, int32_t my_le,
+                                                int64_t jlo, int64_t jhi) {
+    typedef typename Op<MODE>::H H;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        float e = __builtin_amdgcn_exp2f(t[r]);
+        const int64_t j = jt + 8 * (r >> 2) + 4 * g + (r & 3);
+        e = (j < jlo || j >= jhi || (j >= my_lb && j < my_le)) ? 0.0f : e;
+        const H hi = (H)e;
+        ahi[r >> 3][r & 7] = hi;
+        if (TERMS == 2) alo[r >> 3][r & 7] = (H)(e - (float)hi);
+    }
+}
+
+template <int MODE, int TERMS>
+__global__ __launch_bounds__(64 * WW) void k_sample_wide(const float *__restrict__ XA, const float *__restrict__ YA,
+                                                         int KP, int64_t n, const void *__restrict__ Rsw_, int RBt,
+                                                         const int32_t *__restrict__ lb,
+                                                         const int32_t *__restrict__ le, float *__restrict__ S,
+                                                         int ldS, const SampBlock *__restrict__ bt) {
+    typedef typename Op<MODE>::V V;
+    constexpr int TH = 64 * WW;
+    constexpr int LDK = WKC + 1;
+    // x~ / y~ chunks during the exponent GEMM, then the panel's random block
+    __shared__ __attribute__((aligned(16))) float lds[2 * WROWS * LDK];
+    float(*xs)[LDK] = reinterpret_cast<float(*)[LDK]>(lds);
+    float(*ys)[LDK] = reinterpret_cast<float(*)[LDK]>(lds + WROWS * LDK);
+    const V *rl = reinterpret_cast<const V *>(lds);
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 5;
+    const int cb0 = blockIdx.y * WRB;
+    int64_t i0, iend, jlo, jhi;
+    if (bt) {
+        const SampBlock sb = bt[blockIdx.x];
+        i0 = sb.i0;
+        iend = sb.iend;
+        jlo = sb.jlo;
+        jhi = sb.jhi;
+    } else {
+        i0 = (int64_t)blockIdx.x * WROWS;
+        iend = n;
+        jlo = 0;
+        jhi = n;
+    }
+    const int64_t i = i0 + 32 * w + (lane & 31);
+    const bool row_ok = i < iend;
+    const int32_t my_lb = (row_ok && lb) ? lb[i] : 0;
+    const int32_t my_le = (row_ok && lb) ? le[i] : 0;
+    constexpr float kInvScale = MODE == M_F16 ? 1.0f / 16384.0f : 1.0f;
+    const char *Rg = static_cast<const char *>(Rsw_);
+    constexpr int TILE_B = 2 * 64 * 16;  // bytes of one (tile, column block) of the FP16 / BF16 layout
+    f16v acc[WRB];
+#pragma unroll
+    for (int c = 0; c < WRB; ++c)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc[c][q] = 0.0f;
+
+    for (int64_t p0 = (jlo / 32) * 32; p0 < jhi; p0 += 32 * WPT) {
+        f16v t[WPT];
+#pragma unroll
+        for (int pt = 0; pt < WPT; ++pt)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) t[pt][q] = 0.0f;
+        for (int kc = 0; kc < KP; kc += WKC) {
+            for (int u = tid; u < WROWS * WKC; u += TH) {
+                const int rr = u / WKC, kk = u % WKC;
+                const int64_t gi = i0 + rr, gj = p0 + rr;
+                xs[rr][kk] = gi < iend ? XA[gi * KP + kc + kk] : 0.0f;
+                ys[rr][kk] = gj < jhi ? YA[gj * KP + kc + kk] : 0.0f;
+            }
+            __syncthreads();
+#pragma unroll 4
+            for (int s2 = 0; s2 < WKC / 2; ++s2) {
+                const int kk = 2 * s2 + g;
+                const float b = xs[32 * w + (lane & 31)][kk];
+#pragma unroll
+                for (int pt = 0; pt < WPT; ++pt)
+                    t[pt] = __builtin_amdgcn_mfma_f32_32x32x2f32(ys[32 * pt + (lane & 31)][kk], b, t[pt], 0, 0, 0);
+            }
+            __syncthreads();
+        }
+        // the panel's random block (WPT tiles x WRB column blocks) into LDS
+        {
+            const int pieces = WPT * WRB * TILE_B / 16;
+            uint4 *dst = reinterpret_cast<uint4 *>(lds);
+            for (int u = tid; u < pieces; u += TH) {
+                const int per = WRB * TILE_B / 16, pt = u / per, rem = u % per, c = rem / (TILE_B / 16);
+                const uint4 *src = reinterpret_cast<const uint4 *>(
+                    Rg + ((p0 / 32 + pt) * (int64_t)RBt + cb0) * TILE_B);
+                // column blocks past the last one (a ragged final pass) read as zeros
+                dst[u] = cb0 + c < RBt ? src[rem] : make_uint4(0u, 0u, 0u, 0u);
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int pt = 0; pt < WPT; ++pt) {
+            V hi[2], lo[2];
+            exp_split_range<MODE, TERMS>(hi, lo, t[pt], g, p0 + 32 * pt, my_lb, my_le, jlo, jhi);
+#pragma unroll
+            for (int c = 0; c < WRB; ++c)
+#pragma unroll
+                for (int kb = 0; kb < 2; ++kb) {
+                    const V b = rl[((pt * WRB + c) * 2 + kb) * 64 + lane];
+                    acc[c] = Op<MODE>::mfma(hi[kb], b, acc[c]);
+                    if (TERMS == 2) acc[c] = Op<MODE>::mfma(lo[kb], b, acc[c]);
+                }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int c = 0; c < WRB; ++c)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int m = 8 * (q >> 2) + 4 * g + (q & 3);
+            const int64_t row = i0 + 32 * w + m;
+            if (row < iend && cb0 + c < RBt) S[row * ldS + 32 * (cb0 + c) + (lane & 31)] = acc[c][q] * kInvScale;
+        }
+}
+
 }  // namespace
 
 constexpr int kSampleMfmaMaxD = 64;
 
-bool sample_mfma_supported(int d, int prec) { return prec != KRR_F64 && d <= kSampleMfmaMaxD; }
+namespace {
+
+template <int MODE, int TERMS>
+void launch_wide(dim3 grid, const float *XA, const float *YA, int KP, int64_t n, const void *Rsw, int RBt,
+                 const int32_t *lb, const int32_t *le, float *S, int ldS, const SampBlock *bt, hipStream_t s) {
+    k_sample_wide<MODE, TERMS><<<grid, 64 * WW, 0, s>>>(XA, YA, KP, n, Rsw, RBt, lb, le, S, ldS, bt);
+    check_launch("k_sample_wide");
+}
+
+// Split-mode sampling of points wider than the register-resident kernel.
+void sample_wide(const float *X, int64_t n, int d, double h, const void *Rsw, int r, const int32_t *lb,
+                 const int32_t *le, float *S, int prec, int split, hipStream_t s, const Batch *batch) {
+    const int KP = (d + 2 + WKC - 1) / WKC * WKC;
+    const double c2 = 1.4426950408889634 / (2.0 * h * h);
+    DBuf mean = dalloc<double>(d), XA = dalloc<float>((size_t)n * KP), YA = dalloc<float>((size_t)n * KP);
+    DBuf pb, cp, bt;
+    int64_t nb = 0;
+    std::vector<SampBlock> blocks;
+    if (batch) {
+        std::vector<double> cpr(batch->np());
+        for (int k = 0; k < batch->np(); ++k) cpr[k] = 1.4426950408889634 / (2.0 * batch->h[k] * batch->h[k]);
+        pb = upload(batch->pbeg, s);
+        cp = upload(cpr, s);
+        blocks = row_blocks(*batch, WROWS);
+        nb = (int64_t)blocks.size();
+        bt = upload(blocks, s);
+        sync(s);
+    }
+    k_col_mean<<<d, 256, 0, s>>>(X, n, d, mean.as<double>());
+    check_launch("k_col_mean");
+    const float off = prec == KRR_F16_SPLIT ? 14.0f : 0.0f;  // FP16 entries carry a 2^14 scale
+    k_wide_aug<<<(unsigned)n, 256, 0, s>>>(X, n, d, KP, mean.as<double>(), c2, pb.as<int64_t>(), cp.as<double>(),
+                                          batch ? batch->np() : 0, off, 0, XA.as<float>());
+    check_launch("k_wide_aug");
+    k_wide_aug<<<(unsigned)n, 256, 0, s>>>(X, n, d, KP, mean.as<double>(), c2, pb.as<int64_t>(), cp.as<double>(),
+                                          batch ? batch->np() : 0, off, 1, YA.as<float>());
+    check_launch("k_wide_aug");
+    const int RBt = r / 32;
+    dim3 grid((unsigned)(batch ? nb : ceil_div(n, WROWS)), ceil_div(RBt, WRB));
+    const SampBlock *b = bt.as<SampBlock>();
+    if (prec == KRR_F16_SPLIT)
+        split == 2 ? launch_wide<M_F16, 2>(grid, XA.as<float>(), YA.as<float>(), KP, n, Rsw, RBt, lb, le, S, r, b, s)
+                   : launch_wide<M_F16, 1>(grid, XA.as<float>(), YA.as<float>(), KP, n, Rsw, RBt, lb, le, S, r, b, s);
+    else
+        split == 2 ? launch_wide<M_BF16, 2>(grid, XA.as<float>(), YA.as<float>(), KP, n, Rsw, RBt, lb, le, S, r, b, s)
+                   : launch_wide<M_BF16, 1>(grid, XA.as<float>(), YA.as<float>(), KP, n, Rsw, RBt, lb, le, S, r, b, s);
+    sync(s);  // the prepared coordinates are released on return
+}
+
+}  // namespace
+
+bool sample_mfma_supported(int d, int prec) {
+    // FP32 entries of wide points stay on the vector ALUs; the split modes of
+    // any width run on the matrix cores
+    return prec != KRR_F64 && (d <= kSampleMfmaMaxD || prec != KRR_F32);
+}
 
 // R: n x r FP32 (exact in the operand precision); S: n x r FP32.
 void sample_mfma(const void *X, int64_t n, int d, int xprec, double h, const float *R, int r, const int32_t *lb,
                  const int32_t *le, float *S, int prec, int split, hipStream_t s, const Batch *batch) {
-    // two zero tiles past the end keep the kernel's prefetches in bounds
-    const int64_t tiles = (n + JT - 1) / JT + 2;
+    // zero tiles past the end keep every prefetch in bounds: two for the
+    // narrow kernel, a whole panel for the wide one
+    const int64_t tiles = (n + JT - 1) / JT + WPT;
     const float cs = (float)(1.4426950408889634 / (2.0 * h * h));
     DBuf Rsw;
     if (prec == KRR_F32) {
@@ -603,6 +803,11 @@ void sample_mfma(const void *X, int64_t n, int d, int xprec, double h, const flo
         nb = (int64_t)blocks.size();
         bt = upload(blocks, s);
         sync(s);  // `blocks` is released on return from this scope
+    }
+    if (d > kSampleMfmaMaxD) {
+        sample_wide(Xs, n, d, h, Rsw.get(), r, lb, le, S, prec, split, s, batch);
+        sync(s);  // Rsw is released on return
+        return;
     }
     dispatch_d<float>(Xs, n, d, cs, Rsw.get(), r, lb, le, S, prec, split, s, bt.as<SampBlock>(), nb);
     sync(s);  // Rsw and the block table are released on return

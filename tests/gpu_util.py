@@ -30,6 +30,24 @@ def fp32_product_bound(X, Y, W, h, tile=64, safety=4.0, mask=None):
     return safety * U32 * ((tile + 2) * (K @ aW) + (d + 3) * ((K * t) @ aW))
 
 
+def fp32_wide_product_bound(X, Y, W, h, panel=128, safety=4.0):
+    """Elementwise bound for the FP32-entry product of wide points: exponents
+    from the norm expansion on coordinates centred on the mean of Y (FP32
+    matrix-core dot products of d + 2 terms: |dt| <= (d + 2) u (|x'| + |y'|)^2
+    / (2 h^2) in natural-log units), exp2 within 2 ulp, FP32 sums over a panel
+    of `panel` points and FP64 sums across panels."""
+    X = np.asarray(X, dtype=np.float64)
+    Y = np.asarray(Y, dtype=np.float64)
+    a = Y.mean(axis=0)
+    nx = np.linalg.norm(X - a, axis=1)
+    ny = np.linalg.norm(Y - a, axis=1)
+    q = sqdist(X, Y)
+    K = np.exp(-q / (2 * h * h))
+    T = (X.shape[1] + 2) * (nx[:, None] + ny[None, :]) ** 2 / (2 * h * h)
+    aW = np.abs(np.asarray(W, dtype=np.float64)).reshape(W.shape[0], -1)
+    return safety * U32 * ((panel + 2) * (K @ aW) + (K * T) @ aW)
+
+
 def leaf_ranges(nodes, n):
     lb = np.empty(n, dtype=np.int32)
     le = np.empty(n, dtype=np.int32)
@@ -45,7 +63,7 @@ SPLIT_U = {("f32", 1): 0.0, ("f16", 1): 2.0 ** -11, ("f16", 2): 2.0 ** -22,
            ("bf16", 1): 2.0 ** -8, ("bf16", 2): 2.0 ** -16}
 
 
-def mfma_sample_bound(Xp, R, h, lb, le, prec, split, rows, rows_per_block=256, safety=4.0):
+def mfma_sample_bound(Xp, R, h, lb, le, prec, split, rows, rows_per_block=256, safety=4.0, anchor=None):
     """Bound for the matrix-core sampler on the given rows.
 
     Entry e_ij = exp2(t) with t formed in FP32 from coordinates re-centred on
@@ -57,7 +75,8 @@ def mfma_sample_bound(Xp, R, h, lb, le, prec, split, rows, rows_per_block=256, s
     FP16 entries (scaled by 2^14) add 2^-38 absolute where they fall below
     FP16's normal range,
     n_adds = n / 16 + 16 for the 16-deep FP16 / BF16 products and n / 2 + 2
-    for the 2-deep FP32 ones."""
+    for the 2-deep FP32 ones.  anchor: the centring point when it is one for
+    all rows (the wide-point kernel centres on the mean point)."""
     Xp = np.asarray(Xp, dtype=np.float64)
     R = np.asarray(R, dtype=np.float64)
     n, d = Xp.shape
@@ -65,7 +84,7 @@ def mfma_sample_bound(Xp, R, h, lb, le, prec, split, rows, rows_per_block=256, s
     us = SPLIT_U[(prec, split)]
     nadd = n / 2 + 2 if prec == "f32" else n / 16 + 16
     for t, i in enumerate(rows):
-        a = Xp[(i // rows_per_block) * rows_per_block]
+        a = Xp[(i // rows_per_block) * rows_per_block] if anchor is None else anchor
         xr = np.linalg.norm(Xp[i] - a)
         yr = np.linalg.norm(Xp - a, axis=1)
         q = ((Xp - Xp[i]) ** 2).sum(axis=1)

@@ -249,3 +249,29 @@ def test_batched_symmetric_matvec_per_problem(gpu_lib):
         a, b = off[k], off[k + 1]
         ref = cmath.kmv(X[a:b], X[a:b], W[a:b], p.h)
         assert np.all(np.abs(out[a:b] - ref) <= fp32_product_bound(X[a:b], X[a:b], W[a:b], p.h)), k
+
+
+def test_batched_wide_sample_per_problem(gpu_lib):
+    # a batch of wide points (d = 100) through the matrix-core wide sampler
+    ps = _problems(count=4, d=8, n_hi=900, seed=13)
+    rng = np.random.default_rng(1)
+    for p in ps:  # widen each problem's points to d = 100 (seeded extra coordinates)
+        p.X = np.ascontiguousarray(np.concatenate([p.X, 0.3 * rng.standard_normal((p.X.shape[0], 92))], 1)
+                                   .astype(np.float32))
+        p.h = 0.4 * np.sqrt(100) * (0.5 + p.h / 2)
+    X, off = _concat(ps)
+    perm, tree = gpu_lib.cluster_2mn_batched(_t(X), off, 64, 3)
+    Xp = X[perm.cpu().numpy()]
+    lb, le = leaf_ranges(tree.nodes, X.shape[0])
+    R = sd.random_block(X.shape[0], 64, seed=5)
+    S = gpu_lib.kernel_sample_batched(_t(Xp), off, [p.h for p in ps], _t(R), _t(lb), _t(le), prec="f16",
+                                      split_terms=2).cpu().numpy()
+    mean = Xp.astype(np.float64).mean(axis=0)
+    for k, p in enumerate(ps):
+        a, b = off[k], off[k + 1]
+        Xk, Rk = Xp[a:b], R[a:b]
+        lbk, lek = lb[a:b] - a, le[a:b] - a
+        rows = np.arange(b - a)
+        ref = cmath.sample_masked(Xk, Rk, p.h, lbk, lek, rows)
+        bound = mfma_sample_bound(Xk, Rk, p.h, lbk, lek, "f16", 2, rows, anchor=mean)
+        assert np.all(np.abs(S[a:b] - ref) <= bound), k

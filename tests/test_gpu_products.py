@@ -7,7 +7,7 @@ import torch
 
 import synthdata as sd
 from oracle import cmath, grad as og, cluster as oc, kernel as ok
-from gpu_util import fp32_product_bound, leaf_ranges, sqdist, U32
+from gpu_util import fp32_product_bound, fp32_wide_product_bound, leaf_ranges, sqdist, U32
 
 pytestmark = pytest.mark.gpu
 
@@ -38,7 +38,26 @@ def test_matvec_fp32(gpu_lib, d, nrhs):
     h = 0.2 * np.sqrt(d)
     got = gpu_lib.kernel_matvec(_t(X), _t(Y), h, _t(W), prec="f32").cpu().numpy()
     ref = cmath.kmv(X, Y, W, h)
-    assert np.all(np.abs(got - ref) <= fp32_product_bound(X, Y, W, h))
+    # points wider than 64 take the matrix-core exponent GEMM on centred coordinates
+    bound = fp32_product_bound(X, Y, W, h) if d <= 64 else fp32_wide_product_bound(X, Y, W, h)
+    assert np.all(np.abs(got - ref) <= bound)
+
+
+@pytest.mark.parametrize("d", [65, 100, 784])
+@pytest.mark.parametrize("nrhs", [1, 10, 40])
+def test_matvec_wide_symmetric_and_ragged(gpu_lib, d, nrhs):
+    # K(X, X) W with 700 points: 6 row blocks, ragged panels, two passes of
+    # right-hand sides at nrhs = 40, and the image-like data at d = 784
+    if d == 784:
+        X = sd.c3_image_like(n=700, m=1).X
+        h = 4.0
+    else:
+        X = sd.points(700, d, seed=d, scale=0.3)
+        h = 0.3 * np.sqrt(d)
+    W = sd.vectors(700, nrhs, seed=nrhs)
+    got = gpu_lib.kernel_matvec(_t(X), _t(X), h, _t(W), prec="f32").cpu().numpy()
+    ref = cmath.kmv(X, X, W, h)
+    assert np.all(np.abs(got - ref) <= fp32_wide_product_bound(X, X, W, h))
 
 
 def test_matvec_beta_and_empty(gpu_lib):

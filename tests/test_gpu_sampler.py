@@ -73,3 +73,28 @@ def test_sampler_sampled_rows_large(gpu_lib, prec, split):
     ref = cmath.sample_masked(Xp, R, h, lb, le, rows)
     bound = mfma_sample_bound(Xp, R, h, lb, le, prec, split, rows)
     assert np.all(np.abs(S[rows] - ref) <= bound)
+
+
+@pytest.mark.parametrize("prec,split", [("f16", 1), ("f16", 2), ("bf16", 2)])
+@pytest.mark.parametrize("d,r", [(65, 64), (100, 288), (784, 128)])
+def test_sampler_wide_points(gpu_lib, prec, split, d, r):
+    # points wider than 64: exponents as a chunked GEMM on the matrix cores,
+    # coordinates centred on the mean point; 700 points are 6 row blocks and
+    # a ragged panel, r = 288 leaves a ragged last column pass
+    n = 700
+    if d == 784:
+        X = sd.c3_image_like(n=n, m=1).X
+        h = 4.0
+    else:
+        X = sd.points(n, d, seed=d, scale=0.3)
+        h = 0.4 * np.sqrt(d)
+    t = oc.cluster2mn(X, 64, 1)
+    Xp = np.ascontiguousarray(X[t.perm])
+    lb, le = leaf_ranges(t.nodes, n)
+    R = sd.random_block(n, r, seed=r)
+    S = gpu_lib.kernel_sample(_t(Xp), h, _t(R), _t(lb), _t(le), prec=prec, split_terms=split).cpu().numpy()
+    rows = np.arange(n)
+    ref = cmath.sample_masked(Xp, R, h, lb, le, rows)
+    mean = Xp.astype(np.float64).mean(axis=0)
+    bound = mfma_sample_bound(Xp, R, h, lb, le, prec, split, rows, anchor=mean)
+    assert np.all(np.abs(S - ref) <= bound)
