@@ -308,14 +308,19 @@ typedef struct {
  * factor as preconditioner (F = NULL: no preconditioner) and kernel_matvec
  * (prec mv_prec) for the products;
  * the stopping test uses the recomputed true residual ||Y - (K + lambda I)
- * alpha|| / ||Y|| <= tol per column.  alpha: in = start, out = solution
+ * alpha|| / ||Y|| <= tol per column, formed with products of precision
+ * res_prec; when the iteration's own residual has converged but the true one
+ * has not, the iteration restarts from the true residual (res_prec = KRR_F64
+ * with mv_prec = KRR_F32 is mixed-precision iterative refinement: FP32-entry
+ * products inside, FP64 residuals outside).  alpha: in = start, out = solution
  * (n x nrhs FP64, permuted order).  Returns KRR_E_NOT_CONVERGED if max_iter
  * is reached first (alpha then holds the last iterate).  Synchronizes
  * `stream` once per iteration.
  */
 int krr_refine(hss_ulv_t F, const void *Xp, int64_t n, int32_t xprec, int32_t d, double h,
                double lambda, const double *Y, int32_t nrhs, double *alpha, double tol,
-               int32_t max_iter, int32_t mv_prec, void *stream, krr_refine_stats *stats_host);
+               int32_t max_iter, int32_t mv_prec, int32_t res_prec, void *stream,
+               krr_refine_stats *stats_host);
 
 /* --------------------------------------------------- prediction (A9) */
 
@@ -396,7 +401,7 @@ int kernel_matvec_batched(const void *X, int32_t xprec, const int64_t *offsets, 
 int krr_refine_batched(hss_ulv_t F, const void *Xp, int32_t xprec, const int64_t *offsets,
                        int32_t np, int32_t d, const double *h, const double *lambda,
                        const double *Y, int32_t nrhs, double *alpha, double tol,
-                       int32_t max_iter, int32_t mv_prec, void *stream,
+                       int32_t max_iter, int32_t mv_prec, int32_t res_prec, void *stream,
                        krr_refine_stats *stats_host, double *relres_host);
 
 /* ------------------------------------------------------------ tuning */

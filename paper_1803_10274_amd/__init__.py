@@ -312,16 +312,19 @@ class ULV:
             self.h = None
 
 
-def refine(F, Xp, h, lam, Y, alpha, tol=1e-6, max_iter=100, mv_prec="f32", raise_on_fail=True):
+def refine(F, Xp, h, lam, Y, alpha, tol=1e-6, max_iter=100, mv_prec="f32", raise_on_fail=True, res_prec=None):
     """PCG on (K + lam I) alpha = Y preconditioned by the ULV factor F (None:
-    plain CG); alpha is updated in place."""
+    plain CG); alpha is updated in place.  res_prec: precision of the true
+    residual (default mv_prec; "f64" with mv_prec "f32" is mixed-precision
+    iterative refinement)."""
     _dev(Xp)
     Y2 = _dev(Y, torch.float64).reshape(Y.shape[0], -1)
     a2 = _dev(alpha, torch.float64).reshape(alpha.shape[0], -1)
     st = RefineStats()
     rc = load().krr_refine(F.h if F is not None else None, _p(Xp), Xp.shape[0], _xprec(Xp), Xp.shape[1], float(h),
                            float(lam), _p(Y2), Y2.shape[1],
-                           _p(a2), float(tol), int(max_iter), _prec(mv_prec), _stream(), ctypes.byref(st))
+                           _p(a2), float(tol), int(max_iter), _prec(mv_prec), _prec(res_prec or mv_prec), _stream(),
+                           ctypes.byref(st))
     if rc != 0 and (raise_on_fail or rc != _lib.KRR_E_NOT_CONVERGED):
         check(rc)
     return {"iterations": st.iterations, "matvecs": st.matvecs, "relres": list(st.relres[:Y2.shape[1]]),
@@ -356,7 +359,7 @@ class FitResult:
 
 
 def fit(X, y, h, lam, leaf=128, opts: HssOptions = HssOptions(), seed=7, tol=1e-6, max_iter=200,
-        mv_prec="f32", refine_solution=True, raise_on_fail=True, tune_cache=None):
+        mv_prec="f32", refine_solution=True, raise_on_fail=True, tune_cache=None, res_prec=None):
     """Algorithm 1 steps 0-2: cluster, compress, factor, solve, refine.
 
     info["phases"] holds the wall time of each library call (seconds, the
@@ -393,7 +396,7 @@ def fit(X, y, h, lam, leaf=128, opts: HssOptions = HssOptions(), seed=7, tol=1e-
     info = {"hss": H.stats.as_dict(), "tree_stats": tree.stats.tolist(), "ulv_shift": F.shift}
     if refine_solution:
         info["refine"] = refine(F, Xp, h, lam, yp, ap, tol=tol, max_iter=max_iter, mv_prec=mv_prec,
-                                raise_on_fail=raise_on_fail)
+                                raise_on_fail=raise_on_fail, res_prec=res_prec)
         t = mark("refine", t)
     alpha = scatter_rows(ap, perm)
     if y.dim() == 1:
@@ -498,7 +501,8 @@ def kernel_sample_batched(X, offsets, h, R, leaf_begin=None, leaf_end=None, prec
     return S
 
 
-def refine_batched(F, Xp, offsets, h, lam, Y, alpha, tol=1e-6, max_iter=100, mv_prec="f32", raise_on_fail=True):
+def refine_batched(F, Xp, offsets, h, lam, Y, alpha, tol=1e-6, max_iter=100, mv_prec="f32", raise_on_fail=True,
+                   res_prec=None):
     """PCG on every problem at once (alpha updated in place); returns stats
     with each problem's final relative residuals."""
     _dev(Xp)
@@ -512,7 +516,8 @@ def refine_batched(F, Xp, offsets, h, lam, Y, alpha, tol=1e-6, max_iter=100, mv_
     st = RefineStats()
     rc = load().krr_refine_batched(F.h if F is not None else None, _p(Xp), _xprec(Xp), _i64p(off), npb, Xp.shape[1],
                                    _dblp(hs), _dblp(ls), _p(Y2), Y2.shape[1], _p(a2), float(tol), int(max_iter),
-                                   _prec(mv_prec), _stream(), ctypes.byref(st), _dblp(rel))
+                                   _prec(mv_prec), _prec(res_prec or mv_prec), _stream(), ctypes.byref(st),
+                                   _dblp(rel))
     if rc != 0 and (raise_on_fail or rc != _lib.KRR_E_NOT_CONVERGED):
         check(rc)
     return {"iterations": st.iterations, "matvecs": st.matvecs, "relres": rel.reshape(npb, Y2.shape[1]),

@@ -78,8 +78,8 @@ SIGNATURES = {
     "hss_ulv_destroy": (None, [_vp]),
     "hss_ulv_use_graph": (ctypes.c_int, [_vp, _i32]),
     "hss_solve": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp]),
-    "krr_refine": (ctypes.c_int, [_vp, _vp, _i64, _i32, _i32, _dbl, _dbl, _vp, _i32, _vp, _dbl, _i32, _i32, _vp,
-                                  _P(RefineStats)]),
+    "krr_refine": (ctypes.c_int, [_vp, _vp, _i64, _i32, _i32, _dbl, _dbl, _vp, _i32, _vp, _dbl, _i32, _i32, _i32,
+                                  _vp, _P(RefineStats)]),
     "krr_predict": (ctypes.c_int, [_vp, _i64, _vp, _i64, _i32, _i32, _dbl, _vp, _i32, _vp, _vp, _i32, _vp]),
     "krr_dot_columns": (ctypes.c_int, [_vp, _vp, _i64, _i32, _vp, _vp]),
     "krr_set_tuning": (ctypes.c_int, [_i32, _i32]),
@@ -97,7 +97,7 @@ SIGNATURES = {
     "kernel_matvec_batched": (ctypes.c_int, [_vp, _i32, _P(_i64), _i32, _i32, _P(_dbl), _vp, _i32, _vp, _i32,
                                              _vp]),
     "krr_refine_batched": (ctypes.c_int, [_vp, _vp, _i32, _P(_i64), _i32, _i32, _P(_dbl), _P(_dbl), _vp, _i32,
-                                          _vp, _dbl, _i32, _i32, _vp, _P(RefineStats), _P(_dbl)]),
+                                          _vp, _dbl, _i32, _i32, _i32, _vp, _P(RefineStats), _P(_dbl)]),
 }
 
 _lib = None

@@ -466,7 +466,7 @@ int hss_solve(hss_ulv_t F, const double *B, int32_t nrhs, double *Xout, void *st
 
 int krr_refine(hss_ulv_t F, const void *Xp, int64_t n, int32_t xprec, int32_t d, double h, double lambda,
                const double *Y, int32_t nrhs, double *alpha, double tol, int32_t max_iter, int32_t mv_prec,
-               void *stream, krr_refine_stats *stats_host) {
+               int32_t res_prec, void *stream, krr_refine_stats *stats_host) {
     return guard([&] {
         KRR_REQUIRE(Xp && Y && alpha, "krr_refine: NULL argument");
         KRR_REQUIRE(n >= 1 && (!F || F->n == n), "krr_refine: n must be >= 1 and match the factor");
@@ -474,8 +474,10 @@ int krr_refine(hss_ulv_t F, const void *Xp, int64_t n, int32_t xprec, int32_t d,
         KRR_REQUIRE(nrhs >= 1 && nrhs <= 64, "krr_refine: nrhs must be in [1, 64]");
         KRR_REQUIRE(h > 0.0 && lambda >= 0.0 && tol > 0.0 && max_iter >= 0, "krr_refine: bad parameters");
         KRR_REQUIRE(mv_prec == KRR_F32 || mv_prec == KRR_F64, "krr_refine: mv_prec must be KRR_F32 or KRR_F64");
+        KRR_REQUIRE(res_prec == KRR_F32 || res_prec == KRR_F64, "krr_refine: res_prec must be KRR_F32 or KRR_F64");
         require_device();
-        int rc = refine(F, n, Xp, xprec, d, h, lambda, Y, nrhs, alpha, tol, max_iter, mv_prec, S(stream), stats_host);
+        int rc = refine(F, n, Xp, xprec, d, h, lambda, Y, nrhs, alpha, tol, max_iter, mv_prec, res_prec, S(stream),
+                        stats_host);
         if (rc == KRR_E_NOT_CONVERGED) g_last_error = "krr_refine: tolerance not reached within max_iter";
         return rc;
     });
@@ -673,7 +675,8 @@ int kernel_matvec_batched(const void *X, int32_t xprec, const int64_t *offsets, 
 
 int krr_refine_batched(hss_ulv_t F, const void *Xp, int32_t xprec, const int64_t *offsets, int32_t np, int32_t d,
                        const double *h, const double *lambda, const double *Y, int32_t nrhs, double *alpha,
-                       double tol, int32_t max_iter, int32_t mv_prec, void *stream, krr_refine_stats *stats_host,
+                       double tol, int32_t max_iter, int32_t mv_prec, int32_t res_prec, void *stream,
+                       krr_refine_stats *stats_host,
                        double *relres_host) {
     return guard([&] {
         check_xprec(xprec);
@@ -686,8 +689,10 @@ int krr_refine_batched(hss_ulv_t F, const void *Xp, int32_t xprec, const int64_t
         KRR_REQUIRE(d >= 1 && nrhs >= 1 && nrhs <= 64, "krr_refine_batched: bad sizes");
         KRR_REQUIRE(tol > 0.0 && max_iter >= 0, "krr_refine_batched: bad parameters");
         KRR_REQUIRE(mv_prec == KRR_F32 || mv_prec == KRR_F64, "krr_refine_batched: mv_prec must be KRR_F32 or KRR_F64");
+        KRR_REQUIRE(res_prec == KRR_F32 || res_prec == KRR_F64,
+                    "krr_refine_batched: res_prec must be KRR_F32 or KRR_F64");
         require_device();
-        int rc = refine(F, n, Xp, xprec, d, b.h[0], b.lam[0], Y, nrhs, alpha, tol, max_iter, mv_prec, S(stream),
+        int rc = refine(F, n, Xp, xprec, d, b.h[0], b.lam[0], Y, nrhs, alpha, tol, max_iter, mv_prec, res_prec, S(stream),
                         stats_host, &b, relres_host);
         if (rc == KRR_E_NOT_CONVERGED) g_last_error = "krr_refine_batched: tolerance not reached within max_iter";
         return rc;

@@ -148,10 +148,14 @@ int64_t ulv_factor(const hss_s *H, const std::vector<double> &lam, const std::ve
                    std::vector<uint8_t> *active = nullptr);
 void ulv_solve(const hss_ulv_s *F, const double *Bin, int nrhs, double *Xout, hipStream_t s);
 void hss_matvec_impl(const hss_s *H, const double *x, int nrhs, double *y, hipStream_t s);
+// mv_prec: the iterations' kernel products; res_prec: the recomputed true
+// residual that confirms convergence and restarts the iteration (KRR_F64 with
+// mv_prec KRR_F32 is mixed-precision iterative refinement).
 // batch == nullptr: one problem (h, lambda); otherwise per-problem h and lam
 // (relres_all, if given, receives np x nrhs relative residuals)
 int refine(const hss_ulv_s *F, int64_t n, const void *Xp, int xprec, int d, double h, double lambda, const double *Y,
-           int nrhs, double *alpha, double tol, int max_iter, int mv_prec, hipStream_t s, krr_refine_stats *st,
+           int nrhs, double *alpha, double tol, int max_iter, int mv_prec, int res_prec, hipStream_t s,
+           krr_refine_stats *st,
            const Batch *batch = nullptr, double *relres_all = nullptr);
 void predict_labels(const double *scores, int64_t m, int k, int32_t *labels, hipStream_t s);
 void dot_columns(const double *a, const double *b, int64_t n, int k, double *out, DBuf &scratch, hipStream_t s);

@@ -132,7 +132,8 @@ void predict_labels(const double *scores, int64_t m, int k, int32_t *labels, hip
 }
 
 int refine(const hss_ulv_s *F, int64_t n, const void *Xp, int xprec, int d, double h, double lambda, const double *Y,
-           int nrhs, double *alpha, double tol, int max_iter, int mv_prec, hipStream_t s, krr_refine_stats *st,
+           int nrhs, double *alpha, double tol, int max_iter, int mv_prec, int res_prec, hipStream_t s,
+           krr_refine_stats *st,
            const Batch *batch, double *relres_all) {
     EventTimer timer(s);
     const int64_t len = n * nrhs;
@@ -162,12 +163,12 @@ int refine(const hss_ulv_s *F, int64_t n, const void *Xp, int xprec, int d, doub
             KRR_HIP(hipMemcpyAsync(out, in, sizeof(double) * len, hipMemcpyDeviceToDevice, s));
     };
     int matvecs = 0;
-    auto matvec = [&](const double *x, double *out) {
-        kernel_matvec_impl(Xp, n, Xp, n, d, xprec, h, x, nrhs, 0.0, out, mv_prec, s, batch);
+    auto matvec = [&](const double *x, double *out, int prec) {
+        kernel_matvec_impl(Xp, n, Xp, n, d, xprec, h, x, nrhs, 0.0, out, prec, s, batch);
         ++matvecs;
     };
     auto true_residual = [&]() {
-        matvec(alpha, q.as<double>());
+        matvec(alpha, q.as<double>(), res_prec);
         k_residual<<<ceil_div(len, 256), 256, 0, s>>>(Y, q.as<double>(), alpha, sg.lam.as<double>(),
                                                       sg.pid.as<int32_t>(), n, nrhs, r.as<double>());
         check_launch("k_residual");
@@ -198,7 +199,7 @@ int refine(const hss_ulv_s *F, int64_t n, const void *Xp, int xprec, int d, doub
         for (int c = 0; c < cnt; ++c) done[c] = relres[c] <= tol;
         while (it < max_iter) {
             ++it;
-            matvec(p.as<double>(), q.as<double>());
+            matvec(p.as<double>(), q.as<double>(), mv_prec);
             k_add_shift<<<ceil_div(len, 256), 256, 0, s>>>(q.as<double>(), p.as<double>(), sg.lam.as<double>(),
                                                            sg.pid.as<int32_t>(), n, nrhs);
             check_launch("k_add_shift");

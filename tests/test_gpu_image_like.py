@@ -36,3 +36,21 @@ def test_image_like_fit_matches_dense(gpu_lib, prec):
     clear = (srt[:, -1] - srt[:, -2]) > 1e-6 * np.abs(s_ref).max()
     assert np.all(labels.cpu().numpy()[clear] == lab_ref[clear])
     assert abs(ok.accuracy(labels.cpu().numpy(), p.yt) - ok.accuracy(lab_ref, p.yt)) <= 1.0 / 500
+
+
+def test_image_like_mixed_precision_refinement(gpu_lib):
+    # FP32-entry products inside the iteration, FP64 residuals outside: the
+    # iteration restarts from the FP64 residual until it meets a tolerance
+    # the FP32 products alone cannot certify
+    p = sd.c3_image_like(n=3000, m=1)
+    X = torch.from_numpy(p.X).cuda()
+    Y = torch.from_numpy(np.ascontiguousarray(p.y[:, :2])).cuda()
+    opts = gpu_lib.HssOptions(rtol=1e-2, r0=256, dr=256, r_max=512, prec="f16", cap_policy=1)
+    res = gpu_lib.fit(X, Y, p.h, p.lam, leaf=p.leaf, opts=opts, tol=1e-10, max_iter=1000, mv_prec="f32",
+                      res_prec="f64")
+    assert res.info["refine"]["converged"]
+    Xd = p.X.astype(np.float64)
+    K = ok.kernel_dense(Xd, Xd, p.h)
+    a = res.alpha.cpu().numpy()
+    r = p.y[:, :2] - K @ a - p.lam * a
+    assert np.all(np.linalg.norm(r, axis=0) <= 1e-10 * np.linalg.norm(p.y[:, :2], axis=0) * 1.01)
