@@ -40,14 +40,14 @@ PEAK_FP64_VECTOR = 78.6e12
 # WRITE_SIZE 1,048,576 KiB -> x1.000).  Valid only while the kernel's source
 # file is unchanged (sha256 below); otherwise the bench reports null.
 PMC_TRAFFIC = {
-    "sampling": {"fetch_kib": 35674244.0625, "write_kib": 1048576.0, "fetch_scale": 2.0, "write_scale": 1.0,
+    "sampling": {"fetch_kib": 35674219.0625, "write_kib": 1048576.0, "fetch_scale": 2.0, "write_scale": 1.0,
                  "source": "paper_1803_10274_amd/csrc/sample_mfma.hip",
-                 "sha256": "bb13880f6df282452d873c16ce5e9c725506bc644d342ab3764d687b91de32f7", "n": 1 << 20, "r": 256},
+                 "sha256": "cfc253f215a76348ca29ca680c2353d660e1eec1bb092fbdc27116f7fcd2bdc6", "n": 1 << 20, "r": 256},
     # the symmetric product's five launches: column data, FP32 weights,
     # diagonal blocks, upper triangle, reduction
-    "kernel_product": {"fetch_kib": 20258092.375, "write_kib": 2818343.09375, "fetch_scale": 2.0, "write_scale": 1.0,
+    "kernel_product": {"fetch_kib": 20179393.1875, "write_kib": 2819169.40625, "fetch_scale": 2.0, "write_scale": 1.0,
                        "source": "paper_1803_10274_amd/csrc/matvec.hip",
-                       "sha256": "a15827d83896382c9eba4b36e52f7077ba82dca1ec5588e296225381090ec11b",
+                       "sha256": "49507fab21e49192d1f803ee8cae9898d98a6ba82fe2d07b1fb527194102ce7e",
                        "n": 1 << 20, "r": None},
 }
 
@@ -378,7 +378,7 @@ def grad_leg():
     L, gh, gl, _ = once(st)
     t = time.perf_counter() - t0
     out = {"workload": f"eight_gaussians n={p.X.shape[0]} d={p.d} m_v={p.Xt.shape[0]} h={p.h} lambda={p.lam}",
-           "loss_and_grad_s": t, "loss": float(L), "dL_dlogh": float(gh), "dL_dloglam": float(gl)}
+           "loss_and_grad_s": t, "loss": float(L.detach()), "dL_dlogh": float(gh), "dL_dloglam": float(gl)}
     log(f"gradient: {out}")
     return out
 
