@@ -349,6 +349,187 @@ __global__ __launch_bounds__(MV_ROWS) void k_kmv_sym(const T *__restrict__ X, in
     }
 }
 
+// The same items with the FP64 exponents on the matrix cores.  Per 16 x 16
+// tile, v_mfma_f64_16x16x4_f64 multiplies 16 points (A: 2 c y_p, D / 4
+// k-steps) into 16 rows (B: x_r) on top of the rows' constant -c |x_r|^2
+// (the C operand); the points' constant -c |y_p|^2 enters through a spare k
+// slot when d < D (A holds it, B a one), else as one FP64 add per entry.  The
+// vector ALUs are left with the FP32 entry (convert, exp2) and its two uses.
+// (On gfx950 the matrix-core and vector work of a SIMD do not overlap, and
+// FP64 matrix throughput equals FP64 vector throughput, so the gain is the
+// removed per-entry adds and LDS traffic: measured 3% at d = 8, 30% at
+// d = 18 for one right-hand side, none for two.)  A wave owns RT row tiles of 16;
+// in the FP64 C layout register q of lane l holds row l % 16 of the row tile
+// against point l / 16 + 4 q of the point tile, so row sums stay in the lane
+// (the four quarters are added at the end) and column sums are reduced
+// across the 16 lanes of a quarter, then across the waves in LDS.  Entries
+// and their tile sums are FP32 over a panel of SM_PN points (SM_PN / 4 terms
+// per lane and row), FP64 across panels.
+constexpr int SM_WAVES = 8;
+constexpr int SM_PN = 256;  // points per staged panel
+constexpr int symm_rt(int D) { return D <= 8 ? 8 : 4; }  // row tiles per wave (registers)
+constexpr int symm_rows(int D) { return 16 * SM_WAVES * symm_rt(D); }
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+template <int D, bool PCK>
+__global__ __launch_bounds__(64 * SM_WAVES) void k_kmv_symm(const float *__restrict__ X, int d,
+                                                            const double *__restrict__ ya,
+                                                            const float *__restrict__ wf, int64_t n,
+                                                            const SymItem *__restrict__ items,
+                                                            double *__restrict__ rowpart, float *__restrict__ colpart) {
+    constexpr int NR = 1;  // one right-hand side (two take the vector form)
+    constexpr int RT = symm_rt(D);
+    constexpr int KS = D / 4;  // k-steps of 4
+    constexpr int LDG = ColLd<D>::V;  // the column data's stride (k_col_aug)
+    constexpr int LD = D + 1;         // staged point: 2 c y (D slots), -c |y|^2
+    constexpr int TH = 64 * SM_WAVES;
+    __shared__ double ys[SM_PN * LD];
+    __shared__ float ws[SM_PN][NR];
+    __shared__ float csum[SM_WAVES][SM_PN][NR];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, g = lane >> 4, lr = lane & 15;
+    const SymItem it = items[blockIdx.x];
+    const double c2 = it.c2;
+    double xb[RT][KS];
+    d4v rc[RT];
+    float wi[RT][NR];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+        const int64_t i = it.i0 + (int64_t)(wv * RT + rt) * 16 + lr;
+        const bool ok = i < it.iend;
+        double nrm = 0.0;
+        if (ok)
+            for (int k = 0; k < d; ++k) {
+                const double v = (double)X[i * d + k];
+                nrm = fma(v, v, nrm);
+            }
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const int k = g + 4 * s;
+            xb[rt][s] = !ok ? 0.0 : (k < d ? (double)X[i * d + k] : ((PCK && k == d) ? 1.0 : 0.0));
+        }
+        const double r0 = ok ? -c2 * nrm : 0.0;
+        rc[rt] = d4v{r0, r0, r0, r0};
+#pragma unroll
+        for (int r = 0; r < NR; ++r) wi[rt][r] = ok ? wf[i * NR + r] : 0.0f;
+    }
+    double acc[RT][NR];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int r = 0; r < NR; ++r) acc[rt][r] = 0.0;
+    for (int64_t p0 = it.j0; p0 < it.j1; p0 += SM_PN) {
+        const int cnt = (int)min((int64_t)SM_PN, it.j1 - p0);
+        // stage the panel; points past the item get zero coordinates and a
+        // constant of -1e300 (entry 0 for every row, no infinities in the GEMM)
+        for (int u = tid; u < SM_PN * LD; u += TH) {
+            const int pp = u / LD, k = u % LD;
+            const bool cst = k == D || (PCK && k == d);
+            double v;
+            if (pp < cnt) {
+                const double *row = ya + (p0 + pp) * LDG;
+                v = cst ? row[D] : row[k];
+            } else {
+                v = cst ? -1e300 : 0.0;
+            }
+            ys[u] = v;
+        }
+        for (int u = tid; u < SM_PN * NR; u += TH) {
+            const int pp = u / NR, r = u % NR;
+            ws[pp][r] = pp < cnt ? wf[(p0 + pp) * NR + r] : 0.0f;
+        }
+        __syncthreads();
+        float pacc[RT][NR];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int r = 0; r < NR; ++r) pacc[rt][r] = 0.0f;
+#pragma unroll 1
+        for (int tl = 0; tl < SM_PN / 16; ++tl) {
+            const int pb = tl * 16 + g;  // this quarter's points: pb + 4 q
+            double a[KS];
+#pragma unroll
+            for (int s = 0; s < KS; ++s) a[s] = ys[(tl * 16 + lr) * LD + g + 4 * s];
+            double pq[4];
+            float wp[4][NR];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                pq[q] = PCK ? 0.0 : ys[(pb + 4 * q) * LD + D];
+#pragma unroll
+                for (int r = 0; r < NR; ++r) wp[q][r] = ws[pb + 4 * q][r];
+            }
+            float cacc[4][NR];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int r = 0; r < NR; ++r) cacc[q][r] = 0.0f;
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) {
+                d4v t = rc[rt];
+#pragma unroll
+                for (int s = 0; s < KS; ++s) t = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], xb[rt][s], t, 0, 0, 0);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const double tq = PCK ? t[q] : t[q] + pq[q];
+                    const float e = __builtin_amdgcn_exp2f((float)tq);
+#pragma unroll
+                    for (int r = 0; r < NR; ++r) {
+                        pacc[rt][r] = fmaf(e, wp[q][r], pacc[rt][r]);
+                        cacc[q][r] = fmaf(e, wi[rt][r], cacc[q][r]);
+                    }
+                }
+            }
+            // column sums over the quarter's 16 lanes: reduce-scatter over
+            // lane bits 3 and 2 (leaving point q = 2 b3 + b2), then add over
+            // bits 1 and 0
+#pragma unroll
+            for (int o = 8, h = 2; o >= 4; o >>= 1, h >>= 1) {
+                const bool up = (lane & o) != 0;
+#pragma unroll
+                for (int kk = 0; kk < h; ++kk)
+#pragma unroll
+                    for (int r = 0; r < NR; ++r) {
+                        const float lo = cacc[kk][r], hi = cacc[kk + h][r];
+                        const float send = up ? lo : hi;
+                        cacc[kk][r] = (up ? hi : lo) + __shfl_xor(send, o, 64);
+                    }
+            }
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                float v = cacc[0][r];
+                v += __shfl_xor(v, 2, 64);
+                v += __shfl_xor(v, 1, 64);
+                if ((lane & 3) == 0) csum[wv][pb + 4 * ((lane >> 2) & 3)][r] = v;
+            }
+        }
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int r = 0; r < NR; ++r) acc[rt][r] += (double)pacc[rt][r];
+        __syncthreads();
+        // the waves' column sums; the next panel's staging touches ys / ws only
+        for (int u = tid; u < cnt * NR; u += TH) {
+            const int pp = u / NR, r = u % NR;
+            float c = csum[0][pp][r];
+#pragma unroll
+            for (int w = 1; w < SM_WAVES; ++w) c += csum[w][pp][r];
+            colpart[((int64_t)it.blk * n + p0 + pp) * NR + r] = c;
+        }
+    }
+    // row sums: the four quarters hold the same rows
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+        const int64_t i = it.i0 + (int64_t)(wv * RT + rt) * 16 + lr;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            double v = acc[rt][r];
+            v += __shfl_xor(v, 16, 64);
+            v += __shfl_xor(v, 32, 64);
+            if (g == 0 && i < it.iend) rowpart[((int64_t)it.chunk * n + i) * NR + r] = v;
+        }
+    }
+}
+
 // Per row block of the symmetric product (problem order).
 struct SymBlock {
     int64_t i0, iend;
@@ -601,15 +782,36 @@ void launch_sym(dim3 gd, dim3 gs, dim3 gr, int rows_pb, const T *X, int d, doubl
     check_launch("k_sym_reduce");
 }
 
+template <int D>
+void launch_symm(dim3 gd, dim3 gs, dim3 gr, int rows_pb, const float *X, int d, double c2, const double *ya,
+                 const float *wf, int64_t n, const SampBlock *dt, const SymItem *it, const SymBlock *bl, double *diag,
+                 double *rowpart, float *colpart, double beta, double *Out, hipStream_t s) {
+    k_kmv_sc<float, D, 1, sc_rpt(D)><<<gd, MV_ROWS, 0, s>>>(X, n, d, c2, ya, wf, 1, 0, n, 0, diag, dt);
+    check_launch("k_kmv_sc (diagonal blocks)");
+    if (gs.x > 0) {
+        if (d < D)
+            k_kmv_symm<D, true><<<gs, 64 * SM_WAVES, 0, s>>>(X, d, ya, wf, n, it, rowpart, colpart);
+        else
+            k_kmv_symm<D, false><<<gs, 64 * SM_WAVES, 0, s>>>(X, d, ya, wf, n, it, rowpart, colpart);
+        check_launch("k_kmv_symm");
+    }
+    k_sym_reduce<1><<<gr, 256, 0, s>>>(bl, rows_pb, diag, rowpart, colpart, n, beta, Out);
+    check_launch("k_sym_reduce");
+}
+
 // The symmetric product y = K(X, X) W + beta y (FP32 entries) when it
 // applies (d <= 32, one or two right-hand sides, partial sums within budget);
-// returns false otherwise.
+// returns false otherwise.  FP32 points with one right-hand side take the
+// matrix-core exponents (k_kmv_symm) unless the vector form is selected;
+// the rest the vector form.
 template <class T>
 bool kmv_sym(const T *X, int64_t n, int d, double h, const double *W, int nrhs, double beta, double *Out,
              hipStream_t s, const Batch *batch) {
     const int D = sc_width(d);
     if (D > 32 || (nrhs != 1 && nrhs != 2)) return false;
-    const int rows_pb = MV_ROWS * sc_rpt(D);
+    const bool mc = sizeof(T) == 4 && nrhs == 1 && tune_get(KRR_TUNE_SYMMETRIC) == 1;
+    const int diag_rows = MV_ROWS * sc_rpt(D);  // rows of one k_kmv_sc workgroup
+    const int rows_pb = mc ? symm_rows(D) : diag_rows;
     const int64_t CH = tune_get(KRR_TUNE_SYM_CHUNK);  // columns per item: a multiple of the tile width
     std::vector<int64_t> pb = batch ? batch->pbeg : std::vector<int64_t>{0, n};
     std::vector<double> hs = batch ? batch->h : std::vector<double>{h};
@@ -644,14 +846,16 @@ bool kmv_sym(const T *X, int64_t n, int d, double h, const double *W, int nrhs, 
             }
             nchunks = std::max(nchunks, b.chunk_hi);
             blocks.push_back(b);
-            SampBlock sb{};
-            sb.i0 = b.i0;
-            sb.iend = b.iend;
-            sb.jlo = b.i0;
-            sb.jhi = b.iend;
-            sb.cps = rows_pb;
-            sb.c2 = c2;
-            diag.push_back(sb);
+            for (int64_t r0 = b.i0; r0 < b.iend; r0 += diag_rows) {
+                SampBlock sb{};
+                sb.i0 = r0;
+                sb.iend = std::min<int64_t>(b.iend, r0 + diag_rows);
+                sb.jlo = b.i0;
+                sb.jhi = b.iend;
+                sb.cps = rows_pb;
+                sb.c2 = c2;
+                diag.push_back(sb);
+            }
         }
     }
     const double col_bytes = (double)blocks.size() * n * nrhs * sizeof(float);
@@ -665,7 +869,15 @@ bool kmv_sym(const T *X, int64_t n, int d, double h, const double *W, int nrhs, 
     DBuf dt = upload(diag, s), it = upload(items, s), bl = upload(blocks, s);
     sync(s);  // the host tables are released on return
     dim3 gd((unsigned)diag.size()), gs((unsigned)items.size()), gr(ceil_div(rows_pb, 256), (unsigned)blocks.size());
-#define KRR_SYM(DD, NRR)                                                                                       \
+#define KRR_SYM(DD, NRR)                                                                                        \
+    if constexpr (sizeof(T) == 4 && NRR == 1) {                                                                 \
+        if (mc) {                                                                                               \
+            launch_symm<DD>(gd, gs, gr, rows_pb, X, d, c2, ya.as<double>(), wf.as<float>(), n,                 \
+                                 dt.as<SampBlock>(), it.as<SymItem>(), bl.as<SymBlock>(), dd.as<double>(),      \
+                                 rp.as<double>(), cpart.as<float>(), beta, Out, s);                             \
+            break;                                                                                              \
+        }                                                                                                       \
+    }                                                                                                           \
     launch_sym<T, DD, NRR>(gd, gs, gr, rows_pb, X, d, c2, ya.as<double>(), wf.as<float>(), n, dt.as<SampBlock>(), \
                            it.as<SymItem>(), bl.as<SymBlock>(), dd.as<double>(), rp.as<double>(),              \
                            cpart.as<float>(), beta, Out, s)

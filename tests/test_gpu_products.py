@@ -163,11 +163,21 @@ def sym_chunk(gpu_lib):
     gpu_lib.set_tuning("sym_chunk", old)
 
 
+@pytest.fixture(params=[1, 2], ids=["matrix_core", "vector"])
+def sym_form(gpu_lib, request):
+    """The symmetric product's exponents on the matrix cores (1) or the vector ALUs (2)."""
+    old = gpu_lib.get_tuning("symmetric")
+    gpu_lib.set_tuning("symmetric", request.param)
+    yield request.param
+    gpu_lib.set_tuning("symmetric", old)
+
+
 @pytest.mark.parametrize("d", [3, 8, 16, 18, 24, 30])
 @pytest.mark.parametrize("nrhs", [1, 2])
-def test_symmetric_product(gpu_lib, sym_chunk, d, nrhs):
+def test_symmetric_product(gpu_lib, sym_chunk, sym_form, d, nrhs):
     # K(X, X) W with each off-diagonal entry evaluated once: 5000 points are
     # several row blocks (a ragged last one) and several column chunks per block
+    # (a ragged last panel of points for the matrix-core form)
     n, h = 5000, 0.9
     X = sd.points(n, d, seed=d, scale=0.7)
     W = sd.vectors(n, nrhs, seed=nrhs)
@@ -198,3 +208,22 @@ def test_symmetric_product_switch(gpu_lib):
     ref = cmath.kmv(X, X, W, h)
     bound = fp32_product_bound(X, X, W, h)
     assert np.all(np.abs(a - ref) <= bound) and np.all(np.abs(b - ref) <= bound)
+
+
+@pytest.mark.parametrize("n,d", [(1, 8), (15, 8), (1023, 8), (1025, 8), (2049, 5), (3000, 20)])
+def test_symmetric_forms_agree_ragged(gpu_lib, sym_chunk, n, d):
+    # sizes around the row blocks (1024 rows at d <= 8, 512 above) and the
+    # 256-point panels: both symmetric forms against the oracle
+    X = sd.points(n, d, seed=n, scale=0.6)
+    W = sd.vectors(n, 1, seed=3)
+    Xd = _t(X)
+    ref = cmath.kmv(X, X, W, 0.8)
+    bound = fp32_product_bound(X, X, W, 0.8)
+    old = gpu_lib.get_tuning("symmetric")
+    try:
+        for form in (1, 2):
+            gpu_lib.set_tuning("symmetric", form)
+            got = gpu_lib.kernel_matvec(Xd, Xd, 0.8, _t(W), prec="f32").cpu().numpy()
+            assert np.all(np.abs(got - ref) <= bound), form
+    finally:
+        gpu_lib.set_tuning("symmetric", old)
