@@ -125,6 +125,9 @@ void kernel_matvec_impl(const void *X, int64_t m, const void *Y, int64_t n, int 
 // FP32-entry K(X, Y; h) W + beta Out for points wider than 64 on the matrix cores.
 void kmv_wide_mfma(const float *X, int64_t m, const float *Y, int64_t n, int d, double h, const double *W, int nrhs,
                    double beta, double *Out, hipStream_t s, const Batch *batch);
+template <class T>
+void kmv_wide_mfma64(const T *X, int64_t m, const T *Y, int64_t n, int d, double h, const double *W, int nrhs,
+                     double beta, double *Out, hipStream_t s, const Batch *batch);
 void kernel_matvec_bwd_impl(const void *X, int64_t m, const void *Y, int64_t n, int d, int xprec, double h,
                             const double *W, const double *G, int nrhs, double *dX, double *dY, double *dW,
                             double *dh, int prec, hipStream_t s);

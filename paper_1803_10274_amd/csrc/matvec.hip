@@ -371,6 +371,7 @@ constexpr int symm_rt(int D) { return D <= 8 ? 8 : 4; }  // row tiles per wave (
 constexpr int symm_rows(int D) { return 16 * SM_WAVES * symm_rt(D); }
 
 typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
 
 template <int D, bool PCK>
 __global__ __launch_bounds__(64 * SM_WAVES) void k_kmv_symm(const float *__restrict__ X, int d,
@@ -558,6 +559,170 @@ __global__ void k_sym_reduce(const SymBlock *__restrict__ blocks, int rows_pb, c
         for (int r = 0; r < NR; ++r) s[r] += (double)colpart[(bb * n + i) * NR + r];
 #pragma unroll
     for (int r = 0; r < NR; ++r) out[i * NR + r] = beta != 0.0 ? s[r] + beta * out[i * NR + r] : s[r];
+}
+
+// The same items with FP32 exponents on the matrix cores.  The kernel is
+// translation invariant, so each item re-centres its rows and columns on its
+// row block's mean point a (x' = x - a, y' = y - a, all FP32): for the pairs
+// that carry weight both vectors are short and the FP32 norm expansion
+// t = -c |x'|^2 + 2 c x'.y' - c |y'|^2 loses little to cancellation.
+// v_mfma_f32_16x16x4_f32 forms t on top of the row constant (C operand), the
+// column constant enters through a spare k slot when d < D, else as one FP32
+// add.  Register q of lane l holds row l % 16 of the row tile against point
+// 4 (l / 16) + q of the point tile; sums as in k_kmv_symm.
+constexpr __device__ __forceinline__ int symf_point(int g, int q) { return 4 * g + q; }
+
+template <int D, bool PCK>
+__global__ __launch_bounds__(64 * SM_WAVES) void k_kmv_symf(const float *__restrict__ X, int d,
+                                                            const float *__restrict__ anchors,
+                                                            const float *__restrict__ wf, int64_t n,
+                                                            const SymItem *__restrict__ items,
+                                                            double *__restrict__ rowpart, float *__restrict__ colpart) {
+    constexpr int RT = symm_rt(D);
+    constexpr int KS = D / 4;  // k-steps of 4
+    constexpr int LD = D + 1;  // staged point: 2 c y' (D slots), -c |y'|^2
+    constexpr int TH = 64 * SM_WAVES;
+    __shared__ float ys[SM_PN * LD];
+    __shared__ float ws[SM_PN];
+    __shared__ float csum[SM_WAVES][SM_PN];
+    __shared__ float anc[D];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, g = lane >> 4, lr = lane & 15;
+    const SymItem it = items[blockIdx.x];
+    const float c = (float)it.c2;
+    if (tid < D) anc[tid] = tid < d ? anchors[it.blk * d + tid] : 0.0f;
+    __syncthreads();
+    float xb[RT][KS];
+    f4v rc[RT];
+    float wi[RT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+        const int64_t i = it.i0 + (int64_t)(wv * RT + rt) * 16 + lr;
+        const bool ok = i < it.iend;
+        float nrm = 0.0f;
+        if (ok)
+            for (int k = 0; k < d; ++k) {
+                const float v = X[i * d + k] - anc[k];
+                nrm = fmaf(v, v, nrm);
+            }
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const int k = g + 4 * s;
+            xb[rt][s] = !ok ? 0.0f : (k < d ? X[i * d + k] - anc[k] : ((PCK && k == d) ? 1.0f : 0.0f));
+        }
+        const float r0 = ok ? -c * nrm : 0.0f;
+        rc[rt] = f4v{r0, r0, r0, r0};
+        wi[rt] = ok ? wf[i] : 0.0f;
+    }
+    double acc[RT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) acc[rt] = 0.0;
+    for (int64_t p0 = it.j0; p0 < it.j1; p0 += SM_PN) {
+        const int cnt = (int)min((int64_t)SM_PN, it.j1 - p0);
+        // stage the panel re-centred on the anchor; points past the item get
+        // zero coordinates and a constant of -1e30 (entry 0 for every row)
+        if (tid < SM_PN) {
+            float *dst = ys + tid * LD;
+            if (tid < cnt) {
+                const float *y = X + (p0 + tid) * d;
+                float nrm = 0.0f;
+                for (int k = 0; k < D; ++k) {
+                    const float v = k < d ? y[k] - anc[k] : 0.0f;
+                    nrm = fmaf(v, v, nrm);
+                    dst[k] = (2.0f * c) * v;
+                }
+                dst[D] = -c * nrm;
+                if (PCK) dst[d] = dst[D];
+            } else {
+                for (int k = 0; k < D; ++k) dst[k] = 0.0f;
+                dst[D] = -1e30f;
+                if (PCK) dst[d] = -1e30f;
+            }
+            ws[tid] = tid < cnt ? wf[p0 + tid] : 0.0f;
+        }
+        __syncthreads();
+        float pacc[RT];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) pacc[rt] = 0.0f;
+#pragma unroll 1
+        for (int tl = 0; tl < SM_PN / 16; ++tl) {
+            float a[KS];
+#pragma unroll
+            for (int s = 0; s < KS; ++s) a[s] = ys[(tl * 16 + lr) * LD + g + 4 * s];
+            float pq[4], wp[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int pp = tl * 16 + symf_point(g, q);
+                pq[q] = PCK ? 0.0f : ys[pp * LD + D];
+                wp[q] = ws[pp];
+            }
+            float cacc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) {
+                f4v t = rc[rt];
+#pragma unroll
+                for (int s = 0; s < KS; ++s) t = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], xb[rt][s], t, 0, 0, 0);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float e = __builtin_amdgcn_exp2f(PCK ? t[q] : t[q] + pq[q]);
+                    pacc[rt] = fmaf(e, wp[q], pacc[rt]);
+                    cacc[q] = fmaf(e, wi[rt], cacc[q]);
+                }
+            }
+            // column sums over the quarter's 16 lanes (reduce-scatter over lane
+            // bits 3 and 2, leaving q = 2 b3 + b2, then add over bits 1 and 0)
+#pragma unroll
+            for (int o = 8, h = 2; o >= 4; o >>= 1, h >>= 1) {
+                const bool up = (lane & o) != 0;
+#pragma unroll
+                for (int kk = 0; kk < h; ++kk) {
+                    const float lo = cacc[kk], hi = cacc[kk + h];
+                    const float send = up ? lo : hi;
+                    cacc[kk] = (up ? hi : lo) + __shfl_xor(send, o, 64);
+                }
+            }
+            float v = cacc[0];
+            v += __shfl_xor(v, 2, 64);
+            v += __shfl_xor(v, 1, 64);
+            if ((lane & 3) == 0) csum[wv][tl * 16 + symf_point(g, (lane >> 2) & 3)] = v;
+        }
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) acc[rt] += (double)pacc[rt];
+        __syncthreads();
+        // the waves' column sums; the next panel's staging touches ys / ws only
+        if (tid < cnt) {
+            float cs = csum[0][tid];
+#pragma unroll
+            for (int w = 1; w < SM_WAVES; ++w) cs += csum[w][tid];
+            colpart[(int64_t)it.blk * n + p0 + tid] = cs;
+        }
+    }
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+        const int64_t i = it.i0 + (int64_t)(wv * RT + rt) * 16 + lr;
+        double v = acc[rt];
+        v += __shfl_xor(v, 16, 64);
+        v += __shfl_xor(v, 32, 64);
+        if (g == 0 && i < it.iend) rowpart[(int64_t)it.chunk * n + i] = v;
+    }
+}
+
+// anchors[b] = the mean point of row block b (FP64 sums, stored in FP32).
+__global__ void k_block_mean(const float *__restrict__ X, int d, const SymBlock *__restrict__ blocks,
+                             float *__restrict__ anchors) {
+    const SymBlock b = blocks[blockIdx.x];
+    __shared__ double part[256];
+    for (int k = 0; k < d; ++k) {
+        double sacc = 0.0;
+        for (int64_t i = b.i0 + threadIdx.x; i < b.iend; i += blockDim.x) sacc += (double)X[i * d + k];
+        part[threadIdx.x] = sacc;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if ((int)threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) anchors[blockIdx.x * d + k] = (float)(part[0] / (double)(b.iend - b.i0));
+        __syncthreads();
+    }
 }
 
 // Column data of k_kmv_sc: ya[j] = (2 c y_j1 .. 2 c y_jd, 0 .., -c |y_j|^2 at
@@ -799,6 +964,28 @@ void launch_symm(dim3 gd, dim3 gs, dim3 gr, int rows_pb, const float *X, int d, 
     check_launch("k_sym_reduce");
 }
 
+template <int D>
+void launch_symf(dim3 gd, dim3 gs, dim3 gr, int rows_pb, const float *X, int d, double c2, const double *ya,
+                 const float *wf, int64_t n, const SampBlock *dt, const SymItem *it, const SymBlock *bl,
+                 int64_t nblocks, double *diag, double *rowpart, float *colpart, double beta, double *Out,
+                 hipStream_t s) {
+    k_kmv_sc<float, D, 1, sc_rpt(D)><<<gd, MV_ROWS, 0, s>>>(X, n, d, c2, ya, wf, 1, 0, n, 0, diag, dt);
+    check_launch("k_kmv_sc (diagonal blocks)");
+    if (gs.x > 0) {
+        DBuf anchors = dalloc<float>((size_t)nblocks * d);
+        k_block_mean<<<(unsigned)nblocks, 256, 0, s>>>(X, d, bl, anchors.as<float>());
+        check_launch("k_block_mean");
+        if (d < D)
+            k_kmv_symf<D, true><<<gs, 64 * SM_WAVES, 0, s>>>(X, d, anchors.as<float>(), wf, n, it, rowpart, colpart);
+        else
+            k_kmv_symf<D, false><<<gs, 64 * SM_WAVES, 0, s>>>(X, d, anchors.as<float>(), wf, n, it, rowpart, colpart);
+        check_launch("k_kmv_symf");
+        sync(s);  // the anchors are released on return
+    }
+    k_sym_reduce<1><<<gr, 256, 0, s>>>(bl, rows_pb, diag, rowpart, colpart, n, beta, Out);
+    check_launch("k_sym_reduce");
+}
+
 // The symmetric product y = K(X, X) W + beta y (FP32 entries) when it
 // applies (d <= 32, one or two right-hand sides, partial sums within budget);
 // returns false otherwise.  FP32 points with one right-hand side take the
@@ -810,8 +997,9 @@ bool kmv_sym(const T *X, int64_t n, int d, double h, const double *W, int nrhs, 
     const int D = sc_width(d);
     if (D > 32 || (nrhs != 1 && nrhs != 2)) return false;
     const bool mc = sizeof(T) == 4 && nrhs == 1 && tune_get(KRR_TUNE_SYMMETRIC) == 1;
+    const bool mf = sizeof(T) == 4 && nrhs == 1 && tune_get(KRR_TUNE_SYMMETRIC) == 3;
     const int diag_rows = MV_ROWS * sc_rpt(D);  // rows of one k_kmv_sc workgroup
-    const int rows_pb = mc ? symm_rows(D) : diag_rows;
+    const int rows_pb = (mc || mf) ? symm_rows(D) : diag_rows;
     const int64_t CH = tune_get(KRR_TUNE_SYM_CHUNK);  // columns per item: a multiple of the tile width
     std::vector<int64_t> pb = batch ? batch->pbeg : std::vector<int64_t>{0, n};
     std::vector<double> hs = batch ? batch->h : std::vector<double>{h};
@@ -877,6 +1065,12 @@ bool kmv_sym(const T *X, int64_t n, int d, double h, const double *W, int nrhs, 
                                  rp.as<double>(), cpart.as<float>(), beta, Out, s);                             \
             break;                                                                                              \
         }                                                                                                       \
+        if (mf) {                                                                                               \
+            launch_symf<DD>(gd, gs, gr, rows_pb, X, d, c2, ya.as<double>(), wf.as<float>(), n,                 \
+                            dt.as<SampBlock>(), it.as<SymItem>(), bl.as<SymBlock>(), (int64_t)blocks.size(),    \
+                            dd.as<double>(), rp.as<double>(), cpart.as<float>(), beta, Out, s);                 \
+            break;                                                                                              \
+        }                                                                                                       \
     }                                                                                                           \
     launch_sym<T, DD, NRR>(gd, gs, gr, rows_pb, X, d, c2, ya.as<double>(), wf.as<float>(), n, dt.as<SampBlock>(), \
                            it.as<SymItem>(), bl.as<SymBlock>(), dd.as<double>(), rp.as<double>(),              \
@@ -909,6 +1103,12 @@ void kmv_typed(const T *X, int64_t m, const T *Y, int64_t n, int d, double h, co
     if constexpr (sizeof(C) == 4 && sizeof(T) == 4) {
         if (d > 64) {  // wide points: the exponents as a matrix-core GEMM
             kmv_wide_mfma(X, m, Y, n, d, h, W, nrhs, beta, Out, s, batch);
+            return;
+        }
+    }
+    if constexpr (sizeof(C) == 8) {
+        if (d > 64) {  // FP64 entries of wide points: an FP64 matrix-core GEMM
+            kmv_wide_mfma64<T>(X, m, Y, n, d, h, W, nrhs, beta, Out, s, batch);
             return;
         }
     }

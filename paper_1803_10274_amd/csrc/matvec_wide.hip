@@ -128,7 +128,169 @@ __global__ void k_reduce_parts(const double *__restrict__ part, int nsplit, int6
     out[t] = (beta != 0.0) ? s + beta * out[t] : s;
 }
 
+// FP64 entries: the exponent GEMM in FP64 on v_mfma_f64_16x16x4_f64.  A
+// workgroup of 8 waves owns 128 rows (16 per wave) and walks the columns in
+// panels of 128 points, accumulating t = x~_i . y~_j (natural-log units) over K
+// chunks of 32 staged through LDS; in the FP64 C layout register q of lane l
+// holds row l % 16 of the wave's rows against point l / 16 + 4 q of each
+// 16-point tile.  exp (FP64) turns t into the entry, and the panel's weights
+// (FP64, up to 16 right-hand sides per pass) are multiplied in on the vector
+// ALUs: for d > 64 the GEMM's d + 2 FMAs per entry dominate the entry's cost.
+constexpr int W64 = 8;            // waves per workgroup
+constexpr int W64ROWS = 16 * W64;  // rows per workgroup
+constexpr int W64PN = 128;         // points per panel (8 tiles of 16)
+constexpr int W64KC = 32;          // augmented coordinates per LDS chunk
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+template <int NR>
+__global__ __launch_bounds__(64 * W64) void k_kmv_wmfma64(const double *__restrict__ XA, int64_t m,
+                                                          const double *__restrict__ YA, int64_t n, int KP,
+                                                          const double *__restrict__ W, int nrhs, int rhs0, int nrc,
+                                                          int64_t cols_per_split, double *__restrict__ part,
+                                                          const SampBlock *__restrict__ bt) {
+    constexpr int TH = 64 * W64;
+    constexpr int LDK = W64KC + 1;
+    constexpr int PT = W64PN / 16;
+    __shared__ double xs[W64ROWS][LDK];
+    __shared__ double ys[W64PN][LDK];
+    __shared__ double wsh[W64PN][NR];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, g = lane >> 4, lr = lane & 15;
+    const int split = blockIdx.y;
+    int64_t i0, iend, j0, j1;
+    if (bt) {
+        const SampBlock sb = bt[blockIdx.x];
+        i0 = sb.i0;
+        iend = sb.iend;
+        j0 = sb.jlo + split * sb.cps;
+        j1 = min(sb.jhi, j0 + sb.cps);
+    } else {
+        i0 = (int64_t)blockIdx.x * W64ROWS;
+        iend = m;
+        j0 = split * cols_per_split;
+        j1 = min(n, j0 + cols_per_split);
+    }
+    double acc[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) acc[r] = 0.0;
+    for (int64_t p0 = j0; p0 < j1; p0 += W64PN) {
+        d4v t[PT];
+#pragma unroll
+        for (int pt = 0; pt < PT; ++pt) t[pt] = d4v{0.0, 0.0, 0.0, 0.0};
+        for (int kc = 0; kc < KP; kc += W64KC) {
+            for (int u = tid; u < W64ROWS * W64KC; u += TH) {
+                const int rr = u / W64KC, kk = u % W64KC;
+                const int64_t gi = i0 + rr, gj = p0 + rr;  // W64ROWS == W64PN
+                xs[rr][kk] = gi < iend ? XA[gi * KP + kc + kk] : 0.0;
+                ys[rr][kk] = gj < j1 ? YA[gj * KP + kc + kk] : 0.0;
+            }
+            __syncthreads();
+#pragma unroll 2
+            for (int kk = 0; kk < W64KC; kk += 4) {
+                const double b = xs[16 * wv + lr][kk + g];
+#pragma unroll
+                for (int pt = 0; pt < PT; ++pt)
+                    t[pt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ys[16 * pt + lr][kk + g], b, t[pt], 0, 0, 0);
+            }
+            __syncthreads();
+        }
+        // the panel's weights (zero past the column range and past nrc)
+        for (int u = tid; u < W64PN * NR; u += TH) {
+            const int pp = u / NR, r = u % NR;
+            const int64_t gj = p0 + pp;
+            wsh[pp][r] = (r < nrc && gj < j1) ? W[gj * nrhs + rhs0 + r] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int pt = 0; pt < PT; ++pt)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double e = exp(t[pt][q]);  // padded points meet zero weights
+                const int pp = 16 * pt + g + 4 * q;
+#pragma unroll
+                for (int r = 0; r < NR; ++r) acc[r] = fma(e, wsh[pp][r], acc[r]);
+            }
+        // the next panel rewrites the weights only after its K loop's barriers
+    }
+    const int64_t row = i0 + 16 * wv + lr;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        double v = acc[r];
+        v += __shfl_xor(v, 16, 64);
+        v += __shfl_xor(v, 32, 64);
+        if (g == 0 && r < nrc && row < iend) part[((int64_t)split * m + row) * nrhs + rhs0 + r] = v;
+    }
+}
+
 }  // namespace
+
+// Out = K(X, Y; h) W + beta Out with FP64 entries for d > 64 (T: the points'
+// type; a batch multiplies its own points).
+template <class T>
+void kmv_wide_mfma64(const T *X, int64_t m, const T *Y, int64_t n, int d, double h, const double *W, int nrhs,
+                     double beta, double *Out, hipStream_t s, const Batch *batch) {
+    const int KP = (d + 2 + W64KC - 1) / W64KC * W64KC;
+    const double cn = 1.0 / (2.0 * h * h);
+    DBuf mean = dalloc<double>(d), XA = dalloc<double>((size_t)m * KP), YA = dalloc<double>((size_t)n * KP);
+    DBuf pb, cp, btab;
+    int64_t nb = 0, cps = 0;
+    int nsplit;
+    if (batch) {
+        std::vector<double> cpr(batch->np());
+        for (int k = 0; k < batch->np(); ++k) cpr[k] = 1.0 / (2.0 * batch->h[k] * batch->h[k]);
+        pb = upload(batch->pbeg, s);
+        cp = upload(cpr, s);
+        std::vector<SampBlock> blocks = row_blocks(*batch, W64ROWS);
+        nb = (int64_t)blocks.size();
+        int64_t nmax = 0;
+        for (int k = 0; k < batch->np(); ++k) nmax = std::max(nmax, batch->size(k));
+        nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(tune_get(KRR_TUNE_MV_BLOCKS), nb),
+                                                             ceil_div(nmax, 4 * W64PN)));
+        for (auto &b : blocks) {
+            int64_t c = ceil_div(b.jhi - b.jlo, nsplit);
+            b.cps = (c + W64PN - 1) / W64PN * W64PN;
+        }
+        btab = upload(blocks, s);
+        sync(s);
+    } else {
+        const int64_t rb = ceil_div(m, W64ROWS);
+        nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(tune_get(KRR_TUNE_MV_BLOCKS), rb),
+                                                             ceil_div(n, 4 * W64PN)));
+        cps = (ceil_div(n, nsplit) + W64PN - 1) / W64PN * W64PN;
+        nsplit = (int)ceil_div(n, cps);
+    }
+    k_col_mean<T><<<d, 256, 0, s>>>(Y, n, d, mean.as<double>());
+    check_launch("k_col_mean");
+    k_wide_aug64<T><<<(unsigned)m, 256, 0, s>>>(X, m, d, KP, mean.as<double>(), cn, pb.as<int64_t>(),
+                                                cp.as<double>(), batch ? batch->np() : 0, 0, XA.as<double>());
+    check_launch("k_wide_aug64");
+    k_wide_aug64<T><<<(unsigned)n, 256, 0, s>>>(Y, n, d, KP, mean.as<double>(), cn, pb.as<int64_t>(),
+                                                cp.as<double>(), batch ? batch->np() : 0, 1, YA.as<double>());
+    check_launch("k_wide_aug64");
+    DBuf part = dalloc<double>((size_t)nsplit * m * nrhs);
+    dim3 grid((unsigned)(batch ? nb : ceil_div(m, W64ROWS)), nsplit);
+    for (int r0 = 0; r0 < nrhs; r0 += 16) {
+        const int nrc = std::min(16, nrhs - r0);
+        if (nrc > 8) {
+            k_kmv_wmfma64<16><<<grid, 64 * W64, 0, s>>>(XA.as<double>(), m, YA.as<double>(), n, KP, W, nrhs, r0, nrc,
+                                                        cps, part.as<double>(), btab.as<SampBlock>());
+        } else if (nrc > 2) {
+            k_kmv_wmfma64<8><<<grid, 64 * W64, 0, s>>>(XA.as<double>(), m, YA.as<double>(), n, KP, W, nrhs, r0, nrc,
+                                                       cps, part.as<double>(), btab.as<SampBlock>());
+        } else {
+            k_kmv_wmfma64<2><<<grid, 64 * W64, 0, s>>>(XA.as<double>(), m, YA.as<double>(), n, KP, W, nrhs, r0, nrc,
+                                                       cps, part.as<double>(), btab.as<SampBlock>());
+        }
+        check_launch("k_kmv_wmfma64");
+    }
+    const int64_t mn = m * nrhs;
+    k_reduce_parts<<<ceil_div(mn, 256), 256, 0, s>>>(part.as<double>(), nsplit, mn, beta, Out);
+    check_launch("k_reduce_parts");
+    sync(s);  // temporaries are released on return
+}
+template void kmv_wide_mfma64<float>(const float *, int64_t, const float *, int64_t, int, double, const double *, int,
+                                     double, double *, hipStream_t, const Batch *);
+template void kmv_wide_mfma64<double>(const double *, int64_t, const double *, int64_t, int, double, const double *,
+                                      int, double, double *, hipStream_t, const Batch *);
 
 // Out = K(X, Y; h) W + beta Out with FP32 entries for d > 64 (X: m FP32
 // points, Y: n FP32 points; a batch multiplies its own points).
@@ -165,7 +327,7 @@ void kmv_wide_mfma(const float *X, int64_t m, const float *Y, int64_t n, int d, 
         nsplit = (int)ceil_div(n, cps);
     }
     // one anchor for rows and columns: the mean of the columns' points
-    k_col_mean<<<d, 256, 0, s>>>(Y, n, d, mean.as<double>());
+    k_col_mean<float><<<d, 256, 0, s>>>(Y, n, d, mean.as<double>());
     check_launch("k_col_mean");
     k_wide_aug<<<(unsigned)m, 256, 0, s>>>(X, m, d, KP, mean.as<double>(), c2, pb.as<int64_t>(), cp.as<double>(),
                                           batch ? batch->np() : 0, 0.0f, 0, XA.as<float>());

@@ -738,7 +738,7 @@ void sample_wide(const float *X, int64_t n, int d, double h, const void *Rsw, in
         bt = upload(blocks, s);
         sync(s);
     }
-    k_col_mean<<<d, 256, 0, s>>>(X, n, d, mean.as<double>());
+    k_col_mean<float><<<d, 256, 0, s>>>(X, n, d, mean.as<double>());
     check_launch("k_col_mean");
     const float off = prec == KRR_F16_SPLIT ? 14.0f : 0.0f;  // FP16 entries carry a 2^14 scale
     k_wide_aug<<<(unsigned)n, 256, 0, s>>>(X, n, d, KP, mean.as<double>(), c2, pb.as<int64_t>(), cp.as<double>(),

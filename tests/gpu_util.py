@@ -48,6 +48,60 @@ def fp32_wide_product_bound(X, Y, W, h, panel=128, safety=4.0):
     return safety * U32 * ((panel + 2) * (K @ aW) + (K * T) @ aW)
 
 
+U64 = 2.0 ** -53
+
+
+def fp64_wide_product_bound(X, Y, W, h, safety=4.0, anchor=None):
+    """Bound for the FP64-entry product of wide points: exponents from the FP64
+    norm expansion on coordinates centred on the mean of Y (matrix-core dot
+    products of d + 2 terms and two FP64 norms: |dt| <= (d + 6) u (|x'| +
+    |y'|)^2 / (2 h^2)), exp within 1 ulp, FP64 sums over the columns.
+    anchor: the centring point when it is not the mean of Y (a batch centres
+    on the mean of all its points)."""
+    X = np.asarray(X, dtype=np.float64)
+    Y = np.asarray(Y, dtype=np.float64)
+    a = Y.mean(axis=0) if anchor is None else np.asarray(anchor, dtype=np.float64)
+    nx = np.linalg.norm(X - a, axis=1)
+    ny = np.linalg.norm(Y - a, axis=1)
+    K = np.exp(-sqdist(X, Y) / (2 * h * h))
+    T = (X.shape[1] + 6) * (nx[:, None] + ny[None, :]) ** 2 / (2 * h * h)
+    aW = np.abs(np.asarray(W, dtype=np.float64)).reshape(W.shape[0], -1)
+    return safety * U64 * ((Y.shape[0] + 4) * (K @ aW) + (K * T) @ aW)
+
+
+def sym_rows_per_block(d):
+    """Row block of the matrix-core symmetric product: 1024 rows for padded
+    widths up to 8, else 512."""
+    D = (d + 3) // 4 * 4 if d <= 24 else 32
+    return 1024 if D <= 8 else 512
+
+
+def fp32_sym_anchored_bound(X, W, h, rows_per_block, tile=64, safety=4.0):
+    """Bound for the symmetric FP32 kernel product with FP32 exponents
+    re-centred per row block: an entry between rows of different blocks is
+    evaluated once, by the earlier block, on x' = x - a, y' = y - a with a that
+    block's mean point; its FP32 norm expansion (d FMAs per norm, d + 2 terms
+    in the matrix-core sum, two constants) is off by at most
+    (2 d + 6) u (|x'| + |y'|)^2 / (2 h^2) in natural-log units.  Entries inside
+    a diagonal block use the FP64 exponent (fp32_product_bound's terms)."""
+    X = np.asarray(X, dtype=np.float64)
+    n, d = X.shape
+    blk = np.arange(n) // rows_per_block
+    nb = blk[-1] + 1 if n else 0
+    anchors = np.stack([X[b * rows_per_block:(b + 1) * rows_per_block].mean(axis=0) for b in range(nb)])
+    anchors = anchors.astype(np.float32).astype(np.float64)
+    r = np.sqrt(((X[:, None, :] - anchors[None, :, :]) ** 2).sum(axis=2))  # |x_i - a_b|
+    bmin = np.minimum(blk[:, None], blk[None, :])
+    rows = np.arange(n)
+    S = (r[rows[:, None], bmin] + r[rows[None, :], bmin]) ** 2 / (2 * h * h)
+    S[blk[:, None] == blk[None, :]] = 0.0
+    q = sqdist(X, X)
+    T = q / (2 * h * h)
+    K = np.exp(-T)
+    aW = np.abs(np.asarray(W, dtype=np.float64)).reshape(W.shape[0], -1)
+    return safety * U32 * ((tile + 2) * (K @ aW) + (d + 3) * ((K * T) @ aW) + (2 * d + 6) * ((K * S) @ aW))
+
+
 def leaf_ranges(nodes, n):
     lb = np.empty(n, dtype=np.int32)
     le = np.empty(n, dtype=np.int32)

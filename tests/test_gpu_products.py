@@ -7,7 +7,8 @@ import torch
 
 import synthdata as sd
 from oracle import cmath, grad as og, cluster as oc, kernel as ok
-from gpu_util import fp32_product_bound, fp32_wide_product_bound, leaf_ranges, sqdist, U32
+from gpu_util import (fp32_product_bound, fp32_sym_anchored_bound, fp32_wide_product_bound, fp64_wide_product_bound,
+                      leaf_ranges, sqdist, sym_rows_per_block, U32)
 
 pytestmark = pytest.mark.gpu
 
@@ -25,8 +26,32 @@ def test_matvec_fp64(gpu_lib, d, nrhs):
     h = 0.2 * np.sqrt(d)
     got = gpu_lib.kernel_matvec(_t(X), _t(Y), h, _t(W), prec="f64").cpu().numpy()
     ref = cmath.kmv(X, Y, W, h)
-    scale = cmath.kmv(X, Y, np.abs(W), h)
-    assert np.all(np.abs(got - ref) <= 1e-13 * scale + 1e-300)
+    if d <= 64:  # exact coordinate differences
+        scale = cmath.kmv(X, Y, np.abs(W), h)
+        assert np.all(np.abs(got - ref) <= 1e-13 * scale + 1e-300)
+    else:  # FP64 matrix-core norm expansion on centred coordinates
+        assert np.all(np.abs(got - ref) <= fp64_wide_product_bound(X, Y, W, h))
+
+
+@pytest.mark.parametrize("xdtype", [np.float32, np.float64])
+def test_matvec_fp64_wide_batched_and_ragged(gpu_lib, xdtype):
+    # FP64 entries of wide points: three problems of ragged sizes (row blocks
+    # of 128, panels of 128 points), per-problem widths, 20 right-hand sides
+    # (a pass of 16 and one of 4)
+    sizes, d = [130, 7, 300], 100
+    rng = np.random.default_rng(4)
+    Xs = [(0.3 * rng.standard_normal((k, d))).astype(xdtype) for k in sizes]
+    hs = [2.0, 3.0, 2.5]
+    X = np.concatenate(Xs)
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    W = sd.vectors(X.shape[0], 20, seed=5)
+    got = gpu_lib.kernel_matvec_batched(_t(X), off, hs, _t(W), prec="f64").cpu().numpy()
+    for k in range(3):
+        a, b = off[k], off[k + 1]
+        ref = cmath.kmv(Xs[k], Xs[k], W[a:b], hs[k])
+        # the batch centres every problem on the mean of all points
+        bound = fp64_wide_product_bound(Xs[k], Xs[k], W[a:b], hs[k], anchor=X.astype(np.float64).mean(axis=0))
+        assert np.all(np.abs(got[a:b] - ref) <= bound), k
 
 
 @pytest.mark.parametrize("d", [8, 18, 54, 784])
@@ -163,9 +188,10 @@ def sym_chunk(gpu_lib):
     gpu_lib.set_tuning("sym_chunk", old)
 
 
-@pytest.fixture(params=[1, 2], ids=["matrix_core", "vector"])
+@pytest.fixture(params=[1, 2, 3], ids=["matrix_core_f64", "vector", "matrix_core_f32"])
 def sym_form(gpu_lib, request):
-    """The symmetric product's exponents on the matrix cores (1) or the vector ALUs (2)."""
+    """The symmetric product's exponents: FP64 on the matrix cores (1), FP64 on
+    the vector ALUs (2), FP32 on the matrix cores re-centred per row block (3)."""
     old = gpu_lib.get_tuning("symmetric")
     gpu_lib.set_tuning("symmetric", request.param)
     yield request.param
@@ -184,7 +210,11 @@ def test_symmetric_product(gpu_lib, sym_chunk, sym_form, d, nrhs):
     Xd = _t(X)
     out = gpu_lib.kernel_matvec(Xd, Xd, h, _t(W), prec="f32").cpu().numpy().reshape(n, nrhs)
     ref = cmath.kmv(X, X, W, h)
-    assert np.all(np.abs(out - ref) <= fp32_product_bound(X, X, W, h))
+    if sym_form == 3 and nrhs == 1:
+        sym_bound = fp32_sym_anchored_bound(X, W, h, sym_rows_per_block(d))
+    else:
+        sym_bound = fp32_product_bound(X, X, W, h)
+    assert np.all(np.abs(out - ref) <= sym_bound)
     # the plain product (the same points at another address) agrees to the same bound
     plain = gpu_lib.kernel_matvec(Xd, Xd.clone(), h, _t(W), prec="f32").cpu().numpy().reshape(n, nrhs)
     assert np.all(np.abs(plain - ref) <= fp32_product_bound(X, X, W, h))
@@ -219,11 +249,12 @@ def test_symmetric_forms_agree_ragged(gpu_lib, sym_chunk, n, d):
     Xd = _t(X)
     ref = cmath.kmv(X, X, W, 0.8)
     bound = fp32_product_bound(X, X, W, 0.8)
+    anchored = fp32_sym_anchored_bound(X, W, 0.8, sym_rows_per_block(d))
     old = gpu_lib.get_tuning("symmetric")
     try:
-        for form in (1, 2):
+        for form in (1, 2, 3):
             gpu_lib.set_tuning("symmetric", form)
             got = gpu_lib.kernel_matvec(Xd, Xd, 0.8, _t(W), prec="f32").cpu().numpy()
-            assert np.all(np.abs(got - ref) <= bound), form
+            assert np.all(np.abs(got - ref) <= (anchored if form == 3 else bound)), form
     finally:
         gpu_lib.set_tuning("symmetric", old)
