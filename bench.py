@@ -32,6 +32,7 @@ sys.path.insert(0, ROOT)
 # MI355X published dense peaks (FLOP/s)
 PEAK = {"f16": 2.5e15, "bf16": 2.5e15, "f32": 157.3e12, "f64": 78.6e12}
 PEAK_FP64_VECTOR = 78.6e12
+PEAK_FP32_VECTOR = 157.3e12
 
 # HBM traffic per launch at n = 2^20, d = 8 (r = 256 for the sampler), from
 # two hardware-counter runs of `bench.py --kernels-only` (FETCH_SIZE, then
@@ -269,13 +270,26 @@ def main():
     # diagonal blocks in full): the executed share of the algorithmic work
     rb = 1024
     executed_entries = n * rb + (float(n) * n - n * rb) / 2
-    roof_mv = {"bound": "alu", "achieved": mv_flops / t_mv / 1e12, "peak": PEAK_FP64_VECTOR / 1e12,
-               "unit": "TFLOP/s", "frac": mv_flops / t_mv / PEAK_FP64_VECTOR,
+    f32_exp = krr.get_tuning("symmetric") == 3
+    mv_peak = PEAK_FP32_VECTOR if f32_exp else PEAK_FP64_VECTOR
+    mv_kernel = ("k_kmv_symf (refinement product K w over K's upper triangle: FP32 exponents on the matrix cores, "
+                 "re-centred per row block, FP32 entries; with its diagonal-block, anchor and reduction launches)"
+                 if f32_exp else
+                 "k_kmv_sym (refinement product K w over K's upper triangle, FP64 exponent, FP32 entries; "
+                 "with its diagonal-block and reduction launches)")
+    roof_mv = {"bound": "alu", "achieved": mv_flops / t_mv / 1e12, "peak": mv_peak / 1e12,
+               "unit": "TFLOP/s", "frac": mv_flops / t_mv / mv_peak,
                "traffic": pmc_traffic("kernel_product", n),
-               "kernel": "k_kmv_sym (refinement product K w over K's upper triangle, FP64 exponent, FP32 entries; "
-                         "with its diagonal-block and reduction launches)", "launch_s": t_mv,
+               "kernel": mv_kernel, "launch_s": t_mv,
                "algorithmic_flops": mv_flops, "entries_per_s": float(n) * n / t_mv,
-               "executed_frac": executed_entries * (2 * p.d + 2) / t_mv / PEAK_FP64_VECTOR}
+               "executed_frac": executed_entries * (2 * p.d + 2) / t_mv / mv_peak}
+    # the fitted coefficients' residual recomputed with the FP64 product
+    yp = krr.gather_rows(y.reshape(-1, 1).contiguous(), res.perm)
+    a64 = res.alpha_perm.reshape(-1, 1).contiguous()
+    r64 = yp - krr.kernel_matvec(Xp, Xp, p.h, a64, prec="f64") - p.lam * a64
+    relres_fp64 = float(torch.linalg.norm(r64) / torch.linalg.norm(yp))
+    del r64, yp, a64
+    log(f"FP64 relative residual of the fitted coefficients: {relres_fp64:.3e}")
     log(f"sampling {t_sample * 1e3:.1f} ms ({achieved / 1e12:.1f} TFLOP/s); "
         f"kernel product {t_mv * 1e3:.1f} ms ({mv_flops / t_mv / 1e12:.1f} TFLOP/s)")
     # the step's dominant kernel: the one whose phase takes longer
@@ -310,6 +324,7 @@ def main():
         "fp32": fp32,
         "sample_tflops": achieved / 1e12,
         "relres": rf["relres"][0],
+        "relres_fp64": relres_fp64,
         "refine_iterations": rf["iterations"],
         "accuracy": acc,
         "hss": {k: hs[k] for k in ("r_final", "regrowths", "max_rank", "levels", "bytes_paper",

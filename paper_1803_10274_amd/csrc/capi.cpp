@@ -15,7 +15,7 @@ namespace krr {
 
 thread_local std::string g_last_error;
 
-std::atomic<int> g_tune[KRR_TUNE_COUNT] = {{1}, {8}, {2048}, {16384}};
+std::atomic<int> g_tune[KRR_TUNE_COUNT] = {{3}, {8}, {2048}, {16384}};
 
 int tune_get(int knob) { return g_tune[knob].load(std::memory_order_relaxed); }
 

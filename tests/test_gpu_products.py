@@ -229,11 +229,12 @@ def test_symmetric_product_switch(gpu_lib):
     X = sd.points(n, d, seed=4)
     W = sd.vectors(n, 1, seed=5)
     Xd = _t(X)
+    old = gpu_lib.get_tuning("symmetric")
     gpu_lib.set_tuning("symmetric", 0)
     try:
         a = gpu_lib.kernel_matvec(Xd, Xd, h, _t(W), prec="f32").cpu().numpy()
     finally:
-        gpu_lib.set_tuning("symmetric", 1)
+        gpu_lib.set_tuning("symmetric", old)
     b = gpu_lib.kernel_matvec(Xd, Xd, h, _t(W), prec="f32").cpu().numpy()
     ref = cmath.kmv(X, X, W, h)
     bound = fp32_product_bound(X, X, W, h)
