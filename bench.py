@@ -41,14 +41,14 @@ PEAK_FP32_VECTOR = 157.3e12
 # WRITE_SIZE 1,048,576 KiB -> x1.000).  Valid only while the kernel's source
 # file is unchanged (sha256 below); otherwise the bench reports null.
 PMC_TRAFFIC = {
-    "sampling": {"fetch_kib": 35674219.0625, "write_kib": 1048576.0, "fetch_scale": 2.0, "write_scale": 1.0,
+    "sampling": {"fetch_kib": 35674229.0, "write_kib": 1048576.0, "fetch_scale": 2.0, "write_scale": 1.0,
                  "source": "paper_1803_10274_amd/csrc/sample_mfma.hip",
-                 "sha256": "cfc253f215a76348ca29ca680c2353d660e1eec1bb092fbdc27116f7fcd2bdc6", "n": 1 << 20, "r": 256},
-    # the symmetric product's five launches: column data, FP32 weights,
-    # diagonal blocks, upper triangle, reduction
-    "kernel_product": {"fetch_kib": 20179393.1875, "write_kib": 2819169.40625, "fetch_scale": 2.0, "write_scale": 1.0,
+                 "sha256": "096faa2ca9031e97e85d848ef1695fc78cd2bf9f2eab871d6a0087b6402f8ba4", "n": 1 << 20, "r": 256},
+    # the symmetric product's six launches: column data, FP32 weights,
+    # diagonal blocks, row-block anchors, upper triangle, reduction
+    "kernel_product": {"fetch_kib": 8367648.0, "write_kib": 2820756.9375, "fetch_scale": 2.0, "write_scale": 1.0,
                        "source": "paper_1803_10274_amd/csrc/matvec.hip",
-                       "sha256": "49507fab21e49192d1f803ee8cae9898d98a6ba82fe2d07b1fb527194102ce7e",
+                       "sha256": "f5887d3895138ea0f2030ba52b2248eb3bbc739b9f0291fda093f6a21ebe5453",
                        "n": 1 << 20, "r": None},
 }
 
