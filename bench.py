@@ -32,7 +32,8 @@ sys.path.insert(0, ROOT)
 # MI355X published dense peaks (FLOP/s)
 PEAK = {"f16": 2.5e15, "bf16": 2.5e15, "f32": 157.3e12, "f64": 78.6e12}
 PEAK_FP64_VECTOR = 78.6e12
-PEAK_FP32_VECTOR = 157.3e12
+# transcendental (v_exp_f32) issue at a quarter of the lane rate: 256 CUs x 64 lanes x 2.4 GHz / 4
+PEAK_EXP2 = 256 * 64 * 2.4e9 / 4
 
 # HBM traffic per launch at n = 2^20, d = 8 (r = 256 for the sampler), from
 # two hardware-counter runs of `bench.py --kernels-only` (FETCH_SIZE, then
@@ -270,19 +271,26 @@ def main():
     # diagonal blocks in full): the executed share of the algorithmic work
     rb = 1024
     executed_entries = n * rb + (float(n) * n - n * rb) / 2
-    f32_exp = krr.get_tuning("symmetric") == 3
-    mv_peak = PEAK_FP32_VECTOR if f32_exp else PEAK_FP64_VECTOR
-    mv_kernel = ("k_kmv_symf (refinement product K w over K's upper triangle: FP32 exponents on the matrix cores, "
-                 "re-centred per row block, FP32 entries; with its diagonal-block, anchor and reduction launches)"
-                 if f32_exp else
-                 "k_kmv_sym (refinement product K w over K's upper triangle, FP64 exponent, FP32 entries; "
-                 "with its diagonal-block and reduction launches)")
+    # the product's floor: one exp2 per entry of K (n^2 of them) at the
+    # quarter-rate transcendental peak, each entry carrying 2d + 2 flops
+    mv_peak = PEAK_EXP2 * (2 * p.d + 2)
+    form = krr.get_tuning("symmetric")
+    mv_kernel = {4: "k_kmv_symb (refinement product K w over K's upper triangle: FP32-accurate exponents from "
+                    "three-term BF16 splits on the matrix cores, re-centred per row block, FP32 entries; with its "
+                    "diagonal-block, anchor and reduction launches)",
+                 3: "k_kmv_symf (refinement product K w over K's upper triangle: FP32 exponents on the matrix "
+                    "cores, re-centred per row block, FP32 entries; with its diagonal-block, anchor and reduction "
+                    "launches)"}.get(form, "k_kmv_sym (refinement product K w over K's upper triangle, FP64 "
+                                           "exponent, FP32 entries; with its diagonal-block and reduction launches)")
     roof_mv = {"bound": "alu", "achieved": mv_flops / t_mv / 1e12, "peak": mv_peak / 1e12,
                "unit": "TFLOP/s", "frac": mv_flops / t_mv / mv_peak,
                "traffic": pmc_traffic("kernel_product", n),
                "kernel": mv_kernel, "launch_s": t_mv,
+               "peak_basis": "n^2 exp2 at 256 CU x 64 lanes x 2.4 GHz / 4 = 9.83e12 exp2/s, x (2d + 2) flops "
+                             "per entry",
                "algorithmic_flops": mv_flops, "entries_per_s": float(n) * n / t_mv,
-               "executed_frac": executed_entries * (2 * p.d + 2) / t_mv / mv_peak}
+               "exp2_floor_s": float(n) * n / PEAK_EXP2,
+               "evaluated_entries_frac": executed_entries / (float(n) * n)}
     # the fitted coefficients' residual recomputed with the FP64 product
     yp = krr.gather_rows(y.reshape(-1, 1).contiguous(), res.perm)
     a64 = res.alpha_perm.reshape(-1, 1).contiguous()

@@ -410,11 +410,13 @@ int krr_refine_batched(hss_ulv_t F, const void *Xp, int32_t xprec, const int64_t
  * Python package sets them from its cache).  Values are validated; results
  * do not depend on them beyond floating-point summation order. */
 enum {
-    KRR_TUNE_SYMMETRIC = 0,  /* K(X, X) W evaluates each off-diagonal entry once: 3 (default) with FP32
-                                exponents on the matrix cores, re-centred on each row block's mean point
-                                (FP32 points, one right-hand side; else as 2), 1 with FP64 exponents on
-                                the matrix cores (FP32 points, one right-hand side; else as 2), 2 with
-                                FP64 exponents on the vector ALUs, 0 off */
+    KRR_TUNE_SYMMETRIC = 0,  /* K(X, X) W evaluates each off-diagonal entry once (FP32 points, one
+                                right-hand side; otherwise the vector form 2). Exponent engine:
+                                4 (default) FP32-accurate exponents from three-term BF16 splits on the
+                                matrix cores, re-centred per row block (d <= 15; else as 3);
+                                3 FP32 exponents on the matrix cores, re-centred per row block;
+                                1 FP64 exponents on the matrix cores; 2 FP64 exponents on the vector
+                                ALUs; 0 off */
     KRR_TUNE_SAMPLE_RB = 1,  /* max 32-column blocks per sampling pass: 1, 2, 4 or 8 (default 8) */
     KRR_TUNE_MV_BLOCKS = 2,  /* workgroups the split-K kernel product aims for, 64..65536 (default 2048) */
     KRR_TUNE_SYM_CHUNK = 3,  /* columns per item of the symmetric product, multiple of 64 (default 16384) */

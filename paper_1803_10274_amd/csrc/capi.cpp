@@ -15,7 +15,7 @@ namespace krr {
 
 thread_local std::string g_last_error;
 
-std::atomic<int> g_tune[KRR_TUNE_COUNT] = {{3}, {8}, {2048}, {16384}};
+std::atomic<int> g_tune[KRR_TUNE_COUNT] = {{4}, {8}, {2048}, {16384}};
 
 int tune_get(int knob) { return g_tune[knob].load(std::memory_order_relaxed); }
 
@@ -502,7 +502,7 @@ int krr_set_tuning(int32_t knob, int32_t value) {
     return guard([&] {
         KRR_REQUIRE(knob >= 0 && knob < KRR_TUNE_COUNT, "krr_set_tuning: unknown knob %d", knob);
         switch (knob) {
-            case KRR_TUNE_SYMMETRIC: KRR_REQUIRE(value >= 0 && value <= 3, "krr_set_tuning: symmetric is 0, 1, 2 or 3"); break;
+            case KRR_TUNE_SYMMETRIC: KRR_REQUIRE(value >= 0 && value <= 4, "krr_set_tuning: symmetric is 0 to 4"); break;
             case KRR_TUNE_SAMPLE_RB:
                 KRR_REQUIRE(value == 1 || value == 2 || value == 4 || value == 8, "krr_set_tuning: sample RB is 1, 2, 4 or 8");
                 break;

@@ -706,6 +706,182 @@ __global__ __launch_bounds__(64 * SM_WAVES) void k_kmv_symf(const float *__restr
     }
 }
 
+// The same items with the exponent GEMM on the BF16 matrix cores: each FP32
+// operand (2 c y', x' and the column constant -c |y'|^2) is split into three
+// BF16 terms (hi + mid + lo, 24 bits, FP32's range), and the six cross
+// products down to 2^-16 (hh, hm, mh, hl, lh, mm) plus the column and row
+// constants' three terms against ones are packed along K (so the C operand
+// is zero and holds no registers): KT = 32 ceil((6 d + 6) / 32) slots,
+// KT / 32 v_mfma_f32_16x16x32_bf16 per 16 x 16 tile instead of d / 4
+// FP32 ones at a sixteenth of the rate.  Products of BF16 terms are exact in
+// FP32, so the exponent carries the FP32 form's accuracy.
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ void split3(float v, __bf16 &h, __bf16 &m, __bf16 &l) {
+    h = (__bf16)v;
+    const float r1 = v - (float)h;
+    m = (__bf16)r1;
+    l = (__bf16)(r1 - (float)m);
+}
+
+constexpr int symb_pn(int KT) { return KT <= 96 ? SM_PN : SM_PN / 2; }  // points per panel (LDS)
+constexpr int symb_rt(int KT) { return KT <= 64 ? 8 : 4; }  // row tiles per wave (registers)
+constexpr int symb_kt(int d) { return (6 * d + 6 + 31) / 32 * 32; }
+constexpr int symb_rows(int d) { return 16 * SM_WAVES * symb_rt(symb_kt(d)); }
+constexpr int symb_max_d = 15;  // KT <= 96
+
+template <int KT, int RT>
+__global__ __launch_bounds__(64 * SM_WAVES) void k_kmv_symb(const float *__restrict__ X, int d,
+                                                            const float *__restrict__ anchors,
+                                                            const float *__restrict__ wf, int64_t n,
+                                                            const SymItem *__restrict__ items,
+                                                            double *__restrict__ rowpart, float *__restrict__ colpart) {
+    constexpr int KS = KT / 32;  // MFMAs per tile
+    constexpr int LDB = KT + 8;  // staged point stride (BF16 elements; 16 bytes of padding)
+    constexpr int PN = symb_pn(KT);
+    constexpr int TH = 64 * SM_WAVES;
+    __shared__ __attribute__((aligned(16))) __bf16 ys[PN * LDB];
+    __shared__ float ws[PN];
+    __shared__ float csum[SM_WAVES][PN];
+    __shared__ float anc[32];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, g = lane >> 4, lr = lane & 15;
+    const SymItem it = items[blockIdx.x];
+    const float c = (float)it.c2;
+    if (tid < 32) anc[tid] = tid < d ? anchors[it.blk * d + tid] : 0.0f;
+    __syncthreads();
+    bf8v xb[RT][KS];
+    float wi[RT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+        const int64_t i = it.i0 + (int64_t)(wv * RT + rt) * 16 + lr;
+        const bool ok = i < it.iend;
+        float nrm = 0.0f;
+        if (ok)
+            for (int k = 0; k < d; ++k) {
+                const float v = X[i * d + k] - anc[k];
+                nrm = fmaf(v, v, nrm);
+            }
+        // this lane's K slots 32 s + 8 g + e of the packed row vector
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int slot = 32 * s + 8 * g + e;
+                float v = 0.0f;
+                int part = 0;  // 0: hi, 1: mid, 2: lo
+                if (ok) {
+                    if (slot < 6 * d) {
+                        const int t = slot / d, k = slot % d;
+                        // B side of (hh, hm, mh, hl, lh, mm)
+                        part = (t == 1 || t == 5) ? 1 : (t == 3 ? 2 : 0);
+                        v = X[i * d + k] - anc[k];
+                    } else if (slot < 6 * d + 3) {
+                        v = 1.0f;
+                    } else if (slot < 6 * d + 6) {
+                        part = slot - (6 * d + 3);
+                        v = -c * nrm;
+                    }
+                }
+                __bf16 h, m, l;
+                split3(v, h, m, l);
+                xb[rt][s][e] = part == 0 ? h : (part == 1 ? m : l);
+            }
+        wi[rt] = ok ? wf[i] : 0.0f;
+    }
+    double acc[RT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) acc[rt] = 0.0;
+    for (int64_t p0 = it.j0; p0 < it.j1; p0 += PN) {
+        const int cnt = (int)min((int64_t)PN, it.j1 - p0);
+        // stage the panel: packed BF16 terms of 2 c y' and of the column
+        // constant; points past the item get a constant of -1e30
+        if (tid < PN) {
+            __bf16 *dst = ys + tid * LDB;
+            float nrm = 0.0f;
+            const bool ok = tid < cnt;
+            const float *y = X + (ok ? p0 + tid : 0) * d;
+            for (int k = 0; k < d; ++k) {
+                const float v = ok ? y[k] - anc[k] : 0.0f;
+                nrm = fmaf(v, v, nrm);
+                __bf16 h, m, l;
+                split3((2.0f * c) * v, h, m, l);
+                // A side of (hh, hm, mh, hl, lh, mm)
+                dst[k] = h;
+                dst[d + k] = h;
+                dst[2 * d + k] = m;
+                dst[3 * d + k] = h;
+                dst[4 * d + k] = l;
+                dst[5 * d + k] = m;
+            }
+            __bf16 h, m, l;
+            split3(ok ? -c * nrm : -1e30f, h, m, l);
+            dst[6 * d] = h;
+            dst[6 * d + 1] = m;
+            dst[6 * d + 2] = l;
+            for (int k = 6 * d + 3; k < 6 * d + 6; ++k) dst[k] = (__bf16)1.0f;
+            for (int k = 6 * d + 6; k < KT; ++k) dst[k] = (__bf16)0.0f;
+            ws[tid] = ok ? wf[p0 + tid] : 0.0f;
+        }
+        __syncthreads();
+        float pacc[RT];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) pacc[rt] = 0.0f;
+#pragma unroll 1
+        for (int tl = 0; tl < PN / 16; ++tl) {
+            bf8v a[KS];
+#pragma unroll
+            for (int s = 0; s < KS; ++s) a[s] = *reinterpret_cast<const bf8v *>(ys + (tl * 16 + lr) * LDB + 32 * s + 8 * g);
+            float wp[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) wp[q] = ws[tl * 16 + symf_point(g, q)];
+            float cacc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) {
+                f4v t = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int s = 0; s < KS; ++s) t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[s], xb[rt][s], t, 0, 0, 0);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float e = __builtin_amdgcn_exp2f(t[q]);
+                    pacc[rt] = fmaf(e, wp[q], pacc[rt]);
+                    cacc[q] = fmaf(e, wi[rt], cacc[q]);
+                }
+            }
+#pragma unroll
+            for (int o = 8, h = 2; o >= 4; o >>= 1, h >>= 1) {
+                const bool up = (lane & o) != 0;
+#pragma unroll
+                for (int kk = 0; kk < h; ++kk) {
+                    const float lo = cacc[kk], hi = cacc[kk + h];
+                    const float send = up ? lo : hi;
+                    cacc[kk] = (up ? hi : lo) + __shfl_xor(send, o, 64);
+                }
+            }
+            float v = cacc[0];
+            v += __shfl_xor(v, 2, 64);
+            v += __shfl_xor(v, 1, 64);
+            if ((lane & 3) == 0) csum[wv][tl * 16 + symf_point(g, (lane >> 2) & 3)] = v;
+        }
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) acc[rt] += (double)pacc[rt];
+        __syncthreads();
+        if (tid < cnt) {
+            float cs = csum[0][tid];
+#pragma unroll
+            for (int w = 1; w < SM_WAVES; ++w) cs += csum[w][tid];
+            colpart[(int64_t)it.blk * n + p0 + tid] = cs;
+        }
+    }
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+        const int64_t i = it.i0 + (int64_t)(wv * RT + rt) * 16 + lr;
+        double v = acc[rt];
+        v += __shfl_xor(v, 16, 64);
+        v += __shfl_xor(v, 32, 64);
+        if (g == 0 && i < it.iend) rowpart[(int64_t)it.chunk * n + i] = v;
+    }
+}
+
 // anchors[b] = the mean point of row block b (FP64 sums, stored in FP32).
 __global__ void k_block_mean(const float *__restrict__ X, int d, const SymBlock *__restrict__ blocks,
                              float *__restrict__ anchors) {
@@ -986,6 +1162,39 @@ void launch_symf(dim3 gd, dim3 gs, dim3 gr, int rows_pb, const float *X, int d, 
     check_launch("k_sym_reduce");
 }
 
+// BF16 three-term exponents: K slots for d and the kernel's row tiles.
+template <int KT, int RT>
+void launch_symb_kernel(dim3 gs, const float *X, int d, const float *anchors, const float *wf, int64_t n,
+                        const SymItem *it, double *rowpart, float *colpart, hipStream_t s) {
+    k_kmv_symb<KT, RT><<<gs, 64 * SM_WAVES, 0, s>>>(X, d, anchors, wf, n, it, rowpart, colpart);
+}
+
+template <int D>
+void launch_symb(dim3 gd, dim3 gs, dim3 gr, int rows_pb, const float *X, int d, double c2, const double *ya,
+                 const float *wf, int64_t n, const SampBlock *dt, const SymItem *it, const SymBlock *bl,
+                 int64_t nblocks, double *diag, double *rowpart, float *colpart, double beta, double *Out,
+                 hipStream_t s) {
+    k_kmv_sc<float, D, 1, sc_rpt(D)><<<gd, MV_ROWS, 0, s>>>(X, n, d, c2, ya, wf, 1, 0, n, 0, diag, dt);
+    check_launch("k_kmv_sc (diagonal blocks)");
+    if (gs.x > 0) {
+        DBuf anchors = dalloc<float>((size_t)nblocks * d);
+        k_block_mean<<<(unsigned)nblocks, 256, 0, s>>>(X, d, bl, anchors.as<float>());
+        check_launch("k_block_mean");
+        const int kt = (6 * d + 6 + 31) / 32 * 32;
+        const float *an = anchors.as<float>();
+        switch (kt) {  // row tiles per wave: symb_rt
+            case 32: launch_symb_kernel<32, symb_rt(32)>(gs, X, d, an, wf, n, it, rowpart, colpart, s); break;
+            case 64: launch_symb_kernel<64, symb_rt(64)>(gs, X, d, an, wf, n, it, rowpart, colpart, s); break;
+            case 96: launch_symb_kernel<96, symb_rt(96)>(gs, X, d, an, wf, n, it, rowpart, colpart, s); break;
+            default: fail(KRR_E_INVAL, "kernel_matvec: no BF16 symmetric variant for width %d", d);
+        }
+        check_launch("k_kmv_symb");
+        sync(s);  // the anchors are released on return
+    }
+    k_sym_reduce<1><<<gr, 256, 0, s>>>(bl, rows_pb, diag, rowpart, colpart, n, beta, Out);
+    check_launch("k_sym_reduce");
+}
+
 // The symmetric product y = K(X, X) W + beta y (FP32 entries) when it
 // applies (d <= 32, one or two right-hand sides, partial sums within budget);
 // returns false otherwise.  FP32 points with one right-hand side take the
@@ -997,9 +1206,11 @@ bool kmv_sym(const T *X, int64_t n, int d, double h, const double *W, int nrhs, 
     const int D = sc_width(d);
     if (D > 32 || (nrhs != 1 && nrhs != 2)) return false;
     const bool mc = sizeof(T) == 4 && nrhs == 1 && tune_get(KRR_TUNE_SYMMETRIC) == 1;
-    const bool mf = sizeof(T) == 4 && nrhs == 1 && tune_get(KRR_TUNE_SYMMETRIC) == 3;
+    const int form = tune_get(KRR_TUNE_SYMMETRIC);
+    const bool mb = sizeof(T) == 4 && nrhs == 1 && form == 4 && d <= symb_max_d;
+    const bool mf = sizeof(T) == 4 && nrhs == 1 && (form == 3 || (form == 4 && d > symb_max_d));
     const int diag_rows = MV_ROWS * sc_rpt(D);  // rows of one k_kmv_sc workgroup
-    const int rows_pb = (mc || mf) ? symm_rows(D) : diag_rows;
+    const int rows_pb = mb ? symb_rows(d) : ((mc || mf) ? symm_rows(D) : diag_rows);
     const int64_t CH = tune_get(KRR_TUNE_SYM_CHUNK);  // columns per item: a multiple of the tile width
     std::vector<int64_t> pb = batch ? batch->pbeg : std::vector<int64_t>{0, n};
     std::vector<double> hs = batch ? batch->h : std::vector<double>{h};
@@ -1063,6 +1274,12 @@ bool kmv_sym(const T *X, int64_t n, int d, double h, const double *W, int nrhs, 
             launch_symm<DD>(gd, gs, gr, rows_pb, X, d, c2, ya.as<double>(), wf.as<float>(), n,                 \
                                  dt.as<SampBlock>(), it.as<SymItem>(), bl.as<SymBlock>(), dd.as<double>(),      \
                                  rp.as<double>(), cpart.as<float>(), beta, Out, s);                             \
+            break;                                                                                              \
+        }                                                                                                       \
+        if (mb) {                                                                                               \
+            launch_symb<DD>(gd, gs, gr, rows_pb, X, d, c2, ya.as<double>(), wf.as<float>(), n,                 \
+                            dt.as<SampBlock>(), it.as<SymItem>(), bl.as<SymBlock>(), (int64_t)blocks.size(),    \
+                            dd.as<double>(), rp.as<double>(), cpart.as<float>(), beta, Out, s);                 \
             break;                                                                                              \
         }                                                                                                       \
         if (mf) {                                                                                               \

@@ -69,21 +69,27 @@ def fp64_wide_product_bound(X, Y, W, h, safety=4.0, anchor=None):
     return safety * U64 * ((Y.shape[0] + 4) * (K @ aW) + (K * T) @ aW)
 
 
-def sym_rows_per_block(d):
-    """Row block of the matrix-core symmetric product: 1024 rows for padded
-    widths up to 8, else 512."""
+def sym_rows_per_block(d, form=3):
+    """Row block of the matrix-core symmetric product: form 3 (FP32
+    exponents) 1024 rows for padded widths up to 8, else 512; form 4 (BF16
+    three-term exponents, d <= 15) 1024 rows while 6 d + 6 <= 64, else 512."""
+    if form == 4 and d <= 15:
+        return 1024 if 6 * d + 6 <= 64 else 512
     D = (d + 3) // 4 * 4 if d <= 24 else 32
     return 1024 if D <= 8 else 512
 
 
-def fp32_sym_anchored_bound(X, W, h, rows_per_block, tile=64, safety=4.0):
+def fp32_sym_anchored_bound(X, W, h, rows_per_block, tile=64, safety=4.0, form=3):
     """Bound for the symmetric FP32 kernel product with FP32 exponents
     re-centred per row block: an entry between rows of different blocks is
     evaluated once, by the earlier block, on x' = x - a, y' = y - a with a that
     block's mean point; its FP32 norm expansion (d FMAs per norm, d + 2 terms
     in the matrix-core sum, two constants) is off by at most
-    (2 d + 6) u (|x'| + |y'|)^2 / (2 h^2) in natural-log units.  Entries inside
-    a diagonal block use the FP64 exponent (fp32_product_bound's terms)."""
+    (2 d + 6) u (|x'| + |y'|)^2 / (2 h^2) in natural-log units.  The BF16
+    three-term form (4) adds the split's representation error (2^-24 per
+    operand) and the dropped cross terms below 2^-16 (2^-23 per product):
+    3 d more units.  Entries inside a diagonal block use the FP64 exponent
+    (fp32_product_bound's terms)."""
     X = np.asarray(X, dtype=np.float64)
     n, d = X.shape
     blk = np.arange(n) // rows_per_block
@@ -99,7 +105,8 @@ def fp32_sym_anchored_bound(X, W, h, rows_per_block, tile=64, safety=4.0):
     T = q / (2 * h * h)
     K = np.exp(-T)
     aW = np.abs(np.asarray(W, dtype=np.float64)).reshape(W.shape[0], -1)
-    return safety * U32 * ((tile + 2) * (K @ aW) + (d + 3) * ((K * T) @ aW) + (2 * d + 6) * ((K * S) @ aW))
+    terms = 2 * d + 6 + (3 * d + 2 if form == 4 else 0)
+    return safety * U32 * ((tile + 2) * (K @ aW) + (d + 3) * ((K * T) @ aW) + terms * ((K * S) @ aW))
 
 
 def leaf_ranges(nodes, n):

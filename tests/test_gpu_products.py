@@ -188,10 +188,11 @@ def sym_chunk(gpu_lib):
     gpu_lib.set_tuning("sym_chunk", old)
 
 
-@pytest.fixture(params=[1, 2, 3], ids=["matrix_core_f64", "vector", "matrix_core_f32"])
+@pytest.fixture(params=[1, 2, 3, 4], ids=["matrix_core_f64", "vector", "matrix_core_f32", "matrix_core_bf16x3"])
 def sym_form(gpu_lib, request):
     """The symmetric product's exponents: FP64 on the matrix cores (1), FP64 on
-    the vector ALUs (2), FP32 on the matrix cores re-centred per row block (3)."""
+    the vector ALUs (2), FP32 on the matrix cores re-centred per row block (3),
+    BF16 three-term splits of the same on the matrix cores (4)."""
     old = gpu_lib.get_tuning("symmetric")
     gpu_lib.set_tuning("symmetric", request.param)
     yield request.param
@@ -210,8 +211,8 @@ def test_symmetric_product(gpu_lib, sym_chunk, sym_form, d, nrhs):
     Xd = _t(X)
     out = gpu_lib.kernel_matvec(Xd, Xd, h, _t(W), prec="f32").cpu().numpy().reshape(n, nrhs)
     ref = cmath.kmv(X, X, W, h)
-    if sym_form == 3 and nrhs == 1:
-        sym_bound = fp32_sym_anchored_bound(X, W, h, sym_rows_per_block(d))
+    if sym_form in (3, 4) and nrhs == 1:
+        sym_bound = fp32_sym_anchored_bound(X, W, h, sym_rows_per_block(d, sym_form), form=sym_form)
     else:
         sym_bound = fp32_product_bound(X, X, W, h)
     assert np.all(np.abs(out - ref) <= sym_bound)
@@ -241,7 +242,8 @@ def test_symmetric_product_switch(gpu_lib):
     assert np.all(np.abs(a - ref) <= bound) and np.all(np.abs(b - ref) <= bound)
 
 
-@pytest.mark.parametrize("n,d", [(1, 8), (15, 8), (1023, 8), (1025, 8), (2049, 5), (3000, 20)])
+@pytest.mark.parametrize("n,d", [(1, 8), (15, 8), (511, 8), (513, 3), (1023, 8), (1025, 8), (2049, 5), (3000, 20),
+                                 (1500, 15)])
 def test_symmetric_forms_agree_ragged(gpu_lib, sym_chunk, n, d):
     # sizes around the row blocks (1024 rows at d <= 8, 512 above) and the
     # 256-point panels: both symmetric forms against the oracle
@@ -250,12 +252,13 @@ def test_symmetric_forms_agree_ragged(gpu_lib, sym_chunk, n, d):
     Xd = _t(X)
     ref = cmath.kmv(X, X, W, 0.8)
     bound = fp32_product_bound(X, X, W, 0.8)
-    anchored = fp32_sym_anchored_bound(X, W, 0.8, sym_rows_per_block(d))
     old = gpu_lib.get_tuning("symmetric")
     try:
-        for form in (1, 2, 3):
+        for form in (1, 2, 3, 4):
             gpu_lib.set_tuning("symmetric", form)
             got = gpu_lib.kernel_matvec(Xd, Xd, 0.8, _t(W), prec="f32").cpu().numpy()
-            assert np.all(np.abs(got - ref) <= (anchored if form == 3 else bound)), form
+            if form >= 3:
+                bound = fp32_sym_anchored_bound(X, W, 0.8, sym_rows_per_block(d, form), form=form)
+            assert np.all(np.abs(got - ref) <= bound), form
     finally:
         gpu_lib.set_tuning("symmetric", old)
