@@ -725,10 +725,10 @@ __device__ __forceinline__ void split3(float v, __bf16 &h, __bf16 &m, __bf16 &l)
 }
 
 constexpr int symb_pn(int KT) { return KT <= 96 ? SM_PN : SM_PN / 2; }  // points per panel (LDS)
-constexpr int symb_rt(int KT) { return KT <= 64 ? 8 : 4; }  // row tiles per wave (registers)
+constexpr int symb_rt(int KT) { return KT <= 64 ? 8 : (KT <= 128 ? 4 : 2); }  // row tiles per wave (registers)
 constexpr int symb_kt(int d) { return (6 * d + 6 + 31) / 32 * 32; }
 constexpr int symb_rows(int d) { return 16 * SM_WAVES * symb_rt(symb_kt(d)); }
-constexpr int symb_max_d = 15;  // KT <= 96
+constexpr int symb_max_d = 31;  // KT <= 192
 
 template <int KT, int RT>
 __global__ __launch_bounds__(64 * SM_WAVES) void k_kmv_symb(const float *__restrict__ X, int d,
@@ -1186,6 +1186,9 @@ void launch_symb(dim3 gd, dim3 gs, dim3 gr, int rows_pb, const float *X, int d, 
             case 32: launch_symb_kernel<32, symb_rt(32)>(gs, X, d, an, wf, n, it, rowpart, colpart, s); break;
             case 64: launch_symb_kernel<64, symb_rt(64)>(gs, X, d, an, wf, n, it, rowpart, colpart, s); break;
             case 96: launch_symb_kernel<96, symb_rt(96)>(gs, X, d, an, wf, n, it, rowpart, colpart, s); break;
+            case 128: launch_symb_kernel<128, symb_rt(128)>(gs, X, d, an, wf, n, it, rowpart, colpart, s); break;
+            case 160: launch_symb_kernel<160, symb_rt(160)>(gs, X, d, an, wf, n, it, rowpart, colpart, s); break;
+            case 192: launch_symb_kernel<192, symb_rt(192)>(gs, X, d, an, wf, n, it, rowpart, colpart, s); break;
             default: fail(KRR_E_INVAL, "kernel_matvec: no BF16 symmetric variant for width %d", d);
         }
         check_launch("k_kmv_symb");

@@ -72,9 +72,11 @@ def fp64_wide_product_bound(X, Y, W, h, safety=4.0, anchor=None):
 def sym_rows_per_block(d, form=3):
     """Row block of the matrix-core symmetric product: form 3 (FP32
     exponents) 1024 rows for padded widths up to 8, else 512; form 4 (BF16
-    three-term exponents, d <= 15) 1024 rows while 6 d + 6 <= 64, else 512."""
-    if form == 4 and d <= 15:
-        return 1024 if 6 * d + 6 <= 64 else 512
+    three-term exponents, d <= 31) 1024 rows while the packed K (6 d + 6
+    rounded up to 32) is at most 64, 512 up to 128, else 256."""
+    if form == 4 and d <= 31:
+        kt = (6 * d + 6 + 31) // 32 * 32
+        return 1024 if kt <= 64 else (512 if kt <= 128 else 256)
     D = (d + 3) // 4 * 4 if d <= 24 else 32
     return 1024 if D <= 8 else 512
 
