@@ -47,9 +47,9 @@ PMC_TRAFFIC = {
                  "sha256": "096faa2ca9031e97e85d848ef1695fc78cd2bf9f2eab871d6a0087b6402f8ba4", "n": 1 << 20, "r": 256},
     # the symmetric product's six launches: column data, FP32 weights,
     # diagonal blocks, row-block anchors, upper triangle, reduction
-    "kernel_product": {"fetch_kib": 8367648.0, "write_kib": 2820756.9375, "fetch_scale": 2.0, "write_scale": 1.0,
+    "kernel_product": {"fetch_kib": 10251055.3125, "write_kib": 6406022.75, "fetch_scale": 2.0, "write_scale": 1.0,
                        "source": "paper_1803_10274_amd/csrc/matvec.hip",
-                       "sha256": "f5887d3895138ea0f2030ba52b2248eb3bbc739b9f0291fda093f6a21ebe5453",
+                       "sha256": "3923b472b66660dfeabcc35a5767f03f8a086ddc8bef3bbc67ab474ab920e2ea",
                        "n": 1 << 20, "r": None},
 }
 
