@@ -106,12 +106,13 @@ struct hss_ulv_s {
     std::vector<krr::HNode> node;       // copy of the HSS node table
     std::vector<std::vector<int>> levels;
     // Per node: Householder vectors of U's QR (m x k, column j = reflector j),
-    // tau (k), Cholesky factor L of the eliminated block ((m-k)^2), and
-    // W = A_ce L^{-T} (k x (m-k)).  The root holds the Cholesky factor of its
-    // whole reduced block in L.
-    std::vector<int64_t> offV, offT, offL, offW;
-    krr::DBuf V, T, L, W;
-    int64_t nV = 0, nT = 0, nL = 0, nW = 0;
+    // tau (k), the compact WY factor Y of Q = I - V Y V^T (k x k, upper
+    // triangular), the inverse L^{-1} of the eliminated block's Cholesky factor
+    // ((m-k)^2, lower triangular), and W = A_ce L^{-T} (k x (m-k)).  The root
+    // holds the inverse Cholesky factor of its whole reduced block in L.
+    std::vector<int64_t> offV, offT, offL, offW, offY;
+    krr::DBuf V, T, L, W, Y;
+    int64_t nV = 0, nT = 0, nL = 0, nW = 0, nY = 0;
 };
 
 // ------------------------------------------------ entry points across units

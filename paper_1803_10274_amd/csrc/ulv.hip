@@ -9,7 +9,9 @@
 // 2. Dw <- Q^T Dw Q;  the last m - k rows no longer couple to the rest of the
 //    matrix, so with Dw = [[A_cc, A_ce], [A_ec, A_ee]]:
 // 3. A_ee = L L^T (Cholesky), W = A_ce L^{-T}, S = A_cc - W W^T (passed up);
-// the root factors its whole Dw.  Solve: forward sweep b <- Q^T b,
+// the root factors its whole Dw.  The factor keeps Q in compact WY form
+// (Q = I - V T V^T) and L^{-1} explicitly, so that every step of the solve
+// is a parallel matrix-vector product.  Solve: forward sweep b <- Q^T b,
 // z = L^{-1} b_e, c = b_c - W z passed up; root solve; backward sweep
 // x_e = L^{-T} (z - W^T x_c), x = Q [x_c; x_e].
 #include <algorithm>
@@ -29,8 +31,8 @@ struct UlvDesc {
     const double *D, *U, *B;           // HSS generators
     const double *S_l, *S_r, *Rh_l, *Rh_r;
     double *Dw, *Uw, *Tmp;             // scratch
-    double *Yw, *Zw, *Tw;              // scratch of the blocked transform: k x m, k x m, k x k
-    double *V, *tau, *L, *W;           // factor
+    double *Yw, *Zw;                   // scratch of the blocked transform: k x m, k x m
+    double *V, *tau, *Tw, *L, *W;      // factor (Tw: the WY T, k x k; L: the inverse Cholesky factor)
     double *S_out, *Rh_out;            // passed to the parent
 };
 
@@ -196,22 +198,21 @@ __global__ __launch_bounds__(BG_T) void k_ulv_factor(const UlvDesc *dsc, int32_t
         if (tid == 0) atomicOr(flag, 1);
         return;
     }
-    for (int t = tid; t < ne * ne; t += BG_T) {
-        int i = t / ne, c = t % ne;
-        q.L[t] = (c <= i) ? Dw[(int64_t)(k + i) * m + k + c] : 0.0;
+    // L^{-1} (lower triangular, zeros stored above the diagonal): column c by
+    // forward substitution on the unit vector e_c, one thread per column
+    for (int c = tid; c < ne; c += BG_T) {
+        for (int i = 0; i < c; ++i) q.L[(int64_t)i * ne + c] = 0.0;
+        for (int i = c; i < ne; ++i) {
+            const double *Li = Dw + (int64_t)(k + i) * m + k;
+            double t = (i == c) ? 1.0 : 0.0;
+            for (int l = c; l < i; ++l) t -= Li[l] * q.L[(int64_t)l * ne + c];
+            q.L[(int64_t)i * ne + c] = t / Li[i];
+        }
     }
     if (q.root) return;
     __syncthreads();
-    // W = A_ce L^{-T}: row i of W solves L w = A_ce[i, :]^T
-    for (int i = tid; i < k; i += BG_T) {
-        double *w = q.W + (int64_t)i * ne;
-        const double *a = Dw + (int64_t)i * m + k;
-        for (int c = 0; c < ne; ++c) {
-            double t = a[c];
-            for (int l = 0; l < c; ++l) t -= q.L[(int64_t)c * ne + l] * w[l];
-            w[c] = t / q.L[(int64_t)c * ne + c];
-        }
-    }
+    // W = A_ce L^{-T}
+    block_gemm(k, ne, ne, 1.0, Dw + k, m, 1, q.L, 1, ne, 0.0, q.W, ne, smem);
     __syncthreads();
     // S = A_cc - W W^T
     block_gemm(k, k, ne, -1.0, q.W, ne, 1, q.W, 1, ne, 1.0, Dw, m, smem);
@@ -224,62 +225,51 @@ __global__ __launch_bounds__(BG_T) void k_ulv_factor(const UlvDesc *dsc, int32_t
 struct SolveDesc {
     int32_t m, k, leaf, root;
     int64_t b;
-    const double *V, *tau, *L, *W;
+    const double *V, *T, *Li, *W;  // Q = I - V T V^T; Li = L^{-1}
     double *bw;              // m x nrhs: rhs on the way up, solution on the way down
     double *z;               // (m - k) x nrhs
     double *c_out;           // k x nrhs (passed up)
+    double *y1, *y2;         // k x nrhs scratch of the WY products
     const double *c_l, *c_r; // children's reduced rhs
     int32_t kl, kr;
     const double *x_par;     // parent's solution rows for this node (k x nrhs), set for the backward sweep
 };
 
-// Apply H_j = I - tau v v^T to columns of bw (m x nrhs), one wave per column.
-__device__ void apply_reflector(const double *v, int ldv, double tau, int j, int m, double *bw, int nrhs) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int c = wv; c < nrhs; c += BG_T / 64) {
-        double w = 0.0;
-        for (int i = j + lane; i < m; i += 64) w += v[(int64_t)i * ldv] * bw[(int64_t)i * nrhs + c];
-        w = wave_sum(w) * tau;
-        for (int i = j + lane; i < m; i += 64) bw[(int64_t)i * nrhs + c] -= w * v[(int64_t)i * ldv];
+// bw (m x nrhs) <- (I - V op(T) V^T) bw with op(T) = T^T (Q^T, `trans`) or T
+// (Q).  V (m x k) holds unit lower-trapezoidal reflectors (zeros above the
+// diagonal, ones on it); each product is spread over the workgroup's threads.
+__device__ void apply_wy(const double *__restrict__ V, const double *__restrict__ T, int m, int k, double *bw,
+                         int nrhs, double *y1, double *y2, bool trans) {
+    const int tid = threadIdx.x;
+    for (int t = tid; t < k * nrhs; t += BG_T) {  // y1 = V^T bw
+        const int j = t / nrhs, c = t % nrhs;
+        double acc = 0.0;
+        for (int i = j; i < m; ++i) acc += V[(int64_t)i * k + j] * bw[(int64_t)i * nrhs + c];
+        y1[t] = acc;
     }
-}
-
-// Triangular solve with the lower factor L (n x n): L y = y, or L^T y = y
-// when `trans`, in place on the n x nrhs block y (leading dimension ldy).
-// One wave per right-hand side; the column is staged in the wave's LDS slice
-// (lds: BG_T / 64 slices of nmax doubles) so every lane sees the entries lane
-// 0 has just solved for.
-__device__ void tri_solve(const double *L, int n, double *y, int nrhs, int ldy, bool trans, double *lds, int nmax) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    double *v = lds + wv * nmax;
-    for (int c = wv; c < nrhs; c += BG_T / 64) {
-        for (int i = lane; i < n; i += 64) v[i] = y[(int64_t)i * ldy + c];
-        __threadfence_block();
-        if (!trans) {
-            for (int i = 0; i < n; ++i) {
-                double t = 0.0;
-                for (int l = lane; l < i; l += 64) t += L[(int64_t)i * n + l] * v[l];
-                t = wave_sum(t);
-                if (lane == 0) v[i] = (v[i] - t) / L[(int64_t)i * n + i];
-                __threadfence_block();
-            }
-        } else {
-            for (int i = n - 1; i >= 0; --i) {
-                double t = 0.0;
-                for (int l = i + 1 + lane; l < n; l += 64) t += L[(int64_t)l * n + i] * v[l];
-                t = wave_sum(t);
-                if (lane == 0) v[i] = (v[i] - t) / L[(int64_t)i * n + i];
-                __threadfence_block();
-            }
-        }
-        for (int i = lane; i < n; i += 64) y[(int64_t)i * ldy + c] = v[i];
-        __threadfence_block();
+    __syncthreads();
+    for (int t = tid; t < k * nrhs; t += BG_T) {  // y2 = op(T) y1, T upper triangular
+        const int j = t / nrhs, c = t % nrhs;
+        double acc = 0.0;
+        if (trans)
+            for (int l = 0; l <= j; ++l) acc += T[(int64_t)l * k + j] * y1[(int64_t)l * nrhs + c];
+        else
+            for (int l = j; l < k; ++l) acc += T[(int64_t)j * k + l] * y1[(int64_t)l * nrhs + c];
+        y2[t] = acc;
     }
+    __syncthreads();
+    for (int t = tid; t < m * nrhs; t += BG_T) {  // bw -= V y2
+        const int i = t / nrhs, c = t % nrhs;
+        const int jm = min(i + 1, k);
+        double acc = 0.0;
+        for (int j = 0; j < jm; ++j) acc += V[(int64_t)i * k + j] * y2[(int64_t)j * nrhs + c];
+        bw[t] -= acc;
+    }
+    __syncthreads();
 }
 
 __global__ __launch_bounds__(BG_T) void k_ulv_fwd(const SolveDesc *dsc, const double *__restrict__ Bin, int nrhs,
-                                                  int nmax, double *__restrict__ Xout) {
-    extern __shared__ double lds[];
+                                                  double *__restrict__ Xout) {
     const SolveDesc q = dsc[blockIdx.x];
     const int m = q.m, k = q.k, ne = m - k, tid = threadIdx.x;
     if (q.leaf) {
@@ -289,54 +279,58 @@ __global__ __launch_bounds__(BG_T) void k_ulv_fwd(const SolveDesc *dsc, const do
         for (int64_t t = tid; t < (int64_t)q.kr * nrhs; t += BG_T) q.bw[(int64_t)q.kl * nrhs + t] = q.c_r[t];
     }
     __syncthreads();
-    for (int j = 0; j < k; ++j) {
-        apply_reflector(q.V + j, k, q.tau[j], j, m, q.bw, nrhs);
-        __syncthreads();
-    }
+    if (k > 0) apply_wy(q.V, q.T, m, k, q.bw, nrhs, q.y1, q.y2, true);
     // z = L^{-1} b_e
-    for (int64_t t = tid; t < (int64_t)ne * nrhs; t += BG_T) q.z[t] = q.bw[(int64_t)k * nrhs + t];
-    __syncthreads();
-    tri_solve(q.L, ne, q.z, nrhs, nrhs, false, lds, nmax);
+    for (int t = tid; t < ne * nrhs; t += BG_T) {
+        const int i = t / nrhs, c = t % nrhs;
+        const double *li = q.Li + (int64_t)i * ne;
+        double acc = 0.0;
+        for (int l = 0; l <= i; ++l) acc += li[l] * q.bw[(int64_t)(k + l) * nrhs + c];
+        q.z[t] = acc;
+    }
     __syncthreads();
     if (q.root) {
-        // whole solve at the root: x = L^{-T} z
-        tri_solve(q.L, ne, q.z, nrhs, nrhs, true, lds, nmax);
-        __syncthreads();
-        for (int64_t t = tid; t < (int64_t)m * nrhs; t += BG_T) q.bw[t] = q.z[t];
-        // a one-node tree (the root is a leaf) has no backward sweep
-        if (q.leaf)
-            for (int64_t t = tid; t < (int64_t)m * nrhs; t += BG_T) Xout[q.b * nrhs + t] = q.z[t];
+        // whole solve at the root (k = 0): x = L^{-T} z
+        for (int t = tid; t < m * nrhs; t += BG_T) {
+            const int i = t / nrhs, c = t % nrhs;
+            double acc = 0.0;
+            for (int l = i; l < m; ++l) acc += q.Li[(int64_t)l * m + i] * q.z[(int64_t)l * nrhs + c];
+            q.bw[t] = acc;
+            // a one-node tree (the root is a leaf) has no backward sweep
+            if (q.leaf) Xout[q.b * nrhs + t] = acc;
+        }
         return;
     }
     // c = b_c - W z
     for (int64_t t = tid; t < (int64_t)k * nrhs; t += BG_T) {
         int i = (int)(t / nrhs), c = (int)(t % nrhs);
-        double s = q.bw[(int64_t)i * nrhs + c];
-        for (int l = 0; l < ne; ++l) s -= q.W[(int64_t)i * ne + l] * q.z[(int64_t)l * nrhs + c];
-        q.c_out[t] = s;
+        double acc = q.bw[(int64_t)i * nrhs + c];
+        for (int l = 0; l < ne; ++l) acc -= q.W[(int64_t)i * ne + l] * q.z[(int64_t)l * nrhs + c];
+        q.c_out[t] = acc;
     }
 }
 
-__global__ __launch_bounds__(BG_T) void k_ulv_bwd(const SolveDesc *dsc, double *__restrict__ Xout, int nrhs,
-                                                  int nmax) {
-    extern __shared__ double lds[];
+__global__ __launch_bounds__(BG_T) void k_ulv_bwd(const SolveDesc *dsc, double *__restrict__ Xout, int nrhs) {
     const SolveDesc q = dsc[blockIdx.x];
     const int m = q.m, k = q.k, ne = m - k, tid = threadIdx.x;
-    // x_c from the parent; x_e = L^{-T} (z - W^T x_c)
+    // x_c from the parent; z <- z - W^T x_c (each thread its own entries)
     for (int64_t t = tid; t < (int64_t)k * nrhs; t += BG_T) q.bw[t] = q.x_par[t];
     for (int64_t t = tid; t < (int64_t)ne * nrhs; t += BG_T) {
         int l = (int)(t / nrhs), c = (int)(t % nrhs);
-        double s = q.z[t];
-        for (int i = 0; i < k; ++i) s -= q.W[(int64_t)i * ne + l] * q.x_par[(int64_t)i * nrhs + c];
-        q.bw[(int64_t)k * nrhs + t] = s;
+        double acc = q.z[t];
+        for (int i = 0; i < k; ++i) acc -= q.W[(int64_t)i * ne + l] * q.x_par[(int64_t)i * nrhs + c];
+        q.z[t] = acc;
     }
     __syncthreads();
-    tri_solve(q.L, ne, q.bw + (int64_t)k * nrhs, nrhs, nrhs, true, lds, nmax);
-    __syncthreads();
-    for (int j = k - 1; j >= 0; --j) {
-        apply_reflector(q.V + j, k, q.tau[j], j, m, q.bw, nrhs);
-        __syncthreads();
+    // x_e = L^{-T} z
+    for (int t = tid; t < ne * nrhs; t += BG_T) {
+        const int i = t / nrhs, c = t % nrhs;
+        double acc = 0.0;
+        for (int l = i; l < ne; ++l) acc += q.Li[(int64_t)l * ne + i] * q.z[(int64_t)l * nrhs + c];
+        q.bw[(int64_t)(k + i) * nrhs + c] = acc;
     }
+    __syncthreads();
+    if (k > 0) apply_wy(q.V, q.T, m, k, q.bw, nrhs, q.y1, q.y2, false);
     if (q.leaf)
         for (int64_t t = tid; t < (int64_t)m * nrhs; t += BG_T) Xout[q.b * nrhs + t] = q.bw[t];
 }
@@ -364,6 +358,7 @@ int64_t ulv_factor(const hss_s *H, const std::vector<double> &lam, const std::ve
         F->offT.assign(nn, 0);
         F->offL.assign(nn, 0);
         F->offW.assign(nn, 0);
+        F->offY.assign(nn, 0);
     }
     // per-node sizes: m (rows of the reduced block) and k
     std::vector<int> m(nn), k(nn);
@@ -375,19 +370,21 @@ int64_t ulv_factor(const hss_s *H, const std::vector<double> &lam, const std::ve
         F->node[i].k = k[i];
     }
     if (!reuse) {
-        int64_t nv = 0, nt = 0, nl = 0, nw = 0;
+        int64_t nv = 0, nt = 0, nl = 0, nw = 0, ny = 0;
         for (int i = 0; i < nn; ++i) {
             int ne = m[i] - k[i];
             F->offV[i] = nv; nv += (int64_t)m[i] * k[i];
             F->offT[i] = nt; nt += k[i];
             F->offL[i] = nl; nl += (int64_t)ne * ne;
             F->offW[i] = nw; nw += (int64_t)k[i] * ne;
+            F->offY[i] = ny; ny += (int64_t)k[i] * k[i];
     }
     F->V.alloc(8 * std::max<int64_t>(nv, 1));
     F->T.alloc(8 * std::max<int64_t>(nt, 1));
     F->L.alloc(8 * std::max<int64_t>(nl, 1));
     F->W.alloc(8 * std::max<int64_t>(nw, 1));
-    F->nV = nv; F->nT = nt; F->nL = nl; F->nW = nw;
+    F->Y.alloc(8 * std::max<int64_t>(ny, 1));
+    F->nV = nv; F->nT = nt; F->nL = nl; F->nW = nw; F->nY = ny;
     }
     std::vector<uint8_t> act(np, 1);
     if (active) act = *active;
@@ -410,20 +407,19 @@ int64_t ulv_factor(const hss_s *H, const std::vector<double> &lam, const std::ve
             if (act[H->nprob[id]]) lv.push_back(id);
         if (lv.empty()) continue;
         const int cnt = (int)lv.size();
-        int64_t dsz = 0, usz = 0, tsz = 0, ysz = 0, wsz = 0;
+        int64_t dsz = 0, usz = 0, tsz = 0, ysz = 0;
         for (int id : lv) {
             dsz += (int64_t)m[id] * m[id];
             usz += (int64_t)m[id] * k[id];
             const HNode &q = H->node[id];
             if (q.left >= 0) tsz += (int64_t)k[q.left] * k[q.right];
             ysz += (int64_t)std::max(m[id], k[id]) * k[id];
-            wsz += (int64_t)k[id] * k[id];
         }
         DBuf Dw = dalloc<double>(std::max<int64_t>(dsz, 1)), Uw = dalloc<double>(std::max<int64_t>(usz, 1)),
              Tm = dalloc<double>(std::max<int64_t>(tsz, 1)), Yb = dalloc<double>(std::max<int64_t>(ysz, 1)),
-             Zb = dalloc<double>(std::max<int64_t>(ysz, 1)), Tb = dalloc<double>(std::max<int64_t>(wsz, 1));
+             Zb = dalloc<double>(std::max<int64_t>(ysz, 1));
         std::vector<UlvDesc> dsc(cnt);
-        int64_t od = 0, ou = 0, ot = 0, oy = 0, ow = 0;
+        int64_t od = 0, ou = 0, ot = 0, oy = 0;
         for (int a = 0; a < cnt; ++a) {
             const int id = lv[a];
             const HNode &q = H->node[id];
@@ -454,11 +450,10 @@ int64_t ulv_factor(const hss_s *H, const std::vector<double> &lam, const std::ve
             u.Uw = Uw.as<double>() + ou;
             u.Yw = Yb.as<double>() + oy;
             u.Zw = Zb.as<double>() + oy;
-            u.Tw = Tb.as<double>() + ow;
+            u.Tw = F->Y.as<double>() + F->offY[id];
             od += (int64_t)u.m * u.m;
             ou += (int64_t)u.m * u.k;
             oy += (int64_t)std::max(u.m, u.k) * u.k;
-            ow += (int64_t)u.k * u.k;
             u.V = F->V.as<double>() + F->offV[id];
             u.tau = F->T.as<double>() + F->offT[id];
             u.L = F->L.as<double>() + F->offL[id];
@@ -510,9 +505,9 @@ int64_t ulv_factor(const hss_s *H, const std::vector<double> &lam, const std::ve
 struct UlvSolvePlan {
     int nrhs = 0;
     int64_t n = 0;
-    DBuf bw, zb, cb, in, out;
+    DBuf bw, zb, cb, y1, y2, in, out;
     std::vector<DBuf> desc;             // forward levels, then backward levels
-    std::vector<int> cnt, nmax, fwd;    // per launch: blocks, LDS rows, 1 = forward
+    std::vector<int> cnt, fwd;          // per launch: blocks, 1 = forward
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     ~UlvSolvePlan() {
@@ -522,8 +517,6 @@ struct UlvSolvePlan {
 };
 
 namespace {
-
-constexpr size_t kSolveLdsMax = 160 * 1024;
 
 std::shared_ptr<UlvSolvePlan> make_plan(const hss_ulv_s *F, int nrhs, hipStream_t s) {
     auto P = std::make_shared<UlvSolvePlan>();
@@ -541,7 +534,10 @@ std::shared_ptr<UlvSolvePlan> make_plan(const hss_ulv_s *F, int nrhs, hipStream_
     P->bw = dalloc<double>(std::max<int64_t>(nb, 1));
     P->zb = dalloc<double>(std::max<int64_t>(nz, 1));
     P->cb = dalloc<double>(std::max<int64_t>(nc, 1));
+    P->y1 = dalloc<double>(std::max<int64_t>(nc, 1));
+    P->y2 = dalloc<double>(std::max<int64_t>(nc, 1));
     double *bw = P->bw.as<double>(), *zb = P->zb.as<double>(), *cb = P->cb.as<double>();
+    double *y1 = P->y1.as<double>(), *y2 = P->y2.as<double>();
     auto make = [&](int id) {
         const HNode &q = F->node[id];
         SolveDesc d;
@@ -552,12 +548,14 @@ std::shared_ptr<UlvSolvePlan> make_plan(const hss_ulv_s *F, int nrhs, hipStream_
         d.root = q.parent < 0;
         d.b = q.b;
         d.V = F->V.as<double>() + F->offV[id];
-        d.tau = F->T.as<double>() + F->offT[id];
-        d.L = F->L.as<double>() + F->offL[id];
+        d.T = F->Y.as<double>() + F->offY[id];
+        d.Li = F->L.as<double>() + F->offL[id];
         d.W = F->W.as<double>() + F->offW[id];
         d.bw = bw + ob[id];
         d.z = zb + oz[id];
         d.c_out = cb + oc[id];
+        d.y1 = y1 + oc[id];
+        d.y2 = y2 + oc[id];
         if (!d.leaf) {
             d.kl = F->node[q.left].k;
             d.kr = F->node[q.right].k;
@@ -573,13 +571,8 @@ std::shared_ptr<UlvSolvePlan> make_plan(const hss_ulv_s *F, int nrhs, hipStream_
     };
     auto add = [&](const std::vector<SolveDesc> &v, int forward) {
         if (v.empty()) return;
-        int nm = 1;
-        for (const auto &d : v) nm = std::max(nm, d.m);
-        KRR_REQUIRE(sizeof(double) * nm * (BG_T / 64) <= kSolveLdsMax,
-                    "ULV solve: a node of %d rows exceeds the LDS budget", nm);
         P->desc.push_back(upload(v, s));
         P->cnt.push_back((int)v.size());
-        P->nmax.push_back(nm);
         P->fwd.push_back(forward);
         sync(s);  // `v` is a temporary of the caller
     };
@@ -599,12 +592,11 @@ std::shared_ptr<UlvSolvePlan> make_plan(const hss_ulv_s *F, int nrhs, hipStream_
 
 void enqueue_solve(const UlvSolvePlan &P, const double *Bin, double *Xout, hipStream_t s) {
     for (size_t l = 0; l < P.desc.size(); ++l) {
-        const size_t lds = sizeof(double) * P.nmax[l] * (BG_T / 64);
         if (P.fwd[l]) {
-            k_ulv_fwd<<<(unsigned)P.cnt[l], BG_T, lds, s>>>(P.desc[l].as<SolveDesc>(), Bin, P.nrhs, P.nmax[l], Xout);
+            k_ulv_fwd<<<(unsigned)P.cnt[l], BG_T, 0, s>>>(P.desc[l].as<SolveDesc>(), Bin, P.nrhs, Xout);
             check_launch("k_ulv_fwd");
         } else {
-            k_ulv_bwd<<<(unsigned)P.cnt[l], BG_T, lds, s>>>(P.desc[l].as<SolveDesc>(), Xout, P.nrhs, P.nmax[l]);
+            k_ulv_bwd<<<(unsigned)P.cnt[l], BG_T, 0, s>>>(P.desc[l].as<SolveDesc>(), Xout, P.nrhs);
             check_launch("k_ulv_bwd");
         }
     }
