@@ -268,14 +268,17 @@ int hss_ulv_factor_spd(hss_t H, double lambda, double pivot_floor, void *stream,
 
 /*
  * As hss_ulv_factor, for use as a preconditioner: factors K_hss + (lambda +
- * delta) I for the first delta in 0, lambda, 4 lambda, 16 lambda, ... (12
- * tries) at which every Cholesky pivot is at least lambda / 2 -- in exact
- * arithmetic every pivot of K + lambda I is at least lambda, so smaller ones
- * are compression error.  A try stops at the first level with such a pivot;
- * the next try skips the deltas below the previous delta plus the largest
- * deficit (lambda / 2 - pivot) seen.
- * The refinement still applies the exact operator K + lambda I.  shift_host
- * (optional) receives delta.  KRR_E_NUMERIC if no try succeeds.
+ * delta) I with every Cholesky pivot at least lambda / 2 (in exact arithmetic
+ * every pivot of K + lambda I is at least lambda; truncated compression can
+ * make K_hss + lambda I indefinite).  delta is found by a bracketed search:
+ * 0; then the first of lambda, 4 lambda, 16 lambda, ... that covers the
+ * largest deficit (lambda / 2 - pivot) seen, repeated until a try succeeds at
+ * delta = hi; then hi / 8 and hi / 2 are tried and the first that succeeds
+ * kept (a smaller shift is a better preconditioner; pivots of the Schur
+ * complements grow faster than the shift, so hi overshoots).  A try stops at
+ * the first level with a failing pivot.  The refinement still applies the
+ * exact operator K + lambda I.  shift_host (optional) receives delta.
+ * KRR_E_NUMERIC if no try succeeds (20 tries).
  */
 int hss_ulv_factor_shifted(hss_t H, double lambda, void *stream, hss_ulv_t *out, double *shift_host);
 
@@ -370,10 +373,10 @@ int hss_num_problems(hss_t H, int32_t *np_host);
 
 /* ULV factorization of every problem of a compressed batch with its own
  * lambda[k] (host, np doubles).  shifted = 0: as hss_ulv_factor.  shifted = 1:
- * as hss_ulv_factor_shifted, each problem with its own shift lambda[k] s_k,
- * s_k in 0, 1, 4, 16, ... (a retry refactors only the problems that still
- * have a pivot below lambda[k] / 2; shift_mult_host, optional, host np
- * doubles, receives every s_k, zeros when shifted = 0).  Solve with
+ * as hss_ulv_factor_shifted, each problem with its own shift lambda[k] s_k
+ * from its own search (a retry refactors only the problems still searching;
+ * shift_mult_host, optional, host np doubles, receives every s_k, zeros when
+ * shifted = 0).  Solve with
  * hss_solve (the factor is block diagonal over the problems). */
 int hss_ulv_factor_batched(hss_t H, const double *lambda, int32_t shifted, void *stream,
                            hss_ulv_t *out, double *shift_mult_host);
