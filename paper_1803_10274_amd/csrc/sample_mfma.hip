@@ -168,6 +168,75 @@ __device__ __forceinline__ f16v dist_mfma(const float *xa, const float (*ya)[D +
     return t;
 }
 
+// BF16 form of the exponent product (split modes, D <= 16): both augmented
+// vectors are split into three BF16 terms (hi + mid + lo: 24 bits, FP32's
+// range) and the six cross products down to 2^-16 (hh, hm, mh, hl, lh, mm)
+// are packed along K, 6 (D + 2) slots rounded up to 16: KB / 16
+// v_mfma_f32_32x32x16_bf16 per 32 x 32 block instead of (D + 3) / 2
+// v_mfma_f32_32x32x2_f32, with the same C layout.  Products of BF16 terms are
+// exact in FP32, so the exponents keep the FP32 form's accuracy.
+template <int D> struct BExp {
+    static constexpr bool on = D <= 16;
+    static constexpr int KB = 16 * ((6 * (D + 2) + 15) / 16);  // packed K
+    static constexpr int LDB = KB + 8;                         // staged row (16 bytes of padding)
+};
+
+__device__ __forceinline__ void split3b(float v, __bf16 &h, __bf16 &m, __bf16 &l) {
+    h = (__bf16)v;
+    const float r1 = v - (float)h;
+    m = (__bf16)r1;
+    l = (__bf16)(r1 - (float)m);
+}
+
+// the term of each packed pair on the A side (points) and on the B side (rows)
+__device__ __forceinline__ int pair_a(int t) { return t == 2 || t == 5 ? 1 : (t == 4 ? 2 : 0); }
+__device__ __forceinline__ int pair_b(int t) { return t == 1 || t == 5 ? 1 : (t == 3 ? 2 : 0); }
+
+// Packed A rows of the augmented points y~ = (y', 1, -c |y'|^2) (outside the
+// columns [jlo, jhi) the last entry is -1e30, so the kernel value is 0).
+template <class T, int D, int YS>
+__device__ __forceinline__ void stage_yb(const T *__restrict__ X, int64_t jlo, int64_t jhi, int d, int64_t j0,
+                                         const float *anchor, float cs, __bf16 *yb) {
+    constexpr int KB = BExp<D>::KB, LDB = BExp<D>::LDB, DA = D + 2;
+    for (int p = threadIdx.x; p < YS; p += THREADS) {
+        const int64_t j = j0 + p;
+        const bool ok = j >= jlo && j < jhi;
+        float v[DA];
+        float nrm = 0.0f;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            v[k] = (ok && k < d) ? (float)X[j * d + k] - anchor[k] : 0.0f;
+            nrm = fmaf(v[k], v[k], nrm);
+        }
+        v[D] = 1.0f;
+        v[D + 1] = ok ? -cs * nrm : -1e30f;
+        __bf16 *row = yb + (int64_t)p * LDB;
+#pragma unroll
+        for (int k = 0; k < DA; ++k) {
+            __bf16 hml[3];
+            split3b(v[k], hml[0], hml[1], hml[2]);
+#pragma unroll
+            for (int t = 0; t < 6; ++t) row[t * DA + k] = hml[pair_a(t)];
+        }
+        for (int k = 6 * DA; k < KB; ++k) row[k] = (__bf16)0.0f;
+    }
+}
+
+// Exponents of one 32 x 32 (point j, row i) block from the packed operands
+// (C layout as dist_mfma); xb[s] holds the lane's row slots 16 s + 8 g + e.
+template <int D>
+__device__ __forceinline__ f16v dist_bf16(const bf8 *xb, const __bf16 *yb, int pbase, int lane) {
+    constexpr int KS = BExp<D>::KB / 16, LDB = BExp<D>::LDB;
+    const int g = lane >> 5;
+    const __bf16 *row = yb + (int64_t)(pbase + (lane & 31)) * LDB + 8 * g;
+    f16v t = {};
+#pragma unroll
+    for (int sidx = 0; sidx < KS; ++sidx)
+        t = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*reinterpret_cast<const bf8 *>(row + 16 * sidx), xb[sidx], t, 0, 0,
+                                                   0);
+    return t;
+}
+
 // Kernel entries from the exponents (masking entries of the row's own leaf),
 // split into the A operands of the two 16-point blocks: block kb takes
 // registers 8 kb .. 8 kb + 7, i.e. points 16 kb + (4 g + q, 8 + 4 g + q).
@@ -298,12 +367,15 @@ __global__ __launch_bounds__(THREADS) void k_sample_mfma(const T *__restrict__ X
     constexpr int YS = YTile<D>::N;
     constexpr int SUPER = YS / JT;  // tiles per Y super-tile
     __shared__ __attribute__((aligned(16))) char rbuf[2][RTILE_B];
-    // plain Y tiles (FP32 mode) or augmented ones (split modes)
-    constexpr int YW = MODE == M_F32 ? D + 1 : D + 3;
-    __shared__ float yab[2][YS][YW];
+    // plain Y tiles (FP32 mode), augmented ones (split modes) or packed BF16
+    // terms of the augmented ones (split modes, D <= 32)
+    constexpr bool BX = MODE != M_F32 && BExp<D>::on;
+    constexpr int YBYTES = MODE == M_F32 ? 2 * YS * (D + 1) * 4
+                                         : (BX ? 2 * YS * BExp<D>::LDB * 2 : 2 * YS * (D + 3) * 4);
+    __shared__ __attribute__((aligned(16))) char yraw[YBYTES];
     __shared__ float anchor[D];
-    float(*ysh0)[D + 1] = reinterpret_cast<float(*)[D + 1]>(&yab[0][0][0]);
-    float(*ysh1)[D + 1] = reinterpret_cast<float(*)[D + 1]>(&yab[1][0][0]);
+    float(*ysh0)[D + 1] = reinterpret_cast<float(*)[D + 1]>(yraw);
+    float(*ysh1)[D + 1] = reinterpret_cast<float(*)[D + 1]>(yraw) + YS;
     float(*const ysh[2])[D + 1] = {ysh0, ysh1};
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 5;
@@ -433,15 +505,49 @@ __global__ __launch_bounds__(THREADS) void k_sample_mfma(const T *__restrict__ X
         auto xt = [&](int k) { return k < D ? xs[k] : (k == D ? nx : (k == D + 1 ? 1.0f : 0.0f)); };
 #pragma unroll
         for (int sidx = 0; sidx < KS; ++sidx) xa[sidx] = g ? xt(2 * sidx + 1) : xt(2 * sidx);
+        // BF16 form: the lane's packed row slots 16 s + 8 g + e
+        constexpr int KS16 = BX ? BExp<D>::KB / 16 : 1;
+        bf8 xb[KS16];
+        if constexpr (BX) {
+#pragma unroll
+            for (int sidx = 0; sidx < KS16; ++sidx)
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int slot = 16 * sidx + 8 * g + e, DA = D + 2;
+                    __bf16 v = (__bf16)0.0f;
+                    if (slot < 6 * DA) {
+                        __bf16 hml[3];
+                        split3b(xt(slot % DA), hml[0], hml[1], hml[2]);
+                        v = hml[pair_b(slot / DA)];
+                    }
+                    xb[sidx][e] = v;
+                }
+        }
         // augmented Y tiles replace the plain ones in this mode
-        float(*ya0)[D + 3] = reinterpret_cast<float(*)[D + 3]>(&yab[0][0][0]);
-        float(*ya1)[D + 3] = reinterpret_cast<float(*)[D + 3]>(&yab[1][0][0]);
-        stage_ya<T, D, YS>(X, jlo, jhi, d, s0 * YS, anchor, cs, (s0 & 1) ? ya1 : ya0);
-        stage_ya<T, D, YS>(X, jlo, jhi, d, (s0 + 1) * YS, anchor, cs, (s0 & 1) ? ya0 : ya1);
+        float(*ya0)[D + 3] = reinterpret_cast<float(*)[D + 3]>(yraw);
+        float(*ya1)[D + 3] = reinterpret_cast<float(*)[D + 3]>(yraw) + YS;
+        __bf16 *yb0 = reinterpret_cast<__bf16 *>(yraw);
+        __bf16 *yb1 = yb0 + (BX ? YS * BExp<D>::LDB : 0);
+        auto stage = [&](int64_t sup) {
+            if constexpr (BX)
+                stage_yb<T, D, YS>(X, jlo, jhi, d, sup * YS, anchor, cs, (sup & 1) ? yb1 : yb0);
+            else
+                stage_ya<T, D, YS>(X, jlo, jhi, d, sup * YS, anchor, cs, (sup & 1) ? ya1 : ya0);
+        };
+        auto dist = [&](int64_t tt) -> f16v {
+            const bool odd = ((tt / SUPER) & 1) != 0;
+            const int pb = (int)((tt * JT) % YS);
+            if constexpr (BX)
+                return dist_bf16<D>(xb, odd ? yb1 : yb0, pb, lane);
+            else
+                return dist_mfma<D>(xa, odd ? ya1 : ya0, pb, lane);
+        };
+        stage(s0);
+        stage(s0 + 1);
         __syncthreads();
         V h0[2], l0[2], h1[2], l1[2];
         {
-            f16v t0 = dist_mfma<D>(xa, (s0 & 1) ? ya1 : ya0, t_lo_off, lane);
+            f16v t0 = dist(t_lo);
             if (KRR_TILE_MASKED(t_lo))
                 exp_split<MODE, TERMS, true>(h0, l0, t0, g, t_lo * JT, my_lb, my_le);
             else
@@ -452,20 +558,15 @@ __global__ __launch_bounds__(THREADS) void k_sample_mfma(const T *__restrict__ X
             for (int half = 0; half < 2; ++half) {
                 const int64_t tc = t + half;
                 if (half == 1 && tc >= t_hi) break;
-                if (tc % SUPER == 0 && tc != t_lo) {
-                    const int64_t sup = tc / SUPER + 1;
-                    stage_ya<T, D, YS>(X, jlo, jhi, d, sup * YS, anchor, cs, (sup & 1) ? ya1 : ya0);
-                }
+                if (tc % SUPER == 0 && tc != t_lo) stage(tc / SUPER + 1);
                 const int64_t tn = tc + 1;
-                const float(*yan)[D + 3] = ((tn / SUPER) & 1) ? ya1 : ya0;
-                const int pbn = (int)((tn * JT) % YS);
                 V(&ch)[2] = half == 0 ? h0 : h1;
                 V(&cl)[2] = half == 0 ? l0 : l1;
                 V(&nh)[2] = half == 0 ? h1 : h0;
                 V(&nl)[2] = half == 0 ? l1 : l0;
                 // exponents of the next tile first (matrix pipe), then this
                 // tile's products, then the next tile's entries (vector ALUs)
-                const f16v tnext = dist_mfma<D>(xa, yan, pbn, lane);
+                const f16v tnext = dist(tn);
                 {
                     const V *rt = reinterpret_cast<const V *>(rbuf[tc & 1]);
 #pragma unroll

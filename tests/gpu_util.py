@@ -131,8 +131,12 @@ def mfma_sample_bound(Xp, R, h, lb, le, prec, split, rows, rows_per_block=256, s
 
     Entry e_ij = exp2(t) with t formed in FP32 from coordinates re-centred on
     the workgroup's first point a (x' = x - a, y' = y - a): the FMA chain of
-    d + 2 terms gives |dt| <= (d + 2) u c (|x'| + |y'|)^2 in log2 units, so
-    |de| <= e u [2 + (d + 2) (|x'| + |y'|)^2 / (2 h^2)] plus the split's own
+    d + 2 terms gives |dt| <= (d + 2) u c (|x'| + |y'|)^2 in log2 units (the
+    split modes at d <= 16 form t from three-term BF16 splits of the same
+    operands: the split's representation error, 2^-24 per operand, and the
+    dropped cross terms, 2^-23 of each product, give at most 4 (d + 2) units
+    in place of d + 2), so |de| <= e u [2 + k (d + 2) (|x'| + |y'|)^2 / (2 h^2)]
+    with k = 4 there and 1 otherwise, plus the split's own
     rounding SPLIT_U * e.  The FP32 accumulation over n terms is charged with
     the probabilistic model sqrt(n_adds) u ||e o r||_2 (Higham and Mary 2019),
     FP16 entries (scaled by 2^14) add 2^-38 absolute where they fall below
@@ -153,7 +157,8 @@ def mfma_sample_bound(Xp, R, h, lb, le, prec, split, rows, rows_per_block=256, s
         q = ((Xp - Xp[i]) ** 2).sum(axis=1)
         e = np.exp(-q / (2 * h * h))
         e[lb[i]:le[i]] = 0.0
-        de = e * (U32 * (2 + (d + 2) * (xr + yr) ** 2 / (2 * h * h)) + us)
+        kx = 4 if (prec != "f32" and d <= 16) else 1
+        de = e * (U32 * (2 + kx * (d + 2) * (xr + yr) ** 2 / (2 * h * h)) + us)
         if prec == "f16":
             # entries carry a 2^14 scale; below FP16's normal range the hi and
             # lo terms keep an absolute precision of 2^-25 in scaled units
