@@ -235,104 +235,108 @@ struct SolveDesc {
     const double *x_par;     // parent's solution rows for this node (k x nrhs), set for the backward sweep
 };
 
+// out(o) = sum over l in [lo(o), hi(o)) of term(o, l), for o < nout: each
+// output is summed by a team of ts consecutive lanes (ts the largest power of
+// two <= blockDim / nout, at most 64, so a team stays inside a wave), which
+// shortens the dependent chain of the big nodes near the root.
+template <class Range, class Term, class Store>
+__device__ __forceinline__ void team_sum(int nout, Range range, Term term, Store store) {
+    const int nt = blockDim.x, tid = threadIdx.x;
+    int ts = 1;
+    while (ts < 64 && 2 * ts * nout <= nt) ts *= 2;
+    const int team = tid / ts, li = tid % ts, nteams = nt / ts;
+    for (int o0 = 0; o0 < nout; o0 += nteams) {  // uniform trip count: every lane takes part in the shuffles
+        const int o = o0 + team;
+        double acc = 0.0;
+        if (o < nout) {
+            int lo, hi;
+            range(o, lo, hi);
+            for (int l = lo + li; l < hi; l += ts) acc += term(o, l);
+        }
+        for (int off = ts / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if (o < nout && li == 0) store(o, acc);
+    }
+}
+
 // bw (m x nrhs) <- (I - V op(T) V^T) bw with op(T) = T^T (Q^T, `trans`) or T
 // (Q).  V (m x k) holds unit lower-trapezoidal reflectors (zeros above the
-// diagonal, ones on it); each product is spread over the workgroup's threads.
+// diagonal, ones on it).
 __device__ void apply_wy(const double *__restrict__ V, const double *__restrict__ T, int m, int k, double *bw,
                          int nrhs, double *y1, double *y2, bool trans) {
-    const int tid = threadIdx.x;
-    for (int t = tid; t < k * nrhs; t += BG_T) {  // y1 = V^T bw
-        const int j = t / nrhs, c = t % nrhs;
-        double acc = 0.0;
-        for (int i = j; i < m; ++i) acc += V[(int64_t)i * k + j] * bw[(int64_t)i * nrhs + c];
-        y1[t] = acc;
-    }
+    // y1 = V^T bw
+    team_sum(k * nrhs, [&](int o, int &lo, int &hi) { lo = o / nrhs; hi = m; },
+             [&](int o, int i) { return V[(int64_t)i * k + o / nrhs] * bw[(int64_t)i * nrhs + o % nrhs]; },
+             [&](int o, double v) { y1[o] = v; });
     __syncthreads();
-    for (int t = tid; t < k * nrhs; t += BG_T) {  // y2 = op(T) y1, T upper triangular
-        const int j = t / nrhs, c = t % nrhs;
-        double acc = 0.0;
-        if (trans)
-            for (int l = 0; l <= j; ++l) acc += T[(int64_t)l * k + j] * y1[(int64_t)l * nrhs + c];
-        else
-            for (int l = j; l < k; ++l) acc += T[(int64_t)j * k + l] * y1[(int64_t)l * nrhs + c];
-        y2[t] = acc;
-    }
+    // y2 = op(T) y1, T upper triangular
+    if (trans)
+        team_sum(k * nrhs, [&](int o, int &lo, int &hi) { lo = 0; hi = o / nrhs + 1; },
+                 [&](int o, int l) { return T[(int64_t)l * k + o / nrhs] * y1[(int64_t)l * nrhs + o % nrhs]; },
+                 [&](int o, double v) { y2[o] = v; });
+    else
+        team_sum(k * nrhs, [&](int o, int &lo, int &hi) { lo = o / nrhs; hi = k; },
+                 [&](int o, int l) { return T[(int64_t)(o / nrhs) * k + l] * y1[(int64_t)l * nrhs + o % nrhs]; },
+                 [&](int o, double v) { y2[o] = v; });
     __syncthreads();
-    for (int t = tid; t < m * nrhs; t += BG_T) {  // bw -= V y2
-        const int i = t / nrhs, c = t % nrhs;
-        const int jm = min(i + 1, k);
-        double acc = 0.0;
-        for (int j = 0; j < jm; ++j) acc += V[(int64_t)i * k + j] * y2[(int64_t)j * nrhs + c];
-        bw[t] -= acc;
-    }
+    // bw -= V y2
+    team_sum(m * nrhs, [&](int o, int &lo, int &hi) { lo = 0; hi = min(o / nrhs + 1, k); },
+             [&](int o, int j) { return V[(int64_t)(o / nrhs) * k + j] * y2[(int64_t)j * nrhs + o % nrhs]; },
+             [&](int o, double v) { bw[o] -= v; });
     __syncthreads();
 }
 
-__global__ __launch_bounds__(BG_T) void k_ulv_fwd(const SolveDesc *dsc, const double *__restrict__ Bin, int nrhs,
+__global__ __launch_bounds__(1024) void k_ulv_fwd(const SolveDesc *dsc, const double *__restrict__ Bin, int nrhs,
                                                   double *__restrict__ Xout) {
     const SolveDesc q = dsc[blockIdx.x];
-    const int m = q.m, k = q.k, ne = m - k, tid = threadIdx.x;
+    const int m = q.m, k = q.k, ne = m - k, tid = threadIdx.x, nt = blockDim.x;
     if (q.leaf) {
-        for (int64_t t = tid; t < (int64_t)m * nrhs; t += BG_T) q.bw[t] = Bin[q.b * nrhs + t];
+        for (int64_t t = tid; t < (int64_t)m * nrhs; t += nt) q.bw[t] = Bin[q.b * nrhs + t];
     } else {
-        for (int64_t t = tid; t < (int64_t)q.kl * nrhs; t += BG_T) q.bw[t] = q.c_l[t];
-        for (int64_t t = tid; t < (int64_t)q.kr * nrhs; t += BG_T) q.bw[(int64_t)q.kl * nrhs + t] = q.c_r[t];
+        for (int64_t t = tid; t < (int64_t)q.kl * nrhs; t += nt) q.bw[t] = q.c_l[t];
+        for (int64_t t = tid; t < (int64_t)q.kr * nrhs; t += nt) q.bw[(int64_t)q.kl * nrhs + t] = q.c_r[t];
     }
     __syncthreads();
     if (k > 0) apply_wy(q.V, q.T, m, k, q.bw, nrhs, q.y1, q.y2, true);
     // z = L^{-1} b_e
-    for (int t = tid; t < ne * nrhs; t += BG_T) {
-        const int i = t / nrhs, c = t % nrhs;
-        const double *li = q.Li + (int64_t)i * ne;
-        double acc = 0.0;
-        for (int l = 0; l <= i; ++l) acc += li[l] * q.bw[(int64_t)(k + l) * nrhs + c];
-        q.z[t] = acc;
-    }
+    const double *bwe = q.bw + (int64_t)k * nrhs;
+    team_sum(ne * nrhs, [&](int o, int &lo, int &hi) { lo = 0; hi = o / nrhs + 1; },
+             [&](int o, int l) { return q.Li[(int64_t)(o / nrhs) * ne + l] * bwe[(int64_t)l * nrhs + o % nrhs]; },
+             [&](int o, double v) { q.z[o] = v; });
     __syncthreads();
     if (q.root) {
         // whole solve at the root (k = 0): x = L^{-T} z
-        for (int t = tid; t < m * nrhs; t += BG_T) {
-            const int i = t / nrhs, c = t % nrhs;
-            double acc = 0.0;
-            for (int l = i; l < m; ++l) acc += q.Li[(int64_t)l * m + i] * q.z[(int64_t)l * nrhs + c];
-            q.bw[t] = acc;
-            // a one-node tree (the root is a leaf) has no backward sweep
-            if (q.leaf) Xout[q.b * nrhs + t] = acc;
-        }
+        team_sum(m * nrhs, [&](int o, int &lo, int &hi) { lo = o / nrhs; hi = m; },
+                 [&](int o, int l) { return q.Li[(int64_t)l * m + o / nrhs] * q.z[(int64_t)l * nrhs + o % nrhs]; },
+                 [&](int o, double v) {
+                     q.bw[o] = v;
+                     if (q.leaf) Xout[q.b * nrhs + o] = v;  // a one-node tree has no backward sweep
+                 });
         return;
     }
     // c = b_c - W z
-    for (int64_t t = tid; t < (int64_t)k * nrhs; t += BG_T) {
-        int i = (int)(t / nrhs), c = (int)(t % nrhs);
-        double acc = q.bw[(int64_t)i * nrhs + c];
-        for (int l = 0; l < ne; ++l) acc -= q.W[(int64_t)i * ne + l] * q.z[(int64_t)l * nrhs + c];
-        q.c_out[t] = acc;
-    }
+    team_sum(k * nrhs, [&](int o, int &lo, int &hi) { lo = 0; hi = ne; },
+             [&](int o, int l) { return q.W[(int64_t)(o / nrhs) * ne + l] * q.z[(int64_t)l * nrhs + o % nrhs]; },
+             [&](int o, double v) { q.c_out[o] = q.bw[o] - v; });
 }
 
-__global__ __launch_bounds__(BG_T) void k_ulv_bwd(const SolveDesc *dsc, double *__restrict__ Xout, int nrhs) {
+__global__ __launch_bounds__(1024) void k_ulv_bwd(const SolveDesc *dsc, double *__restrict__ Xout, int nrhs) {
     const SolveDesc q = dsc[blockIdx.x];
-    const int m = q.m, k = q.k, ne = m - k, tid = threadIdx.x;
-    // x_c from the parent; z <- z - W^T x_c (each thread its own entries)
-    for (int64_t t = tid; t < (int64_t)k * nrhs; t += BG_T) q.bw[t] = q.x_par[t];
-    for (int64_t t = tid; t < (int64_t)ne * nrhs; t += BG_T) {
-        int l = (int)(t / nrhs), c = (int)(t % nrhs);
-        double acc = q.z[t];
-        for (int i = 0; i < k; ++i) acc -= q.W[(int64_t)i * ne + l] * q.x_par[(int64_t)i * nrhs + c];
-        q.z[t] = acc;
-    }
+    const int m = q.m, k = q.k, ne = m - k, tid = threadIdx.x, nt = blockDim.x;
+    // x_c from the parent; z <- z - W^T x_c
+    for (int64_t t = tid; t < (int64_t)k * nrhs; t += nt) q.bw[t] = q.x_par[t];
+    team_sum(ne * nrhs, [&](int o, int &lo, int &hi) { lo = 0; hi = k; },
+             [&](int o, int i) { return q.W[(int64_t)i * ne + o / nrhs] * q.x_par[(int64_t)i * nrhs + o % nrhs]; },
+             [&](int o, double v) { q.z[o] -= v; });
     __syncthreads();
     // x_e = L^{-T} z
-    for (int t = tid; t < ne * nrhs; t += BG_T) {
-        const int i = t / nrhs, c = t % nrhs;
-        double acc = 0.0;
-        for (int l = i; l < ne; ++l) acc += q.Li[(int64_t)l * ne + i] * q.z[(int64_t)l * nrhs + c];
-        q.bw[(int64_t)(k + i) * nrhs + c] = acc;
-    }
+    double *bwe = q.bw + (int64_t)k * nrhs;
+    team_sum(ne * nrhs, [&](int o, int &lo, int &hi) { lo = o / nrhs; hi = ne; },
+             [&](int o, int l) { return q.Li[(int64_t)l * ne + o / nrhs] * q.z[(int64_t)l * nrhs + o % nrhs]; },
+             [&](int o, double v) { bwe[o] = v; });
     __syncthreads();
     if (k > 0) apply_wy(q.V, q.T, m, k, q.bw, nrhs, q.y1, q.y2, false);
     if (q.leaf)
-        for (int64_t t = tid; t < (int64_t)m * nrhs; t += BG_T) Xout[q.b * nrhs + t] = q.bw[t];
+        for (int64_t t = tid; t < (int64_t)m * nrhs; t += nt) Xout[q.b * nrhs + t] = q.bw[t];
 }
 
 }  // namespace
@@ -592,11 +596,13 @@ std::shared_ptr<UlvSolvePlan> make_plan(const hss_ulv_s *F, int nrhs, hipStream_
 
 void enqueue_solve(const UlvSolvePlan &P, const double *Bin, double *Xout, hipStream_t s) {
     for (size_t l = 0; l < P.desc.size(); ++l) {
+        // levels of few nodes (near the root, big nodes) get 1024 threads per node
+        const int nt = P.cnt[l] >= 1024 ? BG_T : 1024;
         if (P.fwd[l]) {
-            k_ulv_fwd<<<(unsigned)P.cnt[l], BG_T, 0, s>>>(P.desc[l].as<SolveDesc>(), Bin, P.nrhs, Xout);
+            k_ulv_fwd<<<(unsigned)P.cnt[l], nt, 0, s>>>(P.desc[l].as<SolveDesc>(), Bin, P.nrhs, Xout);
             check_launch("k_ulv_fwd");
         } else {
-            k_ulv_bwd<<<(unsigned)P.cnt[l], BG_T, 0, s>>>(P.desc[l].as<SolveDesc>(), Xout, P.nrhs);
+            k_ulv_bwd<<<(unsigned)P.cnt[l], nt, 0, s>>>(P.desc[l].as<SolveDesc>(), Xout, P.nrhs);
             check_launch("k_ulv_bwd");
         }
     }
