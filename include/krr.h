@@ -129,9 +129,15 @@ int krr_scatter_rows(const void *src, int32_t prec, int64_t n, int32_t cols,
  * never stored.
  *   X    m x d points, Y  n x d points (both xprec)
  *   W    n x nrhs FP64,  Out  m x nrhs FP64 (read only if beta != 0)
- *   prec KRR_F64: FP64 throughout.  KRR_F32: kernel entries and products in
- *        FP32 from exact coordinate differences, sums over each column tile in
- *        FP32 and across tiles in FP64.
+ *   prec KRR_F64: FP64 throughout (exponents from exact coordinate
+ *        differences for d <= 64; for d > 64 an FP64 matrix-core GEMM of the
+ *        norm expansion on coordinates centred on the mean of Y).
+ *        KRR_F32: kernel entries and products in FP32, sums over each column
+ *        tile in FP32 and across tiles in FP64.  Exponents: for d <= 64 the
+ *        FP64 norm expansion; for K(X, X) with one right-hand side (the
+ *        symmetric form, KRR_TUNE_SYMMETRIC) FP32-accurate matrix-core
+ *        exponents on coordinates re-centred per row block; for d > 64 an
+ *        FP32 matrix-core GEMM on coordinates centred on the mean of Y.
  *   1 <= nrhs <= 64.
  */
 int kernel_matvec(const void *X, int64_t m, const void *Y, int64_t n, int32_t d,
