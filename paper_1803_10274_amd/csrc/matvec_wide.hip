@@ -1,11 +1,16 @@
 // FP32-entry kernel product Out = K(X, Y; h) W for wide points (d > 64) on
 // the matrix cores.  The exponents are a GEMM of prepared coordinates (see
-// wide.hpp): a workgroup owns 128 rows (4 waves x 32) and walks the columns
-// in panels of 128 points, accumulating t = x~_i . y~_j over K chunks of 64
-// staged through LDS with v_mfma_f32_32x32x2_f32 (points as A rows, the
-// wave's rows as B columns).  Each lane then holds, for its row, the
-// exponents of 16 points of every 32-point tile; exp2 turns them into FP32
-// entries that are directly the A operand of a second v_mfma_f32_32x32x2_f32
+// wide.hpp), each split into three BF16 terms (hi + mid + lo: 24 bits, FP32's
+// range) and the six cross products down to 2^-16 (hh, hm, mh, hl, lh, mm)
+// accumulated by v_mfma_f32_32x32x16_bf16, which gives FP32-accurate
+// exponents at about 2.6 times the FP32 matrix-core rate.  Only the three
+// terms are stored and staged (6 bytes per coordinate); each pair reads its
+// operands from the matching term block.  A workgroup owns
+// 128 rows (4 waves x 32) and walks the columns in panels of 128 points,
+// accumulating t = x~_i . y~_j over K chunks staged through LDS (points as A
+// rows, the wave's rows as B columns).  Each lane then holds, for its row,
+// the exponents of 16 points of every 32-point tile; exp2 turns them into
+// FP32 entries that are directly the A operand of a v_mfma_f32_32x32x2_f32
 // product with the panel's weights (B: the weights of the same points, up to
 // 32 right-hand sides), so E never leaves registers.  Products are summed in
 // FP32 over a panel and in FP64 across panels; the columns are split across
@@ -21,22 +26,44 @@ typedef float f16v __attribute__((ext_vector_type(16)));
 constexpr int KW = 4;           // waves per workgroup
 constexpr int KROWS = 32 * KW;  // rows per workgroup
 constexpr int KPT = 4;          // 32-point tiles per panel
-constexpr int KKC = 64;         // augmented coordinates per LDS chunk
+constexpr int KKC = 64;         // augmented coordinates: KP is a multiple of this
+constexpr int BC = 32;          // augmented coordinates per LDS chunk
+constexpr int BCS = 3 * BC;     // BF16 terms per chunk
+constexpr int BLD = BCS + 8;    // staged row (16 bytes of padding)
+
+typedef __bf16 bf8w __attribute__((ext_vector_type(8)));
+
+// Three-term BF16 rows: for coordinate k = 32 c + j, slot 96 c + j holds its
+// hi term, 96 c + 32 + j the mid term and 96 c + 64 + j the lo term.
+__global__ void k_wide_pack(const float *__restrict__ A, int64_t n, int KP, __bf16 *__restrict__ P) {
+    const int64_t i = blockIdx.x;
+    if (i >= n) return;
+    for (int k = threadIdx.x; k < KP; k += blockDim.x) {
+        const float v = A[i * KP + k];
+        const __bf16 h = (__bf16)v;
+        const float r1 = v - (float)h;
+        const __bf16 mid = (__bf16)r1;
+        const __bf16 lo = (__bf16)(r1 - (float)mid);
+        __bf16 *row = P + i * (int64_t)KP * 3 + (int64_t)(k / BC) * BCS + (k % BC);
+        row[0] = h;
+        row[BC] = mid;
+        row[2 * BC] = lo;
+    }
+}
 
 // point of register s of a lane in half g of the wave (the C layout of the
 // exponent GEMM): 8 (s / 4) + 4 g + s % 4
 __device__ __forceinline__ int reg_point(int s, int g) { return 8 * (s >> 2) + 4 * g + (s & 3); }
 
-__global__ __launch_bounds__(64 * KW) void k_kmv_wmfma(const float *__restrict__ XA, int64_t m,
-                                                       const float *__restrict__ YA, int64_t n, int KP,
+__global__ __launch_bounds__(64 * KW) void k_kmv_wmfma(const __bf16 *__restrict__ XB, int64_t m,
+                                                       const __bf16 *__restrict__ YB, int64_t n, int KP,
                                                        const float *__restrict__ wf, int nrhs, int rhs0, int nrc,
                                                        int64_t cols_per_split, double *__restrict__ part,
                                                        const SampBlock *__restrict__ bt) {
     constexpr int TH = 64 * KW;
-    constexpr int LDK = KKC + 1;
-    __shared__ __attribute__((aligned(16))) float lds[2 * KROWS * LDK];
-    float(*xs)[LDK] = reinterpret_cast<float(*)[LDK]>(lds);
-    float(*ys)[LDK] = reinterpret_cast<float(*)[LDK]>(lds + KROWS * LDK);
+    __shared__ __attribute__((aligned(16))) __bf16 lds[2 * KROWS * BLD];
+    __bf16 *xs = lds;                  // [KROWS][BLD] rows
+    __bf16 *ys = lds + KROWS * BLD;    // [KROWS][BLD] points
     float(*ws)[33] = reinterpret_cast<float(*)[33]>(lds);  // the panel's weights, after the GEMM
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 5;
@@ -54,6 +81,7 @@ __global__ __launch_bounds__(64 * KW) void k_kmv_wmfma(const float *__restrict__
         j0 = split * cols_per_split;
         j1 = min(n, j0 + cols_per_split);
     }
+    const int64_t KP3 = (int64_t)KP * 3;
     double acc[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) acc[q] = 0.0;
@@ -63,25 +91,44 @@ __global__ __launch_bounds__(64 * KW) void k_kmv_wmfma(const float *__restrict__
         for (int pt = 0; pt < KPT; ++pt)
 #pragma unroll
             for (int q = 0; q < 16; ++q) t[pt][q] = 0.0f;
-        for (int kc = 0; kc < KP; kc += KKC) {
-            for (int u = tid; u < KROWS * KKC; u += TH) {
-                const int rr = u / KKC, kk = u % KKC;
+        for (int kc = 0; kc < KP; kc += BC) {
+            // 16-byte pieces: KROWS rows x BCS / 8 pieces each, for both sides
+            const int64_t coff = (int64_t)(kc / BC) * BCS;
+            for (int u = tid; u < KROWS * (BCS / 8); u += TH) {
+                const int rr = u / (BCS / 8), e8 = (u % (BCS / 8)) * 8;
                 const int64_t gi = i0 + rr, gj = p0 + rr;
-                xs[rr][kk] = gi < iend ? XA[gi * KP + kc + kk] : 0.0f;
-                ys[rr][kk] = (gj >= j0 && gj < j1) ? YA[gj * KP + kc + kk] : 0.0f;
+                const uint4 zero = {0u, 0u, 0u, 0u};
+                *reinterpret_cast<uint4 *>(xs + rr * BLD + e8) =
+                    gi < iend ? *reinterpret_cast<const uint4 *>(XB + gi * KP3 + coff + e8) : zero;
+                *reinterpret_cast<uint4 *>(ys + rr * BLD + e8) =
+                    (gj >= j0 && gj < j1) ? *reinterpret_cast<const uint4 *>(YB + gj * KP3 + coff + e8) : zero;
             }
             __syncthreads();
-#pragma unroll 4
-            for (int s2 = 0; s2 < KKC / 2; ++s2) {
-                const int kk = 2 * s2 + g;
-                const float b = xs[32 * w + (lane & 31)][kk];
+            // K halves of 16 coordinates; operands: term block (0 hi, 1 mid,
+            // 2 lo) at 32 x block + 16 x half + 8 g within a staged row
+            const __bf16 *xr = xs + (32 * w + (lane & 31)) * BLD + 8 * g;
 #pragma unroll
-                for (int pt = 0; pt < KPT; ++pt)
-                    t[pt] = __builtin_amdgcn_mfma_f32_32x32x2f32(ys[32 * pt + (lane & 31)][kk], b, t[pt], 0, 0, 0);
+            for (int kh = 0; kh < 2; ++kh) {
+                const bf8w bh = *reinterpret_cast<const bf8w *>(xr + 16 * kh);
+                const bf8w bm = *reinterpret_cast<const bf8w *>(xr + BC + 16 * kh);
+                const bf8w bl = *reinterpret_cast<const bf8w *>(xr + 2 * BC + 16 * kh);
+#pragma unroll
+                for (int pt = 0; pt < KPT; ++pt) {
+                    const __bf16 *yr = ys + (32 * pt + (lane & 31)) * BLD + 8 * g + 16 * kh;
+                    const bf8w ah = *reinterpret_cast<const bf8w *>(yr);
+                    const bf8w am = *reinterpret_cast<const bf8w *>(yr + BC);
+                    const bf8w al = *reinterpret_cast<const bf8w *>(yr + 2 * BC);
+                    t[pt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bm, t[pt], 0, 0, 0);
+                    t[pt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, t[pt], 0, 0, 0);
+                    t[pt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, t[pt], 0, 0, 0);
+                    t[pt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bh, t[pt], 0, 0, 0);
+                    t[pt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bm, t[pt], 0, 0, 0);
+                    t[pt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, t[pt], 0, 0, 0);
+                }
             }
             __syncthreads();
         }
-        // the panel's weights (zero outside the column range and past nrc)
+    // the panel's weights (zero outside the column range and past nrc)
         for (int u = tid; u < 32 * KPT * 32; u += TH) {
             const int pp = u / 32, col = u % 32;
             const int64_t gj = p0 + pp;
@@ -337,12 +384,17 @@ void kmv_wide_mfma(const float *X, int64_t m, const float *Y, int64_t n, int d, 
     check_launch("k_wide_aug");
     k_w_to_float_wide<<<ceil_div(n * nrhs, 256), 256, 0, s>>>(W, n * nrhs, wf.as<float>());
     check_launch("k_w_to_float_wide");
+    DBuf XB = dalloc<__bf16>((size_t)m * KP * 3), YB = dalloc<__bf16>((size_t)n * KP * 3);
+    k_wide_pack<<<(unsigned)m, 256, 0, s>>>(XA.as<float>(), m, KP, XB.as<__bf16>());
+    check_launch("k_wide_pack");
+    k_wide_pack<<<(unsigned)n, 256, 0, s>>>(YA.as<float>(), n, KP, YB.as<__bf16>());
+    check_launch("k_wide_pack");
     DBuf part = dalloc<double>((size_t)nsplit * m * nrhs);
     dim3 grid((unsigned)(batch ? nb : ceil_div(m, KROWS)), nsplit);
     for (int r0 = 0; r0 < nrhs; r0 += 32) {
         const int nrc = std::min(32, nrhs - r0);
-        k_kmv_wmfma<<<grid, 64 * KW, 0, s>>>(XA.as<float>(), m, YA.as<float>(), n, KP, wf.as<float>(), nrhs, r0, nrc,
-                                            cps, part.as<double>(), btab.as<SampBlock>());
+        k_kmv_wmfma<<<grid, 64 * KW, 0, s>>>(XB.as<__bf16>(), m, YB.as<__bf16>(), n, KP, wf.as<float>(), nrhs, r0,
+                                            nrc, cps, part.as<double>(), btab.as<SampBlock>());
         check_launch("k_kmv_wmfma");
     }
     const int64_t mn = m * nrhs;
