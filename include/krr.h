@@ -136,8 +136,10 @@ int krr_scatter_rows(const void *src, int32_t prec, int64_t n, int32_t cols,
  *        tile in FP32 and across tiles in FP64.  Exponents: for d <= 64 the
  *        FP64 norm expansion; for K(X, X) with one right-hand side (the
  *        symmetric form, KRR_TUNE_SYMMETRIC) FP32-accurate matrix-core
- *        exponents on coordinates re-centred per row block; for d > 64 an
- *        FP32 matrix-core GEMM on coordinates centred on the mean of Y.
+ *        exponents on coordinates re-centred per row block; for d > 64 a
+ *        matrix-core GEMM of three-term BF16 splits (six cross products,
+ *        FP32 accumulation: FP32-accurate) on coordinates centred on the
+ *        mean of Y.
  *   1 <= nrhs <= 64.
  */
 int kernel_matvec(const void *X, int64_t m, const void *Y, int64_t n, int32_t d,
@@ -422,7 +424,7 @@ enum {
     KRR_TUNE_SYMMETRIC = 0,  /* K(X, X) W evaluates each off-diagonal entry once (FP32 points, one
                                 right-hand side; otherwise the vector form 2). Exponent engine:
                                 4 (default) FP32-accurate exponents from three-term BF16 splits on the
-                                matrix cores, re-centred per row block (d <= 15; else as 3);
+                                matrix cores, re-centred per row block (d <= 31; else as 3);
                                 3 FP32 exponents on the matrix cores, re-centred per row block;
                                 1 FP64 exponents on the matrix cores; 2 FP64 exponents on the vector
                                 ALUs; 0 off */
