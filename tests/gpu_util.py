@@ -30,7 +30,7 @@ def fp32_product_bound(X, Y, W, h, tile=64, safety=4.0, mask=None):
     return safety * U32 * ((tile + 2) * (K @ aW) + (d + 3) * ((K * t) @ aW))
 
 
-def fp32_wide_product_bound(X, Y, W, h, panel=128, safety=4.0):
+def fp32_wide_product_bound(X, Y, W, h, panel=128, safety=4.0, anchor=None):
     """Elementwise bound for the FP32-entry product of wide points: exponents
     from the norm expansion on coordinates centred on the mean of Y, each FP32
     coordinate split into three BF16 terms with six cross products kept, so a
@@ -38,10 +38,11 @@ def fp32_wide_product_bound(X, Y, W, h, panel=128, safety=4.0):
     and the dropped products (below u / 2 of the magnitudes):
     |dt| <= (6 (d + 2) + 1) u (|x'| + |y'|)^2 / (2 h^2) in natural-log units;
     exp2 within 2 ulp, FP32 sums over a panel of `panel` points and FP64 sums
-    across panels."""
+    across panels.  `anchor` replaces the mean of Y as the centre (a batch
+    centres every problem on the mean of all its points)."""
     X = np.asarray(X, dtype=np.float64)
     Y = np.asarray(Y, dtype=np.float64)
-    a = Y.mean(axis=0)
+    a = Y.mean(axis=0) if anchor is None else np.asarray(anchor, dtype=np.float64)
     nx = np.linalg.norm(X - a, axis=1)
     ny = np.linalg.norm(Y - a, axis=1)
     q = sqdist(X, Y)

@@ -85,6 +85,25 @@ def test_matvec_wide_symmetric_and_ragged(gpu_lib, d, nrhs):
     assert np.all(np.abs(got - ref) <= fp32_wide_product_bound(X, X, W, h))
 
 
+def test_matvec_fp32_wide_batched_and_ragged(gpu_lib):
+    # FP32 entries of wide points through the per-problem row-block tables:
+    # three problems of ragged sizes against row blocks and panels of
+    # 128 points, per-problem widths, 40 right-hand sides (passes of 32 and 8)
+    sizes, d = [300, 7, 530], 100
+    rng = np.random.default_rng(6)
+    Xs = [(0.3 * rng.standard_normal((k, d))).astype(np.float32) for k in sizes]
+    hs = [2.0, 3.0, 2.5]
+    X = np.concatenate(Xs)
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    W = sd.vectors(X.shape[0], 40, seed=7)
+    got = gpu_lib.kernel_matvec_batched(_t(X), off, hs, _t(W), prec="f32").cpu().numpy()
+    for k in range(3):
+        a, b = off[k], off[k + 1]
+        ref = cmath.kmv(Xs[k], Xs[k], W[a:b], hs[k])
+        bound = fp32_wide_product_bound(Xs[k], Xs[k], W[a:b], hs[k], anchor=X.astype(np.float64).mean(axis=0))
+        assert np.all(np.abs(got[a:b] - ref) <= bound), k
+
+
 def test_matvec_beta_and_empty(gpu_lib):
     X = sd.points(70, 3, seed=7, dtype=np.float64)
     W = sd.vectors(70, 2, seed=8)
