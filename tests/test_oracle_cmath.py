@@ -46,3 +46,49 @@ def test_residual_zero_for_exact_solution():
     y = sd.vectors(50, 1, seed=7)[:, 0]
     r = cmath.residual(X, y / 1.5, y, 1e-3, 0.5)
     assert np.max(np.abs(r)) < 1e-15
+
+
+def test_kmv_brute_force_wide_points():
+    # widths of the wide-point products (d = 100, 784) on a tiny grid, so a
+    # stride or loop-bound slip past the first coordinates shows
+    for d, h in ((100, 3.0), (784, 4.0)):
+        X = sd.points(5, d, seed=d, scale=0.3).astype(np.float64)
+        Y = sd.points(7, d, seed=d + 1, scale=0.3).astype(np.float64)
+        W = sd.vectors(7, 3, seed=d + 2)
+        np.testing.assert_allclose(cmath.kmv(X, Y, W, h), _brute(X, Y, W, h), rtol=1e-12, atol=1e-14)
+
+
+def test_kmv_closed_forms():
+    # eq. (1.1) at coincident points is 1, so K W is the column sums of W; at
+    # points much farther apart than h it is 0 off the coincident pairs
+    x = sd.points(1, 9, seed=8).astype(np.float64)
+    W = sd.vectors(6, 2, seed=9)
+    np.testing.assert_allclose(cmath.kmv(np.repeat(x, 4, axis=0), np.repeat(x, 6, axis=0), W, 0.7),
+                               np.tile(W.sum(axis=0), (4, 1)), rtol=1e-15, atol=0)
+    far = np.arange(6, dtype=np.float64)[:, None] * np.full((1, 3), 100.0)
+    np.testing.assert_allclose(cmath.kmv(far, far, W, 1.0), W, rtol=0, atol=0)
+
+
+def test_kmv_invariances():
+    # the kernel depends on |x - y| / h only: translating both sets, or
+    # scaling points and h together, leaves K W unchanged; K(X, Y) = K(Y, X)^T
+    X = sd.points(11, 5, seed=10).astype(np.float64)
+    Y = sd.points(8, 5, seed=11).astype(np.float64)
+    W = sd.vectors(8, 2, seed=12)
+    ref = cmath.kmv(X, Y, W, 0.9)
+    shift = np.array([3.0, -2.0, 0.5, 7.0, -1.25])
+    np.testing.assert_allclose(cmath.kmv(X + shift, Y + shift, W, 0.9), ref, rtol=1e-12)
+    np.testing.assert_allclose(cmath.kmv(2.5 * X, 2.5 * Y, W, 2.25), ref, rtol=1e-12)
+    KXY = cmath.kmv(X, Y, np.eye(8), 0.9)
+    KYX = cmath.kmv(Y, X, np.eye(11), 0.9)
+    np.testing.assert_allclose(KXY, KYX.T, rtol=0, atol=0)
+
+
+def test_sample_masked_empty_mask_is_the_product():
+    # with every leaf range empty nothing is skipped: the sample is K R
+    X = sd.points(30, 4, seed=13).astype(np.float64)
+    R = sd.random_block(30, 5, seed=2).astype(np.float64)
+    rows = np.array([29, 3, 0, 17])
+    z = np.zeros(30, dtype=np.int64)
+    got = cmath.sample_masked(X, R, 0.6, z, z, rows)
+    np.testing.assert_allclose(got, cmath.kmv(X, X, R, 0.6, rows=rows), rtol=1e-14, atol=1e-15)
