@@ -65,3 +65,27 @@ def test_adjoint_identity():
     lhs = u @ (ok.kernel_dense(X, Y, 1.2) @ v)
     rhs = (ok.kernel_dense(Y, X, 1.2) @ u) @ v
     assert abs(lhs - rhs) < 1e-13
+
+
+def test_val_loss_closed_forms():
+    # training points 100 apart at h = 1: K = I exactly (off-diagonal entries
+    # underflow to 0), so alpha = y / (1 + lambda).  Validating on the training
+    # points gives f = alpha, L = |y / (1 + lambda) - y_v|^2 / m and
+    #   dL/dlog lambda = lambda * sum 2 (f - y_v) (-y / (1 + lambda)^2) / m;
+    # every entry of K and K_v is 0 or 1 (q = 0 or huge), so dK/dh = 0 and
+    # dL/dlog h = 0.  Validation points far from all training points give
+    # K_v = 0, f = 0 and L = |y_v|^2 / m.
+    m, lam = 12, 0.7
+    X = np.arange(m, dtype=np.float64)[:, None] * np.array([[100.0, 0.0, 50.0]])
+    rng = np.random.default_rng(9)
+    y, yv = rng.standard_normal(m), rng.standard_normal(m)
+    f = y / (1 + lam)
+    L_ref = float(np.sum((f - yv) ** 2) / m)
+    gl_ref = lam * float(np.sum(2 * (f - yv) * (-y / (1 + lam) ** 2)) / m)
+    assert abs(og.val_loss(X, y, X, yv, 1.0, lam) - L_ref) <= 1e-15 * max(1.0, L_ref)
+    L, gh, gl = og.val_loss_grad(X, y, X, yv, 1.0, lam)
+    assert abs(L - L_ref) <= 1e-15 * max(1.0, L_ref)
+    assert abs(gl - gl_ref) <= 1e-14 * max(1.0, abs(gl_ref))
+    assert gh == 0.0
+    Xv = X + np.array([[0.0, 1e4, 0.0]])
+    assert abs(og.val_loss(X, y, Xv, yv, 1.0, lam) - float(yv @ yv / m)) <= 1e-15 * float(yv @ yv)
