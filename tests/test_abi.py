@@ -83,3 +83,104 @@ def test_no_device_reported(lib):
     assert L.krr_device_count() == 0
     R = ctypes.c_void_p(1)
     assert L.krr_random_block(1, 4, 4, 0, R, None) == _lib.KRR_E_NODEVICE
+
+
+def _bad_calls(L, _lib):
+    """One invalid call per entry point: (name, thunk, message fragment).  Every
+    pointer the library only tests for NULL is a fake non-NULL address; host
+    arrays it reads (offsets, h, lambda, options, tree tables) are real."""
+    import numpy as np
+    P = ctypes.c_void_p(64)  # never dereferenced before the device check
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    dblp = ctypes.POINTER(ctypes.c_double)
+    keep = []
+
+    def arr(a, dt, ptr):
+        a = np.ascontiguousarray(a, dtype=dt)
+        keep.append(a)
+        return a.ctypes.data_as(ptr)
+
+    nodes = np.array([[0, 5, -1, -1, 2], [5, 10, -1, -1, 2], [0, 10, 0, 1, -1]], dtype=np.int64)
+    tree = ctypes.c_void_p()
+    assert L.krr_tree_from_host(nodes.ctypes.data_as(ctypes.c_void_p), 3, ctypes.byref(tree)) == 0
+    keep.append(tree)
+    good = _lib.HssOpts(1e-2, 0.0, 64, 32, 256, 10, _lib.KRR_F64, 1, 0, 1)
+    bad_r0 = _lib.HssOpts(1e-2, 0.0, 40, 32, 256, 10, _lib.KRR_F64, 1, 0, 1)
+    out = ctypes.c_void_p(99)
+    copts = _lib.ClusterOpts(16, 100, 1)
+    F32, F64 = _lib.KRR_F32, _lib.KRR_F64
+    off_empty = arr([0, 5, 5], np.int64, i64p)
+    off_bad0 = arr([1, 5], np.int64, i64p)
+    off_ok = arr([0, 5], np.int64, i64p)
+    h_neg = arr([-1.0], np.float64, dblp)
+    h_ok = arr([1.0], np.float64, dblp)
+    return keep, tree, out, [
+        ("krr_gather_rows", lambda: L.krr_gather_rows(P, F32, 4, 0, P, P, None), "bad sizes"),
+        ("krr_scatter_rows", lambda: L.krr_scatter_rows(P, F32, -1, 2, P, P, None), "bad sizes"),
+        ("kernel_sample r", lambda: L.kernel_sample(P, 10, 3, F32, 1.0, P, 48, None, None, P, F32, 1, None),
+         "multiple of 32"),
+        ("kernel_sample leaf", lambda: L.kernel_sample(P, 10, 3, F32, 1.0, P, 32, P, None, P, F32, 1, None),
+         "both leaf arrays"),
+        ("krr_random_block", lambda: L.krr_random_block(1, -1, 4, 0, P, None), "bad arguments"),
+        ("kernel_matvec_bwd", lambda: L.kernel_matvec_bwd(P, 3, P, 4, 2, F32, 0.0, P, P, 1, P, P, P, P, F32, None),
+         "h must be positive"),
+        ("hss_compress", lambda: L.hss_compress(tree, P, F64, 2, 1.0, ctypes.byref(bad_r0), None, ctypes.byref(out),
+                                                None), "r0"),
+        ("hss_matvec", lambda: L.hss_matvec(None, P, 1, P, None), "bad arguments"),
+        ("hss_export_sizes", lambda: L.hss_export_sizes(None, None, None, None), "NULL handle"),
+        ("hss_export", lambda: L.hss_export(None, P, P, P, None), "NULL argument"),
+        ("hss_ulv_factor_spd", lambda: L.hss_ulv_factor_spd(P, 1.0, 0.0, None, ctypes.byref(out), None),
+         "pivot_floor"),
+        ("hss_ulv_factor_shifted", lambda: L.hss_ulv_factor_shifted(P, 0.0, None, ctypes.byref(out), None),
+         "lambda must be > 0"),
+        ("hss_ulv_use_graph", lambda: L.hss_ulv_use_graph(None, 1), "NULL factor"),
+        ("hss_solve", lambda: L.hss_solve(P, P, 0, P, None), "nrhs"),
+        ("krr_refine", lambda: L.krr_refine(None, P, 10, F32, 2, 1.0, 1.0, P, 1, P, 1e-6, 10, 7, F64, None, None),
+         "mv_prec"),
+        ("krr_predict", lambda: L.krr_predict(P, 3, P, 4, 2, F32, 1.0, P, 65, P, P, F32, None), "bad sizes"),
+        ("krr_set_tuning knob", lambda: L.krr_set_tuning(99, 1), "unknown knob"),
+        ("krr_set_tuning value", lambda: L.krr_set_tuning(0, 5), "0 to 4"),
+        ("krr_get_tuning", lambda: L.krr_get_tuning(0, None), "bad arguments"),
+        ("krr_dot_columns", lambda: L.krr_dot_columns(P, P, 5, 0, P, None), "bad arguments"),
+        ("krr_tree_size", lambda: L.krr_tree_size(None, None, None), "NULL tree"),
+        ("krr_tree_export", lambda: L.krr_tree_export(None, None, None), "NULL tree"),
+        ("krr_tree_roots", lambda: L.krr_tree_roots(None, None, None), "NULL tree"),
+        ("krr_cluster_2mn_batched", lambda: L.krr_cluster_2mn_batched(P, F32, off_empty, 2, 3, ctypes.byref(copts),
+                                                                      None, P, ctypes.byref(out)), "problem 1 is empty"),
+        ("hss_compress_batched", lambda: L.hss_compress_batched(tree, P, F64, 2, h_neg, ctypes.byref(good), None,
+                                                                ctypes.byref(out), None), "h[0] must be > 0"),
+        ("hss_num_problems", lambda: L.hss_num_problems(None, None), "NULL argument"),
+        ("hss_ulv_factor_batched", lambda: L.hss_ulv_factor_batched(P, None, 0, None, ctypes.byref(out), None),
+         "NULL argument"),
+        ("kernel_sample_batched", lambda: L.kernel_sample_batched(P, F32, off_bad0, 1, 3, h_ok, P, 32, None, None, P,
+                                                                  F32, 1, None), "offsets[0] must be 0"),
+        ("kernel_matvec_batched", lambda: L.kernel_matvec_batched(P, F32, off_ok, 1, 3, h_neg, P, 1, P, F32, None),
+         "h[0] must be positive"),
+        ("krr_refine_batched", lambda: L.krr_refine_batched(None, P, F32, off_ok, 1, 3, h_ok, None, P, 1, P, 1e-6, 10,
+                                                            F32, F64, None, None, None), "NULL lambda"),
+    ]
+
+
+def test_every_entry_point_validates_before_device(lib):
+    # each call is invalid on the host: the library must answer KRR_E_INVAL
+    # with a message naming the fault, before any device call (on a machine
+    # without a GPU a late check would answer KRR_E_NODEVICE instead), and
+    # leave an out-handle NULL
+    from paper_1803_10274_amd import _lib
+    L = _lib.load(LIB)
+    before = ctypes.c_int()
+    assert L.krr_get_tuning(0, ctypes.byref(before)) == 0
+    keep, tree, out, calls = _bad_calls(L, _lib)
+    try:
+        for name, call, frag in calls:
+            out.value = 99
+            rc = call()
+            assert rc == _lib.KRR_E_INVAL, (name, rc, L.krr_last_error())
+            assert frag.encode() in L.krr_last_error(), (name, L.krr_last_error())
+            if "hss_ulv_factor" in name or "compress" in name or "cluster" in name:
+                assert not out.value, name
+    finally:
+        L.krr_tree_destroy(tree)
+    # a rejected tuning value leaves the knob as it was
+    after = ctypes.c_int()
+    assert L.krr_get_tuning(0, ctypes.byref(after)) == 0 and after.value == before.value
