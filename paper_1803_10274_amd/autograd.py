@@ -70,7 +70,18 @@ def _fit_alpha(st, h, lam, opts, tol, max_iter):
     if st.Xp is None:
         st.Xp = gather_rows(st.X, st.tree_perm)
         st.yp = gather_rows(st.y.reshape(-1, 1), st.tree_perm)
-    H = HSS(st.tree, st.Xp, h, opts)
+    # the compression depends on h only (fixed points, options and seed): a new
+    # lambda refactors the one it has.  Kept: the latest and a pinned h's.
+    cache = st.__dict__.setdefault("hss_cache", {})
+    H = cache.get(h)
+    st.compressed = H is None
+    if H is None:
+        H = HSS(st.tree, st.Xp, h, opts)
+        st.n_compress = getattr(st, "n_compress", 0) + 1
+        for k in [k for k in cache if k != getattr(st, "pin_h", None)]:
+            del cache[k]
+        cache[h] = H
+    st.n_fits = getattr(st, "n_fits", 0) + 1
     F = ULV(H, lam, shifted=True)
     a = F.solve(st.yp)
     info = refine(F, st.Xp, h, lam, st.yp, a, tol=tol, max_iter=max_iter, mv_prec=st.prec)
@@ -131,3 +142,63 @@ def validation_loss(log_h, log_lam, X, y, Xv, yv, leaf=128, opts: HssOptions = N
                                                            prec="f16", cap_policy=1)
         st.tol, st.max_iter, st.prec = tol, max_iter, prec
     return ValidationLoss.apply(log_h, log_lam, st), st
+
+
+def tune_hyperparameters(X, y, Xv, yv, h, lam, steps=8, step=0.5, shrink=3, leaf=128, opts: HssOptions = None,
+                         tol=1e-6, max_iter=300, prec="f32", seed=7):
+    """Gradient-driven choice of (h, lambda) by the validation MSE.
+
+    The paper tunes these two by grid search or a black-box tuner, and notes
+    that a new lambda changes only the diagonal while a new h needs a new
+    compression (Section 5.3).  Here the steps alternate between the two
+    coordinates, lambda first.  A lambda step refactors the compressed matrix
+    it already has; an h step recompresses.  Each step moves its coordinate by
+    `step` (log units) against the sign of its adjoint gradient.  It is halved,
+    up to `shrink` times, until the loss falls, and is skipped if it never does.
+    The gradient is taken only at accepted points.
+
+    Returns a dict: h, lam, loss (at the accepted point), n_compress
+    (compressions built), n_fits (factor + refinement runs), and history: one
+    (kind, h, lam, loss, accepted, compressed) per fit, kind "start", "lambda"
+    or "h"."""
+    dev = X.device
+    st = None
+
+    def fit(lh, ll):
+        nonlocal st
+        a = torch.tensor(lh, dtype=torch.float64, device=dev, requires_grad=True)
+        b = torch.tensor(ll, dtype=torch.float64, device=dev, requires_grad=True)
+        L, st = validation_loss(a, b, X, y, Xv, yv, leaf=leaf, opts=opts, tol=tol, max_iter=max_iter, prec=prec,
+                                seed=seed, state=st)
+        return L, a, b
+
+    def grad(L, a, b):
+        L.backward()
+        return a.grad.item(), b.grad.item()
+
+    lh, ll = math.log(h), math.log(lam)
+    L, a, b = fit(lh, ll)
+    st.pin_h = math.exp(lh)
+    loss = L.item()
+    history = [("start", math.exp(lh), math.exp(ll), loss, True, st.compressed)]
+    g = grad(L, a, b)
+    for it in range(steps):
+        k = 1 - it % 2  # index into g: 0 = log h, 1 = log lambda
+        if g[k] == 0.0:
+            continue
+        d = -step if g[k] > 0 else step
+        for _ in range(shrink + 1):
+            cand = (lh + d, ll) if k == 0 else (lh, ll + d)
+            Lc, a, b = fit(*cand)
+            ok = Lc.item() < loss
+            history.append(("h" if k == 0 else "lambda", math.exp(cand[0]), math.exp(cand[1]), Lc.item(), ok,
+                            st.compressed))
+            if ok:
+                lh, ll = cand
+                st.pin_h = math.exp(lh)
+                loss = Lc.item()
+                g = grad(Lc, a, b)
+                break
+            d *= 0.5
+    return {"h": math.exp(lh), "lam": math.exp(ll), "loss": loss, "n_compress": st.n_compress,
+            "n_fits": st.n_fits, "history": history}

@@ -73,3 +73,25 @@ def test_validation_gradient_finite_differences(gpu_lib):
     fl = (f(math.log(p.h), math.log(p.lam) + s) - f(math.log(p.h), math.log(p.lam) - s)) / (2 * s)
     assert abs(lh.grad.item() - fh) <= 2e-3 * abs(fh) + 1e-7
     assert abs(ll.grad.item() - fl) <= 2e-3 * abs(fl) + 1e-7
+
+
+def test_hyperparameter_descent(gpu_lib):
+    # gradient steps on (log h, log lambda) from a poor start: accepted losses
+    # fall, lambda trials refactor without recompressing, a compression is
+    # built only for a new h (an h still cached is reused), and the loss
+    # reported at the end is the oracle's at the final parameters
+    from paper_1803_10274_amd.autograd import tune_hyperparameters
+    p = sd.c5_eight_gaussians(n=2048, m=512)
+    res = tune_hyperparameters(_t(p.X), _t(p.y), _t(p.Xt), _t(p.yt), p.h / 4, p.lam * 8, steps=4, tol=1e-7)
+    hist = res["history"]
+    print("hyperparameter descent:", [(k, round(h, 4), round(l, 4), round(L, 6), ok, c)
+                                      for k, h, l, L, ok, c in hist], flush=True)
+    acc = [e[3] for e in hist if e[4]]
+    assert len(acc) >= 2
+    assert all(b < a for a, b in zip(acc, acc[1:]))
+    assert hist[0][5] and all(not e[5] for e in hist if e[0] == "lambda")
+    assert all(e[1] != prev[1] for prev, e in zip(hist, hist[1:]) if e[5])  # compress only for a new h
+    assert res["n_fits"] == len(hist)
+    assert res["n_compress"] == sum(1 for e in hist if e[5])
+    L_ref = og.val_loss(p.X.astype(np.float64), p.y, p.Xt.astype(np.float64), p.yt, res["h"], res["lam"])
+    assert abs(res["loss"] - L_ref) <= 1e-6 * abs(L_ref)
