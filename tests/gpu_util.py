@@ -33,10 +33,10 @@ def fp32_product_bound(X, Y, W, h, tile=64, safety=4.0, mask=None):
 def fp32_wide_product_bound(X, Y, W, h, panel=128, safety=4.0, anchor=None):
     """Elementwise bound for the FP32-entry product of wide points: exponents
     from the norm expansion on coordinates centred on the mean of Y, each FP32
-    coordinate split into three BF16 terms with six cross products kept, so a
-    dot product sums 6 (d + 2) exact products in FP32 plus the split residue
-    and the dropped products (below u / 2 of the magnitudes):
-    |dt| <= (6 (d + 2) + 1) u (|x'| + |y'|)^2 / (2 h^2) in natural-log units;
+    coordinate split exactly into three BF16 terms with six cross products
+    kept, so a dot product sums 6 (d + 2) exact products in FP32, and the three
+    dropped products (ml, lm, ll) are below 2 u of each product's magnitude:
+    |dt| <= (6 (d + 2) + 2) u (|x'| + |y'|)^2 / (2 h^2) in natural-log units;
     exp2 within 2 ulp, FP32 sums over a panel of `panel` points and FP64 sums
     across panels.  `anchor` replaces the mean of Y as the centre (a batch
     centres every problem on the mean of all its points)."""
@@ -47,7 +47,7 @@ def fp32_wide_product_bound(X, Y, W, h, panel=128, safety=4.0, anchor=None):
     ny = np.linalg.norm(Y - a, axis=1)
     q = sqdist(X, Y)
     K = np.exp(-q / (2 * h * h))
-    T = (6 * (X.shape[1] + 2) + 1) * (nx[:, None] + ny[None, :]) ** 2 / (2 * h * h)
+    T = (6 * (X.shape[1] + 2) + 2) * (nx[:, None] + ny[None, :]) ** 2 / (2 * h * h)
     aW = np.abs(np.asarray(W, dtype=np.float64)).reshape(W.shape[0], -1)
     return safety * U32 * ((panel + 2) * (K @ aW) + (K * T) @ aW)
 
