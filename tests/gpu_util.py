@@ -92,9 +92,9 @@ def fp32_sym_anchored_bound(X, W, h, rows_per_block, tile=64, safety=4.0, form=3
     block's mean point; its FP32 norm expansion (d FMAs per norm, d + 2 terms
     in the matrix-core sum, two constants) is off by at most
     (2 d + 6) u (|x'| + |y'|)^2 / (2 h^2) in natural-log units.  The BF16
-    three-term form (4) adds the split's representation error (2^-24 per
-    operand) and the dropped cross terms below 2^-16 (2^-23 per product):
-    3 d more units.  Entries inside a diagonal block use the FP64 exponent
+    three-term form (4) adds 3 d + 2 units: the split's representation error
+    (counted as 2^-24 per operand, though the split of a normal FP32 value is
+    exact) and the dropped cross terms below 2^-16 (2^-23 per product).  Entries inside a diagonal block use the FP64 exponent
     (fp32_product_bound's terms)."""
     X = np.asarray(X, dtype=np.float64)
     n, d = X.shape
