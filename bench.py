@@ -84,6 +84,8 @@ def parse():
     ap.add_argument("--no-grad", action="store_true", help="skip the gradient leg")
     ap.add_argument("--no-image", action="store_true", help="skip the image-like (d = 784) leg")
     ap.add_argument("--kernels-only", action="store_true", help="one launch of each hot kernel (profiling)")
+    ap.add_argument("--wide-kernels", action="store_true",
+                    help="launches of the wide-point kernel products at the image-like size (profiling)")
     ap.add_argument("--reps", type=int, default=3, help="launches per kernel timing")
     ap.add_argument("--summarize-trace", metavar="CSV",
                     help="print per-(kernel, grid) launch statistics of a rocprofv3 kernel-trace CSV and exit")
@@ -176,6 +178,28 @@ def kernels_only(args):
     print(json.dumps({"kernels_only": True, "n": args.n, "r": args.r0, "copy_bytes": 2 * a.numel() * 4}), flush=True)
 
 
+def wide_kernels(args):
+    """The wide-point kernel products at the image-like size (n = 60,000,
+    d = 784, ten right-hand sides): two launches with FP32 entries (BF16
+    three-term exponents), one with FP64 entries."""
+    import numpy as np
+    import torch
+
+    import paper_1803_10274_amd as krr
+    import synthdata as sd
+    krr.load()
+    dev = torch.device("cuda:0")
+    p = sd.c3_image_like()
+    X = torch.from_numpy(np.ascontiguousarray(p.X, dtype=np.float32)).to(dev)
+    W = torch.from_numpy(sd.vectors(p.n, 10, seed=3)).to(dev)
+    torch.cuda.synchronize()
+    for prec in ("f32", "f32", "f64"):
+        log(f"wide kernel product, {prec} entries")
+        krr.kernel_matvec(X, X, p.h, W, prec=prec)
+        torch.cuda.synchronize()
+    print(json.dumps({"wide_kernels": True, "n": p.n, "d": p.d, "nrhs": 10}), flush=True)
+
+
 def main():
     args = parse()
     if args.summarize_trace:
@@ -185,6 +209,9 @@ def main():
         print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.wide_kernels:
+        wide_kernels(args)
+        return
     if args.kernels_only:
         kernels_only(args)
         return
