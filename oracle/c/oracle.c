@@ -7,6 +7,8 @@
  *   oracle_cluster2mn   recursive two-means ordering and cluster tree
  *                       (Section 4.2 steps 1-3, Section 4.3 "Recursive
  *                       two-means", tree numbered in postorder as in Fig. 3)
+ *   oracle_seeds        the two seeds (and integer weights) the clustering
+ *                       draws for one node, for the tests' distribution pins
  *   oracle_kmv          Out = K(X, Y; h) W, Gaussian kernel of eq. (1.1) formed
  *                       entry by entry from the difference x_i - y_j
  *   oracle_sample_masked  S = K(X, X; h) R with each row's own leaf block
@@ -145,8 +147,14 @@ static void centroids(ctx_t *C, int64_t b, int64_t e) {
     }
 }
 
-/* Returns the size of the left part, or -1 when the fallback split applies. */
-static int64_t two_means(ctx_t *C, int64_t b, int64_t e) {
+/* The two seeds of a node [b, e) (Section 4.3 "Recursive two-means"): the
+ * first uniform over the node, the second drawn with probability proportional
+ * to its distance (not squared) from the first.  The integer weights
+ * w_j = isqrt(floor(q_j 2^(62 - e))) are, up to the floor, the distances
+ * |x_j - x_i1| scaled by 2^(31 - e/2), so the draw is exact and independent of
+ * summation order.  Returns 0 with *i1, *i2 set, or -1 when every point of the
+ * node equals the first seed (the fallback split applies). */
+static int pick_seeds(ctx_t *C, int64_t b, int64_t e, int64_t *i1_out, int64_t *i2_out) {
     int32_t d = C->d;
     int64_t s = e - b;
     int64_t i1 = b + (int64_t)mulhi64(oracle_node_draw(C->seed, b, e, 0), (uint64_t)s);
@@ -156,6 +164,7 @@ static int64_t two_means(ctx_t *C, int64_t b, int64_t e) {
         C->q[p] = sqdist(C->X + p * d, x1, d);
         if (C->q[p] > qmax) qmax = C->q[p];
     }
+    *i1_out = i1;
     if (qmax == 0.0) return -1;
     int ex;
     frexp(qmax, &ex);
@@ -174,6 +183,16 @@ static int64_t two_means(ctx_t *C, int64_t b, int64_t e) {
         acc += C->w[p];
         if (acc > u) { i2 = p; break; }
     }
+    *i2_out = i2;
+    return 0;
+}
+
+/* Returns the size of the left part, or -1 when the fallback split applies. */
+static int64_t two_means(ctx_t *C, int64_t b, int64_t e) {
+    int32_t d = C->d;
+    int64_t s = e - b;
+    int64_t i1, i2;
+    if (pick_seeds(C, b, e, &i1, &i2) < 0) return -1;
     memcpy(C->c0, C->X + i1 * d, sizeof(double) * d);
     memcpy(C->c1, C->X + i2 * d, sizeof(double) * d);
     int64_t n1 = assign(C, b, e, C->lab);
@@ -263,6 +282,31 @@ int64_t oracle_cluster2mn(const double *X, int64_t n, int32_t d, int32_t leaf,
     free(C.X); free(C.tmp_row); free(C.tmp_idx); free(C.lab); free(C.lab_new);
     free(C.q); free(C.w); free(cbuf);
     return C.n_nodes;
+}
+
+/*
+ * The seed pick of one node [b, e) of X (n x d FP64) under `seed`, exposed so
+ * that tests observe the draw the clustering actually makes.
+ * seeds (out, 2): i1, i2 (i2 = -1 when the fallback split applies).
+ * weights (out, optional, n): the integer weights w_j at positions [b, e).
+ * Returns 0, -1 on invalid arguments, -2 on allocation failure.
+ */
+int oracle_seeds(const double *X, int64_t n, int32_t d, int64_t b, int64_t e,
+                 uint64_t seed, int64_t *seeds, uint64_t *weights) {
+    if (b < 0 || e > n || e - b < 1 || d < 1) return -1;
+    ctx_t C;
+    memset(&C, 0, sizeof C);
+    C.n = n; C.d = d; C.seed = seed;
+    C.X = (double *)X;
+    C.q = malloc(sizeof(double) * n);
+    C.w = calloc((size_t)n, sizeof(uint64_t));
+    if (!C.q || !C.w) { free(C.q); free(C.w); return -2; }
+    int64_t i1 = -1, i2 = -1;
+    if (pick_seeds(&C, b, e, &i1, &i2) < 0) i2 = -1;
+    seeds[0] = i1; seeds[1] = i2;
+    if (weights) memcpy(weights + b, C.w + b, sizeof(uint64_t) * (size_t)(e - b));
+    free(C.q); free(C.w);
+    return 0;
 }
 
 /* Out[i, c] = sum_j exp(-||x_i - y_j||^2 / (2 h^2)) W[j, c], all FP64.

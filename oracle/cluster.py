@@ -66,6 +66,25 @@ def cluster2mn(X, leaf, seed, max_iter=100):
     return Tree(perm, nodes[:cnt].copy(), int(stats[0]), int(stats[1]), int(stats[2]))
 
 
+def seeds(X, b, e, seed):
+    """The two seeds (i1, i2) and the integer weights (positions b..e-1) that
+    the clustering draws for node [b, e) of X; i2 = -1 means the fallback split
+    (all points equal the first seed).  Exposed so tests observe the draw."""
+    Xd = np.ascontiguousarray(np.asarray(X).astype(np.float64))
+    if Xd.ndim == 1:
+        Xd = Xd[:, None]
+    n, d = Xd.shape
+    out = np.empty(2, dtype=np.int64)
+    w = np.zeros(n, dtype=np.uint64)
+    rc = lib().oracle_seeds(Xd.ctypes.data_as(ctypes.c_void_p), n, d, int(b), int(e),
+                            ctypes.c_uint64(seed & (2**64 - 1)),
+                            out.ctypes.data_as(ctypes.c_void_p),
+                            w.ctypes.data_as(ctypes.c_void_p))
+    if rc != 0:
+        raise ValueError(f"oracle_seeds: invalid node [{b}, {e}) or allocation failure ({rc})")
+    return int(out[0]), int(out[1]), w[b:e].copy()
+
+
 def node_draw(seed, b, e, k):
     """The counter-based draw the 2MN seeding uses (exposed for tests)."""
     return int(lib().oracle_node_draw(seed & (2**64 - 1), b, e, k))

@@ -131,30 +131,62 @@ def test_degenerate_inputs():
     check_tree(t, 33, 1)
 
 
-def test_second_seed_distribution_follows_distance():
-    # 1-D node of 3 points at 0, 1, 3 with the first seed forced to be the
-    # point at 0 by construction: weights ~ distance 0 : 1 : 3.  Empirical
-    # frequency of the second seed over many node ranges / seeds.
-    counts = {1: 0, 3: 0}
-    trials = 3000
-    for s in range(trials):
-        draw0 = oc.node_draw(s, 0, 3, 0)
-        i1 = (draw0 * 3) >> 64
-        pts = np.array([0.0, 1.0, 3.0])
-        q = (pts - pts[i1]) ** 2
-        qmax = q.max()
-        ex = math.frexp(qmax)[1]
-        w = [math.isqrt(int(math.floor(math.ldexp(v, 62 - ex)))) for v in q]
-        W = sum(w)
-        u = (oc.node_draw(s, 0, 3, 1) * W) >> 64
-        acc, i2 = 0, 2
-        for j in range(3):
-            acc += w[j]
-            if acc > u:
-                i2 = j
-                break
+def test_second_seed_weights_hand_computed():
+    # Node of three 1-D points at 0, 1, 3 (Section 4.3: the second seed is
+    # drawn proportionally to the distance from the first).  With the first
+    # seed at 0: q = (0, 1, 9), qmax = 9 = 0.5625 * 2^4, so the weights are
+    # isqrt(q * 2^58) = (0, 2^29, 3 * 2^29), exactly the distances 0 : 1 : 3.
+    # Squared-distance weights would give 0 : 1 : 9.
+    pts = np.array([0.0, 1.0, 3.0])
+    for s in range(200):
+        i1, i2, w = oc.seeds(pts, 0, 3, s)
         if i1 == 0:
-            counts[int(pts[i2])] += 1
-    tot = counts[1] + counts[3]
-    assert tot > 500
-    assert abs(counts[3] / tot - 0.75) < 0.06
+            assert list(w) == [0, 2**29, 3 * 2**29]
+            break
+    else:
+        pytest.fail("no seed put the first centre at position 0")
+    # First seed at 1 (x = 1): q = (1, 0, 4), qmax = 4 = 0.5 * 2^3, shift 59:
+    # weights (2^29.5 floored, 0, 2^30.5 floored) = (isqrt(2^59), 0, isqrt(2^61)).
+    # isqrt(2^59) = floor(2^29 sqrt 2) = 759250124 (2^29 * 1.41421356237 =
+    # 759250124.99), isqrt(2^61) = floor(2^30 sqrt 2) = 1518500249.
+    for s in range(200):
+        i1, i2, w = oc.seeds(pts, 0, 3, s)
+        if i1 == 1:
+            assert list(w) == [759250124, 0, 1518500249]
+            break
+    else:
+        pytest.fail("no seed put the first centre at position 1")
+    # Every point equal: no second seed (the fallback split applies).
+    i1, i2, w = oc.seeds(np.zeros((5, 2)), 0, 5, 7)
+    assert 0 <= i1 < 5 and i2 == -1 and not w.any()
+
+
+def test_second_seed_distribution_follows_distance():
+    # Tally the seeds the C oracle itself draws on the node 0 / 1 / 3 over
+    # many seeds.  Conditional on the first seed, the second seed lands on
+    # each other point with probability distance / (sum of distances):
+    #   first at 0: P(3) = 3 / 4   (squared distance would give 9 / 10)
+    #   first at 1: P(3) = 2 / 3   (squared: 4 / 5)
+    #   first at 3: P(0) = 3 / 5   (squared: 9 / 13)
+    pts = np.array([0.0, 1.0, 3.0])
+    hits = {0: [0, 0], 1: [0, 0], 2: [0, 0]}   # first seed -> [draws, hits]
+    target = {0: 2, 1: 2, 2: 0}
+    for s in range(6000):
+        i1, i2, _ = oc.seeds(pts, 0, 3, s)
+        assert i2 != i1 and 0 <= i2 < 3
+        hits[i1][0] += 1
+        hits[i1][1] += int(i2 == target[i1])
+    for i1, p in ((0, 3 / 4), (1, 2 / 3), (2, 3 / 5)):
+        n, k = hits[i1]
+        assert n > 1500
+        sigma = math.sqrt(p * (1 - p) / n)
+        assert abs(k / n - p) < 4.5 * sigma, (i1, k / n, p)
+    # The same node embedded in a bigger array draws within its own range.
+    big = np.concatenate([np.full(4, 50.0), pts, np.full(2, -9.0)])
+    # The counter key includes (b, e), so the draws differ from the node at 0,
+    # but the weights depend only on the node's own points.
+    for s in range(50):
+        i1, i2, w = oc.seeds(big, 4, 7, s)
+        assert 4 <= i1 < 7 and 4 <= i2 < 7 and i2 != i1
+        if i1 == 4:
+            assert list(w) == [0, 2**29, 3 * 2**29]
