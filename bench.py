@@ -32,6 +32,7 @@ sys.path.insert(0, ROOT)
 # MI355X published dense peaks (FLOP/s)
 PEAK = {"f16": 2.5e15, "bf16": 2.5e15, "f32": 157.3e12, "f64": 78.6e12}
 PEAK_FP64_VECTOR = 78.6e12
+PEAK_F32_VECTOR = 157.3e12
 # transcendental (v_exp_f32) issue at a quarter of the lane rate: 256 CUs x 64 lanes x 2.4 GHz / 4
 PEAK_EXP2 = 256 * 64 * 2.4e9 / 4
 
@@ -66,6 +67,42 @@ def pmc_traffic(kind, n, r=None):
     return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
 
 
+# Executed matrix-core work per launch from hardware counters
+# (SQ_INSTS_VALU_MFMA_MOPS_* count matrix-core math operations in units of
+# 512; SQ_VALU_MFMA_BUSY_CYCLES and GRBM_GUI_ACTIVE give the busy share), from
+# `rocprofv3 --pmc` runs of `bench.py --kernels-only`; valid only while the
+# kernel's source file is unchanged (sha256), otherwise reported as null.
+PMC_MFMA = {}
+
+
+def pmc_mfma(kind, n, r, launch_s):
+    """Counter-based matrix-core figures for one launch, or nulls."""
+    import hashlib
+    t = PMC_MFMA.get(kind)
+    none = {"executed_mfma_tflops": None, "executed_mfma_frac": None, "mfma_busy_frac": None}
+    if t is None or t["n"] != n or (t["r"] is not None and t["r"] != r):
+        return none
+    with open(os.path.join(ROOT, t["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != t["sha256"]:
+            return none
+    ops = 512.0 * sum(t["mops"].values())
+    peak = sum(PEAK[k] * v for k, v in t["mops"].items()) / max(sum(t["mops"].values()), 1e-30)
+    return {"executed_mfma_tflops": ops / launch_s / 1e12, "executed_mfma_frac": ops / launch_s / peak,
+            "mfma_busy_frac": t.get("mfma_busy_frac"), "valu_busy_frac": t.get("valu_busy_frac"),
+            "mfma_counters": t["profile"]}
+
+
+def fp64_relres(krr, res, y, p):
+    """The fitted coefficients' relative residual recomputed with the FP64
+    kernel product (the library's own FP64 kernel; the CPU oracle certifies
+    the same coefficients separately from a dump)."""
+    import torch
+    yp = krr.gather_rows(y.reshape(-1, 1).contiguous(), res.perm)
+    a64 = res.alpha_perm.reshape(-1, 1).contiguous()
+    r64 = yp - krr.kernel_matvec(res.Xp, res.Xp, p.h, a64, prec="f64") - p.lam * a64
+    return float(torch.linalg.norm(r64) / torch.linalg.norm(yp))
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +115,15 @@ def parse():
     ap.add_argument("--rtol", type=float, default=1e-2)
     ap.add_argument("--r0", type=int, default=256)
     ap.add_argument("--atol", type=float, default=6.0)
+    ap.add_argument("--r-max", type=int, default=4096, help="largest sample width adaptive growth may reach")
+    ap.add_argument("--cap-policy", type=int, default=0,
+                    help="at r_max: 0 fails with a rank-cap error, 1 truncates every rank")
+    ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner before the fits")
+    ap.add_argument("--tune-dir", default=os.path.join(ROOT, "gpurun_out"),
+                    help="where the autotuner's cache file is written")
+    ap.add_argument("--dump-alpha", metavar="DIR",
+                    help="write the fitted coefficients (original order) of the headline and image-like fits "
+                         "to DIR for certification by the CPU oracle")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-sampling comparison fit")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-problem batched leg")
@@ -228,11 +274,22 @@ def main():
     y = torch.from_numpy(p.y).to(dev)
     Xt = torch.from_numpy(p.Xt).to(dev)
     torch.cuda.synchronize()
-    opts = krr.HssOptions(rtol=args.rtol, atol=args.atol, r0=args.r0, dr=args.r0, r_max=args.r0, prec=args.prec,
-                          split_terms=args.split, cap_policy=1)
+    opts = krr.HssOptions(rtol=args.rtol, atol=args.atol, r0=args.r0, dr=args.r0, r_max=args.r_max,
+                          prec=args.prec, split_terms=args.split, cap_policy=args.cap_policy)
+    tune_cache = None
+    if not args.no_tune:
+        # launch shapes for this point width and sample width, chosen by the
+        # autotuner at the workload's own size before anything is timed (the
+        # best column chunk of the symmetric product depends on n)
+        from paper_1803_10274_amd import tune
+        tune_cache = os.path.join(args.tune_dir, "tune.json")
+        log("autotuning launch shapes")
+        tune.autotune(p.d, r=args.r0, prec=args.prec, n=args.n, split_terms=args.split, reps=2, path=tune_cache)
+        log(f"tuned: {json.load(open(tune_cache))}")
 
     def step(o):
-        res = krr.fit(X, y, p.h, p.lam, leaf=p.leaf, opts=o, tol=1e-6, max_iter=300, raise_on_fail=False)
+        res = krr.fit(X, y, p.h, p.lam, leaf=p.leaf, opts=o, tol=1e-6, max_iter=300, raise_on_fail=False,
+                      tune_cache=tune_cache)
         torch.cuda.synchronize()
         t_fit = time.perf_counter()
         _, lab = krr.predict(Xt, res.Xp, p.h, res.alpha_perm)
@@ -264,13 +321,14 @@ def main():
     # FP32-sampling comparison fit, same data, tree, lambda and tolerance
     fp32 = None
     if not args.no_fp32:
-        o32 = krr.HssOptions(rtol=args.rtol, atol=args.atol, r0=args.r0, dr=args.r0, r_max=args.r0, prec="f32",
-                             cap_policy=1)
+        o32 = krr.HssOptions(rtol=args.rtol, atol=args.atol, r0=args.r0, dr=args.r0, r_max=args.r_max, prec="f32",
+                             cap_policy=args.cap_policy)
         t0 = time.perf_counter()
         r32, _, t_fit32 = step(o32)
         fp32 = {"fit_s": t_fit32 - t0, "phases": r32.info["phases"], "t_sample_ms": r32.info["hss"]["t_sample_ms"],
                 "refine_iterations": r32.info["refine"]["iterations"],
                 "relres": r32.info["refine"]["relres"][0], "r_final": r32.info["hss"]["r_final"]}
+        fp32["relres_fp64"] = fp64_relres(krr, r32, y, p)
         log(f"fp32 fit: {fp32}")
         del r32
 
@@ -280,63 +338,69 @@ def main():
     R = krr.random_block(1, n, r)
     Xp = res.Xp
     lb, le = leaf_arrays(res.tree.nodes, n, dev)
+    log("timing the sampling product")
     t_sample = time_launches(lambda: krr.kernel_sample(Xp, p.h, R, lb, le, prec=args.prec, split_terms=args.split),
                              args.reps)
     flops = float(n) * n * (2 * p.d + 2 * r)
     achieved = flops / t_sample
     peak = PEAK[args.prec if args.prec in PEAK else "f16"]
-    executed = achieved * (args.split if args.prec in ("f16", "bf16") else 1)
     roof_sample = {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
                    "frac": achieved / peak, "traffic": pmc_traffic("sampling", n, r),
                    "kernel": "k_sample_mfma (sampling product S = K R)",
-                   "launch_s": t_sample, "algorithmic_flops": flops, "executed_mfma_frac": executed / peak}
+                   "launch_s": t_sample, "algorithmic_flops": flops,
+                   "flops_basis": "n^2 (2d + 2r): one distance dot product and one row of K R per kernel entry"}
+    roof_sample.update(pmc_mfma("sampling", n, r, t_sample))
     del R
     w = res.alpha_perm.reshape(n, -1)[:, :1].contiguous()
+    log("timing the refinement kernel product")
     t_mv = time_launches(lambda: krr.kernel_matvec(Xp, Xp, p.h, w, prec="f32"), args.reps)
-    mv_flops = float(n) * n * (2 * p.d + 2)
-    # the symmetric product evaluates each off-diagonal entry once (1024-row
-    # diagonal blocks in full): the executed share of the algorithmic work
+    # The symmetric product evaluates each off-diagonal entry once and the
+    # 1024-row diagonal blocks in full; the unit of work is an evaluated entry
+    # (2d + 2 flops for its exponent, one exp2), priced against the FP32
+    # vector peak, with the exp2 issue floor of the same entries beside it.
     rb = 1024
-    executed_entries = n * rb + (float(n) * n - n * rb) / 2
-    # the product's floor: one exp2 per entry of K (n^2 of them) at the
-    # quarter-rate transcendental peak, each entry carrying 2d + 2 flops
-    mv_peak = PEAK_EXP2 * (2 * p.d + 2)
+    evaluated = n * rb + (float(n) * n - n * rb) / 2
+    mv_flops = evaluated * (2 * p.d + 2)
     form = krr.get_tuning("symmetric")
     mv_kernel = {4: "k_kmv_symb (refinement product K w over K's upper triangle: FP32-accurate exponents from "
-                    "three-term BF16 splits on the matrix cores, re-centred per row block, FP32 entries; with its "
-                    "diagonal-block, anchor and reduction launches)",
+                    "three-term BF16 splits on the matrix cores, re-centred per row block, FP32 entries; timed "
+                    "with its diagonal-block, anchor and reduction launches)",
                  3: "k_kmv_symf (refinement product K w over K's upper triangle: FP32 exponents on the matrix "
-                    "cores, re-centred per row block, FP32 entries; with its diagonal-block, anchor and reduction "
-                    "launches)"}.get(form, "k_kmv_sym (refinement product K w over K's upper triangle, FP64 "
-                                           "exponent, FP32 entries; with its diagonal-block and reduction launches)")
-    roof_mv = {"bound": "alu", "achieved": mv_flops / t_mv / 1e12, "peak": mv_peak / 1e12,
-               "unit": "TFLOP/s", "frac": mv_flops / t_mv / mv_peak,
+                    "cores, re-centred per row block, FP32 entries; timed with its diagonal-block, anchor and "
+                    "reduction launches)"}.get(form, "k_kmv_sym (refinement product K w over K's upper triangle, "
+                                                    "FP64 exponent, FP32 entries; timed with its diagonal-block "
+                                                    "and reduction launches)")
+    roof_mv = {"bound": "alu", "achieved": mv_flops / t_mv / 1e12, "peak": PEAK_F32_VECTOR / 1e12,
+               "unit": "TFLOP/s", "frac": mv_flops / t_mv / PEAK_F32_VECTOR,
                "traffic": pmc_traffic("kernel_product", n),
                "kernel": mv_kernel, "launch_s": t_mv,
-               "peak_basis": "n^2 exp2 at 256 CU x 64 lanes x 2.4 GHz / 4 = 9.83e12 exp2/s, x (2d + 2) flops "
-                             "per entry",
-               "algorithmic_flops": mv_flops, "entries_per_s": float(n) * n / t_mv,
-               "exp2_floor_s": float(n) * n / PEAK_EXP2,
-               "evaluated_entries_frac": executed_entries / (float(n) * n)}
-    # the fitted coefficients' residual recomputed with the FP64 product
-    yp = krr.gather_rows(y.reshape(-1, 1).contiguous(), res.perm)
-    a64 = res.alpha_perm.reshape(-1, 1).contiguous()
-    r64 = yp - krr.kernel_matvec(Xp, Xp, p.h, a64, prec="f64") - p.lam * a64
-    relres_fp64 = float(torch.linalg.norm(r64) / torch.linalg.norm(yp))
-    del r64, yp, a64
+               "peak_basis": "FP32 vector peak 157.3 TFLOP/s (256 CU x 128 lanes x 2 flops x 2.4 GHz)",
+               "flops_basis": "(2d + 2) flops per evaluated kernel entry; evaluated entries = n x 1024 + "
+                              "(n^2 - n x 1024) / 2 (upper triangle plus full 1024-row diagonal blocks)",
+               "evaluated_entries": evaluated, "evaluated_entries_frac": evaluated / (float(n) * n),
+               "algorithmic_flops": mv_flops, "entries_per_s": evaluated / t_mv,
+               "exp2_floor_frac": evaluated / PEAK_EXP2 / t_mv,
+               "exp2_floor_basis": "one exp2 per evaluated entry at 256 CU x 64 lanes x 2.4 GHz / 4 = "
+                                   "9.83e12 exp2/s"}
+    roof_mv.update(pmc_mfma("kernel_product", n, None, t_mv))
+    relres_fp64 = fp64_relres(krr, res, y, p)
     log(f"FP64 relative residual of the fitted coefficients: {relres_fp64:.3e}")
     log(f"sampling {t_sample * 1e3:.1f} ms ({achieved / 1e12:.1f} TFLOP/s); "
-        f"kernel product {t_mv * 1e3:.1f} ms ({mv_flops / t_mv / 1e12:.1f} TFLOP/s)")
+        f"kernel product {t_mv * 1e3:.1f} ms ({mv_flops / t_mv / 1e12:.1f} TFLOP/s evaluated)")
+    if args.dump_alpha:
+        os.makedirs(args.dump_alpha, exist_ok=True)
+        np.save(os.path.join(args.dump_alpha, "alpha_sixteen_gaussians.npy"), res.alpha.cpu().numpy())
     # the step's dominant kernel: the one whose phase takes longer
     ph = res.info["phases"]
     mv_dominant = ph.get("refine", 0.0) > ph.get("compress", 0.0)
     roofline = roof_mv if mv_dominant else roof_sample
+    cert = {"r_final": hs["r_final"], "iterations": rf["iterations"]}
     del res
 
     batched = None if args.no_batched else batched_leg()
     grad = None if args.no_grad else grad_leg()
-    image = None if args.no_image else image_leg()
-    cpu = None if args.no_cpu else cpu_baseline(p)
+    image = None if args.no_image else image_leg(args.dump_alpha)
+    cpu = None if args.no_cpu else cpu_baseline(p, cert)
 
     out = {
         "metric": "KRR fit s at n=1M d=8: mixed vs FP32 HSS at equal acc; sample TFLOP/s",
@@ -352,8 +416,10 @@ def main():
         "dtype": f"{args.prec}-split{args.split}/f32/f64",
         "data": "synthetic",
         "config": {"workload": f"sixteen_gaussians n={n} d={p.d} h={p.h} lambda={p.lam} leaf={p.leaf} "
-                               f"rtol={args.rtol} atol={args.atol} r={args.r0} test_m={args.m}",
-                   "sampling": args.prec, "split_terms": args.split},
+                               f"rtol={args.rtol} atol={args.atol} r0={args.r0} dr={args.r0} r_max={args.r_max} "
+                               f"cap_policy={args.cap_policy} test_m={args.m}",
+                   "sampling": args.prec, "split_terms": args.split, "r0": args.r0, "r_max": args.r_max,
+                   "cap_policy": args.cap_policy, "autotuned": tune_cache is not None},
         "fit_s_min": float(np.min(fit_times)),
         "phases_s": ph,
         "fp32": fp32,
@@ -433,7 +499,7 @@ def grad_leg():
     return out
 
 
-def image_leg():
+def image_leg(dump=None):
     """The image-like workload at full size (n = 60,000, d = 784, ten
     one-vs-all right-hand sides): FP16 2-term sampling on the matrix cores
     (wide-point GEMM kernel), mixed-precision refinement (FP32-entry products,
@@ -454,6 +520,9 @@ def image_leg():
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     _, lab = krr.predict(torch.from_numpy(p.Xt).cuda(), res.Xp, p.h, res.alpha_perm)
+    if dump:
+        os.makedirs(dump, exist_ok=True)
+        np.save(os.path.join(dump, "alpha_image_like.npy"), res.alpha.cpu().numpy())
     out = {"workload": f"image_like n={p.n} d={p.d} classes=10 h={p.h} lambda={p.lam}", "fit_s": t,
            "phases_s": res.info["phases"], "refine_iterations": res.info["refine"]["iterations"],
            "relres_fp64_max": float(max(res.info["refine"]["relres"])),
@@ -463,34 +532,76 @@ def image_leg():
     return out
 
 
-def cpu_baseline(p):
-    """The oracle on a bounded sample: dense FP64 KRR (form K, Cholesky, solve)
-    at n_s = 8192 points of the same workload, timed on the host, scaled to
-    n = 2^20 by the O(n^3) Cholesky cost (and its O(n^2) forming cost)."""
-    import numpy as np
-
-    from oracle import kernel as ok
-    n_s = 8192
-    Xs = p.X[:n_s].astype(np.float64)
-    ys = p.y[:n_s]
-    t0 = time.perf_counter()
-    K = ok.kernel_dense(Xs, Xs, p.h)
-    t1 = time.perf_counter()
-    ok.krr_solve_dense(K, ys, p.lam)
-    t2 = time.perf_counter()
-    scale = p.n / n_s
-    est = (t1 - t0) * scale ** 2 + (t2 - t1) * scale ** 3
+def cpu_info():
+    """Host cores this process may use, and the CPU model."""
     try:
         cores = len(os.sched_getaffinity(0))
     except AttributeError:
         cores = os.cpu_count()
-    # the BLAS behind the Cholesky uses at most OMP_NUM_THREADS threads
+    # the oracle's OpenMP loops use at most OMP_NUM_THREADS threads
     if os.environ.get("OMP_NUM_THREADS", "").isdigit():
         cores = min(cores, int(os.environ["OMP_NUM_THREADS"]))
-    return {"value": est, "unit": "s", "cores": cores, "kind": "oracle",
-            "sample": f"dense FP64 KRR fit (kernel_dense + Cholesky) on the first {n_s} points, "
-                      f"measured form {t1 - t0:.2f} s + solve {t2 - t1:.2f} s, scaled to n={p.n} by "
-                      "n^2 (forming) and n^3 (Cholesky)"}
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return cores, os.cpu_count(), model
+
+
+def cpu_baseline(p, cert):
+    """The oracle timed on the host on bounded samples of the headline
+    workload, extrapolated (labelled as such) to the GPU fit's dominant work:
+      - the 2MN clustering of all n points, single-threaded (measured in full);
+      - the FP64 matrix-free product K w (all host cores) on 2048 rows x all n
+        columns, extrapolated linearly in rows to one full product;
+      - the sampling pass S = K R with r columns (all host cores) on 64 rows x
+        all n columns, extrapolated linearly in rows to the whole pass.
+    value = clustering + one sampling pass + one product per refinement
+    iteration of the GPU fit (the same algorithm's dominant work, in seconds)."""
+    import numpy as np
+
+    import synthdata as sd
+    from oracle import cluster as oc, cmath
+    cores, nproc, model = cpu_info()
+    log("cpu baseline: oracle 2MN")
+    t0 = time.perf_counter()
+    tree = oc.cluster2mn(p.X, p.leaf, 7)
+    t_cluster = time.perf_counter() - t0
+    Xp = np.ascontiguousarray(p.X[tree.perm], dtype=np.float64)
+    n = p.n
+    rows = np.arange(0, n, n // 2048)[:2048]
+    w = sd.vectors(n, 1, seed=3)
+    log("cpu baseline: oracle FP64 kernel product rows")
+    t0 = time.perf_counter()
+    cmath.kmv(Xp, Xp, w, p.h, rows=rows)
+    t_rows = time.perf_counter() - t0
+    t_product = t_rows * n / rows.shape[0]
+    r = cert["r_final"]
+    srows = np.arange(0, n, n // 64)[:64]
+    R = sd.random_block(n, r, seed=1)
+    lb, le = tree.leaf_ranges_per_point()
+    log("cpu baseline: oracle sampling rows")
+    t0 = time.perf_counter()
+    cmath.sample_masked(Xp, R, p.h, lb, le, srows)
+    t_srows = time.perf_counter() - t0
+    t_pass = t_srows * n / srows.shape[0]
+    iters = int(cert["iterations"])
+    value = t_cluster + t_pass + iters * t_product
+    return {"value": value, "unit": "s", "cores": cores, "kind": "oracle",
+            "sample": f"oracle 2MN of all {n} points (1 thread, measured {t_cluster:.1f} s); FP64 matrix-free "
+                      f"K w on {rows.shape[0]} rows x {n} columns ({cores} threads, {t_rows:.2f} s, extrapolated "
+                      f"to {t_product:.0f} s per product); FP64 sample K R, r = {r}, on {srows.shape[0]} rows "
+                      f"({cores} threads, {t_srows:.2f} s, extrapolated to {t_pass:.0f} s per pass); value = "
+                      f"clustering + one pass + {iters} products (the GPU fit's refinement iterations), "
+                      "extrapolated",
+            "cluster_s": t_cluster, "product_s_extrapolated": t_product, "sampling_pass_s_extrapolated": t_pass,
+            "product_entries_per_s": rows.shape[0] * float(n) / t_rows,
+            "nproc": nproc, "cpu_model": model}
 
 
 if __name__ == "__main__":

@@ -36,6 +36,8 @@ def lib():
             _lib.oracle_kmv.argtypes = [vp, vp, i64, i32, dbl, vp, i32, vp, i64, vp]
             _lib.oracle_sample_masked.restype = None
             _lib.oracle_sample_masked.argtypes = [vp, i64, i32, dbl, vp, i32, vp, vp, vp, i64, vp]
+            _lib.oracle_order.restype = i64
+            _lib.oracle_order.argtypes = [vp, i64, i32, i32, i32, vp, vp, vp]
             _lib.oracle_seeds.restype = ctypes.c_int
             _lib.oracle_seeds.argtypes = [vp, i64, i32, i64, i64, u64, vp, vp]
             _lib.oracle_node_draw.restype = u64

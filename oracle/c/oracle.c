@@ -7,6 +7,8 @@
  *   oracle_cluster2mn   recursive two-means ordering and cluster tree
  *                       (Section 4.2 steps 1-3, Section 4.3 "Recursive
  *                       two-means", tree numbered in postorder as in Fig. 3)
+ *   oracle_order        the NP, KD and PCA orderings of Section 4.3 with
+ *                       their cluster trees (readings at the function)
  *   oracle_seeds        the two seeds (and integer weights) the clustering
  *                       draws for one node, for the tests' distribution pins
  *   oracle_kmv          Out = K(X, Y; h) W, Gaussian kernel of eq. (1.1) formed
@@ -281,6 +283,202 @@ int64_t oracle_cluster2mn(const double *X, int64_t n, int32_t d, int32_t leaf,
     stats[0] = C.fallbacks; stats[1] = C.capped; stats[2] = C.iterations;
     free(C.X); free(C.tmp_row); free(C.tmp_idx); free(C.lab); free(C.lab_new);
     free(C.q); free(C.w); free(cbuf);
+    return C.n_nodes;
+}
+
+/* ------------------------------------------------------------------------
+ * The other orderings of Section 4.3 ("Selected Preprocessing Methods"),
+ * each a recursive split of [b, e) while its size exceeds the leaf size, the
+ * left part first, the split stable (relative order kept), the tree numbered
+ * in postorder.  Readings where the paper is silent:
+ *   NP   no reordering: the left part is the first floor(size / 2) positions.
+ *   KD   the coordinate of maximum spread (max - min over the node, lowest
+ *        index on ties); its mean (chunked sum as the 2MN centroids, divided
+ *        by the size); left = points with coordinate <= mean.  When
+ *        100 * min(left, right) < max(left, right) (the paper's imbalance
+ *        test, applied to either side) the split falls back to the median:
+ *        the left part is the floor(size / 2) points first in the order of
+ *        (coordinate, position).  Zero spread splits into halves.
+ *   PCA  mean point mu (chunked sums); the first principal direction v by
+ *        PCA_ITERS power iterations v <- C v / |C v| with C the (unscaled)
+ *        scatter matrix of the node, applied as sum_j (x_j - mu) t_j with
+ *        t_j = (x_j - mu) . v, from v0 = (1, ..., 1); projections
+ *        p_j = (x_j - mu) . v and their chunked mean m; left = p_j <= m.
+ *        An empty side or |C v| = 0 splits into halves.
+ * Every sum runs in the written order with no fused multiply-add.
+ * ---------------------------------------------------------------------- */
+#define PCA_ITERS 32
+enum { ORDER_NP = 1, ORDER_KD = 2, ORDER_PCA = 3 };
+
+typedef struct {
+    ctx_t *C;
+    int method;
+    double *mu, *v, *wv, *acc, *key;
+    int64_t median_splits;
+} octx_t;
+
+/* sum over positions [b, e) of f(p) in the fixed chunked order */
+static double chunked_sum(const double *val, int64_t b, int64_t e) {
+    double s = 0.0;
+    for (int64_t cs = b; cs < e; cs += CHUNK) {
+        int64_t ce = cs + CHUNK < e ? cs + CHUNK : e;
+        double part = 0.0;
+        for (int64_t p = cs; p < ce; ++p) part = part + val[p];
+        s = s + part;
+    }
+    return s;
+}
+
+static int cmp_key_pos(const void *a, const void *b, const double *key) {
+    int64_t i = *(const int64_t *)a, j = *(const int64_t *)b;
+    if (key[i] < key[j]) return -1;
+    if (key[i] > key[j]) return 1;
+    return (i > j) - (i < j);
+}
+
+static const double *g_sort_key;
+static int cmp_idx(const void *a, const void *b) { return cmp_key_pos(a, b, g_sort_key); }
+
+/* Labels for a KD split of [b, e): 0 = left.  Returns the left size, or -1
+ * for the halves fallback. */
+static int64_t kd_labels(octx_t *O, int64_t b, int64_t e) {
+    ctx_t *C = O->C;
+    int32_t d = C->d;
+    int64_t s = e - b;
+    int32_t kbest = 0;
+    double best = -1.0;
+    for (int32_t k = 0; k < d; ++k) {
+        double lo = C->X[b * d + k], hi = lo;
+        for (int64_t p = b; p < e; ++p) {
+            double v = C->X[p * d + k];
+            if (v < lo) lo = v;
+            if (v > hi) hi = v;
+        }
+        double spread = hi - lo;
+        if (spread > best) { best = spread; kbest = k; }
+    }
+    if (!(best > 0.0)) return -1;
+    for (int64_t p = b; p < e; ++p) O->key[p] = C->X[p * d + kbest] + 0.0;  /* -0 becomes +0 */
+    double mean = chunked_sum(O->key, b, e) / (double)s;
+    int64_t n0 = 0;
+    for (int64_t p = b; p < e; ++p) {
+        C->lab[p] = O->key[p] <= mean ? 0 : 1;
+        n0 += C->lab[p] == 0;
+    }
+    int64_t n1 = s - n0;
+    int64_t mn = n0 < n1 ? n0 : n1, mx = n0 < n1 ? n1 : n0;
+    if (100 * mn < mx) {
+        /* median: the floor(s / 2) first points in (key, position) order */
+        int64_t *idx = C->tmp_idx + b;  /* scratch, restored by the partition */
+        for (int64_t p = b; p < e; ++p) idx[p - b] = p;
+        g_sort_key = O->key;
+        qsort(idx, (size_t)s, sizeof(int64_t), cmp_idx);
+        for (int64_t r = 0; r < s; ++r) C->lab[idx[r]] = r < s / 2 ? 0 : 1;
+        n0 = s / 2;
+        O->median_splits++;
+    }
+    return n0;
+}
+
+/* Labels for a PCA split of [b, e); returns the left size or -1. */
+static int64_t pca_labels(octx_t *O, int64_t b, int64_t e) {
+    ctx_t *C = O->C;
+    int32_t d = C->d;
+    int64_t s = e - b;
+    double *col = O->key;
+    for (int32_t k = 0; k < d; ++k) {
+        for (int64_t p = b; p < e; ++p) col[p] = C->X[p * d + k];
+        O->mu[k] = chunked_sum(col, b, e) / (double)s;
+    }
+    for (int32_t k = 0; k < d; ++k) O->v[k] = 1.0;
+    for (int it = 0; it < PCA_ITERS; ++it) {
+        for (int64_t p = b; p < e; ++p) {
+            double t = 0.0;
+            for (int32_t k = 0; k < d; ++k) t = t + (C->X[p * d + k] - O->mu[k]) * O->v[k];
+            C->q[p] = t;
+        }
+        for (int32_t k = 0; k < d; ++k) {
+            for (int64_t p = b; p < e; ++p) col[p] = (C->X[p * d + k] - O->mu[k]) * C->q[p];
+            O->wv[k] = chunked_sum(col, b, e);
+        }
+        double nrm2 = 0.0;
+        for (int32_t k = 0; k < d; ++k) nrm2 = nrm2 + O->wv[k] * O->wv[k];
+        if (!(nrm2 > 0.0)) return -1;
+        double nrm = sqrt(nrm2);
+        for (int32_t k = 0; k < d; ++k) O->v[k] = O->wv[k] / nrm;
+    }
+    for (int64_t p = b; p < e; ++p) {
+        double t = 0.0;
+        for (int32_t k = 0; k < d; ++k) t = t + (C->X[p * d + k] - O->mu[k]) * O->v[k];
+        C->q[p] = t;
+    }
+    double m = chunked_sum(C->q, b, e) / (double)s;
+    int64_t n0 = 0;
+    for (int64_t p = b; p < e; ++p) {
+        C->lab[p] = C->q[p] <= m ? 0 : 1;
+        n0 += C->lab[p] == 0;
+    }
+    if (n0 == 0 || n0 == s) return -1;
+    return n0;
+}
+
+static int64_t build_order(octx_t *O, int64_t b, int64_t e) {
+    ctx_t *C = O->C;
+    int64_t s = e - b, left = -1, right = -1;
+    if (s > C->leaf) {
+        int64_t nl = -1;
+        if (O->method == ORDER_KD) nl = kd_labels(O, b, e);
+        else if (O->method == ORDER_PCA) nl = pca_labels(O, b, e);
+        if (nl < 0) {
+            if (O->method != ORDER_NP) C->fallbacks++;
+            nl = s / 2;
+        } else {
+            stable_partition(C, b, e);
+        }
+        left = build_order(O, b, b + nl);
+        right = build_order(O, b + nl, e);
+    }
+    int64_t id = C->n_nodes++;
+    int64_t *row = C->nodes + 5 * id;
+    row[0] = b; row[1] = e; row[2] = left; row[3] = right; row[4] = -1;
+    if (left >= 0) { C->nodes[5 * left + 4] = id; C->nodes[5 * right + 4] = id; }
+    return id;
+}
+
+/*
+ * NP / KD / PCA ordering of X (n x d FP64) with the tree in postorder.
+ * method: 1 NP, 2 KD, 3 PCA.  perm, nodes as oracle_cluster2mn.
+ * stats (out, 2): fallback (halves) splits, median splits (KD).
+ * Returns the node count, -1 on allocation failure, -2 on a bad method.
+ */
+int64_t oracle_order(const double *X, int64_t n, int32_t d, int32_t leaf, int32_t method,
+                     int64_t *perm, int64_t *nodes, int64_t *stats) {
+    if (method < ORDER_NP || method > ORDER_PCA) return -2;
+    ctx_t C;
+    octx_t O;
+    memset(&C, 0, sizeof C);
+    memset(&O, 0, sizeof O);
+    C.n = n; C.d = d; C.leaf = leaf < 1 ? 1 : leaf;
+    C.X = malloc(sizeof(double) * n * d);
+    C.tmp_row = malloc(sizeof(double) * n * d);
+    C.tmp_idx = malloc(sizeof(int64_t) * n);
+    C.lab = malloc(n);
+    C.q = malloc(sizeof(double) * n);
+    O.key = malloc(sizeof(double) * n);
+    double *dbuf = malloc(sizeof(double) * 4 * d);
+    if (!C.X || !C.tmp_row || !C.tmp_idx || !C.lab || !C.q || !O.key || !dbuf) {
+        free(C.X); free(C.tmp_row); free(C.tmp_idx); free(C.lab); free(C.q); free(O.key); free(dbuf);
+        return -1;
+    }
+    O.C = &C; O.method = method;
+    O.mu = dbuf; O.v = dbuf + d; O.wv = dbuf + 2 * d; O.acc = dbuf + 3 * d;
+    memcpy(C.X, X, sizeof(double) * n * d);
+    for (int64_t i = 0; i < n; ++i) perm[i] = i;
+    C.perm = perm;
+    C.nodes = nodes;
+    if (n > 0) build_order(&O, 0, n);
+    stats[0] = C.fallbacks; stats[1] = O.median_splits;
+    free(C.X); free(C.tmp_row); free(C.tmp_idx); free(C.lab); free(C.q); free(O.key); free(dbuf);
     return C.n_nodes;
 }
 

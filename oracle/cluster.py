@@ -1,4 +1,5 @@
-"""Recursive two-means (2MN) ordering and cluster tree.
+"""Recursive two-means (2MN) ordering and cluster tree, and the other
+orderings the paper compares it with (NP, KD, PCA).
 
 Section 4.2 (split in two, make each group consecutive, recurse, the ranges are
 the HSS tree nodes), Section 4.3 "Recursive two-means" (seeding, Lloyd
@@ -64,6 +65,27 @@ def cluster2mn(X, leaf, seed, max_iter=100):
     if cnt < 0:
         raise MemoryError("oracle_cluster2mn: allocation failed")
     return Tree(perm, nodes[:cnt].copy(), int(stats[0]), int(stats[1]), int(stats[2]))
+
+
+ORDERINGS = {"np": 1, "kd": 2, "pca": 3}
+
+
+def order(X, leaf, method):
+    """The NP, KD or PCA ordering of Section 4.3 ("Selected Preprocessing
+    Methods") with its cluster tree; the split rules are spelled out in
+    oracle/c/oracle.c.  Tree.fallbacks counts halves splits, Tree.capped the
+    KD median splits (Tree.iterations is 0)."""
+    Xd = np.ascontiguousarray(np.asarray(X).astype(np.float64))
+    n, d = Xd.shape
+    perm = np.empty(n, dtype=np.int64)
+    nodes = np.empty((max(2 * n - 1, 1), 5), dtype=np.int64)
+    stats = np.zeros(2, dtype=np.int64)
+    cnt = lib().oracle_order(Xd.ctypes.data_as(ctypes.c_void_p), n, d, int(leaf), ORDERINGS[method],
+                             perm.ctypes.data_as(ctypes.c_void_p), nodes.ctypes.data_as(ctypes.c_void_p),
+                             stats.ctypes.data_as(ctypes.c_void_p))
+    if cnt < 0:
+        raise MemoryError("oracle_order: allocation failed")
+    return Tree(perm, nodes[:cnt].copy(), int(stats[0]), int(stats[1]), 0)
 
 
 def seeds(X, b, e, seed):

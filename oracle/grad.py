@@ -79,3 +79,49 @@ def matvec_bwd(X, Y, W, G, h):
     dY = (P.T @ X - P.sum(axis=0)[:, None] * Y) / h**2
     dh = float(np.sum(P * Q) / h**3)
     return dX, dY, dW, dh
+
+
+def val_loss_grad_blocked(X, y, Xv, yv, h, lam, block=4096):
+    """(L, dL/dlog h, dL/dlog lambda) by the same formulas as val_loss_grad,
+    dense FP64 with one n x n array (K + lambda I, then its Cholesky factor in
+    place): the products with K_v, dK_v/dh and dK/dh are formed block of rows
+    by block of rows from the differences, so n = 32,768 fits in ~12 GB."""
+    X = np.asarray(X, dtype=np.float64)
+    Xv = np.asarray(Xv, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    yv = np.asarray(yv, dtype=np.float64)
+    n = X.shape[0]
+    A = np.empty((n, n))
+    for b in range(0, n, block):
+        e = min(b + block, n)
+        A[b:e] = np.exp(-_sqdist(X[b:e], X) / (2 * h * h))
+    A[np.diag_indices_from(A)] += lam
+    c = sla.cho_factor(A, lower=True, overwrite_a=True, check_finite=False)
+    alpha = sla.cho_solve(c, y)
+    mv = Xv.shape[0]
+    f = np.empty(mv)
+    dKva = np.empty(mv)
+    g = np.zeros(n)
+    for b in range(0, mv, block):
+        e = min(b + block, mv)
+        Qv = _sqdist(Xv[b:e], X)
+        Kv = np.exp(-Qv / (2 * h * h))
+        f[b:e] = Kv @ alpha
+        dKva[b:e] = (Kv * Qv / h**3) @ alpha
+    err = f - yv
+    L = float(err @ err / mv)
+    for b in range(0, mv, block):
+        e = min(b + block, mv)
+        Kv = np.exp(-_sqdist(Xv[b:e], X) / (2 * h * h))
+        g += Kv.T @ err[b:e]
+    g *= 2.0 / mv
+    beta = sla.cho_solve(c, g)
+    del A, c
+    dKa = np.empty(n)
+    for b in range(0, n, block):
+        e = min(b + block, n)
+        Q = _sqdist(X[b:e], X)
+        dKa[b:e] = (np.exp(-Q / (2 * h * h)) * Q / h**3) @ alpha
+    dL_dlam = -float(beta @ alpha)
+    dL_dh = float((2.0 / mv) * err @ dKva - beta @ dKa)
+    return L, h * dL_dh, lam * dL_dlam

@@ -92,9 +92,13 @@ def fp32_sym_anchored_bound(X, W, h, rows_per_block, tile=64, safety=4.0, form=3
     block's mean point; its FP32 norm expansion (d FMAs per norm, d + 2 terms
     in the matrix-core sum, two constants) is off by at most
     (2 d + 6) u (|x'| + |y'|)^2 / (2 h^2) in natural-log units.  The BF16
-    three-term form (4) adds 3 d + 2 units: the split's representation error
-    (counted as 2^-24 per operand, though the split of a normal FP32 value is
-    exact) and the dropped cross terms below 2^-16 (2^-23 per product).  Entries inside a diagonal block use the FP64 exponent
+    three-term form (4) uses the error model of the wide-point product: the
+    split of a normal FP32 operand is exact, the products of BF16 terms are
+    exact in FP32, the matrix-core sum adds 6 d + 6 of them (six cross
+    products per coordinate, three terms of each constant against ones) and
+    the dropped cross terms add at most 2 u of each product, so its sum counts
+    6 d + 8 units where the FP32 form's counts d + 2: 7 d + 12 in all.
+    Entries inside a diagonal block use the FP64 exponent
     (fp32_product_bound's terms)."""
     X = np.asarray(X, dtype=np.float64)
     n, d = X.shape
@@ -111,7 +115,7 @@ def fp32_sym_anchored_bound(X, W, h, rows_per_block, tile=64, safety=4.0, form=3
     T = q / (2 * h * h)
     K = np.exp(-T)
     aW = np.abs(np.asarray(W, dtype=np.float64)).reshape(W.shape[0], -1)
-    terms = 2 * d + 6 + (3 * d + 2 if form == 4 else 0)
+    terms = 7 * d + 12 if form == 4 else 2 * d + 6
     return safety * U32 * ((tile + 2) * (K @ aW) + (d + 3) * ((K * T) @ aW) + terms * ((K * S) @ aW))
 
 
@@ -135,16 +139,17 @@ def mfma_sample_bound(Xp, R, h, lb, le, prec, split, rows, rows_per_block=256, s
 
     Entry e_ij = exp2(t) with t formed in FP32 from coordinates re-centred on
     the workgroup's first point a (x' = x - a, y' = y - a): the FMA chain of
-    d + 2 terms gives |dt| <= (d + 2) u c (|x'| + |y'|)^2 in log2 units (the
+    d + 2 terms gives |dt| <= (d + 2) u c (|x'| + |y'|)^2 in log2 units.  The
     split modes at d <= 16 form t from three-term BF16 splits of the same
-    operands: the split's representation error, 2^-24 per operand, and the
-    dropped cross terms, 2^-23 of each product, give at most 4 (d + 2) units
-    in place of d + 2), so |de| <= e u [2 + k (d + 2) (|x'| + |y'|)^2 / (2 h^2)]
-    with k = 4 there and 1 otherwise, plus the split's own
-    rounding SPLIT_U * e.  The FP32 accumulation over n terms is charged with
-    the probabilistic model sqrt(n_adds) u ||e o r||_2 (Higham and Mary 2019),
-    FP16 entries (scaled by 2^14) add 2^-38 absolute where they fall below
-    FP16's normal range,
+    operands; the error model is the one of the wide-point product: the split
+    of a normal FP32 value is exact, the 6 (d + 2) kept cross products are
+    exact in FP32 and summed in FP32, and the dropped ones add at most 2 u of
+    each product, so 6 (d + 2) + 2 units take the place of d + 2.  Then
+    |de| <= e u [2 + k c (|x'| + |y'|)^2 / (2 h^2)] with k the unit count,
+    plus the split's own rounding SPLIT_U * e.  The FP32 accumulation over n
+    terms is charged with the probabilistic model sqrt(n_adds) u ||e o r||_2
+    (Higham and Mary 2019), FP16 entries (scaled by 2^14) add 2^-38 absolute
+    where they fall below FP16's normal range,
     n_adds = n / 16 + 16 for the 16-deep FP16 / BF16 products and n / 2 + 2
     for the 2-deep FP32 ones.  anchor: the centring point when it is one for
     all rows (the wide-point kernel centres on the mean point)."""
@@ -161,8 +166,8 @@ def mfma_sample_bound(Xp, R, h, lb, le, prec, split, rows, rows_per_block=256, s
         q = ((Xp - Xp[i]) ** 2).sum(axis=1)
         e = np.exp(-q / (2 * h * h))
         e[lb[i]:le[i]] = 0.0
-        kx = 4 if (prec != "f32" and d <= 16) else 1
-        de = e * (U32 * (2 + kx * (d + 2) * (xr + yr) ** 2 / (2 * h * h)) + us)
+        units = 6 * (d + 2) + 2 if (prec != "f32" and d <= 16) else d + 2
+        de = e * (U32 * (2 + units * (xr + yr) ** 2 / (2 * h * h)) + us)
         if prec == "f16":
             # entries carry a 2^14 scale; below FP16's normal range the hi and
             # lo terms keep an absolute precision of 2^-25 in scaled units

@@ -275,3 +275,50 @@ def test_batched_wide_sample_per_problem(gpu_lib):
         ref = cmath.sample_masked(Xk, Rk, p.h, lbk, lek, rows)
         bound = mfma_sample_bound(Xk, Rk, p.h, lbk, lek, "f16", 2, rows, anchor=mean)
         assert np.all(np.abs(S[a:b] - ref) <= bound), k
+
+
+def test_fit_batched_wide_group_with_ranks(gpu_lib):
+    # the d = 54 group of the ragged batch through the D = 64 sampler with an
+    # h large enough (h^2 about half the within-cluster squared distance) that
+    # the off-diagonal blocks have rank: the compressed ranks are not all zero,
+    # and every problem's coefficients match dense KRR
+    ps = _problems(count=3, d=54, n_lo=1500, n_hi=3000, seed=14)
+    for p in ps:
+        p.h = 4.0 + p.h  # h in [4.5, 6]: within-cluster K ~ exp(-108 / 2 h^2) in 0.07 .. 0.22
+    probs = [(_t(p.X), _t(p.y), p.h, p.lam) for p in ps]
+    tol = 1e-6
+    res = gpu_lib.fit_batched(probs, leaf=128, opts=gpu_lib.HssOptions(rtol=1e-3, r0=128, prec="f16", atol=0.0),
+                              tol=tol, max_iter=300, mv_prec="f32")
+    assert len(res.groups) == 1
+    assert res.info["hss"][0]["max_rank"] > 0
+    for rf in res.info["refine"]:
+        assert rf["converged"] and np.all(rf["relres"] <= tol)
+    for k, p in enumerate(ps):
+        a = res.alphas[k].cpu().numpy()
+        Xd = p.X.astype(np.float64)
+        ref = ok.krr_fit_dense(Xd, p.y, p.h, p.lam)
+        K = ok.kernel_dense(Xd, Xd, p.h)
+        cond = np.linalg.cond(K + p.lam * np.eye(K.shape[0]))
+        err = np.linalg.norm(a - ref) / np.linalg.norm(ref)
+        assert err <= 50.0 * cond * tol, (k, err, cond)
+
+
+def test_fit_batched_top_of_size_range(gpu_lib):
+    # a problem at the top of the ragged batch's size range (n = 32,767)
+    # beside two small ones; the FP64 residual of every problem's
+    # coefficients is recomputed by the oracle over all rows
+    big = sd.c4_ragged_batch(count=1, n_lo=32768, n_hi=32768, dims=(8,), m=16, config=15)[0]
+    small = _problems(count=2, d=8, n_lo=400, n_hi=2000, seed=16)
+    ps = [big] + small
+    probs = [(_t(p.X), _t(p.y), p.h, p.lam) for p in ps]
+    tol = 1e-6
+    res = gpu_lib.fit_batched(probs, leaf=128, opts=gpu_lib.HssOptions(rtol=1e-2, r0=256, prec="f16"),
+                              tol=tol, max_iter=300, mv_prec="f32")
+    for rf in res.info["refine"]:
+        assert rf["converged"] and np.all(rf["relres"] <= tol)
+    for k, p in enumerate(ps):
+        a = res.alphas[k].cpu().numpy()
+        r = cmath.residual(p.X, a, p.y, p.h, p.lam)
+        # FP32-entry products stop the solve at 1e-6; in FP64 the residual is
+        # within the products' error, ~1e-7 of |K||alpha| / |y|
+        assert np.linalg.norm(r) <= 2e-6 * np.linalg.norm(p.y), k

@@ -1,5 +1,5 @@
 """The benchmark configuration at full size (16-Gaussian workload, n = 2^20,
-d = 8, FP16 2-term sampling, r = 256, refinement on the FP32-entry product to
+d = 8, FP16 2-term sampling, r0 = 256 grown adaptively, refinement on the FP32-entry product to
 1e-6), certified in FP64: the residual of the fitted coefficients is
 recomputed with the FP64 kernel product over all n^2 entries, its rows are
 checked one by one against the oracle's matrix-free FP64 residual on sampled
@@ -20,8 +20,10 @@ def fitted(gpu_lib):
     p = sd.c2_sixteen_gaussians(m=2000)
     X = torch.from_numpy(p.X).cuda()
     y = torch.from_numpy(p.y).cuda()
-    opts = gpu_lib.HssOptions(rtol=1e-2, atol=3.0, r0=256, dr=256, r_max=256, prec="f16", split_terms=2,
-                              cap_policy=1)
+    # the benchmark's options: C2's rtol 1e-2 and r0 = 256 grown adaptively,
+    # with the absolute tolerance the benchmark uses
+    opts = gpu_lib.HssOptions(rtol=1e-2, atol=6.0, r0=256, dr=256, r_max=4096, prec="f16", split_terms=2,
+                              cap_policy=0)
     res = gpu_lib.fit(X, y, p.h, p.lam, leaf=p.leaf, opts=opts, tol=1e-6, max_iter=300)
     return p, res
 
@@ -34,9 +36,9 @@ def test_fullsize_fp64_residual(gpu_lib, fitted):
     Ka = gpu_lib.kernel_matvec(Xp, Xp, p.h, a, prec="f64")
     r = (yp - Ka - p.lam * a).cpu().numpy().ravel()
     ynorm = float(np.linalg.norm(p.y))
-    # the solve stops at relres <= 1e-6 measured with FP32-entry products, whose
-    # error is ~1e-7 of |K||alpha|; in FP64 the residual stays below 2e-6
-    assert np.linalg.norm(r) <= 2e-6 * ynorm
+    # the solve stops at relres <= 1e-6 measured with FP32-entry products; the
+    # target is the FP64 residual, which must be within it too
+    assert np.linalg.norm(r) <= 1e-6 * ynorm
     # the FP64 product row by row against the oracle's matrix-free residual
     rows = np.concatenate([np.arange(4), np.random.default_rng(0).choice(p.n, 28, replace=False), [p.n - 1]])
     Xh = Xp.cpu().numpy()

@@ -53,6 +53,25 @@ def test_validation_gradient_against_oracle(gpu_lib, n, mv):
     assert abs(ll.grad.item() - gl_ref) <= 1e-3 * abs(gl_ref)
 
 
+def test_validation_gradient_against_stored_oracle_32k(gpu_lib):
+    # n = 32,768, m_v = 4,096 (the gradient workload at a quarter of its size):
+    # the dense FP64 oracle's value was written by tests/golden/make_c5_gradient.py
+    import json
+    import os
+    from paper_1803_10274_amd.autograd import validation_loss
+    with open(os.path.join(os.path.dirname(__file__), "golden", "c5_gradient_n32768.json")) as f:
+        ref = json.load(f)
+    p = sd.c5_eight_gaussians(n=ref["n"], m=ref["m_v"])
+    assert (p.h, p.lam) == (ref["h"], ref["lam"])
+    lh = torch.tensor(math.log(p.h), dtype=torch.float64, device="cuda", requires_grad=True)
+    ll = torch.tensor(math.log(p.lam), dtype=torch.float64, device="cuda", requires_grad=True)
+    L, st = validation_loss(lh, ll, _t(p.X), _t(p.y), _t(p.Xt), _t(p.yt), tol=1e-7)
+    L.backward()
+    assert abs(L.item() - ref["loss"]) <= 1e-6 * abs(ref["loss"])
+    assert abs(lh.grad.item() - ref["dL_dlogh"]) <= 1e-3 * abs(ref["dL_dlogh"])
+    assert abs(ll.grad.item() - ref["dL_dloglam"]) <= 1e-3 * abs(ref["dL_dloglam"])
+
+
 def test_validation_gradient_finite_differences(gpu_lib):
     # central differences of the GPU objective (tightly refined, so smooth in h)
     from paper_1803_10274_amd.autograd import validation_loss

@@ -39,14 +39,35 @@ def test_sampler_all_rows(gpu_lib, prec, split, r):
     assert np.all(np.abs(S - ref) <= bound)
 
 
-@pytest.mark.parametrize("d", [3, 18, 30])
-def test_sampler_point_widths(gpu_lib, d):
-    n, h = 777, 1.5
-    Xp, lb, le = _case(n, d, 64)
+SPLIT_MODES = [("f32", 1), ("f16", 1), ("f16", 2), ("bf16", 1), ("bf16", 2)]
+
+
+@pytest.mark.parametrize("prec,split", SPLIT_MODES)
+@pytest.mark.parametrize("d", [3, 12, 16, 18, 30, 40, 54, 64])
+@pytest.mark.parametrize("kind", ["mixture", "smooth"])
+def test_sampler_point_widths(gpu_lib, prec, split, d, kind):
+    # every narrow instantiation: D = 8 (d 3), D = 16 (d 12, 16: BF16 split
+    # exponents in the split modes), D = 32 (18, 30), D = 64 (40, 54, 64).
+    # mixture: the 16-Gaussian data with h = 0.35 sqrt(d) (within-cluster
+    # kernel values near e^-2 at every width); smooth: one Gaussian cloud
+    # (sigma 0.3) with h = 0.4 sqrt(d), so most of each row's sample comes
+    # from outside its own leaf.
+    n = 777
+    if kind == "mixture":
+        h = 0.35 * np.sqrt(d)
+        Xp, lb, le = _case(n, d, 64)
+    else:
+        h = 0.4 * np.sqrt(d)
+        X = sd.points(n, d, seed=d, scale=0.3)
+        t = oc.cluster2mn(X, 64, 1)
+        Xp = np.ascontiguousarray(X[t.perm])
+        lb, le = leaf_ranges(t.nodes, n)
     R = sd.random_block(n, 64, seed=d)
-    S = gpu_lib.kernel_sample(_t(Xp), h, _t(R), _t(lb), _t(le), prec="f16", split_terms=2).cpu().numpy()
+    S = gpu_lib.kernel_sample(_t(Xp), h, _t(R), _t(lb), _t(le), prec=prec, split_terms=split).cpu().numpy()
     ref = cmath.sample_masked(Xp, R, h, lb, le, np.arange(n))
-    assert np.all(np.abs(S - ref) <= mfma_sample_bound(Xp, R, h, lb, le, "f16", 2, np.arange(n)))
+    if kind == "smooth":
+        assert np.abs(ref).mean() > 1.0
+    assert np.all(np.abs(S - ref) <= mfma_sample_bound(Xp, R, h, lb, le, prec, split, np.arange(n)))
 
 
 def test_sampler_no_mask_and_fp64_points(gpu_lib):

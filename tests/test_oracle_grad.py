@@ -89,3 +89,23 @@ def test_val_loss_closed_forms():
     assert gh == 0.0
     Xv = X + np.array([[0.0, 1e4, 0.0]])
     assert abs(og.val_loss(X, y, Xv, yv, 1.0, lam) - float(yv @ yv / m)) <= 1e-15 * float(yv @ yv)
+
+
+def test_blocked_gradient_matches_central_differences():
+    # the blocked form (rows in blocks smaller than n, a ragged last block)
+    # against central differences of the dense objective, and against the
+    # unblocked form
+    p = sd.c5_eight_gaussians(n=700, m=150, d=5)
+    X, y, Xv, yv = p.X.astype(np.float64), p.y, p.Xt.astype(np.float64), p.yt
+    h, lam = 1.7, 0.6
+    L, gh, gl = og.val_loss_grad_blocked(X, y, Xv, yv, h, lam, block=128)
+    s = 1e-4
+    fh = (og.val_loss(X, y, Xv, yv, h * np.exp(s), lam)
+          - og.val_loss(X, y, Xv, yv, h * np.exp(-s), lam)) / (2 * s)
+    fl = (og.val_loss(X, y, Xv, yv, h, lam * np.exp(s))
+          - og.val_loss(X, y, Xv, yv, h, lam * np.exp(-s))) / (2 * s)
+    assert abs(L - og.val_loss(X, y, Xv, yv, h, lam)) <= 1e-12 * L
+    assert abs(gh - fh) <= 1e-6 * max(abs(fh), 1e-3)
+    assert abs(gl - fl) <= 1e-6 * max(abs(fl), 1e-3)
+    L2, gh2, gl2 = og.val_loss_grad(X, y, Xv, yv, h, lam)
+    assert abs(gh - gh2) <= 1e-10 * abs(gh2) and abs(gl - gl2) <= 1e-10 * abs(gl2)

@@ -78,3 +78,35 @@ def test_six_products_within_2u_of_the_product():
     # every kept product matters: dropping hl (2^-16 of the product) breaks it
     five = six - hx * ly
     assert np.any(np.abs(exact - five) > bound)
+
+
+def _split_dot_fp32(x, y):
+    """Dot product of FP32 vectors from three-term BF16 splits: the six kept
+    cross products of each coordinate pair, exact in FP32, summed one after
+    the other in FP32 (the worst order for the bound)."""
+    hx, mx, lx = split3(x)
+    hy, my, ly = split3(y)
+    acc = np.float32(0.0)
+    for k in range(x.shape[0]):
+        for a, b in ((hx, hy), (hx, my), (mx, hy), (hx, ly), (lx, hy), (mx, my)):
+            acc = np.float32(acc + np.float32(a[k] * b[k]))
+    return float(acc)
+
+
+def test_split_dot_product_unit_count():
+    # The unit count the GPU tolerances use for a dot product of n FP32 terms
+    # formed from three-term BF16 splits: 6 n + 2 units of sum |x_k y_k|
+    # (6 n exact products summed in FP32, dropped cross terms 2 u each).
+    rng = np.random.default_rng(7)
+    worst = 0.0
+    for n in (3, 10, 18, 54):
+        for _ in range(300):
+            x = rng.standard_normal(n).astype(np.float32)
+            y = rng.standard_normal(n).astype(np.float32)
+            exact = float(np.dot(x.astype(np.float64), y.astype(np.float64)))
+            mag = float(np.abs(x.astype(np.float64) * y.astype(np.float64)).sum())
+            err = abs(_split_dot_fp32(x, y) - exact)
+            assert err <= (6 * n + 2) * U32 * mag
+            worst = max(worst, err / (U32 * mag))
+    # the count is not vacuous: the sums do lose several units
+    assert worst > 1.0
