@@ -302,9 +302,10 @@ int64_t oracle_cluster2mn(const double *X, int64_t n, int32_t d, int32_t leaf,
  *   PCA  mean point mu (chunked sums); the first principal direction v by
  *        PCA_ITERS power iterations v <- C v / |C v| with C the (unscaled)
  *        scatter matrix of the node, applied as sum_j (x_j - mu) t_j with
- *        t_j = (x_j - mu) . v, from v0 = (1, ..., 1); projections
+ *        t_j = (x_j - mu) . v, from v0 = (1, ..., 1), each step scaled by
+ *        its largest |component| (max norm, so no square root); projections
  *        p_j = (x_j - mu) . v and their chunked mean m; left = p_j <= m.
- *        An empty side or |C v| = 0 splits into halves.
+ *        An empty side or C v = 0 splits into halves.
  * Every sum runs in the written order with no fused multiply-add.
  * ---------------------------------------------------------------------- */
 #define PCA_ITERS 32
@@ -401,10 +402,10 @@ static int64_t pca_labels(octx_t *O, int64_t b, int64_t e) {
             for (int64_t p = b; p < e; ++p) col[p] = (C->X[p * d + k] - O->mu[k]) * C->q[p];
             O->wv[k] = chunked_sum(col, b, e);
         }
-        double nrm2 = 0.0;
-        for (int32_t k = 0; k < d; ++k) nrm2 = nrm2 + O->wv[k] * O->wv[k];
-        if (!(nrm2 > 0.0)) return -1;
-        double nrm = sqrt(nrm2);
+        double nrm = 0.0;
+        for (int32_t k = 0; k < d; ++k)
+            if (fabs(O->wv[k]) > nrm) nrm = fabs(O->wv[k]);
+        if (!(nrm > 0.0)) return -1;
         for (int32_t k = 0; k < d; ++k) O->v[k] = O->wv[k] / nrm;
     }
     for (int64_t p = b; p < e; ++p) {

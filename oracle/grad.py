@@ -83,9 +83,11 @@ def matvec_bwd(X, Y, W, G, h):
 
 def val_loss_grad_blocked(X, y, Xv, yv, h, lam, block=4096):
     """(L, dL/dlog h, dL/dlog lambda) by the same formulas as val_loss_grad,
-    dense FP64 with one n x n array (K + lambda I, then its Cholesky factor in
-    place): the products with K_v, dK_v/dh and dK/dh are formed block of rows
-    by block of rows from the differences, so n = 32,768 fits in ~12 GB."""
+    dense FP64 with one n x n array (K + lambda I) and its Cholesky factor
+    (torch's CPU Cholesky: SciPy's LAPACK build fails at n = 32,768 here): the
+    products with K_v, dK_v/dh and dK/dh are formed block of rows by block of
+    rows from the differences, so n = 32,768 fits in ~20 GB."""
+    import torch
     X = np.asarray(X, dtype=np.float64)
     Xv = np.asarray(Xv, dtype=np.float64)
     y = np.asarray(y, dtype=np.float64)
@@ -96,8 +98,13 @@ def val_loss_grad_blocked(X, y, Xv, yv, h, lam, block=4096):
         e = min(b + block, n)
         A[b:e] = np.exp(-_sqdist(X[b:e], X) / (2 * h * h))
     A[np.diag_indices_from(A)] += lam
-    c = sla.cho_factor(A, lower=True, overwrite_a=True, check_finite=False)
-    alpha = sla.cho_solve(c, y)
+    Lc = torch.linalg.cholesky(torch.from_numpy(A))
+    del A
+
+    def solve(rhs):
+        return torch.cholesky_solve(torch.from_numpy(rhs.reshape(-1, 1).copy()), Lc).numpy().ravel()
+
+    alpha = solve(y)
     mv = Xv.shape[0]
     f = np.empty(mv)
     dKva = np.empty(mv)
@@ -115,8 +122,8 @@ def val_loss_grad_blocked(X, y, Xv, yv, h, lam, block=4096):
         Kv = np.exp(-_sqdist(Xv[b:e], X) / (2 * h * h))
         g += Kv.T @ err[b:e]
     g *= 2.0 / mv
-    beta = sla.cho_solve(c, g)
-    del A, c
+    beta = solve(g)
+    del Lc
     dKa = np.empty(n)
     for b in range(0, n, block):
         e = min(b + block, n)
