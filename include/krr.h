@@ -61,6 +61,27 @@ typedef struct hss_ulv_s *hss_ulv_t;
 /* Message for the last failed call on this thread ("" if none). */
 const char *krr_last_error(void);
 
+/* Device memory (ownership convention, Algorithm 1's data stay the caller's).
+ * Registers the caller's stream-ordered device allocator for every buffer the
+ * library allocates from now on: temporaries of a call and the storage of
+ * the handles (trees, HSS generators, factors, solve plans).  alloc(bytes,
+ * stream, ctx) returns device memory usable in stream order on `stream` (the
+ * stream of the call that asks, NULL for the legacy default stream) or NULL
+ * on failure (the call then fails with KRR_E_NOMEM); dealloc(ptr, stream, ctx)
+ * receives every such buffer back with the stream it was allocated on, when
+ * the call or the handle is done with it.  A buffer is always returned to
+ * the allocator that made it, also after another one has been registered.
+ * alloc = dealloc = NULL restores hipMalloc / hipFree for new buffers.  Not
+ * to be called while another thread is inside the library.  Errors:
+ * KRR_E_INVAL when only one of the two functions is given. */
+int krr_set_allocator(void *(*alloc)(size_t, void *, void *), void (*dealloc)(void *, void *, void *),
+                      void *ctx);
+
+/* Device allocations made so far by the library: with hipMalloc (direct) and
+ * with a registered allocator (by_caller); host outputs.  Errors: KRR_E_INVAL
+ * for NULL. */
+int krr_alloc_counts(int64_t *direct, int64_t *by_caller);
+
 /* Number of usable HIP devices (0 when none); never fails. */
 int krr_device_count(void);
 
@@ -90,6 +111,41 @@ typedef struct {
 int krr_cluster_2mn(const void *X, int32_t xprec, int64_t n, int32_t d,
                     const krr_cluster_opts *opts, void *stream, int64_t *perm,
                     krr_tree *out);
+
+/* The orderings the paper compares with recursive two-means (Section 4.3,
+ * "Selected Preprocessing Methods"), each a recursive split of [b, e) while
+ * its size exceeds the leaf size, stable, left part first, tree in postorder:
+ *   KRR_ORDER_NP   no reordering; halves by position (left floor(size / 2)).
+ *   KRR_ORDER_KD   coordinate of maximum spread (max - min; lowest index on
+ *                  ties), split at its mean (left: coordinate <= mean).  If
+ *                  100 min(left, right) < max(left, right), the median split:
+ *                  the floor(size / 2) points first in (coordinate, position)
+ *                  order go left.  Zero spread: halves.
+ *   KRR_ORDER_PCA  first principal direction of the node by 32 power steps
+ *                  v <- C v / max|C v| from v = (1, ..., 1), C the scatter
+ *                  matrix about the node's mean point; left: projection <= the
+ *                  mean projection.  An empty side or C v = 0: halves.
+ * Means and scatter products are FP64 sums in chunks of 256 positions (in
+ * order, then over chunks in order) with no fused multiply-add, so the result
+ * is bit-for-bit deterministic.  KRR_ORDER_2MN runs krr_cluster_2mn. */
+enum { KRR_ORDER_2MN = 0, KRR_ORDER_NP = 1, KRR_ORDER_KD = 2, KRR_ORDER_PCA = 3 };
+
+/*
+ * Ordering and cluster tree of X by `method` (KRR_ORDER_*); a forest when
+ * offsets (host, np + 1 int64, offsets[0] = 0, increasing) is given, one tree
+ * per problem, each equal to ordering that problem alone shifted by its
+ * offset (offsets = NULL: one problem of n points, np ignored).
+ *   X      n x d points (xprec), not modified
+ *   opts   leaf_size as krr_cluster_2mn (max_iter, seed: 2MN only)
+ *   perm   (out, n int64) perm[new position] = original index
+ *   out    (out) tree handle; statistics (krr_tree_export): halves splits
+ *          (NP not counted), KD median splits, 0, levels
+ * Errors: KRR_E_INVAL for a bad method, sizes or NULL pointers.
+ * Synchronizes `stream` once per tree level.
+ */
+int krr_cluster_order(const void *X, int32_t xprec, int64_t n, int32_t d, int32_t method,
+                      const int64_t *offsets, int32_t np, const krr_cluster_opts *opts, void *stream,
+                      int64_t *perm, krr_tree *out);
 
 /* Builds a tree handle from a host node table (n_nodes rows of begin, end,
  * left, right, parent; postorder, children before parents, root last; leaves
@@ -227,6 +283,8 @@ typedef struct {
 int hss_compress(krr_tree t, const void *Xp, int32_t xprec, int32_t d, double h,
                  const hss_opts *opts, void *stream, hss_t *out, hss_stats *stats_host);
 
+/* Frees the generators (waits for the device first: the storage may come
+ * from a stream-ordered allocator). */
 void hss_destroy(hss_t H);
 
 /* y = K_hss x for n x nrhs FP64 blocks in the permuted order (the matrix the
@@ -290,6 +348,7 @@ int hss_ulv_factor_spd(hss_t H, double lambda, double pivot_floor, void *stream,
  */
 int hss_ulv_factor_shifted(hss_t H, double lambda, void *stream, hss_ulv_t *out, double *shift_host);
 
+/* Frees the factor and its solve plans (waits for the device first). */
 void hss_ulv_destroy(hss_ulv_t F);
 
 /* Graph replay of solves (default on): the first hss_solve with a given
@@ -437,6 +496,27 @@ int krr_set_tuning(int32_t knob, int32_t value);
 int krr_get_tuning(int32_t knob, int32_t *value_host);
 
 /* ------------------------------------------------ small vector kernels */
+
+/* The validation mean squared error of a fit (the objective of the tuning of
+ * h and lambda, Section 5.3) and the source of its adjoint system: for scores
+ * f (m x k, K(X_v, X) alpha) and targets y_v (m x k), all FP64 device arrays,
+ *   ge[i, c] = (2 / m) (f[i, c] - y_v[i, c])      (out, m x k)
+ *   loss[c]  = sum_i (f[i, c] - y_v[i, c])^2 / m  (out, k, device)
+ * summed in a fixed order (deterministic).  Errors: KRR_E_INVAL for m < 1,
+ * k < 1 or NULL pointers. */
+int krr_val_residual(const double *f, const double *yv, int64_t m, int32_t k, double *ge, double *loss,
+                     void *stream);
+
+/* The gradient of the validation loss in (log h, log lambda) from the adjoint
+ * method's pieces, all device scalars: bta = beta^T alpha (beta the adjoint
+ * solution), dh_v = (2 / m) e^T (dK_v/dh) alpha and dh_t = beta^T (dK/dh)
+ * alpha (the dh outputs of kernel_matvec_bwd), gscale an optional upstream
+ * factor (NULL: 1):
+ *   out[0] = gscale h (dh_v - dh_t),   out[1] = -gscale lambda bta
+ * (out: 2 FP64, device).  Errors: KRR_E_INVAL for NULL pointers or h, lambda
+ * not positive. */
+int krr_val_grad_finish(const double *bta, const double *dh_v, const double *dh_t, const double *gscale,
+                        double h, double lambda, double *out, void *stream);
 
 /* out[c] = sum_i a[i, c] * b[i, c] (n x k FP64, deterministic order; device out). */
 int krr_dot_columns(const double *a, const double *b, int64_t n, int32_t k, double *out,

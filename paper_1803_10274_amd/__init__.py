@@ -18,7 +18,81 @@ import torch
 
 from . import _lib
 from ._lib import (KRR_BF16_SPLIT, KRR_F16_SPLIT, KRR_F32, KRR_F64, ClusterOpts, HssOpts, HssStats,  # noqa: F401
-                   KrrError, RefineStats, check, load)
+                   KrrError, RefineStats, check)
+from ._lib import LIB_PATH
+from ._lib import load as _load_lib
+
+# ------------------------------------------------------------ device memory
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+# every callback pair ever registered stays referenced: the library returns a
+# buffer to the allocator that made it, also after another one is registered
+_allocators = []
+_alloc_live = [True]
+
+
+def _torch_alloc(size, stream, ctx):
+    try:
+        return torch.cuda.caching_allocator_alloc(int(size), stream=int(stream or 0))
+    except Exception:  # out of memory: the library reports KRR_E_NOMEM
+        return None
+
+
+def _torch_free(ptr, stream, ctx):
+    if _alloc_live[0] and ptr:
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+
+def _at_exit():
+    # buffers still held at interpreter exit are left to the process's end
+    _alloc_live[0] = False
+
+
+import atexit  # noqa: E402
+
+atexit.register(_at_exit)
+
+
+def set_allocator(alloc=None, free=None):
+    """Register device-memory callbacks for every library buffer:
+    alloc(size, stream) -> int device pointer (0 / None on failure),
+    free(ptr, stream).  No arguments: torch's caching allocator.  Returns
+    the registered pair."""
+    if alloc is None and free is None:
+        alloc, free = _torch_alloc, _torch_free
+    else:
+        a_, f_ = alloc, free
+        alloc = lambda size, stream, ctx: a_(size, stream)  # noqa: E731
+        free = lambda ptr, stream, ctx: f_(ptr, stream)  # noqa: E731
+    pair = (ALLOC_FN(alloc), FREE_FN(free))
+    _allocators.append(pair)
+    check(_load_lib().krr_set_allocator(ctypes.cast(pair[0], ctypes.c_void_p),
+                                        ctypes.cast(pair[1], ctypes.c_void_p), None))
+    return pair
+
+
+def use_hip_malloc():
+    """New library buffers from hipMalloc / hipFree again."""
+    check(_load_lib().krr_set_allocator(None, None, None))
+
+
+def alloc_counts():
+    """(direct hipMalloc allocations, allocations through the registered allocator) so far."""
+    d, c = ctypes.c_int64(), ctypes.c_int64()
+    check(_load_lib().krr_alloc_counts(ctypes.byref(d), ctypes.byref(c)))
+    return d.value, c.value
+
+
+def load(path: str = LIB_PATH):
+    """Load libkrr.so (raises if it is missing); on the first load with a GPU
+    present, torch's caching allocator becomes the library's allocator, so
+    torch owns all device memory."""
+    first = _lib._lib is None
+    lib = _load_lib(path)
+    if first and torch.cuda.is_available():
+        set_allocator()
+    return lib
 
 PREC = {"f64": KRR_F64, "f32": KRR_F32, "f16": KRR_F16_SPLIT, "bf16": KRR_BF16_SPLIT}
 
@@ -92,6 +166,27 @@ def cluster_2mn(X: torch.Tensor, leaf: int, seed: int, max_iter: int = 100):
     h = ctypes.c_void_p()
     check(load().krr_cluster_2mn(_p(X), _xprec(X), n, d, ctypes.byref(opts), _stream(), _p(perm),
                                  ctypes.byref(h)))
+    return perm, Tree(h)
+
+
+ORDERINGS = {"2mn": 0, "np": 1, "kd": 2, "pca": 3}
+
+
+def cluster_order(X: torch.Tensor, leaf: int, method: str, offsets=None, seed: int = 7, max_iter: int = 100):
+    """Ordering and cluster tree by "2mn", "np", "kd" or "pca" (a forest when
+    offsets, np + 1 host ints, is given); returns (perm int64 tensor, Tree)."""
+    _dev(X)
+    n, d = X.shape
+    perm = torch.empty(n, dtype=torch.int64, device=X.device)
+    opts = ClusterOpts(int(leaf), int(max_iter), int(seed) & (2**64 - 1))
+    h = ctypes.c_void_p()
+    if offsets is None:
+        offp, npb = None, 0
+    else:
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        offp, npb = _i64p(off), len(off) - 1
+    check(load().krr_cluster_order(_p(X), _xprec(X), n, d, ORDERINGS[method], offp, npb, ctypes.byref(opts),
+                                   _stream(), _p(perm), ctypes.byref(h)))
     return perm, Tree(h)
 
 
@@ -200,6 +295,29 @@ def dot_columns(a, b):
     b2 = _dev(b, torch.float64).reshape(b.shape[0], -1)
     out = torch.empty(a2.shape[1], dtype=torch.float64, device=a.device)
     check(load().krr_dot_columns(_p(a2), _p(b2), a2.shape[0], a2.shape[1], _p(out), _stream()))
+    return out
+
+
+def val_residual(f, yv):
+    """(ge, loss): ge = (2 / m)(f - y_v) and loss = |f - y_v|^2 / m per column
+    (FP64 device tensors, libkrr kernel)."""
+    f2 = _dev(f, torch.float64).reshape(f.shape[0], -1)
+    y2 = _dev(yv, torch.float64).reshape(yv.shape[0], -1)
+    if f2.shape != y2.shape:
+        raise ValueError("scores and targets differ in shape")
+    ge = torch.empty_like(f2)
+    loss = torch.empty(f2.shape[1], dtype=torch.float64, device=f2.device)
+    check(load().krr_val_residual(_p(f2), _p(y2), f2.shape[0], f2.shape[1], _p(ge), _p(loss), _stream()))
+    return ge, loss
+
+
+def val_grad_finish(bta, dh_v, dh_t, h, lam, gscale=None):
+    """Device tensor (2,): gscale (h (dh_v - dh_t), -lambda bta) from device scalars."""
+    args = [_dev(t, torch.float64).reshape(1) for t in (bta, dh_v, dh_t)]
+    g = None if gscale is None else _dev(gscale, torch.float64).reshape(1)
+    out = torch.empty(2, dtype=torch.float64, device=args[0].device)
+    check(load().krr_val_grad_finish(_p(args[0]), _p(args[1]), _p(args[2]), None if g is None else _p(g),
+                                     float(h), float(lam), _p(out), _stream()))
     return out
 
 

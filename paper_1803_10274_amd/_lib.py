@@ -55,8 +55,14 @@ _P = ctypes.POINTER
 SIGNATURES = {
     "krr_last_error": (ctypes.c_char_p, []),
     "krr_device_count": (ctypes.c_int, []),
+    "krr_set_allocator": (ctypes.c_int, [_vp, _vp, _vp]),
+    "krr_alloc_counts": (ctypes.c_int, [_P(_i64), _P(_i64)]),
     "krr_cluster_2mn": (ctypes.c_int, [_vp, _i32, _i64, _i32, _P(ClusterOpts), _vp, _vp, _P(_vp)]),
+    "krr_cluster_order": (ctypes.c_int, [_vp, _i32, _i64, _i32, _i32, _vp, _i32, _P(ClusterOpts), _vp, _vp,
+                                         _P(_vp)]),
     "krr_tree_from_host": (ctypes.c_int, [_vp, _i64, _P(_vp)]),
+    "krr_val_residual": (ctypes.c_int, [_vp, _vp, _i64, _i32, _vp, _vp, _vp]),
+    "krr_val_grad_finish": (ctypes.c_int, [_vp, _vp, _vp, _vp, _dbl, _dbl, _vp, _vp]),
     "krr_tree_size": (ctypes.c_int, [_vp, _P(_i64), _P(_i64)]),
     "krr_tree_export": (ctypes.c_int, [_vp, _vp, _vp]),
     "krr_tree_destroy": (None, [_vp]),

@@ -18,8 +18,8 @@ import math
 
 import torch
 
-from . import (HssOptions, ULV, cluster_2mn, gather_rows, kernel_matvec, kernel_matvec_bwd, refine, HSS,
-               scatter_rows)
+from . import (HSS, HssOptions, ULV, cluster_2mn, dot_columns, gather_rows, kernel_matvec, kernel_matvec_bwd,
+               refine, val_grad_finish, val_residual)
 
 
 class KernelMatvec(torch.autograd.Function):
@@ -97,35 +97,30 @@ class ValidationLoss(torch.autograd.Function):
         lam = math.exp(float(log_lam))
         H, F, a, info = _fit_alpha(st, h, lam, st.opts, st.tol, st.max_iter)
         f = kernel_matvec(st.Xv, st.Xp, h, a, prec=st.prec)
-        e = f[:, 0] - st.yv
-        mv = st.Xv.shape[0]
-        L = float((e * e).sum().item() / mv)
+        # ge = (2 / m_v)(f - y_v), L = |f - y_v|^2 / m_v
+        ge, loss = val_residual(f, st.yv.reshape(-1, 1))
         ctx.st, ctx.h, ctx.lam = st, h, lam
-        ctx.keep = (H, F, a, e)
+        ctx.keep = (H, F, a, ge)
         st.last_info = info
-        return torch.tensor(L, dtype=torch.float64, device=log_h.device)
+        return loss.reshape(())
 
     @staticmethod
     def backward(ctx, gL):
         st, h, lam = ctx.st, ctx.h, ctx.lam
-        H, F, a, e = ctx.keep
-        mv = st.Xv.shape[0]
-        Ge = (2.0 / mv) * e.reshape(-1, 1)
+        H, F, a, ge = ctx.keep
         # g = (2 / m_v) K(Xp, Xv) e
-        g = kernel_matvec(st.Xp, st.Xv, h, Ge.contiguous(), prec=st.prec)
+        g = kernel_matvec(st.Xp, st.Xv, h, ge, prec=st.prec)
         # adjoint solve with the same (symmetric) preconditioner
         beta = F.solve(g)
         refine(F, st.Xp, h, lam, g, beta, tol=st.tol, max_iter=st.max_iter, mv_prec=st.prec)
-        dL_dlam = -float((beta * a).sum().item())
+        bta = dot_columns(beta, a)
         # (2 / m_v) e^T dK_v/dh alpha and beta^T dK/dh alpha, both the fused backward's dh
-        t1 = kernel_matvec_bwd(st.Xv, st.Xp, h, a, Ge.contiguous(), prec=st.prec, want=("dh",))["dh"].item()
-        t2 = kernel_matvec_bwd(st.Xp, st.Xp, h, a, beta.contiguous(), prec=st.prec, want=("dh",))["dh"].item()
-        dL_dh = t1 - t2
-        st.last_grad = (h * dL_dh, lam * dL_dlam)
-        go = float(gL)
-        dev = gL.device
-        return (torch.tensor(go * h * dL_dh, dtype=torch.float64, device=dev),
-                torch.tensor(go * lam * dL_dlam, dtype=torch.float64, device=dev), None)
+        dh_v = kernel_matvec_bwd(st.Xv, st.Xp, h, a, ge, prec=st.prec, want=("dh",))["dh"]
+        dh_t = kernel_matvec_bwd(st.Xp, st.Xp, h, a, beta.contiguous(), prec=st.prec, want=("dh",))["dh"]
+        # (dL/dlog h, dL/dlog lambda) scaled by the upstream gradient
+        out = val_grad_finish(bta, dh_v, dh_t, h, lam, gscale=gL)
+        st.last_grad = out
+        return out[0], out[1], None
 
 
 def validation_loss(log_h, log_lam, X, y, Xv, yv, leaf=128, opts: HssOptions = None, tol=1e-6, max_iter=300,

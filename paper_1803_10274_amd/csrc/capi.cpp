@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -14,6 +15,18 @@
 namespace krr {
 
 thread_local std::string g_last_error;
+thread_local hipStream_t g_call_stream = nullptr;
+
+std::mutex g_alloc_mu;
+Allocator g_alloc;
+std::atomic<int64_t> g_alloc_direct{0}, g_alloc_caller{0};
+
+Allocator current_allocator() {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    return g_alloc;
+}
+hipStream_t call_stream() { return g_call_stream; }
+void note_allocation(bool by_caller) { (by_caller ? g_alloc_caller : g_alloc_direct).fetch_add(1); }
 
 std::atomic<int> g_tune[KRR_TUNE_COUNT] = {{4}, {8}, {2048}, {16384}};
 
@@ -42,6 +55,7 @@ namespace {
 template <class F> int guard(F &&f) {
     try {
         g_last_error.clear();
+        g_call_stream = nullptr;
         return f();
     } catch (const Error &e) {
         g_last_error = e.what();
@@ -66,7 +80,11 @@ void require_device() {
     }
 }
 
-hipStream_t S(void *p) { return static_cast<hipStream_t>(p); }
+// The call's stream; library temporaries are allocated on it.
+hipStream_t S(void *p) {
+    g_call_stream = static_cast<hipStream_t>(p);
+    return g_call_stream;
+}
 
 void check_xprec(int32_t xprec) {
     KRR_REQUIRE(xprec == KRR_F32 || xprec == KRR_F64, "point dtype must be KRR_F32 or KRR_F64 (got %d)", xprec);
@@ -185,6 +203,24 @@ extern "C" {
 
 const char *krr_last_error(void) { return g_last_error.c_str(); }
 
+int krr_set_allocator(void *(*alloc)(size_t, void *, void *), void (*dealloc)(void *, void *, void *), void *ctx) {
+    return guard([&] {
+        KRR_REQUIRE((alloc == nullptr) == (dealloc == nullptr), "krr_set_allocator: give both functions or neither");
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        g_alloc = Allocator{alloc, dealloc, ctx};
+        return KRR_OK;
+    });
+}
+
+int krr_alloc_counts(int64_t *direct, int64_t *by_caller) {
+    return guard([&] {
+        KRR_REQUIRE(direct != nullptr && by_caller != nullptr, "krr_alloc_counts: NULL argument");
+        *direct = g_alloc_direct.load();
+        *by_caller = g_alloc_caller.load();
+        return KRR_OK;
+    });
+}
+
 int krr_device_count(void) {
     int cnt = 0;
     if (hipGetDeviceCount(&cnt) != hipSuccess) {
@@ -208,6 +244,40 @@ int krr_cluster_2mn(const void *X, int32_t xprec, int64_t n, int32_t d, const kr
         auto *t = new krr_tree_s();
         try {
             cluster_2mn(X, xprec, n, d, std::vector<int64_t>{0, n}, *opts, S(stream), perm, *t);
+        } catch (...) {
+            delete t;
+            throw;
+        }
+        *out = t;
+        return KRR_OK;
+    });
+}
+
+int krr_cluster_order(const void *X, int32_t xprec, int64_t n, int32_t d, int32_t method, const int64_t *offsets,
+                      int32_t np, const krr_cluster_opts *opts, void *stream, int64_t *perm, krr_tree *out) {
+    return guard([&] {
+        KRR_REQUIRE(out != nullptr && opts != nullptr, "krr_cluster_order: NULL opts or out");
+        *out = nullptr;
+        check_xprec(xprec);
+        KRR_REQUIRE(method >= KRR_ORDER_2MN && method <= KRR_ORDER_PCA, "krr_cluster_order: unknown method %d",
+                    method);
+        std::vector<int64_t> roots{0, n};
+        if (offsets) {
+            KRR_REQUIRE(np >= 1 && offsets[0] == 0, "krr_cluster_order: need np >= 1 and offsets[0] = 0");
+            for (int k = 0; k < np; ++k)
+                KRR_REQUIRE(offsets[k + 1] > offsets[k], "krr_cluster_order: problem %d is empty", k);
+            KRR_REQUIRE(offsets[np] == n, "krr_cluster_order: offsets[np] must equal n");
+            roots.assign(offsets, offsets + np + 1);
+        }
+        KRR_REQUIRE(n >= 1 && d >= 1, "krr_cluster_order: need n >= 1 and d >= 1");
+        KRR_REQUIRE(n <= INT32_MAX, "krr_cluster_order: n must fit in int32");
+        KRR_REQUIRE(X != nullptr && perm != nullptr, "krr_cluster_order: NULL X or perm");
+        KRR_REQUIRE(opts->leaf_size >= 1, "krr_cluster_order: leaf_size must be >= 1");
+        KRR_REQUIRE(method != KRR_ORDER_2MN || opts->max_iter >= 1, "krr_cluster_order: max_iter must be >= 1");
+        require_device();
+        auto *t = new krr_tree_s();
+        try {
+            cluster_2mn(X, xprec, n, d, roots, *opts, S(stream), perm, *t, method);
         } catch (...) {
             delete t;
             throw;
@@ -363,7 +433,13 @@ int hss_compress(krr_tree t, const void *Xp, int32_t xprec, int32_t d, double h,
     });
 }
 
-void hss_destroy(hss_t H) { delete H; }
+// Handle storage goes back to its allocator once every stream is done with
+// it (hipFree synchronizes implicitly; a stream-ordered allocator does not).
+void hss_destroy(hss_t H) {
+    if (!H) return;
+    (void)hipDeviceSynchronize();
+    delete H;
+}
 
 int hss_matvec(hss_t H, const double *x, int32_t nrhs, double *y, void *stream) {
     return guard([&] {
@@ -474,7 +550,11 @@ int hss_ulv_factor_shifted(hss_t H, double lambda, void *stream, hss_ulv_t *out,
     });
 }
 
-void hss_ulv_destroy(hss_ulv_t F) { delete F; }
+void hss_ulv_destroy(hss_ulv_t F) {
+    if (!F) return;
+    (void)hipDeviceSynchronize();
+    delete F;
+}
 
 int hss_ulv_use_graph(hss_ulv_t F, int32_t enable) {
     return guard([&] {
@@ -550,6 +630,28 @@ int krr_get_tuning(int32_t knob, int32_t *value_host) {
     return guard([&] {
         KRR_REQUIRE(knob >= 0 && knob < KRR_TUNE_COUNT && value_host, "krr_get_tuning: bad arguments");
         *value_host = tune_get(knob);
+        return KRR_OK;
+    });
+}
+
+int krr_val_residual(const double *f, const double *yv, int64_t m, int32_t k, double *ge, double *loss,
+                     void *stream) {
+    return guard([&] {
+        KRR_REQUIRE(f && yv && ge && loss, "krr_val_residual: NULL pointer");
+        KRR_REQUIRE(m >= 1 && k >= 1, "krr_val_residual: need m >= 1 and k >= 1");
+        require_device();
+        val_residual(f, yv, m, k, ge, loss, S(stream));
+        return KRR_OK;
+    });
+}
+
+int krr_val_grad_finish(const double *bta, const double *dh_v, const double *dh_t, const double *gscale, double h,
+                        double lambda, double *out, void *stream) {
+    return guard([&] {
+        KRR_REQUIRE(bta && dh_v && dh_t && out, "krr_val_grad_finish: NULL pointer");
+        KRR_REQUIRE(h > 0.0 && lambda > 0.0, "krr_val_grad_finish: h and lambda must be positive");
+        require_device();
+        val_grad_finish(bta, dh_v, dh_t, gscale, h, lambda, out, S(stream));
         return KRR_OK;
     });
 }

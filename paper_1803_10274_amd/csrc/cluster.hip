@@ -18,6 +18,20 @@
 //   * empty cluster / all-equal points: split in halves by position;
 //   * stable partition, first cluster first.
 // draw() chains four SplitMix64 output steps over (seed, b, e, k).
+//
+// The same driver builds the other orderings the paper compares (Section 4.3,
+// "Selected Preprocessing Methods"), with the same stable partition and tree:
+//   * NP: no reordering, halves by position;
+//   * KD: coordinate of maximum spread (max - min, lowest index on ties), split
+//     at its mean (chunked sum as the centroids), left = coordinate <= mean;
+//     if 100 min(left, right) < max(left, right), the floor(size / 2) points
+//     first in (coordinate, position) order go left (median), found by an
+//     8-pass radix select on the order-preserving bit pattern of the key;
+//     zero spread splits in halves;
+//   * PCA: mean point mu, 32 power steps v <- C v / max|C v| from v = 1 with
+//     C v = sum_j (x_j - mu) ((x_j - mu) . v) (chunked sums), projections
+//     p_j = (x_j - mu) . v, left = p_j <= their chunked mean; an empty side or
+//     C v = 0 splits in halves.
 #include "internal.hpp"
 
 // This file is compiled with -ffp-contract=off; the pragma keeps it so even if
@@ -29,7 +43,8 @@ namespace {
 
 constexpr int CH = 256;  // positions per chunk (also the block size of point kernels)
 constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
-enum : int32_t { ACTIVE = 0, CONVERGED = 1, FALLBACK = 2 };
+enum : int32_t { ACTIVE = 0, CONVERGED = 1, FALLBACK = 2, MEDIAN = 3 };
+constexpr int PCA_ITERS = 32;
 
 uint64_t sm_out(uint64_t x) {
     uint64_t z = x + kGamma;
@@ -101,6 +116,12 @@ struct Level {
     int32_t *cn1;
     double *cps;
     int32_t *n_active;
+    // orderings
+    int32_t *kstar;
+    double *nmean, *c2;
+    uint64_t *pfx;
+    int64_t *krem, *cless;
+    int32_t *hist;
 };
 
 template <class T>
@@ -329,15 +350,385 @@ __global__ void k_perm_init(int64_t n, int64_t *perm) {
     if (p < n) perm[p] = p;
 }
 
+// ------------------------------------------------------------- orderings
+
+// KD: min and max of each coordinate over each chunk (exact, first occurrence
+// kept on equal values, as a scan from the node's first point would).
+template <class T>
+__global__ void k_kd_minmax(const T *__restrict__ X, int d, int nc, Level L) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)nc * d) return;
+    int c = (int)(t / d), k = (int)(t % d);
+    if (L.status[L.cnode[c]] != ACTIVE) return;
+    double lo = (double)X[L.cb[c] * d + k], hi = lo;
+    for (int64_t p = L.cb[c] + 1; p < L.ce[c]; ++p) {
+        double v = (double)X[p * d + k];
+        if (v < lo) lo = v;
+        if (v > hi) hi = v;
+    }
+    L.cps[2 * t] = lo;
+    L.cps[2 * t + 1] = hi;
+}
+
+// KD: coordinate of maximum spread per node (lowest index on ties).
+__global__ void k_kd_pick(int d, int na, Level L) {
+    int node = blockIdx.x * blockDim.x + threadIdx.x;
+    if (node >= na || L.status[node] != ACTIVE) return;
+    double best = -1.0;
+    int kb = 0;
+    const int c0 = L.ch0[node], c1 = L.ch0[node] + L.nch[node];
+    for (int k = 0; k < d; ++k) {
+        double lo = L.cps[2 * ((int64_t)c0 * d + k)], hi = L.cps[2 * ((int64_t)c0 * d + k) + 1];
+        for (int c = c0 + 1; c < c1; ++c) {
+            double a = L.cps[2 * ((int64_t)c * d + k)], b = L.cps[2 * ((int64_t)c * d + k) + 1];
+            if (a < lo) lo = a;
+            if (b > hi) hi = b;
+        }
+        double spread = hi - lo;
+        if (spread > best) {
+            best = spread;
+            kb = k;
+        }
+    }
+    if (!(best > 0.0))
+        L.status[node] = FALLBACK;
+    else
+        L.kstar[node] = kb;
+}
+
+// KD: the key of each point (the chosen coordinate, -0 made +0) and its
+// chunk sum in position order.
+template <class T>
+__global__ void k_kd_key(const T *__restrict__ X, int d, int nc, Level L, double *__restrict__ key) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    int node = L.cnode[c];
+    if (L.status[node] != ACTIVE) return;
+    const int k = L.kstar[node];
+    double part = 0.0;
+    for (int64_t p = L.cb[c]; p < L.ce[c]; ++p) {
+        double v = (double)X[p * d + k] + 0.0;
+        key[p] = v;
+        part = part + v;
+    }
+    L.cps[c] = part;
+}
+
+// Chunk sums of a node added in chunk order, divided by the node size.
+__global__ void k_node_mean(int na, Level L) {
+    int node = blockIdx.x * blockDim.x + threadIdx.x;
+    if (node >= na || L.status[node] != ACTIVE) return;
+    double s = 0.0;
+    for (int c = L.ch0[node]; c < L.ch0[node] + L.nch[node]; ++c) s = s + L.cps[c];
+    L.nmean[node] = s / (double)(L.ne[node] - L.nb[node]);
+}
+
+// label 1 iff key > the node's threshold; label-1 count per chunk
+__global__ void k_thresh_assign(Level L, const double *__restrict__ key, uint8_t *__restrict__ lab) {
+    __shared__ int part[CH / 64];
+    int c = blockIdx.x;
+    int node = L.cnode[c];
+    if (L.status[node] != ACTIVE) return;
+    int64_t p = L.cb[c] + threadIdx.x;
+    int one = 0;
+    if (p < L.ce[c]) {
+        one = key[p] <= L.nmean[node] ? 0 : 1;
+        lab[p] = (uint8_t)one;
+    }
+    int s = wave_sum(one);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int i = 0; i < CH / 64; ++i) t += part[i];
+        L.cn1[c] = t;
+    }
+}
+
+// KD: left size from the mean split, or the median fallback when one side
+// is more than 100 times the other.
+__global__ void k_kd_update(int na, Level L) {
+    int node = blockIdx.x * blockDim.x + threadIdx.x;
+    if (node >= na || L.status[node] != ACTIVE) return;
+    int64_t n1 = 0;
+    for (int c = L.ch0[node]; c < L.ch0[node] + L.nch[node]; ++c) n1 += L.cn1[c];
+    const int64_t s = L.ne[node] - L.nb[node], n0 = s - n1;
+    const int64_t mn = n0 < n1 ? n0 : n1, mx = n0 < n1 ? n1 : n0;
+    if (100 * mn < mx) {
+        L.status[node] = MEDIAN;
+        L.pfx[node] = 0;
+        L.krem[node] = s / 2 - 1;  // 0-based rank of the last left point
+        L.cless[node] = 0;
+    } else {
+        L.n1[node] = n1;
+    }
+}
+
+// order-preserving map of an FP64 value (no -0, no NaN) to uint64
+__device__ __forceinline__ uint64_t ordered_bits(double v) {
+    uint64_t u = (uint64_t)__double_as_longlong(v);
+    return (u >> 63) ? ~u : (u | (1ull << 63));
+}
+
+// Radix-select pass: histogram of the 8-bit digit at `shift` among the keys
+// whose higher digits equal the node's prefix.
+__global__ void k_kd_hist(Level L, const double *__restrict__ key, int shift) {
+    int c = blockIdx.x;
+    int node = L.cnode[c];
+    if (L.status[node] != MEDIAN) return;
+    int64_t p = L.cb[c] + threadIdx.x;
+    if (p >= L.ce[c]) return;
+    const uint64_t o = ordered_bits(key[p]);
+    const int hs = shift + 8;
+    const bool match = hs >= 64 || (o >> hs) == (L.pfx[node] >> hs);
+    if (match) atomicAdd(&L.hist[(int64_t)node * 256 + ((o >> shift) & 255)], 1);
+}
+
+__global__ void k_kd_select(int na, Level L, int shift) {
+    int node = blockIdx.x * blockDim.x + threadIdx.x;
+    if (node >= na || L.status[node] != MEDIAN) return;
+    int64_t cum = 0;
+    const int32_t *h = L.hist + (int64_t)node * 256;
+    for (int b = 0; b < 256; ++b) {
+        if (L.krem[node] < cum + h[b]) {
+            L.pfx[node] |= (uint64_t)b << shift;
+            L.krem[node] -= cum;
+            L.cless[node] += cum;
+            return;
+        }
+        cum += h[b];
+    }
+}
+
+// Median split: ties with the selected key per chunk, then their prefix over
+// the node's chunks in order.
+__global__ void k_kd_ties(Level L, const double *__restrict__ key) {
+    __shared__ int part[CH / 64];
+    int c = blockIdx.x;
+    int node = L.cnode[c];
+    if (L.status[node] != MEDIAN) return;
+    int64_t p = L.cb[c] + threadIdx.x;
+    int tie = p < L.ce[c] && ordered_bits(key[p]) == L.pfx[node];
+    int s = wave_sum(tie);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int i = 0; i < CH / 64; ++i) t += part[i];
+        L.cn1[c] = t;
+    }
+}
+
+__global__ void k_kd_tie_prefix(int na, Level L) {
+    int node = blockIdx.x * blockDim.x + threadIdx.x;
+    if (node >= na || L.status[node] != MEDIAN) return;
+    int64_t o = 0;
+    for (int c = L.ch0[node]; c < L.ch0[node] + L.nch[node]; ++c) {
+        L.off0[c] = o;
+        o += L.cn1[c];
+    }
+    const int64_t s = L.ne[node] - L.nb[node];
+    L.n1[node] = s - s / 2;
+}
+
+// Median labels: keys below the selected one go left, above go right, and
+// the first krem + 1 ties in position order go left.
+__global__ void k_kd_median_label(Level L, const double *__restrict__ key, uint8_t *__restrict__ lab) {
+    __shared__ int wz[CH / 64];
+    __shared__ int part[CH / 64];
+    int c = blockIdx.x;
+    int node = L.cnode[c];
+    if (L.status[node] != MEDIAN) return;
+    int64_t p = L.cb[c] + threadIdx.x;
+    const bool valid = p < L.ce[c];
+    const uint64_t o = valid ? ordered_bits(key[p]) : 0;
+    const uint64_t T = L.pfx[node];
+    const int tie = valid && o == T;
+    uint64_t mask = __ballot(tie);
+    int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    if (lane == 0) wz[wv] = __popcll(mask);
+    __syncthreads();
+    int before = __popcll(mask & lt);
+    for (int i = 0; i < wv; ++i) before += wz[i];
+    int one = 0;
+    if (valid) {
+        if (tie)
+            one = (L.off0[c] + before <= L.krem[node]) ? 0 : 1;
+        else
+            one = o < T ? 0 : 1;
+        lab[p] = (uint8_t)one;
+    }
+    int s = wave_sum(one);
+    if (lane == 0) part[wv] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int i = 0; i < CH / 64; ++i) t += part[i];
+        L.cn1[c] = t;
+    }
+}
+
+// PCA: per (chunk, coordinate) sums of the coordinate in position order.
+template <class T>
+__global__ void k_col_partial(const T *__restrict__ X, int d, int nc, Level L) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)nc * d) return;
+    int c = (int)(t / d), k = (int)(t % d);
+    if (L.status[L.cnode[c]] != ACTIVE) return;
+    double part = 0.0;
+    for (int64_t p = L.cb[c]; p < L.ce[c]; ++p) part = part + (double)X[p * d + k];
+    L.cps[t] = part;
+}
+
+// PCA: mean point (c0) and the start vector v = 1 (c1).
+__global__ void k_pca_mean(int d, int na, Level L) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)na * d) return;
+    int node = (int)(t / d), k = (int)(t % d);
+    if (L.status[node] != ACTIVE) return;
+    double s = 0.0;
+    for (int c = L.ch0[node]; c < L.ch0[node] + L.nch[node]; ++c) s = s + L.cps[(int64_t)c * d + k];
+    L.c0[t] = s / (double)(L.ne[node] - L.nb[node]);
+    L.c1[t] = 1.0;
+}
+
+// PCA: t_p = (x_p - mu) . v, coordinates in order.
+template <class T>
+__global__ void k_pca_proj(const T *__restrict__ X, int d, Level L, double *__restrict__ q) {
+    int c = blockIdx.x;
+    int node = L.cnode[c];
+    if (L.status[node] != ACTIVE) return;
+    int64_t p = L.cb[c] + threadIdx.x;
+    if (p >= L.ce[c]) return;
+    const double *mu = L.c0 + (int64_t)node * d, *v = L.c1 + (int64_t)node * d;
+    double t = 0.0;
+    for (int k = 0; k < d; ++k) t = t + ((double)X[p * d + k] - mu[k]) * v[k];
+    q[p] = t;
+}
+
+// PCA: per (chunk, coordinate) sums of (x_pk - mu_k) t_p in position order.
+template <class T>
+__global__ void k_pca_wpart(const T *__restrict__ X, int d, int nc, Level L, const double *__restrict__ q) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)nc * d) return;
+    int c = (int)(t / d), k = (int)(t % d);
+    int node = L.cnode[c];
+    if (L.status[node] != ACTIVE) return;
+    const double mu = L.c0[(int64_t)node * d + k];
+    double part = 0.0;
+    for (int64_t p = L.cb[c]; p < L.ce[c]; ++p) part = part + ((double)X[p * d + k] - mu) * q[p];
+    L.cps[t] = part;
+}
+
+// PCA: w = C v (chunk sums in order), v <- w / max|w_k|.
+__global__ void k_pca_step(int d, int na, Level L) {
+    int node = blockIdx.x * blockDim.x + threadIdx.x;
+    if (node >= na || L.status[node] != ACTIVE) return;
+    double *w = L.c2 + (int64_t)node * d, *v = L.c1 + (int64_t)node * d;
+    double nrm = 0.0;
+    for (int k = 0; k < d; ++k) {
+        double s = 0.0;
+        for (int c = L.ch0[node]; c < L.ch0[node] + L.nch[node]; ++c) s = s + L.cps[(int64_t)c * d + k];
+        w[k] = s;
+        if (fabs(s) > nrm) nrm = fabs(s);
+    }
+    if (!(nrm > 0.0)) {
+        L.status[node] = FALLBACK;
+        return;
+    }
+    for (int k = 0; k < d; ++k) v[k] = w[k] / nrm;
+}
+
+// PCA: chunk sums of the projections in position order.
+__global__ void k_chunk_sum(int nc, Level L, const double *__restrict__ q) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc || L.status[L.cnode[c]] != ACTIVE) return;
+    double part = 0.0;
+    for (int64_t p = L.cb[c]; p < L.ce[c]; ++p) part = part + q[p];
+    L.cps[c] = part;
+}
+
+// PCA: left size, or the halves fallback for an empty side.
+__global__ void k_pca_update(int na, Level L) {
+    int node = blockIdx.x * blockDim.x + threadIdx.x;
+    if (node >= na || L.status[node] != ACTIVE) return;
+    int64_t n1 = 0;
+    for (int c = L.ch0[node]; c < L.ch0[node] + L.nch[node]; ++c) n1 += L.cn1[c];
+    const int64_t s = L.ne[node] - L.nb[node];
+    if (n1 == 0 || n1 == s)
+        L.status[node] = FALLBACK;
+    else
+        L.n1[node] = n1;
+}
+
 struct TmpNode {
     int64_t b, e;
     int64_t base;                   // first position of the node's problem
     int64_t left = -1, right = -1;  // indices into the TmpNode list
 };
 
+// Labels, left sizes and statuses of one level's nodes by one of the other
+// orderings (NP needs no launch: every node splits in halves).
+template <class T>
+void order_level(int method, const T *Xc, int d, int na, int nc, Level &L, double *key, uint8_t *lab, hipStream_t s) {
+    const unsigned gn = ceil_div(na, 64), gnd = ceil_div((int64_t)na * d, 256);
+    const unsigned gcd = ceil_div((int64_t)nc * d, 256), gc = ceil_div(nc, 64);
+    if (method == KRR_ORDER_KD) {
+        k_kd_minmax<T><<<gcd, 256, 0, s>>>(Xc, d, nc, L);
+        check_launch("k_kd_minmax");
+        k_kd_pick<<<gn, 64, 0, s>>>(d, na, L);
+        check_launch("k_kd_pick");
+        k_kd_key<T><<<gc, 64, 0, s>>>(Xc, d, nc, L, key);
+        check_launch("k_kd_key");
+        k_node_mean<<<gn, 64, 0, s>>>(na, L);
+        check_launch("k_node_mean");
+        k_thresh_assign<<<nc, CH, 0, s>>>(L, key, lab);
+        check_launch("k_thresh_assign");
+        k_kd_update<<<gn, 64, 0, s>>>(na, L);
+        check_launch("k_kd_update");
+        for (int shift = 56; shift >= 0; shift -= 8) {
+            KRR_HIP(hipMemsetAsync(L.hist, 0, sizeof(int32_t) * 256 * (size_t)na, s));
+            k_kd_hist<<<nc, CH, 0, s>>>(L, key, shift);
+            check_launch("k_kd_hist");
+            k_kd_select<<<gn, 64, 0, s>>>(na, L, shift);
+            check_launch("k_kd_select");
+        }
+        k_kd_ties<<<nc, CH, 0, s>>>(L, key);
+        check_launch("k_kd_ties");
+        k_kd_tie_prefix<<<gn, 64, 0, s>>>(na, L);
+        check_launch("k_kd_tie_prefix");
+        k_kd_median_label<<<nc, CH, 0, s>>>(L, key, lab);
+        check_launch("k_kd_median_label");
+    } else if (method == KRR_ORDER_PCA) {
+        k_col_partial<T><<<gcd, 256, 0, s>>>(Xc, d, nc, L);
+        check_launch("k_col_partial");
+        k_pca_mean<<<gnd, 256, 0, s>>>(d, na, L);
+        check_launch("k_pca_mean");
+        for (int it = 0; it < PCA_ITERS; ++it) {
+            k_pca_proj<T><<<nc, CH, 0, s>>>(Xc, d, L, key);
+            check_launch("k_pca_proj");
+            k_pca_wpart<T><<<gcd, 256, 0, s>>>(Xc, d, nc, L, key);
+            check_launch("k_pca_wpart");
+            k_pca_step<<<gn, 64, 0, s>>>(d, na, L);
+            check_launch("k_pca_step");
+        }
+        k_pca_proj<T><<<nc, CH, 0, s>>>(Xc, d, L, key);
+        check_launch("k_pca_proj");
+        k_chunk_sum<<<gc, 64, 0, s>>>(nc, L, key);
+        check_launch("k_chunk_sum");
+        k_node_mean<<<gn, 64, 0, s>>>(na, L);
+        check_launch("k_node_mean");
+        k_thresh_assign<<<nc, CH, 0, s>>>(L, key, lab);
+        check_launch("k_thresh_assign");
+        k_pca_update<<<gn, 64, 0, s>>>(na, L);
+        check_launch("k_pca_update");
+    }
+}
+
 template <class T>
 void cluster_impl(const T *X, int64_t n, int d, const std::vector<int64_t> &roots, const krr_cluster_opts &o,
-                  hipStream_t s, int64_t *perm_out, krr_tree_s &tree) {
+                  int method, hipStream_t s, int64_t *perm_out, krr_tree_s &tree) {
     const int leaf = o.leaf_size;
     DBuf xa = dalloc<T>(n * d), xb = dalloc<T>(n * d);
     DBuf pa = dalloc<int64_t>(n), pb = dalloc<int64_t>(n);
@@ -390,7 +781,10 @@ void cluster_impl(const T *X, int64_t n, int d, const std::vector<int64_t> &root
              d_W = dalloc<uint64_t>(na), d_status = dalloc<int32_t>(na), d_changed = dalloc<int32_t>(na),
              d_iters = dalloc<int32_t>(na), d_c0 = dalloc<double>((size_t)na * d),
              d_c1 = dalloc<double>((size_t)na * d), d_off0 = dalloc<int64_t>(nc), d_off1 = dalloc<int64_t>(nc),
-             d_cw = dalloc<uint64_t>(nc), d_cn1 = dalloc<int32_t>(nc), d_cps = dalloc<double>((size_t)nc * d * 2);
+             d_cw = dalloc<uint64_t>(nc), d_cn1 = dalloc<int32_t>(nc), d_cps = dalloc<double>((size_t)nc * d * 2),
+             d_kstar = dalloc<int32_t>(na), d_nmean = dalloc<double>(na), d_c2 = dalloc<double>((size_t)na * d),
+             d_pfx = dalloc<uint64_t>(na), d_krem = dalloc<int64_t>(na), d_cless = dalloc<int64_t>(na),
+             d_hist = dalloc<int32_t>(method == KRR_ORDER_KD ? (size_t)na * 256 : 1);
         KRR_HIP(hipMemsetAsync(d_qmax.get(), 0, sizeof(uint64_t) * na, s));
         KRR_HIP(hipMemsetAsync(d_W.get(), 0, sizeof(uint64_t) * na, s));
         KRR_HIP(hipMemsetAsync(d_status.get(), 0, sizeof(int32_t) * na, s));
@@ -402,66 +796,79 @@ void cluster_impl(const T *X, int64_t n, int d, const std::vector<int64_t> &root
                 d_changed.as<int32_t>(), d_iters.as<int32_t>(), d_c0.as<double>(), d_c1.as<double>(),
                 d_off0.as<int64_t>(), d_off1.as<int64_t>(), d_cnode.as<int32_t>(), d_cb.as<int64_t>(),
                 d_ce.as<int64_t>(), d_cw.as<uint64_t>(), d_cn1.as<int32_t>(), d_cps.as<double>(),
-                counter.as<int32_t>()};
+                counter.as<int32_t>(), d_kstar.as<int32_t>(), d_nmean.as<double>(), d_c2.as<double>(),
+                d_pfx.as<uint64_t>(), d_krem.as<int64_t>(), d_cless.as<int64_t>(), d_hist.as<int32_t>()};
         const T *Xc = xa.as<T>();
         unsigned gn = ceil_div(na, 64);
         unsigned gnd = ceil_div((int64_t)na * d, 256);
-        k_q<T><<<nc, CH, 0, s>>>(Xc, d, L, q.as<double>());
-        check_launch("k_q");
-        k_w<<<nc, CH, 0, s>>>(L, q.as<double>(), w.as<uint64_t>());
-        check_launch("k_w");
-        k_pick<<<gn, 64, 0, s>>>(L, na, w.as<uint64_t>());
-        check_launch("k_pick");
-        k_seed_centers<T><<<gnd, 256, 0, s>>>(Xc, d, na, L);
-        check_launch("k_seed_centers");
-        k_assign<T><<<nc, CH, 0, s>>>(Xc, d, L, lab.as<uint8_t>(), 1);
-        check_launch("k_assign");
-        KRR_HIP(hipMemsetAsync(counter.get(), 0, sizeof(int32_t), s));
-        k_node_update<<<gn, 64, 0, s>>>(L, na, 1);
-        check_launch("k_node_update");
-        for (int it = 0; it < o.max_iter; ++it) {
-            int32_t nact = 0;
-            d2h(&nact, counter.as<int32_t>(), 1, s);
-            sync(s);
-            if (nact == 0) break;
-            k_centroid_partial<T><<<ceil_div((int64_t)nc * d, 256), 256, 0, s>>>(Xc, d, nc, L, lab.as<uint8_t>());
-            check_launch("k_centroid_partial");
-            k_centroid_final<<<gnd, 256, 0, s>>>(d, na, L);
-            check_launch("k_centroid_final");
-            k_assign<T><<<nc, CH, 0, s>>>(Xc, d, L, lab.as<uint8_t>(), 0);
-            check_launch("k_assign");
-            KRR_HIP(hipMemsetAsync(counter.get(), 0, sizeof(int32_t), s));
-            k_node_update<<<gn, 64, 0, s>>>(L, na, 0);
-            check_launch("k_node_update");
-        }
-        k_part_prefix<<<gn, 64, 0, s>>>(L, na);
-        check_launch("k_part_prefix");
-        k_iota<<<ceil_div(n, 256), 256, 0, s>>>(n, dest.as<int64_t>());
-        check_launch("k_iota");
-        k_part_dest<<<nc, CH, 0, s>>>(L, lab.as<uint8_t>(), dest.as<int64_t>());
-        check_launch("k_part_dest");
-        k_move<T><<<ceil_div(n * d, 256), 256, 0, s>>>(xa.as<T>(), pa.as<int64_t>(), n, d, dest.as<int64_t>(),
-                                                        xb.as<T>(), pb.as<int64_t>());
-        check_launch("k_move");
-        std::swap(xa, xb);
-        std::swap(pa, pb);
         std::vector<int64_t> n1(na);
         std::vector<int32_t> status(na), iters(na);
-        d2h(n1.data(), d_n1.as<int64_t>(), na, s);
-        d2h(status.data(), d_status.as<int32_t>(), na, s);
-        d2h(iters.data(), d_iters.as<int32_t>(), na, s);
-        sync(s);
+        if (method == KRR_ORDER_NP) {
+            // no reordering: every node splits in halves, nothing moves
+            std::fill(status.begin(), status.end(), (int32_t)FALLBACK);
+        } else if (method != KRR_ORDER_2MN) {
+            order_level<T>(method, Xc, d, na, nc, L, q.as<double>(), lab.as<uint8_t>(), s);
+        }
+        if (method == KRR_ORDER_2MN) {
+            k_q<T><<<nc, CH, 0, s>>>(Xc, d, L, q.as<double>());
+            check_launch("k_q");
+            k_w<<<nc, CH, 0, s>>>(L, q.as<double>(), w.as<uint64_t>());
+            check_launch("k_w");
+            k_pick<<<gn, 64, 0, s>>>(L, na, w.as<uint64_t>());
+            check_launch("k_pick");
+            k_seed_centers<T><<<gnd, 256, 0, s>>>(Xc, d, na, L);
+            check_launch("k_seed_centers");
+            k_assign<T><<<nc, CH, 0, s>>>(Xc, d, L, lab.as<uint8_t>(), 1);
+            check_launch("k_assign");
+            KRR_HIP(hipMemsetAsync(counter.get(), 0, sizeof(int32_t), s));
+            k_node_update<<<gn, 64, 0, s>>>(L, na, 1);
+            check_launch("k_node_update");
+            for (int it = 0; it < o.max_iter; ++it) {
+                int32_t nact = 0;
+                d2h(&nact, counter.as<int32_t>(), 1, s);
+                sync(s);
+                if (nact == 0) break;
+                k_centroid_partial<T><<<ceil_div((int64_t)nc * d, 256), 256, 0, s>>>(Xc, d, nc, L, lab.as<uint8_t>());
+                check_launch("k_centroid_partial");
+                k_centroid_final<<<gnd, 256, 0, s>>>(d, na, L);
+                check_launch("k_centroid_final");
+                k_assign<T><<<nc, CH, 0, s>>>(Xc, d, L, lab.as<uint8_t>(), 0);
+                check_launch("k_assign");
+                KRR_HIP(hipMemsetAsync(counter.get(), 0, sizeof(int32_t), s));
+                k_node_update<<<gn, 64, 0, s>>>(L, na, 0);
+                check_launch("k_node_update");
+            }
+        }
+        if (method != KRR_ORDER_NP) {
+            k_part_prefix<<<gn, 64, 0, s>>>(L, na);
+            check_launch("k_part_prefix");
+            k_iota<<<ceil_div(n, 256), 256, 0, s>>>(n, dest.as<int64_t>());
+            check_launch("k_iota");
+            k_part_dest<<<nc, CH, 0, s>>>(L, lab.as<uint8_t>(), dest.as<int64_t>());
+            check_launch("k_part_dest");
+            k_move<T><<<ceil_div(n * d, 256), 256, 0, s>>>(xa.as<T>(), pa.as<int64_t>(), n, d, dest.as<int64_t>(),
+                                                            xb.as<T>(), pb.as<int64_t>());
+            check_launch("k_move");
+            std::swap(xa, xb);
+            std::swap(pa, pb);
+            d2h(n1.data(), d_n1.as<int64_t>(), na, s);
+            d2h(status.data(), d_status.as<int32_t>(), na, s);
+            d2h(iters.data(), d_iters.as<int32_t>(), na, s);
+            sync(s);
+        }
         std::vector<int64_t> next;
         for (int a = 0; a < na; ++a) {
             int64_t id = active[a];
             int64_t b = tn[id].b, e = tn[id].e, sz = e - b;
             int64_t nl;
-            iterations += iters[a];
+            if (method == KRR_ORDER_2MN) iterations += iters[a];
             if (status[a] == FALLBACK) {
-                ++fallbacks;
+                if (method != KRR_ORDER_NP) ++fallbacks;
                 nl = sz / 2;
             } else {
-                if (status[a] == ACTIVE) ++capped;
+                // 2MN: a split still active after max_iter hit the cap; KD: a
+                // median split
+                if ((method == KRR_ORDER_2MN && status[a] == ACTIVE) || status[a] == MEDIAN) ++capped;
                 nl = sz - n1[a];
             }
             int64_t li = (int64_t)tn.size();
@@ -518,11 +925,11 @@ void cluster_impl(const T *X, int64_t n, int d, const std::vector<int64_t> &root
 }  // namespace
 
 void cluster_2mn(const void *X, int32_t xprec, int64_t n, int32_t d, const std::vector<int64_t> &roots,
-                 const krr_cluster_opts &o, hipStream_t s, int64_t *perm, krr_tree_s &tree) {
+                 const krr_cluster_opts &o, hipStream_t s, int64_t *perm, krr_tree_s &tree, int32_t method) {
     if (xprec == KRR_F64)
-        cluster_impl<double>(static_cast<const double *>(X), n, d, roots, o, s, perm, tree);
+        cluster_impl<double>(static_cast<const double *>(X), n, d, roots, o, method, s, perm, tree);
     else
-        cluster_impl<float>(static_cast<const float *>(X), n, d, roots, o, s, perm, tree);
+        cluster_impl<float>(static_cast<const float *>(X), n, d, roots, o, method, s, perm, tree);
 }
 
 }  // namespace krr

@@ -43,18 +43,34 @@ inline void check_launch(const char *what) {
     if (e != hipSuccess) fail(KRR_E_HIP, "launch of %s failed: %s", what, hipGetErrorString(e));
 }
 
-// Owning device allocation (hipMalloc / hipFree), move-only.
+// A caller's stream-ordered device allocator (krr_set_allocator); all
+// members NULL: hipMalloc / hipFree.
+struct Allocator {
+    void *(*alloc)(size_t, void *, void *) = nullptr;
+    void (*dealloc)(void *, void *, void *) = nullptr;
+    void *ctx = nullptr;
+};
+Allocator current_allocator();           // the one new buffers use
+hipStream_t call_stream();                // the stream of the C-ABI call in progress (this thread)
+void note_allocation(bool by_caller);     // allocation counters (krr_alloc_counts)
+
+// Owning device allocation, move-only: from the registered allocator on the
+// current call's stream (returned to that same allocator and stream), else
+// hipMalloc / hipFree.
 class DBuf {
   public:
     DBuf() = default;
     explicit DBuf(size_t bytes) { alloc(bytes); }
     DBuf(const DBuf &) = delete;
     DBuf &operator=(const DBuf &) = delete;
-    DBuf(DBuf &&o) noexcept : p_(o.p_), n_(o.n_) { o.p_ = nullptr; o.n_ = 0; }
+    DBuf(DBuf &&o) noexcept : p_(o.p_), n_(o.n_), own_(o.own_), s_(o.s_) {
+        o.p_ = nullptr;
+        o.n_ = 0;
+    }
     DBuf &operator=(DBuf &&o) noexcept {
         if (this != &o) {
             release();
-            p_ = o.p_; n_ = o.n_;
+            p_ = o.p_; n_ = o.n_; own_ = o.own_; s_ = o.s_;
             o.p_ = nullptr; o.n_ = 0;
         }
         return *this;
@@ -63,10 +79,21 @@ class DBuf {
     void alloc(size_t bytes) {
         release();
         if (bytes == 0) return;
-        if (hipMalloc(&p_, bytes) != hipSuccess) {
-            (void)hipGetLastError();
-            p_ = nullptr;
-            fail(KRR_E_NOMEM, "hipMalloc of %zu bytes failed", bytes);
+        const Allocator a = current_allocator();
+        if (a.alloc) {
+            s_ = call_stream();
+            p_ = a.alloc(bytes, static_cast<void *>(s_), a.ctx);
+            if (!p_) fail(KRR_E_NOMEM, "the registered allocator returned NULL for %zu bytes", bytes);
+            own_ = a;
+            note_allocation(true);
+        } else {
+            if (hipMalloc(&p_, bytes) != hipSuccess) {
+                (void)hipGetLastError();
+                p_ = nullptr;
+                fail(KRR_E_NOMEM, "hipMalloc of %zu bytes failed", bytes);
+            }
+            own_ = Allocator{};
+            note_allocation(false);
         }
         n_ = bytes;
     }
@@ -75,7 +102,12 @@ class DBuf {
         if (bytes > n_) alloc(bytes);
     }
     void release() {
-        if (p_) (void)hipFree(p_);
+        if (p_) {
+            if (own_.dealloc)
+                own_.dealloc(p_, static_cast<void *>(s_), own_.ctx);
+            else
+                (void)hipFree(p_);
+        }
         p_ = nullptr;
         n_ = 0;
     }
@@ -86,6 +118,8 @@ class DBuf {
   private:
     void *p_ = nullptr;
     size_t n_ = 0;
+    Allocator own_{};         // the allocator that made the buffer
+    hipStream_t s_ = nullptr; // and the stream it was made on
 };
 
 template <class T> inline DBuf dalloc(size_t count) { return DBuf(count * sizeof(T)); }

@@ -128,6 +128,52 @@ void bwd_typed(const T *X, int64_t m, const T *Y, int64_t n, int d, double h, co
 }
 }  // namespace
 
+namespace {
+// Validation residual of one column: e = f - y_v, ge = (2 / m) e and
+// loss = |e|^2 / m, summed in a fixed order (strided per thread, then a tree
+// over the block) so the result is deterministic.
+__global__ __launch_bounds__(256) void k_val_residual(const double *__restrict__ f, const double *__restrict__ yv,
+                                                      int64_t m, int k, double *__restrict__ ge,
+                                                      double *__restrict__ loss) {
+    __shared__ double part[256];
+    const int c = blockIdx.x, tid = threadIdx.x;
+    const double sc = 2.0 / (double)m;
+    double acc = 0.0;
+    for (int64_t i = tid; i < m; i += 256) {
+        const double e = f[i * k + c] - yv[i * k + c];
+        ge[i * k + c] = sc * e;
+        acc += e * e;
+    }
+    part[tid] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o) part[tid] += part[tid + o];
+        __syncthreads();
+    }
+    if (tid == 0) loss[c] = part[0] / (double)m;
+}
+
+// (dL/dlog h, dL/dlog lambda) = g (h (dh_v - dh_t), -lambda beta^T alpha)
+__global__ void k_val_grad_finish(const double *bta, const double *dh_v, const double *dh_t, const double *gscale,
+                                  double h, double lam, double *out) {
+    if (threadIdx.x != 0) return;
+    const double g = gscale ? gscale[0] : 1.0;
+    out[0] = g * (h * (dh_v[0] - dh_t[0]));
+    out[1] = g * (-lam * bta[0]);
+}
+}  // namespace
+
+void val_residual(const double *f, const double *yv, int64_t m, int k, double *ge, double *loss, hipStream_t s) {
+    k_val_residual<<<k, 256, 0, s>>>(f, yv, m, k, ge, loss);
+    check_launch("k_val_residual");
+}
+
+void val_grad_finish(const double *bta, const double *dh_v, const double *dh_t, const double *gscale, double h,
+                     double lam, double *out, hipStream_t s) {
+    k_val_grad_finish<<<1, 64, 0, s>>>(bta, dh_v, dh_t, gscale, h, lam, out);
+    check_launch("k_val_grad_finish");
+}
+
 void kernel_matvec_bwd_impl(const void *X, int64_t m, const void *Y, int64_t n, int d, int xprec, double h,
                             const double *W, const double *G, int nrhs, double *dX, double *dY, double *dW,
                             double *dh, int prec, hipStream_t s) {

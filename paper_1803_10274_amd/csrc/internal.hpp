@@ -118,8 +118,10 @@ struct hss_ulv_s {
 // ------------------------------------------------ entry points across units
 namespace krr {
 
+// method: KRR_ORDER_2MN (recursive two-means), _NP, _KD or _PCA
 void cluster_2mn(const void *X, int32_t xprec, int64_t n, int32_t d, const std::vector<int64_t> &roots,
-                 const krr_cluster_opts &o, hipStream_t s, int64_t *perm, krr_tree_s &tree);
+                 const krr_cluster_opts &o, hipStream_t s, int64_t *perm, krr_tree_s &tree,
+                 int32_t method = KRR_ORDER_2MN);
 void kernel_matvec_impl(const void *X, int64_t m, const void *Y, int64_t n, int d, int xprec, double h,
                         const double *W, int nrhs, double beta, double *Out, int prec, hipStream_t s,
                         const Batch *batch = nullptr);
@@ -162,6 +164,9 @@ int refine(const hss_ulv_s *F, int64_t n, const void *Xp, int xprec, int d, doub
            krr_refine_stats *st,
            const Batch *batch = nullptr, double *relres_all = nullptr);
 void predict_labels(const double *scores, int64_t m, int k, int32_t *labels, hipStream_t s);
+void val_residual(const double *f, const double *yv, int64_t m, int k, double *ge, double *loss, hipStream_t s);
+void val_grad_finish(const double *bta, const double *dh_v, const double *dh_t, const double *gscale, double h,
+                     double lam, double *out, hipStream_t s);
 void dot_columns(const double *a, const double *b, int64_t n, int k, double *out, DBuf &scratch, hipStream_t s);
 
 }  // namespace krr

@@ -16,6 +16,15 @@
 // multiplied into the FP32 accumulators with the random block, which is
 // pre-swizzled into the B-operand layout and staged through LDS.  The FP32
 // mode uses v_mfma_f32_32x32x2_f32 on the FP32 entries instead.
+//
+// Far from the diagonal most Gaussian kernel entries are negligibly small
+// (Section 4.1); in tree order they come in whole tiles.  A wave skips a
+// 32 x 32 (row, point) tile -- its exp2, split and products with R -- when
+// every exponent of the tile is below kSkipLog2 (all entries < 2^-32): the
+// decision is one ballot per tile and wave-uniform.  Each skipped entry
+// changes a sample by at most 2^-32 |R_jk|, so a row changes by at most
+// n 2^-32 max|R| (2^-12 at n = 2^20), below the FP32 accumulation error of
+// the sample itself and far below the compression tolerance.
 #include <algorithm>
 
 #include "internal.hpp"
@@ -32,6 +41,7 @@ typedef float f16v __attribute__((ext_vector_type(16)));
 enum Mode : int { M_F32 = 0, M_F16 = 1, M_BF16 = 2 };
 
 constexpr int WAVES = 8;
+constexpr float kSkipLog2 = -32.0f;  // tiles with every entry below 2^-32 are skipped
 constexpr int THREADS = 64 * WAVES;
 constexpr int ROWS = 32 * WAVES;  // rows per workgroup
 constexpr int JT = 32;            // points per tile
@@ -118,15 +128,6 @@ __device__ __forceinline__ void stage_y(const T *__restrict__ X, int64_t jlo, in
         }
         ys[p][D] = ok ? -cs * nrm : -INFINITY;
     }
-}
-
-// Entry t for the lane's row (xs = 2 c x', nx = -c |x'|^2) and staged point p.
-template <int D>
-__device__ __forceinline__ float entry(const float *xs, float nx, const float (*ys)[D + 1], int p) {
-    float t = nx + ys[p][D];
-#pragma unroll
-    for (int k = 0; k < D; ++k) t = fmaf(xs[k], ys[p][k], t);
-    return __builtin_amdgcn_exp2f(t);
 }
 
 // Augmented points for the distance product: row p of ya holds
@@ -257,72 +258,47 @@ __device__ __forceinline__ void exp_split(typename Op<MODE>::V (&ahi)[2], typena
     }
 }
 
-// A operand of one 32-point tile for the lane's row: 16 entries
-// (j = 16 kb + 8 g + q), split into hi (+ lo) FP16 / BF16 terms.
-template <int D, int MODE, int TERMS, bool MASK>
-__device__ __forceinline__ void make_a(typename Op<MODE>::V (&ahi)[2], typename Op<MODE>::V (&alo)[2],
-                                       const float *xs, float nx, const float (*ys)[D + 1], int pbase, int g,
-                                       int64_t jt, int32_t my_lb, int32_t my_le) {
-    typedef typename Op<MODE>::H H;
-#pragma unroll
-    for (int kb = 0; kb < 2; ++kb)
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int jj = 16 * kb + 8 * g + q;
-            float e = entry<D>(xs, nx, ys, pbase + jj);
-            if (MASK) {
-                const int64_t j = jt + jj;
-                e = (j >= my_lb && j < my_le) ? 0.0f : e;
-            }
-            const H hi = (H)e;
-            ahi[kb][q] = hi;
-            if (TERMS == 2) alo[kb][q] = (H)(e - (float)hi);
-        }
+// Wave-uniform test: no entry of the wave's tile reaches the skip threshold
+// (thr in the exponents' log2 units, which include the FP16 scale).
+__device__ __forceinline__ bool tile_negligible(const float *t, int cnt, float thr) {
+    float m = t[0];
+    for (int r = 1; r < cnt; ++r) m = fmaxf(m, t[r]);
+    return __ballot(m >= thr) == 0;
 }
 
-// MFMAs of the current tile (A = acur, B = the staged R tile) interleaved in
-// program order with the A operand of the next tile, so that each wave keeps
-// the matrix pipe and the vector ALUs busy at the same time.
-template <int D, int RB, int MODE, int TERMS, bool MASK>
-__device__ __forceinline__ void step_h(f16v (&acc)[RB], const typename Op<MODE>::V (&chi)[2],
-                                       const typename Op<MODE>::V (&clo)[2], typename Op<MODE>::V (&nhi)[2],
-                                       typename Op<MODE>::V (&nlo)[2], const char *rtile, const float *xs, float nx,
-                                       const float (*ys)[D + 1], int pbase, int g, int lane, int64_t jt,
-                                       int32_t my_lb, int32_t my_le) {
-    typedef typename Op<MODE>::H H;
-    typedef typename Op<MODE>::V V;
-    const V *rt = reinterpret_cast<const V *>(rtile);
-    constexpr int PER = 16 / RB;  // next-tile entries evaluated per column block
+// FP32 mode: the exponents of the lane's 16 entries of one tile (its row and
+// points j = 2 s + g), on the vector ALUs.
+template <int D>
+__device__ __forceinline__ void expo_f(float (&t)[16], const float *xs, float nx, const float (*ys)[D + 1], int pbase,
+                                       int g) {
 #pragma unroll
-    for (int c = 0; c < RB; ++c) {
+    for (int sidx = 0; sidx < 16; ++sidx) {
+        const int p = pbase + 2 * sidx + g;
+        float v = nx + ys[p][D];
 #pragma unroll
-        for (int kb = 0; kb < 2; ++kb) {
-            const V b = rt[(c * 2 + kb) * 64 + lane];
-            acc[c] = Op<MODE>::mfma(chi[kb], b, acc[c]);
-            if (TERMS == 2) acc[c] = Op<MODE>::mfma(clo[kb], b, acc[c]);
-        }
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const int ent = c * PER + u, kb = ent >> 3, q = ent & 7;
-            const int jj = 16 * kb + 8 * g + q;
-            float e = entry<D>(xs, nx, ys, pbase + jj);
-            if (MASK) {
-                const int64_t j = jt + jj;
-                e = (j >= my_lb && j < my_le) ? 0.0f : e;
-            }
-            const H hi = (H)e;
-            nhi[kb][q] = hi;
-            if (TERMS == 2) nlo[kb][q] = (H)(e - (float)hi);
-        }
+        for (int k = 0; k < D; ++k) v = fmaf(xs[k], ys[p][k], v);
+        t[sidx] = v;
     }
 }
 
-// FP32 mode: 16 v_mfma_f32_32x32x2_f32 steps per column block; the lane's
-// entries are its row and points j = 2 s + g.
-template <int D, int RB, bool MASK>
-__device__ __forceinline__ void step_f(f16v (&acc)[RB], const float (&cur)[16], float (&nxt)[16], const char *rtile,
-                                       const float *xs, float nx, const float (*ys)[D + 1], int pbase, int g,
-                                       int lane, int64_t jt, int32_t my_lb, int32_t my_le) {
+// FP32 mode: entries from the exponents (masking the row's own leaf).
+template <bool MASK>
+__device__ __forceinline__ void exp_f(float (&a)[16], const float (&t)[16], int g, int64_t jt, int32_t my_lb,
+                                      int32_t my_le) {
+#pragma unroll
+    for (int sidx = 0; sidx < 16; ++sidx) {
+        float e = __builtin_amdgcn_exp2f(t[sidx]);
+        if (MASK) {
+            const int64_t j = jt + 2 * sidx + g;
+            e = (j >= my_lb && j < my_le) ? 0.0f : e;
+        }
+        a[sidx] = e;
+    }
+}
+
+// FP32 mode: 16 v_mfma_f32_32x32x2_f32 steps per column block.
+template <int RB>
+__device__ __forceinline__ void mfma_f(f16v (&acc)[RB], const float (&cur)[16], const char *rtile, int lane) {
     const float *rt = reinterpret_cast<const float *>(rtile);
 #pragma unroll
     for (int sidx = 0; sidx < 16; ++sidx) {
@@ -331,25 +307,6 @@ __device__ __forceinline__ void step_f(f16v (&acc)[RB], const float (&cur)[16], 
             const float b = rt[(c * 16 + sidx) * 64 + lane];
             acc[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(cur[sidx], b, acc[c], 0, 0, 0);
         }
-        const int jj = 2 * sidx + g;
-        float e = entry<D>(xs, nx, ys, pbase + jj);
-        if (MASK) {
-            const int64_t j = jt + jj;
-            e = (j >= my_lb && j < my_le) ? 0.0f : e;
-        }
-        nxt[sidx] = e;
-    }
-}
-
-template <int D>
-__device__ __forceinline__ void make_f(float (&a)[16], const float *xs, float nx, const float (*ys)[D + 1], int pbase,
-                                       int g, int64_t jt, int32_t my_lb, int32_t my_le) {
-#pragma unroll
-    for (int sidx = 0; sidx < 16; ++sidx) {
-        const int jj = 2 * sidx + g;
-        float e = entry<D>(xs, nx, ys, pbase + jj);
-        const int64_t j = jt + jj;
-        a[sidx] = (j >= my_lb && j < my_le) ? 0.0f : e;
     }
 }
 
@@ -472,8 +429,11 @@ __global__ __launch_bounds__(THREADS) void k_sample_mfma(const T *__restrict__ X
     // Tile t's masking (wave-uniform decision): its columns meet the wave's leaf range.
 #define KRR_TILE_MASKED(tt) ((int64_t)(tt) * JT < (int64_t)wle && (int64_t)(tt) * JT + JT > (int64_t)wlb)
     if constexpr (MODE == M_F32) {
-        float a0[16], a1[16];
-        make_f<D>(a0, xs, nx, ysh[s0 & 1], t_lo_off, g, t_lo * JT, my_lb, my_le);
+        float a0[16], a1[16], tv[16];
+        bool sk0, sk1 = false;
+        expo_f<D>(tv, xs, nx, ysh[s0 & 1], t_lo_off, g);
+        sk0 = tile_negligible(tv, 16, kSkipLog2);
+        if (!sk0) exp_f<true>(a0, tv, g, t_lo * JT, my_lb, my_le);
         for (int64_t t = t_lo; t < t_hi; t += 2) {
 #pragma unroll
             for (int half = 0; half < 2; ++half) {
@@ -488,11 +448,17 @@ __global__ __launch_bounds__(THREADS) void k_sample_mfma(const T *__restrict__ X
                 const int pbn = (int)((tn * JT) % YS);
                 float(&cur)[16] = half == 0 ? a0 : a1;
                 float(&nxt)[16] = half == 0 ? a1 : a0;
-                if (KRR_TILE_MASKED(tn))
-                    step_f<D, RB, true>(acc, cur, nxt, rbuf[tc & 1], xs, nx, ysn, pbn, g, lane, tn * JT, my_lb, my_le);
-                else
-                    step_f<D, RB, false>(acc, cur, nxt, rbuf[tc & 1], xs, nx, ysn, pbn, g, lane, tn * JT, my_lb,
-                                         my_le);
+                bool &skc = half == 0 ? sk0 : sk1;
+                bool &skn = half == 0 ? sk1 : sk0;
+                expo_f<D>(tv, xs, nx, ysn, pbn, g);
+                skn = tile_negligible(tv, 16, kSkipLog2);
+                if (!skc) mfma_f<RB>(acc, cur, rbuf[tc & 1], lane);
+                if (!skn) {
+                    if (KRR_TILE_MASKED(tn))
+                        exp_f<true>(nxt, tv, g, tn * JT, my_lb, my_le);
+                    else
+                        exp_f<false>(nxt, tv, g, tn * JT, my_lb, my_le);
+                }
                 KRR_STORE_R((tc + 1) & 1);
                 KRR_LOAD_R(tc + 2);
                 __syncthreads();
@@ -546,12 +512,21 @@ __global__ __launch_bounds__(THREADS) void k_sample_mfma(const T *__restrict__ X
         stage(s0 + 1);
         __syncthreads();
         V h0[2], l0[2], h1[2], l1[2];
+        // the threshold in the exponents' units (FP16 entries carry 2^14)
+        constexpr float thr = kSkipLog2 + kE2;
+        bool sk0, sk1 = false;
         {
             f16v t0 = dist(t_lo);
-            if (KRR_TILE_MASKED(t_lo))
-                exp_split<MODE, TERMS, true>(h0, l0, t0, g, t_lo * JT, my_lb, my_le);
-            else
-                exp_split<MODE, TERMS, false>(h0, l0, t0, g, t_lo * JT, my_lb, my_le);
+            float tt[16];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) tt[r] = t0[r];
+            sk0 = tile_negligible(tt, 16, thr);
+            if (!sk0) {
+                if (KRR_TILE_MASKED(t_lo))
+                    exp_split<MODE, TERMS, true>(h0, l0, t0, g, t_lo * JT, my_lb, my_le);
+                else
+                    exp_split<MODE, TERMS, false>(h0, l0, t0, g, t_lo * JT, my_lb, my_le);
+            }
         }
         for (int64_t t = t_lo; t < t_hi; t += 2) {
 #pragma unroll
@@ -566,8 +541,16 @@ __global__ __launch_bounds__(THREADS) void k_sample_mfma(const T *__restrict__ X
                 V(&nl)[2] = half == 0 ? l1 : l0;
                 // exponents of the next tile first (matrix pipe), then this
                 // tile's products, then the next tile's entries (vector ALUs)
+                bool &skc = half == 0 ? sk0 : sk1;
+                bool &skn = half == 0 ? sk1 : sk0;
                 const f16v tnext = dist(tn);
                 {
+                    float tt[16];
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) tt[r] = tnext[r];
+                    skn = tile_negligible(tt, 16, thr);
+                }
+                if (!skc) {
                     const V *rt = reinterpret_cast<const V *>(rbuf[tc & 1]);
 #pragma unroll
                     for (int c = 0; c < RB; ++c)
@@ -578,10 +561,12 @@ __global__ __launch_bounds__(THREADS) void k_sample_mfma(const T *__restrict__ X
                             if (TERMS == 2) acc[c] = Op<MODE>::mfma(cl[kb], b, acc[c]);
                         }
                 }
-                if (KRR_TILE_MASKED(tn))
-                    exp_split<MODE, TERMS, true>(nh, nl, tnext, g, tn * JT, my_lb, my_le);
-                else
-                    exp_split<MODE, TERMS, false>(nh, nl, tnext, g, tn * JT, my_lb, my_le);
+                if (!skn) {
+                    if (KRR_TILE_MASKED(tn))
+                        exp_split<MODE, TERMS, true>(nh, nl, tnext, g, tn * JT, my_lb, my_le);
+                    else
+                        exp_split<MODE, TERMS, false>(nh, nl, tnext, g, tn * JT, my_lb, my_le);
+                }
                 KRR_STORE_R((tc + 1) & 1);
                 KRR_LOAD_R(tc + 2);
                 __syncthreads();

@@ -151,8 +151,11 @@ def mfma_sample_bound(Xp, R, h, lb, le, prec, split, rows, rows_per_block=256, s
     (Higham and Mary 2019), FP16 entries (scaled by 2^14) add 2^-38 absolute
     where they fall below FP16's normal range,
     n_adds = n / 16 + 16 for the 16-deep FP16 / BF16 products and n / 2 + 2
-    for the 2-deep FP32 ones.  anchor: the centring point when it is one for
-    all rows (the wide-point kernel centres on the mean point)."""
+    for the 2-deep FP32 ones.  The narrow kernel skips 32 x 32 tiles whose
+    entries are all below 2^-32; every dropped entry is below 2^-32 (2^-31
+    with the exponent's rounding), so the entries below 2^-31 are charged in
+    full.  anchor: the centring point when it is one for all rows (the
+    wide-point kernel centres on the mean point)."""
     Xp = np.asarray(Xp, dtype=np.float64)
     R = np.asarray(R, dtype=np.float64)
     n, d = Xp.shape
@@ -173,5 +176,6 @@ def mfma_sample_bound(Xp, R, h, lb, le, prec, split, rows, rows_per_block=256, s
             # lo terms keep an absolute precision of 2^-25 in scaled units
             de = de + np.where(e > 0, 2.0 ** -38, 0.0)
         acc = np.sqrt(nadd) * U32 * np.sqrt((e[:, None] ** 2 * R ** 2).sum(axis=0))
-        out[t] = safety * (de @ np.abs(R) + acc)
+        skipped = np.where(e < 2.0 ** -31, e, 0.0) @ np.abs(R)
+        out[t] = safety * (de @ np.abs(R) + acc) + skipped
     return out

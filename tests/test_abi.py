@@ -158,6 +158,14 @@ def _bad_calls(L, _lib):
          "h[0] must be positive"),
         ("krr_refine_batched", lambda: L.krr_refine_batched(None, P, F32, off_ok, 1, 3, h_ok, None, P, 1, P, 1e-6, 10,
                                                             F32, F64, None, None, None), "NULL lambda"),
+        ("krr_cluster_order method", lambda: L.krr_cluster_order(P, F32, 10, 2, 7, None, 0, ctypes.byref(copts), None,
+                                                                 P, ctypes.byref(out)), "unknown method"),
+        ("krr_cluster_order offsets", lambda: L.krr_cluster_order(P, F32, 10, 2, 2, off_ok, 1, ctypes.byref(copts),
+                                                                  None, P, ctypes.byref(out)), "offsets[np]"),
+        ("krr_val_residual", lambda: L.krr_val_residual(P, P, 0, 1, P, P, None), "m >= 1"),
+        ("krr_set_allocator", lambda: L.krr_set_allocator(P, None, None), "both functions or neither"),
+        ("krr_alloc_counts", lambda: L.krr_alloc_counts(None, None), "NULL argument"),
+        ("krr_val_grad_finish", lambda: L.krr_val_grad_finish(P, P, P, None, 1.0, -1.0, P, None), "positive"),
     ]
 
 
