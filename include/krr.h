@@ -404,6 +404,31 @@ int krr_predict(const void *Xt, int64_t m, const void *Xp, int64_t n, int32_t d,
                 int32_t xprec, double h, const double *alpha, int32_t nrhs,
                 double *scores, int32_t *labels, int32_t prec, void *stream);
 
+/* Scratch of krr_predict_noalloc per device: 128 MiB. */
+#define KRR_NOALLOC_SCRATCH_BYTES (128u * 1024u * 1024u)
+
+/*
+ * krr_predict without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments and results as krr_predict (the same
+ * kernels; identical scores) for d <= 64 and Xt != Xp; the split-K partial
+ * sums and column data live in a static device array of
+ * KRR_NOALLOC_SCRATCH_BYTES per device, held until the process ends.  It
+ * needs 8 nsplit m nrhs bytes (nsplit, the column splits of the product, is
+ * at most ceil(2048 / ceil(m / rows per workgroup)) with the default launch
+ * knobs) plus, for prec = KRR_F32, n (8 LD + 4 nrhs) bytes, LD = D + 2 with D
+ * the kernel width d is rounded up to (a multiple of 4 up to 24, then 32, 48,
+ * 56 or 64), each part rounded up to 256 bytes; larger sizes fail with
+ * KRR_E_INVAL (use krr_predict).  No hipMalloc, hipFree, memset or
+ * stream synchronization.  Every call on a device shares its array: calls that
+ * overlap on one device (two streams, two threads) race and must be ordered by
+ * the caller.  Errors as krr_predict, plus KRR_E_INVAL for d > 64, Xt == Xp,
+ * or a size over the limit.
+ */
+int krr_predict_noalloc(const void *Xt, int64_t m, const void *Xp, int64_t n, int32_t d, int32_t xprec,
+                        double h, const double *alpha, int32_t nrhs, double *scores, int32_t *labels,
+                        int32_t prec, void *stream);
+
 /* ---------------------------------------------- batched form (A1-A8) */
 
 /*

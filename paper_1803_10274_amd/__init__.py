@@ -462,6 +462,20 @@ def predict(Xt, Xp, h, alpha, prec="f32"):
     return scores, labels
 
 
+def predict_noalloc(Xt, Xp, h, alpha, scores, labels=None, prec="f32"):
+    """predict into caller tensors with no device allocation by the library
+    (krr_predict_noalloc; d <= 64, sizes within its static scratch)."""
+    _dev(Xt)
+    _dev(Xp)
+    a2 = _dev(alpha, torch.float64).reshape(alpha.shape[0], -1)
+    _dev(scores, torch.float64)
+    if labels is not None:
+        _dev(labels, torch.int32)
+    check(load().krr_predict_noalloc(_p(Xt), Xt.shape[0], _p(Xp), Xp.shape[0], Xp.shape[1], _xprec(Xt), float(h),
+                                     _p(a2), a2.shape[1], _p(scores), _p(labels), _prec(prec), _stream()))
+    return scores, labels
+
+
 # ------------------------------------------------------------------ fit
 
 @dataclass

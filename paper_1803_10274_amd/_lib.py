@@ -87,6 +87,7 @@ SIGNATURES = {
     "krr_refine": (ctypes.c_int, [_vp, _vp, _i64, _i32, _i32, _dbl, _dbl, _vp, _i32, _vp, _dbl, _i32, _i32, _i32,
                                   _vp, _P(RefineStats)]),
     "krr_predict": (ctypes.c_int, [_vp, _i64, _vp, _i64, _i32, _i32, _dbl, _vp, _i32, _vp, _vp, _i32, _vp]),
+    "krr_predict_noalloc": (ctypes.c_int, [_vp, _i64, _vp, _i64, _i32, _i32, _dbl, _vp, _i32, _vp, _vp, _i32, _vp]),
     "krr_dot_columns": (ctypes.c_int, [_vp, _vp, _i64, _i32, _vp, _vp]),
     "krr_set_tuning": (ctypes.c_int, [_i32, _i32]),
     "krr_get_tuning": (ctypes.c_int, [_i32, _P(_i32)]),

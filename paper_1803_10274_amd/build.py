@@ -16,7 +16,7 @@ LIB = os.path.join(HERE, "libkrr.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["capi.cpp", "cluster.hip", "matvec.hip", "matvec_wide.hip", "sample.hip", "sample_mfma.hip", "hss.hip",
-           "hss_mv.hip", "ulv.hip", "refine.hip", "grad.hip"]
+           "hss_mv.hip", "ulv.hip", "refine.hip", "grad.hip", "noalloc.hip"]
 COMMON = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-x", "hip",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(ROOT, "include"), "-Wno-unused-command-line-argument"]

@@ -608,6 +608,24 @@ int krr_predict(const void *Xt, int64_t m, const void *Xp, int64_t n, int32_t d,
     });
 }
 
+int krr_predict_noalloc(const void *Xt, int64_t m, const void *Xp, int64_t n, int32_t d, int32_t xprec, double h,
+                        const double *alpha, int32_t nrhs, double *scores, int32_t *labels, int32_t prec,
+                        void *stream) {
+    return guard([&] {
+        check_xprec(xprec);
+        KRR_REQUIRE(m >= 0 && n >= 1 && d >= 1 && nrhs >= 1 && nrhs <= 64, "krr_predict_noalloc: bad sizes");
+        KRR_REQUIRE(d <= 64, "krr_predict_noalloc: d = %d > 64 is not supported (use krr_predict)", d);
+        KRR_REQUIRE(h > 0.0, "krr_predict_noalloc: h must be positive");
+        KRR_REQUIRE(prec == KRR_F32 || prec == KRR_F64, "krr_predict_noalloc: prec must be KRR_F32 or KRR_F64");
+        KRR_REQUIRE(m == 0 || (Xt && Xp && alpha && scores), "krr_predict_noalloc: NULL pointer");
+        KRR_REQUIRE(Xt != Xp, "krr_predict_noalloc: Xt and Xp alias (use krr_predict)");
+        require_device();
+        if (m == 0) return KRR_OK;
+        predict_noalloc(Xt, m, Xp, n, d, xprec, h, alpha, nrhs, scores, labels, prec, S(stream));
+        return KRR_OK;
+    });
+}
+
 int krr_set_tuning(int32_t knob, int32_t value) {
     return guard([&] {
         KRR_REQUIRE(knob >= 0 && knob < KRR_TUNE_COUNT, "krr_set_tuning: unknown knob %d", knob);

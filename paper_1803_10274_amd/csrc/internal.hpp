@@ -164,6 +164,13 @@ int refine(const hss_ulv_s *F, int64_t n, const void *Xp, int xprec, int d, doub
            krr_refine_stats *st,
            const Batch *batch = nullptr, double *relres_all = nullptr);
 void predict_labels(const double *scores, int64_t m, int k, int32_t *labels, hipStream_t s);
+void predict_noalloc(const void *Xt, int64_t m, const void *Xp, int64_t n, int d, int xprec, double h,
+                     const double *alpha, int nrhs, double *scores, int32_t *labels, int prec, hipStream_t s);
+// The plain product Out = K(X, Y) W (d <= 64, no symmetric form) with
+// caller-given scratch: its size, and the product (no allocation, no sync).
+size_t kernel_matvec_ws_bytes(int64_t m, int64_t n, int d, int nrhs, int prec);
+void kernel_matvec_ws(const void *X, int64_t m, const void *Y, int64_t n, int d, int xprec, double h,
+                      const double *W, int nrhs, double *Out, int prec, void *ws, size_t ws_bytes, hipStream_t s);
 void val_residual(const double *f, const double *yv, int64_t m, int k, double *ge, double *loss, hipStream_t s);
 void val_grad_finish(const double *bta, const double *dh_v, const double *dh_t, const double *gscale, double h,
                      double lam, double *out, hipStream_t s);

@@ -1317,6 +1317,84 @@ bool kmv_sym(const T *X, int64_t n, int d, double h, const double *W, int nrhs, 
     return true;
 }
 
+// The plain product K(X, Y) W (no batch, no symmetric form, d <= 64 for the
+// FP32 entries' scalar-operand kernel): column splits so that the grid fills
+// the chip, and the scratch it needs -- split-K partial sums, and for FP32
+// entries the column data and FP32 weights.
+struct KmvPlan {
+    bool sc;
+    int D, rows_pb, nsplit;
+    int64_t cps;
+    size_t part_elems, ya_elems, wf_elems;  // doubles, doubles, floats
+};
+
+KmvPlan kmv_plan(int64_t m, int64_t n, int d, int nrhs, bool f32) {
+    KmvPlan P{};
+    P.sc = f32 && d <= 64;
+    P.D = P.sc ? sc_width(d) : 0;
+    P.rows_pb = P.sc ? MV_ROWS * sc_rpt(P.D) : MV_ROWS;
+    const int64_t row_blocks = ceil_div(m, P.rows_pb);
+    int nsplit = (int)std::max<int64_t>(
+        1, std::min<int64_t>(ceil_div(tune_get(KRR_TUNE_MV_BLOCKS), row_blocks), ceil_div(n, 4 * MV_TN)));
+    int64_t cps = (int64_t)ceil_div(n, nsplit);
+    cps = (cps + MV_TN - 1) / MV_TN * MV_TN;
+    P.nsplit = (int)ceil_div(n, cps);
+    P.cps = cps;
+    P.part_elems = (size_t)P.nsplit * m * nrhs;
+    const int LD = (P.D + 2) & ~1;  // ColLd
+    P.ya_elems = P.sc ? (size_t)n * LD : 0;
+    P.wf_elems = P.sc ? (size_t)n * nrhs : 0;
+    return P;
+}
+
+// Runs a plan with caller-given scratch (part, and ya / wf for FP32 entries).
+// Every scratch element read is written first by the same call; nothing is
+// allocated and the stream is not synchronized.
+template <class T, class C>
+void kmv_run(const T *X, int64_t m, const T *Y, int64_t n, int d, double h, const double *W, int nrhs, double beta,
+             double *Out, const KmvPlan &P, double *part, double *ya, float *wf, hipStream_t s) {
+    const C scale = kernel_scale<C>(h);
+    const double c2 = kernel_scale_log2(h);
+    const int nsplit = P.nsplit;
+    const int64_t cps = P.cps;
+    if (P.sc) {
+        const int D = P.D, LD = (D + 2) & ~1;
+        k_col_aug<T><<<ceil_div(n, 256), 256, 0, s>>>(Y, n, d, D, LD, c2, nullptr, nullptr, 0, ya);
+        check_launch("k_col_aug");
+        k_w_to_float<<<ceil_div(n * nrhs, 256), 256, 0, s>>>(W, n * nrhs, wf);
+        check_launch("k_w_to_float");
+        dim3 grid(ceil_div(m, P.rows_pb), nsplit);
+        for (int r0 = 0; r0 < nrhs;) {
+            const int left = nrhs - r0;
+            const int nr = left >= 16 ? 16 : left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
+            switch (nr) {
+                case 16: launch_sc<T, 16>(D, grid, X, m, d, c2, ya, wf, nrhs, r0, n, cps, part, nullptr, s); break;
+                case 8: launch_sc<T, 8>(D, grid, X, m, d, c2, ya, wf, nrhs, r0, n, cps, part, nullptr, s); break;
+                case 4: launch_sc<T, 4>(D, grid, X, m, d, c2, ya, wf, nrhs, r0, n, cps, part, nullptr, s); break;
+                case 2: launch_sc<T, 2>(D, grid, X, m, d, c2, ya, wf, nrhs, r0, n, cps, part, nullptr, s); break;
+                default: launch_sc<T, 1>(D, grid, X, m, d, c2, ya, wf, nrhs, r0, n, cps, part, nullptr, s); break;
+            }
+            r0 += nr;
+        }
+    } else {
+        for (int r0 = 0; r0 < nrhs;) {
+            const int left = nrhs - r0;
+            const int nr = left >= 16 ? 16 : left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
+            switch (nr) {
+                case 16: dispatch_d<T, C, 16>(X, m, Y, n, d, scale, c2, W, nrhs, r0, nsplit, cps, part, s, nullptr, 0); break;
+                case 8: dispatch_d<T, C, 8>(X, m, Y, n, d, scale, c2, W, nrhs, r0, nsplit, cps, part, s, nullptr, 0); break;
+                case 4: dispatch_d<T, C, 4>(X, m, Y, n, d, scale, c2, W, nrhs, r0, nsplit, cps, part, s, nullptr, 0); break;
+                case 2: dispatch_d<T, C, 2>(X, m, Y, n, d, scale, c2, W, nrhs, r0, nsplit, cps, part, s, nullptr, 0); break;
+                default: dispatch_d<T, C, 1>(X, m, Y, n, d, scale, c2, W, nrhs, r0, nsplit, cps, part, s, nullptr, 0); break;
+            }
+            r0 += nr;
+        }
+    }
+    const int64_t mn = m * nrhs;
+    k_reduce_splits<<<ceil_div(mn, 256), 256, 0, s>>>(part, nsplit, mn, beta, Out);
+    check_launch("k_reduce_splits");
+}
+
 template <class T, class C>
 void kmv_typed(const T *X, int64_t m, const T *Y, int64_t n, int d, double h, const double *W, int nrhs,
                double beta, double *Out, hipStream_t s, const Batch *batch) {
@@ -1337,16 +1415,25 @@ void kmv_typed(const T *X, int64_t m, const T *Y, int64_t n, int d, double h, co
         if (X == Y && m == n && tune_get(KRR_TUNE_SYMMETRIC) && kmv_sym<T>(X, n, d, h, W, nrhs, beta, Out, s, batch))
             return;
     }
+    if (!batch) {
+        const KmvPlan P = kmv_plan(m, n, d, nrhs, sizeof(C) == 4);
+        DBuf part = dalloc<double>(P.part_elems), ya = dalloc<double>(P.ya_elems), wf = dalloc<float>(P.wf_elems);
+        kmv_run<T, C>(X, m, Y, n, d, h, W, nrhs, beta, Out, P, part.as<double>(), ya.as<double>(), wf.as<float>(),
+                      s);
+        sync(s);  // the temporaries are released on return
+        return;
+    }
     const C scale = kernel_scale<C>(h);
     const double c2 = kernel_scale_log2(h);
     const bool sc = sizeof(C) == 4 && d <= 64;
     const int D = sc ? sc_width(d) : 0;
     const int rows_pb = sc ? MV_ROWS * sc_rpt(D) : MV_ROWS;  // rows per workgroup
-    // split the columns so that the grid has enough blocks to fill the chip
+    // a batch: one block table row per (problem, row block), each problem's
+    // columns split so that the grid has enough blocks to fill the chip
     int nsplit;
     int64_t cps = 0, nb = 0;
     DBuf btab;
-    if (batch) {
+    {
         std::vector<SampBlock> blocks = row_blocks(*batch, rows_pb);
         nb = (int64_t)blocks.size();
         int64_t nmax = 0;
@@ -1358,12 +1445,6 @@ void kmv_typed(const T *X, int64_t m, const T *Y, int64_t n, int d, double h, co
         }
         btab = upload(blocks, s);
         sync(s);
-    } else {
-        const int64_t row_blocks = ceil_div(m, rows_pb);
-        nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(tune_get(KRR_TUNE_MV_BLOCKS), row_blocks), ceil_div(n, 4 * MV_TN)));
-        cps = (int64_t)ceil_div(n, nsplit);
-        cps = (cps + MV_TN - 1) / MV_TN * MV_TN;
-        nsplit = (int)ceil_div(n, cps);
     }
     const SampBlock *bt = btab.as<SampBlock>();
     DBuf part = dalloc<double>((size_t)nsplit * m * nrhs);
@@ -1455,6 +1536,41 @@ void kernel_matvec_impl(const void *X, int64_t m, const void *Y, int64_t n, int 
             kmv_typed<float, double>(Xf, m, Yf, n, d, h, W, nrhs, beta, Out, s, batch);
         else
             kmv_typed<float, float>(Xf, m, Yf, n, d, h, W, nrhs, beta, Out, s, batch);
+    }
+}
+
+size_t kernel_matvec_ws_bytes(int64_t m, int64_t n, int d, int nrhs, int prec) {
+    const KmvPlan P = kmv_plan(m, n, d, nrhs, prec != KRR_F64);
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    return up(P.part_elems * sizeof(double)) + up(P.ya_elems * sizeof(double)) + up(P.wf_elems * sizeof(float));
+}
+
+void kernel_matvec_ws(const void *X, int64_t m, const void *Y, int64_t n, int d, int xprec, double h,
+                      const double *W, int nrhs, double *Out, int prec, void *ws, size_t ws_bytes, hipStream_t s) {
+    KRR_REQUIRE(d <= 64, "kernel_matvec_ws: d = %d > 64 is not supported", d);
+    const bool f32 = prec != KRR_F64;
+    const KmvPlan P = kmv_plan(m, n, d, nrhs, f32);
+    const size_t need = kernel_matvec_ws_bytes(m, n, d, nrhs, prec);
+    KRR_REQUIRE(need <= ws_bytes, "kernel_matvec_ws: needs %zu bytes of scratch, %zu available", need, ws_bytes);
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    char *base = static_cast<char *>(ws);
+    double *part = reinterpret_cast<double *>(base);
+    double *ya = reinterpret_cast<double *>(base + up(P.part_elems * sizeof(double)));
+    float *wf = reinterpret_cast<float *>(base + up(P.part_elems * sizeof(double)) + up(P.ya_elems * sizeof(double)));
+    if (xprec == KRR_F64) {
+        auto Xd = static_cast<const double *>(X);
+        auto Yd = static_cast<const double *>(Y);
+        if (f32)
+            kmv_run<double, float>(Xd, m, Yd, n, d, h, W, nrhs, 0.0, Out, P, part, ya, wf, s);
+        else
+            kmv_run<double, double>(Xd, m, Yd, n, d, h, W, nrhs, 0.0, Out, P, part, ya, wf, s);
+    } else {
+        auto Xf = static_cast<const float *>(X);
+        auto Yf = static_cast<const float *>(Y);
+        if (f32)
+            kmv_run<float, float>(Xf, m, Yf, n, d, h, W, nrhs, 0.0, Out, P, part, ya, wf, s);
+        else
+            kmv_run<float, double>(Xf, m, Yf, n, d, h, W, nrhs, 0.0, Out, P, part, ya, wf, s);
     }
 }
 

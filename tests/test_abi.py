@@ -164,6 +164,8 @@ def _bad_calls(L, _lib):
                                                                   None, P, ctypes.byref(out)), "offsets[np]"),
         ("krr_val_residual", lambda: L.krr_val_residual(P, P, 0, 1, P, P, None), "m >= 1"),
         ("krr_set_allocator", lambda: L.krr_set_allocator(P, None, None), "both functions or neither"),
+        ("krr_predict_noalloc", lambda: L.krr_predict_noalloc(P, 3, P, 4, 65, F32, 1.0, P, 1, P, P, F32, None),
+         "d = 65 > 64"),
         ("krr_alloc_counts", lambda: L.krr_alloc_counts(None, None), "NULL argument"),
         ("krr_val_grad_finish", lambda: L.krr_val_grad_finish(P, P, P, None, 1.0, -1.0, P, None), "positive"),
     ]
