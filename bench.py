@@ -133,6 +133,12 @@ def parse():
     ap.add_argument("--wide-kernels", action="store_true",
                     help="launches of the wide-point kernel products at the image-like size (profiling)")
     ap.add_argument("--reps", type=int, default=3, help="launches per kernel timing")
+    ap.add_argument("--grad-kernels", action="store_true",
+                    help="the fused backward's two dh launches at the gradient workload's size (profiling)")
+    ap.add_argument("--cpu-dense", action="store_true",
+                    help="time the oracle's dense FP64 KRR fit on the host at n = 1,000, 8,192 and 32,768")
+    ap.add_argument("--scaling", action="store_true",
+                    help="fit the sixteen-Gaussian workload at n = 2^16 .. 2^20 and print the phase times per n")
     ap.add_argument("--summarize-trace", metavar="CSV",
                     help="print per-(kernel, grid) launch statistics of a rocprofv3 kernel-trace CSV and exit")
     return ap.parse_args()
@@ -224,6 +230,71 @@ def kernels_only(args):
     print(json.dumps({"kernels_only": True, "n": args.n, "r": args.r0, "copy_bytes": 2 * a.numel() * 4}), flush=True)
 
 
+def grad_kernels(args):
+    """The two dh launches of the validation-loss gradient on the
+    eight-Gaussian workload (n = 131,072 training, 16,384 validation, d = 18):
+    K o T products of the validation rows against the training points and of
+    the training points against themselves, each timed with HIP events."""
+    import torch
+
+    import paper_1803_10274_amd as krr
+    import synthdata as sd
+    krr.load()
+    p = sd.c5_eight_gaussians()
+    X = torch.from_numpy(p.X).cuda()
+    Xv = torch.from_numpy(p.Xt).cuda()
+    a = torch.from_numpy(sd.vectors(p.X.shape[0], 1, seed=3)).cuda()
+    g = torch.from_numpy(sd.vectors(p.Xt.shape[0], 1, seed=4)).cuda()
+    b = torch.from_numpy(sd.vectors(p.X.shape[0], 1, seed=5)).cuda()
+    torch.cuda.synchronize()
+    out = {"grad_kernels": True, "n": p.X.shape[0], "m_v": p.Xt.shape[0], "d": p.d}
+    for name, fn, entries in (
+            ("validation", lambda: krr.kernel_matvec_bwd(Xv, X, p.h, a, g, want=("dh",)),
+             float(p.Xt.shape[0]) * p.X.shape[0]),
+            ("training", lambda: krr.kernel_matvec_bwd(X, X, p.h, a, b, want=("dh",)),
+             float(p.X.shape[0]) ** 2)):
+        log(f"dh launch: {name}")
+        t = time_launches(fn, args.reps)
+        out[name] = {"s": t, "entries_per_s": entries / t, "exp2_rate_frac": entries / t / PEAK_EXP2}
+    print(json.dumps(out), flush=True)
+
+
+def scaling(args):
+    """The headline fit at n = 2^16 .. 2^20 (same options, one warm-up fit at
+    each n, then one timed), one JSON line per n: phase times, the sampling
+    kernel's time, iterations and the FP64 residual.  Checks the work model:
+    sampling O(n^2 r), clustering / compression / factorization / solve near
+    O(n), refinement O(n^2) per iteration."""
+    import torch
+
+    import paper_1803_10274_amd as krr
+    import synthdata as sd
+    krr.load()
+    dev = torch.device("cuda:0")
+    opts = krr.HssOptions(rtol=args.rtol, atol=args.atol, r0=args.r0, dr=args.r0, r_max=args.r_max,
+                          prec=args.prec, split_terms=args.split, cap_policy=args.cap_policy)
+    for lg in range(16, 21):
+        n = 1 << lg
+        p = sd.c2_sixteen_gaussians(n=n, m=1)
+        X = torch.from_numpy(p.X).to(dev)
+        y = torch.from_numpy(p.y).to(dev)
+        torch.cuda.synchronize()
+        log(f"scaling: n = {n}")
+        for rep in range(2):
+            t0 = time.perf_counter()
+            res = krr.fit(X, y, p.h, p.lam, leaf=p.leaf, opts=opts, tol=1e-6, max_iter=300, raise_on_fail=False)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+        out = {"scaling": True, "n": n, "fit_s": t, "phases_s": res.info["phases"],
+               "t_sample_ms": res.info["hss"]["t_sample_ms"], "t_id_ms": res.info["hss"]["t_id_ms"],
+               "r_final": res.info["hss"]["r_final"], "max_rank": res.info["hss"]["max_rank"],
+               "bytes_paper": res.info["hss"]["bytes_paper"], "ulv_shift": res.info["ulv_shift"],
+               "refine_iterations": res.info["refine"]["iterations"],
+               "relres_fp64": fp64_relres(krr, res, y, p)}
+        print(json.dumps(out), flush=True)
+        del res, X, y
+
+
 def wide_kernels(args):
     """The wide-point kernel products at the image-like size (n = 60,000,
     d = 784, ten right-hand sides): two launches with FP32 entries (BF16
@@ -260,6 +331,15 @@ def main():
         return
     if args.kernels_only:
         kernels_only(args)
+        return
+    if args.scaling:
+        scaling(args)
+        return
+    if args.grad_kernels:
+        grad_kernels(args)
+        return
+    if args.cpu_dense:
+        cpu_dense()
         return
     import numpy as np
     import torch
@@ -530,6 +610,42 @@ def image_leg(dump=None):
            "accuracy": float((lab.cpu().numpy() == p.yt).mean())}
     log(f"image-like: {out}")
     return out
+
+
+def cpu_dense():
+    """The oracle's dense FP64 KRR fit (Algorithm 1 steps 1-2: form K from
+    the differences, Cholesky, solve) on the host, on the first n points of
+    the sixteen-Gaussian workload: one thread and all threads at n = 1,000 and
+    8,192 (SciPy LAPACK), all threads at n = 32,768 (torch's CPU Cholesky: the
+    SciPy build fails to factor that size).  One JSON line per case."""
+    import numpy as np
+    import torch
+
+    import synthdata as sd
+    from oracle import kernel as ok
+    cores, nproc, model = cpu_info()
+    p = sd.c2_sixteen_gaussians(n=32768, m=1)
+    from threadpoolctl import threadpool_limits
+    for n, threads in ((1000, 1), (1000, cores), (8192, 1), (8192, cores), (32768, cores)):
+        torch.set_num_threads(threads)
+        X = p.X[:n].astype(np.float64)
+        y = np.asarray(p.y[:n], dtype=np.float64)
+        log(f"cpu dense: n = {n}, {threads} threads")
+        with threadpool_limits(limits=threads):
+            t0 = time.perf_counter()
+            K = ok.kernel_dense(X, X, p.h)
+            t1 = time.perf_counter()
+            if n <= 8192:
+                ok.krr_solve_dense(K, y, p.lam)
+            else:
+                K[np.diag_indices_from(K)] += p.lam
+                L = torch.linalg.cholesky(torch.from_numpy(K))
+                torch.cholesky_solve(torch.from_numpy(y).reshape(-1, 1), L)
+                del L
+            t2 = time.perf_counter()
+        del K
+        print(json.dumps({"cpu_dense": True, "n": n, "threads": threads, "form_s": t1 - t0, "solve_s": t2 - t1,
+                          "nproc": nproc, "cpu_model": model}), flush=True)
 
 
 def cpu_info():

@@ -10,63 +10,87 @@ namespace krr {
 
 constexpr int BG_T = 256;  // threads per node workgroup
 
+// One 64 x 64 tile (rows i0.., columns j0..) of
 // C(i, j) = beta * C(i, j) + alpha * sum_k A(i, k) B(k, j)
 // with A(i, k) = A[i * as0 + k * as1], B(k, j) = B[k * bs0 + j * bs1],
 // C row-major with leading dimension ldc.  beta == 0 never reads C.
 // smem: at least 2 * 16 * 65 doubles.  All 256 threads must call it.
 template <class TA, class TB>
-__device__ void block_gemm(int M, int N, int K, double alpha, const TA *__restrict__ A, int64_t as0,
-                           int64_t as1, const TB *__restrict__ B, int64_t bs0, int64_t bs1, double beta,
-                           double *__restrict__ C, int64_t ldc, double *smem) {
+__device__ void tile_gemm(int M, int N, int K, int i0, int j0, double alpha, const TA *__restrict__ A, int64_t as0,
+                          int64_t as1, const TB *__restrict__ B, int64_t bs0, int64_t bs1, double beta,
+                          double *__restrict__ C, int64_t ldc, double *smem) {
     double(*As)[65] = reinterpret_cast<double(*)[65]>(smem);
     double(*Bs)[65] = reinterpret_cast<double(*)[65]>(smem + 16 * 65);
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-    for (int i0 = 0; i0 < M; i0 += 64) {
-        for (int j0 = 0; j0 < N; j0 += 64) {
-            double acc[4][4];
+    double acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        for (int t = tid; t < 16 * 64; t += BG_T) {
+            int kk = t >> 6, ii = t & 63;
+            int gi = i0 + ii, gk = k0 + kk;
+            As[kk][ii] = (gi < M && gk < K) ? (double)A[gi * as0 + gk * as1] : 0.0;
+            int gj = j0 + ii;
+            Bs[kk][ii] = (gj < N && gk < K) ? (double)B[gk * bs0 + gj * bs1] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) av[a] = As[kk][ty + 16 * a];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) bv[b] = Bs[kk][tx + 16 * b];
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
-                for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-            for (int k0 = 0; k0 < K; k0 += 16) {
-                for (int t = tid; t < 16 * 64; t += BG_T) {
-                    int kk = t >> 6, ii = t & 63;
-                    int gi = i0 + ii, gk = k0 + kk;
-                    As[kk][ii] = (gi < M && gk < K) ? (double)A[gi * as0 + gk * as1] : 0.0;
-                    int gj = j0 + ii;
-                    Bs[kk][ii] = (gj < N && gk < K) ? (double)B[gk * bs0 + gj * bs1] : 0.0;
-                }
-                __syncthreads();
+                for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
+        }
+        __syncthreads();
+    }
 #pragma unroll
-                for (int kk = 0; kk < 16; ++kk) {
-                    double av[4], bv[4];
+    for (int a = 0; a < 4; ++a) {
+        int gi = i0 + ty + 16 * a;
+        if (gi >= M) continue;
 #pragma unroll
-                    for (int a = 0; a < 4; ++a) av[a] = As[kk][ty + 16 * a];
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) bv[b] = Bs[kk][tx + 16 * b];
-#pragma unroll
-                    for (int a = 0; a < 4; ++a)
-#pragma unroll
-                        for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
-                }
-                __syncthreads();
-            }
-#pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                int gi = i0 + ty + 16 * a;
-                if (gi >= M) continue;
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    int gj = j0 + tx + 16 * b;
-                    if (gj >= N) continue;
-                    double *c = C + (int64_t)gi * ldc + gj;
-                    *c = (beta == 0.0) ? alpha * acc[a][b] : beta * (*c) + alpha * acc[a][b];
-                }
-            }
+        for (int b = 0; b < 4; ++b) {
+            int gj = j0 + tx + 16 * b;
+            if (gj >= N) continue;
+            double *c = C + (int64_t)gi * ldc + gj;
+            *c = (beta == 0.0) ? alpha * acc[a][b] : beta * (*c) + alpha * acc[a][b];
         }
     }
+}
+
+// The whole product by one workgroup, tile after tile.
+template <class TA, class TB>
+__device__ void block_gemm(int M, int N, int K, double alpha, const TA *__restrict__ A, int64_t as0,
+                           int64_t as1, const TB *__restrict__ B, int64_t bs0, int64_t bs1, double beta,
+                           double *__restrict__ C, int64_t ldc, double *smem) {
+    for (int i0 = 0; i0 < M; i0 += 64)
+        for (int j0 = 0; j0 < N; j0 += 64)
+            tile_gemm(M, N, K, i0, j0, alpha, A, as0, as1, B, bs0, bs1, beta, C, ldc, smem);
     __syncthreads();
 }
+
+// A product of a batch of independent ones, spread over workgroups: one
+// 64 x 64 tile per workgroup (the levels of the ULV factorization with few,
+// large nodes).
+struct GemmJob {
+    int M, N, K;
+    double alpha, beta;
+    const double *A;
+    int64_t as0, as1;
+    const double *B;
+    int64_t bs0, bs1;
+    double *C;
+    int64_t ldc;
+};
+struct GemmTile {
+    int job, i0, j0;
+};
 
 // Block-wide reductions (256 threads); red: at least 8 doubles / ints of smem.
 __device__ inline double block_sum(double v, double *red) {

@@ -6,7 +6,9 @@
 //   dh   = sum_ij P_ij ||x_i - y_j||^2 / h^3
 // One thread per row of the left operand; right-operand tiles in LDS; FP32
 // entries from exact differences inside a 64-column tile, FP64 across tiles
-// (FP64 throughout for prec = KRR_F64).
+// (FP64 throughout for prec = KRR_F64).  dh alone with FP32 entries and one
+// right-hand side (the validation-loss gradient) is a kernel product instead:
+// the entry exp2(t) t on the products' split-K kernel, then a dot with G.
 #include "internal.hpp"
 
 namespace krr {
@@ -21,61 +23,63 @@ __device__ __forceinline__ double gexp(double q, double s) { return exp(-q * s);
 // For rows a of A: s_a = sum_b P_ab, t_a = sum_b P_ab B_b, u_a = sum_b P_ab ||A_a - B_b||^2
 // with P_ab = K(A_a, B_b) (GA_a . GB_b).  Writes dA_a = -(1/h^2)(s_a A_a - t_a)
 // and u_a (for dh) when the pointers are given.
-template <class T, class C>
+// D: the point width padded up (8, 16, 32 or 64); NR: 1 or up to 16
+// right-hand sides.
+template <class T, class C, int D, int NR>
 __global__ __launch_bounds__(GB_ROWS) void k_bwd_rows(const T *__restrict__ A, int64_t ma, const T *__restrict__ B,
                                                       int64_t nb, int d, C scale, const double *__restrict__ GA,
                                                       const double *__restrict__ GB, int nrhs, double inv_h2,
                                                       double *__restrict__ dA, double *__restrict__ u_out) {
-    __shared__ C bs[GB_TN][GB_DMAX];
-    __shared__ C gbs[GB_TN][GB_RMAX];
+    __shared__ C bs[GB_TN][D];
+    __shared__ C gbs[GB_TN][NR];
     const int tid = threadIdx.x;
     const int64_t a = (int64_t)blockIdx.x * GB_ROWS + tid;
-    C xa[GB_DMAX];
-    C ga[GB_RMAX];
+    C xa[D];
+    C ga[NR];
 #pragma unroll
-    for (int k = 0; k < GB_DMAX; ++k) xa[k] = (a < ma && k < d) ? (C)A[a * d + k] : (C)0;
+    for (int k = 0; k < D; ++k) xa[k] = (a < ma && k < d) ? (C)A[a * d + k] : (C)0;
 #pragma unroll
-    for (int r = 0; r < GB_RMAX; ++r) ga[r] = (a < ma && r < nrhs) ? (C)GA[a * nrhs + r] : (C)0;
+    for (int r = 0; r < NR; ++r) ga[r] = (a < ma && r < nrhs) ? (C)GA[a * nrhs + r] : (C)0;
     double s = 0.0, u = 0.0;
-    double t[GB_DMAX];
+    double t[D];
 #pragma unroll
-    for (int k = 0; k < GB_DMAX; ++k) t[k] = 0.0;
+    for (int k = 0; k < D; ++k) t[k] = 0.0;
     for (int64_t j0 = 0; j0 < nb; j0 += GB_TN) {
-        for (int e = tid; e < GB_TN * GB_DMAX; e += GB_ROWS) {
-            int jj = e / GB_DMAX, k = e % GB_DMAX;
+        for (int e = tid; e < GB_TN * D; e += GB_ROWS) {
+            int jj = e / D, k = e % D;
             int64_t j = j0 + jj;
             bs[jj][k] = (j < nb && k < d) ? (C)B[j * d + k] : (C)0;
         }
-        for (int e = tid; e < GB_TN * GB_RMAX; e += GB_ROWS) {
-            int jj = e / GB_RMAX, r = e % GB_RMAX;
+        for (int e = tid; e < GB_TN * NR; e += GB_ROWS) {
+            int jj = e / NR, r = e % NR;
             int64_t j = j0 + jj;
             gbs[jj][r] = (j < nb && r < nrhs) ? (C)GB[j * nrhs + r] : (C)0;
         }
         __syncthreads();
         C ps = 0, pu = 0;
-        C pt[GB_DMAX];
+        C pt[D];
 #pragma unroll
-        for (int k = 0; k < GB_DMAX; ++k) pt[k] = 0;
+        for (int k = 0; k < D; ++k) pt[k] = 0;
         for (int jj = 0; jj < GB_TN; ++jj) {
             C q = 0;
 #pragma unroll
-            for (int k = 0; k < GB_DMAX; ++k) {
+            for (int k = 0; k < D; ++k) {
                 C df = xa[k] - bs[jj][k];
                 q = fma(df, df, q);
             }
             C g = 0;
 #pragma unroll
-            for (int r = 0; r < GB_RMAX; ++r) g = fma(ga[r], gbs[jj][r], g);
+            for (int r = 0; r < NR; ++r) g = fma(ga[r], gbs[jj][r], g);
             C p = gexp(q, scale) * g;
             ps += p;
             pu = fma(p, q, pu);
 #pragma unroll
-            for (int k = 0; k < GB_DMAX; ++k) pt[k] = fma(p, bs[jj][k], pt[k]);
+            for (int k = 0; k < D; ++k) pt[k] = fma(p, bs[jj][k], pt[k]);
         }
         s += (double)ps;
         u += (double)pu;
 #pragma unroll
-        for (int k = 0; k < GB_DMAX; ++k) t[k] += (double)pt[k];
+        for (int k = 0; k < D; ++k) t[k] += (double)pt[k];
         __syncthreads();
     }
     if (a >= ma) return;
@@ -94,13 +98,43 @@ __global__ void k_sum_scaled(const double *__restrict__ u, int64_t m, double sca
     if (threadIdx.x == 0) *out = scale * (red[0] + red[1] + red[2] + red[3]);
 }
 
+template <class T, class C, int D>
+void bwd_rows_d(const T *A, int64_t ma, const T *B, int64_t nb, int d, C scale, const double *GA, const double *GB,
+                int nrhs, double inv_h2, double *dA, double *u, hipStream_t s) {
+    if (nrhs == 1)
+        k_bwd_rows<T, C, D, 1><<<ceil_div(ma, GB_ROWS), GB_ROWS, 0, s>>>(A, ma, B, nb, d, scale, GA, GB, nrhs, inv_h2,
+                                                                         dA, u);
+    else
+        k_bwd_rows<T, C, D, GB_RMAX><<<ceil_div(ma, GB_ROWS), GB_ROWS, 0, s>>>(A, ma, B, nb, d, scale, GA, GB, nrhs,
+                                                                               inv_h2, dA, u);
+    check_launch("k_bwd_rows");
+}
+
 template <class T, class C>
 void bwd_rows(const T *A, int64_t ma, const T *B, int64_t nb, int d, double h, const double *GA, const double *GB,
               int nrhs, double *dA, double *u, hipStream_t s) {
     C scale = (sizeof(C) == 4) ? (C)(1.4426950408889634 / (2.0 * h * h)) : (C)(1.0 / (2.0 * h * h));
-    k_bwd_rows<T, C><<<ceil_div(ma, GB_ROWS), GB_ROWS, 0, s>>>(A, ma, B, nb, d, scale, GA, GB, nrhs, 1.0 / (h * h),
-                                                                dA, u);
-    check_launch("k_bwd_rows");
+    const double ih2 = 1.0 / (h * h);
+    if (d <= 8)
+        bwd_rows_d<T, C, 8>(A, ma, B, nb, d, scale, GA, GB, nrhs, ih2, dA, u, s);
+    else if (d <= 16)
+        bwd_rows_d<T, C, 16>(A, ma, B, nb, d, scale, GA, GB, nrhs, ih2, dA, u, s);
+    else if (d <= 32)
+        bwd_rows_d<T, C, 32>(A, ma, B, nb, d, scale, GA, GB, nrhs, ih2, dA, u, s);
+    else
+        bwd_rows_d<T, C, GB_DMAX>(A, ma, B, nb, d, scale, GA, GB, nrhs, ih2, dA, u, s);
+}
+
+// dh = scale sum_a G_a v_a (one block, fixed order: deterministic)
+__global__ void k_dot_scaled(const double *__restrict__ g, const double *__restrict__ v, int64_t m, double scale,
+                             double *__restrict__ out) {
+    __shared__ double red[4];
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < m; i += blockDim.x) acc += g[i] * v[i];
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) *out = scale * (red[0] + red[1] + red[2] + red[3]);
 }
 
 template <class T>
@@ -180,6 +214,18 @@ void kernel_matvec_bwd_impl(const void *X, int64_t m, const void *Y, int64_t n, 
     KRR_REQUIRE(d <= GB_DMAX, "kernel_matvec_bwd: d = %d exceeds %d", d, GB_DMAX);
     KRR_REQUIRE(nrhs <= GB_RMAX, "kernel_matvec_bwd: nrhs = %d exceeds %d", nrhs, GB_RMAX);
     if (dW) kernel_matvec_impl(Y, n, X, m, d, xprec, h, G, nrhs, 0.0, dW, prec, s);
+    if (dh && !dX && !dY && prec == KRR_F32 && nrhs == 1) {
+        // dh alone: sum_ab P_ab q_ab / h^3 = sum_a G_a [(K o Q) W]_a / h^3, and
+        // K o Q = -(1 / c) exp2(t) t with t = -c q in log2 units: a kernel
+        // product whose entry is exp2(t) t, on the products' fast kernel
+        DBuf v = dalloc<double>(m);
+        kernel_matvec_q(X, m, Y, n, d, xprec, h, W, v.as<double>(), s);
+        const double c = 1.4426950408889634 / (2.0 * h * h);
+        k_dot_scaled<<<1, 256, 0, s>>>(G, v.as<double>(), m, -1.0 / (c * h * h * h), dh);
+        check_launch("k_dot_scaled");
+        sync(s);
+        return;
+    }
     if (xprec == KRR_F64)
         bwd_typed<double>(static_cast<const double *>(X), m, static_cast<const double *>(Y), n, d, h, W, G, nrhs, dX,
                           dY, dh, prec, s);

@@ -171,6 +171,10 @@ void predict_noalloc(const void *Xt, int64_t m, const void *Xp, int64_t n, int d
 size_t kernel_matvec_ws_bytes(int64_t m, int64_t n, int d, int nrhs, int prec);
 void kernel_matvec_ws(const void *X, int64_t m, const void *Y, int64_t n, int d, int xprec, double h,
                       const double *W, int nrhs, double *Out, int prec, void *ws, size_t ws_bytes, hipStream_t s);
+// Out = sum_j exp2(t_ij) t_ij W_j, t_ij = -|x_i - y_j|^2 log2(e) / (2 h^2):
+// the product with K o T (FP32 entries, one right-hand side, d <= 64).
+void kernel_matvec_q(const void *X, int64_t m, const void *Y, int64_t n, int d, int xprec, double h,
+                     const double *W, double *Out, hipStream_t s);
 void val_residual(const double *f, const double *yv, int64_t m, int k, double *ge, double *loss, hipStream_t s);
 void val_grad_finish(const double *bta, const double *dh_v, const double *dh_t, const double *gscale, double h,
                      double lam, double *out, hipStream_t s);

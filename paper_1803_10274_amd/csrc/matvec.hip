@@ -109,7 +109,9 @@ __global__ __launch_bounds__(MV_ROWS) void k_kmv(const T *__restrict__ X, int64_
 // LDS reads return one copy per lane and would otherwise bound the loop).
 template <int D> struct ColLd { static constexpr int V = (D + 2) & ~1; };
 
-template <class T, int D, int NR, int RPT>
+// QM: the entry is exp2(t) t instead of exp2(t) (K o T in log2 units: the
+// h-derivative of the kernel up to a constant, for the fused backward's dh).
+template <class T, int D, int NR, int RPT, bool QM = false>
 __global__ __launch_bounds__(MV_ROWS) void k_kmv_sc(const T *__restrict__ X, int64_t m, int d, double c2,
                                                     const double *__restrict__ ya, const float *__restrict__ wf,
                                                     int nrhs, int rhs0, int64_t n, int64_t cols_per_split,
@@ -181,7 +183,9 @@ __global__ __launch_bounds__(MV_ROWS) void k_kmv_sc(const T *__restrict__ X, int
                 double t = nx[q] + yv[D];
 #pragma unroll
                 for (int k = 0; k < D; ++k) t = fma(xs[q][k], yv[k], t);
-                const float kv = __builtin_amdgcn_exp2f((float)t);
+                const float tf = (float)t;
+                float kv = __builtin_amdgcn_exp2f(tf);
+                if (QM) kv = kv == 0.0f ? 0.0f : kv * tf;  // t = -inf past the tile: entry 0
 #pragma unroll
                 for (int r = 0; r < NR; ++r) pacc[q][r] = fmaf(kv, wv[r], pacc[q][r]);
             }
@@ -1051,13 +1055,13 @@ void dispatch_d(const T *X, int64_t m, const T *Y, int64_t n, int d, C scale, do
 }
 
 // Widths of the scalar-operand kernel (coordinates padded with zeros).
-template <class T, int NR>
+template <class T, int NR, bool QM = false>
 void launch_sc(int D, dim3 grid, const T *X, int64_t m, int d, double c2, const double *ya, const float *wf,
                int nrhs, int rhs0, int64_t n, int64_t cps, double *part, const SampBlock *bt, hipStream_t s) {
 #define KRR_SC(DD)                                                                                              \
     case DD:                                                                                                     \
-        k_kmv_sc<T, DD, NR, sc_rpt(DD)><<<grid, MV_ROWS, 0, s>>>(X, m, d, c2, ya, wf, nrhs, rhs0, n, cps, part, \
-                                                                 bt);                                        \
+        k_kmv_sc<T, DD, NR, sc_rpt(DD), QM><<<grid, MV_ROWS, 0, s>>>(X, m, d, c2, ya, wf, nrhs, rhs0, n, cps,   \
+                                                                     part, bt);                              \
         break;
     switch (D) {
         KRR_SC(4)
@@ -1352,7 +1356,7 @@ KmvPlan kmv_plan(int64_t m, int64_t n, int d, int nrhs, bool f32) {
 // allocated and the stream is not synchronized.
 template <class T, class C>
 void kmv_run(const T *X, int64_t m, const T *Y, int64_t n, int d, double h, const double *W, int nrhs, double beta,
-             double *Out, const KmvPlan &P, double *part, double *ya, float *wf, hipStream_t s) {
+             double *Out, const KmvPlan &P, double *part, double *ya, float *wf, hipStream_t s, bool qmode = false) {
     const C scale = kernel_scale<C>(h);
     const double c2 = kernel_scale_log2(h);
     const int nsplit = P.nsplit;
@@ -1364,7 +1368,10 @@ void kmv_run(const T *X, int64_t m, const T *Y, int64_t n, int d, double h, cons
         k_w_to_float<<<ceil_div(n * nrhs, 256), 256, 0, s>>>(W, n * nrhs, wf);
         check_launch("k_w_to_float");
         dim3 grid(ceil_div(m, P.rows_pb), nsplit);
-        for (int r0 = 0; r0 < nrhs;) {
+        if (qmode) {  // one right-hand side (checked by the caller)
+            launch_sc<T, 1, true>(D, grid, X, m, d, c2, ya, wf, nrhs, 0, n, cps, part, nullptr, s);
+        }
+        for (int r0 = qmode ? nrhs : 0; r0 < nrhs;) {
             const int left = nrhs - r0;
             const int nr = left >= 16 ? 16 : left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
             switch (nr) {
@@ -1572,6 +1579,20 @@ void kernel_matvec_ws(const void *X, int64_t m, const void *Y, int64_t n, int d,
         else
             kmv_run<float, double>(Xf, m, Yf, n, d, h, W, nrhs, 0.0, Out, P, part, ya, wf, s);
     }
+}
+
+void kernel_matvec_q(const void *X, int64_t m, const void *Y, int64_t n, int d, int xprec, double h,
+                     const double *W, double *Out, hipStream_t s) {
+    KRR_REQUIRE(d <= 64, "kernel_matvec_q: d = %d > 64", d);
+    const KmvPlan P = kmv_plan(m, n, d, 1, true);
+    DBuf part = dalloc<double>(P.part_elems), ya = dalloc<double>(P.ya_elems), wf = dalloc<float>(P.wf_elems);
+    if (xprec == KRR_F64)
+        kmv_run<double, float>(static_cast<const double *>(X), m, static_cast<const double *>(Y), n, d, h, W, 1, 0.0,
+                               Out, P, part.as<double>(), ya.as<double>(), wf.as<float>(), s, true);
+    else
+        kmv_run<float, float>(static_cast<const float *>(X), m, static_cast<const float *>(Y), n, d, h, W, 1, 0.0,
+                              Out, P, part.as<double>(), ya.as<double>(), wf.as<float>(), s, true);
+    sync(s);  // the temporaries are released on return
 }
 
 // ------------------------------------------------- tiled VALU sampling

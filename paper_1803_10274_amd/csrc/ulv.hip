@@ -24,6 +24,10 @@
 namespace krr {
 namespace {
 
+// Levels with fewer nodes than this factor in phases with their products
+// spread over many workgroups (k_tile_gemms).
+constexpr int kPhasedNodes = 64;
+
 struct UlvDesc {
     int32_t m, k, kl, kr, leaf, root;
     int32_t prob, pad_;                // the node's problem (batch)
@@ -36,13 +40,10 @@ struct UlvDesc {
     double *S_out, *Rh_out;            // passed to the parent
 };
 
-__global__ __launch_bounds__(BG_T) void k_ulv_factor(const UlvDesc *dsc, int32_t *flag, unsigned long long *clamped,
-                                                     unsigned long long *worst) {
-    __shared__ double smem[2 * 16 * 65];
-    __shared__ double red[BG_T / 64];
-    const UlvDesc q = dsc[blockIdx.x];
-    const double pivot_floor = q.pivot_floor;
-    const int m = q.m, k = q.k, ne = m - k, tid = threadIdx.x;
+// Phase 1: assemble Dw and Uw, Householder QR of Uw (V, tau, Rh_out) and the
+// compact WY factor T (Tw).
+__device__ void ulv_assemble_qr(const UlvDesc &q, double *smem, double *red) {
+    const int m = q.m, k = q.k, tid = threadIdx.x;
     double *Dw = q.Dw, *Uw = q.Uw;
     // ---- assemble
     if (q.leaf) {
@@ -121,21 +122,46 @@ __global__ __launch_bounds__(BG_T) void k_ulv_factor(const UlvDesc *dsc, int32_t
             if (tid == 0) q.Tw[(int64_t)j * k + j] = tj;
             __syncthreads();
         }
-        // ---- Dw <- Q^T Dw Q as GEMMs: left Dw -= V (T^T (V^T Dw)),
-        // right Dw -= ((Dw V) T) V^T
-        double *Y = q.Yw, *Z = q.Zw;
-        block_gemm(k, m, m, 1.0, q.V, 1, k, Dw, m, 1, 0.0, Y, m, smem);         // Y = V^T Dw   (k x m)
-        block_gemm(k, m, k, 1.0, q.Tw, 1, k, Y, m, 1, 0.0, Z, m, smem);         // Z = T^T Y    (k x m)
-        block_gemm(m, m, k, -1.0, q.V, k, 1, Z, m, 1, 1.0, Dw, m, smem);        // Dw -= V Z
-        block_gemm(m, k, m, 1.0, Dw, m, 1, q.V, k, 1, 0.0, Y, k, smem);         // Y = Dw V     (m x k)
-        block_gemm(m, k, k, 1.0, Y, k, 1, q.Tw, k, 1, 0.0, Z, k, smem);         // Z = Y T      (m x k)
-        block_gemm(m, m, k, -1.0, Z, k, 1, q.V, 1, k, 1.0, Dw, m, smem);        // Dw -= Z V^T
     }
     if (!q.root)
         for (int t = tid; t < k * k; t += BG_T) {
             int i = t / k, c = t % k;
             q.Rh_out[t] = (c >= i) ? Uw[(int64_t)i * k + c] : 0.0;
         }
+    __syncthreads();
+}
+
+// Phase 2: Dw <- Q^T Dw Q as GEMMs: left Dw -= V (T^T (V^T Dw)), right
+// Dw -= ((Dw V) T) V^T.  The six products, as batch jobs (j < 6) or one
+// workgroup's block products.
+__device__ __forceinline__ GemmJob ulv_transform_job(const UlvDesc &q, int j) {
+    const int m = q.m, k = q.k;
+    double *Y = q.Yw, *Z = q.Zw, *Dw = q.Dw;
+    switch (j) {
+        case 0: return {k, m, m, 1.0, 0.0, q.V, 1, k, Dw, m, 1, Y, m};        // Y = V^T Dw   (k x m)
+        case 1: return {k, m, k, 1.0, 0.0, q.Tw, 1, k, Y, m, 1, Z, m};       // Z = T^T Y    (k x m)
+        case 2: return {m, m, k, -1.0, 1.0, q.V, k, 1, Z, m, 1, Dw, m};      // Dw -= V Z
+        case 3: return {m, k, m, 1.0, 0.0, Dw, m, 1, q.V, k, 1, Y, k};       // Y = Dw V     (m x k)
+        case 4: return {m, k, k, 1.0, 0.0, Y, k, 1, q.Tw, k, 1, Z, k};       // Z = Y T      (m x k)
+        default: return {m, m, k, -1.0, 1.0, Z, k, 1, q.V, 1, k, Dw, m};     // Dw -= Z V^T
+    }
+}
+
+__device__ void ulv_transform(const UlvDesc &q, double *smem) {
+    if (q.k <= 0) return;
+    for (int j = 0; j < 6; ++j) {
+        const GemmJob J = ulv_transform_job(q, j);
+        block_gemm(J.M, J.N, J.K, J.alpha, J.A, J.as0, J.as1, J.B, J.bs0, J.bs1, J.beta, J.C, J.ldc, smem);
+    }
+}
+
+// Phase 3: Cholesky of A_ee and its inverse; false (and the flag raised) on a
+// non-positive pivot.
+__device__ bool ulv_chol_inv(const UlvDesc &q, int32_t *flag, unsigned long long *clamped,
+                             unsigned long long *worst, double *red) {
+    const double pivot_floor = q.pivot_floor;
+    const int m = q.m, k = q.k, ne = m - k, tid = threadIdx.x;
+    double *Dw = q.Dw;
     // ---- Cholesky of A_ee = Dw[k:, k:] (right-looking, in place).  With a
     // pivot floor, a pivot d below it is replaced, as in the modified Cholesky
     // of Gill, Murray and Wright, by max(floor, |d|, theta^2 / beta^2), theta
@@ -196,7 +222,7 @@ __global__ __launch_bounds__(BG_T) void k_ulv_factor(const UlvDesc *dsc, int32_t
     }
     if (bad) {
         if (tid == 0) atomicOr(flag, 1);
-        return;
+        return false;
     }
     // L^{-1} (lower triangular, zeros stored above the diagonal): column c by
     // forward substitution on the unit vector e_c, one thread per column
@@ -209,17 +235,74 @@ __global__ __launch_bounds__(BG_T) void k_ulv_factor(const UlvDesc *dsc, int32_t
             q.L[(int64_t)i * ne + c] = t / Li[i];
         }
     }
-    if (q.root) return;
     __syncthreads();
-    // W = A_ce L^{-T}
-    block_gemm(k, ne, ne, 1.0, Dw + k, m, 1, q.L, 1, ne, 0.0, q.W, ne, smem);
-    __syncthreads();
-    // S = A_cc - W W^T
-    block_gemm(k, k, ne, -1.0, q.W, ne, 1, q.W, 1, ne, 1.0, Dw, m, smem);
-    for (int t = tid; t < k * k; t += BG_T) {
+    return true;
+}
+
+// Phase 4: W = A_ce L^{-T}, S = A_cc - W W^T (jobs 0, 1), and S passed up
+// symmetrized.
+__device__ __forceinline__ GemmJob ulv_schur_job(const UlvDesc &q, int j) {
+    const int m = q.m, k = q.k, ne = m - k;
+    if (j == 0) return {k, ne, ne, 1.0, 0.0, q.Dw + k, m, 1, q.L, 1, ne, q.W, ne};  // W = A_ce L^{-T}
+    return {k, k, ne, -1.0, 1.0, q.W, ne, 1, q.W, 1, ne, q.Dw, m};                   // A_cc -= W W^T
+}
+
+__device__ void ulv_schur_out(const UlvDesc &q) {
+    const int m = q.m, k = q.k;
+    for (int t = threadIdx.x; t < k * k; t += BG_T) {
         int i = t / k, c = t % k;
-        q.S_out[t] = 0.5 * (Dw[(int64_t)i * m + c] + Dw[(int64_t)c * m + i]);
+        q.S_out[t] = 0.5 * (q.Dw[(int64_t)i * m + c] + q.Dw[(int64_t)c * m + i]);
     }
+}
+
+// The whole elimination of a level's nodes, one workgroup per node.
+__global__ __launch_bounds__(BG_T) void k_ulv_factor(const UlvDesc *dsc, int32_t *flag, unsigned long long *clamped,
+                                                     unsigned long long *worst) {
+    __shared__ double smem[2 * 16 * 65];
+    __shared__ double red[BG_T / 64];
+    const UlvDesc q = dsc[blockIdx.x];
+    ulv_assemble_qr(q, smem, red);
+    ulv_transform(q, smem);
+    if (!ulv_chol_inv(q, flag, clamped, worst, red)) return;
+    if (q.root) return;
+    for (int j = 0; j < 2; ++j) {
+        const GemmJob J = ulv_schur_job(q, j);
+        block_gemm(J.M, J.N, J.K, J.alpha, J.A, J.as0, J.as1, J.B, J.bs0, J.bs1, J.beta, J.C, J.ldc, smem);
+    }
+    ulv_schur_out(q);
+}
+
+// The same phases for levels of few, large nodes: phases 1 and 3 one
+// workgroup per node, the products of phases 2 and 4 one workgroup per tile
+// of every node of the level (k_tile_gemms), the output last.
+__global__ __launch_bounds__(BG_T) void k_ulv_phase1(const UlvDesc *dsc) {
+    __shared__ double smem[2 * 16 * 65];
+    __shared__ double red[BG_T / 64];
+    const UlvDesc q = dsc[blockIdx.x];
+    ulv_assemble_qr(q, smem, red);
+}
+
+__global__ __launch_bounds__(BG_T) void k_ulv_phase3(const UlvDesc *dsc, int32_t *flag, unsigned long long *clamped,
+                                                     unsigned long long *worst) {
+    __shared__ double red[BG_T / 64];
+    const UlvDesc q = dsc[blockIdx.x];
+    ulv_chol_inv(q, flag, clamped, worst, red);
+}
+
+__global__ __launch_bounds__(BG_T) void k_ulv_schur_out(const UlvDesc *dsc) {
+    const UlvDesc q = dsc[blockIdx.x];
+    if (!q.root) ulv_schur_out(q);
+}
+
+// One 64 x 64 tile of one job per workgroup; jobs are filled in on the device
+// from the level's descriptors (step: 0-5 the transform, 6-7 the Schur
+// complement).
+__global__ __launch_bounds__(BG_T) void k_tile_gemms(const UlvDesc *dsc, const GemmTile *tiles, int step) {
+    __shared__ double smem[2 * 16 * 65];
+    const GemmTile t = tiles[blockIdx.x];
+    const UlvDesc q = dsc[t.job];
+    const GemmJob J = step < 6 ? ulv_transform_job(q, step) : ulv_schur_job(q, step - 6);
+    tile_gemm(J.M, J.N, J.K, t.i0, t.j0, J.alpha, J.A, J.as0, J.as1, J.B, J.bs0, J.bs1, J.beta, J.C, J.ldc, smem);
 }
 
 struct SolveDesc {
@@ -466,9 +549,53 @@ int64_t ulv_factor(const hss_s *H, const std::vector<double> &lam, const std::ve
             u.Rh_out = Rb.as<double>() + offS[id];
         }
         DBuf dd = upload(dsc, s);
-        k_ulv_factor<<<cnt, BG_T, 0, s>>>(dd.as<UlvDesc>(), flag.as<int32_t>(), nclamp.as<unsigned long long>(),
-                                          nclamp.as<unsigned long long>() + np);
-        check_launch("k_ulv_factor");
+        if (cnt >= kPhasedNodes) {
+            k_ulv_factor<<<cnt, BG_T, 0, s>>>(dd.as<UlvDesc>(), flag.as<int32_t>(), nclamp.as<unsigned long long>(),
+                                              nclamp.as<unsigned long long>() + np);
+            check_launch("k_ulv_factor");
+        } else {
+            // few, large nodes (near the root): the products of each phase
+            // spread over one workgroup per 64 x 64 tile of every node
+            std::vector<GemmTile> tiles;
+            std::vector<int64_t> step_off(9, 0);
+            for (int step = 0; step < 8; ++step) {
+                step_off[step] = (int64_t)tiles.size();
+                for (int a = 0; a < cnt; ++a) {
+                    const UlvDesc &u = dsc[a];
+                    const int ne = u.m - u.k;
+                    if (u.k <= 0 || (step >= 6 && u.root)) continue;
+                    int M, N;
+                    if (step < 6) {
+                        M = (step <= 1) ? u.k : u.m;
+                        N = (step == 3 || step == 4) ? u.k : u.m;
+                    } else {
+                        M = u.k;
+                        N = step == 6 ? ne : u.k;
+                    }
+                    for (int i0 = 0; i0 < M; i0 += 64)
+                        for (int j0 = 0; j0 < N; j0 += 64) tiles.push_back({a, i0, j0});
+                }
+            }
+            step_off[8] = (int64_t)tiles.size();
+            DBuf dt = upload(tiles, s);
+            auto gemms = [&](int step) {
+                const int64_t nt = step_off[step + 1] - step_off[step];
+                if (nt == 0) return;
+                k_tile_gemms<<<(unsigned)nt, BG_T, 0, s>>>(dd.as<UlvDesc>(), dt.as<GemmTile>() + step_off[step], step);
+                check_launch("k_tile_gemms");
+            };
+            k_ulv_phase1<<<cnt, BG_T, 0, s>>>(dd.as<UlvDesc>());
+            check_launch("k_ulv_phase1");
+            for (int step = 0; step < 6; ++step) gemms(step);
+            k_ulv_phase3<<<cnt, BG_T, 0, s>>>(dd.as<UlvDesc>(), flag.as<int32_t>(), nclamp.as<unsigned long long>(),
+                                              nclamp.as<unsigned long long>() + np);
+            check_launch("k_ulv_phase3");
+            gemms(6);
+            gemms(7);
+            k_ulv_schur_out<<<cnt, BG_T, 0, s>>>(dd.as<UlvDesc>());
+            check_launch("k_ulv_schur_out");
+            sync(s);  // `tiles` is released at the end of this scope
+        }
         sync(s);
         if (stop_at_floor) {
             // a problem with a pivot below its floor stops here (its factor

@@ -38,6 +38,26 @@ def test_kernel_matvec_autograd(gpu_lib):
     assert abs(ht.grad.item() - dh) <= 1e-10 * abs(dh)
 
 
+@pytest.mark.parametrize("m,n,d,same", [(3001, 2500, 18, False), (1000, 1000, 8, True), (777, 4099, 40, False)])
+def test_fused_backward_dh_fp32(gpu_lib, m, n, d, same):
+    # dh alone with FP32 entries runs as the product with the entry exp2(t) t
+    # (split-K kernel, FP64 exponents rounded to FP32, FP32 tile sums of 64
+    # columns, FP64 across tiles): within 1e-5 of sum_ab |P_ab| q_ab / h^3
+    Y = sd.points(n, d, seed=41 + d, scale=0.4)
+    X = Y if same else sd.points(m, d, seed=42 + d, scale=0.4)
+    W = sd.vectors(n, 1, seed=43)
+    G = sd.vectors(X.shape[0], 1, seed=44)
+    h = 0.3 * np.sqrt(d)
+    Xt = _t(X)
+    Yt = Xt if same else _t(Y)
+    got = gpu_lib.kernel_matvec_bwd(Xt, Yt, h, _t(W), _t(G), prec="f32", want=("dh",))["dh"].item()
+    _, _, _, dh = og.matvec_bwd(X.astype(np.float64), Y.astype(np.float64), W, G, h)
+    Xd, Yd = X.astype(np.float64), Y.astype(np.float64)
+    Q = ((Xd[:, None, :] - Yd[None, :, :]) ** 2).sum(axis=2)
+    mag = float((np.abs(G) * (np.exp(-Q / (2 * h * h)) * Q) @ np.abs(W)).sum() / h**3)
+    assert abs(got - dh) <= 1e-5 * mag, (got, dh, mag)
+
+
 @pytest.mark.parametrize("n,mv", [(2048, 512), (8192, 1024)])
 def test_validation_gradient_against_oracle(gpu_lib, n, mv):
     from paper_1803_10274_amd.autograd import validation_loss
