@@ -200,8 +200,9 @@ def time_launches(fn, reps):
 
 
 def kernels_only(args):
-    """One launch each: a 1 GiB device copy, the sampling product and the
-    refinement kernel product, on the 16-Gaussian workload in tree order."""
+    """One launch each: a 1 GiB device copy, the sampling product (with the
+    negligible-tile skip, then with every tile evaluated) and the refinement
+    kernel product, on the 16-Gaussian workload in tree order."""
     import torch
 
     import paper_1803_10274_amd as krr
@@ -221,8 +222,13 @@ def kernels_only(args):
     log("copy 1 GiB")
     b.copy_(a)
     torch.cuda.synchronize()
-    log("sampling product")
+    log("sampling product (negligible tiles skipped)")
     krr.kernel_sample(Xp, p.h, R, lb, le, prec=args.prec, split_terms=args.split)
+    torch.cuda.synchronize()
+    log("sampling product (every tile evaluated)")
+    krr.set_tuning("sample_skip", 0)
+    krr.kernel_sample(Xp, p.h, R, lb, le, prec=args.prec, split_terms=args.split)
+    krr.set_tuning("sample_skip", 1)
     torch.cuda.synchronize()
     log("kernel product")
     krr.kernel_matvec(Xp, Xp, p.h, w, prec="f32")
@@ -430,6 +436,14 @@ def main():
                    "launch_s": t_sample, "algorithmic_flops": flops,
                    "flops_basis": "n^2 (2d + 2r): one distance dot product and one row of K R per kernel entry"}
     roof_sample.update(pmc_mfma("sampling", n, r, t_sample))
+    # the same launch with every tile evaluated (no entry dropped): the
+    # kernel's efficiency on full tiles
+    krr.set_tuning("sample_skip", 0)
+    t_full = time_launches(lambda: krr.kernel_sample(Xp, p.h, R, lb, le, prec=args.prec, split_terms=args.split),
+                           args.reps)
+    krr.set_tuning("sample_skip", 1)
+    roof_sample["every_tile"] = {"launch_s": t_full, "achieved": flops / t_full / 1e12, "frac": flops / t_full / peak}
+    roof_sample["every_tile"].update(pmc_mfma("sampling_every_tile", n, r, t_full))
     del R
     w = res.alpha_perm.reshape(n, -1)[:, :1].contiguous()
     log("timing the refinement kernel product")

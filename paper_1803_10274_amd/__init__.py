@@ -276,7 +276,8 @@ def kernel_matvec_bwd(X, Y, h, W, G, prec="f32", want=("dX", "dY", "dW", "dh")):
 
 
 TUNE = {"symmetric": _lib.KRR_TUNE_SYMMETRIC, "sample_rb": _lib.KRR_TUNE_SAMPLE_RB,
-        "mv_blocks": _lib.KRR_TUNE_MV_BLOCKS, "sym_chunk": _lib.KRR_TUNE_SYM_CHUNK}
+        "mv_blocks": _lib.KRR_TUNE_MV_BLOCKS, "sym_chunk": _lib.KRR_TUNE_SYM_CHUNK,
+        "sample_skip": _lib.KRR_TUNE_SAMPLE_SKIP}
 
 
 def set_tuning(knob: str, value: int):

@@ -9,7 +9,7 @@ LIB_PATH = os.path.join(HERE, "libkrr.so")
 KRR_OK, KRR_E_INVAL, KRR_E_NOMEM, KRR_E_HIP = 0, -1, -2, -3
 KRR_E_RANK_CAP, KRR_E_NUMERIC, KRR_E_NOT_CONVERGED, KRR_E_NODEVICE = -4, -5, -6, -7
 KRR_F64, KRR_F32, KRR_F16_SPLIT, KRR_BF16_SPLIT = 0, 1, 2, 3
-KRR_TUNE_SYMMETRIC, KRR_TUNE_SAMPLE_RB, KRR_TUNE_MV_BLOCKS, KRR_TUNE_SYM_CHUNK = 0, 1, 2, 3
+KRR_TUNE_SYMMETRIC, KRR_TUNE_SAMPLE_RB, KRR_TUNE_MV_BLOCKS, KRR_TUNE_SYM_CHUNK, KRR_TUNE_SAMPLE_SKIP = 0, 1, 2, 3, 4
 
 _CODES = {KRR_E_INVAL: "KRR_E_INVAL", KRR_E_NOMEM: "KRR_E_NOMEM", KRR_E_HIP: "KRR_E_HIP",
           KRR_E_RANK_CAP: "KRR_E_RANK_CAP", KRR_E_NUMERIC: "KRR_E_NUMERIC",

@@ -28,7 +28,7 @@ Allocator current_allocator() {
 hipStream_t call_stream() { return g_call_stream; }
 void note_allocation(bool by_caller) { (by_caller ? g_alloc_caller : g_alloc_direct).fetch_add(1); }
 
-std::atomic<int> g_tune[KRR_TUNE_COUNT] = {{4}, {8}, {2048}, {16384}};
+std::atomic<int> g_tune[KRR_TUNE_COUNT] = {{4}, {8}, {2048}, {16384}, {1}};
 
 int tune_get(int knob) { return g_tune[knob].load(std::memory_order_relaxed); }
 
@@ -635,6 +635,7 @@ int krr_set_tuning(int32_t knob, int32_t value) {
                 KRR_REQUIRE(value == 1 || value == 2 || value == 4 || value == 8, "krr_set_tuning: sample RB is 1, 2, 4 or 8");
                 break;
             case KRR_TUNE_MV_BLOCKS: KRR_REQUIRE(value >= 64 && value <= 65536, "krr_set_tuning: blocks in [64, 65536]"); break;
+            case KRR_TUNE_SAMPLE_SKIP: KRR_REQUIRE(value == 0 || value == 1, "krr_set_tuning: sample skip is 0 or 1"); break;
             case KRR_TUNE_SYM_CHUNK:
                 KRR_REQUIRE(value >= 64 && value % 64 == 0 && value <= (1 << 24), "krr_set_tuning: chunk multiple of 64");
                 break;

@@ -16,7 +16,7 @@ constexpr int BG_T = 256;  // threads per node workgroup
 // C row-major with leading dimension ldc.  beta == 0 never reads C.
 // smem: at least 2 * 16 * 65 doubles.  All 256 threads must call it.
 template <class TA, class TB>
-__device__ void tile_gemm(int M, int N, int K, int i0, int j0, double alpha, const TA *__restrict__ A, int64_t as0,
+__device__ __forceinline__ void tile_gemm(int M, int N, int K, int i0, int j0, double alpha, const TA *__restrict__ A, int64_t as0,
                           int64_t as1, const TB *__restrict__ B, int64_t bs0, int64_t bs1, double beta,
                           double *__restrict__ C, int64_t ldc, double *smem) {
     double(*As)[65] = reinterpret_cast<double(*)[65]>(smem);
@@ -66,7 +66,7 @@ __device__ void tile_gemm(int M, int N, int K, int i0, int j0, double alpha, con
 
 // The whole product by one workgroup, tile after tile.
 template <class TA, class TB>
-__device__ void block_gemm(int M, int N, int K, double alpha, const TA *__restrict__ A, int64_t as0,
+__device__ __forceinline__ void block_gemm(int M, int N, int K, double alpha, const TA *__restrict__ A, int64_t as0,
                            int64_t as1, const TB *__restrict__ B, int64_t bs0, int64_t bs1, double beta,
                            double *__restrict__ C, int64_t ldc, double *smem) {
     for (int i0 = 0; i0 < M; i0 += 64)

@@ -315,7 +315,7 @@ __global__ __launch_bounds__(THREADS) void k_sample_mfma(const T *__restrict__ X
                                                          const void *__restrict__ Rsw_, int RBt, int cb0,
                                                          const int32_t *__restrict__ lb, const int32_t *__restrict__ le,
                                                          float *__restrict__ S, int ldS,
-                                                         const SampBlock *__restrict__ bt) {
+                                                         const SampBlock *__restrict__ bt, float skip_log2) {
     constexpr int OPM = MODE == M_F32 ? M_F16 : MODE;
     typedef typename Op<OPM>::V V;
     constexpr int RTILE_H = RB * 2 * 64 * 8;
@@ -432,7 +432,7 @@ __global__ __launch_bounds__(THREADS) void k_sample_mfma(const T *__restrict__ X
         float a0[16], a1[16], tv[16];
         bool sk0, sk1 = false;
         expo_f<D>(tv, xs, nx, ysh[s0 & 1], t_lo_off, g);
-        sk0 = tile_negligible(tv, 16, kSkipLog2);
+        sk0 = tile_negligible(tv, 16, skip_log2);
         if (!sk0) exp_f<true>(a0, tv, g, t_lo * JT, my_lb, my_le);
         for (int64_t t = t_lo; t < t_hi; t += 2) {
 #pragma unroll
@@ -451,7 +451,7 @@ __global__ __launch_bounds__(THREADS) void k_sample_mfma(const T *__restrict__ X
                 bool &skc = half == 0 ? sk0 : sk1;
                 bool &skn = half == 0 ? sk1 : sk0;
                 expo_f<D>(tv, xs, nx, ysn, pbn, g);
-                skn = tile_negligible(tv, 16, kSkipLog2);
+                skn = tile_negligible(tv, 16, skip_log2);
                 if (!skc) mfma_f<RB>(acc, cur, rbuf[tc & 1], lane);
                 if (!skn) {
                     if (KRR_TILE_MASKED(tn))
@@ -513,7 +513,7 @@ __global__ __launch_bounds__(THREADS) void k_sample_mfma(const T *__restrict__ X
         __syncthreads();
         V h0[2], l0[2], h1[2], l1[2];
         // the threshold in the exponents' units (FP16 entries carry 2^14)
-        constexpr float thr = kSkipLog2 + kE2;
+        const float thr = skip_log2 + kE2;
         bool sk0, sk1 = false;
         {
             f16v t0 = dist(t_lo);
@@ -599,6 +599,8 @@ void launch_passes(const T *X, int64_t n, int d, float cs, const void *Rsw, int 
                    const int32_t *le, float *S, hipStream_t s, const SampBlock *bt, int64_t nblk) {
     constexpr int RBM = RbMax<D, MODE>::V;
     const int cap = std::min(RBM, tune_get(KRR_TUNE_SAMPLE_RB));  // column blocks per pass
+    // no tile's exponents are below -inf: the knob off evaluates every tile
+    const float skip = tune_get(KRR_TUNE_SAMPLE_SKIP) ? kSkipLog2 : -INFINITY;
     const int RBt = r / 32;
     int cb0 = 0;
     while (cb0 < RBt) {
@@ -606,17 +608,17 @@ void launch_passes(const T *X, int64_t n, int d, float cs, const void *Rsw, int 
         dim3 grid((unsigned)(bt ? nblk : ceil_div(n, ROWS)));
         if (RBM >= 8 && cap >= 8 && left >= 8) {
             k_sample_mfma<T, D, (RBM >= 8 ? 8 : RBM), MODE, TERMS><<<grid, THREADS, 0, s>>>(X, n, d, cs, Rsw, RBt, cb0,
-                                                                                        lb, le, S, r, bt);
+                                                                                        lb, le, S, r, bt, skip);
             cb0 += 8;
         } else if (RBM >= 4 && cap >= 4 && left >= 4) {
             k_sample_mfma<T, D, (RBM >= 4 ? 4 : RBM), MODE, TERMS><<<grid, THREADS, 0, s>>>(X, n, d, cs, Rsw, RBt, cb0,
-                                                                                        lb, le, S, r, bt);
+                                                                                        lb, le, S, r, bt, skip);
             cb0 += 4;
         } else if (cap >= 2 && left >= 2) {
-            k_sample_mfma<T, D, 2, MODE, TERMS><<<grid, THREADS, 0, s>>>(X, n, d, cs, Rsw, RBt, cb0, lb, le, S, r, bt);
+            k_sample_mfma<T, D, 2, MODE, TERMS><<<grid, THREADS, 0, s>>>(X, n, d, cs, Rsw, RBt, cb0, lb, le, S, r, bt, skip);
             cb0 += 2;
         } else {
-            k_sample_mfma<T, D, 1, MODE, TERMS><<<grid, THREADS, 0, s>>>(X, n, d, cs, Rsw, RBt, cb0, lb, le, S, r, bt);
+            k_sample_mfma<T, D, 1, MODE, TERMS><<<grid, THREADS, 0, s>>>(X, n, d, cs, Rsw, RBt, cb0, lb, le, S, r, bt, skip);
             cb0 += 1;
         }
         check_launch("k_sample_mfma");

@@ -36,14 +36,43 @@ struct UlvDesc {
     const double *S_l, *S_r, *Rh_l, *Rh_r;
     double *Dw, *Uw, *Tmp;             // scratch
     double *Yw, *Zw;                   // scratch of the blocked transform: k x m, k x m
+    double *Sw;                        // scratch of the blocked inverse: 32 x m
     double *V, *tau, *Tw, *L, *W;      // factor (Tw: the WY T, k x k; L: the inverse Cholesky factor)
     double *S_out, *Rh_out;            // passed to the parent
 };
 
+constexpr int QR_NB = 16;  // panel width of the blocked QR (and block of T)
+constexpr int CH_NB = 32;  // panel width of the blocked Cholesky and of L^{-1}'s blocks
+
+// The diagonal block T_p (pb x pb, pb <= 32) of the compact WY factor from
+// G_p = V_p^T V_p (row-major pb x pb) and the reflectors' tau, by the
+// recurrence T(i, j) = -tau_j sum_{l=i}^{j-1} T(i, l) G(l, j), T(j, j) = tau_j,
+// in LDS; written to T (leading dimension ldt).
+__device__ void wy_diag_block(const double *tau, const double *G, int pb, double *T, int ldt, double (*blk)[33]) {
+    double(*g)[33] = blk, (*t)[33] = blk + 32;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < pb * pb; e += BG_T) {
+        g[e / pb][e % pb] = G[e];
+        t[e / pb][e % pb] = 0.0;
+    }
+    __syncthreads();
+    for (int j = 0; j < pb; ++j) {
+        if (tid < j) {
+            double acc = 0.0;
+            for (int l = tid; l < j; ++l) acc += t[tid][l] * g[l][j];
+            t[tid][j] = -tau[j] * acc;
+        }
+        if (tid == j) t[j][j] = tau[j];
+        __syncthreads();
+    }
+    for (int e = tid; e < pb * pb; e += BG_T) T[(int64_t)(e / pb) * ldt + e % pb] = t[e / pb][e % pb];
+    __syncthreads();
+}
+
 // Phase 1: assemble Dw and Uw, Householder QR of Uw (V, tau, Rh_out) and the
 // compact WY factor T (Tw).
-__device__ void ulv_assemble_qr(const UlvDesc &q, double *smem, double *red) {
-    const int m = q.m, k = q.k, tid = threadIdx.x;
+__device__ void ulv_assemble_qr(const UlvDesc &q, double *smem, double *red, double (*blk)[33]) {
+    const int m = q.m, k = q.k, tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
     double *Dw = q.Dw, *Uw = q.Uw;
     // ---- assemble
     if (q.leaf) {
@@ -67,61 +96,77 @@ __device__ void ulv_assemble_qr(const UlvDesc &q, double *smem, double *red) {
         }
     }
     __syncthreads();
-    // ---- Householder QR of Uw (reflectors kept in V, tau)
-    for (int j = 0; j < k; ++j) {
-        double part = 0.0;
-        for (int i = j + 1 + tid; i < m; i += BG_T) part += Uw[(int64_t)i * k + j] * Uw[(int64_t)i * k + j];
-        double sig = block_sum(part, red);
-        double alpha = Uw[(int64_t)j * k + j];
-        double tau, beta, scal;
-        if (sig == 0.0) {
-            tau = 0.0;
-            beta = alpha;
-            scal = 0.0;
-        } else {
-            double nrm = sqrt(alpha * alpha + sig);
-            beta = alpha >= 0.0 ? -nrm : nrm;
-            tau = (beta - alpha) / beta;
-            scal = 1.0 / (alpha - beta);
-        }
-        // reflector v: v[j] = 1, v[i > j] = x[i] * scal; stored in column j of V
-        for (int i = tid; i < m; i += BG_T) {
-            double v = (i < j) ? 0.0 : (i == j ? 1.0 : Uw[(int64_t)i * k + j] * scal);
-            q.V[(int64_t)i * k + j] = v;
-        }
-        if (tid == 0) q.tau[j] = tau;
-        __syncthreads();
-        const double *v = q.V + j;  // stride k
-        // Uw[j:, c] for c > j
-        for (int c = j + 1 + tid; c < k; c += BG_T) {
-            double w = 0.0;
-            for (int i = j; i < m; ++i) w += v[(int64_t)i * k] * Uw[(int64_t)i * k + c];
-            w *= tau;
-            for (int i = j; i < m; ++i) Uw[(int64_t)i * k + c] -= w * v[(int64_t)i * k];
-        }
-        __syncthreads();
-        if (tid == 0) Uw[(int64_t)j * k + j] = beta;
-        for (int i = j + 1 + tid; i < m; i += BG_T) Uw[(int64_t)i * k + j] = 0.0;
-    }
+    // ---- Householder QR of Uw (reflectors in V, tau), blocked: panels of
+    // QR_NB columns are factored column by column, the columns right of a
+    // panel get its block reflector Q_p^T = I - V_p T_p^T V_p^T as three
+    // products.  T_p is the diagonal block of the compact WY factor T of
+    // Q = H_0 ... H_(k-1) = I - V T V^T, whose column j is T(0:j, j) =
+    // -tau_j T(0:j, 0:j) G(0:j, j), T(j, j) = tau_j, G = V^T V.
+    for (int t = tid; t < k * k; t += BG_T) q.Tw[t] = 0.0;
     __syncthreads();
-    if (k > 0) {
-        // ---- compact WY form Q = H_0 ... H_(k-1) = I - V T V^T (T upper
-        // triangular): with G = V^T V, column j of T is T(0:j, j) =
-        // -tau_j T(0:j, 0:j) G(0:j, j) and T(j, j) = tau_j
-        double *G = q.Yw;  // k x k, before Yw is needed
-        block_gemm(k, k, m, 1.0, q.V, 1, k, q.V, k, 1, 0.0, G, k, smem);
-        for (int t = tid; t < k * k; t += BG_T) q.Tw[t] = 0.0;
-        __syncthreads();
-        for (int j = 0; j < k; ++j) {
-            const double tj = q.tau[j];
-            for (int i = tid; i < j; i += BG_T) {
-                double acc = 0.0;
-                for (int l = i; l < j; ++l) acc += q.Tw[(int64_t)i * k + l] * G[(int64_t)l * k + j];
-                q.Tw[(int64_t)i * k + j] = -tj * acc;
+    for (int p0 = 0; p0 < k; p0 += QR_NB) {
+        const int p1 = min(k, p0 + QR_NB), pb = p1 - p0;
+        for (int j = p0; j < p1; ++j) {
+            double part = 0.0;
+            for (int i = j + 1 + tid; i < m; i += BG_T) part += Uw[(int64_t)i * k + j] * Uw[(int64_t)i * k + j];
+            double sig = block_sum(part, red);
+            double alpha = Uw[(int64_t)j * k + j];
+            double tau, beta, scal;
+            if (sig == 0.0) {
+                tau = 0.0;
+                beta = alpha;
+                scal = 0.0;
+            } else {
+                double nrm = sqrt(alpha * alpha + sig);
+                beta = alpha >= 0.0 ? -nrm : nrm;
+                tau = (beta - alpha) / beta;
+                scal = 1.0 / (alpha - beta);
             }
-            if (tid == 0) q.Tw[(int64_t)j * k + j] = tj;
+            // reflector v: v[j] = 1, v[i > j] = x[i] * scal; stored in column j of V
+            for (int i = tid; i < m; i += BG_T) {
+                double v = (i < j) ? 0.0 : (i == j ? 1.0 : Uw[(int64_t)i * k + j] * scal);
+                q.V[(int64_t)i * k + j] = v;
+            }
+            if (tid == 0) q.tau[j] = tau;
+            __syncthreads();
+            // the panel's columns c > j: a wave per column, lanes over rows
+            const double *v = q.V + j;  // stride k
+            for (int c = j + 1 + wv; c < p1; c += BG_T / 64) {
+                double w = 0.0;
+                for (int i = j + ln; i < m; i += 64) w += v[(int64_t)i * k] * Uw[(int64_t)i * k + c];
+                w = tau * wave_sum(w);
+                for (int i = j + ln; i < m; i += 64) Uw[(int64_t)i * k + c] -= w * v[(int64_t)i * k];
+            }
+            __syncthreads();
+            if (tid == 0) Uw[(int64_t)j * k + j] = beta;
+            for (int i = j + 1 + tid; i < m; i += BG_T) Uw[(int64_t)i * k + j] = 0.0;
             __syncthreads();
         }
+        // T_p from G_p = V_p^T V_p (rows p0..m) by the recurrence, in LDS
+        double *Gs = q.Yw;  // pb x pb
+        block_gemm(pb, pb, m - p0, 1.0, q.V + (int64_t)p0 * k + p0, 1, k, q.V + (int64_t)p0 * k + p0, k, 1, 0.0, Gs,
+                   pb, smem);
+        wy_diag_block(q.tau + p0, Gs, pb, q.Tw + (int64_t)p0 * k + p0, k, blk);
+        if (p1 < k) {
+            // Uw(p0:m, p1:k) -= V_p (T_p^T (V_p^T Uw(p0:m, p1:k)))
+            const int nt = k - p1;
+            double *W1 = q.Yw, *W2 = q.Zw;  // pb x nt each
+            block_gemm(pb, nt, m - p0, 1.0, q.V + (int64_t)p0 * k + p0, 1, k, Uw + (int64_t)p0 * k + p1, k, 1, 0.0,
+                       W1, nt, smem);
+            block_gemm(pb, nt, pb, 1.0, q.Tw + (int64_t)p0 * k + p0, 1, k, W1, nt, 1, 0.0, W2, nt, smem);
+            block_gemm(m - p0, nt, pb, -1.0, q.V + (int64_t)p0 * k + p0, k, 1, W2, nt, 1, 1.0,
+                       Uw + (int64_t)p0 * k + p1, k, smem);
+        }
+    }
+    // ---- the rest of T, block column by block column:
+    // T(0:p0, p0:p1) = -T(0:p0, 0:p0) G(0:p0, p0:p1) T_p
+    for (int p0 = QR_NB; p0 < k; p0 += QR_NB) {
+        const int p1 = min(k, p0 + QR_NB), pb = p1 - p0;
+        double *Gc = q.Yw, *Z = q.Zw;  // p0 x pb each
+        block_gemm(p0, pb, m - p0, 1.0, q.V + (int64_t)p0 * k, 1, k, q.V + (int64_t)p0 * k + p0, k, 1, 0.0, Gc, pb,
+                   smem);
+        block_gemm(p0, pb, pb, 1.0, Gc, pb, 1, q.Tw + (int64_t)p0 * k + p0, k, 1, 0.0, Z, pb, smem);
+        block_gemm(p0, pb, p0, -1.0, q.Tw, k, 1, Z, pb, 1, 0.0, q.Tw + p0, k, smem);
     }
     if (!q.root)
         for (int t = tid; t < k * k; t += BG_T) {
@@ -158,7 +203,7 @@ __device__ void ulv_transform(const UlvDesc &q, double *smem) {
 // Phase 3: Cholesky of A_ee and its inverse; false (and the flag raised) on a
 // non-positive pivot.
 __device__ bool ulv_chol_inv(const UlvDesc &q, int32_t *flag, unsigned long long *clamped,
-                             unsigned long long *worst, double *red) {
+                             unsigned long long *worst, double *red, double *smem, double (*blk)[33]) {
     const double pivot_floor = q.pivot_floor;
     const int m = q.m, k = q.k, ne = m - k, tid = threadIdx.x;
     double *Dw = q.Dw;
@@ -181,58 +226,92 @@ __device__ bool ulv_chol_inv(const UlvDesc &q, int32_t *flag, unsigned long long
         beta2 = fmax(beta2, pivot_floor);
         __syncthreads();
     }
-    for (int j = 0; j < ne; ++j) {
-        double *Ajj = Dw + (int64_t)(k + j) * m + k + j;
-        double djj = *Ajj;
-        if (!(djj == djj) || isinf(djj)) {
-            bad = true;
-            break;
-        }
-        if (pivot_floor > 0.0 && !(djj >= pivot_floor)) {
-            double th = 0.0;
-            for (int i = j + 1 + tid; i < ne; i += BG_T) th = fmax(th, fabs(Dw[(int64_t)(k + i) * m + k + j]));
-            th = wave_max(th);
-            __syncthreads();
-            if ((tid & 63) == 0) red[tid >> 6] = th;
-            __syncthreads();
-            double theta = 0.0;
-            for (int i = 0; i < BG_T / 64; ++i) theta = fmax(theta, red[i]);
-            if (tid == 0) {
-                atomicAdd(clamped + q.prob, 1ull);
-                // largest deficit below the floor (non-negative, so its bits order like integers)
-                atomicMax(worst + q.prob, (unsigned long long)__double_as_longlong(pivot_floor - djj));
+    // blocked: panels of CH_NB columns factored column by column (each
+    // column updates the rest of its panel), then the trailing block gets
+    // A22 -= L21 L21^T as one product
+    for (int p0 = 0; p0 < ne && !bad; p0 += CH_NB) {
+        const int p1 = min(ne, p0 + CH_NB);
+        for (int j = p0; j < p1; ++j) {
+            double *Ajj = Dw + (int64_t)(k + j) * m + k + j;
+            double djj = *Ajj;
+            if (!(djj == djj) || isinf(djj)) {
+                bad = true;
+                break;
             }
-            djj = fmax(fmax(pivot_floor, fabs(djj)), theta * theta / beta2);
+            if (pivot_floor > 0.0 && !(djj >= pivot_floor)) {
+                double th = 0.0;
+                for (int i = j + 1 + tid; i < ne; i += BG_T) th = fmax(th, fabs(Dw[(int64_t)(k + i) * m + k + j]));
+                th = wave_max(th);
+                __syncthreads();
+                if ((tid & 63) == 0) red[tid >> 6] = th;
+                __syncthreads();
+                double theta = 0.0;
+                for (int i = 0; i < BG_T / 64; ++i) theta = fmax(theta, red[i]);
+                if (tid == 0) {
+                    atomicAdd(clamped + q.prob, 1ull);
+                    // largest deficit below the floor (non-negative, so its bits order like integers)
+                    atomicMax(worst + q.prob, (unsigned long long)__double_as_longlong(pivot_floor - djj));
+                }
+                djj = fmax(fmax(pivot_floor, fabs(djj)), theta * theta / beta2);
+            }
+            if (!(djj > 0.0)) {
+                bad = true;
+                break;
+            }
+            double ljj = sqrt(djj);
+            __syncthreads();
+            if (tid == 0) *Ajj = ljj;
+            for (int i = j + 1 + tid; i < ne; i += BG_T) Dw[(int64_t)(k + i) * m + k + j] /= ljj;
+            __syncthreads();
+            for (int i = j + 1 + tid; i < ne; i += BG_T) {
+                double lij = Dw[(int64_t)(k + i) * m + k + j];
+                double *rowi = Dw + (int64_t)(k + i) * m + k;
+                const int cend = min(i, p1 - 1);
+                for (int c = j + 1; c <= cend; ++c) rowi[c] -= lij * Dw[(int64_t)(k + c) * m + k + j];
+            }
+            __syncthreads();
         }
-        if (!(djj > 0.0)) {
-            bad = true;
-            break;
-        }
-        double ljj = sqrt(djj);
-        __syncthreads();
-        if (tid == 0) *Ajj = ljj;
-        for (int i = j + 1 + tid; i < ne; i += BG_T) Dw[(int64_t)(k + i) * m + k + j] /= ljj;
-        __syncthreads();
-        for (int i = j + 1 + tid; i < ne; i += BG_T) {
-            double lij = Dw[(int64_t)(k + i) * m + k + j];
-            double *rowi = Dw + (int64_t)(k + i) * m + k;
-            for (int c = j + 1; c <= i; ++c) rowi[c] -= lij * Dw[(int64_t)(k + c) * m + k + j];
-        }
-        __syncthreads();
+        if (!bad && p1 < ne)
+            block_gemm(ne - p1, ne - p1, p1 - p0, -1.0, Dw + (int64_t)(k + p1) * m + k + p0, m, 1,
+                       Dw + (int64_t)(k + p1) * m + k + p0, 1, m, 1.0, Dw + (int64_t)(k + p1) * m + k + p1, m, smem);
     }
     if (bad) {
         if (tid == 0) atomicOr(flag, 1);
         return false;
     }
-    // L^{-1} (lower triangular, zeros stored above the diagonal): column c by
-    // forward substitution on the unit vector e_c, one thread per column
-    for (int c = tid; c < ne; c += BG_T) {
-        for (int i = 0; i < c; ++i) q.L[(int64_t)i * ne + c] = 0.0;
-        for (int i = c; i < ne; ++i) {
-            const double *Li = Dw + (int64_t)(k + i) * m + k;
-            double t = (i == c) ? 1.0 : 0.0;
-            for (int l = c; l < i; ++l) t -= Li[l] * q.L[(int64_t)l * ne + c];
-            q.L[(int64_t)i * ne + c] = t / Li[i];
+    // L^{-1} (lower triangular, zeros stored above the diagonal) in blocks of
+    // CH_NB: the diagonal block X_II = L_II^{-1} by substitution in LDS, then
+    // X(I, 0:I) = -X_II (L(I, 0:I) X(0:I, 0:I)) as two products
+    for (int t = tid; t < ne * ne; t += BG_T) q.L[t] = 0.0;
+    __syncthreads();
+    for (int I0 = 0; I0 < ne; I0 += CH_NB) {
+        const int nb = min(CH_NB, ne - I0);
+        double(*lb)[33] = blk, (*xb)[33] = blk + 32;
+        for (int e = tid; e < nb * nb; e += BG_T) {
+            const int i = e / nb, c = e % nb;
+            lb[i][c] = Dw[(int64_t)(k + I0 + i) * m + k + I0 + c];
+            xb[i][c] = 0.0;
+        }
+        __syncthreads();
+        if (tid < nb) {
+            const int c = tid;
+            for (int i = c; i < nb; ++i) {
+                double t = (i == c) ? 1.0 : 0.0;
+                for (int l = c; l < i; ++l) t -= lb[i][l] * xb[l][c];
+                xb[i][c] = t / lb[i][i];
+            }
+        }
+        __syncthreads();
+        for (int e = tid; e < nb * nb; e += BG_T) {
+            const int i = e / nb, c = e % nb;
+            if (c <= i) q.L[(int64_t)(I0 + i) * ne + I0 + c] = xb[i][c];
+        }
+        __syncthreads();
+        if (I0 > 0) {
+            double *S = q.Sw;  // nb x I0
+            block_gemm(nb, I0, I0, 1.0, Dw + (int64_t)(k + I0) * m + k, m, 1, q.L, ne, 1, 0.0, S, I0, smem);
+            block_gemm(nb, I0, nb, -1.0, q.L + (int64_t)I0 * ne + I0, ne, 1, S, I0, 1, 0.0, q.L + (int64_t)I0 * ne, ne,
+                       smem);
         }
     }
     __syncthreads();
@@ -260,10 +339,11 @@ __global__ __launch_bounds__(BG_T) void k_ulv_factor(const UlvDesc *dsc, int32_t
                                                      unsigned long long *worst) {
     __shared__ double smem[2 * 16 * 65];
     __shared__ double red[BG_T / 64];
+    __shared__ double blk[64][33];
     const UlvDesc q = dsc[blockIdx.x];
-    ulv_assemble_qr(q, smem, red);
+    ulv_assemble_qr(q, smem, red, blk);
     ulv_transform(q, smem);
-    if (!ulv_chol_inv(q, flag, clamped, worst, red)) return;
+    if (!ulv_chol_inv(q, flag, clamped, worst, red, smem, blk)) return;
     if (q.root) return;
     for (int j = 0; j < 2; ++j) {
         const GemmJob J = ulv_schur_job(q, j);
@@ -278,15 +358,18 @@ __global__ __launch_bounds__(BG_T) void k_ulv_factor(const UlvDesc *dsc, int32_t
 __global__ __launch_bounds__(BG_T) void k_ulv_phase1(const UlvDesc *dsc) {
     __shared__ double smem[2 * 16 * 65];
     __shared__ double red[BG_T / 64];
+    __shared__ double blk[64][33];
     const UlvDesc q = dsc[blockIdx.x];
-    ulv_assemble_qr(q, smem, red);
+    ulv_assemble_qr(q, smem, red, blk);
 }
 
 __global__ __launch_bounds__(BG_T) void k_ulv_phase3(const UlvDesc *dsc, int32_t *flag, unsigned long long *clamped,
                                                      unsigned long long *worst) {
+    __shared__ double smem[2 * 16 * 65];
     __shared__ double red[BG_T / 64];
+    __shared__ double blk[64][33];
     const UlvDesc q = dsc[blockIdx.x];
-    ulv_chol_inv(q, flag, clamped, worst, red);
+    ulv_chol_inv(q, flag, clamped, worst, red, smem, blk);
 }
 
 __global__ __launch_bounds__(BG_T) void k_ulv_schur_out(const UlvDesc *dsc) {
@@ -494,19 +577,20 @@ int64_t ulv_factor(const hss_s *H, const std::vector<double> &lam, const std::ve
             if (act[H->nprob[id]]) lv.push_back(id);
         if (lv.empty()) continue;
         const int cnt = (int)lv.size();
-        int64_t dsz = 0, usz = 0, tsz = 0, ysz = 0;
+        int64_t dsz = 0, usz = 0, tsz = 0, ysz = 0, ssz = 0;
         for (int id : lv) {
             dsz += (int64_t)m[id] * m[id];
             usz += (int64_t)m[id] * k[id];
             const HNode &q = H->node[id];
             if (q.left >= 0) tsz += (int64_t)k[q.left] * k[q.right];
             ysz += (int64_t)std::max(m[id], k[id]) * k[id];
+            ssz += (int64_t)CH_NB * m[id];
         }
         DBuf Dw = dalloc<double>(std::max<int64_t>(dsz, 1)), Uw = dalloc<double>(std::max<int64_t>(usz, 1)),
              Tm = dalloc<double>(std::max<int64_t>(tsz, 1)), Yb = dalloc<double>(std::max<int64_t>(ysz, 1)),
-             Zb = dalloc<double>(std::max<int64_t>(ysz, 1));
+             Zb = dalloc<double>(std::max<int64_t>(ysz, 1)), Sb2 = dalloc<double>(std::max<int64_t>(ssz, 1));
         std::vector<UlvDesc> dsc(cnt);
-        int64_t od = 0, ou = 0, ot = 0, oy = 0;
+        int64_t od = 0, ou = 0, ot = 0, oy = 0, os = 0;
         for (int a = 0; a < cnt; ++a) {
             const int id = lv[a];
             const HNode &q = H->node[id];
@@ -537,6 +621,8 @@ int64_t ulv_factor(const hss_s *H, const std::vector<double> &lam, const std::ve
             u.Uw = Uw.as<double>() + ou;
             u.Yw = Yb.as<double>() + oy;
             u.Zw = Zb.as<double>() + oy;
+            u.Sw = Sb2.as<double>() + os;
+            os += (int64_t)CH_NB * u.m;
             u.Tw = F->Y.as<double>() + F->offY[id];
             od += (int64_t)u.m * u.m;
             ou += (int64_t)u.m * u.k;
