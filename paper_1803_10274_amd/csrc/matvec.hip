@@ -718,7 +718,8 @@ __global__ __launch_bounds__(64 * SM_WAVES) void k_kmv_symf(const float *__restr
 // is zero and holds no registers): KT = 32 ceil((6 d + 6) / 32) slots,
 // KT / 32 v_mfma_f32_16x16x32_bf16 per 16 x 16 tile instead of d / 4
 // FP32 ones at a sixteenth of the rate.  Products of BF16 terms are exact in
-// FP32, so the exponent carries the FP32 form's accuracy.
+// FP32, so the exponent carries the FP32 form's accuracy.  QM: the entry is
+// exp2(t) t (as in k_kmv_sc), for the fused backward's dh on K(X, X).
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ void split3(float v, __bf16 &h, __bf16 &m, __bf16 &l) {
@@ -734,7 +735,7 @@ constexpr int symb_kt(int d) { return (6 * d + 6 + 31) / 32 * 32; }
 constexpr int symb_rows(int d) { return 16 * SM_WAVES * symb_rt(symb_kt(d)); }
 constexpr int symb_max_d = 31;  // KT <= 192
 
-template <int KT, int RT>
+template <int KT, int RT, bool QM>
 __global__ __launch_bounds__(64 * SM_WAVES) void k_kmv_symb(const float *__restrict__ X, int d,
                                                             const float *__restrict__ anchors,
                                                             const float *__restrict__ wf, int64_t n,
@@ -846,7 +847,8 @@ __global__ __launch_bounds__(64 * SM_WAVES) void k_kmv_symb(const float *__restr
                 for (int s = 0; s < KS; ++s) t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[s], xb[rt][s], t, 0, 0, 0);
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const float e = __builtin_amdgcn_exp2f(t[q]);
+                    float e = __builtin_amdgcn_exp2f(t[q]);
+                    if (QM) e = e == 0.0f ? 0.0f : e * t[q];  // -1e30 past the item: entry 0
                     pacc[rt] = fmaf(e, wp[q], pacc[rt]);
                     cacc[q] = fmaf(e, wi[rt], cacc[q]);
                 }
@@ -1167,18 +1169,18 @@ void launch_symf(dim3 gd, dim3 gs, dim3 gr, int rows_pb, const float *X, int d, 
 }
 
 // BF16 three-term exponents: K slots for d and the kernel's row tiles.
-template <int KT, int RT>
+template <int KT, int RT, bool QM>
 void launch_symb_kernel(dim3 gs, const float *X, int d, const float *anchors, const float *wf, int64_t n,
                         const SymItem *it, double *rowpart, float *colpart, hipStream_t s) {
-    k_kmv_symb<KT, RT><<<gs, 64 * SM_WAVES, 0, s>>>(X, d, anchors, wf, n, it, rowpart, colpart);
+    k_kmv_symb<KT, RT, QM><<<gs, 64 * SM_WAVES, 0, s>>>(X, d, anchors, wf, n, it, rowpart, colpart);
 }
 
-template <int D>
+template <int D, bool QM>
 void launch_symb(dim3 gd, dim3 gs, dim3 gr, int rows_pb, const float *X, int d, double c2, const double *ya,
                  const float *wf, int64_t n, const SampBlock *dt, const SymItem *it, const SymBlock *bl,
                  int64_t nblocks, double *diag, double *rowpart, float *colpart, double beta, double *Out,
                  hipStream_t s) {
-    k_kmv_sc<float, D, 1, sc_rpt(D)><<<gd, MV_ROWS, 0, s>>>(X, n, d, c2, ya, wf, 1, 0, n, 0, diag, dt);
+    k_kmv_sc<float, D, 1, sc_rpt(D), QM><<<gd, MV_ROWS, 0, s>>>(X, n, d, c2, ya, wf, 1, 0, n, 0, diag, dt);
     check_launch("k_kmv_sc (diagonal blocks)");
     if (gs.x > 0) {
         DBuf anchors = dalloc<float>((size_t)nblocks * d);
@@ -1187,12 +1189,12 @@ void launch_symb(dim3 gd, dim3 gs, dim3 gr, int rows_pb, const float *X, int d, 
         const int kt = (6 * d + 6 + 31) / 32 * 32;
         const float *an = anchors.as<float>();
         switch (kt) {  // row tiles per wave: symb_rt
-            case 32: launch_symb_kernel<32, symb_rt(32)>(gs, X, d, an, wf, n, it, rowpart, colpart, s); break;
-            case 64: launch_symb_kernel<64, symb_rt(64)>(gs, X, d, an, wf, n, it, rowpart, colpart, s); break;
-            case 96: launch_symb_kernel<96, symb_rt(96)>(gs, X, d, an, wf, n, it, rowpart, colpart, s); break;
-            case 128: launch_symb_kernel<128, symb_rt(128)>(gs, X, d, an, wf, n, it, rowpart, colpart, s); break;
-            case 160: launch_symb_kernel<160, symb_rt(160)>(gs, X, d, an, wf, n, it, rowpart, colpart, s); break;
-            case 192: launch_symb_kernel<192, symb_rt(192)>(gs, X, d, an, wf, n, it, rowpart, colpart, s); break;
+            case 32: launch_symb_kernel<32, symb_rt(32), QM>(gs, X, d, an, wf, n, it, rowpart, colpart, s); break;
+            case 64: launch_symb_kernel<64, symb_rt(64), QM>(gs, X, d, an, wf, n, it, rowpart, colpart, s); break;
+            case 96: launch_symb_kernel<96, symb_rt(96), QM>(gs, X, d, an, wf, n, it, rowpart, colpart, s); break;
+            case 128: launch_symb_kernel<128, symb_rt(128), QM>(gs, X, d, an, wf, n, it, rowpart, colpart, s); break;
+            case 160: launch_symb_kernel<160, symb_rt(160), QM>(gs, X, d, an, wf, n, it, rowpart, colpart, s); break;
+            case 192: launch_symb_kernel<192, symb_rt(192), QM>(gs, X, d, an, wf, n, it, rowpart, colpart, s); break;
             default: fail(KRR_E_INVAL, "kernel_matvec: no BF16 symmetric variant for width %d", d);
         }
         check_launch("k_kmv_symb");
@@ -1206,16 +1208,17 @@ void launch_symb(dim3 gd, dim3 gs, dim3 gr, int rows_pb, const float *X, int d, 
 // applies (d <= 32, one or two right-hand sides, partial sums within budget);
 // returns false otherwise.  FP32 points with one right-hand side take the
 // matrix-core exponents (k_kmv_symm) unless the vector form is selected;
-// the rest the vector form.
+// the rest the vector form.  qm: the entry exp2(t) t, on the BF16 form only.
 template <class T>
 bool kmv_sym(const T *X, int64_t n, int d, double h, const double *W, int nrhs, double beta, double *Out,
-             hipStream_t s, const Batch *batch) {
+             hipStream_t s, const Batch *batch, bool qm = false) {
     const int D = sc_width(d);
     if (D > 32 || (nrhs != 1 && nrhs != 2)) return false;
     const bool mc = sizeof(T) == 4 && nrhs == 1 && tune_get(KRR_TUNE_SYMMETRIC) == 1;
     const int form = tune_get(KRR_TUNE_SYMMETRIC);
     const bool mb = sizeof(T) == 4 && nrhs == 1 && form == 4 && d <= symb_max_d;
     const bool mf = sizeof(T) == 4 && nrhs == 1 && (form == 3 || (form == 4 && d > symb_max_d));
+    if (qm && !mb) return false;
     const int diag_rows = MV_ROWS * sc_rpt(D);  // rows of one k_kmv_sc workgroup
     const int rows_pb = mb ? symb_rows(d) : ((mc || mf) ? symm_rows(D) : diag_rows);
     const int64_t CH = tune_get(KRR_TUNE_SYM_CHUNK);  // columns per item: a multiple of the tile width
@@ -1284,9 +1287,10 @@ bool kmv_sym(const T *X, int64_t n, int d, double h, const double *W, int nrhs, 
             break;                                                                                              \
         }                                                                                                       \
         if (mb) {                                                                                               \
-            launch_symb<DD>(gd, gs, gr, rows_pb, X, d, c2, ya.as<double>(), wf.as<float>(), n,                 \
-                            dt.as<SampBlock>(), it.as<SymItem>(), bl.as<SymBlock>(), (int64_t)blocks.size(),    \
-                            dd.as<double>(), rp.as<double>(), cpart.as<float>(), beta, Out, s);                 \
+            (qm ? launch_symb<DD, true> : launch_symb<DD, false>)(                                              \
+                gd, gs, gr, rows_pb, X, d, c2, ya.as<double>(), wf.as<float>(), n, dt.as<SampBlock>(),          \
+                it.as<SymItem>(), bl.as<SymBlock>(), (int64_t)blocks.size(), dd.as<double>(), rp.as<double>(),  \
+                cpart.as<float>(), beta, Out, s);                                                               \
             break;                                                                                              \
         }                                                                                                       \
         if (mf) {                                                                                               \
@@ -1584,6 +1588,11 @@ void kernel_matvec_ws(const void *X, int64_t m, const void *Y, int64_t n, int d,
 void kernel_matvec_q(const void *X, int64_t m, const void *Y, int64_t n, int d, int xprec, double h,
                      const double *W, double *Out, hipStream_t s) {
     KRR_REQUIRE(d <= 64, "kernel_matvec_q: d = %d > 64", d);
+    // K(X, X) with FP32 points: the symmetric matrix-core form, each
+    // off-diagonal entry once
+    if (X == Y && m == n && xprec == KRR_F32 && tune_get(KRR_TUNE_SYMMETRIC) &&
+        kmv_sym<float>(static_cast<const float *>(X), n, d, h, W, 1, 0.0, Out, s, nullptr, true))
+        return;
     const KmvPlan P = kmv_plan(m, n, d, 1, true);
     DBuf part = dalloc<double>(P.part_elems), ya = dalloc<double>(P.ya_elems), wf = dalloc<float>(P.wf_elems);
     if (xprec == KRR_F64)

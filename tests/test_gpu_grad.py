@@ -38,11 +38,14 @@ def test_kernel_matvec_autograd(gpu_lib):
     assert abs(ht.grad.item() - dh) <= 1e-10 * abs(dh)
 
 
-@pytest.mark.parametrize("m,n,d,same", [(3001, 2500, 18, False), (1000, 1000, 8, True), (777, 4099, 40, False)])
+@pytest.mark.parametrize("m,n,d,same", [(3001, 2500, 18, False), (1000, 1000, 8, True), (3000, 3000, 18, True),
+                                         (777, 4099, 40, False)])
 def test_fused_backward_dh_fp32(gpu_lib, m, n, d, same):
-    # dh alone with FP32 entries runs as the product with the entry exp2(t) t
-    # (split-K kernel, FP64 exponents rounded to FP32, FP32 tile sums of 64
-    # columns, FP64 across tiles): within 1e-5 of sum_ab |P_ab| q_ab / h^3
+    # dh alone with FP32 entries runs as the product with the entry exp2(t) t:
+    # for X != Y the split-K kernel (FP64 exponents rounded to FP32), for
+    # X = Y the symmetric form (BF16 three-term exponents on the matrix cores,
+    # each off-diagonal entry once; 2 and 12 row blocks here); FP32 tile
+    # sums, FP64 across tiles: within 1e-5 of sum_ab |P_ab| q_ab / h^3
     Y = sd.points(n, d, seed=41 + d, scale=0.4)
     X = Y if same else sd.points(m, d, seed=42 + d, scale=0.4)
     W = sd.vectors(n, 1, seed=43)
@@ -53,7 +56,7 @@ def test_fused_backward_dh_fp32(gpu_lib, m, n, d, same):
     got = gpu_lib.kernel_matvec_bwd(Xt, Yt, h, _t(W), _t(G), prec="f32", want=("dh",))["dh"].item()
     _, _, _, dh = og.matvec_bwd(X.astype(np.float64), Y.astype(np.float64), W, G, h)
     Xd, Yd = X.astype(np.float64), Y.astype(np.float64)
-    Q = ((Xd[:, None, :] - Yd[None, :, :]) ** 2).sum(axis=2)
+    Q = np.maximum((Xd * Xd).sum(1)[:, None] + (Yd * Yd).sum(1)[None, :] - 2.0 * Xd @ Yd.T, 0.0)
     mag = float((np.abs(G) * (np.exp(-Q / (2 * h * h)) * Q) @ np.abs(W)).sum() / h**3)
     assert abs(got - dh) <= 1e-5 * mag, (got, dh, mag)
 
