@@ -514,7 +514,8 @@ enum {
                                 ALUs; 0 off */
     KRR_TUNE_SAMPLE_RB = 1,  /* max 32-column blocks per sampling pass: 1, 2, 4 or 8 (default 8) */
     KRR_TUNE_MV_BLOCKS = 2,  /* workgroups the split-K kernel product aims for, 64..65536 (default 2048) */
-    KRR_TUNE_SYM_CHUNK = 3,  /* columns per item of the symmetric product, multiple of 64 (default 16384) */
+    KRR_TUNE_SYM_CHUNK = 3,  /* columns per item of the symmetric product, multiple of 64 (default 16384;
+                                halved for products too small to fill the chip) */
     KRR_TUNE_SAMPLE_SKIP = 4, /* 1: the matrix-core sampler skips 32 x 32 tiles whose entries are all below
                                  2^-32 (default); 0: every tile is evaluated */
     KRR_TUNE_COUNT = 5

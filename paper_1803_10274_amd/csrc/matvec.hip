@@ -719,7 +719,9 @@ __global__ __launch_bounds__(64 * SM_WAVES) void k_kmv_symf(const float *__restr
 // KT / 32 v_mfma_f32_16x16x32_bf16 per 16 x 16 tile instead of d / 4
 // FP32 ones at a sixteenth of the rate.  Products of BF16 terms are exact in
 // FP32, so the exponent carries the FP32 form's accuracy.  QM: the entry is
-// exp2(t) t (as in k_kmv_sc), for the fused backward's dh on K(X, X).
+// exp2(t) t (as in k_kmv_sc), for the fused backward's dh.  SYM false: the
+// rows are X's and the columns Y's (no column sums; the row partials of item
+// chunk c at rowpart[c * n + i], n being then the number of rows).
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ void split3(float v, __bf16 &h, __bf16 &m, __bf16 &l) {
@@ -735,8 +737,9 @@ constexpr int symb_kt(int d) { return (6 * d + 6 + 31) / 32 * 32; }
 constexpr int symb_rows(int d) { return 16 * SM_WAVES * symb_rt(symb_kt(d)); }
 constexpr int symb_max_d = 31;  // KT <= 192
 
-template <int KT, int RT, bool QM>
-__global__ __launch_bounds__(64 * SM_WAVES) void k_kmv_symb(const float *__restrict__ X, int d,
+template <int KT, int RT, bool QM, bool SYM>
+__global__ __launch_bounds__(64 * SM_WAVES) void k_kmv_symb(const float *__restrict__ X,
+                                                            const float *__restrict__ Ycols, int d,
                                                             const float *__restrict__ anchors,
                                                             const float *__restrict__ wf, int64_t n,
                                                             const SymItem *__restrict__ items,
@@ -754,44 +757,49 @@ __global__ __launch_bounds__(64 * SM_WAVES) void k_kmv_symb(const float *__restr
     const float c = (float)it.c2;
     if (tid < 32) anc[tid] = tid < d ? anchors[it.blk * d + tid] : 0.0f;
     __syncthreads();
+    // The packed row vectors, one row tile of every wave per round: a thread
+    // packs one row into the panel buffer (B side of hh, hm, mh, hl, lh, mm:
+    // terms hi, mid, hi, lo, hi, mid; ones against the column constant's
+    // three terms; the row constant's three terms; zero padding), then each
+    // lane loads its K slots 32 s + 8 g .. + 7.  Rows past the item are zero.
     bf8v xb[RT][KS];
     float wi[RT];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
-        const int64_t i = it.i0 + (int64_t)(wv * RT + rt) * 16 + lr;
-        const bool ok = i < it.iend;
-        float nrm = 0.0f;
-        if (ok)
+        if (tid < 16 * SM_WAVES) {
+            const int64_t i = it.i0 + (int64_t)((tid >> 4) * RT + rt) * 16 + (tid & 15);
+            const bool ok = i < it.iend;
+            __bf16 *dst = ys + tid * LDB;
+            float nrm = 0.0f;
             for (int k = 0; k < d; ++k) {
-                const float v = X[i * d + k] - anc[k];
+                const float v = ok ? X[i * d + k] - anc[k] : 0.0f;
                 nrm = fmaf(v, v, nrm);
-            }
-        // this lane's K slots 32 s + 8 g + e of the packed row vector
-#pragma unroll
-        for (int s = 0; s < KS; ++s)
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int slot = 32 * s + 8 * g + e;
-                float v = 0.0f;
-                int part = 0;  // 0: hi, 1: mid, 2: lo
-                if (ok) {
-                    if (slot < 6 * d) {
-                        const int t = slot / d, k = slot % d;
-                        // B side of (hh, hm, mh, hl, lh, mm)
-                        part = (t == 1 || t == 5) ? 1 : (t == 3 ? 2 : 0);
-                        v = X[i * d + k] - anc[k];
-                    } else if (slot < 6 * d + 3) {
-                        v = 1.0f;
-                    } else if (slot < 6 * d + 6) {
-                        part = slot - (6 * d + 3);
-                        v = -c * nrm;
-                    }
-                }
                 __bf16 h, m, l;
                 split3(v, h, m, l);
-                xb[rt][s][e] = part == 0 ? h : (part == 1 ? m : l);
+                dst[k] = h;
+                dst[d + k] = m;
+                dst[2 * d + k] = h;
+                dst[3 * d + k] = l;
+                dst[4 * d + k] = h;
+                dst[5 * d + k] = m;
             }
-        wi[rt] = ok ? wf[i] : 0.0f;
+            const __bf16 one = (__bf16)(ok ? 1.0f : 0.0f);
+            dst[6 * d] = one;
+            dst[6 * d + 1] = one;
+            dst[6 * d + 2] = one;
+            __bf16 h, m, l;
+            split3(ok ? -c * nrm : 0.0f, h, m, l);
+            dst[6 * d + 3] = h;
+            dst[6 * d + 4] = m;
+            dst[6 * d + 5] = l;
+            for (int k = 6 * d + 6; k < KT; ++k) dst[k] = (__bf16)0.0f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < KS; ++s) xb[rt][s] = *reinterpret_cast<const bf8v *>(ys + (wv * 16 + lr) * LDB + 32 * s + 8 * g);
+        const int64_t i = it.i0 + (int64_t)(wv * RT + rt) * 16 + lr;
+        wi[rt] = (SYM && i < it.iend) ? wf[i] : 0.0f;  // row weights: the column sums only
+        __syncthreads();
     }
     double acc[RT];
 #pragma unroll
@@ -804,7 +812,7 @@ __global__ __launch_bounds__(64 * SM_WAVES) void k_kmv_symb(const float *__restr
             __bf16 *dst = ys + tid * LDB;
             float nrm = 0.0f;
             const bool ok = tid < cnt;
-            const float *y = X + (ok ? p0 + tid : 0) * d;
+            const float *y = (SYM ? X : Ycols) + (ok ? p0 + tid : 0) * d;
             for (int k = 0; k < d; ++k) {
                 const float v = ok ? y[k] - anc[k] : 0.0f;
                 nrm = fmaf(v, v, nrm);
@@ -850,9 +858,10 @@ __global__ __launch_bounds__(64 * SM_WAVES) void k_kmv_symb(const float *__restr
                     float e = __builtin_amdgcn_exp2f(t[q]);
                     if (QM) e = e == 0.0f ? 0.0f : e * t[q];  // -1e30 past the item: entry 0
                     pacc[rt] = fmaf(e, wp[q], pacc[rt]);
-                    cacc[q] = fmaf(e, wi[rt], cacc[q]);
+                    if (SYM) cacc[q] = fmaf(e, wi[rt], cacc[q]);
                 }
             }
+            if (!SYM) continue;
 #pragma unroll
             for (int o = 8, h = 2; o >= 4; o >>= 1, h >>= 1) {
                 const bool up = (lane & o) != 0;
@@ -871,7 +880,7 @@ __global__ __launch_bounds__(64 * SM_WAVES) void k_kmv_symb(const float *__restr
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) acc[rt] += (double)pacc[rt];
         __syncthreads();
-        if (tid < cnt) {
+        if (SYM && tid < cnt) {
             float cs = csum[0][tid];
 #pragma unroll
             for (int w = 1; w < SM_WAVES; ++w) cs += csum[w][tid];
@@ -1172,7 +1181,7 @@ void launch_symf(dim3 gd, dim3 gs, dim3 gr, int rows_pb, const float *X, int d, 
 template <int KT, int RT, bool QM>
 void launch_symb_kernel(dim3 gs, const float *X, int d, const float *anchors, const float *wf, int64_t n,
                         const SymItem *it, double *rowpart, float *colpart, hipStream_t s) {
-    k_kmv_symb<KT, RT, QM><<<gs, 64 * SM_WAVES, 0, s>>>(X, d, anchors, wf, n, it, rowpart, colpart);
+    k_kmv_symb<KT, RT, QM, true><<<gs, 64 * SM_WAVES, 0, s>>>(X, X, d, anchors, wf, n, it, rowpart, colpart);
 }
 
 template <int D, bool QM>
@@ -1221,10 +1230,16 @@ bool kmv_sym(const T *X, int64_t n, int d, double h, const double *W, int nrhs, 
     if (qm && !mb) return false;
     const int diag_rows = MV_ROWS * sc_rpt(D);  // rows of one k_kmv_sc workgroup
     const int rows_pb = mb ? symb_rows(d) : ((mc || mf) ? symm_rows(D) : diag_rows);
-    const int64_t CH = tune_get(KRR_TUNE_SYM_CHUNK);  // columns per item: a multiple of the tile width
     std::vector<int64_t> pb = batch ? batch->pbeg : std::vector<int64_t>{0, n};
     std::vector<double> hs = batch ? batch->h : std::vector<double>{h};
     const int np = (int)hs.size();
+    // columns per item: a multiple of the tile width, halved (while it is a
+    // multiple of 2048) as long as the grid would hold fewer than ~4096
+    // items (sum of n_p^2 / (2 rows_pb CH)), so small products fill the chip
+    int64_t CH = tune_get(KRR_TUNE_SYM_CHUNK);
+    double sq = 0.0;
+    for (int p = 0; p < np; ++p) sq += (double)(pb[p + 1] - pb[p]) * (double)(pb[p + 1] - pb[p]);
+    while (CH % 2048 == 0 && sq / (2.0 * rows_pb * CH) < 4096.0) CH /= 2;
     std::vector<SymBlock> blocks;
     std::vector<SymItem> items;
     std::vector<SampBlock> diag;
@@ -1321,6 +1336,73 @@ bool kmv_sym(const T *X, int64_t n, int d, double h, const double *W, int nrhs, 
         default: fail(KRR_E_INVAL, "kernel_matvec: no symmetric variant for width %d", D);
     }
 #undef KRR_SYM
+    sync(s);  // temporaries are released on return
+    return true;
+}
+
+// K(X, Y) w with the entry exp2(t) t for FP32 points of width d <= 31 (the
+// fused backward's dh when X != Y): the BF16 matrix-core exponents of
+// k_kmv_symb without column sums.  Items are (row block of X, chunk of Y's
+// columns), the chunk sized so that the grid holds about 2048 workgroups;
+// the chunks' FP64 row partials are summed in a fixed order.
+bool kmv_q_rect(const float *X, int64_t m, const float *Y, int64_t n, int d, double h, const double *W, double *Out,
+                hipStream_t s) {
+    if (d > symb_max_d || tune_get(KRR_TUNE_SYMMETRIC) != 4 || m <= 0 || n <= 0) return false;
+    const int kt = symb_kt(d), rows_pb = symb_rows(d);
+    const int64_t pn = symb_pn(kt), nblocks = (m + rows_pb - 1) / rows_pb;
+    const int64_t want = std::max<int64_t>(1, (2048 + nblocks - 1) / nblocks);
+    int64_t ch = (n + want - 1) / want;
+    ch = std::max<int64_t>(pn, (ch + pn - 1) / pn * pn);
+    const int64_t nch = (n + ch - 1) / ch;
+    const double c2 = kernel_scale_log2(h);
+    std::vector<SymBlock> blocks;
+    std::vector<SymItem> items;
+    for (int64_t b = 0; b < nblocks; ++b) {
+        SymBlock sb{};
+        sb.i0 = b * rows_pb;
+        sb.iend = std::min<int64_t>(m, sb.i0 + rows_pb);
+        blocks.push_back(sb);
+        for (int64_t c = 0; c < nch; ++c) {
+            SymItem it{};
+            it.i0 = sb.i0;
+            it.iend = sb.iend;
+            it.j0 = c * ch;
+            it.j1 = std::min<int64_t>(n, (c + 1) * ch);
+            it.blk = b;
+            it.chunk = c;
+            it.c2 = c2;
+            items.push_back(it);
+        }
+    }
+    DBuf wf = dalloc<float>((size_t)n), rp = dalloc<double>((size_t)(nch * m)), an = dalloc<float>((size_t)(nblocks * d));
+    DBuf bl = upload(blocks, s), it = upload(items, s);
+    sync(s);  // the host tables are released on return
+    k_w_to_float<<<ceil_div(n, 256), 256, 0, s>>>(W, n, wf.as<float>());
+    check_launch("k_w_to_float");
+    k_block_mean<<<(unsigned)nblocks, 256, 0, s>>>(X, d, bl.as<SymBlock>(), an.as<float>());
+    check_launch("k_block_mean");
+    const dim3 gs((unsigned)items.size());
+    const float *a = an.as<float>(), *w = wf.as<float>();
+    const SymItem *ip = it.as<SymItem>();
+    double *r = rp.as<double>();
+#define KRR_QR(KT)                                                                                      \
+    case KT:                                                                                            \
+        k_kmv_symb<KT, symb_rt(KT), true, false><<<gs, 64 * SM_WAVES, 0, s>>>(X, Y, d, a, w, m, ip, r, \
+                                                                               nullptr);                \
+        break;
+    switch (kt) {
+        KRR_QR(32)
+        KRR_QR(64)
+        KRR_QR(96)
+        KRR_QR(128)
+        KRR_QR(160)
+        KRR_QR(192)
+        default: fail(KRR_E_INVAL, "kernel_matvec_q: no BF16 variant for width %d", d);
+    }
+#undef KRR_QR
+    check_launch("k_kmv_symb (rectangular)");
+    k_reduce_splits<<<ceil_div(m, 256), 256, 0, s>>>(r, (int)nch, m, 0.0, Out);
+    check_launch("k_reduce_splits");
     sync(s);  // temporaries are released on return
     return true;
 }
@@ -1592,6 +1674,10 @@ void kernel_matvec_q(const void *X, int64_t m, const void *Y, int64_t n, int d, 
     // off-diagonal entry once
     if (X == Y && m == n && xprec == KRR_F32 && tune_get(KRR_TUNE_SYMMETRIC) &&
         kmv_sym<float>(static_cast<const float *>(X), n, d, h, W, 1, 0.0, Out, s, nullptr, true))
+        return;
+    // other FP32 operands: the same exponents without column sums
+    if (xprec == KRR_F32 &&
+        kmv_q_rect(static_cast<const float *>(X), m, static_cast<const float *>(Y), n, d, h, W, Out, s))
         return;
     const KmvPlan P = kmv_plan(m, n, d, 1, true);
     DBuf part = dalloc<double>(P.part_elems), ya = dalloc<double>(P.ya_elems), wf = dalloc<float>(P.wf_elems);

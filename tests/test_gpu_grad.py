@@ -41,11 +41,12 @@ def test_kernel_matvec_autograd(gpu_lib):
 @pytest.mark.parametrize("m,n,d,same", [(3001, 2500, 18, False), (1000, 1000, 8, True), (3000, 3000, 18, True),
                                          (777, 4099, 40, False)])
 def test_fused_backward_dh_fp32(gpu_lib, m, n, d, same):
-    # dh alone with FP32 entries runs as the product with the entry exp2(t) t:
-    # for X != Y the split-K kernel (FP64 exponents rounded to FP32), for
-    # X = Y the symmetric form (BF16 three-term exponents on the matrix cores,
-    # each off-diagonal entry once; 2 and 12 row blocks here); FP32 tile
-    # sums, FP64 across tiles: within 1e-5 of sum_ab |P_ab| q_ab / h^3
+    # dh alone with FP32 entries runs as the product with the entry exp2(t) t.
+    # d <= 31: BF16 three-term exponents on the matrix cores, for X = Y in the
+    # symmetric form (each off-diagonal entry once; 2 and 12 row blocks here),
+    # otherwise in the rectangular form (6 row blocks x column chunks); d = 40:
+    # the split-K kernel with FP64 exponents rounded to FP32.  FP32 tile sums,
+    # FP64 across tiles: within 1e-5 of sum_ab |P_ab| q_ab / h^3
     Y = sd.points(n, d, seed=41 + d, scale=0.4)
     X = Y if same else sd.points(m, d, seed=42 + d, scale=0.4)
     W = sd.vectors(n, 1, seed=43)
