@@ -43,14 +43,14 @@ PEAK_EXP2 = 256 * 64 * 2.4e9 / 4
 # WRITE_SIZE 1,048,576 KiB -> x1.000).  Valid only while the kernel's source
 # file is unchanged (sha256 below); otherwise the bench reports null.
 PMC_TRAFFIC = {
-    "sampling": {"fetch_kib": 35674272.875, "write_kib": 1048576.0, "fetch_scale": 2.0, "write_scale": 1.0,
+    "sampling": {"fetch_kib": 931370229.9375, "write_kib": 1048576.0, "fetch_scale": 2.0, "write_scale": 1.0,
                  "source": "paper_1803_10274_amd/csrc/sample_mfma.hip",
-                 "sha256": "6c180a43baaae35f60eb9bb6b5ad08497c499da1cb23daf03cbb18c3dd0b128d", "n": 1 << 20, "r": 256},
+                 "sha256": "bcd0d5396bd1701e27d4c92645b02fded9aa6e4ae6559e2bc90a8edeb4e761b3", "n": 1 << 20, "r": 256},
     # the symmetric product's six launches: column data, FP32 weights,
     # diagonal blocks, row-block anchors, upper triangle, reduction
-    "kernel_product": {"fetch_kib": 10256450.3125, "write_kib": 6406804.6875, "fetch_scale": 2.0, "write_scale": 1.0,
+    "kernel_product": {"fetch_kib": 8328471.3125, "write_kib": 2822946.625, "fetch_scale": 2.0, "write_scale": 1.0,
                        "source": "paper_1803_10274_amd/csrc/matvec.hip",
-                       "sha256": "3923b472b66660dfeabcc35a5767f03f8a086ddc8bef3bbc67ab474ab920e2ea",
+                       "sha256": "a656c5da9c339bf3f3f2258207c567a4904a6fad7acb152b1d7b16b382242df8",
                        "n": 1 << 20, "r": None},
 }
 
@@ -72,7 +72,23 @@ def pmc_traffic(kind, n, r=None):
 # 512; SQ_VALU_MFMA_BUSY_CYCLES and GRBM_GUI_ACTIVE give the busy share), from
 # `rocprofv3 --pmc` runs of `bench.py --kernels-only`; valid only while the
 # kernel's source file is unchanged (sha256), otherwise reported as null.
-PMC_MFMA = {}
+PMC_MFMA = {
+    "sampling": {"mops": {"f16": 659243755520.0, "bf16": 274886295552.0}, "mfma_busy_frac": 0.348,
+                 "valu_busy_frac": 0.2221, "coexec_frac": 0.0447,
+                 "source": "paper_1803_10274_amd/csrc/sample_mfma.hip",
+                 "sha256": "bcd0d5396bd1701e27d4c92645b02fded9aa6e4ae6559e2bc90a8edeb4e761b3", "n": 1 << 20, "r": 256,
+                 "profile": "profiles/k_sample_mfma_sixteen_gaussians_n1048576_r256.md"},
+    "sampling_every_tile": {"mops": {"f16": 2199023255552.0, "bf16": 274886295552.0}, "mfma_busy_frac": 0.5944,
+                            "valu_busy_frac": 0.3311, "coexec_frac": 0.0864,
+                            "source": "paper_1803_10274_amd/csrc/sample_mfma.hip",
+                            "sha256": "bcd0d5396bd1701e27d4c92645b02fded9aa6e4ae6559e2bc90a8edeb4e761b3",
+                            "n": 1 << 20, "r": 256,
+                            "profile": "profiles/k_sample_mfma_sixteen_gaussians_n1048576_r256.md"},
+    "kernel_product": {"mops": {"bf16": 137304735744.0}, "mfma_busy_frac": 0.2445, "valu_busy_frac": 0.63,
+                       "coexec_frac": 0.0756, "source": "paper_1803_10274_amd/csrc/matvec.hip",
+                       "sha256": "a656c5da9c339bf3f3f2258207c567a4904a6fad7acb152b1d7b16b382242df8",
+                       "n": 1 << 20, "r": None, "profile": "profiles/k_kmv_symb_sixteen_gaussians_n1048576.md"},
+}
 
 
 def pmc_mfma(kind, n, r, launch_s):
@@ -89,7 +105,7 @@ def pmc_mfma(kind, n, r, launch_s):
     peak = sum(PEAK[k] * v for k, v in t["mops"].items()) / max(sum(t["mops"].values()), 1e-30)
     return {"executed_mfma_tflops": ops / launch_s / 1e12, "executed_mfma_frac": ops / launch_s / peak,
             "mfma_busy_frac": t.get("mfma_busy_frac"), "valu_busy_frac": t.get("valu_busy_frac"),
-            "mfma_counters": t["profile"]}
+            "mfma_valu_coexec_frac": t.get("coexec_frac"), "mfma_counters": t["profile"]}
 
 
 def fp64_relres(krr, res, y, p):

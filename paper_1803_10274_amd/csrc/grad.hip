@@ -126,15 +126,21 @@ void bwd_rows(const T *A, int64_t ma, const T *B, int64_t nb, int d, double h, c
 }
 
 // dh = scale sum_a G_a v_a (one block, fixed order: deterministic)
-__global__ void k_dot_scaled(const double *__restrict__ g, const double *__restrict__ v, int64_t m, double scale,
-                             double *__restrict__ out) {
-    __shared__ double red[4];
+// One workgroup of up to 1024 threads; the waves' sums are added in a fixed
+// order, so the result is deterministic.
+__global__ __launch_bounds__(1024) void k_dot_scaled(const double *__restrict__ g, const double *__restrict__ v,
+                                                     int64_t m, double scale, double *__restrict__ out) {
+    __shared__ double red[16];
     double acc = 0.0;
     for (int64_t i = threadIdx.x; i < m; i += blockDim.x) acc += g[i] * v[i];
     acc = wave_sum(acc);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
     __syncthreads();
-    if (threadIdx.x == 0) *out = scale * (red[0] + red[1] + red[2] + red[3]);
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+        *out = scale * t;
+    }
 }
 
 template <class T>
@@ -221,7 +227,7 @@ void kernel_matvec_bwd_impl(const void *X, int64_t m, const void *Y, int64_t n, 
         DBuf v = dalloc<double>(m);
         kernel_matvec_q(X, m, Y, n, d, xprec, h, W, v.as<double>(), s);
         const double c = 1.4426950408889634 / (2.0 * h * h);
-        k_dot_scaled<<<1, 256, 0, s>>>(G, v.as<double>(), m, -1.0 / (c * h * h * h), dh);
+        k_dot_scaled<<<1, 1024, 0, s>>>(G, v.as<double>(), m, -1.0 / (c * h * h * h), dh);
         check_launch("k_dot_scaled");
         sync(s);
         return;

@@ -736,14 +736,15 @@ constexpr int symb_rt(int KT) { return KT <= 64 ? 8 : (KT <= 128 ? 4 : 2); }  //
 constexpr int symb_kt(int d) { return (6 * d + 6 + 31) / 32 * 32; }
 constexpr int symb_rows(int d) { return 16 * SM_WAVES * symb_rt(symb_kt(d)); }
 constexpr int symb_max_d = 31;  // KT <= 192
+// waves per SIMD the registers are budgeted for: the rectangular form of
+// wide points fits two workgroups per CU without spills
+constexpr int symb_wpe(int KT, bool SYM) { return !SYM && KT >= 96 ? 4 : 2; }
 
 template <int KT, int RT, bool QM, bool SYM>
-__global__ __launch_bounds__(64 * SM_WAVES) void k_kmv_symb(const float *__restrict__ X,
-                                                            const float *__restrict__ Ycols, int d,
-                                                            const float *__restrict__ anchors,
-                                                            const float *__restrict__ wf, int64_t n,
-                                                            const SymItem *__restrict__ items,
-                                                            double *__restrict__ rowpart, float *__restrict__ colpart) {
+__global__ __launch_bounds__(64 * SM_WAVES) __attribute__((amdgpu_waves_per_eu(symb_wpe(KT, SYM))))
+void k_kmv_symb(const float *__restrict__ X, const float *__restrict__ Ycols, int d, const float *__restrict__ anchors,
+                const float *__restrict__ wf, int64_t n, const SymItem *__restrict__ items,
+                double *__restrict__ rowpart, float *__restrict__ colpart) {
     constexpr int KS = KT / 32;  // MFMAs per tile
     constexpr int LDB = KT + 8;  // staged point stride (BF16 elements; 16 bytes of padding)
     constexpr int PN = symb_pn(KT);
