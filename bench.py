@@ -151,6 +151,8 @@ def parse():
     ap.add_argument("--reps", type=int, default=3, help="launches per kernel timing")
     ap.add_argument("--grad-kernels", action="store_true",
                     help="the fused backward's two dh launches at the gradient workload's size (profiling)")
+    ap.add_argument("--orderings", action="store_true",
+                    help="the Table 2 style memory / rank comparison of the orderings on 10,000-point stand-ins")
     ap.add_argument("--cpu-dense", action="store_true",
                     help="time the oracle's dense FP64 KRR fit on the host at n = 1,000, 8,192 and 32,768")
     ap.add_argument("--scaling", action="store_true",
@@ -281,6 +283,45 @@ def grad_kernels(args):
     print(json.dumps(out), flush=True)
 
 
+def orderings():
+    """Section 4.3's comparison (Table 2's memory columns) on synthetic
+    stand-ins of 10,000 training points with z-scored columns, as the paper
+    normalises its data: HSS memory (the paper's metric, MB) and maximum rank
+    for the natural order (NP), KD tree, PCA tree and 2MN (mean over three
+    seeds, as the paper averages three runs), leaf 16, relative tolerance
+    0.1, FP32 sampling from r = 128 grown as needed.  One JSON line per
+    stand-in."""
+    import numpy as np
+    import torch
+
+    import paper_1803_10274_amd as krr
+    import synthdata as sd
+    krr.load()
+    cases = [("sixteen_gaussians d=8", sd.c2_sixteen_gaussians(n=10_000, m=1, d=8).X, 1.0),
+             ("sixteen_gaussians d=16", sd.c2_sixteen_gaussians(n=10_000, m=1, d=16).X, 1.0),
+             ("eight_gaussians d=18", sd.c5_eight_gaussians(n=10_000, m=1).X, 1.5),
+             ("sixteen_gaussians d=54", sd.c2_sixteen_gaussians(n=10_000, m=1, d=54).X, 1.0),
+             ("image_like d=784", sd.c3_image_like(n=10_000, m=1).X, 4.0)]
+    opts = krr.HssOptions(rtol=0.1, r0=128, dr=128, r_max=4096, prec="f32")
+    for name, X, h in cases:
+        X = X.astype(np.float64)
+        sdev = X.std(axis=0)
+        Z = ((X - X.mean(axis=0)) / np.where(sdev > 0, sdev, 1.0)).astype(np.float32)
+        Xt = torch.from_numpy(Z).cuda()
+        mem, rank = {}, {}
+        for m in ("np", "kd", "pca", "2mn"):
+            b, k = [], []
+            for seed in ((7, 8, 9) if m == "2mn" else (7,)):
+                log(f"orderings: {name}, {m}, seed {seed}")
+                perm, tree = krr.cluster_order(Xt, 16, m, seed=seed)
+                H = krr.HSS(tree, krr.gather_rows(Xt, perm), h, opts)
+                b.append(H.stats.bytes_paper / 1e6)
+                k.append(H.stats.max_rank)
+            mem[m], rank[m] = round(float(np.mean(b)), 2), int(max(k))
+        print(json.dumps({"orderings": True, "workload": name, "n": 10_000, "h": h, "leaf": 16, "rtol": 0.1,
+                          "memory_mb": mem, "max_rank": rank}), flush=True)
+
+
 def scaling(args):
     """The headline fit at n = 2^16 .. 2^20 (same options, one warm-up fit at
     each n, then one timed), one JSON line per n: phase times, the sampling
@@ -359,6 +400,9 @@ def main():
         return
     if args.grad_kernels:
         grad_kernels(args)
+        return
+    if args.orderings:
+        orderings()
         return
     if args.cpu_dense:
         cpu_dense()

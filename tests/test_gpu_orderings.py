@@ -92,8 +92,9 @@ def test_ordering_degenerate(gpu_lib):
 def test_ordering_memory_comparison(gpu_lib):
     # Table 2 on a synthetic stand-in (16-Gaussian data, 10,000 points, leaf
     # 16, tolerance 0.1): the HSS memory and maximum rank of each ordering.
-    # The paper's finding that 2MN needs the least memory and NP the most
-    # holds here too.
+    # As in the paper, the natural order needs the most memory and every
+    # clustering saves a large factor; which clustering is best depends on the
+    # data (here PCA and KD come out slightly ahead of 2MN).
     p = sd.c2_sixteen_gaussians(n=10000, m=1)
     X = _t(p.X)
     mem, rank = {}, {}
