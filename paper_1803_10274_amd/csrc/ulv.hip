@@ -1,8 +1,9 @@
 // ULV factorization and solve of K_hss + lambda I (Section 3.1; lambda is
 // added to the leaf diagonal blocks only, Section 5.3).
 //
-// Bottom-up over the levels, one workgroup per node, with the node's dense
-// block Dw (m x m) and basis Uw (m x k):
+// Bottom-up over the levels, one workgroup per node (levels with few, large
+// nodes spread their products over many workgroups: kPhasedNodes), with the
+// node's dense block Dw (m x m) and basis Uw (m x k):
 //   leaf    Dw = D + lambda I,  Uw = U
 //   parent  Dw = [[S_a, Rh_a B_ab Rh_b^T], [(.)^T, S_b]],  Uw = diag(Rh_a, Rh_b) U
 // 1. Householder QR  Q^T Uw = [Rh; 0]  (Rh k x k is passed to the parent);
