@@ -252,6 +252,20 @@ __global__ void k_leaf_ranges(const int64_t *lb64, const int64_t *le64, int nlea
 }
 
 // Per-node device storage produced by one level.
+// Gather of the per-level node outputs into the generator pools: one
+// workgroup per (source, destination, 4-byte words) segment, so the pools are
+// filled by a single launch instead of a copy per node and pool.
+struct CopySeg {
+    const uint32_t *src;
+    uint32_t *dst;
+    int64_t words;
+};
+
+__global__ __launch_bounds__(256) void k_copy_segments(const CopySeg *__restrict__ segs) {
+    const CopySeg c = segs[blockIdx.x];
+    for (int64_t w = threadIdx.x; w < c.words; w += blockDim.x) c.dst[w] = c.src[w];
+}
+
 struct NodeOut {
     double *U = nullptr, *Ysk = nullptr, *Om = nullptr, *B = nullptr, *D = nullptr;
     int32_t *J = nullptr;
@@ -559,18 +573,26 @@ void compress(const krr_tree_s *t, const void *Xp, int xprec, int d, const std::
     H->nU = usz;
     H->nJ = jsz;
     H->nB = bsz;
+    std::vector<CopySeg> segs;
+    segs.reserve(3 * nn);
+    auto seg = [&](const void *src, void *dst, int64_t bytes) {
+        segs.push_back({static_cast<const uint32_t *>(src), static_cast<uint32_t *>(dst), bytes / 4});
+    };
     for (int64_t i = 0; i < nn; ++i) {
         const HNode &q = H->node[i];
         const NodeOut &no = A.out[i];
-        if (q.offU >= 0 && q.m * (int64_t)q.k > 0)
-            KRR_HIP(hipMemcpyAsync(H->U.as<double>() + q.offU, no.U, sizeof(double) * q.m * q.k,
-                                   hipMemcpyDeviceToDevice, s));
-        if (q.offJ >= 0 && q.k > 0)
-            KRR_HIP(hipMemcpyAsync(H->J.as<int32_t>() + q.offJ, no.J, sizeof(int32_t) * q.k, hipMemcpyDeviceToDevice, s));
+        if (q.offU >= 0 && q.m * (int64_t)q.k > 0) seg(no.U, H->U.as<double>() + q.offU, sizeof(double) * q.m * q.k);
+        if (q.offJ >= 0 && q.k > 0) seg(no.J, H->J.as<int32_t>() + q.offJ, sizeof(int32_t) * q.k);
         if (q.offB >= 0) {
-            int64_t kb = (int64_t)A.out[q.left].k * A.out[q.right].k;
-            if (kb) KRR_HIP(hipMemcpyAsync(H->B.as<double>() + q.offB, no.B, sizeof(double) * kb, hipMemcpyDeviceToDevice, s));
+            const int64_t kb = (int64_t)A.out[q.left].k * A.out[q.right].k;
+            if (kb) seg(no.B, H->B.as<double>() + q.offB, sizeof(double) * kb);
         }
+    }
+    if (!segs.empty()) {
+        DBuf dseg = upload(segs, s);
+        k_copy_segments<<<(unsigned)segs.size(), 256, 0, s>>>(dseg.as<CopySeg>());
+        check_launch("k_copy_segments");
+        sync(s);  // the segment table and the per-level outputs are released after this
     }
     sync(s);
     H->r_final = r;
