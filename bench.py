@@ -505,6 +505,17 @@ def main():
     roof_sample["every_tile"] = {"launch_s": t_full, "achieved": flops / t_full / 1e12, "frac": flops / t_full / peak}
     roof_sample["every_tile"].update(pmc_mfma("sampling_every_tile", n, r, t_full))
     del R
+    # the metric's second sample width: one pass at r = 2 r0 (same points and
+    # tree, tile skip on as in the fit)
+    r2 = 2 * args.r0
+    R2 = krr.random_block(1, n, r2)
+    log(f"timing the sampling product at r = {r2}")
+    t_r2 = time_launches(lambda: krr.kernel_sample(Xp, p.h, R2, lb, le, prec=args.prec, split_terms=args.split),
+                         args.reps)
+    flops2 = float(n) * n * (2 * p.d + 2 * r2)
+    roof_sample["wider_sample"] = {"r": r2, "launch_s": t_r2, "achieved": flops2 / t_r2 / 1e12,
+                                   "frac": flops2 / t_r2 / peak}
+    del R2
     w = res.alpha_perm.reshape(n, -1)[:, :1].contiguous()
     log("timing the refinement kernel product")
     t_mv = time_launches(lambda: krr.kernel_matvec(Xp, Xp, p.h, w, prec="f32"), args.reps)
@@ -591,8 +602,39 @@ def main():
         "gradient": grad,
         "image_like": image,
         "cpu_baseline": cpu,
+        "fit_s_all": [float(t) for t in fit_times],
+        "environment": run_environment(),
     }
     print(json.dumps(out), flush=True)
+
+
+def run_environment():
+    """What the run was measured on: device, ROCm and torch versions, the
+    GPU clocks amd-smi reports (when it is there) and a hash of the library
+    sources (the box has no git history)."""
+    import hashlib
+    import subprocess
+
+    import torch
+    env = {"device": torch.cuda.get_device_name(0), "torch": torch.__version__, "hip": torch.version.hip}
+    try:
+        with open("/opt/rocm/.info/version") as f:
+            env["rocm"] = f.read().strip()
+    except OSError:
+        env["rocm"] = None
+    try:
+        r = subprocess.run(["amd-smi", "metric", "--clock", "-g", "0"], capture_output=True, text=True, timeout=20)
+        lines = [l.strip() for l in r.stdout.splitlines() if "CLK" in l or "MHZ" in l.upper()]
+        env["amd_smi_clock"] = lines[:12] if r.returncode == 0 else None
+    except (OSError, subprocess.SubprocessError):
+        env["amd_smi_clock"] = None
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1803_10274_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + f.read())
+    env["sources_sha256"] = h.hexdigest()
+    return env
 
 
 def batched_leg():
