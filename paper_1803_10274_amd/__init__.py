@@ -665,31 +665,39 @@ class BatchedFitResult:
 
 
 def fit_batched(problems, leaf=128, opts: HssOptions = HssOptions(), seed=7, tol=1e-6, max_iter=200,
-                mv_prec="f32", refine_solution=True, raise_on_fail=True):
+                mv_prec="f32", refine_solution=True, raise_on_fail=True, concurrent=True):
     """Algorithm 1 steps 0-2 for many independent problems at once.
 
     problems: sequence of (X_k, y_k, h_k, lam_k) with X_k an n_k x d_k GPU
     tensor.  Problems of equal d (and dtype) form one batch: they are stored
     one after the other and every library call covers all of them (one launch
-    per phase and tree level).  Returns each problem's alpha in its own order."""
+    per phase and tree level).  With several such groups and `concurrent`,
+    each group runs in a host thread of its own on a stream of its own, so
+    that one group's kernels fill the gaps of another's host decisions; the
+    phase times are then summed over the groups.  Returns each problem's
+    alpha in its own order."""
+    import threading
     import time
-
-    ph = {}
-
-    def mark(name, t0):
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        ph[name] = ph.get(name, 0.0) + (t1 - t0)
-        return t1
 
     groups = {}
     for idx, (X, y, h, lam) in enumerate(problems):
         _dev(X)
         groups.setdefault((X.shape[1], X.dtype), []).append(idx)
+    keys = list(groups.items())
     alphas = [None] * len(problems)
-    out_groups = []
-    info = {"refine": [], "hss": [], "ulv_shift_mult": []}
-    for (d, _), members in groups.items():
+    results = [None] * len(keys)
+    errors = [None] * len(keys)
+    caller = torch.cuda.current_stream()
+
+    def run_group(gi, members):
+        ph = {}
+
+        def mark(name, t0):
+            torch.cuda.current_stream().synchronize()
+            t1 = time.perf_counter()
+            ph[name] = ph.get(name, 0.0) + (t1 - t0)
+            return t1
+
         t = time.perf_counter()
         Xs = [problems[i][0] for i in members]
         ys = [_dev(problems[i][1], torch.float64).reshape(problems[i][1].shape[0], -1) for i in members]
@@ -712,18 +720,63 @@ def fit_batched(problems, leaf=128, opts: HssOptions = HssOptions(), seed=7, tol
         t = mark("factor", t)
         ap = F.solve(Yp)
         t = mark("solve", t)
-        info["hss"].append(H.stats.as_dict())
-        info["ulv_shift_mult"].append(F.shift_mults.tolist())
+        ref = None
         if refine_solution:
-            info["refine"].append(refine_batched(F, Xp, off, hs, ls, Yp, ap, tol=tol, max_iter=max_iter,
-                                                 mv_prec=mv_prec, raise_on_fail=raise_on_fail))
+            ref = refine_batched(F, Xp, off, hs, ls, Yp, ap, tol=tol, max_iter=max_iter, mv_prec=mv_prec,
+                                 raise_on_fail=raise_on_fail)
             t = mark("refine", t)
         alpha = scatter_rows(ap, perm)
-        for j, i in enumerate(members):
+        mark("unpermute", t)
+        results[gi] = {"members": members, "offsets": off, "perm": perm, "Xp": Xp, "tree": tree, "hss": H,
+                       "ulv": F, "h": hs, "lam": ls, "alpha_perm": ap, "alpha": alpha, "refine": ref,
+                       "phases": ph}
+
+    def run_on_stream(gi, members, stream):
+        try:
+            with torch.cuda.stream(stream):
+                run_group(gi, members)
+        except BaseException as e:  # re-raised by the caller's thread
+            errors[gi] = e
+
+    t_all = time.perf_counter()
+    if concurrent and len(keys) > 1:
+        caller.synchronize()  # the inputs are ready before other streams read them
+        streams = [torch.cuda.Stream() for _ in keys]
+        threads = [threading.Thread(target=run_on_stream, args=(gi, members, streams[gi]))
+                   for gi, (_, members) in enumerate(keys)]
+        for th in threads:
+            th.start()
+        for th in threads:
+            th.join()
+        for st in streams:
+            st.synchronize()
+        for e in errors:
+            if e is not None:
+                raise e
+        # the results are used on the caller's stream from here on
+        for r in results:
+            for name in ("perm", "Xp", "alpha_perm", "alpha"):
+                r[name].record_stream(caller)
+    else:
+        for gi, (_, members) in enumerate(keys):
+            run_group(gi, members)
+    wall = time.perf_counter() - t_all
+    out_groups, ph = [], {}
+    info = {"refine": [], "hss": [], "ulv_shift_mult": []}
+    for r in results:
+        alpha, off = r.pop("alpha"), r["offsets"]
+        for j, i in enumerate(r["members"]):
             a = alpha[off[j]:off[j + 1]]
             alphas[i] = a.reshape(-1) if problems[i][1].dim() == 1 else a
-        mark("unpermute", t)
-        out_groups.append({"members": members, "offsets": off, "perm": perm, "Xp": Xp, "tree": tree, "hss": H,
-                           "ulv": F, "h": hs, "lam": ls, "alpha_perm": ap})
+        for k, v in r.pop("phases").items():
+            ph[k] = ph.get(k, 0.0) + v
+        info["hss"].append(r["hss"].stats.as_dict())
+        info["ulv_shift_mult"].append(r["ulv"].shift_mults.tolist())
+        ref = r.pop("refine")
+        if ref is not None:
+            info["refine"].append(ref)
+        out_groups.append(r)
     info["phases"] = ph
+    info["wall_s"] = wall
+    info["concurrent_groups"] = bool(concurrent and len(keys) > 1)
     return BatchedFitResult(alphas, out_groups, info)
