@@ -52,8 +52,17 @@ void validate_tree(const krr_tree_s *t);
 struct Batch {
     std::vector<int64_t> pbeg;
     std::vector<double> h, lam;
+    // problems a kernel product may leave out (the refinement's converged
+    // ones): their output rows are not computed (the plain paths write 0)
+    std::vector<uint8_t> skip;
     int np() const { return (int)h.size(); }
     int64_t size(int k) const { return pbeg[k + 1] - pbeg[k]; }
+    bool skipped(int k) const { return k < (int)skip.size() && skip[k]; }
+    bool any_skipped() const {
+        for (uint8_t v : skip)
+            if (v) return true;
+        return false;
+    }
 };
 
 // One workgroup's share of a batched kernel product: rows [i0, iend) and

@@ -1246,6 +1246,7 @@ bool kmv_sym(const T *X, int64_t n, int d, double h, const double *W, int nrhs, 
     std::vector<SampBlock> diag;
     int64_t nchunks = 0;
     for (int p = 0; p < np; ++p) {
+        if (batch && batch->skipped(p)) continue;  // rows left as they are
         const double c2 = kernel_scale_log2(hs[p]);
         const int64_t first = (int64_t)blocks.size(), pe = pb[p + 1];
         for (int64_t i0 = pb[p]; i0 < pe; i0 += rows_pb) {
@@ -1283,6 +1284,7 @@ bool kmv_sym(const T *X, int64_t n, int d, double h, const double *W, int nrhs, 
             }
         }
     }
+    if (blocks.empty()) return true;  // every problem left out: nothing to compute
     const double col_bytes = (double)blocks.size() * n * nrhs * sizeof(float);
     const double row_bytes = (double)nchunks * n * nrhs * sizeof(double);
     if (col_bytes + row_bytes > 24e9) return false;  // the plain product needs no partial sums
@@ -1542,6 +1544,8 @@ void kmv_typed(const T *X, int64_t m, const T *Y, int64_t n, int d, double h, co
     }
     const SampBlock *bt = btab.as<SampBlock>();
     DBuf part = dalloc<double>((size_t)nsplit * m * nrhs);
+    if (batch && batch->any_skipped())  // rows of left-out problems reduce to 0
+        KRR_HIP(hipMemsetAsync(part.get(), 0, sizeof(double) * nsplit * m * nrhs, s));
     if (sc) {
         const int LD = (D + 2) & ~1;  // ColLd
         DBuf ya = dalloc<double>((size_t)n * LD), wf = dalloc<float>((size_t)n * nrhs), pb, cp;

@@ -314,6 +314,8 @@ void kmv_wide_mfma64(const T *X, int64_t m, const T *Y, int64_t n, int d, double
                                                 cp.as<double>(), batch ? batch->np() : 0, 1, YA.as<double>());
     check_launch("k_wide_aug64");
     DBuf part = dalloc<double>((size_t)nsplit * m * nrhs);
+    if (batch && batch->any_skipped())  // rows of left-out problems reduce to 0
+        KRR_HIP(hipMemsetAsync(part.get(), 0, sizeof(double) * nsplit * m * nrhs, s));
     dim3 grid((unsigned)(batch ? nb : ceil_div(m, W64ROWS)), nsplit);
     for (int r0 = 0; r0 < nrhs; r0 += 16) {
         const int nrc = std::min(16, nrhs - r0);
@@ -390,6 +392,8 @@ void kmv_wide_mfma(const float *X, int64_t m, const float *Y, int64_t n, int d, 
     k_wide_pack<<<(unsigned)n, 256, 0, s>>>(YA.as<float>(), n, KP, YB.as<__bf16>());
     check_launch("k_wide_pack");
     DBuf part = dalloc<double>((size_t)nsplit * m * nrhs);
+    if (batch && batch->any_skipped())  // rows of left-out problems reduce to 0
+        KRR_HIP(hipMemsetAsync(part.get(), 0, sizeof(double) * nsplit * m * nrhs, s));
     dim3 grid((unsigned)(batch ? nb : ceil_div(m, KROWS)), nsplit);
     for (int r0 = 0; r0 < nrhs; r0 += 32) {
         const int nrc = std::min(32, nrhs - r0);

@@ -156,6 +156,12 @@ int refine(const hss_ulv_s *F, int64_t n, const void *Xp, int xprec, int d, doub
     sg.lam = upload(lam_h, s);
     const int np = sg.np, cnt = np * nrhs;
     DBuf r = dalloc<double>(len), z = dalloc<double>(len), p = dalloc<double>(len), q = dalloc<double>(len);
+    // q's rows of problems that the products leave out keep finite values
+    KRR_HIP(hipMemsetAsync(q.get(), 0, sizeof(double) * len, s));
+    // the inner products leave out problems whose every right-hand side has
+    // converged (their step lengths are 0 from then on)
+    Batch active;
+    if (batch) active = *batch;
     auto precond = [&](const double *in, double *out) {
         if (F)
             ulv_solve(F, in, nrhs, out, s);
@@ -163,12 +169,12 @@ int refine(const hss_ulv_s *F, int64_t n, const void *Xp, int xprec, int d, doub
             KRR_HIP(hipMemcpyAsync(out, in, sizeof(double) * len, hipMemcpyDeviceToDevice, s));
     };
     int matvecs = 0;
-    auto matvec = [&](const double *x, double *out, int prec) {
-        kernel_matvec_impl(Xp, n, Xp, n, d, xprec, h, x, nrhs, 0.0, out, prec, s, batch);
+    auto matvec = [&](const double *x, double *out, int prec, const Batch *b) {
+        kernel_matvec_impl(Xp, n, Xp, n, d, xprec, h, x, nrhs, 0.0, out, prec, s, b);
         ++matvecs;
     };
     auto true_residual = [&]() {
-        matvec(alpha, q.as<double>(), res_prec);
+        matvec(alpha, q.as<double>(), res_prec, batch);
         k_residual<<<ceil_div(len, 256), 256, 0, s>>>(Y, q.as<double>(), alpha, sg.lam.as<double>(),
                                                       sg.pid.as<int32_t>(), n, nrhs, r.as<double>());
         check_launch("k_residual");
@@ -199,7 +205,15 @@ int refine(const hss_ulv_s *F, int64_t n, const void *Xp, int xprec, int d, doub
         for (int c = 0; c < cnt; ++c) done[c] = relres[c] <= tol;
         while (it < max_iter) {
             ++it;
-            matvec(p.as<double>(), q.as<double>(), mv_prec);
+            if (batch) {
+                active.skip.assign(np, 0);
+                for (int pp = 0; pp < np; ++pp) {
+                    bool all = true;
+                    for (int c = 0; c < nrhs; ++c) all = all && done[(size_t)pp * nrhs + c];
+                    active.skip[pp] = all ? 1 : 0;
+                }
+            }
+            matvec(p.as<double>(), q.as<double>(), mv_prec, batch ? &active : nullptr);
             k_add_shift<<<ceil_div(len, 256), 256, 0, s>>>(q.as<double>(), p.as<double>(), sg.lam.as<double>(),
                                                            sg.pid.as<int32_t>(), n, nrhs);
             check_launch("k_add_shift");

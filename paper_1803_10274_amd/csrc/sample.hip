@@ -26,6 +26,7 @@ std::vector<SampBlock> row_blocks(const Batch &b, int rows) {
     std::stable_sort(ord.begin(), ord.end(), [&](int a, int c) { return b.size(a) > b.size(c); });
     std::vector<SampBlock> out;
     for (int k : ord) {
+        if (b.skipped(k)) continue;
         const double h = b.h[k];
         SampBlock sb{};
         sb.jlo = b.pbeg[k];

@@ -322,3 +322,30 @@ def test_fit_batched_top_of_size_range(gpu_lib):
         # FP32-entry products stop the solve at 1e-6; in FP64 the residual is
         # within the products' error, ~1e-7 of |K||alpha| / |y|
         assert np.linalg.norm(r) <= 2e-6 * np.linalg.norm(p.y), k
+
+
+@pytest.mark.parametrize("mv", ["f32", "f64"])
+def test_batched_refine_leaves_out_converged_problems(gpu_lib, mv):
+    # problems that converge at very different rates in one batch: a nearly
+    # diagonal kernel (h = 0.05: a few iterations) beside smooth, weakly
+    # regularised ones (lambda = 0.1: many).  Once a problem has converged the
+    # batched products leave it out (its rows of the product are not
+    # computed); every problem still reaches the tolerance and matches dense
+    # KRR, including the d > 64 and FP64 product paths through mv
+    ps = _problems(count=4, d=8, n_lo=600, n_hi=1200, seed=13)
+    ps[0].h, ps[0].lam = 0.05, 1.0
+    for p in ps[1:]:
+        p.h, p.lam = 1.5, 0.1
+    tol = 1e-6 if mv == "f32" else 1e-10
+    probs = [(_t(p.X), _t(p.y), p.h, p.lam) for p in ps]
+    res = gpu_lib.fit_batched(probs, leaf=64, opts=gpu_lib.HssOptions(rtol=1e-2, r0=64, prec="f16", atol=0.0),
+                              tol=tol, max_iter=400, mv_prec=mv)
+    rf = res.info["refine"][0]
+    assert rf["converged"] and np.all(rf["relres"] <= tol)
+    for k, p in enumerate(ps):
+        a = res.alphas[k].cpu().numpy()
+        ref = ok.krr_fit_dense(p.X.astype(np.float64), p.y, p.h, p.lam)
+        K = ok.kernel_dense(p.X.astype(np.float64), p.X.astype(np.float64), p.h)
+        cond = np.linalg.cond(K + p.lam * np.eye(K.shape[0]))
+        err = np.linalg.norm(a - ref) / np.linalg.norm(ref)
+        assert err <= (50.0 if mv == "f32" else 10.0) * cond * tol, (k, err, cond)
