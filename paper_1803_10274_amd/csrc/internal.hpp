@@ -122,6 +122,12 @@ struct hss_ulv_s {
     std::vector<int64_t> offV, offT, offL, offW, offY;
     krr::DBuf V, T, L, W, Y;
     int64_t nV = 0, nT = 0, nL = 0, nW = 0, nY = 0;
+    // The QR of a node's basis (V, tau, Y and the triangular factor Rh passed
+    // to the parent, k x k at offY) depends only on the HSS bases, not on
+    // lambda or a shift: passes over the same compression (the shift search's
+    // tries) reuse it.  qr_ok marks the nodes whose QR is in place.
+    krr::DBuf R;
+    std::vector<uint8_t> qr_ok;
 };
 
 // ------------------------------------------------ entry points across units

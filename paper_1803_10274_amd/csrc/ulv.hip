@@ -31,7 +31,8 @@ constexpr int kPhasedNodes = 64;
 
 struct UlvDesc {
     int32_t m, k, kl, kr, leaf, root;
-    int32_t prob, pad_;                // the node's problem (batch)
+    int32_t prob;                      // the node's problem (batch)
+    int32_t qr_done;                   // V, tau, Tw and Rh_out are in place from an earlier pass
     double lambda, pivot_floor;        // of the node's problem
     const double *D, *U, *B;           // HSS generators
     const double *S_l, *S_r, *Rh_l, *Rh_r;
@@ -78,7 +79,8 @@ __device__ void ulv_assemble_qr(const UlvDesc &q, double *smem, double *red, dou
     // ---- assemble
     if (q.leaf) {
         for (int t = tid; t < m * m; t += BG_T) Dw[t] = q.D[t] + ((t / m == t % m) ? q.lambda : 0.0);
-        for (int t = tid; t < m * k; t += BG_T) Uw[t] = q.U[t];
+        if (!q.qr_done)
+            for (int t = tid; t < m * k; t += BG_T) Uw[t] = q.U[t];
     } else {
         const int kl = q.kl, kr = q.kr;
         for (int t = tid; t < kl * kl; t += BG_T) Dw[(t / kl) * m + t % kl] = q.S_l[t];
@@ -91,12 +93,13 @@ __device__ void ulv_assemble_qr(const UlvDesc &q, double *smem, double *red, dou
             int i = t / kr, j = t % kr;
             Dw[(int64_t)(kl + j) * m + i] = Dw[(int64_t)i * m + kl + j];
         }
-        if (!q.root) {
+        if (!q.root && !q.qr_done) {
             block_gemm(kl, k, kl, 1.0, q.Rh_l, kl, 1, q.U, k, 1, 0.0, Uw, k, smem);
             block_gemm(kr, k, kr, 1.0, q.Rh_r, kr, 1, q.U + (int64_t)kl * k, k, 1, 0.0, Uw + (int64_t)kl * k, k, smem);
         }
     }
     __syncthreads();
+    if (q.qr_done) return;  // the basis's QR does not depend on lambda or the shift
     // ---- Householder QR of Uw (reflectors in V, tau), blocked: panels of
     // QR_NB columns are factored column by column, the columns right of a
     // panel get its block reflector Q_p^T = I - V_p T_p^T V_p^T as three
@@ -555,18 +558,21 @@ int64_t ulv_factor(const hss_s *H, const std::vector<double> &lam, const std::ve
     F->L.alloc(8 * std::max<int64_t>(nl, 1));
     F->W.alloc(8 * std::max<int64_t>(nw, 1));
     F->Y.alloc(8 * std::max<int64_t>(ny, 1));
+    F->R.alloc(8 * std::max<int64_t>(ny, 1));
     F->nV = nv; F->nT = nt; F->nL = nl; F->nW = nw; F->nY = ny;
+    F->qr_ok.assign(nn, 0);
     }
     std::vector<uint8_t> act(np, 1);
     if (active) act = *active;
-    // S and Rh of every non-root node live until the parent is done
+    // S of every non-root node lives until the parent is done (Rh lives in
+    // the factor, at offY)
     std::vector<int64_t> offS(nn, 0);
     int64_t ns = 0;
     for (int i = 0; i < nn; ++i) {
         offS[i] = ns;
         ns += (int64_t)k[i] * k[i];
     }
-    DBuf Sb = dalloc<double>(std::max<int64_t>(ns, 1)), Rb = dalloc<double>(std::max<int64_t>(ns, 1));
+    DBuf Sb = dalloc<double>(std::max<int64_t>(ns, 1));
     // counters: raised pivots per problem, then each problem's largest deficit
     DBuf flag = dalloc<int32_t>(1), nclamp = dalloc<unsigned long long>(2 * np);
     KRR_HIP(hipMemsetAsync(flag.get(), 0, sizeof(int32_t), s));
@@ -612,8 +618,8 @@ int64_t ulv_factor(const hss_s *H, const std::vector<double> &lam, const std::ve
                 u.B = H->B.as<double>() + q.offB;
                 u.S_l = Sb.as<double>() + offS[q.left];
                 u.S_r = Sb.as<double>() + offS[q.right];
-                u.Rh_l = Rb.as<double>() + offS[q.left];
-                u.Rh_r = Rb.as<double>() + offS[q.right];
+                u.Rh_l = F->R.as<double>() + F->offY[q.left];
+                u.Rh_r = F->R.as<double>() + F->offY[q.right];
                 u.Tmp = Tm.as<double>() + ot;
                 ot += (int64_t)u.kl * u.kr;
             }
@@ -633,7 +639,8 @@ int64_t ulv_factor(const hss_s *H, const std::vector<double> &lam, const std::ve
             u.L = F->L.as<double>() + F->offL[id];
             u.W = F->W.as<double>() + F->offW[id];
             u.S_out = Sb.as<double>() + offS[id];
-            u.Rh_out = Rb.as<double>() + offS[id];
+            u.Rh_out = F->R.as<double>() + F->offY[id];
+            u.qr_done = F->qr_ok[id];
         }
         DBuf dd = upload(dsc, s);
         if (cnt >= kPhasedNodes) {
@@ -684,6 +691,7 @@ int64_t ulv_factor(const hss_s *H, const std::vector<double> &lam, const std::ve
             sync(s);  // `tiles` is released at the end of this scope
         }
         sync(s);
+        for (int id : lv) F->qr_ok[id] = 1;  // the level's QR ran whatever its pivots did
         if (stop_at_floor) {
             // a problem with a pivot below its floor stops here (its factor
             // is left incomplete); the others go on
