@@ -808,13 +808,20 @@ void k_kmv_symb(const float *__restrict__ X, const float *__restrict__ Ycols, in
     for (int64_t p0 = it.j0; p0 < it.j1; p0 += PN) {
         const int cnt = (int)min((int64_t)PN, it.j1 - p0);
         // stage the panel: packed BF16 terms of 2 c y' and of the column
-        // constant; points past the item get a constant of -1e30
-        if (tid < PN) {
-            __bf16 *dst = ys + tid * LDB;
+        // constant; points past the item get a constant of -1e30.  TPP
+        // threads per point (every thread of the workgroup takes part), each
+        // a contiguous share of the coordinates; the norm's partial sums meet
+        // by shuffles.  The slots of ones and the zero padding are the same
+        // in every panel and are written with the first.
+        {
+            constexpr int TPP = TH / PN;
+            const int pt = tid / TPP, sub = tid % TPP;
+            __bf16 *dst = ys + pt * LDB;
+            const bool ok = pt < cnt;
+            const float *y = (SYM ? X : Ycols) + (ok ? p0 + pt : 0) * d;
+            const int kb = (d * sub) / TPP, ke = (d * (sub + 1)) / TPP;
             float nrm = 0.0f;
-            const bool ok = tid < cnt;
-            const float *y = (SYM ? X : Ycols) + (ok ? p0 + tid : 0) * d;
-            for (int k = 0; k < d; ++k) {
+            for (int k = kb; k < ke; ++k) {
                 const float v = ok ? y[k] - anc[k] : 0.0f;
                 nrm = fmaf(v, v, nrm);
                 __bf16 h, m, l;
@@ -827,14 +834,20 @@ void k_kmv_symb(const float *__restrict__ X, const float *__restrict__ Ycols, in
                 dst[4 * d + k] = l;
                 dst[5 * d + k] = m;
             }
-            __bf16 h, m, l;
-            split3(ok ? -c * nrm : -1e30f, h, m, l);
-            dst[6 * d] = h;
-            dst[6 * d + 1] = m;
-            dst[6 * d + 2] = l;
-            for (int k = 6 * d + 3; k < 6 * d + 6; ++k) dst[k] = (__bf16)1.0f;
-            for (int k = 6 * d + 6; k < KT; ++k) dst[k] = (__bf16)0.0f;
-            ws[tid] = ok ? wf[p0 + tid] : 0.0f;
+#pragma unroll
+            for (int o = 1; o < TPP; o <<= 1) nrm += __shfl_xor(nrm, o, 64);
+            if (sub == 0) {
+                __bf16 h, m, l;
+                split3(ok ? -c * nrm : -1e30f, h, m, l);
+                dst[6 * d] = h;
+                dst[6 * d + 1] = m;
+                dst[6 * d + 2] = l;
+                if (p0 == it.j0) {
+                    for (int k = 6 * d + 3; k < 6 * d + 6; ++k) dst[k] = (__bf16)1.0f;
+                    for (int k = 6 * d + 6; k < KT; ++k) dst[k] = (__bf16)0.0f;
+                }
+                ws[pt] = ok ? wf[p0 + pt] : 0.0f;
+            }
         }
         __syncthreads();
         float pacc[RT];
