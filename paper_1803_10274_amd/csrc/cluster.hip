@@ -262,7 +262,27 @@ __global__ void k_centroid_partial(const T *__restrict__ X, int d, int nc, Level
     int c = (int)(t / d), k = (int)(t % d);
     if (L.status[L.cnode[c]] != ACTIVE) return;
     double p0 = 0.0, p1 = 0.0;
-    for (int64_t p = L.cb[c]; p < L.ce[c]; ++p) {
+    // the loads of eight points are issued together, the sums still run
+    // point by point in order (the result is the sequential sum)
+    const int64_t pe = L.ce[c];
+    int64_t p = L.cb[c];
+    for (; p + 8 <= pe; p += 8) {
+        double v[8];
+        uint8_t lb[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            v[u] = (double)X[(p + u) * d + k];
+            lb[u] = lab[p + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (lb[u] == 0)
+                p0 = p0 + v[u];
+            else
+                p1 = p1 + v[u];
+        }
+    }
+    for (; p < pe; ++p) {
         double v = (double)X[p * d + k];
         if (lab[p] == 0)
             p0 = p0 + v;
@@ -279,7 +299,23 @@ __global__ void k_centroid_final(int d, int na, Level L) {
     int node = (int)(t / d), k = (int)(t % d);
     if (L.status[node] != ACTIVE) return;
     double s0 = 0.0, s1 = 0.0;
-    for (int c = L.ch0[node]; c < L.ch0[node] + L.nch[node]; ++c) {
+    // chunks in order, their loads eight at a time
+    const int ce = L.ch0[node] + L.nch[node];
+    int c = L.ch0[node];
+    for (; c + 8 <= ce; c += 8) {
+        double a0[8], a1[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            a0[u] = L.cps[2 * ((int64_t)(c + u) * d + k)];
+            a1[u] = L.cps[2 * ((int64_t)(c + u) * d + k) + 1];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            s0 = s0 + a0[u];
+            s1 = s1 + a1[u];
+        }
+    }
+    for (; c < ce; ++c) {
         s0 = s0 + L.cps[2 * ((int64_t)c * d + k)];
         s1 = s1 + L.cps[2 * ((int64_t)c * d + k) + 1];
     }
@@ -823,20 +859,28 @@ void cluster_impl(const T *X, int64_t n, int d, const std::vector<int64_t> &root
             KRR_HIP(hipMemsetAsync(counter.get(), 0, sizeof(int32_t), s));
             k_node_update<<<gn, 64, 0, s>>>(L, na, 1);
             check_launch("k_node_update");
-            for (int it = 0; it < o.max_iter; ++it) {
+            // Lloyd iterations in groups of four between checks of the
+            // active count: the kernels skip nodes that are no longer active,
+            // so an iteration after the last node settles changes nothing
+            // (each node still runs at most max_iter iterations)
+            constexpr int kLloydGroup = 4;
+            for (int it = 0; it < o.max_iter; it += kLloydGroup) {
                 int32_t nact = 0;
                 d2h(&nact, counter.as<int32_t>(), 1, s);
                 sync(s);
                 if (nact == 0) break;
-                k_centroid_partial<T><<<ceil_div((int64_t)nc * d, 256), 256, 0, s>>>(Xc, d, nc, L, lab.as<uint8_t>());
-                check_launch("k_centroid_partial");
-                k_centroid_final<<<gnd, 256, 0, s>>>(d, na, L);
-                check_launch("k_centroid_final");
-                k_assign<T><<<nc, CH, 0, s>>>(Xc, d, L, lab.as<uint8_t>(), 0);
-                check_launch("k_assign");
-                KRR_HIP(hipMemsetAsync(counter.get(), 0, sizeof(int32_t), s));
-                k_node_update<<<gn, 64, 0, s>>>(L, na, 0);
-                check_launch("k_node_update");
+                for (int j = 0; j < kLloydGroup && it + j < o.max_iter; ++j) {
+                    k_centroid_partial<T><<<ceil_div((int64_t)nc * d, 256), 256, 0, s>>>(Xc, d, nc, L,
+                                                                                         lab.as<uint8_t>());
+                    check_launch("k_centroid_partial");
+                    k_centroid_final<<<gnd, 256, 0, s>>>(d, na, L);
+                    check_launch("k_centroid_final");
+                    k_assign<T><<<nc, CH, 0, s>>>(Xc, d, L, lab.as<uint8_t>(), 0);
+                    check_launch("k_assign");
+                    KRR_HIP(hipMemsetAsync(counter.get(), 0, sizeof(int32_t), s));
+                    k_node_update<<<gn, 64, 0, s>>>(L, na, 0);
+                    check_launch("k_node_update");
+                }
             }
         }
         if (method != KRR_ORDER_NP) {
