@@ -43,14 +43,14 @@ PEAK_EXP2 = 256 * 64 * 2.4e9 / 4
 # WRITE_SIZE 1,048,576 KiB -> x1.000).  Valid only while the kernel's source
 # file is unchanged (sha256 below); otherwise the bench reports null.
 PMC_TRAFFIC = {
-    "sampling": {"fetch_kib": 931370229.9375, "write_kib": 1048576.0, "fetch_scale": 2.0, "write_scale": 1.0,
+    "sampling": {"fetch_kib": 929733190.125, "write_kib": 1048576.0, "fetch_scale": 2.0, "write_scale": 1.0,
                  "source": "paper_1803_10274_amd/csrc/sample_mfma.hip",
                  "sha256": "bcd0d5396bd1701e27d4c92645b02fded9aa6e4ae6559e2bc90a8edeb4e761b3", "n": 1 << 20, "r": 256},
     # the symmetric product's six launches: column data, FP32 weights,
     # diagonal blocks, row-block anchors, upper triangle, reduction
-    "kernel_product": {"fetch_kib": 8328471.3125, "write_kib": 2822946.625, "fetch_scale": 2.0, "write_scale": 1.0,
+    "kernel_product": {"fetch_kib": 8332009.75, "write_kib": 2824314.71875, "fetch_scale": 2.0, "write_scale": 1.0,
                        "source": "paper_1803_10274_amd/csrc/matvec.hip",
-                       "sha256": "a656c5da9c339bf3f3f2258207c567a4904a6fad7acb152b1d7b16b382242df8",
+                       "sha256": "2da142bd019360bdabf48a4f933c7ba1478dfec6a371b1ff742c9f38a7fce438",
                        "n": 1 << 20, "r": None},
 }
 
@@ -73,20 +73,20 @@ def pmc_traffic(kind, n, r=None):
 # `rocprofv3 --pmc` runs of `bench.py --kernels-only`; valid only while the
 # kernel's source file is unchanged (sha256), otherwise reported as null.
 PMC_MFMA = {
-    "sampling": {"mops": {"f16": 659243755520.0, "bf16": 274886295552.0}, "mfma_busy_frac": 0.348,
-                 "valu_busy_frac": 0.2221, "coexec_frac": 0.0447,
+    "sampling": {"mops": {"f16": 659243755520.0, "bf16": 274886295552.0}, "mfma_busy_frac": 0.3471,
+                 "valu_busy_frac": 0.2215, "coexec_frac": 0.0445,
                  "source": "paper_1803_10274_amd/csrc/sample_mfma.hip",
                  "sha256": "bcd0d5396bd1701e27d4c92645b02fded9aa6e4ae6559e2bc90a8edeb4e761b3", "n": 1 << 20, "r": 256,
                  "profile": "profiles/k_sample_mfma_sixteen_gaussians_n1048576_r256.md"},
-    "sampling_every_tile": {"mops": {"f16": 2199023255552.0, "bf16": 274886295552.0}, "mfma_busy_frac": 0.5944,
-                            "valu_busy_frac": 0.3311, "coexec_frac": 0.0864,
+    "sampling_every_tile": {"mops": {"f16": 2199023255552.0, "bf16": 274886295552.0}, "mfma_busy_frac": 0.5948,
+                            "valu_busy_frac": 0.3314, "coexec_frac": 0.0864,
                             "source": "paper_1803_10274_amd/csrc/sample_mfma.hip",
                             "sha256": "bcd0d5396bd1701e27d4c92645b02fded9aa6e4ae6559e2bc90a8edeb4e761b3",
                             "n": 1 << 20, "r": 256,
                             "profile": "profiles/k_sample_mfma_sixteen_gaussians_n1048576_r256.md"},
-    "kernel_product": {"mops": {"bf16": 137304735744.0}, "mfma_busy_frac": 0.2445, "valu_busy_frac": 0.63,
-                       "coexec_frac": 0.0756, "source": "paper_1803_10274_amd/csrc/matvec.hip",
-                       "sha256": "a656c5da9c339bf3f3f2258207c567a4904a6fad7acb152b1d7b16b382242df8",
+    "kernel_product": {"mops": {"bf16": 137304735744.0}, "mfma_busy_frac": 0.2536, "valu_busy_frac": 0.663,
+                       "coexec_frac": 0.0787, "source": "paper_1803_10274_amd/csrc/matvec.hip",
+                       "sha256": "2da142bd019360bdabf48a4f933c7ba1478dfec6a371b1ff742c9f38a7fce438",
                        "n": 1 << 20, "r": None, "profile": "profiles/k_kmv_symb_sixteen_gaussians_n1048576.md"},
 }
 

@@ -240,7 +240,16 @@ __global__ void k_node_update(Level L, int na, int first) {
     int node = blockIdx.x * blockDim.x + threadIdx.x;
     if (node >= na || L.status[node] != ACTIVE) return;
     int64_t n1 = 0;
-    for (int c = L.ch0[node]; c < L.ch0[node] + L.nch[node]; ++c) n1 += L.cn1[c];
+    const int ce = L.ch0[node] + L.nch[node];
+    int c = L.ch0[node];
+    for (; c + 8 <= ce; c += 8) {  // eight loads in flight
+        int32_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = L.cn1[c + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) n1 += v[u];
+    }
+    for (; c < ce; ++c) n1 += L.cn1[c];
     int64_t s = L.ne[node] - L.nb[node];
     L.n1[node] = n1;
     if (!first) L.iters[node] += 1;
