@@ -58,8 +58,8 @@ def pmc_traffic(kind, n, r=None):
     """Calibrated HBM bytes per launch, or None if the counters do not
     describe the current kernel and size."""
     import hashlib
-    t = PMC_TRAFFIC[kind]
-    if t["n"] != n or (t["r"] is not None and t["r"] != r):
+    t = PMC_TRAFFIC.get(kind)
+    if t is None or t["n"] != n or (t["r"] is not None and t["r"] != r):
         return None
     with open(os.path.join(ROOT, t["source"]), "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != t["sha256"]:
@@ -220,7 +220,8 @@ def time_launches(fn, reps):
 def kernels_only(args):
     """One launch each: a 1 GiB device copy, the sampling product (with the
     negligible-tile skip, then with every tile evaluated) and the refinement
-    kernel product, on the 16-Gaussian workload in tree order."""
+    kernel product (every entry, then recording its tile map, then through
+    the map), on the 16-Gaussian workload in tree order."""
     import torch
 
     import paper_1803_10274_amd as krr
@@ -251,6 +252,13 @@ def kernels_only(args):
     log("kernel product")
     krr.kernel_matvec(Xp, Xp, p.h, w, prec="f32")
     torch.cuda.synchronize()
+    log("kernel product through its tile map: recording, then one product")
+    tmap = krr.TileMap()
+    tmap.matvec(Xp, p.h, w)
+    torch.cuda.synchronize()
+    tmap.matvec(Xp, p.h, w)
+    torch.cuda.synchronize()
+    del tmap
     print(json.dumps({"kernels_only": True, "n": args.n, "r": args.r0, "copy_bytes": 2 * a.numel() * 4}), flush=True)
 
 
@@ -517,7 +525,7 @@ def main():
                                    "frac": flops2 / t_r2 / peak}
     del R2
     w = res.alpha_perm.reshape(n, -1)[:, :1].contiguous()
-    log("timing the refinement kernel product")
+    log("timing the refinement kernel product (every entry)")
     t_mv = time_launches(lambda: krr.kernel_matvec(Xp, Xp, p.h, w, prec="f32"), args.reps)
     # The symmetric product evaluates each off-diagonal entry once and the
     # 1024-row diagonal blocks in full; the unit of work is an evaluated entry
@@ -526,32 +534,60 @@ def main():
     rb = 1024
     evaluated = n * rb + (float(n) * n - n * rb) / 2
     mv_flops = evaluated * (2 * p.d + 2)
+    every_entry = {"launch_s": t_mv, "achieved": mv_flops / t_mv / 1e12, "frac": mv_flops / t_mv / PEAK_F32_VECTOR,
+                   "traffic": pmc_traffic("kernel_product", n),
+                   "evaluated_entries": evaluated, "algorithmic_flops": mv_flops,
+                   "entries_per_s": evaluated / t_mv, "exp2_floor_frac": evaluated / PEAK_EXP2 / t_mv}
+    every_entry.update(pmc_mfma("kernel_product", n, None, t_mv))
+    # The refinement's products after its first: through the tile map that
+    # the first one recorded (tiles whose entries are all below 2^-32 left
+    # out).  Evaluated entries: the diagonal blocks plus the kept tiles.
+    log("timing the refinement kernel product through its tile map")
+    tmap = krr.TileMap()
+    tmap.matvec(Xp, p.h, w)  # records the map (every entry evaluated)
+    kept, tiles, per_tile = tmap.counts()
+    t_map = time_launches(lambda: tmap.matvec(Xp, p.h, w), args.reps)
+    del tmap
+    evaluated_map = n * rb + float(kept) * per_tile
+    map_flops = evaluated_map * (2 * p.d + 2)
     form = krr.get_tuning("symmetric")
+    mapped = form == 4 and p.d <= 31 and kept > 0
     mv_kernel = {4: "k_kmv_symb (refinement product K w over K's upper triangle: FP32-accurate exponents from "
-                    "three-term BF16 splits on the matrix cores, re-centred per row block, FP32 entries; timed "
-                    "with its diagonal-block, anchor and reduction launches)",
+                    "three-term BF16 splits on the matrix cores, re-centred per row block, FP32 entries; "
+                    "through the negligible-tile map the refinement's first product records; timed with its "
+                    "diagonal-block, anchor and reduction launches)",
                  3: "k_kmv_symf (refinement product K w over K's upper triangle: FP32 exponents on the matrix "
                     "cores, re-centred per row block, FP32 entries; timed with its diagonal-block, anchor and "
                     "reduction launches)"}.get(form, "k_kmv_sym (refinement product K w over K's upper triangle, "
                                                     "FP64 exponent, FP32 entries; timed with its diagonal-block "
                                                     "and reduction launches)")
-    roof_mv = {"bound": "alu", "achieved": mv_flops / t_mv / 1e12, "peak": PEAK_F32_VECTOR / 1e12,
-               "unit": "TFLOP/s", "frac": mv_flops / t_mv / PEAK_F32_VECTOR,
-               "traffic": pmc_traffic("kernel_product", n),
-               "kernel": mv_kernel, "launch_s": t_mv,
+    if mapped:
+        t_use, ev_use, fl_use = t_map, evaluated_map, map_flops
+        basis = ("(2d + 2) flops per evaluated kernel entry; evaluated entries = n x 1024 (the 1024-row "
+                 "diagonal blocks) + the tile map's kept wave tiles x their entries (128 rows x 16 points)")
+    else:
+        t_use, ev_use, fl_use = t_mv, evaluated, mv_flops
+        basis = ("(2d + 2) flops per evaluated kernel entry; evaluated entries = n x 1024 + "
+                 "(n^2 - n x 1024) / 2 (upper triangle plus full 1024-row diagonal blocks)")
+    roof_mv = {"bound": "alu", "achieved": fl_use / t_use / 1e12, "peak": PEAK_F32_VECTOR / 1e12,
+               "unit": "TFLOP/s", "frac": fl_use / t_use / PEAK_F32_VECTOR,
+               "traffic": pmc_traffic("kernel_product_mapped" if mapped else "kernel_product", n),
+               "kernel": mv_kernel, "launch_s": t_use,
                "peak_basis": "FP32 vector peak 157.3 TFLOP/s (256 CU x 128 lanes x 2 flops x 2.4 GHz)",
-               "flops_basis": "(2d + 2) flops per evaluated kernel entry; evaluated entries = n x 1024 + "
-                              "(n^2 - n x 1024) / 2 (upper triangle plus full 1024-row diagonal blocks)",
-               "evaluated_entries": evaluated, "evaluated_entries_frac": evaluated / (float(n) * n),
-               "algorithmic_flops": mv_flops, "entries_per_s": evaluated / t_mv,
-               "exp2_floor_frac": evaluated / PEAK_EXP2 / t_mv,
+               "flops_basis": basis,
+               "evaluated_entries": ev_use, "evaluated_entries_frac": ev_use / (float(n) * n),
+               "tile_map": {"kept_tiles": kept, "tiles": tiles, "entries_per_tile": per_tile},
+               "algorithmic_flops": fl_use, "entries_per_s": ev_use / t_use,
+               "exp2_floor_frac": ev_use / PEAK_EXP2 / t_use,
                "exp2_floor_basis": "one exp2 per evaluated entry at 256 CU x 64 lanes x 2.4 GHz / 4 = "
-                                   "9.83e12 exp2/s"}
-    roof_mv.update(pmc_mfma("kernel_product", n, None, t_mv))
+                                   "9.83e12 exp2/s",
+               "every_entry": every_entry}
+    roof_mv.update(pmc_mfma("kernel_product_mapped" if mapped else "kernel_product", n, None, t_use))
     relres_fp64 = fp64_relres(krr, res, y, p)
     log(f"FP64 relative residual of the fitted coefficients: {relres_fp64:.3e}")
     log(f"sampling {t_sample * 1e3:.1f} ms ({achieved / 1e12:.1f} TFLOP/s); "
-        f"kernel product {t_mv * 1e3:.1f} ms ({mv_flops / t_mv / 1e12:.1f} TFLOP/s evaluated)")
+        f"kernel product {t_mv * 1e3:.1f} ms ({mv_flops / t_mv / 1e12:.1f} TFLOP/s evaluated), through its tile map "
+        f"{t_map * 1e3:.1f} ms ({map_flops / t_map / 1e12:.1f} TFLOP/s evaluated, {kept} of {tiles} tiles)")
     if args.dump_alpha:
         os.makedirs(args.dump_alpha, exist_ok=True)
         np.save(os.path.join(args.dump_alpha, "alpha_sixteen_gaussians.npy"), res.alpha.cpu().numpy())

@@ -203,6 +203,40 @@ int kernel_matvec(const void *X, int64_t m, const void *Y, int64_t n, int32_t d,
                   double *Out, int32_t prec, void *stream);
 
 /*
+ * Negligible-tile map of the symmetric FP32 product (the products of the
+ * refinement of Section 6, kept across a sequence of products with the same
+ * points and width).  The first product through a map evaluates every entry
+ * and records which 16-point tiles of the product's waves hold an entry of
+ * at least 2^-32; later products evaluate only those tiles and leave out the
+ * rest (every entry left out is below 2^-32).  A map is recorded again when
+ * the address of X, n, d or h differs from its recording; the caller makes
+ * a new map (or destroys this one) when the contents of X change at the same
+ * address.  Applies to K(X, X) with FP32 points, d <= 31, one right-hand
+ * side and the BF16 symmetric form (KRR_TUNE_SYMMETRIC 4); other products
+ * evaluate every entry, and so do all products when KRR_TUNE_SYM_SKIP is 0.
+ * The map's device memory belongs to the handle (about 8 bytes per 256 x
+ * 1024 entries of K's upper triangle: 68 MB at n = 2^20).  Errors:
+ * KRR_E_INVAL for NULL handles.
+ */
+typedef struct krr_tile_map_s *krr_tile_map_t;
+int krr_tile_map_create(krr_tile_map_t *map_out);
+int krr_tile_map_destroy(krr_tile_map_t map);
+
+/* Out = K(X, X; h) W + beta * Out as kernel_matvec (X = Y, prec KRR_F32)
+ * through a tile map (recording it when it does not match).  X n x d
+ * (xprec), W and Out n x nrhs FP64.  Calls that share a map run one after
+ * the other on one stream. */
+int kernel_matvec_mapped(const void *X, int64_t n, int32_t d, int32_t xprec, double h,
+                         const double *W, int32_t nrhs, double beta, double *Out,
+                         krr_tile_map_t map, void *stream);
+
+/* counts_host[0] = tiles the map marks for evaluation, [1] = tiles it covers,
+ * [2] = kernel entries per tile (rows of a wave x 16 points); all 0 before a
+ * recording.  The diagonal blocks of the symmetric form (all of their
+ * entries) are not part of the map.  Synchronizes `stream`. */
+int krr_tile_map_counts(krr_tile_map_t map, int64_t *counts_host, void *stream);
+
+/*
  * Off-diagonal sampling product of the randomized HSS construction
  * (Section 3.1): S = K(X, X; h) R where row i skips the columns of its own
  * leaf [leaf_begin[i], leaf_end[i]) (pass both NULL for no masking).
@@ -518,7 +552,12 @@ enum {
                                 halved for products too small to fill the chip) */
     KRR_TUNE_SAMPLE_SKIP = 4, /* 1: the matrix-core sampler skips 32 x 32 tiles whose entries are all below
                                  2^-32 (default); 0: every tile is evaluated */
-    KRR_TUNE_COUNT = 5
+    KRR_TUNE_SYM_SKIP = 5,    /* negligible tiles of the BF16 symmetric product (a wave's 16-point tile with
+                                 every entry below 2^-32): 1 (default) the refinement's first product
+                                 records them and its later products skip them; 2 as 1, and every other
+                                 such product records, then skips them, in two passes; 0 every tile is
+                                 evaluated */
+    KRR_TUNE_COUNT = 6
 };
 int krr_set_tuning(int32_t knob, int32_t value);
 int krr_get_tuning(int32_t knob, int32_t *value_host);

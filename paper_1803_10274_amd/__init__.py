@@ -234,6 +234,42 @@ def kernel_matvec(X, Y, h, W, beta=0.0, out=None, prec="f32"):
     return out.reshape((m,) + tuple(W.shape[1:]))
 
 
+class TileMap:
+    """Negligible-tile map of the symmetric FP32 product K(X, X) W, kept
+    across products with the same points and width: the first product records
+    which tiles hold an entry of at least 2^-32, later ones evaluate only
+    those (krr_tile_map_*).  Make a new map when X changes in place."""
+
+    def __init__(self):
+        h = ctypes.c_void_p()
+        check(load().krr_tile_map_create(ctypes.byref(h)))
+        self.h = h
+
+    def matvec(self, X, h, W, beta=0.0, out=None):
+        """out = K(X, X; h) W + beta out through the map (FP32 entries)."""
+        _dev(X)
+        _dev(W, torch.float64)
+        W2 = W.reshape(W.shape[0], -1)
+        n = X.shape[0]
+        if out is None:
+            out = torch.empty((n, W2.shape[1]), dtype=torch.float64, device=X.device)
+        _dev(out, torch.float64)
+        check(load().kernel_matvec_mapped(_p(X), n, X.shape[1], _xprec(X), float(h), _p(W2), W2.shape[1],
+                                          float(beta), _p(out), self.h, _stream()))
+        return out.reshape((n,) + tuple(W.shape[1:]))
+
+    def counts(self):
+        """(tiles marked for evaluation, tiles covered, kernel entries per tile)."""
+        c = (ctypes.c_int64 * 3)()
+        check(load().krr_tile_map_counts(self.h, c, _stream()))
+        return int(c[0]), int(c[1]), int(c[2])
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None and _lib._lib is not None:
+            _lib._lib.krr_tile_map_destroy(self.h)
+            self.h = None
+
+
 def kernel_sample(X, h, R, leaf_begin=None, leaf_end=None, prec="f32", split_terms=2):
     """Off-diagonal sample S = K(X, X; h) R with each row's own leaf removed."""
     _dev(X)
@@ -277,7 +313,7 @@ def kernel_matvec_bwd(X, Y, h, W, G, prec="f32", want=("dX", "dY", "dW", "dh")):
 
 TUNE = {"symmetric": _lib.KRR_TUNE_SYMMETRIC, "sample_rb": _lib.KRR_TUNE_SAMPLE_RB,
         "mv_blocks": _lib.KRR_TUNE_MV_BLOCKS, "sym_chunk": _lib.KRR_TUNE_SYM_CHUNK,
-        "sample_skip": _lib.KRR_TUNE_SAMPLE_SKIP}
+        "sample_skip": _lib.KRR_TUNE_SAMPLE_SKIP, "sym_skip": _lib.KRR_TUNE_SYM_SKIP}
 
 
 def set_tuning(knob: str, value: int):

@@ -10,6 +10,7 @@ KRR_OK, KRR_E_INVAL, KRR_E_NOMEM, KRR_E_HIP = 0, -1, -2, -3
 KRR_E_RANK_CAP, KRR_E_NUMERIC, KRR_E_NOT_CONVERGED, KRR_E_NODEVICE = -4, -5, -6, -7
 KRR_F64, KRR_F32, KRR_F16_SPLIT, KRR_BF16_SPLIT = 0, 1, 2, 3
 KRR_TUNE_SYMMETRIC, KRR_TUNE_SAMPLE_RB, KRR_TUNE_MV_BLOCKS, KRR_TUNE_SYM_CHUNK, KRR_TUNE_SAMPLE_SKIP = 0, 1, 2, 3, 4
+KRR_TUNE_SYM_SKIP = 5
 
 _CODES = {KRR_E_INVAL: "KRR_E_INVAL", KRR_E_NOMEM: "KRR_E_NOMEM", KRR_E_HIP: "KRR_E_HIP",
           KRR_E_RANK_CAP: "KRR_E_RANK_CAP", KRR_E_NUMERIC: "KRR_E_NUMERIC",
@@ -69,6 +70,10 @@ SIGNATURES = {
     "krr_gather_rows": (ctypes.c_int, [_vp, _i32, _i64, _i32, _vp, _vp, _vp]),
     "krr_scatter_rows": (ctypes.c_int, [_vp, _i32, _i64, _i32, _vp, _vp, _vp]),
     "kernel_matvec": (ctypes.c_int, [_vp, _i64, _vp, _i64, _i32, _i32, _dbl, _vp, _i32, _dbl, _vp, _i32, _vp]),
+    "krr_tile_map_create": (ctypes.c_int, [_P(_vp)]),
+    "krr_tile_map_destroy": (ctypes.c_int, [_vp]),
+    "kernel_matvec_mapped": (ctypes.c_int, [_vp, _i64, _i32, _i32, _dbl, _vp, _i32, _dbl, _vp, _vp, _vp]),
+    "krr_tile_map_counts": (ctypes.c_int, [_vp, _P(_i64), _vp]),
     "kernel_sample": (ctypes.c_int, [_vp, _i64, _i32, _i32, _dbl, _vp, _i32, _vp, _vp, _vp, _i32, _i32, _vp]),
     "krr_random_block": (ctypes.c_int, [_u64, _i64, _i32, _i32, _vp, _vp]),
     "kernel_matvec_bwd": (ctypes.c_int, [_vp, _i64, _vp, _i64, _i32, _i32, _dbl, _vp, _vp, _i32, _vp, _vp, _vp,

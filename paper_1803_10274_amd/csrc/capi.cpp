@@ -28,7 +28,7 @@ Allocator current_allocator() {
 hipStream_t call_stream() { return g_call_stream; }
 void note_allocation(bool by_caller) { (by_caller ? g_alloc_caller : g_alloc_direct).fetch_add(1); }
 
-std::atomic<int> g_tune[KRR_TUNE_COUNT] = {{4}, {8}, {2048}, {16384}, {1}};
+std::atomic<int> g_tune[KRR_TUNE_COUNT] = {{4}, {8}, {2048}, {16384}, {1}, {1}};
 
 int tune_get(int knob) { return g_tune[knob].load(std::memory_order_relaxed); }
 
@@ -367,6 +367,53 @@ int kernel_matvec(const void *X, int64_t m, const void *Y, int64_t n, int32_t d,
     });
 }
 
+struct krr_tile_map_s {
+    krr::SymSkip map;
+};
+
+int krr_tile_map_create(krr_tile_map_t *map_out) {
+    return guard([&] {
+        KRR_REQUIRE(map_out, "krr_tile_map_create: NULL pointer");
+        *map_out = new krr_tile_map_s();
+        return KRR_OK;
+    });
+}
+
+int krr_tile_map_destroy(krr_tile_map_t map) {
+    return guard([&] {
+        KRR_REQUIRE(map, "krr_tile_map_destroy: NULL handle");
+        delete map;
+        return KRR_OK;
+    });
+}
+
+int kernel_matvec_mapped(const void *X, int64_t n, int32_t d, int32_t xprec, double h, const double *W,
+                         int32_t nrhs, double beta, double *Out, krr_tile_map_t map, void *stream) {
+    return guard([&] {
+        check_xprec(xprec);
+        KRR_REQUIRE(map, "kernel_matvec_mapped: NULL map");
+        KRR_REQUIRE(n >= 1 && d >= 1, "kernel_matvec_mapped: need n >= 1, d >= 1");
+        KRR_REQUIRE(nrhs >= 1 && nrhs <= 64, "kernel_matvec_mapped: nrhs must be in [1, 64]");
+        KRR_REQUIRE(h > 0.0 && h == h, "kernel_matvec_mapped: h must be positive");
+        KRR_REQUIRE(X && W && Out, "kernel_matvec_mapped: NULL pointer");
+        require_device();
+        kernel_matvec_impl(X, n, X, n, d, xprec, h, W, nrhs, beta, Out, KRR_F32, S(stream), nullptr, &map->map);
+        return KRR_OK;
+    });
+}
+
+int krr_tile_map_counts(krr_tile_map_t map, int64_t *counts_host, void *stream) {
+    return guard([&] {
+        KRR_REQUIRE(map && counts_host, "krr_tile_map_counts: NULL pointer");
+        require_device();
+        const bool rec = map->map.ready;
+        counts_host[0] = rec ? krr::sym_skip_kept(map->map, S(stream)) : 0;
+        counts_host[1] = rec ? map->map.tiles : 0;
+        counts_host[2] = rec ? map->map.entries_per_tile : 0;
+        return KRR_OK;
+    });
+}
+
 int kernel_sample(const void *X, int64_t n, int32_t d, int32_t xprec, double h, const float *R, int32_t r,
                   const int32_t *leaf_begin, const int32_t *leaf_end, void *Sout, int32_t prec, int32_t split_terms,
                   void *stream) {
@@ -636,6 +683,7 @@ int krr_set_tuning(int32_t knob, int32_t value) {
                 break;
             case KRR_TUNE_MV_BLOCKS: KRR_REQUIRE(value >= 64 && value <= 65536, "krr_set_tuning: blocks in [64, 65536]"); break;
             case KRR_TUNE_SAMPLE_SKIP: KRR_REQUIRE(value == 0 || value == 1, "krr_set_tuning: sample skip is 0 or 1"); break;
+            case KRR_TUNE_SYM_SKIP: KRR_REQUIRE(value >= 0 && value <= 2, "krr_set_tuning: symmetric skip is 0, 1 or 2"); break;
             case KRR_TUNE_SYM_CHUNK:
                 KRR_REQUIRE(value >= 64 && value % 64 == 0 && value <= (1 << 24), "krr_set_tuning: chunk multiple of 64");
                 break;

@@ -79,6 +79,22 @@ struct SampBlock {
 // blocks carry the most work, so they start before the short ones).
 std::vector<SampBlock> row_blocks(const Batch &b, int rows);
 
+// Negligible-tile map of the symmetric FP32-entry product, kept across the
+// products of one refinement (same points, same kernel widths): the first
+// product that takes the BF16 symmetric form records which of its waves'
+// 16-point tiles hold an entry of at least 2^-32, the later ones evaluate
+// only those.  key identifies the item layout the map was recorded for; a
+// product with another layout records again.
+struct SymSkip {
+    DBuf bits;
+    std::vector<double> key;
+    bool ready = false;
+    int64_t tiles = 0;          // wave tiles the map covers
+    int64_t entries_per_tile = 0;
+};
+// Number of tiles a recorded map marks for evaluation (synchronizes s).
+int64_t sym_skip_kept(const SymSkip &m, hipStream_t s);
+
 // Diagnostic logging to stderr when the environment sets KRR_VERBOSE.
 bool verbose();
 
@@ -137,9 +153,11 @@ namespace krr {
 void cluster_2mn(const void *X, int32_t xprec, int64_t n, int32_t d, const std::vector<int64_t> &roots,
                  const krr_cluster_opts &o, hipStream_t s, int64_t *perm, krr_tree_s &tree,
                  int32_t method = KRR_ORDER_2MN);
+// skip (optional): the negligible-tile map of a sequence of products with the
+// same X = Y and widths (recorded by the first that can use it).
 void kernel_matvec_impl(const void *X, int64_t m, const void *Y, int64_t n, int d, int xprec, double h,
                         const double *W, int nrhs, double beta, double *Out, int prec, hipStream_t s,
-                        const Batch *batch = nullptr);
+                        const Batch *batch = nullptr, SymSkip *skip = nullptr);
 // FP32-entry K(X, Y; h) W + beta Out for points wider than 64 on the matrix cores.
 void kmv_wide_mfma(const float *X, int64_t m, const float *Y, int64_t n, int d, double h, const double *W, int nrhs,
                    double beta, double *Out, hipStream_t s, const Batch *batch);

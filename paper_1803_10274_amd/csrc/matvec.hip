@@ -221,6 +221,7 @@ struct SymItem {
     int64_t i0, iend, j0, j1;
     int64_t blk, chunk;
     double c2;
+    int64_t mid;  // index of the item's words in a negligible-tile map (stable across a batch's skips)
 };
 
 template <class T, int D, int NR, int RPT>
@@ -740,11 +741,23 @@ constexpr int symb_max_d = 31;  // KT <= 192
 // wide points fits two workgroups per CU without spills
 constexpr int symb_wpe(int KT, bool SYM) { return !SYM && KT >= 96 ? 4 : 2; }
 
-template <int KT, int RT, bool QM, bool SYM>
+// MK: the negligible-tile map (SYM only).  0 none; 1 record: every tile is
+// evaluated, and each wave writes per panel the word whose bit t says that
+// its 16 x 16-point tile t (all RT row tiles) holds an exponent of at least
+// kSymSkipLog2 (rows and points past the item do not count); 2 use: a wave
+// evaluates only the tiles whose bit is set, and a panel with no bit set in
+// any wave is not staged.  The word of (item, panel p, wave w) is
+// mask[(mid * ppi + p) * SM_WAVES + w].
+constexpr float kSymSkipLog2 = -32.0f;
+
+template <int KT, int RT, bool QM, bool SYM, int MK = 0>
 __global__ __launch_bounds__(64 * SM_WAVES) __attribute__((amdgpu_waves_per_eu(symb_wpe(KT, SYM))))
 void k_kmv_symb(const float *__restrict__ X, const float *__restrict__ Ycols, int d, const float *__restrict__ anchors,
                 const float *__restrict__ wf, int64_t n, const SymItem *__restrict__ items,
-                double *__restrict__ rowpart, float *__restrict__ colpart) {
+                double *__restrict__ rowpart, float *__restrict__ colpart, uint32_t *__restrict__ mask = nullptr,
+                int ppi = 0) {
+    static_assert(MK == 0 || (SYM && !QM), "the tile map is for the symmetric product");
+    static_assert(symb_pn(KT) / 16 <= 32, "a panel's tiles fill at most one map word");
     constexpr int KS = KT / 32;  // MFMAs per tile
     constexpr int LDB = KT + 8;  // staged point stride (BF16 elements; 16 bytes of padding)
     constexpr int PN = symb_pn(KT);
@@ -805,8 +818,23 @@ void k_kmv_symb(const float *__restrict__ X, const float *__restrict__ Ycols, in
     double acc[RT];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) acc[rt] = 0.0;
+    bool fresh = true;  // no panel staged yet: the constant slots are still to be written
     for (int64_t p0 = it.j0; p0 < it.j1; p0 += PN) {
         const int cnt = (int)min((int64_t)PN, it.j1 - p0);
+        uint32_t *mw = nullptr;
+        uint32_t wbits = ~0u;  // the wave's tiles to evaluate in this panel
+        if (MK != 0) mw = mask + (it.mid * ppi + (p0 - it.j0) / PN) * SM_WAVES;
+        if (MK == 2) {
+            uint32_t any = 0;
+#pragma unroll
+            for (int w = 0; w < SM_WAVES; ++w) any |= mw[w];
+            if (any == 0) {  // negligible for every wave: the panel's column partials are 0
+                if (tid < cnt) colpart[(int64_t)it.blk * n + p0 + tid] = 0.0f;
+                continue;
+            }
+            wbits = __builtin_amdgcn_readfirstlane(mw[wv]);
+        }
+        uint32_t rec = 0;  // MK 1: the tiles found to matter
         // stage the panel: packed BF16 terms of 2 c y' and of the column
         // constant; points past the item get a constant of -1e30.  TPP
         // threads per point (every thread of the workgroup takes part), each
@@ -842,19 +870,24 @@ void k_kmv_symb(const float *__restrict__ X, const float *__restrict__ Ycols, in
                 dst[6 * d] = h;
                 dst[6 * d + 1] = m;
                 dst[6 * d + 2] = l;
-                if (p0 == it.j0) {
+                if (fresh) {
                     for (int k = 6 * d + 3; k < 6 * d + 6; ++k) dst[k] = (__bf16)1.0f;
                     for (int k = 6 * d + 6; k < KT; ++k) dst[k] = (__bf16)0.0f;
                 }
                 ws[pt] = ok ? wf[p0 + pt] : 0.0f;
             }
         }
+        fresh = false;
         __syncthreads();
         float pacc[RT];
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) pacc[rt] = 0.0f;
 #pragma unroll 1
         for (int tl = 0; tl < PN / 16; ++tl) {
+            if (MK == 2 && !((wbits >> tl) & 1u)) {  // every entry of the wave's tile is negligible
+                if ((lane & 3) == 0) csum[wv][tl * 16 + symf_point(g, (lane >> 2) & 3)] = 0.0f;
+                continue;
+            }
             bf8v a[KS];
 #pragma unroll
             for (int s = 0; s < KS; ++s) a[s] = *reinterpret_cast<const bf8v *>(ys + (tl * 16 + lr) * LDB + 32 * s + 8 * g);
@@ -862,6 +895,7 @@ void k_kmv_symb(const float *__restrict__ X, const float *__restrict__ Ycols, in
 #pragma unroll
             for (int q = 0; q < 4; ++q) wp[q] = ws[tl * 16 + symf_point(g, q)];
             float cacc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            float tmax = -INFINITY;
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt) {
                 f4v t = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -874,7 +908,10 @@ void k_kmv_symb(const float *__restrict__ X, const float *__restrict__ Ycols, in
                     pacc[rt] = fmaf(e, wp[q], pacc[rt]);
                     if (SYM) cacc[q] = fmaf(e, wi[rt], cacc[q]);
                 }
+                if (MK == 1 && it.i0 + (int64_t)(wv * RT + rt) * 16 + lr < it.iend)
+                    tmax = fmaxf(tmax, fmaxf(fmaxf(t[0], t[1]), fmaxf(t[2], t[3])));
             }
+            if (MK == 1 && __ballot(tmax >= kSymSkipLog2) != 0) rec |= 1u << tl;
             if (!SYM) continue;
 #pragma unroll
             for (int o = 8, h = 2; o >= 4; o >>= 1, h >>= 1) {
@@ -893,6 +930,7 @@ void k_kmv_symb(const float *__restrict__ X, const float *__restrict__ Ycols, in
         }
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) acc[rt] += (double)pacc[rt];
+        if (MK == 1 && lane == 0) mw[wv] = rec;
         __syncthreads();
         if (SYM && tid < cnt) {
             float cs = csum[0][tid];
@@ -1191,18 +1229,32 @@ void launch_symf(dim3 gd, dim3 gs, dim3 gr, int rows_pb, const float *X, int d, 
     check_launch("k_sym_reduce");
 }
 
-// BF16 three-term exponents: K slots for d and the kernel's row tiles.
+// BF16 three-term exponents: K slots for d and the kernel's row tiles.  mk:
+// the tile map's use (k_kmv_symb's MK; 3: record, then use, in one call).
 template <int KT, int RT, bool QM>
 void launch_symb_kernel(dim3 gs, const float *X, int d, const float *anchors, const float *wf, int64_t n,
-                        const SymItem *it, double *rowpart, float *colpart, hipStream_t s) {
-    k_kmv_symb<KT, RT, QM, true><<<gs, 64 * SM_WAVES, 0, s>>>(X, X, d, anchors, wf, n, it, rowpart, colpart);
+                        const SymItem *it, double *rowpart, float *colpart, int mk, uint32_t *mask, int ppi,
+                        hipStream_t s) {
+    if constexpr (QM) {
+        k_kmv_symb<KT, RT, true, true><<<gs, 64 * SM_WAVES, 0, s>>>(X, X, d, anchors, wf, n, it, rowpart, colpart);
+    } else {
+        if (mk == 0)
+            k_kmv_symb<KT, RT, false, true, 0><<<gs, 64 * SM_WAVES, 0, s>>>(X, X, d, anchors, wf, n, it, rowpart,
+                                                                            colpart);
+        if (mk == 1 || mk == 3)
+            k_kmv_symb<KT, RT, false, true, 1><<<gs, 64 * SM_WAVES, 0, s>>>(X, X, d, anchors, wf, n, it, rowpart,
+                                                                            colpart, mask, ppi);
+        if (mk == 2 || mk == 3)
+            k_kmv_symb<KT, RT, false, true, 2><<<gs, 64 * SM_WAVES, 0, s>>>(X, X, d, anchors, wf, n, it, rowpart,
+                                                                            colpart, mask, ppi);
+    }
 }
 
 template <int D, bool QM>
 void launch_symb(dim3 gd, dim3 gs, dim3 gr, int rows_pb, const float *X, int d, double c2, const double *ya,
                  const float *wf, int64_t n, const SampBlock *dt, const SymItem *it, const SymBlock *bl,
                  int64_t nblocks, double *diag, double *rowpart, float *colpart, double beta, double *Out,
-                 hipStream_t s) {
+                 int mk, uint32_t *mask, int ppi, hipStream_t s) {
     k_kmv_sc<float, D, 1, sc_rpt(D), QM><<<gd, MV_ROWS, 0, s>>>(X, n, d, c2, ya, wf, 1, 0, n, 0, diag, dt);
     check_launch("k_kmv_sc (diagonal blocks)");
     if (gs.x > 0) {
@@ -1211,15 +1263,20 @@ void launch_symb(dim3 gd, dim3 gs, dim3 gr, int rows_pb, const float *X, int d, 
         check_launch("k_block_mean");
         const int kt = (6 * d + 6 + 31) / 32 * 32;
         const float *an = anchors.as<float>();
+#define KRR_SYMB(KT)                                                                                  \
+    case KT:                                                                                          \
+        launch_symb_kernel<KT, symb_rt(KT), QM>(gs, X, d, an, wf, n, it, rowpart, colpart, mk, mask, ppi, s); \
+        break;
         switch (kt) {  // row tiles per wave: symb_rt
-            case 32: launch_symb_kernel<32, symb_rt(32), QM>(gs, X, d, an, wf, n, it, rowpart, colpart, s); break;
-            case 64: launch_symb_kernel<64, symb_rt(64), QM>(gs, X, d, an, wf, n, it, rowpart, colpart, s); break;
-            case 96: launch_symb_kernel<96, symb_rt(96), QM>(gs, X, d, an, wf, n, it, rowpart, colpart, s); break;
-            case 128: launch_symb_kernel<128, symb_rt(128), QM>(gs, X, d, an, wf, n, it, rowpart, colpart, s); break;
-            case 160: launch_symb_kernel<160, symb_rt(160), QM>(gs, X, d, an, wf, n, it, rowpart, colpart, s); break;
-            case 192: launch_symb_kernel<192, symb_rt(192), QM>(gs, X, d, an, wf, n, it, rowpart, colpart, s); break;
+            KRR_SYMB(32)
+            KRR_SYMB(64)
+            KRR_SYMB(96)
+            KRR_SYMB(128)
+            KRR_SYMB(160)
+            KRR_SYMB(192)
             default: fail(KRR_E_INVAL, "kernel_matvec: no BF16 symmetric variant for width %d", d);
         }
+#undef KRR_SYMB
         check_launch("k_kmv_symb");
         sync(s);  // the anchors are released on return
     }
@@ -1232,9 +1289,11 @@ void launch_symb(dim3 gd, dim3 gs, dim3 gr, int rows_pb, const float *X, int d, 
 // returns false otherwise.  FP32 points with one right-hand side take the
 // matrix-core exponents (k_kmv_symm) unless the vector form is selected;
 // the rest the vector form.  qm: the entry exp2(t) t, on the BF16 form only.
+// skip: the negligible-tile map (BF16 form, qm false): used when it was
+// recorded for the same item layout, otherwise recorded by this product.
 template <class T>
 bool kmv_sym(const T *X, int64_t n, int d, double h, const double *W, int nrhs, double beta, double *Out,
-             hipStream_t s, const Batch *batch, bool qm = false) {
+             hipStream_t s, const Batch *batch, bool qm = false, SymSkip *skip = nullptr) {
     const int D = sc_width(d);
     if (D > 32 || (nrhs != 1 && nrhs != 2)) return false;
     const bool mc = sizeof(T) == 4 && nrhs == 1 && tune_get(KRR_TUNE_SYMMETRIC) == 1;
@@ -1257,9 +1316,9 @@ bool kmv_sym(const T *X, int64_t n, int d, double h, const double *W, int nrhs, 
     std::vector<SymBlock> blocks;
     std::vector<SymItem> items;
     std::vector<SampBlock> diag;
-    int64_t nchunks = 0;
+    int64_t nchunks = 0, mids = 0;  // mids: items of every problem, left-out ones included
     for (int p = 0; p < np; ++p) {
-        if (batch && batch->skipped(p)) continue;  // rows left as they are
+        const bool out = batch && batch->skipped(p);  // rows left as they are
         const double c2 = kernel_scale_log2(hs[p]);
         const int64_t first = (int64_t)blocks.size(), pe = pb[p + 1];
         for (int64_t i0 = pb[p]; i0 < pe; i0 += rows_pb) {
@@ -1281,8 +1340,10 @@ bool kmv_sym(const T *X, int64_t n, int d, double h, const double *W, int nrhs, 
                 it.blk = blk;
                 it.chunk = c;
                 it.c2 = c2;
-                items.push_back(it);
+                it.mid = mids++;
+                if (!out) items.push_back(it);
             }
+            if (out) continue;
             nchunks = std::max(nchunks, b.chunk_hi);
             blocks.push_back(b);
             for (int64_t r0 = b.i0; r0 < b.iend; r0 += diag_rows) {
@@ -1301,6 +1362,41 @@ bool kmv_sym(const T *X, int64_t n, int d, double h, const double *W, int nrhs, 
     const double col_bytes = (double)blocks.size() * n * nrhs * sizeof(float);
     const double row_bytes = (double)nchunks * n * nrhs * sizeof(double);
     if (col_bytes + row_bytes > 24e9) return false;  // the plain product needs no partial sums
+    // the tile map: mk as in launch_symb_kernel
+    int mk = 0, ppi = 0;
+    uint32_t *mask = nullptr;
+    DBuf own_map;
+    const int map_knob = tune_get(KRR_TUNE_SYM_SKIP);
+    if (mb && !qm && map_knob != 0 && (skip || map_knob == 2)) {
+        ppi = (int)ceil_div(CH, (int64_t)symb_pn(symb_kt(d)));
+        const size_t words = (size_t)mids * ppi * SM_WAVES;
+        std::vector<double> key{(double)(uintptr_t)X, (double)n, (double)d, (double)CH, (double)rows_pb,
+                                (double)mids};
+        for (int p = 0; p < np; ++p) {
+            key.push_back((double)pb[p + 1]);
+            key.push_back(hs[p]);
+        }
+        if (skip && skip->ready && skip->key == key) {
+            mk = 2;
+        } else if (!(batch && batch->any_skipped())) {  // a recording covers every item
+            DBuf &map = skip ? skip->bits : own_map;
+            map = dalloc<uint32_t>(std::max<size_t>(words, 1));
+            // words past an item's last panel are never read; bits past a
+            // panel's tiles stay 0
+            KRR_HIP(hipMemsetAsync(map.get(), 0, std::max<size_t>(words, 1) * sizeof(uint32_t), s));
+            mk = skip ? 1 : 3;
+            if (skip) {
+                const int64_t pn = symb_pn(symb_kt(d));
+                int64_t panels = 0;
+                for (const SymItem &it : items) panels += ceil_div(it.j1 - it.j0, pn);
+                skip->key = key;
+                skip->ready = true;
+                skip->tiles = panels * SM_WAVES * (pn / 16);
+                skip->entries_per_tile = (int64_t)symb_rows(d) / SM_WAVES * 16;
+            }
+        }
+        if (mk != 0) mask = (skip ? skip->bits : own_map).as<uint32_t>();
+    }
     const double c2 = kernel_scale_log2(h);
     DBuf ya, wf;
     prep_columns<T>(X, n, d, D, c2, W, nrhs, batch, ya, wf, s);
@@ -1321,7 +1417,7 @@ bool kmv_sym(const T *X, int64_t n, int d, double h, const double *W, int nrhs, 
             (qm ? launch_symb<DD, true> : launch_symb<DD, false>)(                                              \
                 gd, gs, gr, rows_pb, X, d, c2, ya.as<double>(), wf.as<float>(), n, dt.as<SampBlock>(),          \
                 it.as<SymItem>(), bl.as<SymBlock>(), (int64_t)blocks.size(), dd.as<double>(), rp.as<double>(),  \
-                cpart.as<float>(), beta, Out, s);                                                               \
+                cpart.as<float>(), beta, Out, mk, mask, ppi, s);                                                \
             break;                                                                                              \
         }                                                                                                       \
         if (mf) {                                                                                               \
@@ -1358,6 +1454,37 @@ bool kmv_sym(const T *X, int64_t n, int d, double h, const double *W, int nrhs, 
 
 // K(X, Y) w with the entry exp2(t) t for FP32 points of width d <= 31 (the
 // fused backward's dh when X != Y): the BF16 matrix-core exponents of
+// Set bits of a tile map (one 64-bit atomic per workgroup).
+__global__ __launch_bounds__(256) void k_popcount(const uint32_t *__restrict__ w, int64_t nw,
+                                                  unsigned long long *__restrict__ out) {
+    __shared__ unsigned long long part[4];
+    unsigned long long c = 0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nw; i += (int64_t)gridDim.x * 256)
+        c += (unsigned long long)__popc(w[i]);
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(out, part[0] + part[1] + part[2] + part[3]);
+}
+
+}  // namespace
+
+int64_t sym_skip_kept(const SymSkip &m, hipStream_t s) {
+    if (!m.ready) return 0;
+    const int64_t nw = (int64_t)(m.bits.bytes() / sizeof(uint32_t));
+    DBuf cnt = dalloc<unsigned long long>(1);
+    KRR_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(unsigned long long), s));
+    k_popcount<<<(unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, ceil_div(nw, 256))), 256, 0, s>>>(
+        m.bits.as<uint32_t>(), nw, cnt.as<unsigned long long>());
+    check_launch("k_popcount");
+    unsigned long long h = 0;
+    d2h(&h, cnt.as<unsigned long long>(), 1, s);
+    sync(s);
+    return (int64_t)h;
+}
+
+namespace {
+
 // k_kmv_symb without column sums.  Items are (row block of X, chunk of Y's
 // columns), the chunk sized so that the grid holds about 2048 workgroups;
 // the chunks' FP64 row partials are summed in a fixed order.
@@ -1506,7 +1633,7 @@ void kmv_run(const T *X, int64_t m, const T *Y, int64_t n, int d, double h, cons
 
 template <class T, class C>
 void kmv_typed(const T *X, int64_t m, const T *Y, int64_t n, int d, double h, const double *W, int nrhs,
-               double beta, double *Out, hipStream_t s, const Batch *batch) {
+               double beta, double *Out, hipStream_t s, const Batch *batch, SymSkip *skip) {
     if constexpr (sizeof(C) == 4 && sizeof(T) == 4) {
         if (d > 64) {  // wide points: the exponents as a matrix-core GEMM
             kmv_wide_mfma(X, m, Y, n, d, h, W, nrhs, beta, Out, s, batch);
@@ -1521,7 +1648,8 @@ void kmv_typed(const T *X, int64_t m, const T *Y, int64_t n, int d, double h, co
     }
     if constexpr (sizeof(C) == 4) {
         // K(X, X): each off-diagonal entry once, for its row and its column
-        if (X == Y && m == n && tune_get(KRR_TUNE_SYMMETRIC) && kmv_sym<T>(X, n, d, h, W, nrhs, beta, Out, s, batch))
+        if (X == Y && m == n && tune_get(KRR_TUNE_SYMMETRIC) &&
+            kmv_sym<T>(X, n, d, h, W, nrhs, beta, Out, s, batch, false, skip))
             return;
     }
     if (!batch) {
@@ -1626,7 +1754,7 @@ void kmv_typed(const T *X, int64_t m, const T *Y, int64_t n, int d, double h, co
 
 void kernel_matvec_impl(const void *X, int64_t m, const void *Y, int64_t n, int d, int xprec, double h,
                         const double *W, int nrhs, double beta, double *Out, int prec, hipStream_t s,
-                        const Batch *batch) {
+                        const Batch *batch, SymSkip *skip) {
     if (m == 0) return;
     if (batch && batch->np() == 1) batch = nullptr;  // one problem: the plain launch
     KRR_REQUIRE(!batch || (X == Y && m == n), "kernel_matvec: a batch multiplies its own points");
@@ -1637,16 +1765,16 @@ void kernel_matvec_impl(const void *X, int64_t m, const void *Y, int64_t n, int 
         auto Xd = static_cast<const double *>(X);
         auto Yd = static_cast<const double *>(Y);
         if (prec == KRR_F64)
-            kmv_typed<double, double>(Xd, m, Yd, n, d, h, W, nrhs, beta, Out, s, batch);
+            kmv_typed<double, double>(Xd, m, Yd, n, d, h, W, nrhs, beta, Out, s, batch, skip);
         else
-            kmv_typed<double, float>(Xd, m, Yd, n, d, h, W, nrhs, beta, Out, s, batch);
+            kmv_typed<double, float>(Xd, m, Yd, n, d, h, W, nrhs, beta, Out, s, batch, skip);
     } else {
         auto Xf = static_cast<const float *>(X);
         auto Yf = static_cast<const float *>(Y);
         if (prec == KRR_F64)
-            kmv_typed<float, double>(Xf, m, Yf, n, d, h, W, nrhs, beta, Out, s, batch);
+            kmv_typed<float, double>(Xf, m, Yf, n, d, h, W, nrhs, beta, Out, s, batch, skip);
         else
-            kmv_typed<float, float>(Xf, m, Yf, n, d, h, W, nrhs, beta, Out, s, batch);
+            kmv_typed<float, float>(Xf, m, Yf, n, d, h, W, nrhs, beta, Out, s, batch, skip);
     }
 }
 

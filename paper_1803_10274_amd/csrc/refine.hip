@@ -169,12 +169,19 @@ int refine(const hss_ulv_s *F, int64_t n, const void *Xp, int xprec, int d, doub
             KRR_HIP(hipMemcpyAsync(out, in, sizeof(double) * len, hipMemcpyDeviceToDevice, s));
     };
     int matvecs = 0;
-    auto matvec = [&](const double *x, double *out, int prec, const Batch *b) {
-        kernel_matvec_impl(Xp, n, Xp, n, d, xprec, h, x, nrhs, 0.0, out, prec, s, b);
+    // The products see the same points and widths throughout, so the
+    // negligible tiles of the symmetric product are found once: by the first
+    // true residual when it takes that form (recording evaluates every
+    // entry), else by the first iteration's product.  The iterations' products
+    // skip them; the true residuals that confirm convergence evaluate every
+    // entry.
+    SymSkip skipmap;
+    auto matvec = [&](const double *x, double *out, int prec, const Batch *b, SymSkip *sk) {
+        kernel_matvec_impl(Xp, n, Xp, n, d, xprec, h, x, nrhs, 0.0, out, prec, s, b, sk);
         ++matvecs;
     };
     auto true_residual = [&]() {
-        matvec(alpha, q.as<double>(), res_prec, batch);
+        matvec(alpha, q.as<double>(), res_prec, batch, skipmap.ready ? nullptr : &skipmap);
         k_residual<<<ceil_div(len, 256), 256, 0, s>>>(Y, q.as<double>(), alpha, sg.lam.as<double>(),
                                                       sg.pid.as<int32_t>(), n, nrhs, r.as<double>());
         check_launch("k_residual");
@@ -213,7 +220,7 @@ int refine(const hss_ulv_s *F, int64_t n, const void *Xp, int xprec, int d, doub
                     active.skip[pp] = all ? 1 : 0;
                 }
             }
-            matvec(p.as<double>(), q.as<double>(), mv_prec, batch ? &active : nullptr);
+            matvec(p.as<double>(), q.as<double>(), mv_prec, batch ? &active : nullptr, &skipmap);
             k_add_shift<<<ceil_div(len, 256), 256, 0, s>>>(q.as<double>(), p.as<double>(), sg.lam.as<double>(),
                                                            sg.pid.as<int32_t>(), n, nrhs);
             check_launch("k_add_shift");

@@ -119,6 +119,18 @@ def fp32_sym_anchored_bound(X, W, h, rows_per_block, tile=64, safety=4.0, form=3
     return safety * U32 * ((tile + 2) * (K @ aW) + (d + 3) * ((K * T) @ aW) + terms * ((K * S) @ aW))
 
 
+def negligible_mass(X, W, h, log2_thr=-31.5):
+    """Per row, sum_j |K_ij| |W_j| over the entries below 2^log2_thr: what a
+    product that skips tiles whose entries are all below 2^-32 can leave out
+    (the threshold is raised by half a binade to cover the error of the
+    exponents the skip test reads)."""
+    q = sqdist(X, X)
+    K = np.exp(-q / (2 * h * h))
+    K = np.where(K < 2.0 ** log2_thr, K, 0.0)
+    aW = np.abs(np.asarray(W, dtype=np.float64)).reshape(W.shape[0], -1)
+    return K @ aW
+
+
 def leaf_ranges(nodes, n):
     lb = np.empty(n, dtype=np.int32)
     le = np.empty(n, dtype=np.int32)

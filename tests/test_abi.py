@@ -140,6 +140,12 @@ def _bad_calls(L, _lib):
         ("krr_predict", lambda: L.krr_predict(P, 3, P, 4, 2, F32, 1.0, P, 65, P, P, F32, None), "bad sizes"),
         ("krr_set_tuning knob", lambda: L.krr_set_tuning(99, 1), "unknown knob"),
         ("krr_set_tuning value", lambda: L.krr_set_tuning(0, 5), "0 to 4"),
+        ("krr_set_tuning sym skip", lambda: L.krr_set_tuning(_lib.KRR_TUNE_SYM_SKIP, 3), "0, 1 or 2"),
+        ("krr_tile_map_create", lambda: L.krr_tile_map_create(None), "NULL pointer"),
+        ("krr_tile_map_destroy", lambda: L.krr_tile_map_destroy(None), "NULL handle"),
+        ("kernel_matvec_mapped", lambda: L.kernel_matvec_mapped(P, 10, 3, F32, 1.0, P, 1, 0.0, P, None, None),
+         "NULL map"),
+        ("krr_tile_map_counts", lambda: L.krr_tile_map_counts(None, None, None), "NULL pointer"),
         ("krr_get_tuning", lambda: L.krr_get_tuning(0, None), "bad arguments"),
         ("krr_dot_columns", lambda: L.krr_dot_columns(P, P, 5, 0, P, None), "bad arguments"),
         ("krr_tree_size", lambda: L.krr_tree_size(None, None, None), "NULL tree"),

@@ -8,7 +8,7 @@ import torch
 import synthdata as sd
 from oracle import cmath, grad as og, cluster as oc, kernel as ok
 from gpu_util import (fp32_product_bound, fp32_sym_anchored_bound, fp32_wide_product_bound, fp64_wide_product_bound,
-                      leaf_ranges, sqdist, sym_rows_per_block, U32)
+                      leaf_ranges, negligible_mass, sqdist, sym_rows_per_block, U32)
 
 pytestmark = pytest.mark.gpu
 
@@ -279,5 +279,100 @@ def test_symmetric_forms_agree_ragged(gpu_lib, sym_chunk, n, d):
             if form >= 3:
                 bound = fp32_sym_anchored_bound(X, W, 0.8, sym_rows_per_block(d, form), form=form)
             assert np.all(np.abs(got - ref) <= bound), form
+        # the BF16 form recording its negligible-tile map, then skipping
+        # those tiles (every item's map words, ragged panels and row blocks)
+        gpu_lib.set_tuning("symmetric", 4)
+        gpu_lib.set_tuning("sym_skip", 2)
+        got = gpu_lib.kernel_matvec(Xd, Xd, 0.8, _t(W), prec="f32").cpu().numpy()
+        assert np.all(np.abs(got - ref) <= bound + negligible_mass(X, W, 0.8))
     finally:
         gpu_lib.set_tuning("symmetric", old)
+        gpu_lib.set_tuning("sym_skip", 1)
+
+
+def _line_clusters(n, seed):
+    """Eight tight clusters (sigma 0.02) on a line, 6.87 apart, in cluster
+    order, and positive weights near 1e9 on every other cluster."""
+    rng = np.random.default_rng(seed)
+    lab = np.sort(rng.integers(0, 8, n))
+    X = (0.02 * rng.standard_normal((n, 8))).astype(np.float32)
+    X[:, 0] += (6.87 * lab).astype(np.float32)
+    W = (1.0 + 0.5 * rng.random((n, 1))) * np.where(lab % 2 == 1, 1e9, 1.0)[:, None]
+    return X, W
+
+
+def test_tile_map_entry_point(gpu_lib, sym_chunk):
+    # kernel_matvec_mapped: the first call records (every entry evaluated:
+    # the plain bound), the next ones with the same points and width leave
+    # out the negligible tiles (bound widened by the mass below 2^-31.5); a
+    # new width or another address of the points records again
+    n, h = 6037, 1.0
+    X, W = _line_clusters(n, 11)
+    Xh = X.astype(np.float64)
+    W2 = W[::-1].copy()
+    Xd = _t(X)
+    tm = gpu_lib.TileMap()
+    assert tm.counts() == (0, 0, 0)
+    b1 = fp32_sym_anchored_bound(Xh, W, h, sym_rows_per_block(8, 4), form=4)
+    first = tm.matvec(Xd, h, _t(W)).cpu().numpy()
+    assert np.all(np.abs(first - cmath.kmv(Xh, Xh, W, h)) <= b1)
+    kept, tiles, per_tile = tm.counts()
+    assert per_tile == 128 * 16 and 0 < kept < tiles
+    # the map covers every wave tile (8 waves x 16 tiles of a 256-point
+    # panel) of each item: a 1024-row block against a 1024-column chunk
+    # right of its diagonal block
+    want = 0
+    for i0 in range(0, n, 1024):
+        off = min(n, i0 + 1024)
+        for c in range(off // 1024, (n - 1) // 1024 + 1) if off < n else ():
+            j0, j1 = max(off, c * 1024), min(n, (c + 1) * 1024)
+            want += -(-(j1 - j0) // 256) * 8 * 16
+    assert tiles == want
+    ref2 = cmath.kmv(Xh, Xh, W2, h)
+    b2 = fp32_sym_anchored_bound(Xh, W2, h, sym_rows_per_block(8, 4), form=4)
+    second = tm.matvec(Xd, h, _t(W2)).cpu().numpy()
+    assert np.all(np.abs(second - ref2) <= b2 + negligible_mass(Xh, W2, h))
+    assert np.any(np.abs(second - ref2) > b2)
+    assert tm.counts() == (kept, tiles, per_tile)
+    # beta accumulates as in kernel_matvec (the same tiles again)
+    got = tm.matvec(Xd, h, _t(W2), beta=0.5, out=_t(W2)).cpu().numpy()
+    np.testing.assert_allclose(got, second + 0.5 * W2, rtol=1e-15, atol=0)
+    # a wider kernel: recorded again, every entry evaluated
+    h3 = 1.6
+    third = tm.matvec(Xd, h3, _t(W)).cpu().numpy()
+    assert np.all(np.abs(third - cmath.kmv(Xh, Xh, W, h3)) <= fp32_sym_anchored_bound(
+        Xh, W, h3, sym_rows_per_block(8, 4), form=4))
+    assert tm.counts()[0] > kept
+    # the points at another address: recorded again
+    Xc = Xd.clone()
+    fourth = tm.matvec(Xc, h, _t(W2)).cpu().numpy()
+    assert np.all(np.abs(fourth - ref2) <= b2)
+
+
+def test_symmetric_product_tile_map(gpu_lib, sym_chunk):
+    # Eight tight clusters on a line, 6.87 h apart: entries between neighbours
+    # are about 2^-34 and the rest underflow, so most wave tiles are
+    # negligible.  Positive weights near 1e9 on every other cluster make the
+    # skipped entries' share visible (about 40 on the other clusters' rows).  With the map (record, then skip) the product is within
+    # the FP32 bound widened by the mass of the entries below 2^-31.5; it does
+    # leave that mass out (beyond the bound on some rows), and without the
+    # map every entry is evaluated (the plain bound).
+    n, d, h = 6037, 8, 1.0
+    X, W = _line_clusters(n, 11)
+    Xd = _t(X)
+    Xh = X.astype(np.float64)
+    ref = cmath.kmv(Xh, Xh, W, h)
+    bound = fp32_sym_anchored_bound(Xh, W, h, sym_rows_per_block(d, 4), form=4)
+    old = gpu_lib.get_tuning("symmetric")
+    try:
+        gpu_lib.set_tuning("symmetric", 4)
+        gpu_lib.set_tuning("sym_skip", 0)
+        full = gpu_lib.kernel_matvec(Xd, Xd, h, _t(W), prec="f32").cpu().numpy()
+        gpu_lib.set_tuning("sym_skip", 2)
+        skip = gpu_lib.kernel_matvec(Xd, Xd, h, _t(W), prec="f32").cpu().numpy()
+    finally:
+        gpu_lib.set_tuning("symmetric", old)
+        gpu_lib.set_tuning("sym_skip", 1)
+    assert np.all(np.abs(full - ref) <= bound)
+    assert np.all(np.abs(skip - ref) <= bound + negligible_mass(Xh, W, h))
+    assert np.any(np.abs(skip - ref) > bound)
