@@ -749,6 +749,8 @@ constexpr int symb_wpe(int KT, bool SYM) { return !SYM && KT >= 96 ? 4 : 2; }
 // any wave is not staged.  The word of (item, panel p, wave w) is
 // mask[(mid * ppi + p) * SM_WAVES + w].
 constexpr float kSymSkipLog2 = -32.0f;
+constexpr int kMapPanels = 64;  // panels per item with a map in use (the item's words fit one load per thread)
+constexpr int kStageK = 8;      // coordinates per staging thread (d <= 15 at 2 threads per point, <= 31 at 4)
 
 template <int KT, int RT, bool QM, bool SYM, int MK = 0>
 __global__ __launch_bounds__(64 * SM_WAVES) __attribute__((amdgpu_waves_per_eu(symb_wpe(KT, SYM))))
@@ -766,10 +768,13 @@ void k_kmv_symb(const float *__restrict__ X, const float *__restrict__ Ycols, in
     __shared__ float ws[PN];
     __shared__ float csum[SM_WAVES][PN];
     __shared__ float anc[32];
+    __shared__ uint32_t mwl[MK == 2 ? kMapPanels * SM_WAVES : 1];  // MK 2: the item's map words
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, g = lane >> 4, lr = lane & 15;
     const SymItem it = items[blockIdx.x];
     const float c = (float)it.c2;
     if (tid < 32) anc[tid] = tid < d ? anchors[it.blk * d + tid] : 0.0f;
+    if (MK == 2 && tid < (int)((it.j1 - it.j0 + PN - 1) / PN) * SM_WAVES)
+        mwl[tid] = mask[it.mid * ppi * SM_WAVES + tid];
     __syncthreads();
     // The packed row vectors, one row tile of every wave per round: a thread
     // packs one row into the panel buffer (B side of hh, hm, mh, hl, lh, mm:
@@ -818,49 +823,79 @@ void k_kmv_symb(const float *__restrict__ X, const float *__restrict__ Ycols, in
     double acc[RT];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) acc[rt] = 0.0;
-    bool fresh = true;  // no panel staged yet: the constant slots are still to be written
-    for (int64_t p0 = it.j0; p0 < it.j1; p0 += PN) {
-        const int cnt = (int)min((int64_t)PN, it.j1 - p0);
-        uint32_t *mw = nullptr;
-        uint32_t wbits = ~0u;  // the wave's tiles to evaluate in this panel
-        if (MK != 0) mw = mask + (it.mid * ppi + (p0 - it.j0) / PN) * SM_WAVES;
+    // Panels are staged from registers: each thread loads its share of the
+    // next panel's points (TPP threads per point, a contiguous share of the
+    // coordinates, at most kStageK of them) and its weight while the current
+    // panel is computed.
+    constexpr int TPP = TH / PN;
+    static_assert(((KT - 6) / 6 + TPP - 1) / TPP <= kStageK, "a staging thread's coordinates fit its registers");
+    const int pt = tid / TPP, sub = tid % TPP;
+    const int kb = (d * sub) / TPP, ke = (d * (sub + 1)) / TPP;
+    float pre[kStageK];
+    float prew = 0.0f;
+    // MK 2: the first panel at or after p that some wave evaluates; the
+    // column partials of the panels passed over are 0
+    auto visit = [&](int64_t p) {
         if (MK == 2) {
-            uint32_t any = 0;
+            while (p < it.j1) {
+                const int pi = (int)((p - it.j0) / PN);
+                uint32_t any = 0;
 #pragma unroll
-            for (int w = 0; w < SM_WAVES; ++w) any |= mw[w];
-            if (any == 0) {  // negligible for every wave: the panel's column partials are 0
-                if (tid < cnt) colpart[(int64_t)it.blk * n + p0 + tid] = 0.0f;
-                continue;
+                for (int w = 0; w < SM_WAVES; ++w) any |= mwl[pi * SM_WAVES + w];
+                if (any != 0) break;
+                if (tid < PN && tid < it.j1 - p) colpart[(int64_t)it.blk * n + p + tid] = 0.0f;
+                p += PN;
             }
-            wbits = __builtin_amdgcn_readfirstlane(mw[wv]);
         }
-        uint32_t rec = 0;  // MK 1: the tiles found to matter
+        return p;
+    };
+    auto fetch = [&](int64_t p) {
+        const bool ok = p + pt < it.j1;
+        const float *y = (SYM ? X : Ycols) + (ok ? p + pt : 0) * d;
+#pragma unroll
+        for (int k = 0; k < kStageK; ++k) pre[k] = (ok && kb + k < ke) ? y[kb + k] : 0.0f;
+        prew = (ok && sub == 0) ? wf[p + pt] : 0.0f;
+    };
+    // the rectangular form of wide points keeps its registers for 4 waves per
+    // SIMD: it loads each panel just before staging it
+    constexpr bool PREF = SYM;
+    bool fresh = true;  // no panel staged yet: the constant slots are still to be written
+    int64_t p0 = visit(it.j0);
+    if (PREF && p0 < it.j1) fetch(p0);
+    while (p0 < it.j1) {
+        const int cnt = (int)min((int64_t)PN, it.j1 - p0);
+        const int pi = (int)((p0 - it.j0) / PN);
         // stage the panel: packed BF16 terms of 2 c y' and of the column
-        // constant; points past the item get a constant of -1e30.  TPP
-        // threads per point (every thread of the workgroup takes part), each
-        // a contiguous share of the coordinates; the norm's partial sums meet
-        // by shuffles.  The slots of ones and the zero padding are the same
-        // in every panel and are written with the first.
+        // constant; points past the item get a constant of -1e30.  The
+        // norm's partial sums meet by shuffles.  The slots of ones and the
+        // zero padding are the same in every panel and are written with the
+        // first.
         {
-            constexpr int TPP = TH / PN;
-            const int pt = tid / TPP, sub = tid % TPP;
             __bf16 *dst = ys + pt * LDB;
             const bool ok = pt < cnt;
-            const float *y = (SYM ? X : Ycols) + (ok ? p0 + pt : 0) * d;
-            const int kb = (d * sub) / TPP, ke = (d * (sub + 1)) / TPP;
             float nrm = 0.0f;
-            for (int k = kb; k < ke; ++k) {
-                const float v = ok ? y[k] - anc[k] : 0.0f;
+            // A side of (hh, hm, mh, hl, lh, mm)
+            auto put = [&](int kk, float yk) {
+                const float v = ok ? yk - anc[kk] : 0.0f;
                 nrm = fmaf(v, v, nrm);
                 __bf16 h, m, l;
                 split3((2.0f * c) * v, h, m, l);
-                // A side of (hh, hm, mh, hl, lh, mm)
-                dst[k] = h;
-                dst[d + k] = h;
-                dst[2 * d + k] = m;
-                dst[3 * d + k] = h;
-                dst[4 * d + k] = l;
-                dst[5 * d + k] = m;
+                dst[kk] = h;
+                dst[d + kk] = h;
+                dst[2 * d + kk] = m;
+                dst[3 * d + kk] = h;
+                dst[4 * d + kk] = l;
+                dst[5 * d + kk] = m;
+            };
+            if constexpr (PREF) {
+#pragma unroll
+                for (int k = 0; k < kStageK; ++k) {
+                    if (kb + k >= ke) break;
+                    put(kb + k, pre[k]);
+                }
+            } else {
+                const float *y = (SYM ? X : Ycols) + (ok ? p0 + pt : 0) * d;
+                for (int k = kb; k < ke; ++k) put(k, ok ? y[k] : 0.0f);
             }
 #pragma unroll
             for (int o = 1; o < TPP; o <<= 1) nrm += __shfl_xor(nrm, o, 64);
@@ -874,11 +909,16 @@ void k_kmv_symb(const float *__restrict__ X, const float *__restrict__ Ycols, in
                     for (int k = 6 * d + 3; k < 6 * d + 6; ++k) dst[k] = (__bf16)1.0f;
                     for (int k = 6 * d + 6; k < KT; ++k) dst[k] = (__bf16)0.0f;
                 }
-                ws[pt] = ok ? wf[p0 + pt] : 0.0f;
+                ws[pt] = PREF ? prew : (ok ? wf[p0 + pt] : 0.0f);
             }
         }
         fresh = false;
         __syncthreads();
+        const int64_t pnext = visit(p0 + PN);
+        if (PREF && pnext < it.j1) fetch(pnext);  // in flight during the panel's products
+        uint32_t wbits = ~0u;  // the wave's tiles to evaluate in this panel
+        if (MK == 2) wbits = __builtin_amdgcn_readfirstlane(mwl[pi * SM_WAVES + wv]);
+        uint32_t rec = 0;  // MK 1: the tiles found to matter
         float pacc[RT];
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) pacc[rt] = 0.0f;
@@ -930,7 +970,7 @@ void k_kmv_symb(const float *__restrict__ X, const float *__restrict__ Ycols, in
         }
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) acc[rt] += (double)pacc[rt];
-        if (MK == 1 && lane == 0) mw[wv] = rec;
+        if (MK == 1 && lane == 0) mask[(it.mid * ppi + pi) * SM_WAVES + wv] = rec;
         __syncthreads();
         if (SYM && tid < cnt) {
             float cs = csum[0][tid];
@@ -938,6 +978,7 @@ void k_kmv_symb(const float *__restrict__ X, const float *__restrict__ Ycols, in
             for (int w = 1; w < SM_WAVES; ++w) cs += csum[w][tid];
             colpart[(int64_t)it.blk * n + p0 + tid] = cs;
         }
+        p0 = pnext;
     }
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
@@ -1310,6 +1351,10 @@ bool kmv_sym(const T *X, int64_t n, int d, double h, const double *W, int nrhs, 
     // multiple of 2048) as long as the grid would hold fewer than ~4096
     // items (sum of n_p^2 / (2 rows_pb CH)), so small products fill the chip
     int64_t CH = tune_get(KRR_TUNE_SYM_CHUNK);
+    // with a tile map the item's map words sit in LDS: at most kMapPanels panels
+    const int map_knob = tune_get(KRR_TUNE_SYM_SKIP);
+    const bool map_on = mb && !qm && map_knob != 0 && (skip || map_knob == 2);
+    if (map_on) CH = std::min<int64_t>(CH, (int64_t)kMapPanels * symb_pn(symb_kt(d)));
     double sq = 0.0;
     for (int p = 0; p < np; ++p) sq += (double)(pb[p + 1] - pb[p]) * (double)(pb[p + 1] - pb[p]);
     while (CH % 2048 == 0 && sq / (2.0 * rows_pb * CH) < 4096.0) CH /= 2;
@@ -1366,9 +1411,10 @@ bool kmv_sym(const T *X, int64_t n, int d, double h, const double *W, int nrhs, 
     int mk = 0, ppi = 0;
     uint32_t *mask = nullptr;
     DBuf own_map;
-    const int map_knob = tune_get(KRR_TUNE_SYM_SKIP);
-    if (mb && !qm && map_knob != 0 && (skip || map_knob == 2)) {
+    if (map_on) {
         ppi = (int)ceil_div(CH, (int64_t)symb_pn(symb_kt(d)));
+        KRR_REQUIRE(ppi <= kMapPanels, "kernel_matvec: %d panels per item exceed the tile map's %d", ppi,
+                    kMapPanels);
         const size_t words = (size_t)mids * ppi * SM_WAVES;
         std::vector<double> key{(double)(uintptr_t)X, (double)n, (double)d, (double)CH, (double)rows_pb,
                                 (double)mids};
