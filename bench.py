@@ -548,7 +548,8 @@ def main():
     kept, tiles, per_tile = tmap.counts()
     t_map = time_launches(lambda: tmap.matvec(Xp, p.h, w), args.reps)
     del tmap
-    evaluated_map = n * rb + float(kept) * per_tile
+    rb_map = per_tile // 16 * 8 if per_tile else rb  # rows of the map's row blocks (8 waves)
+    evaluated_map = n * rb_map + float(kept) * per_tile
     map_flops = evaluated_map * (2 * p.d + 2)
     form = krr.get_tuning("symmetric")
     mapped = form == 4 and p.d <= 31 and kept > 0
@@ -563,8 +564,9 @@ def main():
                                                     "and reduction launches)")
     if mapped:
         t_use, ev_use, fl_use = t_map, evaluated_map, map_flops
-        basis = ("(2d + 2) flops per evaluated kernel entry; evaluated entries = n x 1024 (the 1024-row "
-                 "diagonal blocks) + the tile map's kept wave tiles x their entries (128 rows x 16 points)")
+        basis = (f"(2d + 2) flops per evaluated kernel entry; evaluated entries = n x {rb_map} (the {rb_map}-row "
+                 f"diagonal blocks) + the tile map's kept wave tiles x their entries ({per_tile // 16} rows x 16 "
+                 "points)")
     else:
         t_use, ev_use, fl_use = t_mv, evaluated, mv_flops
         basis = ("(2d + 2) flops per evaluated kernel entry; evaluated entries = n x 1024 + "

@@ -739,7 +739,12 @@ constexpr int symb_rows(int d) { return 16 * SM_WAVES * symb_rt(symb_kt(d)); }
 constexpr int symb_max_d = 31;  // KT <= 192
 // waves per SIMD the registers are budgeted for: the rectangular form of
 // wide points fits two workgroups per CU without spills
-constexpr int symb_wpe(int KT, bool SYM) { return !SYM && KT >= 96 ? 4 : 2; }
+constexpr int symb_wpe(int KT, bool SYM, int MK) { return MK != 0 || (!SYM && KT >= 96) ? 4 : 2; }
+// With a tile map: half the row tiles per wave (a map bit covers 16 RT rows),
+// registers for four waves per SIMD, so that a second workgroup's waves run
+// while a wave waits at a panel barrier for the others' kept tiles.
+constexpr int symb_rt_map(int KT) { return symb_rt(KT) > 1 ? symb_rt(KT) / 2 : 1; }
+constexpr int symb_rows_map(int d) { return 16 * SM_WAVES * symb_rt_map(symb_kt(d)); }
 
 // MK: the negligible-tile map (SYM only).  0 none; 1 record: every tile is
 // evaluated, and each wave writes per panel the word whose bit t says that
@@ -753,7 +758,7 @@ constexpr int kMapPanels = 64;  // panels per item with a map in use (the item's
 constexpr int kStageK = 8;      // coordinates per staging thread (d <= 15 at 2 threads per point, <= 31 at 4)
 
 template <int KT, int RT, bool QM, bool SYM, int MK = 0>
-__global__ __launch_bounds__(64 * SM_WAVES) __attribute__((amdgpu_waves_per_eu(symb_wpe(KT, SYM))))
+__global__ __launch_bounds__(64 * SM_WAVES) __attribute__((amdgpu_waves_per_eu(symb_wpe(KT, SYM, MK))))
 void k_kmv_symb(const float *__restrict__ X, const float *__restrict__ Ycols, int d, const float *__restrict__ anchors,
                 const float *__restrict__ wf, int64_t n, const SymItem *__restrict__ items,
                 double *__restrict__ rowpart, float *__restrict__ colpart, uint32_t *__restrict__ mask = nullptr,
@@ -828,10 +833,11 @@ void k_kmv_symb(const float *__restrict__ X, const float *__restrict__ Ycols, in
     // coordinates, at most kStageK of them) and its weight while the current
     // panel is computed.
     constexpr int TPP = TH / PN;
-    static_assert(((KT - 6) / 6 + TPP - 1) / TPP <= kStageK, "a staging thread's coordinates fit its registers");
+    constexpr int SK = ((KT - 6) / 6 + TPP - 1) / TPP;  // coordinates per staging thread at most
+    static_assert(SK <= kStageK, "a staging thread's coordinates fit its registers");
     const int pt = tid / TPP, sub = tid % TPP;
     const int kb = (d * sub) / TPP, ke = (d * (sub + 1)) / TPP;
-    float pre[kStageK];
+    float pre[SK];
     float prew = 0.0f;
     // MK 2: the first panel at or after p that some wave evaluates; the
     // column partials of the panels passed over are 0
@@ -853,7 +859,7 @@ void k_kmv_symb(const float *__restrict__ X, const float *__restrict__ Ycols, in
         const bool ok = p + pt < it.j1;
         const float *y = (SYM ? X : Ycols) + (ok ? p + pt : 0) * d;
 #pragma unroll
-        for (int k = 0; k < kStageK; ++k) pre[k] = (ok && kb + k < ke) ? y[kb + k] : 0.0f;
+        for (int k = 0; k < SK; ++k) pre[k] = (ok && kb + k < ke) ? y[kb + k] : 0.0f;
         prew = (ok && sub == 0) ? wf[p + pt] : 0.0f;
     };
     // the rectangular form of wide points keeps its registers for 4 waves per
@@ -889,7 +895,7 @@ void k_kmv_symb(const float *__restrict__ X, const float *__restrict__ Ycols, in
             };
             if constexpr (PREF) {
 #pragma unroll
-                for (int k = 0; k < kStageK; ++k) {
+                for (int k = 0; k < SK; ++k) {
                     if (kb + k >= ke) break;
                     put(kb + k, pre[k]);
                 }
@@ -1282,12 +1288,13 @@ void launch_symb_kernel(dim3 gs, const float *X, int d, const float *anchors, co
         if (mk == 0)
             k_kmv_symb<KT, RT, false, true, 0><<<gs, 64 * SM_WAVES, 0, s>>>(X, X, d, anchors, wf, n, it, rowpart,
                                                                             colpart);
+        constexpr int RTM = symb_rt_map(KT);
         if (mk == 1 || mk == 3)
-            k_kmv_symb<KT, RT, false, true, 1><<<gs, 64 * SM_WAVES, 0, s>>>(X, X, d, anchors, wf, n, it, rowpart,
-                                                                            colpart, mask, ppi);
+            k_kmv_symb<KT, RTM, false, true, 1><<<gs, 64 * SM_WAVES, 0, s>>>(X, X, d, anchors, wf, n, it, rowpart,
+                                                                             colpart, mask, ppi);
         if (mk == 2 || mk == 3)
-            k_kmv_symb<KT, RT, false, true, 2><<<gs, 64 * SM_WAVES, 0, s>>>(X, X, d, anchors, wf, n, it, rowpart,
-                                                                            colpart, mask, ppi);
+            k_kmv_symb<KT, RTM, false, true, 2><<<gs, 64 * SM_WAVES, 0, s>>>(X, X, d, anchors, wf, n, it, rowpart,
+                                                                             colpart, mask, ppi);
     }
 }
 
@@ -1343,7 +1350,10 @@ bool kmv_sym(const T *X, int64_t n, int d, double h, const double *W, int nrhs, 
     const bool mf = sizeof(T) == 4 && nrhs == 1 && (form == 3 || (form == 4 && d > symb_max_d));
     if (qm && !mb) return false;
     const int diag_rows = MV_ROWS * sc_rpt(D);  // rows of one k_kmv_sc workgroup
-    const int rows_pb = mb ? symb_rows(d) : ((mc || mf) ? symm_rows(D) : diag_rows);
+    // with a tile map (the refinement's products): half the rows per item
+    const int map_knob = tune_get(KRR_TUNE_SYM_SKIP);
+    const bool map_on = mb && !qm && map_knob != 0 && (skip || map_knob == 2);
+    const int rows_pb = mb ? (map_on ? symb_rows_map(d) : symb_rows(d)) : ((mc || mf) ? symm_rows(D) : diag_rows);
     std::vector<int64_t> pb = batch ? batch->pbeg : std::vector<int64_t>{0, n};
     std::vector<double> hs = batch ? batch->h : std::vector<double>{h};
     const int np = (int)hs.size();
@@ -1352,8 +1362,6 @@ bool kmv_sym(const T *X, int64_t n, int d, double h, const double *W, int nrhs, 
     // items (sum of n_p^2 / (2 rows_pb CH)), so small products fill the chip
     int64_t CH = tune_get(KRR_TUNE_SYM_CHUNK);
     // with a tile map the item's map words sit in LDS: at most kMapPanels panels
-    const int map_knob = tune_get(KRR_TUNE_SYM_SKIP);
-    const bool map_on = mb && !qm && map_knob != 0 && (skip || map_knob == 2);
     if (map_on) CH = std::min<int64_t>(CH, (int64_t)kMapPanels * symb_pn(symb_kt(d)));
     double sq = 0.0;
     for (int p = 0; p < np; ++p) sq += (double)(pb[p + 1] - pb[p]) * (double)(pb[p + 1] - pb[p]);
@@ -1438,7 +1446,7 @@ bool kmv_sym(const T *X, int64_t n, int d, double h, const double *W, int nrhs, 
                 skip->key = key;
                 skip->ready = true;
                 skip->tiles = panels * SM_WAVES * (pn / 16);
-                skip->entries_per_tile = (int64_t)symb_rows(d) / SM_WAVES * 16;
+                skip->entries_per_tile = (int64_t)rows_pb / SM_WAVES * 16;
             }
         }
         if (mk != 0) mask = (skip ? skip->bits : own_map).as<uint32_t>();

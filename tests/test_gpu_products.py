@@ -284,6 +284,7 @@ def test_symmetric_forms_agree_ragged(gpu_lib, sym_chunk, n, d):
         gpu_lib.set_tuning("symmetric", 4)
         gpu_lib.set_tuning("sym_skip", 2)
         got = gpu_lib.kernel_matvec(Xd, Xd, 0.8, _t(W), prec="f32").cpu().numpy()
+        bound = fp32_sym_anchored_bound(X, W, 0.8, sym_rows_per_block(d, 4, mapped=True), form=4)
         assert np.all(np.abs(got - ref) <= bound + negligible_mass(X, W, 0.8))
     finally:
         gpu_lib.set_tuning("symmetric", old)
@@ -313,23 +314,24 @@ def test_tile_map_entry_point(gpu_lib, sym_chunk):
     Xd = _t(X)
     tm = gpu_lib.TileMap()
     assert tm.counts() == (0, 0, 0)
-    b1 = fp32_sym_anchored_bound(Xh, W, h, sym_rows_per_block(8, 4), form=4)
+    rows = sym_rows_per_block(8, 4, mapped=True)
+    b1 = fp32_sym_anchored_bound(Xh, W, h, rows, form=4)
     first = tm.matvec(Xd, h, _t(W)).cpu().numpy()
     assert np.all(np.abs(first - cmath.kmv(Xh, Xh, W, h)) <= b1)
     kept, tiles, per_tile = tm.counts()
-    assert per_tile == 128 * 16 and 0 < kept < tiles
+    assert per_tile == rows // 8 * 16 and 0 < kept < tiles
     # the map covers every wave tile (8 waves x 16 tiles of a 256-point
-    # panel) of each item: a 1024-row block against a 1024-column chunk
-    # right of its diagonal block
+    # panel) of each item: a row block against a 1024-column chunk right of
+    # its diagonal block
     want = 0
-    for i0 in range(0, n, 1024):
-        off = min(n, i0 + 1024)
+    for i0 in range(0, n, rows):
+        off = min(n, i0 + rows)
         for c in range(off // 1024, (n - 1) // 1024 + 1) if off < n else ():
             j0, j1 = max(off, c * 1024), min(n, (c + 1) * 1024)
             want += -(-(j1 - j0) // 256) * 8 * 16
     assert tiles == want
     ref2 = cmath.kmv(Xh, Xh, W2, h)
-    b2 = fp32_sym_anchored_bound(Xh, W2, h, sym_rows_per_block(8, 4), form=4)
+    b2 = fp32_sym_anchored_bound(Xh, W2, h, rows, form=4)
     second = tm.matvec(Xd, h, _t(W2)).cpu().numpy()
     assert np.all(np.abs(second - ref2) <= b2 + negligible_mass(Xh, W2, h))
     assert np.any(np.abs(second - ref2) > b2)
@@ -340,8 +342,7 @@ def test_tile_map_entry_point(gpu_lib, sym_chunk):
     # a wider kernel: recorded again, every entry evaluated
     h3 = 1.6
     third = tm.matvec(Xd, h3, _t(W)).cpu().numpy()
-    assert np.all(np.abs(third - cmath.kmv(Xh, Xh, W, h3)) <= fp32_sym_anchored_bound(
-        Xh, W, h3, sym_rows_per_block(8, 4), form=4))
+    assert np.all(np.abs(third - cmath.kmv(Xh, Xh, W, h3)) <= fp32_sym_anchored_bound(Xh, W, h3, rows, form=4))
     assert tm.counts()[0] > kept
     # the points at another address: recorded again
     Xc = Xd.clone()
@@ -363,6 +364,7 @@ def test_symmetric_product_tile_map(gpu_lib, sym_chunk):
     Xh = X.astype(np.float64)
     ref = cmath.kmv(Xh, Xh, W, h)
     bound = fp32_sym_anchored_bound(Xh, W, h, sym_rows_per_block(d, 4), form=4)
+    bmap = fp32_sym_anchored_bound(Xh, W, h, sym_rows_per_block(d, 4, mapped=True), form=4)
     old = gpu_lib.get_tuning("symmetric")
     try:
         gpu_lib.set_tuning("symmetric", 4)
@@ -374,5 +376,5 @@ def test_symmetric_product_tile_map(gpu_lib, sym_chunk):
         gpu_lib.set_tuning("symmetric", old)
         gpu_lib.set_tuning("sym_skip", 1)
     assert np.all(np.abs(full - ref) <= bound)
-    assert np.all(np.abs(skip - ref) <= bound + negligible_mass(Xh, W, h))
-    assert np.any(np.abs(skip - ref) > bound)
+    assert np.all(np.abs(skip - ref) <= bmap + negligible_mass(Xh, W, h))
+    assert np.any(np.abs(skip - ref) > bmap)
