@@ -528,10 +528,11 @@ def main():
     log("timing the refinement kernel product (every entry)")
     t_mv = time_launches(lambda: krr.kernel_matvec(Xp, Xp, p.h, w, prec="f32"), args.reps)
     # The symmetric product evaluates each off-diagonal entry once and the
-    # 1024-row diagonal blocks in full; the unit of work is an evaluated entry
-    # (2d + 2 flops for its exponent, one exp2), priced against the FP32
-    # vector peak, with the exp2 issue floor of the same entries beside it.
-    rb = 1024
+    # diagonal row blocks (512 rows at d <= 9, 8 waves x 4 row tiles x 16) in
+    # full; the unit of work is an evaluated entry (2d + 2 flops for its
+    # exponent, one exp2), priced against the FP32 vector peak, with the exp2
+    # issue floor of the same entries beside it.
+    rb = 512 if p.d <= 9 else 256
     evaluated = n * rb + (float(n) * n - n * rb) / 2
     mv_flops = evaluated * (2 * p.d + 2)
     every_entry = {"launch_s": t_mv, "achieved": mv_flops / t_mv / 1e12, "frac": mv_flops / t_mv / PEAK_F32_VECTOR,
@@ -569,8 +570,8 @@ def main():
                  "points)")
     else:
         t_use, ev_use, fl_use = t_mv, evaluated, mv_flops
-        basis = ("(2d + 2) flops per evaluated kernel entry; evaluated entries = n x 1024 + "
-                 "(n^2 - n x 1024) / 2 (upper triangle plus full 1024-row diagonal blocks)")
+        basis = (f"(2d + 2) flops per evaluated kernel entry; evaluated entries = n x {rb} + "
+                 f"(n^2 - n x {rb}) / 2 (upper triangle plus full {rb}-row diagonal blocks)")
     roof_mv = {"bound": "alu", "achieved": fl_use / t_use / 1e12, "peak": PEAK_F32_VECTOR / 1e12,
                "unit": "TFLOP/s", "frac": fl_use / t_use / PEAK_F32_VECTOR,
                "traffic": pmc_traffic("kernel_product_mapped" if mapped else "kernel_product", n),

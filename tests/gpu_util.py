@@ -73,16 +73,15 @@ def fp64_wide_product_bound(X, Y, W, h, safety=4.0, anchor=None):
     return safety * U64 * ((Y.shape[0] + 4) * (K @ aW) + (K * T) @ aW)
 
 
-def sym_rows_per_block(d, form=3, mapped=False):
+def sym_rows_per_block(d, form=3):
     """Row block of the matrix-core symmetric product: form 3 (FP32
     exponents) 1024 rows for padded widths up to 8, else 512; form 4 (BF16
-    three-term exponents, d <= 31) 1024 rows while the packed K (6 d + 6
-    rounded up to 32) is at most 64, 512 up to 128, else 256, and half of
-    that for the products that record or use a negligible-tile map."""
+    three-term exponents, d <= 31) 512 rows while the packed K (6 d + 6
+    rounded up to 32) is at most 64, 256 up to 128, else 128 (the same with
+    and without a negligible-tile map)."""
     if form == 4 and d <= 31:
         kt = (6 * d + 6 + 31) // 32 * 32
-        rows = 1024 if kt <= 64 else (512 if kt <= 128 else 256)
-        return rows // 2 if mapped else rows
+        return 512 if kt <= 64 else (256 if kt <= 128 else 128)
     D = (d + 3) // 4 * 4 if d <= 24 else 32
     return 1024 if D <= 8 else 512
 

@@ -264,7 +264,8 @@ def test_symmetric_product_switch(gpu_lib):
 @pytest.mark.parametrize("n,d", [(1, 8), (15, 8), (511, 8), (513, 3), (1023, 8), (1025, 8), (2049, 5), (3000, 20),
                                  (1500, 15)])
 def test_symmetric_forms_agree_ragged(gpu_lib, sym_chunk, n, d):
-    # sizes around the row blocks (1024 rows at d <= 8, 512 above) and the
+    # sizes around the row blocks (BF16 form: 512 rows at d <= 9, 256 up to
+    # d = 20; FP32 form: 1024 rows at d <= 8, 512 above) and the
     # 256-point panels: both symmetric forms against the oracle
     X = sd.points(n, d, seed=n, scale=0.6)
     W = sd.vectors(n, 1, seed=3)
@@ -284,7 +285,7 @@ def test_symmetric_forms_agree_ragged(gpu_lib, sym_chunk, n, d):
         gpu_lib.set_tuning("symmetric", 4)
         gpu_lib.set_tuning("sym_skip", 2)
         got = gpu_lib.kernel_matvec(Xd, Xd, 0.8, _t(W), prec="f32").cpu().numpy()
-        bound = fp32_sym_anchored_bound(X, W, 0.8, sym_rows_per_block(d, 4, mapped=True), form=4)
+        bound = fp32_sym_anchored_bound(X, W, 0.8, sym_rows_per_block(d, 4), form=4)
         assert np.all(np.abs(got - ref) <= bound + negligible_mass(X, W, 0.8))
     finally:
         gpu_lib.set_tuning("symmetric", old)
@@ -314,7 +315,7 @@ def test_tile_map_entry_point(gpu_lib, sym_chunk):
     Xd = _t(X)
     tm = gpu_lib.TileMap()
     assert tm.counts() == (0, 0, 0)
-    rows = sym_rows_per_block(8, 4, mapped=True)
+    rows = sym_rows_per_block(8, 4)
     b1 = fp32_sym_anchored_bound(Xh, W, h, rows, form=4)
     first = tm.matvec(Xd, h, _t(W)).cpu().numpy()
     assert np.all(np.abs(first - cmath.kmv(Xh, Xh, W, h)) <= b1)
@@ -364,7 +365,7 @@ def test_symmetric_product_tile_map(gpu_lib, sym_chunk):
     Xh = X.astype(np.float64)
     ref = cmath.kmv(Xh, Xh, W, h)
     bound = fp32_sym_anchored_bound(Xh, W, h, sym_rows_per_block(d, 4), form=4)
-    bmap = fp32_sym_anchored_bound(Xh, W, h, sym_rows_per_block(d, 4, mapped=True), form=4)
+    bmap = fp32_sym_anchored_bound(Xh, W, h, sym_rows_per_block(d, 4), form=4)
     old = gpu_lib.get_tuning("symmetric")
     try:
         gpu_lib.set_tuning("symmetric", 4)
