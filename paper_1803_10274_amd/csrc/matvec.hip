@@ -739,7 +739,7 @@ constexpr int symb_rows(int d) { return 16 * SM_WAVES * symb_rt(symb_kt(d)); }
 constexpr int symb_max_d = 31;  // KT <= 192
 // waves per SIMD the registers are budgeted for: the rectangular form of
 // wide points fits two workgroups per CU without spills
-constexpr int symb_wpe(int KT, bool SYM, bool QM) { return (SYM && !QM) || (!SYM && KT >= 96) ? 4 : 2; }
+constexpr int symb_wpe(int KT, bool SYM, bool QM) { return SYM || KT >= 96 ? 4 : 2; }
 // With a tile map: half the row tiles per wave (a map bit covers 16 RT rows),
 // registers for four waves per SIMD, so that a second workgroup's waves run
 // while a wave waits at a panel barrier for the others' kept tiles.
@@ -1282,10 +1282,10 @@ template <int KT, int RT, bool QM>
 void launch_symb_kernel(dim3 gs, const float *X, int d, const float *anchors, const float *wf, int64_t n,
                         const SymItem *it, double *rowpart, float *colpart, int mk, uint32_t *mask, int ppi,
                         hipStream_t s) {
+    constexpr int RTM = symb_rt_map(KT);
     if constexpr (QM) {
-        k_kmv_symb<KT, RT, true, true><<<gs, 64 * SM_WAVES, 0, s>>>(X, X, d, anchors, wf, n, it, rowpart, colpart);
+        k_kmv_symb<KT, RTM, true, true><<<gs, 64 * SM_WAVES, 0, s>>>(X, X, d, anchors, wf, n, it, rowpart, colpart);
     } else {
-        constexpr int RTM = symb_rt_map(KT);
         if (mk == 0)
             k_kmv_symb<KT, RTM, false, true, 0><<<gs, 64 * SM_WAVES, 0, s>>>(X, X, d, anchors, wf, n, it, rowpart,
                                                                              colpart);
@@ -1353,7 +1353,7 @@ bool kmv_sym(const T *X, int64_t n, int d, double h, const double *W, int nrhs, 
     // with a tile map (the refinement's products): half the rows per item
     const int map_knob = tune_get(KRR_TUNE_SYM_SKIP);
     const bool map_on = mb && !qm && map_knob != 0 && (skip || map_knob == 2);
-    const int rows_pb = mb ? (qm ? symb_rows(d) : symb_rows_map(d)) : ((mc || mf) ? symm_rows(D) : diag_rows);
+    const int rows_pb = mb ? symb_rows_map(d) : ((mc || mf) ? symm_rows(D) : diag_rows);
     std::vector<int64_t> pb = batch ? batch->pbeg : std::vector<int64_t>{0, n};
     std::vector<double> hs = batch ? batch->h : std::vector<double>{h};
     const int np = (int)hs.size();
