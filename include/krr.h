@@ -214,8 +214,8 @@ int kernel_matvec(const void *X, int64_t m, const void *Y, int64_t n, int32_t d,
  * address.  Applies to K(X, X) with FP32 points, d <= 31, one right-hand
  * side and the BF16 symmetric form (KRR_TUNE_SYMMETRIC 4); other products
  * evaluate every entry, and so do all products when KRR_TUNE_SYM_SKIP is 0.
- * The map's device memory belongs to the handle (about 8 bytes per 256 x
- * 1024 entries of K's upper triangle: 68 MB at n = 2^20).  Errors:
+ * The map's device memory belongs to the handle (4 bytes per 64 x 256
+ * entries of K's upper triangle at d <= 9: 136 MB at n = 2^20).  Errors:
  * KRR_E_INVAL for NULL handles.
  */
 typedef struct krr_tile_map_s *krr_tile_map_t;
