@@ -351,6 +351,34 @@ def test_tile_map_entry_point(gpu_lib, sym_chunk):
     assert np.all(np.abs(fourth - ref2) <= b2)
 
 
+def test_batched_symmetric_product_tile_map(gpu_lib, sym_chunk):
+    # a batch of three line-cluster problems (per-problem widths) through the
+    # batched symmetric product, recording its map and then skipping: each
+    # item's map words are found by its index among every problem's items
+    parts = [_line_clusters(n, 20 + n) for n in (1500, 2300, 777)]
+    hs = [1.0, 1.05, 0.95]
+    X = np.concatenate([x for x, _ in parts]).astype(np.float32)
+    W = np.concatenate([w for _, w in parts])
+    off = np.cumsum([0] + [x.shape[0] for x, _ in parts])
+    old = gpu_lib.get_tuning("symmetric")
+    try:
+        gpu_lib.set_tuning("symmetric", 4)
+        gpu_lib.set_tuning("sym_skip", 2)
+        out = gpu_lib.kernel_matvec_batched(_t(X), off, hs, _t(W), prec="f32").cpu().numpy()
+    finally:
+        gpu_lib.set_tuning("symmetric", old)
+        gpu_lib.set_tuning("sym_skip", 1)
+    dropped = False
+    for k, h in enumerate(hs):
+        a, b = off[k], off[k + 1]
+        Xk = X[a:b].astype(np.float64)
+        ref = cmath.kmv(Xk, Xk, W[a:b], h)
+        bound = fp32_sym_anchored_bound(Xk, W[a:b], h, sym_rows_per_block(8, 4), form=4)
+        assert np.all(np.abs(out[a:b] - ref) <= bound + negligible_mass(Xk, W[a:b], h)), k
+        dropped = dropped or bool(np.any(np.abs(out[a:b] - ref) > bound))
+    assert dropped
+
+
 def test_symmetric_product_tile_map(gpu_lib, sym_chunk):
     # Eight tight clusters on a line, 6.87 h apart: entries between neighbours
     # are about 2^-34 and the rest underflow, so most wave tiles are
