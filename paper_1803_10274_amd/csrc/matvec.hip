@@ -737,14 +737,15 @@ constexpr int symb_rt(int KT) { return KT <= 64 ? 8 : (KT <= 128 ? 4 : 2); }  //
 constexpr int symb_kt(int d) { return (6 * d + 6 + 31) / 32 * 32; }
 constexpr int symb_rows(int d) { return 16 * SM_WAVES * symb_rt(symb_kt(d)); }
 constexpr int symb_max_d = 31;  // KT <= 192
-// waves per SIMD the registers are budgeted for: the rectangular form of
-// wide points fits two workgroups per CU without spills
-constexpr int symb_wpe(int KT, bool SYM, bool QM) { return SYM || KT >= 96 ? 4 : 2; }
-// With a tile map: half the row tiles per wave (a map bit covers 16 RT rows),
-// registers for four waves per SIMD, so that a second workgroup's waves run
-// while a wave waits at a panel barrier for the others' kept tiles.
-constexpr int symb_rt_map(int KT) { return symb_rt(KT) > 1 ? symb_rt(KT) / 2 : 1; }
-constexpr int symb_rows_map(int d) { return 16 * SM_WAVES * symb_rt_map(symb_kt(d)); }
+// Waves per SIMD the registers are budgeted for.  The symmetric form runs
+// half the rectangular form's row tiles per wave (a map bit covers 16 of its
+// RT rows) at four waves per SIMD: two workgroups share a CU, and one's waves
+// run while the other's wait at a panel barrier (for the wave with the most
+// kept tiles, with a map).  The rectangular form of wide points also fits
+// four waves per SIMD without spills.
+constexpr int symb_wpe(int KT, bool SYM) { return SYM || KT >= 96 ? 4 : 2; }
+constexpr int symb_rt_sym(int KT) { return symb_rt(KT) > 1 ? symb_rt(KT) / 2 : 1; }
+constexpr int symb_rows_sym(int d) { return 16 * SM_WAVES * symb_rt_sym(symb_kt(d)); }
 
 // MK: the negligible-tile map (SYM only).  0 none; 1 record: every tile is
 // evaluated, and each wave writes per panel the word whose bit t says that
@@ -758,7 +759,7 @@ constexpr int kMapPanels = 64;  // panels per item with a map in use (the item's
 constexpr int kStageK = 8;      // coordinates per staging thread (d <= 15 at 2 threads per point, <= 31 at 4)
 
 template <int KT, int RT, bool QM, bool SYM, int MK = 0>
-__global__ __launch_bounds__(64 * SM_WAVES) __attribute__((amdgpu_waves_per_eu(symb_wpe(KT, SYM, QM))))
+__global__ __launch_bounds__(64 * SM_WAVES) __attribute__((amdgpu_waves_per_eu(symb_wpe(KT, SYM))))
 void k_kmv_symb(const float *__restrict__ X, const float *__restrict__ Ycols, int d, const float *__restrict__ anchors,
                 const float *__restrict__ wf, int64_t n, const SymItem *__restrict__ items,
                 double *__restrict__ rowpart, float *__restrict__ colpart, uint32_t *__restrict__ mask = nullptr,
@@ -1276,13 +1277,14 @@ void launch_symf(dim3 gd, dim3 gs, dim3 gr, int rows_pb, const float *X, int d, 
     check_launch("k_sym_reduce");
 }
 
-// BF16 three-term exponents: K slots for d and the kernel's row tiles.  mk:
-// the tile map's use (k_kmv_symb's MK; 3: record, then use, in one call).
-template <int KT, int RT, bool QM>
+// BF16 three-term exponents: K slots for d (the symmetric form's row tiles
+// follow from them).  mk: the tile map's use (k_kmv_symb's MK; 3: record,
+// then use, in one call).
+template <int KT, bool QM>
 void launch_symb_kernel(dim3 gs, const float *X, int d, const float *anchors, const float *wf, int64_t n,
                         const SymItem *it, double *rowpart, float *colpart, int mk, uint32_t *mask, int ppi,
                         hipStream_t s) {
-    constexpr int RTM = symb_rt_map(KT);
+    constexpr int RTM = symb_rt_sym(KT);
     if constexpr (QM) {
         k_kmv_symb<KT, RTM, true, true><<<gs, 64 * SM_WAVES, 0, s>>>(X, X, d, anchors, wf, n, it, rowpart, colpart);
     } else {
@@ -1313,9 +1315,9 @@ void launch_symb(dim3 gd, dim3 gs, dim3 gr, int rows_pb, const float *X, int d, 
         const float *an = anchors.as<float>();
 #define KRR_SYMB(KT)                                                                                  \
     case KT:                                                                                          \
-        launch_symb_kernel<KT, symb_rt(KT), QM>(gs, X, d, an, wf, n, it, rowpart, colpart, mk, mask, ppi, s); \
+        launch_symb_kernel<KT, QM>(gs, X, d, an, wf, n, it, rowpart, colpart, mk, mask, ppi, s);             \
         break;
-        switch (kt) {  // row tiles per wave: symb_rt
+        switch (kt) {  // row tiles per wave: symb_rt_sym
             KRR_SYMB(32)
             KRR_SYMB(64)
             KRR_SYMB(96)
@@ -1350,10 +1352,11 @@ bool kmv_sym(const T *X, int64_t n, int d, double h, const double *W, int nrhs, 
     const bool mf = sizeof(T) == 4 && nrhs == 1 && (form == 3 || (form == 4 && d > symb_max_d));
     if (qm && !mb) return false;
     const int diag_rows = MV_ROWS * sc_rpt(D);  // rows of one k_kmv_sc workgroup
-    // with a tile map (the refinement's products): half the rows per item
+    // the tile map: the refinement's products (skip given) or every product
+    // (knob 2)
     const int map_knob = tune_get(KRR_TUNE_SYM_SKIP);
     const bool map_on = mb && !qm && map_knob != 0 && (skip || map_knob == 2);
-    const int rows_pb = mb ? symb_rows_map(d) : ((mc || mf) ? symm_rows(D) : diag_rows);
+    const int rows_pb = mb ? symb_rows_sym(d) : ((mc || mf) ? symm_rows(D) : diag_rows);
     std::vector<int64_t> pb = batch ? batch->pbeg : std::vector<int64_t>{0, n};
     std::vector<double> hs = batch ? batch->h : std::vector<double>{h};
     const int np = (int)hs.size();
