@@ -724,6 +724,7 @@ __global__ __launch_bounds__(64 * SM_WAVES) void k_kmv_symf(const float *__restr
 // rows are X's and the columns Y's (no column sums; the row partials of item
 // chunk c at rowpart[c * n + i], n being then the number of rows).
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef __bf16 bf4v __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ void split3(float v, __bf16 &h, __bf16 &m, __bf16 &l) {
     h = (__bf16)v;
@@ -894,7 +895,35 @@ void k_kmv_symb(const float *__restrict__ X, const float *__restrict__ Ycols, in
                 dst[4 * d + kk] = l;
                 dst[5 * d + kk] = m;
             };
-            if constexpr (PREF) {
+            if constexpr (PREF && SK >= 4) {
+                if (ke - kb == 4 && (d & 3) == 0) {
+                    // four coordinates per thread, each term group's four
+                    // values 8-byte aligned: one 8-byte store per group
+                    bf4v th, tm, tl;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const float v = ok ? pre[k] - anc[kb + k] : 0.0f;
+                        nrm = fmaf(v, v, nrm);
+                        __bf16 h, m, l;
+                        split3((2.0f * c) * v, h, m, l);
+                        th[k] = h;
+                        tm[k] = m;
+                        tl[k] = l;
+                    }
+                    *reinterpret_cast<bf4v *>(dst + kb) = th;
+                    *reinterpret_cast<bf4v *>(dst + d + kb) = th;
+                    *reinterpret_cast<bf4v *>(dst + 2 * d + kb) = tm;
+                    *reinterpret_cast<bf4v *>(dst + 3 * d + kb) = th;
+                    *reinterpret_cast<bf4v *>(dst + 4 * d + kb) = tl;
+                    *reinterpret_cast<bf4v *>(dst + 5 * d + kb) = tm;
+                } else {
+#pragma unroll
+                    for (int k = 0; k < SK; ++k) {
+                        if (kb + k >= ke) break;
+                        put(kb + k, pre[k]);
+                    }
+                }
+            } else if constexpr (PREF) {
 #pragma unroll
                 for (int k = 0; k < SK; ++k) {
                     if (kb + k >= ke) break;
