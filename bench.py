@@ -43,19 +43,19 @@ PEAK_EXP2 = 256 * 64 * 2.4e9 / 4
 # WRITE_SIZE 1,048,576 KiB -> x1.000).  Valid only while the kernel's source
 # file is unchanged (sha256 below); otherwise the bench reports null.
 PMC_TRAFFIC = {
-    "sampling": {"fetch_kib": 931508822.5625, "write_kib": 1048576.0, "fetch_scale": 2.0, "write_scale": 1.0,
+    "sampling": {"fetch_kib": 930383607.1875, "write_kib": 1048576.0, "fetch_scale": 2.0, "write_scale": 1.0,
                  "source": "paper_1803_10274_amd/csrc/sample_mfma.hip",
                  "sha256": "bcd0d5396bd1701e27d4c92645b02fded9aa6e4ae6559e2bc90a8edeb4e761b3", "n": 1 << 20, "r": 256},
     # the symmetric product's six launches: column data, FP32 weights,
     # diagonal blocks, row-block anchors, upper triangle, reduction
-    "kernel_product": {"fetch_kib": 17837734.9375, "write_kib": 5718690.3125, "fetch_scale": 2.0, "write_scale": 1.0,
+    "kernel_product": {"fetch_kib": 17890529.375, "write_kib": 6384645.15625, "fetch_scale": 2.0, "write_scale": 1.0,
                        "source": "paper_1803_10274_amd/csrc/matvec.hip",
-                       "sha256": "e107688498a95b1e2297bdda1e8948d0f4fcd6f1dee6b6393d8773f71edca9dd",
+                       "sha256": "a3885e9b4f9550f2388f8e28c44e3c996e5c34ab6301c944f84e4f613bd03194",
                        "n": 1 << 20, "r": None},
     # the same six launches through the negligible-tile map
-    "kernel_product_mapped": {"fetch_kib": 8439777.8125, "write_kib": 5614335.4375, "fetch_scale": 2.0,
+    "kernel_product_mapped": {"fetch_kib": 8465179.125, "write_kib": 6115831.375, "fetch_scale": 2.0,
                               "write_scale": 1.0, "source": "paper_1803_10274_amd/csrc/matvec.hip",
-                              "sha256": "e107688498a95b1e2297bdda1e8948d0f4fcd6f1dee6b6393d8773f71edca9dd",
+                              "sha256": "a3885e9b4f9550f2388f8e28c44e3c996e5c34ab6301c944f84e4f613bd03194",
                               "n": 1 << 20, "r": None},
 }
 
@@ -78,24 +78,24 @@ def pmc_traffic(kind, n, r=None):
 # `rocprofv3 --pmc` runs of `bench.py --kernels-only`; valid only while the
 # kernel's source file is unchanged (sha256), otherwise reported as null.
 PMC_MFMA = {
-    "sampling": {"mops": {"f16": 659243755520.0, "bf16": 274886295552.0}, "mfma_busy_frac": 0.3457,
-                 "valu_busy_frac": 0.2207, "coexec_frac": 0.0444,
+    "sampling": {"mops": {"f16": 659243755520.0, "bf16": 274886295552.0}, "mfma_busy_frac": 0.3469,
+                 "valu_busy_frac": 0.2214, "coexec_frac": 0.0445,
                  "source": "paper_1803_10274_amd/csrc/sample_mfma.hip",
                  "sha256": "bcd0d5396bd1701e27d4c92645b02fded9aa6e4ae6559e2bc90a8edeb4e761b3", "n": 1 << 20, "r": 256,
                  "profile": "profiles/k_sample_mfma_sixteen_gaussians_n1048576_r256.md"},
-    "sampling_every_tile": {"mops": {"f16": 2199023255552.0, "bf16": 274886295552.0}, "mfma_busy_frac": 0.5949,
-                            "valu_busy_frac": 0.3314, "coexec_frac": 0.0865,
+    "sampling_every_tile": {"mops": {"f16": 2199023255552.0, "bf16": 274886295552.0}, "mfma_busy_frac": 0.5938,
+                            "valu_busy_frac": 0.3308, "coexec_frac": 0.0863,
                             "source": "paper_1803_10274_amd/csrc/sample_mfma.hip",
                             "sha256": "bcd0d5396bd1701e27d4c92645b02fded9aa6e4ae6559e2bc90a8edeb4e761b3",
                             "n": 1 << 20, "r": 256,
                             "profile": "profiles/k_sample_mfma_sixteen_gaussians_n1048576_r256.md"},
-    "kernel_product": {"mops": {"bf16": 137371844608.0}, "mfma_busy_frac": 0.2932, "valu_busy_frac": 0.8515,
-                       "coexec_frac": 0.1262, "source": "paper_1803_10274_amd/csrc/matvec.hip",
-                       "sha256": "e107688498a95b1e2297bdda1e8948d0f4fcd6f1dee6b6393d8773f71edca9dd",
+    "kernel_product": {"mops": {"bf16": 137371844608.0}, "mfma_busy_frac": 0.2973, "valu_busy_frac": 0.864,
+                       "coexec_frac": 0.1303, "source": "paper_1803_10274_amd/csrc/matvec.hip",
+                       "sha256": "a3885e9b4f9550f2388f8e28c44e3c996e5c34ab6301c944f84e4f613bd03194",
                        "n": 1 << 20, "r": None, "profile": "profiles/k_kmv_symb_sixteen_gaussians_n1048576.md"},
-    "kernel_product_mapped": {"mops": {"bf16": 41267506944.0}, "mfma_busy_frac": 0.1893, "valu_busy_frac": 0.6506,
-                              "coexec_frac": 0.0695, "source": "paper_1803_10274_amd/csrc/matvec.hip",
-                              "sha256": "e107688498a95b1e2297bdda1e8948d0f4fcd6f1dee6b6393d8773f71edca9dd",
+    "kernel_product_mapped": {"mops": {"bf16": 41267506944.0}, "mfma_busy_frac": 0.1974, "valu_busy_frac": 0.6788,
+                              "coexec_frac": 0.0738, "source": "paper_1803_10274_amd/csrc/matvec.hip",
+                              "sha256": "a3885e9b4f9550f2388f8e28c44e3c996e5c34ab6301c944f84e4f613bd03194",
                               "n": 1 << 20, "r": None,
                               "profile": "profiles/k_kmv_symb_tile_map_sixteen_gaussians_n1048576.md"},
 }
